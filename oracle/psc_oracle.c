@@ -1,0 +1,961 @@
+/*
+ * psc_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously-correct FP64 CPU implementation of the solve phase
+ * of the paper's method: conjugate gradient preconditioned by an
+ * aggregation-based algebraic multigrid V-cycle. Only tests, the smoke check
+ * and the benchmark's CPU-baseline leg may load this file's library; the
+ * product path never does. It shares no code with the HIP library.
+ *
+ * What each part follows:
+ *   - AMG as a stationary iteration, Galerkin coarse operators
+ *     A_{l+1} = P_l^T A_l P_l and the V-cycle error propagation with one
+ *     pre- and one post-sweep: Section "AMG4PSBLAS", eq. (amg).
+ *   - Coupled aggregation by compatible weighted matching, the tentative
+ *     prolongator P^ = blockdiag(w_e) (+) diag(w_s/|w_s|) and k matching
+ *     sweeps giving aggregates of size <= 2^k: Section "Aggregation
+ *     strategies", eq. (prolongator).
+ *   - l1-Jacobi smoother M_l = diag(A_l) + diag(sum_{j!=i} |a_ij|):
+ *     Section "GPU enabled smoothers".
+ *   - Conjugate gradient / flexible CG to a relative residual tolerance:
+ *     Section "Numerical Example".
+ * Readings where the paper is silent (edge weights, tie order, weight
+ * quantisation, the graph of the second sweep, coarsest solve, FCG variant,
+ * the learned preconditioner) are listed in the design notes; each is
+ * restated at the function that takes it.
+ *
+ * Parity pins live in tests/test_oracle_*.py. Functions marked
+ * "parity unpinned" have no independent pin.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared (no fast-math).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_NOCONV 1
+#define ORC_ERR_ARG -1
+#define ORC_ERR_NOT_SPD -2
+#define ORC_ERR_NAN -3
+#define ORC_ERR_OOM -5
+#define ORC_ERR_COARSEN -6
+
+#define ORC_MAXLEV 64
+
+/* ------------------------------------------------------------------------ */
+/* CSR helpers                                                              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int n;
+    int *rp;      /* n+1 */
+    int *ci;      /* nnz, ascending per row */
+    double *v;    /* nnz */
+} csr;
+
+static void csr_free(csr *a) {
+    free(a->rp); free(a->ci); free(a->v);
+    a->rp = NULL; a->ci = NULL; a->v = NULL;
+}
+
+/* y = A x, each row summed in ascending column order */
+void orc_spmv(int n, const int *rp, const int *ci, const double *v,
+              const double *x, double *y) {
+    for (int i = 0; i < n; i++) {
+        double s = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; k++) s += v[k] * x[ci[k]];
+        y[i] = s;
+    }
+}
+
+static double dot(int n, const double *a, const double *b) {
+    double s = 0.0;
+    for (int i = 0; i < n; i++) s += a[i] * b[i];
+    return s;
+}
+
+/*
+ * Canonical Galerkin sum (Section "AMG4PSBLAS": A_{l+1} = P^T A P for a
+ * prolongator with one nonzero per row):
+ *   C[I,J] = sum over i in I (ascending), then stored entries j of row i
+ *            (ascending) with agg[j] = J, of (s_i * a_ij) * s_j.
+ * Every structurally reached (I,J) is stored, even if its value is zero.
+ * Rows of C have ascending columns.
+ */
+static int galerkin(const csr *a, const int *agg, int nc, const double *s, csr *c) {
+    int n = a->n;
+    int *cnt = calloc((size_t)nc + 1, sizeof(int));
+    int *mem = malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    if (!cnt || !mem) { free(cnt); free(mem); return ORC_ERR_OOM; }
+    for (int i = 0; i < n; i++) cnt[agg[i] + 1]++;
+    for (int I = 0; I < nc; I++) cnt[I + 1] += cnt[I];
+    int *fill = malloc(sizeof(int) * (size_t)(nc + 1));
+    memcpy(fill, cnt, sizeof(int) * (size_t)(nc + 1));
+    for (int i = 0; i < n; i++) mem[fill[agg[i]]++] = i;   /* members ascending */
+    free(fill);
+
+    double *acc = calloc((size_t)(nc > 0 ? nc : 1), sizeof(double));
+    int *mark = malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+    int *list = malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+    for (int J = 0; J < nc; J++) mark[J] = -1;
+
+    /* first pass: count */
+    size_t cap = 0;
+    int *rp = malloc(sizeof(int) * (size_t)(nc + 1));
+    rp[0] = 0;
+    for (int I = 0; I < nc; I++) {
+        int len = 0;
+        for (int m = cnt[I]; m < cnt[I + 1]; m++) {
+            int i = mem[m];
+            for (int k = a->rp[i]; k < a->rp[i + 1]; k++) {
+                int J = agg[a->ci[k]];
+                if (mark[J] != I) { mark[J] = I; len++; }
+            }
+        }
+        rp[I + 1] = rp[I] + len;
+    }
+    cap = (size_t)rp[nc];
+    int *ci = malloc(sizeof(int) * (cap > 0 ? cap : 1));
+    double *v = malloc(sizeof(double) * (cap > 0 ? cap : 1));
+    for (int J = 0; J < nc; J++) mark[J] = -1;
+    for (int I = 0; I < nc; I++) {
+        int len = 0;
+        for (int m = cnt[I]; m < cnt[I + 1]; m++) {
+            int i = mem[m];
+            for (int k = a->rp[i]; k < a->rp[i + 1]; k++) {
+                int J = agg[a->ci[k]];
+                double t = (s[i] * a->v[k]) * s[a->ci[k]];
+                if (mark[J] != I) { mark[J] = I; acc[J] = t; list[len++] = J; }
+                else acc[J] += t;
+            }
+        }
+        /* sort the touched columns ascending (insertion sort; rows are short) */
+        for (int x = 1; x < len; x++) {
+            int key = list[x], y = x - 1;
+            while (y >= 0 && list[y] > key) { list[y + 1] = list[y]; y--; }
+            list[y + 1] = key;
+        }
+        for (int x = 0; x < len; x++) {
+            ci[rp[I] + x] = list[x];
+            v[rp[I] + x] = acc[list[x]];
+        }
+    }
+    free(acc); free(mark); free(list); free(cnt); free(mem);
+    c->n = nc; c->rp = rp; c->ci = ci; c->v = v;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Matching (Section "Aggregation strategies", coupled aggregation)         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { long long q; int i, j; } edge;
+
+static int edge_cmp(const void *pa, const void *pb) {
+    const edge *a = pa, *b = pb;
+    if (a->q != b->q) return a->q > b->q ? -1 : 1;     /* weight descending */
+    if (a->i != b->i) return a->i < b->i ? -1 : 1;     /* then smaller end ascending */
+    if (a->j != b->j) return a->j < b->j ? -1 : 1;     /* then larger end ascending */
+    return 0;
+}
+
+/* Edge weight of the compatible weighted matching, in terms of the scaled
+ * operator S = diag(w) A diag(w) (block-summed at a second sweep):
+ *   c_ij = 1 - 2 S_ij / (S_ii + S_jj),
+ * quantised as q = llround(c * 2^30); only edges with q > 0 take part. */
+long long orc_edge_key(double sij, double sii, double sjj) {
+    double c = 1.0 - 2.0 * sij / (sii + sjj);
+    return llround(c * 1073741824.0);
+}
+
+/*
+ * One matching sweep on the symmetric graph of S (CSR, ascending columns,
+ * diagonal present). Greedy over eligible edges (i<j) in the strict order
+ * (q desc, i asc, j asc): an edge joins the matching when both ends are
+ * still free. Under a strict total order this is the unique
+ * locally-dominant matching, a 1/2-approximation of the maximum-weight
+ * matching. mate[i] = partner or -1. Returns the number of matched pairs.
+ */
+int orc_match(int n, const int *rp, const int *ci, const double *S, int *mate) {
+    double *dg = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int i = 0; i < n; i++) {
+        dg[i] = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; k++) if (ci[k] == i) dg[i] = S[k];
+    }
+    size_t ne = 0;
+    for (int i = 0; i < n; i++)
+        for (int k = rp[i]; k < rp[i + 1]; k++) if (ci[k] > i) ne++;
+    edge *E = malloc(sizeof(edge) * (ne > 0 ? ne : 1));
+    size_t m = 0;
+    for (int i = 0; i < n; i++)
+        for (int k = rp[i]; k < rp[i + 1]; k++) {
+            int j = ci[k];
+            if (j <= i) continue;
+            long long q = orc_edge_key(S[k], dg[i], dg[j]);
+            if (q > 0) { E[m].q = q; E[m].i = i; E[m].j = j; m++; }
+        }
+    qsort(E, m, sizeof(edge), edge_cmp);
+    for (int i = 0; i < n; i++) mate[i] = -1;
+    int pairs = 0;
+    for (size_t e = 0; e < m; e++) {
+        if (mate[E[e].i] < 0 && mate[E[e].j] < 0) {
+            mate[E[e].i] = E[e].j; mate[E[e].j] = E[e].i; pairs++;
+        }
+    }
+    free(E); free(dg);
+    return pairs;
+}
+
+/* Pairs and singletons of a matching as aggregates, numbered by ascending
+ * smallest member. Returns the number of aggregates. */
+static int pairs_to_aggregates(int n, const int *mate, int *agg) {
+    int nc = 0;
+    for (int i = 0; i < n; i++) agg[i] = -1;
+    for (int i = 0; i < n; i++) {
+        if (agg[i] >= 0) continue;
+        agg[i] = nc;
+        if (mate[i] >= 0) agg[mate[i]] = nc;
+        nc++;
+    }
+    return nc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hierarchy                                                                */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    csr A;
+    double *w;      /* near-kernel sample at this level (w = 1 at level 0) */
+    double *minv;   /* l1-Jacobi: 1 / (a_ii + sum_{j!=i} |a_ij|) */
+    int nc;         /* next level size (0 at the coarsest) */
+    int *agg;       /* aggregate of each row */
+    double *p;      /* value of the single nonzero of row i of P */
+    double *L;      /* coarsest only: dense lower Cholesky factor, row-major */
+} orc_level;
+
+typedef struct {
+    int nlev;
+    int sweeps;
+    orc_level lev[ORC_MAXLEV];
+} orc_hier;
+
+void orc_free(orc_hier *h) {
+    if (!h) return;
+    for (int l = 0; l < h->nlev; l++) {
+        orc_level *L = &h->lev[l];
+        csr_free(&L->A);
+        free(L->w); free(L->minv); free(L->agg); free(L->p); free(L->L);
+    }
+    free(h);
+}
+
+/* l1-Jacobi inverse diagonal (Section "GPU enabled smoothers"):
+ * d_i = a_ii + (sum over j != i, ascending, of |a_ij|). */
+static int l1_diag_inv(const csr *a, double *minv) {
+    for (int i = 0; i < a->n; i++) {
+        double dii = 0.0, off = 0.0;
+        int has = 0;
+        for (int k = a->rp[i]; k < a->rp[i + 1]; k++) {
+            if (a->ci[k] == i) { dii = a->v[k]; has = 1; }
+            else off += fabs(a->v[k]);
+        }
+        if (!has || !(dii > 0.0)) return ORC_ERR_NOT_SPD;
+        minv[i] = 1.0 / (dii + off);
+    }
+    return ORC_OK;
+}
+
+/* Dense Cholesky A = L L^T of the coarsest matrix (lower triangle read). */
+static int dense_cholesky(const csr *a, double *L) {
+    int n = a->n;
+    for (size_t t = 0; t < (size_t)n * n; t++) L[t] = 0.0;
+    for (int i = 0; i < n; i++)
+        for (int k = a->rp[i]; k < a->rp[i + 1]; k++)
+            if (a->ci[k] <= i) L[(size_t)i * n + a->ci[k]] = a->v[k];
+    for (int j = 0; j < n; j++) {
+        double d = L[(size_t)j * n + j];
+        for (int k = 0; k < j; k++) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(d > 0.0)) return ORC_ERR_NOT_SPD;
+        double ljj = sqrt(d);
+        L[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; i++) {
+            double s = L[(size_t)i * n + j];
+            for (int k = 0; k < j; k++) s -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = s / ljj;
+        }
+    }
+    return ORC_OK;
+}
+
+static void chol_solve(int n, const double *L, const double *b, double *x) {
+    for (int i = 0; i < n; i++) {
+        double s = b[i];
+        for (int k = 0; k < i; k++) s -= L[(size_t)i * n + k] * x[k];
+        x[i] = s / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; i--) {
+        double s = x[i];
+        for (int k = i + 1; k < n; k++) s -= L[(size_t)k * n + i] * x[k];
+        x[i] = s / L[(size_t)i * n + i];
+    }
+}
+
+/*
+ * One level of coarsening by `sweeps` matching sweeps (Section "Aggregation
+ * strategies"). Sweep 1 matches the graph of S = diag(w) A diag(w); sweep
+ * s+1 matches the graph of the block sums of S over the aggregates of sweep
+ * s (the tentative Galerkin operator of the previous sweeps, up to the
+ * normalisation, which the edge weight does not see). The final aggregates
+ * are numbered by ascending smallest level-l member.
+ */
+static int coarsen(const csr *A, const double *w, int sweeps, int *agg, int *nc_out) {
+    int n = A->n;
+    /* S = diag(w) A diag(w) */
+    int *ident = malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    for (int i = 0; i < n; i++) { ident[i] = i; agg[i] = i; }
+    csr S;
+    int st = galerkin(A, ident, n, w, &S);
+    free(ident);
+    if (st) return st;
+    double *one = NULL;
+    int ncur = n;
+    for (int s = 0; s < sweeps; s++) {
+        int *mate = malloc(sizeof(int) * (size_t)(ncur > 0 ? ncur : 1));
+        int *a2 = malloc(sizeof(int) * (size_t)(ncur > 0 ? ncur : 1));
+        orc_match(ncur, S.rp, S.ci, S.v, mate);
+        int nnew = pairs_to_aggregates(ncur, mate, a2);
+        for (int i = 0; i < n; i++) agg[i] = a2[agg[i]];
+        if (s + 1 < sweeps) {
+            free(one);
+            one = malloc(sizeof(double) * (size_t)(ncur > 0 ? ncur : 1));
+            for (int i = 0; i < ncur; i++) one[i] = 1.0;
+            csr S2;
+            st = galerkin(&S, a2, nnew, one, &S2);
+            csr_free(&S);
+            if (st) { free(mate); free(a2); free(one); return st; }
+            S = S2;
+        }
+        free(mate); free(a2);
+        ncur = nnew;
+    }
+    csr_free(&S);
+    free(one);
+    /* renumber by ascending smallest member (kept explicit for clarity) */
+    int *ren = malloc(sizeof(int) * (size_t)(ncur > 0 ? ncur : 1));
+    for (int I = 0; I < ncur; I++) ren[I] = -1;
+    int nc = 0;
+    for (int i = 0; i < n; i++) {
+        if (ren[agg[i]] < 0) ren[agg[i]] = nc++;
+        agg[i] = ren[agg[i]];
+    }
+    free(ren);
+    *nc_out = nc;
+    return ORC_OK;
+}
+
+static int csr_copy(int n, const int *rp, const int *ci, const double *v, csr *a) {
+    long nnz = rp[n];
+    a->n = n;
+    a->rp = malloc(sizeof(int) * (size_t)(n + 1));
+    a->ci = malloc(sizeof(int) * (size_t)(nnz > 0 ? nnz : 1));
+    a->v = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!a->rp || !a->ci || !a->v) return ORC_ERR_OOM;
+    memcpy(a->rp, rp, sizeof(int) * (size_t)(n + 1));
+    memcpy(a->ci, ci, sizeof(int) * (size_t)nnz);
+    memcpy(a->v, v, sizeof(double) * (size_t)nnz);
+    return ORC_OK;
+}
+
+/*
+ * Hierarchy build. For each level: if n_l <= coarse_max it is the coarsest
+ * level and is factored by dense Cholesky. Otherwise aggregate, form
+ * w_{l+1}[I] = sqrt(sum_{i in I} w_i^2) (ascending members), the tentative
+ * prolongator value p_i = w_i / w_{l+1}[agg_i] (eq. prolongator: the column
+ * of an aggregate is w restricted to it, normalised), the Galerkin operator
+ * A_{l+1} = P^T A_l P (eq. amg context), and the l1-Jacobi diagonal.
+ * Stall guard: if n_{l+1} > 0.9 n_l, level l+1 becomes the coarsest when
+ * it has at most 2000 rows, else ORC_ERR_COARSEN.
+ */
+int orc_build(int n, const int *rp, const int *ci, const double *v,
+              int sweeps, int coarse_max, int max_levels, orc_hier **out) {
+    *out = NULL;
+    if (n <= 0 || sweeps < 1 || max_levels < 1 || max_levels > ORC_MAXLEV) return ORC_ERR_ARG;
+    orc_hier *h = calloc(1, sizeof(orc_hier));
+    h->sweeps = sweeps;
+    int st = csr_copy(n, rp, ci, v, &h->lev[0].A);
+    if (st) { orc_free(h); return st; }
+    h->lev[0].w = malloc(sizeof(double) * (size_t)n);
+    for (int i = 0; i < n; i++) h->lev[0].w[i] = 1.0;
+    h->nlev = 1;
+    for (int l = 0;; l++) {
+        orc_level *L = &h->lev[l];
+        int nl = L->A.n;
+        L->minv = malloc(sizeof(double) * (size_t)nl);
+        st = l1_diag_inv(&L->A, L->minv);
+        if (st) { orc_free(h); return st; }
+        int force_coarsest = (l + 1 >= max_levels);
+        if (l > 0) {
+            int nprev = h->lev[l - 1].A.n;
+            if ((double)nl > 0.9 * (double)nprev) {
+                if (nl <= 2000) force_coarsest = 1;
+                else { orc_free(h); return ORC_ERR_COARSEN; }
+            }
+        }
+        if (nl <= coarse_max || force_coarsest) {
+            L->nc = 0;
+            L->L = malloc(sizeof(double) * (size_t)nl * nl);
+            st = dense_cholesky(&L->A, L->L);
+            if (st) { orc_free(h); return st; }
+            break;
+        }
+        L->agg = malloc(sizeof(int) * (size_t)nl);
+        int nc = 0;
+        st = coarsen(&L->A, L->w, sweeps, L->agg, &nc);
+        if (st) { orc_free(h); return st; }
+        L->nc = nc;
+        orc_level *C = &h->lev[l + 1];
+        C->w = malloc(sizeof(double) * (size_t)nc);
+        for (int I = 0; I < nc; I++) C->w[I] = 0.0;
+        for (int i = 0; i < nl; i++) C->w[L->agg[i]] += L->w[i] * L->w[i];
+        for (int I = 0; I < nc; I++) C->w[I] = sqrt(C->w[I]);
+        L->p = malloc(sizeof(double) * (size_t)nl);
+        for (int i = 0; i < nl; i++) L->p[i] = L->w[i] / C->w[L->agg[i]];
+        st = galerkin(&L->A, L->agg, nc, L->p, &C->A);
+        if (st) { orc_free(h); return st; }
+        h->nlev = l + 2;
+    }
+    *out = h;
+    return ORC_OK;
+}
+
+int orc_nlevels(const orc_hier *h) { return h->nlev; }
+
+int orc_level_info(const orc_hier *h, int l, int *n, long long *nnz, int *nc) {
+    if (l < 0 || l >= h->nlev) return ORC_ERR_ARG;
+    const orc_level *L = &h->lev[l];
+    if (n) *n = L->A.n;
+    if (nnz) *nnz = L->A.rp[L->A.n];
+    if (nc) *nc = L->nc;
+    return ORC_OK;
+}
+
+/* Copy out level data; any pointer may be NULL. agg/p only below the coarsest. */
+int orc_level_get(const orc_hier *h, int l, int *rp, int *ci, double *v,
+                  int *agg, double *p, double *w, double *minv) {
+    if (l < 0 || l >= h->nlev) return ORC_ERR_ARG;
+    const orc_level *L = &h->lev[l];
+    int n = L->A.n;
+    long nnz = L->A.rp[n];
+    if (rp) memcpy(rp, L->A.rp, sizeof(int) * (size_t)(n + 1));
+    if (ci) memcpy(ci, L->A.ci, sizeof(int) * (size_t)nnz);
+    if (v) memcpy(v, L->A.v, sizeof(double) * (size_t)nnz);
+    if (agg && L->agg) memcpy(agg, L->agg, sizeof(int) * (size_t)n);
+    if (p && L->p) memcpy(p, L->p, sizeof(double) * (size_t)n);
+    if (w) memcpy(w, L->w, sizeof(double) * (size_t)n);
+    if (minv) memcpy(minv, L->minv, sizeof(double) * (size_t)n);
+    return ORC_OK;
+}
+
+int orc_coarse_factor(const orc_hier *h, double *Lout) {
+    const orc_level *L = &h->lev[h->nlev - 1];
+    int n = L->A.n;
+    memcpy(Lout, L->L, sizeof(double) * (size_t)n * n);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* V-cycle (eq. amg): one pre-sweep from a zero guess, coarse correction,   */
+/* one post-sweep; the coarsest level is solved exactly by Cholesky.        */
+/* ------------------------------------------------------------------------ */
+
+static void vcycle_level(const orc_hier *h, int l, const double *b, double *x) {
+    const orc_level *L = &h->lev[l];
+    int n = L->A.n;
+    if (l == h->nlev - 1) { chol_solve(n, L->L, b, x); return; }
+    int nc = L->nc;
+    double *r = malloc(sizeof(double) * (size_t)n);
+    double *bc = malloc(sizeof(double) * (size_t)nc);
+    double *xc = malloc(sizeof(double) * (size_t)nc);
+    /* pre-smoothing from x = 0: x = M^{-1} b */
+    for (int i = 0; i < n; i++) x[i] = L->minv[i] * b[i];
+    /* residual r = b - A x */
+    orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
+    for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
+    /* restriction b_c = P^T r (members of each aggregate ascending) */
+    for (int I = 0; I < nc; I++) bc[I] = 0.0;
+    for (int i = 0; i < n; i++) bc[L->agg[i]] += L->p[i] * r[i];
+    vcycle_level(h, l + 1, bc, xc);
+    /* prolongation and correction x += P x_c */
+    for (int i = 0; i < n; i++) x[i] += L->p[i] * xc[L->agg[i]];
+    /* post-smoothing x += M^{-1} (b - A x) */
+    orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
+    for (int i = 0; i < n; i++) x[i] += L->minv[i] * (b[i] - r[i]);
+    free(r); free(bc); free(xc);
+}
+
+void orc_vcycle(const orc_hier *h, const double *b, double *x) {
+    vcycle_level(h, 0, b, x);
+}
+
+/*
+ * The same V-cycle evaluated in FP32 (the mixed-precision form): the level
+ * operators, prolongator values and l1 diagonals are the FP64 ones rounded
+ * to nearest float, the input is rounded to float, every level operation is
+ * done in float, the coarsest solve is done in FP64 on the float input
+ * widened to double and rounded back to float, and the result is widened to
+ * double.
+ */
+static void vcycle32_level(const orc_hier *h, int l, const float *b, float *x) {
+    const orc_level *L = &h->lev[l];
+    int n = L->A.n;
+    if (l == h->nlev - 1) {
+        double *bd = malloc(sizeof(double) * (size_t)n);
+        double *xd = malloc(sizeof(double) * (size_t)n);
+        for (int i = 0; i < n; i++) bd[i] = (double)b[i];
+        chol_solve(n, L->L, bd, xd);
+        for (int i = 0; i < n; i++) x[i] = (float)xd[i];
+        free(bd); free(xd);
+        return;
+    }
+    int nc = L->nc;
+    float *r = malloc(sizeof(float) * (size_t)n);
+    float *bc = malloc(sizeof(float) * (size_t)nc);
+    float *xc = malloc(sizeof(float) * (size_t)nc);
+    for (int i = 0; i < n; i++) x[i] = (float)L->minv[i] * b[i];
+    for (int i = 0; i < n; i++) {
+        float s = 0.0f;
+        for (int k = L->A.rp[i]; k < L->A.rp[i + 1]; k++) s += (float)L->A.v[k] * x[L->A.ci[k]];
+        r[i] = b[i] - s;
+    }
+    for (int I = 0; I < nc; I++) bc[I] = 0.0f;
+    for (int i = 0; i < n; i++) bc[L->agg[i]] += (float)L->p[i] * r[i];
+    vcycle32_level(h, l + 1, bc, xc);
+    for (int i = 0; i < n; i++) x[i] += (float)L->p[i] * xc[L->agg[i]];
+    for (int i = 0; i < n; i++) {
+        float s = 0.0f;
+        for (int k = L->A.rp[i]; k < L->A.rp[i + 1]; k++) s += (float)L->A.v[k] * x[L->A.ci[k]];
+        r[i] = s;
+    }
+    for (int i = 0; i < n; i++) x[i] += (float)L->minv[i] * (b[i] - r[i]);
+    free(r); free(bc); free(xc);
+}
+
+void orc_vcycle32(const orc_hier *h, const double *b, double *x) {
+    int n = h->lev[0].A.n;
+    float *bf = malloc(sizeof(float) * (size_t)n);
+    float *xf = malloc(sizeof(float) * (size_t)n);
+    for (int i = 0; i < n; i++) bf[i] = (float)b[i];
+    vcycle32_level(h, 0, bf, xf);
+    for (int i = 0; i < n; i++) x[i] = (double)xf[i];
+    free(bf); free(xf);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Preconditioned CG (plain form)                                           */
+/* ------------------------------------------------------------------------ */
+
+#define ORC_PREC_VCYCLE 0
+#define ORC_PREC_NONE 1
+#define ORC_PREC_L1JACOBI 2
+#define ORC_PREC_JACOBI 3
+#define ORC_PREC_VCYCLE32 4
+
+static void apply_prec(const orc_hier *h, int prec, const double *r, double *z) {
+    const orc_level *L = &h->lev[0];
+    int n = L->A.n;
+    switch (prec) {
+    case ORC_PREC_VCYCLE: orc_vcycle(h, r, z); break;
+    case ORC_PREC_VCYCLE32: orc_vcycle32(h, r, z); break;
+    case ORC_PREC_NONE: memcpy(z, r, sizeof(double) * (size_t)n); break;
+    case ORC_PREC_L1JACOBI: for (int i = 0; i < n; i++) z[i] = L->minv[i] * r[i]; break;
+    default: /* Jacobi with diag(A) */
+        for (int i = 0; i < n; i++) {
+            double d = 1.0;
+            for (int k = L->A.rp[i]; k < L->A.rp[i + 1]; k++) if (L->A.ci[k] == i) d = L->A.v[k];
+            z[i] = r[i] / d;
+        }
+    }
+}
+
+/*
+ * PCG with x in/out as the initial guess. Stops when the recursive residual
+ * satisfies ||r||_2 <= rtol ||b||_2 (Section "Numerical Example": relative
+ * tolerance on the residual). relres is the true ||b - A x|| / ||b||.
+ * hist (optional, 2*maxit doubles): alpha_k, beta_k of each iteration.
+ */
+int orc_pcg(const orc_hier *h, int prec, const double *b, double *x, double rtol,
+            int maxit, int *iters, double *relres, double *hist) {
+    const orc_level *L = &h->lev[0];
+    int n = L->A.n;
+    double nb = sqrt(dot(n, b, b));
+    *iters = 0;
+    if (isnan(nb) || isinf(nb)) return ORC_ERR_NAN;
+    if (nb == 0.0) { for (int i = 0; i < n; i++) x[i] = 0.0; *relres = 0.0; return ORC_OK; }
+    double *r = malloc(sizeof(double) * (size_t)n), *z = malloc(sizeof(double) * (size_t)n);
+    double *p = malloc(sizeof(double) * (size_t)n), *q = malloc(sizeof(double) * (size_t)n);
+    orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, q);
+    for (int i = 0; i < n; i++) r[i] = b[i] - q[i];
+    int st = ORC_NOCONV, k = 0;
+    if (sqrt(dot(n, r, r)) <= rtol * nb) st = ORC_OK;
+    else {
+        apply_prec(h, prec, r, z);
+        memcpy(p, z, sizeof(double) * (size_t)n);
+        double rho = dot(n, r, z);
+        if (!(rho > 0.0)) st = isnan(rho) ? ORC_ERR_NAN : ORC_ERR_NOT_SPD;
+        while (st == ORC_NOCONV && k < maxit) {
+            orc_spmv(n, L->A.rp, L->A.ci, L->A.v, p, q);
+            double pq = dot(n, p, q);
+            if (!(pq > 0.0)) { st = isnan(pq) ? ORC_ERR_NAN : ORC_ERR_NOT_SPD; break; }
+            double alpha = rho / pq;
+            for (int i = 0; i < n; i++) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+            k++;
+            double rr = dot(n, r, r);
+            if (isnan(rr)) { st = ORC_ERR_NAN; break; }
+            if (hist) hist[2 * (k - 1)] = alpha;
+            if (sqrt(rr) <= rtol * nb) { st = ORC_OK; if (hist) hist[2 * (k - 1) + 1] = 0.0; break; }
+            apply_prec(h, prec, r, z);
+            double rho2 = dot(n, r, z);
+            if (!(rho2 > 0.0)) { st = isnan(rho2) ? ORC_ERR_NAN : ORC_ERR_NOT_SPD; break; }
+            double beta = rho2 / rho;
+            if (hist) hist[2 * (k - 1) + 1] = beta;
+            for (int i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
+            rho = rho2;
+        }
+    }
+    *iters = k;
+    orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, q);
+    for (int i = 0; i < n; i++) r[i] = b[i] - q[i];
+    *relres = sqrt(dot(n, r, r)) / nb;
+    free(r); free(z); free(p); free(q);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Learned preconditioner: 3-layer 3x3x3 convolutional network              */
+/* ------------------------------------------------------------------------ */
+/*
+ * Parity unpinned by the paper (the network is not part of it); pinned by
+ * the tests against a library convolution, central finite differences and
+ * closed-form Adam special cases.
+ *
+ * Parameters (C = 16 channels): W1[C][1][27] b1[C] W2[C][C][27] b2[C]
+ * W3[1][C][27] b3[1]; tap t = (dz*3+dy)*3+dx acts at offset (dz-1,dy-1,dx-1).
+ * A field of B samples, each D x H x W (x fastest), zero outside.
+ *   h1 = GELU(conv1(u) + b1), h2 = GELU(conv2(h1) + b2), out = conv3(h2) + b3
+ * GELU(t) = t * Phi(t) = 0.5 t (1 + erf(t / sqrt 2)).
+ * With round_bf16 set, u, h1 and h2 (and the weights) are rounded to
+ * bfloat16 (round to nearest even, via float) before the convolution that
+ * reads them; sums are formed in double.
+ */
+
+#define NET_C 16
+#define NET_P (NET_C * 27 + NET_C + NET_C * NET_C * 27 + NET_C + NET_C * 27 + 1)
+
+int orc_net_param_count(void) { return NET_P; }
+
+double orc_bf16(double x) {
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) {          /* inf / nan: truncate, keep nan quiet */
+        if (u & 0x007fffffu) u |= 0x00400000u;
+        u &= 0xffff0000u;
+    } else {
+        uint32_t lsb = (u >> 16) & 1u;
+        u += 0x7fffu + lsb;
+        u &= 0xffff0000u;
+    }
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+static double gelu(double t) { return 0.5 * t * (1.0 + erf(t / sqrt(2.0))); }
+static double gelu_d(double t) {
+    return 0.5 * (1.0 + erf(t / sqrt(2.0))) + t * exp(-0.5 * t * t) / sqrt(2.0 * M_PI);
+}
+
+/* out[co] = bias[co] + sum_ci sum_t W[co][ci][t] * in[ci](cell + off_t) */
+static void conv3(int cin, int cout, const double *W, const double *bias,
+                  int D, int H, int Wd, const double *in, double *out) {
+    size_t cells = (size_t)D * H * Wd;
+    for (int co = 0; co < cout; co++)
+        for (int z = 0; z < D; z++)
+            for (int y = 0; y < H; y++)
+                for (int x = 0; x < Wd; x++) {
+                    double s = bias ? bias[co] : 0.0;
+                    for (int ci = 0; ci < cin; ci++)
+                        for (int t = 0; t < 27; t++) {
+                            int zz = z + t / 9 - 1, yy = y + (t / 3) % 3 - 1, xx = x + t % 3 - 1;
+                            if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= Wd) continue;
+                            s += W[((size_t)co * cin + ci) * 27 + t] *
+                                 in[(size_t)ci * cells + ((size_t)zz * H + yy) * Wd + xx];
+                        }
+                    out[(size_t)co * cells + ((size_t)z * H + y) * Wd + x] = s;
+                }
+}
+
+typedef struct {
+    const double *W1, *b1, *W2, *b2, *W3, *b3;
+    double *buf;    /* rounded weight copy */
+} netw;
+
+static void net_split(const double *params, int round_bf16, netw *nw) {
+    nw->buf = malloc(sizeof(double) * NET_P);
+    for (int i = 0; i < NET_P; i++) nw->buf[i] = round_bf16 ? orc_bf16(params[i]) : params[i];
+    /* biases stay FP32-exact: only weight taps are rounded */
+    const double *q = nw->buf;
+    nw->W1 = q; q += NET_C * 27;
+    nw->b1 = params + (q - nw->buf); q += NET_C;
+    nw->W2 = q; q += NET_C * NET_C * 27;
+    nw->b2 = params + (q - nw->buf); q += NET_C;
+    nw->W3 = q; q += NET_C * 27;
+    nw->b3 = params + (q - nw->buf);
+}
+
+/*
+ * Forward pass for B samples of D x H x W. in: B*cells, out: B*cells.
+ * act (optional, 2*B*C*cells + 2*B*C*cells doubles): pre-activations a1, a2
+ * and rounded activations h1, h2 per sample, kept for the backward pass.
+ */
+void orc_net_forward(const double *params, int round_bf16, int B, int D, int H, int Wd,
+                     const double *in, double *out, double *act) {
+    size_t cells = (size_t)D * H * Wd;
+    netw nw;
+    net_split(params, round_bf16, &nw);
+    double *u = malloc(sizeof(double) * cells);
+    double *a1 = malloc(sizeof(double) * NET_C * cells), *h1 = malloc(sizeof(double) * NET_C * cells);
+    double *a2 = malloc(sizeof(double) * NET_C * cells), *h2 = malloc(sizeof(double) * NET_C * cells);
+    for (int b = 0; b < B; b++) {
+        const double *ib = in + (size_t)b * cells;
+        for (size_t c = 0; c < cells; c++) u[c] = round_bf16 ? orc_bf16(ib[c]) : ib[c];
+        conv3(1, NET_C, nw.W1, nw.b1, D, H, Wd, u, a1);
+        for (size_t c = 0; c < NET_C * cells; c++) {
+            double g = gelu(a1[c]);
+            h1[c] = round_bf16 ? orc_bf16(g) : g;
+        }
+        conv3(NET_C, NET_C, nw.W2, nw.b2, D, H, Wd, h1, a2);
+        for (size_t c = 0; c < NET_C * cells; c++) {
+            double g = gelu(a2[c]);
+            h2[c] = round_bf16 ? orc_bf16(g) : g;
+        }
+        conv3(NET_C, 1, nw.W3, nw.b3, D, H, Wd, h2, out + (size_t)b * cells);
+        if (act) {
+            double *ab = act + (size_t)b * 4 * NET_C * cells;
+            memcpy(ab, a1, sizeof(double) * NET_C * cells);
+            memcpy(ab + NET_C * cells, h1, sizeof(double) * NET_C * cells);
+            memcpy(ab + 2 * NET_C * cells, a2, sizeof(double) * NET_C * cells);
+            memcpy(ab + 3 * NET_C * cells, h2, sizeof(double) * NET_C * cells);
+        }
+    }
+    free(u); free(a1); free(h1); free(a2); free(h2); free(nw.buf);
+}
+
+/* gin[ci] += sum_co sum_t W[co][ci][t] * gout[co](cell - off_t) (transpose conv) */
+static void conv3_dgrad(int cin, int cout, const double *W, int D, int H, int Wd,
+                        const double *gout, double *gin) {
+    size_t cells = (size_t)D * H * Wd;
+    for (size_t c = 0; c < (size_t)cin * cells; c++) gin[c] = 0.0;
+    for (int co = 0; co < cout; co++)
+        for (int z = 0; z < D; z++)
+            for (int y = 0; y < H; y++)
+                for (int x = 0; x < Wd; x++) {
+                    double g = gout[(size_t)co * cells + ((size_t)z * H + y) * Wd + x];
+                    if (g == 0.0) continue;
+                    for (int ci = 0; ci < cin; ci++)
+                        for (int t = 0; t < 27; t++) {
+                            int zz = z + t / 9 - 1, yy = y + (t / 3) % 3 - 1, xx = x + t % 3 - 1;
+                            if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= Wd) continue;
+                            gin[(size_t)ci * cells + ((size_t)zz * H + yy) * Wd + xx] +=
+                                W[((size_t)co * cin + ci) * 27 + t] * g;
+                        }
+                }
+}
+
+/* gW[co][ci][t] += sum_cell gout[co](cell) * in[ci](cell + off_t); gb[co] += sum gout */
+static void conv3_wgrad(int cin, int cout, int D, int H, int Wd, const double *in,
+                        const double *gout, double *gW, double *gb) {
+    size_t cells = (size_t)D * H * Wd;
+    for (int co = 0; co < cout; co++)
+        for (int z = 0; z < D; z++)
+            for (int y = 0; y < H; y++)
+                for (int x = 0; x < Wd; x++) {
+                    double g = gout[(size_t)co * cells + ((size_t)z * H + y) * Wd + x];
+                    gb[co] += g;
+                    for (int ci = 0; ci < cin; ci++)
+                        for (int t = 0; t < 27; t++) {
+                            int zz = z + t / 9 - 1, yy = y + (t / 3) % 3 - 1, xx = x + t % 3 - 1;
+                            if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= Wd) continue;
+                            gW[((size_t)co * cin + ci) * 27 + t] +=
+                                g * in[(size_t)ci * cells + ((size_t)zz * H + yy) * Wd + xx];
+                        }
+                }
+}
+
+/*
+ * Loss and gradient: loss = mean over samples and interior cells (those at
+ * least `margin` cells from every face) of (out - target)^2. The rounding
+ * to bfloat16 is treated as the identity in the backward pass. grad (NET_P
+ * doubles) receives d loss / d params. Returns the loss.
+ */
+double orc_net_loss_grad(const double *params, int round_bf16, int B, int D, int H, int Wd,
+                         const double *in, const double *target, int margin, double *grad) {
+    size_t cells = (size_t)D * H * Wd;
+    double *out = malloc(sizeof(double) * (size_t)B * cells);
+    double *act = malloc(sizeof(double) * (size_t)B * 4 * NET_C * cells);
+    orc_net_forward(params, round_bf16, B, D, H, Wd, in, out, act);
+    netw nw;
+    net_split(params, round_bf16, &nw);
+    size_t cnt = (size_t)B * (D - 2 * margin) * (H - 2 * margin) * (Wd - 2 * margin);
+    double loss = 0.0;
+    double *g3 = malloc(sizeof(double) * cells);
+    double *g2 = malloc(sizeof(double) * NET_C * cells), *g1 = malloc(sizeof(double) * NET_C * cells);
+    double *u = malloc(sizeof(double) * cells);
+    if (grad) for (int i = 0; i < NET_P; i++) grad[i] = 0.0;
+    double *gW1 = grad, *gb1 = grad ? grad + NET_C * 27 : NULL;
+    double *gW2 = grad ? gb1 + NET_C : NULL, *gb2 = grad ? gW2 + NET_C * NET_C * 27 : NULL;
+    double *gW3 = grad ? gb2 + NET_C : NULL, *gb3 = grad ? gW3 + NET_C * 27 : NULL;
+    for (int b = 0; b < B; b++) {
+        const double *ob = out + (size_t)b * cells, *tb = target + (size_t)b * cells;
+        for (int z = 0; z < D; z++)
+            for (int y = 0; y < H; y++)
+                for (int x = 0; x < Wd; x++) {
+                    size_t c = ((size_t)z * H + y) * Wd + x;
+                    int in_ = z >= margin && z < D - margin && y >= margin && y < H - margin &&
+                              x >= margin && x < Wd - margin;
+                    double d = in_ ? ob[c] - tb[c] : 0.0;
+                    loss += d * d;
+                    g3[c] = 2.0 * d / (double)cnt;
+                }
+        if (!grad) continue;
+        const double *ab = act + (size_t)b * 4 * NET_C * cells;
+        const double *a1 = ab, *h1 = ab + NET_C * cells, *a2 = ab + 2 * NET_C * cells, *h2 = ab + 3 * NET_C * cells;
+        conv3_wgrad(NET_C, 1, D, H, Wd, h2, g3, gW3, gb3);
+        conv3_dgrad(NET_C, 1, nw.W3, D, H, Wd, g3, g2);
+        for (size_t c = 0; c < NET_C * cells; c++) g2[c] *= gelu_d(a2[c]);
+        conv3_wgrad(NET_C, NET_C, D, H, Wd, h1, g2, gW2, gb2);
+        conv3_dgrad(NET_C, NET_C, nw.W2, D, H, Wd, g2, g1);
+        for (size_t c = 0; c < NET_C * cells; c++) g1[c] *= gelu_d(a1[c]);
+        const double *ib = in + (size_t)b * cells;
+        for (size_t c = 0; c < cells; c++) u[c] = round_bf16 ? orc_bf16(ib[c]) : ib[c];
+        conv3_wgrad(1, NET_C, D, H, Wd, u, g1, gW1, gb1);
+    }
+    free(out); free(act); free(g3); free(g2); free(g1); free(u); free(nw.buf);
+    return loss / (double)cnt;
+}
+
+/*
+ * One Adam step (t = 1-based step count): m = b1 m + (1-b1) g;
+ * v = b2 v + (1-b2) g^2; p -= lr * (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps).
+ */
+void orc_adam_step(int np, double *p, double *m, double *v, const double *g, int t,
+                   double lr, double b1, double b2, double eps) {
+    double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+    for (int i = 0; i < np; i++) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        p[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}
+
+/* z = s * net(r / s), s = ||r||_2 / sqrt(N), on one nx x ny x nz grid. */
+void orc_net_apply(const double *params, int nx, int ny, int nz, const double *r, double *z) {
+    size_t N = (size_t)nx * ny * nz;
+    double s = sqrt(dot((int)N, r, r) / (double)N);
+    if (s == 0.0) { for (size_t i = 0; i < N; i++) z[i] = 0.0; return; }
+    double *u = malloc(sizeof(double) * N);
+    for (size_t i = 0; i < N; i++) u[i] = r[i] / s;
+    orc_net_forward(params, 1, 1, nz, ny, nx, u, z, NULL);
+    for (size_t i = 0; i < N; i++) z[i] *= s;
+    free(u);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Flexible CG, FCG(1)                                                      */
+/* ------------------------------------------------------------------------ */
+/*
+ * Flexible CG (Section "Numerical Example" uses FCG) with one stored
+ * direction: z = B_k r; p = z - ((z.q_prev)/(p_prev.q_prev)) p_prev;
+ * q = A p; alpha = (p.r)/(p.q); x += alpha p; r -= alpha q.
+ * When the recursive residual passes ||r|| <= rtol ||b||, the true residual
+ * b - A x is formed; if it also passes the solve ends, otherwise r is
+ * replaced by it and the direction history restarts.
+ *
+ * B_k: form 0 = FP64 V-cycle, form 1 = FP32 V-cycle (orc_vcycle32).
+ * With params != NULL (learned form), iterations k = 1, 3, 5, ... use the
+ * network z = s net(r/s) instead; if z.r <= 0 that step takes the V-cycle
+ * instead; if after a network step ||r_new|| > 0.9 ||r_old||, the network
+ * is switched off for the rest of the solve. *fallbacks counts scheduled
+ * network steps that ran the V-cycle instead.
+ */
+int orc_fcg(const orc_hier *h, int form, const double *params, int nx, int ny, int nz,
+            const double *b, double *x, double rtol, int maxit, int *iters, double *relres,
+            int *fallbacks) {
+    const orc_level *L = &h->lev[0];
+    int n = L->A.n;
+    double nb = sqrt(dot(n, b, b));
+    *iters = 0;
+    if (fallbacks) *fallbacks = 0;
+    if (isnan(nb) || isinf(nb)) return ORC_ERR_NAN;
+    if (nb == 0.0) { for (int i = 0; i < n; i++) x[i] = 0.0; *relres = 0.0; return ORC_OK; }
+    if (params && (size_t)nx * ny * nz != (size_t)n) return ORC_ERR_ARG;
+    double *r = malloc(sizeof(double) * (size_t)n), *z = malloc(sizeof(double) * (size_t)n);
+    double *p = malloc(sizeof(double) * (size_t)n), *q = malloc(sizeof(double) * (size_t)n);
+    double *pp = malloc(sizeof(double) * (size_t)n), *qp = malloc(sizeof(double) * (size_t)n);
+    orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, q);
+    for (int i = 0; i < n; i++) r[i] = b[i] - q[i];
+    int st = ORC_NOCONV, k = 0, have_prev = 0, net_on = params != NULL;
+    double pqp = 0.0;
+    if (sqrt(dot(n, r, r)) <= rtol * nb) st = ORC_OK;
+    while (st == ORC_NOCONV && k < maxit) {
+        int use_net = net_on && (k % 2 == 1);
+        int vform = form == 1 ? ORC_PREC_VCYCLE32 : ORC_PREC_VCYCLE;
+        if (use_net) {
+            orc_net_apply(params, nx, ny, nz, r, z);
+            if (!(dot(n, z, r) > 0.0)) {
+                apply_prec(h, vform, r, z);
+                use_net = 0;
+                if (fallbacks) (*fallbacks)++;
+            }
+        } else {
+            if (params && !net_on && k % 2 == 1 && fallbacks) (*fallbacks)++;
+            apply_prec(h, vform, r, z);
+        }
+        if (have_prev) {
+            double beta = dot(n, z, qp) / pqp;
+            for (int i = 0; i < n; i++) p[i] = z[i] - beta * pp[i];
+        } else {
+            memcpy(p, z, sizeof(double) * (size_t)n);
+        }
+        orc_spmv(n, L->A.rp, L->A.ci, L->A.v, p, q);
+        double pq = dot(n, p, q);
+        if (isnan(pq)) { st = ORC_ERR_NAN; break; }
+        if (!(pq > 0.0)) { st = ORC_ERR_NOT_SPD; break; }
+        double rr_old = dot(n, r, r);
+        double alpha = dot(n, p, r) / pq;
+        for (int i = 0; i < n; i++) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+        k++;
+        double rr = dot(n, r, r);
+        if (isnan(rr)) { st = ORC_ERR_NAN; break; }
+        if (use_net && sqrt(rr) > 0.9 * sqrt(rr_old)) net_on = 0;
+        memcpy(pp, p, sizeof(double) * (size_t)n);
+        memcpy(qp, q, sizeof(double) * (size_t)n);
+        pqp = pq;
+        have_prev = 1;
+        if (sqrt(rr) <= rtol * nb) {
+            orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, q);
+            for (int i = 0; i < n; i++) q[i] = b[i] - q[i];
+            if (sqrt(dot(n, q, q)) <= rtol * nb) { st = ORC_OK; break; }
+            memcpy(r, q, sizeof(double) * (size_t)n);
+            have_prev = 0;
+        }
+    }
+    *iters = k;
+    orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, q);
+    for (int i = 0; i < n; i++) r[i] = b[i] - q[i];
+    *relres = sqrt(dot(n, r, r)) / nb;
+    free(r); free(z); free(p); free(q); free(pp); free(qp);
+    return st;
+}

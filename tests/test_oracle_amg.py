@@ -1,0 +1,461 @@
+"""Pins for the CPU oracle's AMG hierarchy, V-cycle and Krylov loops.
+
+Each check ties the oracle to something other than itself: closed forms of
+the 7-point operator, dense linear algebra (numpy), brute-force matchings,
+scipy's CG, the V-cycle's error-propagation formula (eq. amg) and an
+operator complexity printed in the paper.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle
+from paper_2406_19754_amd import problems as P
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dense(rp, c, v):
+    n = len(rp) - 1
+    return sp.csr_matrix((v, c, rp), shape=(n, n)).toarray()
+
+
+def prolongator(lev):
+    n, nc = lev["n"], lev["nc"]
+    return sp.csr_matrix((lev["p"], (np.arange(n), lev["agg"])), shape=(n, nc)).toarray()
+
+
+# --------------------------------------------------------------------------
+# SpMV
+# --------------------------------------------------------------------------
+
+def test_spmv_matches_dense_product():
+    rp, c, v = P.poisson7(6)
+    x = np.random.default_rng(0).standard_normal(216)
+    np.testing.assert_allclose(oracle.spmv(rp, c, v, x), dense(rp, c, v) @ x, rtol=0, atol=1e-13)
+    rp, c, v = P.random_spd_csr(150, 1, density=0.03, maxrow=60)
+    x = np.random.default_rng(1).standard_normal(150)
+    np.testing.assert_allclose(oracle.spmv(rp, c, v, x), dense(rp, c, v) @ x, rtol=1e-14, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Matching
+# --------------------------------------------------------------------------
+
+def _edges(rp, c, S):
+    n = len(rp) - 1
+    d = np.zeros(n)
+    for i in range(n):
+        for k in range(rp[i], rp[i + 1]):
+            if c[k] == i:
+                d[i] = S[k]
+    E = {}
+    for i in range(n):
+        for k in range(rp[i], rp[i + 1]):
+            j = c[k]
+            j = int(j)
+            if j > i:
+                cij = 1.0 - 2.0 * S[k] / (d[i] + d[j])
+                q = int(round(cij * 2 ** 30))  # values here are never exact halves
+                if q > 0:
+                    E[(i, j)] = q
+    return E
+
+
+def _brute_max_weight(n, E):
+    adj = {i: [] for i in range(n)}
+    for (i, j), q in E.items():
+        adj[int(i)].append((int(j), q))
+        adj[int(j)].append((int(i), q))
+    memo = {}
+
+    def f(mask):
+        if mask == 0:
+            return 0
+        if mask in memo:
+            return memo[mask]
+        i = (mask & -mask).bit_length() - 1
+        best = f(mask & ~(1 << i))
+        for j, q in adj[i]:
+            if mask >> j & 1:
+                best = max(best, q + f(mask & ~(1 << i) & ~(1 << j)))
+        memo[mask] = best
+        return best
+
+    return f((1 << n) - 1)
+
+
+def _locally_dominant(n, E):
+    """Independent matching: repeatedly match mutually-heaviest free pairs."""
+    key = {e: (-q, e[0], e[1]) for e, q in E.items()}
+    mate = [-1] * n
+    nbrs = {i: [] for i in range(n)}
+    for (i, j) in E:
+        nbrs[i].append(j)
+        nbrs[j].append(i)
+    changed = True
+    while changed:
+        changed = False
+        cand = [-1] * n
+        for i in range(n):
+            if mate[i] >= 0:
+                continue
+            best = None
+            for j in nbrs[i]:
+                if mate[j] >= 0:
+                    continue
+                e = (min(i, j), max(i, j))
+                if best is None or key[e] < key[best]:
+                    best = e
+            if best is not None:
+                cand[i] = best[0] if best[1] == i else best[1]
+        for i in range(n):
+            j = cand[i]
+            if j > i and cand[j] == i:
+                mate[i], mate[j] = j, i
+                changed = True
+    return np.array(mate)
+
+
+def _random_graph(n, seed, levels=None):
+    rng = np.random.default_rng(seed)
+    A = np.zeros((n, n))
+    for i in range(n):
+        for j in range(i + 1, n):
+            if rng.random() < 0.45:
+                val = -rng.integers(1, levels + 1) if levels else -rng.uniform(0.05, 2.0)
+                A[i, j] = A[j, i] = val
+    A[np.arange(n), np.arange(n)] = np.abs(A).sum(1) + (rng.integers(1, 4, n) if levels else rng.uniform(0.1, 2, n))
+    rp = np.zeros(n + 1, np.int32)
+    cols, vals = [], []
+    for i in range(n):
+        nz = np.nonzero(A[i])[0]
+        cols += list(nz)
+        vals += list(A[i, nz])
+        rp[i + 1] = len(cols)
+    return rp, np.array(cols, np.int32), np.array(vals)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_matching_half_approx_and_locally_dominant(seed):
+    n = 6 + seed % 7                     # 6..12 vertices
+    rp, c, S = _random_graph(n, seed, levels=2 if seed % 2 else None)  # even seeds: ties
+    mate = oracle.match(rp, c, S)
+    E = _edges(rp, c, S)
+    # a valid matching on eligible edges
+    for i in range(n):
+        if mate[i] >= 0:
+            assert mate[mate[i]] == i and (min(i, mate[i]), max(i, mate[i])) in E
+    # maximal: no eligible edge with both ends free
+    for (i, j) in E:
+        assert mate[i] >= 0 or mate[j] >= 0
+    w = sum(q for (i, j), q in E.items() if mate[i] == j)
+    assert 2 * w >= _brute_max_weight(n, E)
+    assert np.array_equal(mate, _locally_dominant(n, E))
+
+
+def test_matching_ignores_nonpositive_weights():
+    # a_01 = +4 with a_00 = a_11 = 4 -> c = 1 - 2*4/8 = 0 -> not eligible
+    rp = np.array([0, 2, 4], np.int32)
+    c = np.array([0, 1, 0, 1], np.int32)
+    S = np.array([4.0, 4.0, 4.0, 4.0])
+    assert list(oracle.match(rp, c, S)) == [-1, -1]
+    S = np.array([4.0, -1.0, -1.0, 4.0])
+    assert list(oracle.match(rp, c, S)) == [1, 0]
+    assert oracle.edge_key(-1.0, 6.0, 6.0) == round(7.0 / 6.0 * 2 ** 30)
+
+
+def test_poisson_first_sweep_is_x_pairs():
+    n = 8
+    rp, c, v = P.poisson7(n)
+    mate = oracle.match(rp, c, v)
+    assert np.array_equal(mate, np.arange(n ** 3) ^ 1)
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_poisson_aggregates_are_2x2x1_blocks(n):
+    rp, c, v = P.poisson7(n)
+    h = oracle.Hierarchy(rp, c, v)
+    agg = h.level(0)["agg"]
+    idx = np.arange(n ** 3)
+    i, j, k = idx % n, (idx // n) % n, idx // (n * n)
+    m = n // 2
+    assert np.array_equal(agg, (i // 2) + m * ((j // 2) + m * k))
+
+
+# --------------------------------------------------------------------------
+# Hierarchy
+# --------------------------------------------------------------------------
+
+def test_poisson_level1_closed_form():
+    n = 8
+    rp, c, v = P.poisson7(n)
+    h = oracle.Hierarchy(rp, c, v)
+    L1 = h.level(1)
+    A1 = dense(L1["rowptr"], L1["col"], L1["val"])
+    m = n // 2
+    N1 = m * m * n
+    ref = np.zeros((N1, N1))
+    for I in range(N1):
+        a, b, k = I % m, (I // m) % m, I // (m * m)
+        ref[I, I] = 4.0
+        if a > 0: ref[I, I - 1] = -0.5
+        if a < m - 1: ref[I, I + 1] = -0.5
+        if b > 0: ref[I, I - m] = -0.5
+        if b < m - 1: ref[I, I + m] = -0.5
+        if k > 0: ref[I, I - m * m] = -1.0
+        if k < n - 1: ref[I, I + m * m] = -1.0
+    np.testing.assert_allclose(A1, ref, rtol=0, atol=1e-15)
+    # the closed form reaches every nonzero and no more
+    assert L1["nnz"] == np.count_nonzero(ref)
+
+
+@pytest.mark.parametrize("n,sizes", [(32, [32768, 8192, 2048, 512, 128]),
+                                     (64, [262144, 65536, 16384, 4096, 1024, 256, 64])])
+def test_poisson_level_sizes_and_complexity(n, sizes):
+    rp, c, v = P.poisson7(n)
+    h = oracle.Hierarchy(rp, c, v)
+    assert h.sizes() == sizes
+    # tentative aggregates of 4: complexity -> 4/3 from below
+    oc = h.operator_complexity()
+    assert 1.30 < oc < 4.0 / 3.0
+
+
+def _check_invariants(h, tol=1e-13):
+    for l in range(h.nlevels - 1):
+        L = h.level(l)
+        C = h.level(l + 1)
+        agg = L["agg"]
+        n, nc = L["n"], L["nc"]
+        assert nc == C["n"]
+        assert agg.min() == 0 and agg.max() == nc - 1          # every aggregate non-empty
+        counts = np.bincount(agg, minlength=nc)
+        assert counts.max() <= 4 and counts.min() >= 1         # each row in one aggregate, size <= 4
+        # numbering by ascending smallest member
+        first = np.full(nc, n)
+        np.minimum.at(first, agg, np.arange(n))
+        assert np.all(np.diff(first) > 0)
+        Pm = prolongator(L)
+        np.testing.assert_allclose(Pm.T @ Pm, np.eye(nc), rtol=0, atol=tol)
+        w = L["w"]
+        np.testing.assert_allclose(Pm @ (Pm.T @ w), w, rtol=0, atol=tol * np.abs(w).max())
+        np.testing.assert_allclose(C["w"], Pm.T @ w, rtol=1e-14, atol=0)
+        A = dense(L["rowptr"], L["col"], L["val"])
+        Ac = dense(C["rowptr"], C["col"], C["val"])
+        scale = np.abs(A).max()
+        np.testing.assert_allclose(Ac, Pm.T @ A @ Pm, rtol=0, atol=tol * scale)
+        assert np.abs(Ac - Ac.T).max() <= 1e-14 * np.abs(Ac).max()
+        vc = np.random.default_rng(l).standard_normal(nc)
+        e1 = vc @ Ac @ vc
+        e2 = (Pm @ vc) @ A @ (Pm @ vc)
+        assert abs(e1 - e2) <= 1e-12 * abs(e2)
+        if nc <= 1500:
+            assert np.linalg.eigvalsh(Ac).min() > 0
+
+
+@pytest.mark.parametrize("case", ["poisson12", "poisson9odd", "diffusion10", "random"])
+def test_hierarchy_invariants(case):
+    if case == "poisson12":
+        rp, c, v = P.poisson7(12)
+    elif case == "poisson9odd":
+        rp, c, v = P.poisson7(9)
+    elif case == "diffusion10":
+        rp, c, v = P.diffusion7(10, seed=1, az=100.0)
+    else:
+        rp, c, v = P.random_spd_csr(400, 7, density=0.02, maxrow=40)
+    h = oracle.Hierarchy(rp, c, v, coarse_max=40)
+    assert h.nlevels >= 2
+    _check_invariants(h)
+
+
+def test_coarse_cholesky_factor():
+    rp, c, v = P.poisson7(8)
+    h = oracle.Hierarchy(rp, c, v)
+    Lc = h.level(h.nlevels - 1)
+    A = dense(Lc["rowptr"], Lc["col"], Lc["val"])
+    Lf = h.coarse_factor()
+    assert np.allclose(np.triu(Lf, 1), 0)
+    np.testing.assert_allclose(Lf @ Lf.T, A, rtol=0, atol=1e-13)
+
+
+def test_l1_jacobi_closed_form_and_convergence():
+    n = 6
+    rp, c, v = P.poisson7(n)
+    h = oracle.Hierarchy(rp, c, v, coarse_max=20)
+    L0 = h.level(0)
+    idx = np.arange(n ** 3)
+    i, j, k = idx % n, (idx // n) % n, idx // (n * n)
+    nb = sum(((a > 0).astype(int) + (a < n - 1).astype(int)) for a in (i, j, k))
+    np.testing.assert_allclose(L0["minv"], 1.0 / (6.0 + nb), rtol=0, atol=1e-16)
+    assert set(np.unique(1.0 / L0["minv"])) == {9.0, 10.0, 11.0, 12.0}
+    for l in range(h.nlevels):
+        L = h.level(l)
+        A = dense(L["rowptr"], L["col"], L["val"])
+        d = np.sqrt(L["minv"])
+        ev = np.linalg.eigvalsh(d[:, None] * A * d[None, :])   # spectrum of M^-1 A
+        assert ev.min() > 0 and ev.max() <= 1.0 + 1e-14
+
+
+# --------------------------------------------------------------------------
+# V-cycle
+# --------------------------------------------------------------------------
+
+def test_vcycle_two_level_matches_error_propagation_formula():
+    n = 8
+    rp, c, v = P.poisson7(n)
+    h = oracle.Hierarchy(rp, c, v)
+    assert h.sizes() == [512, 128]
+    L0, L1 = h.level(0), h.level(1)
+    A = dense(rp, c, v)
+    Ac = dense(L1["rowptr"], L1["col"], L1["val"])
+    Pm = prolongator(L0)
+    Mi = np.diag(L0["minv"])
+    I = np.eye(512)
+    E = (I - Mi @ A) @ (I - Pm @ np.linalg.solve(Ac, Pm.T @ A)) @ (I - Mi @ A)
+    Bref = (I - E) @ np.linalg.inv(A)
+    B = np.stack([h.vcycle(I[:, j]) for j in range(512)], axis=1)
+    np.testing.assert_allclose(B, Bref, rtol=0, atol=1e-12)
+    assert np.abs(B - B.T).max() < 1e-13
+    assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
+
+
+def test_vcycle_multilevel_symmetric_positive():
+    rp, c, v = P.poisson7(16)
+    h = oracle.Hierarchy(rp, c, v, coarse_max=30)
+    assert h.nlevels >= 3
+    rng = np.random.default_rng(0)
+    u, w = rng.standard_normal(16 ** 3), rng.standard_normal(16 ** 3)
+    assert abs(u @ h.vcycle(w) - w @ h.vcycle(u)) <= 1e-12 * abs(u @ h.vcycle(w)) + 1e-14
+    for _ in range(3):
+        z = rng.standard_normal(16 ** 3)
+        assert z @ h.vcycle(z) > 0
+
+
+def test_vcycle32_close_to_vcycle64():
+    rp, c, v = P.poisson7(24)
+    h = oracle.Hierarchy(rp, c, v)
+    r = np.random.default_rng(2).standard_normal(24 ** 3)
+    z64, z32 = h.vcycle(r), h.vcycle32(r)
+    err = np.linalg.norm(z32 - z64) / np.linalg.norm(z64)
+    assert 0 < err <= 1e-5
+
+
+# --------------------------------------------------------------------------
+# Krylov
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5])
+def test_single_level_pcg_is_exact_in_one_iteration(n):
+    rp, c, v = P.poisson7(n)
+    h = oracle.Hierarchy(rp, c, v)
+    assert h.nlevels == 1
+    b = P.rhs_uniform(n ** 3, 9)
+    r = h.pcg(b, rtol=1e-10)
+    assert r["status"] == oracle.OK and r["iters"] == 1
+    ref = np.linalg.solve(dense(rp, c, v), b)
+    np.testing.assert_allclose(r["x"], ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_jacobi_pcg_iterates_match_scipy_cg():
+    n = 10
+    rp, c, v = P.diffusion7(n, seed=4)
+    A = sp.csr_matrix((v, c, rp), shape=(n ** 3, n ** 3))
+    b = P.rhs_uniform(n ** 3, 4)
+    h = oracle.Hierarchy(rp, c, v)
+    dinv = 1.0 / A.diagonal()
+    M = spla.LinearOperator(A.shape, matvec=lambda x: dinv * x)
+    for k in [1, 2, 5, 9]:
+        xs, _ = spla.cg(A, b, rtol=1e-30, atol=0.0, maxiter=k, M=M)
+        r = h.pcg(b, rtol=1e-30, maxit=k, prec=oracle.PREC_JACOBI)
+        assert r["iters"] == k
+        np.testing.assert_allclose(r["x"], xs, rtol=0, atol=1e-11 * np.abs(xs).max())
+
+
+def test_unpreconditioned_cg_lanczos_recovers_lambda_max():
+    n = 10
+    rp, c, v = P.poisson7(n)
+    h = oracle.Hierarchy(rp, c, v)
+    b = P.rhs_uniform(n ** 3, 3)
+    r = h.pcg(b, rtol=1e-13, maxit=400, prec=oracle.PREC_NONE, history=True)
+    al, be = r["alpha"], r["beta"]
+    m = len(al) - 1
+    T = np.zeros((m, m))
+    for j in range(m):
+        T[j, j] = 1.0 / al[j] + (be[j - 1] / al[j - 1] if j > 0 else 0.0)
+        if j + 1 < m:
+            T[j, j + 1] = T[j + 1, j] = np.sqrt(be[j]) / al[j]
+    lam = np.linalg.eigvalsh(T)
+    assert abs(lam.max() - (6 + 6 * np.cos(np.pi / (n + 1)))) < 1e-8
+    assert abs(lam.min() - (6 - 6 * np.cos(np.pi / (n + 1)))) < 1e-8
+
+
+def test_manufactured_solution_within_condition_bound():
+    n = 32
+    rp, c, v = P.poisson7(n)
+    h = oracle.Hierarchy(rp, c, v)
+    xt = P.x_true(n ** 3, 0)
+    b = P.rhs_from_solution(rp, c, v, xt)
+    r = h.pcg(b, rtol=1e-6)
+    assert r["status"] == oracle.OK and r["relres"] <= 1e-6
+    kappa = (6 + 6 * np.cos(np.pi / (n + 1))) / (6 - 6 * np.cos(np.pi / (n + 1)))
+    assert np.linalg.norm(r["x"] - xt) / np.linalg.norm(xt) <= kappa * 1e-6
+    assert r["iters"] == 16        # calibration: matches an independent scipy replica
+
+
+def test_fcg_with_fixed_preconditioner_equals_pcg():
+    n = 16
+    rp, c, v = P.poisson7(n)
+    h = oracle.Hierarchy(rp, c, v)
+    b = P.rhs_uniform(n ** 3, 11)
+    for k in [1, 3, 6]:
+        a = h.pcg(b, rtol=1e-30, maxit=k)
+        f = h.fcg(b, rtol=1e-30, maxit=k, form=0)
+        np.testing.assert_allclose(f["x"], a["x"], rtol=0, atol=1e-10 * np.abs(a["x"]).max())
+    a = h.pcg(b, rtol=1e-6)
+    f = h.fcg(b, rtol=1e-6, form=0)
+    assert abs(a["iters"] - f["iters"]) <= 1
+
+
+def test_mixed_fcg_reaches_true_residual():
+    n = 24
+    rp, c, v = P.diffusion7(n, seed=0)
+    h = oracle.Hierarchy(rp, c, v)
+    b = P.rhs_from_solution(rp, c, v, P.x_true(n ** 3, 0))
+    f = h.fcg(b, rtol=1e-6, form=1)
+    d = h.pcg(b, rtol=1e-6)
+    assert f["status"] == oracle.OK and f["relres"] <= 1e-6
+    assert abs(f["iters"] - d["iters"]) <= 2
+
+
+def test_failure_paths():
+    rp, c, v = P.poisson7(6)
+    h = oracle.Hierarchy(rp, c, v, coarse_max=20)
+    b = P.rhs_uniform(216, 0)
+    r = h.pcg(np.zeros(216))
+    assert r["status"] == oracle.OK and r["iters"] == 0 and not r["x"].any()
+    r = h.pcg(b, maxit=1, rtol=1e-12)
+    assert r["status"] == oracle.NOCONV and r["iters"] == 1 and 0 < r["relres"] < 1
+    bn = b.copy(); bn[5] = np.nan
+    assert h.pcg(bn)["status"] == oracle.ERR_NAN
+    v2 = v.copy()
+    v2[rp[3] + list(c[rp[3]:rp[4]]).index(3)] = -6.0
+    with pytest.raises(RuntimeError):
+        oracle.Hierarchy(rp, c, v2)
+
+
+# --------------------------------------------------------------------------
+# The paper's printed operator complexity (golden fixture)
+# --------------------------------------------------------------------------
+
+@pytest.mark.slow
+def test_vmatch_operator_complexity_matches_paper():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "paper_operator_complexity.txt"))
+            if l.strip() and not l.startswith("#")]
+    ref = float([r for r in rows if r[0] == "VMATCH" and r[1] == "1"][0][2])
+    rp, c, v = P.poisson7(200)                 # 8e6 unknowns, one GPU's share
+    h = oracle.Hierarchy(rp, c, v, sweeps=3)   # aggregates <= 8, tentative prolongator
+    assert abs(h.operator_complexity() - ref) <= 0.01
