@@ -1,0 +1,275 @@
+/*
+ * psc.h -- C ABI of the MI355X (gfx950) AMG-preconditioned CG library.
+ *
+ * The library implements the solve phase of the method of D'Ambra,
+ * Durastante and Filippone, "PSCToolkit: solving sparse linear systems with
+ * a large number of GPUs" (arXiv 2406.19754): conjugate gradient
+ * preconditioned by an algebraic multigrid V-cycle built by coupled
+ * aggregation based on compatible weighted matching, with l1-Jacobi
+ * smoothing. Two further forms run inside flexible CG: a V-cycle evaluated
+ * in FP32, and a small learned convolutional preconditioner alternated with
+ * the V-cycle.
+ *
+ * Conventions for every entry point:
+ *   - Return value is a status code (PSC_OK = 0, PSC_NOCONV = 1, errors < 0),
+ *     in the spirit of the paper's `info` argument (Section "PSBLAS
+ *     applications"). No C++ exception crosses this boundary.
+ *   - psc_last_error() returns a thread-local message for the last error.
+ *   - Pointers named *_host are host memory; pointers named *_dev are device
+ *     memory on the GPU that was current when the handle was created. All
+ *     arrays are dense, contiguous, and owned by the caller; the library
+ *     never keeps a caller pointer after a call returns.
+ *   - All device work of a handle is issued on the HIP stream given at
+ *     creation (NULL = the null stream). Calls on one handle are not
+ *     thread-safe; distinct handles are independent.
+ *   - Out-parameters are written only on PSC_OK, except that iteration
+ *     counts and residuals are also written on PSC_NOCONV.
+ */
+#ifndef PSC_H
+#define PSC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define PSC_OK            0
+#define PSC_NOCONV        1   /* maxit reached; iters / relres are valid */
+#define PSC_ERR_ARG      -1   /* malformed argument (CSR structure, sizes, NULL) */
+#define PSC_ERR_NOT_SPD  -2   /* non-positive diagonal, Cholesky or CG breakdown */
+#define PSC_ERR_NAN      -3   /* NaN / Inf met in the right-hand side or iteration */
+#define PSC_ERR_HIP      -4   /* a HIP runtime call failed */
+#define PSC_ERR_OOM      -5   /* host or device allocation failed */
+#define PSC_ERR_COARSEN  -6   /* coarsening stalled above the coarsest-size limit */
+#define PSC_ERR_STATE    -7   /* handle not in a state that allows the call */
+
+/* ---- precisions ---------------------------------------------------------- */
+#define PSC_FP64 0
+#define PSC_FP32 1
+
+typedef struct psc_hier psc_hier;   /* opaque: owns all device memory of a hierarchy */
+typedef struct psc_net  psc_net;    /* opaque: owns the learned preconditioner       */
+
+/*
+ * Hierarchy options. psc_amg_opts_default() fills the defaults:
+ *   sweeps = 2       pairwise matching sweeps per level; aggregates hold at
+ *                    most 2^sweeps rows (Section "Aggregation strategies",
+ *                    multiple matching sweeps).
+ *   coarse_max = 200 a level with at most this many rows is the coarsest one
+ *                    and is solved exactly by dense Cholesky.
+ *   max_levels = 30  hard cap on the number of levels.
+ *   build_fp32 = 0   also build the FP32 copies of the level operators that
+ *                    the mixed-precision V-cycle needs.
+ *   use_graph = 1    capture the per-iteration kernel sequence as a HIP
+ *                    graph and replay it.
+ *   host_only = 0    build the hierarchy on the host only and make no HIP
+ *                    call (for inspection with psc_hier_info and
+ *                    psc_hier_export_level on machines without a GPU);
+ *                    solve and apply calls then return PSC_ERR_STATE.
+ */
+typedef struct {
+    int32_t sweeps;
+    int32_t coarse_max;
+    int32_t max_levels;
+    int32_t build_fp32;
+    int32_t use_graph;
+    int32_t host_only;
+    int32_t reserved[10];
+} psc_amg_opts;
+
+void psc_amg_opts_default(psc_amg_opts* opts);
+
+/*
+ * Build the AMG hierarchy of the n x n symmetric positive-definite matrix A
+ * given in CSR form (Section "AMG4PSBLAS": Galerkin coarse operators
+ * A_{l+1} = P_l^T A_l P_l; Section "Aggregation strategies": coupled
+ * aggregation by compatible weighted matching with tentative prolongator,
+ * eq. (prolongator); Section "GPU enabled smoothers": l1-Jacobi diagonal).
+ *   n           rows (> 0)
+ *   rowptr_host n+1 int32, rowptr[0] = 0, non-decreasing
+ *   col_host    rowptr[n] int32 column indices, strictly ascending per row,
+ *               in [0, n); every row holds its diagonal
+ *   val_host    rowptr[n] FP64 values; diagonal entries must be > 0
+ *   opts        NULL for defaults
+ *   hip_stream  hipStream_t used for all device work of the handle
+ *   out         receives the handle; release with psc_hier_free
+ * The setup runs on the host (as in the paper, where the hierarchy build is
+ * mostly host-side) and ends with one host-to-device copy of every level.
+ * Errors: PSC_ERR_ARG (malformed CSR), PSC_ERR_NOT_SPD (diagonal <= 0 or
+ * coarsest Cholesky breakdown), PSC_ERR_COARSEN, PSC_ERR_OOM, PSC_ERR_HIP.
+ * Symmetry is assumed, not checked.
+ */
+int psc_amg_build(int32_t n, const int32_t* rowptr_host, const int32_t* col_host,
+                  const double* val_host, const psc_amg_opts* opts, void* hip_stream,
+                  psc_hier** out);
+
+/*
+ * Preconditioned conjugate gradient with the FP64 V-cycle (one l1-Jacobi
+ * pre- and post-sweep, exact coarsest solve; Section "AMG4PSBLAS",
+ * eq. (amg)) as the preconditioner. Stops when the recursive residual
+ * satisfies ||r||_2 <= rtol ||b||_2 (Section "Numerical Example").
+ *   b_dev    n FP64, right-hand side
+ *   x_dev    n FP64, in: initial guess, out: solution
+ *   iters    out: iterations taken
+ *   relres   out: true relative residual ||b - A x||_2 / ||b||_2 in FP64
+ * b = 0 gives x = 0, iters = 0. Returns PSC_NOCONV when maxit is reached,
+ * PSC_ERR_NAN when b or an iterate holds NaN/Inf, PSC_ERR_NOT_SPD on a
+ * breakdown (p.q <= 0 or r.z <= 0).
+ */
+int psc_pcg_solve(psc_hier* h, const double* b_dev, double* x_dev, double rtol,
+                  int32_t maxit, int32_t* iters, double* relres);
+
+/*
+ * Flexible CG with one stored direction, FCG(1) (the paper runs its tests
+ * with flexible CG, Section "Numerical Example"): z = B_k r,
+ * p = z - ((z.q_prev)/(p_prev.q_prev)) p_prev, q = A p,
+ * alpha = (p.r)/(p.q). When the recursive residual passes the test the
+ * true residual b - A x is formed in FP64; if it fails, r is replaced by it
+ * and the directions restart.
+ *   vcycle_prec  PSC_FP64, or PSC_FP32 (the V-cycle in FP32: level
+ *                operators, smoothing and transfers in FP32, the coarsest
+ *                solve in FP64; needs build_fp32)
+ *   net          NULL for the V-cycle only; else odd iterations apply the
+ *                learned network z = s net(r/s), s = ||r||/sqrt(n), with
+ *                the V-cycle taken instead when z.r <= 0, and the network
+ *                switched off for the rest of the solve when a network step
+ *                leaves ||r_new|| > 0.9 ||r_old||. The grid given at
+ *                psc_net_apply time must have nx*ny*nz = n.
+ *   fallbacks    out (may be NULL): scheduled network steps that ran the
+ *                V-cycle instead
+ * Other arguments and errors as for psc_pcg_solve.
+ */
+int psc_fcg_solve(psc_hier* h, psc_net* net, int32_t vcycle_prec, const double* b_dev,
+                  double* x_dev, double rtol, int32_t maxit, int32_t* iters,
+                  double* relres, int32_t* fallbacks);
+
+/* Hierarchy statistics. Arrays hold one entry per level. */
+#define PSC_MAX_LEVELS 32
+typedef struct {
+    int32_t levels;
+    int64_t rows[PSC_MAX_LEVELS];
+    int64_t nnz[PSC_MAX_LEVELS];
+    int64_t ell_slots[PSC_MAX_LEVELS];       /* padded hacked-ELL slots of A_l */
+    double  operator_complexity;             /* sum nnz(A_l) / nnz(A_0) */
+    double  vcycle_bytes_fp64;               /* algorithmic bytes of one V-cycle */
+    double  vcycle_bytes_fp32;
+    double  spmv_bytes_fp64;                 /* algorithmic bytes of y = A_0 x */
+    double  setup_seconds;                   /* host setup wall time */
+    int64_t device_bytes;                    /* device memory held by the handle */
+} psc_hier_stats;
+
+int psc_hier_info(const psc_hier* h, psc_hier_stats* s);
+
+/*
+ * Copy one level's setup data to host arrays (for tests). Any pointer may
+ * be NULL. agg_host (rows[l] int32): aggregate of each row; p_host
+ * (rows[l] FP64): value of the single prolongator entry of each row;
+ * minv_host (rows[l] FP64): l1-Jacobi inverse diagonal; rowptr/col/val:
+ * A_l in CSR (rows[l]+1, nnz[l], nnz[l]). agg and p are only defined below
+ * the coarsest level.
+ */
+int psc_hier_export_level(const psc_hier* h, int32_t level, int32_t* agg_host,
+                          double* p_host, double* minv_host, int32_t* rowptr_host,
+                          int32_t* col_host, double* val_host);
+
+/* z = B r: one V-cycle (FP64 or FP32 form) on device vectors of size n. */
+int psc_vcycle_apply(psc_hier* h, int32_t prec, const double* r_dev, double* z_dev);
+
+/* y = A_l x on level l's hacked-ELL operator, FP64 (prec = PSC_FP64) or
+ * its FP32 copy (x and y are then float*). For tests and bandwidth runs. */
+int psc_spmv(psc_hier* h, int32_t level, int32_t prec, const void* x_dev, void* y_dev);
+
+/*
+ * Kernel timing. When enabled, the library records HIP events on its stream
+ * around every launch of the level-0 kernels during solves (which disables
+ * graph replay) and accumulates their durations; psc_timing_get returns,
+ * per kernel id, the launch count and the total milliseconds, and resets.
+ * Kernel ids: 0 outer SpMV (+p.q), 1 CG update (+||r||^2), 2 level-0
+ * pre-smoothing + residual, 3 level-0 restriction, 4 level-0 prolongation +
+ * post-smoothing (+r.z), 5 direction update, 6 whole V-cycle.
+ */
+#define PSC_TIMING_KERNELS 8
+int psc_timing_enable(psc_hier* h, int32_t on);
+int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
+
+/*
+ * Launch-shape tuning. PSC_TUNE_GRID_MAX caps the number of workgroups of
+ * the streaming kernels (multiple of 8, at most 65536; default 4096).
+ * Invalidates captured graphs.
+ */
+#define PSC_TUNE_GRID_MAX 1
+int psc_tune(psc_hier* h, int32_t key, int32_t value);
+
+void psc_hier_free(psc_hier* h);
+
+/* ---- learned preconditioner ---------------------------------------------- */
+/*
+ * A 3-layer 3x3x3 convolutional network with C = 16 channels:
+ *   h1 = GELU(W1 * u + b1), h2 = GELU(W2 * h1 + b2), out = W3 * h2 + b3,
+ * zero padding, GELU(t) = t Phi(t). Inputs and activations are bfloat16,
+ * convolution sums are FP32 (MFMA for the 16 -> 16 layer); weights are kept
+ * as an FP32 master copy and a bfloat16 working copy.
+ * Parameter layout (psc_net_param_count() = 7809 floats):
+ *   W1[16][1][27] b1[16] W2[16][16][27] b2[16] W3[1][16][27] b3[1],
+ * tap t = (dz*3+dy)*3+dx acting at offset (dz-1, dy-1, dx-1).
+ */
+int32_t psc_net_param_count(void);
+int psc_net_create(const float* params_host, void* hip_stream, psc_net** out);
+int psc_net_get_params(const psc_net* net, float* params_host);
+int psc_net_set_params(psc_net* net, const float* params_host);
+
+/* z = s net(r/s), s = ||r||_2/sqrt(n), on an nx x ny x nz grid (x fastest). */
+int psc_net_apply(psc_net* net, const double* r_dev, double* z_dev, int32_t nx,
+                  int32_t ny, int32_t nz);
+
+/* Declare the grid used by psc_fcg_solve (n = nx*ny*nz). */
+int psc_net_set_grid(psc_net* net, int32_t nx, int32_t ny, int32_t nz);
+
+/*
+ * Batched forward / loss-gradient on B cubic crops of side D (float, device):
+ *   in_dev, target_dev, out_dev: B*D^3 floats.
+ * psc_net_loss_grad: loss = mean over samples and cells at least `margin`
+ * from every face of (out - target)^2; grad_host receives d loss / d params
+ * (7809 floats), computed by the backward kernels (bfloat16 rounding
+ * treated as identity). Returns the loss in *loss.
+ */
+int psc_net_forward_batch(psc_net* net, const float* in_dev, float* out_dev, int32_t B,
+                          int32_t D);
+int psc_net_loss_grad(psc_net* net, const float* in_dev, const float* target_dev,
+                      int32_t B, int32_t D, int32_t margin, float* loss, float* grad_host);
+
+/*
+ * Collect training pairs from preconditioned CG runs: runs PCG on b_dev and,
+ * after every iteration k, crops `crops_per_iter` cubes of side `crop` at
+ * the corners origins_host[(k*crops_per_iter + c)*3 + {0,1,2}] = (z,y,x)
+ * from (r_k / s_k, z_k / s_k) with z_k = B r_k and s_k = ||r_k||/sqrt(n),
+ * appending them as floats to r_out_dev / z_out_dev (capacity crops).
+ * n_origins: number of origin triples provided. *count is in/out: the
+ * number of crops already stored, advanced by the crops added.
+ */
+int psc_pairs_collect(psc_hier* h, const double* b_dev, int32_t nx, int32_t ny, int32_t nz,
+                      double rtol, int32_t maxit, int32_t crop, int32_t crops_per_iter,
+                      const int32_t* origins_host, int32_t n_origins, float* r_out_dev,
+                      float* z_out_dev, int32_t capacity, int32_t* count);
+
+/*
+ * Train with Adam (FP32 master weights, bfloat16 working copy refreshed
+ * after each step) on stored crops: step s uses the `batch` crops
+ * order_host[s*batch .. s*batch+batch-1]. Loss as psc_net_loss_grad.
+ * losses_host (steps floats, may be NULL) receives each step's loss.
+ */
+int psc_net_train(psc_net* net, const float* r_dev, const float* z_dev, int32_t ncrops,
+                  int32_t crop, int32_t margin, const int32_t* order_host, int32_t steps,
+                  int32_t batch, float lr, float beta1, float beta2, float eps,
+                  float* losses_host);
+
+void psc_net_free(psc_net* net);
+
+const char* psc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSC_H */

@@ -5,14 +5,12 @@ is the thin ctypes binding over the C-ABI library ``libpsc.so`` (HIP for
 gfx950); ``paper_2406_19754_amd.problems`` holds the seeded synthetic
 inputs.
 """
+import importlib
+
 __all__ = ["problems", "psc"]
 
 
 def __getattr__(name):
-    if name == "psc":
-        from . import psc
-        return psc
-    if name == "problems":
-        from . import problems
-        return problems
+    if name in __all__:
+        return importlib.import_module(f"{__name__}.{name}")
     raise AttributeError(name)

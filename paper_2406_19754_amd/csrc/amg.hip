@@ -1,0 +1,1365 @@
+// amg.hip -- gfx950 kernels and C ABI of the AMG-preconditioned CG solve phase.
+//
+// Method (arXiv 2406.19754): CG / flexible CG preconditioned by the V-cycle
+// of eq. (amg), Section "AMG4PSBLAS": one l1-Jacobi pre-sweep from a zero
+// guess, restriction with P^T, recursive coarse correction, prolongation and
+// one l1-Jacobi post-sweep; the coarsest level is solved exactly. The matrix
+// storage is hacked ELLPACK (Section "GPU support"): rows in groups of one
+// wavefront (64 rows here) stored as independent ELLPACK blocks.
+//
+// MI355X mapping:
+//   * one lane per row, one wavefront per 64-row slice, column-major slice
+//     layout so each load instruction of a wavefront reads 512 contiguous
+//     bytes of values and 256 of indices, streamed with non-temporal loads
+//     so the gathered vectors keep the L2 and Infinity Cache;
+//   * streaming kernels run a fixed grid (a few workgroups per CU) in which
+//     workgroup b walks a contiguous range of slices; workgroup ids are
+//     remapped so each of the 8 XCDs (which receive workgroups round-robin)
+//     owns one contiguous eighth of the rows and its L2 holds the x-planes
+//     its rows gather from;
+//   * every dot product is fused into the kernel that produces one of its
+//     operands: wavefront shuffles, then LDS, then one partial per
+//     workgroup; a one-workgroup finishing kernel adds the partials in a
+//     fixed order and updates the Krylov scalars on the device --
+//     deterministic, no atomics, no fences, no host sync (a device-scope
+//     fence per workgroup would write back the XCD's L2 each time);
+//   * the V-cycle never stores the pre-smoothed iterate: x = M^-1 b is
+//     recomputed where it is needed, the pre-smoothing kernel writes only
+//     the residual, and prolongation is fused into the post-smoothing kernel;
+//   * the whole iteration is captured once as a HIP graph and replayed;
+//     kernels of iterations launched past convergence exit at entry.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/psc.h"
+#include "kernels.h"
+#include "net.h"
+#include "setup.h"
+
+namespace psc {
+
+thread_local std::string g_err;
+
+static int fail(int st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIPCHK(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(PSC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// XCD-aware logical workgroup id: physical ids are dealt round-robin to the
+// 8 XCDs, so XCD x receives ids x, x+8, ...; mapping them to the contiguous
+// range [x*G/8, (x+1)*G/8) gives each XCD one contiguous block of rows.
+// G (gridDim.x) is always a multiple of 8.
+__device__ __forceinline__ int logical_block() {
+    int g8 = gridDim.x / NXCD;
+    return (blockIdx.x % NXCD) * g8 + blockIdx.x / NXCD;
+}
+
+__device__ __forceinline__ void chunk_range(long long total, long long& lo, long long& hi) {
+    int lb = logical_block();
+    long long per = (total + gridDim.x - 1) / gridDim.x;
+    lo = (long long)lb * per;
+    hi = lo + per;
+    if (hi > total) hi = total;
+    if (lo > total) lo = total;
+}
+
+template <typename T>
+__device__ __forceinline__ T ntload(const T* p) {
+    return __builtin_nontemporal_load(p);
+}
+
+__device__ __forceinline__ void publish(Ctl* c, HostCtl* hc) {
+    if (hc) {
+        hc->done = c->done;
+        hc->iter = c->iter;
+        hc->status = c->status;
+        hc->fallbacks = c->fallbacks;
+        __threadfence_system();
+    }
+}
+
+enum Fin {
+    FIN_NONE = 0,
+    FIN_INIT,         // s0 = ||b||^2, s1 = ||r0||^2
+    FIN_ALPHA_PCG,    // s0 = p.q
+    FIN_ALPHA_FCG,    // s0 = p.q, s1 = p.r
+    FIN_UPDATE_PCG,   // s0 = ||r||^2
+    FIN_UPDATE_FCG,   // s0 = ||r||^2
+    FIN_RHO_INIT,     // s0 = r.z
+    FIN_RHO,          // s0 = r.z
+    FIN_BETA_FCG,     // s0 = z.q_prev
+    FIN_TRUE,         // s0 = ||b - A x||^2 (r replaced by it)
+    FIN_STORE,        // out0 = s0, out1 = s1
+    FIN_NETCHECK,     // s0 = z.r, s1 = z.q_prev of a network step
+};
+
+__device__ void finalize(int fin, double s0, double s1, Ctl* c, HostCtl* hc) {
+    switch (fin) {
+    case FIN_INIT:
+        c->nb2 = s0;
+        c->rr = s1;
+        c->rr_old = s1;
+        if (!isfinite(s0) || !isfinite(s1)) { c->status = PSC_ERR_NAN; c->done = 1; }
+        else if (s0 == 0.0) { c->status = PSC_OK; c->done = 1; }
+        else if (sqrt(s1) <= c->rtol * sqrt(s0)) { c->status = PSC_OK; c->done = 1; }
+        break;
+    case FIN_ALPHA_PCG:
+        c->pq = s0;
+        if (isnan(s0)) { c->status = PSC_ERR_NAN; c->done = 1; }
+        else if (!(s0 > 0.0)) { c->status = PSC_ERR_NOT_SPD; c->done = 1; }
+        else c->alpha = c->rho / s0;
+        break;
+    case FIN_ALPHA_FCG:
+        c->pq = s0;
+        c->pr = s1;
+        if (isnan(s0) || isnan(s1)) { c->status = PSC_ERR_NAN; c->done = 1; }
+        else if (!(s0 > 0.0)) { c->status = PSC_ERR_NOT_SPD; c->done = 1; }
+        else { c->alpha = s1 / s0; c->pq_prev = s0; c->have_prev = 1; }
+        break;
+    case FIN_UPDATE_PCG:
+    case FIN_UPDATE_FCG:
+        c->rr_old = c->rr;
+        c->rr = s0;
+        c->iter += 1;
+        if (c->use_net && sqrt(s0) > 0.9 * sqrt(c->rr_old)) c->net_on = 0;   // network stagnates
+        if (isnan(s0)) { c->status = PSC_ERR_NAN; c->done = 1; }
+        else if (sqrt(s0) <= c->rtol * sqrt(c->nb2)) {
+            if (fin == FIN_UPDATE_PCG) { c->status = PSC_OK; c->done = 1; }
+            else c->check = 1;
+        } else if (c->iter >= c->maxit) { c->status = PSC_NOCONV; c->done = 1; }
+        break;
+    case FIN_RHO_INIT:
+        if (isnan(s0)) { c->status = PSC_ERR_NAN; c->done = 1; }
+        else if (!(s0 > 0.0)) { c->status = PSC_ERR_NOT_SPD; c->done = 1; }
+        c->rho = s0;
+        break;
+    case FIN_RHO:
+        if (isnan(s0)) { c->status = PSC_ERR_NAN; c->done = 1; }
+        else if (!(s0 > 0.0)) { c->status = PSC_ERR_NOT_SPD; c->done = 1; }
+        else { c->beta = s0 / c->rho; c->rho = s0; }
+        break;
+    case FIN_BETA_FCG:
+        c->zq = s0;
+        c->beta = c->have_prev ? s0 / c->pq_prev : 0.0;
+        break;
+    case FIN_TRUE:
+        c->check = 0;
+        if (isnan(s0)) { c->status = PSC_ERR_NAN; c->done = 1; }
+        else if (sqrt(s0) <= c->rtol * sqrt(c->nb2)) { c->status = PSC_OK; c->done = 1; }
+        else {
+            c->have_prev = 0;
+            c->rr = s0;
+            if (c->iter >= c->maxit) { c->status = PSC_NOCONV; c->done = 1; }
+        }
+        break;
+    case FIN_STORE:
+        c->out0 = s0;
+        c->out1 = s1;
+        break;
+    case FIN_NETCHECK:
+        c->zr = s0;
+        if (!(s0 > 0.0)) { c->use_net = 0; c->fallbacks += 1; }   // the V-cycle runs instead
+        else { c->zq = s1; c->beta = c->have_prev ? s1 / c->pq_prev : 0.0; }
+        break;
+    default:
+        break;
+    }
+    publish(c, hc);
+}
+
+struct Red {
+    double* part;      // 2 doubles per workgroup
+    Ctl* ctl;          // control block (finaliser target, and the gate)
+    HostCtl* hctl;     // host-mapped mirror (may be NULL)
+    int fin;           // finaliser run by k_finish
+    int gmode;         // GateMode applied with ctl
+};
+
+__device__ __forceinline__ bool skip_red(const Red& R) { return gate_skip(Gate{R.ctl, R.gmode}); }
+
+// Block-reduce (s0, s1) and store this workgroup's partial pair. The
+// partials are added in a fixed order by k_finish, launched right after
+// (the kernel boundary makes them visible); no atomics, no fences.
+__device__ void block_partial(double s0, double s1, double* part) {
+    __shared__ double red[2][WG / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (lane == 0) { red[0][w] = s0; red[1][w] = s1; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int lb = logical_block();
+        part[2 * lb] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        part[2 * lb + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    }
+}
+
+// Second stage: one workgroup adds the nblk partial pairs in a fixed order
+// and runs the finaliser on the control block.
+__global__ __launch_bounds__(WG) void k_finish(Red R, int nblk) {
+    if (skip_red(R)) return;
+    __shared__ double red[2][WG / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += WG) {
+        a += R.part[2 * i];
+        b += R.part[2 * i + 1];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) { red[0][w] = a; red[1][w] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        b = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        finalize(R.fin, a, b, R.ctl, R.hctl);
+    }
+}
+
+// Row sum over one hacked-ELL row: sum_k val[k] * g(col[k]) in slot order
+// (ascending column order of the CSR input; padded slots carry 0).
+template <typename T, typename G>
+__device__ __forceinline__ T ell_row(const Ell<T>& A, long long s, int lane, G g) {
+    const long long o = A.off[s];
+    const int w = (int)((A.off[s + 1] - o) >> 6);
+    const T* vp = A.val + o + lane;
+    const int* cp = A.col + o + lane;
+    T acc = T(0);
+    int k = 0;
+    for (; k + 4 <= w; k += 4) {
+        T v0 = ntload(vp + 0 * SLICE), v1 = ntload(vp + 1 * SLICE);
+        T v2 = ntload(vp + 2 * SLICE), v3 = ntload(vp + 3 * SLICE);
+        int c0 = ntload(cp + 0 * SLICE), c1 = ntload(cp + 1 * SLICE);
+        int c2 = ntload(cp + 2 * SLICE), c3 = ntload(cp + 3 * SLICE);
+        T g0 = g(c0), g1 = g(c1), g2 = g(c2), g3 = g(c3);
+        acc += v0 * g0;
+        acc += v1 * g1;
+        acc += v2 * g2;
+        acc += v3 * g3;
+        vp += 4 * SLICE;
+        cp += 4 * SLICE;
+    }
+    for (; k < w; k++) {
+        T v0 = ntload(vp);
+        int c0 = ntload(cp);
+        acc += v0 * g(c0);
+        vp += SLICE;
+        cp += SLICE;
+    }
+    return acc;
+}
+
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+// y = A x
+template <typename T>
+__global__ __launch_bounds__(WG) void k_spmv(Ell<T> A, const T* __restrict__ x, T* __restrict__ y,
+                                             Gate g) {
+    if (gate_skip(g)) return;
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        T acc = ell_row(A, s, lane, [&](int c) { return x[c]; });
+        long long row = s * SLICE + lane;
+        if (row < A.nrows) y[row] = acc;
+    }
+}
+
+// q = A p with partials (p.q, p.r); r may be NULL.
+__global__ __launch_bounds__(WG) void k_spmv_dot(Ell<double> A, const double* __restrict__ p,
+                                                 double* __restrict__ q, const double* __restrict__ r,
+                                                 Red R) {
+    if (skip_red(R)) return;
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double s0 = 0.0, s1 = 0.0;
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        double acc = ell_row(A, s, lane, [&](int c) { return p[c]; });
+        long long row = s * SLICE + lane;
+        if (row < A.nrows) {
+            q[row] = acc;
+            double pi = p[row];
+            s0 += pi * acc;
+            if (r) s1 += pi * r[row];
+        }
+    }
+    block_partial(s0, s1, R.part);
+}
+
+// r = b - A x with partials (b.b, r.r). With only_if_check, runs only when
+// the control block asks for a true-residual check.
+__global__ __launch_bounds__(WG) void k_resid(Ell<double> A, const double* __restrict__ b,
+                                              const double* __restrict__ x, double* __restrict__ r,
+                                              int only_if_check, Red R) {
+    if (skip_red(R)) return;
+    if (only_if_check && !R.ctl->check) return;
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double s0 = 0.0, s1 = 0.0;
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        double acc = ell_row(A, s, lane, [&](int c) { return x[c]; });
+        long long row = s * SLICE + lane;
+        if (row < A.nrows) {
+            double bi = b[row];
+            double ri = bi - acc;
+            r[row] = ri;
+            s0 += bi * bi;
+            s1 += ri * ri;
+        }
+    }
+    if (only_if_check) block_partial(s1, 0.0, R.part);
+    else block_partial(s0, s1, R.part);
+}
+
+// x += alpha p; r -= alpha q; partial r.r
+__global__ __launch_bounds__(WG) void k_update(long long n, double* __restrict__ x,
+                                               double* __restrict__ r, const double* __restrict__ p,
+                                               const double* __restrict__ q, Red R) {
+    if (skip_red(R)) return;
+    const double alpha = R.ctl->alpha;
+    long long lo, hi;
+    chunk_range(n, lo, hi);
+    double s0 = 0.0;
+    for (long long i = lo + threadIdx.x; i < hi; i += WG) {
+        double xi = x[i] + alpha * p[i];
+        double ri = r[i] - alpha * q[i];
+        x[i] = xi;
+        r[i] = ri;
+        s0 += ri * ri;
+    }
+    block_partial(s0, 0.0, R.part);
+}
+
+// PCG: p = z + beta p.  FCG: p = z - beta p (p = z without a previous direction).
+__global__ __launch_bounds__(WG) void k_pupdate(long long n, double* __restrict__ p,
+                                                const double* __restrict__ z, int fcg, Gate g) {
+    if (gate_skip(g)) return;
+    const double beta = g.ctl->beta;
+    const int keep = fcg ? g.ctl->have_prev : 1;
+    long long lo, hi;
+    chunk_range(n, lo, hi);
+    if (!keep) {
+        for (long long i = lo + threadIdx.x; i < hi; i += WG) p[i] = z[i];
+    } else if (fcg) {
+        for (long long i = lo + threadIdx.x; i < hi; i += WG) p[i] = z[i] - beta * p[i];
+    } else {
+        for (long long i = lo + threadIdx.x; i < hi; i += WG) p[i] = z[i] + beta * p[i];
+    }
+}
+
+// partials (a.b, 0) for a dot product not fused elsewhere
+__global__ __launch_bounds__(WG) void k_dot(long long n, const double* __restrict__ a,
+                                            const double* __restrict__ b, Red R) {
+    if (skip_red(R)) return;
+    long long lo, hi;
+    chunk_range(n, lo, hi);
+    double s0 = 0.0;
+    for (long long i = lo + threadIdx.x; i < hi; i += WG) s0 += a[i] * b[i];
+    block_partial(s0, 0.0, R.part);
+}
+
+template <typename TD, typename TS>
+__global__ __launch_bounds__(WG) void k_copy(long long n, TD* __restrict__ d, const TS* __restrict__ s,
+                                             Gate g) {
+    if (gate_skip(g)) return;
+    long long lo, hi;
+    chunk_range(n, lo, hi);
+    for (long long i = lo + threadIdx.x; i < hi; i += WG) d[i] = (TD)s[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_fill(long long n, T* __restrict__ d, T v) {
+    long long lo, hi;
+    chunk_range(n, lo, hi);
+    for (long long i = lo + threadIdx.x; i < hi; i += WG) d[i] = v;
+}
+
+__global__ void k_ctl_init(Ctl* c, HostCtl* hc, double rtol, int maxit, int form) {
+    if (threadIdx.x == 0) {
+        c->rtol = rtol;
+        c->nb2 = c->rr = c->rr_old = c->rho = c->alpha = c->beta = 0.0;
+        c->pq = c->pr = c->zq = c->zr = c->pq_prev = c->out0 = c->out1 = 0.0;
+        c->done = 0;
+        c->iter = 0;
+        c->status = PSC_NOCONV;
+        c->maxit = maxit;
+        c->check = 0;
+        c->have_prev = 0;
+        c->net_on = 0;
+        c->use_net = 0;
+        c->fallbacks = 0;
+        c->form = form;
+        publish(c, hc);
+    }
+}
+
+__global__ void k_set_net_on(Ctl* c) {
+    if (threadIdx.x == 0) c->net_on = 1;
+}
+
+// Pre-smoothing from a zero guess and its residual, one pass:
+//   r_i = b_i - sum_j a_ij (minv_j b_j)       (the iterate M^-1 b is not stored)
+template <typename T, typename TB>
+__global__ __launch_bounds__(WG) void k_pre(Ell<T> A, const T* __restrict__ minv,
+                                            const TB* __restrict__ b, T* __restrict__ r, Gate g) {
+    if (gate_skip(g)) return;
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        T acc = ell_row(A, s, lane, [&](int c) { return minv[c] * (T)b[c]; });
+        long long row = s * SLICE + lane;
+        if (row < A.nrows) r[row] = (T)b[row] - acc;
+    }
+}
+
+// Prolongation fused with the post-smoothing sweep:
+//   xs_j = minv_j b_j + p_j xc[agg_j]   (pre-smoothed iterate + coarse correction)
+//   x_i  = xs_i + minv_i (b_i - sum_j a_ij xs_j)
+// With R.fin != FIN_NONE, also the partial sum of x_i * d_i.
+template <typename T, typename TB, typename TX>
+__global__ __launch_bounds__(WG) void k_post(Ell<T> A, const T* __restrict__ minv,
+                                             const TB* __restrict__ b, const int* __restrict__ agg,
+                                             const T* __restrict__ pv, const T* __restrict__ xc,
+                                             TX* __restrict__ x, const double* __restrict__ d, Red R) {
+    if (skip_red(R)) return;
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double s0 = 0.0;
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        auto xs = [&](int c) { return minv[c] * (T)b[c] + pv[c] * xc[agg[c]]; };
+        T acc = ell_row(A, s, lane, xs);
+        long long row = s * SLICE + lane;
+        if (row < A.nrows) {
+            int i = (int)row;
+            T xi = xs(i) + minv[i] * ((T)b[i] - acc);
+            x[row] = (TX)xi;
+            if (d) s0 += (double)(TX)xi * d[row];
+        }
+    }
+    if (R.fin != FIN_NONE) block_partial(s0, 0.0, R.part);
+}
+
+// Coarsest level: x = A_L^{-1} b with the explicit inverse (column-major), FP64.
+template <typename TB, typename TX>
+__global__ __launch_bounds__(WG) void k_coarse(int n, const double* __restrict__ invT,
+                                               const TB* __restrict__ b, TX* __restrict__ x,
+                                               Gate g) {
+    if (gate_skip(g)) return;
+    __shared__ double bs[4096];
+    for (int i = threadIdx.x; i < n; i += WG) bs[i] = (double)b[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += WG) {
+        double s = 0.0;
+        for (int k = 0; k < n; k++) s += invT[(size_t)k * n + i] * bs[k];
+        x[i] = (TX)s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+
+struct GraphEntry {
+    int form;
+    const psc_net* net;
+    uint64_t gen;
+    hipGraphExec_t exec;
+};
+
+template <typename T>
+struct DevEll {
+    long long* off = nullptr;
+    T* val = nullptr;
+    int* col = nullptr;
+    float* val32 = nullptr;
+    long long nrows = 0, nslices = 0, slots = 0;
+    Ell<T> view() const { return Ell<T>{off, val, col, nrows, nslices}; }
+    Ell<float> view32() const { return Ell<float>{off, val32, col, nrows, nslices}; }
+};
+
+struct DevLevel {
+    long long n = 0, nc = 0, nnz = 0;
+    DevEll<double> A, R;                  // R = P^T (coarse rows, members as columns)
+    double* minv = nullptr;
+    float* minv32 = nullptr;
+    int* agg = nullptr;
+    double* pval = nullptr;
+    float* pval32 = nullptr;
+    double *b = nullptr, *x = nullptr, *r = nullptr;      // level vectors (FP64 form)
+    float *b32 = nullptr, *x32 = nullptr, *r32 = nullptr; // level vectors (FP32 form)
+};
+
+}  // namespace psc
+
+struct psc_hier {
+    psc::HostHier host;
+    std::vector<psc::DevLevel> lev;
+    double* coarse_invT = nullptr;
+    int coarse_n = 0;
+    hipStream_t stream = nullptr;         // library work stream (owned, capturable)
+    hipStream_t user_stream = nullptr;    // caller's stream; joined at entry and exit
+    hipEvent_t ev_join[2] = {nullptr, nullptr};
+    int device = 0;
+    psc_amg_opts opts;
+    bool has32 = false;
+    // solver state
+    psc::Ctl* ctl = nullptr;
+    psc::HostCtl* hctl = nullptr;
+    psc::HostCtl* hctl_dev = nullptr;
+    double* part = nullptr;
+    double *xs = nullptr, *bs = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    std::vector<void*> allocs;
+    int64_t device_bytes = 0;
+    double setup_seconds = 0.0;
+    int gmax = 4096;                      // workgroup cap of the streaming kernels
+    // captured iterations, one per (form, network, network generation)
+    std::vector<psc::GraphEntry> graphs;
+    // timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+    std::vector<int> ev_kind;
+    size_t ev_used = 0;
+    int64_t t_count[PSC_TIMING_KERNELS] = {0};
+    double t_ms[PSC_TIMING_KERNELS] = {0};
+    std::vector<hipEvent_t> ring;
+};
+
+namespace psc {
+
+static int dalloc(psc_hier* h, void** p, size_t bytes) {
+    if (bytes == 0) bytes = 64;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail(PSC_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    h->allocs.push_back(*p);
+    h->device_bytes += (int64_t)bytes;
+    return PSC_OK;
+}
+
+// Order the library's work stream after the caller's stream (entry) and the
+// caller's stream after the library's work (exit).
+static int join_in(psc_hier* h) {
+    HIPCHK(hipEventRecord(h->ev_join[0], h->user_stream));
+    HIPCHK(hipStreamWaitEvent(h->stream, h->ev_join[0], 0));
+    return PSC_OK;
+}
+static int join_out(psc_hier* h) {
+    HIPCHK(hipEventRecord(h->ev_join[1], h->stream));
+    HIPCHK(hipStreamWaitEvent(h->user_stream, h->ev_join[1], 0));
+    return PSC_OK;
+}
+
+template <typename T>
+static int upload(psc_hier* h, T** d, const T* src, size_t count) {
+    int st = dalloc(h, (void**)d, count * sizeof(T));
+    if (st) return st;
+    HIPCHK(hipMemcpy(*d, src, count * sizeof(T), hipMemcpyHostToDevice));
+    return PSC_OK;
+}
+
+static int upload_ell(psc_hier* h, DevEll<double>& E, int64_t nrows, const int32_t* rp,
+                      const int32_t* ci, const double* v, bool fp32) {
+    std::vector<long long> off;
+    std::vector<double> val;
+    std::vector<int> col;
+    pack_ell(nrows, rp, ci, v, off, val, col);
+    E.nrows = nrows;
+    E.nslices = (long long)off.size() - 1;
+    E.slots = off.back();
+    int st;
+    if ((st = upload(h, &E.off, off.data(), off.size()))) return st;
+    if ((st = upload(h, &E.val, val.data(), val.size()))) return st;
+    if ((st = upload(h, &E.col, col.data(), col.size()))) return st;
+    if (fp32) {
+        std::vector<float> v32(val.size());
+        for (size_t i = 0; i < val.size(); i++) v32[i] = (float)val[i];
+        if ((st = upload(h, &E.val32, v32.data(), v32.size()))) return st;
+    }
+    return PSC_OK;
+}
+
+static std::vector<float> to32(const std::vector<double>& a) {
+    std::vector<float> r(a.size());
+    for (size_t i = 0; i < a.size(); i++) r[i] = (float)a[i];
+    return r;
+}
+
+static int grid_of(const psc_hier* h, long long units_per_block_4, long long total) {
+    // one workgroup per 4 slices (or 1024 vector elements) up to the cap,
+    // rounded up to a multiple of the XCD count
+    long long g = (total + units_per_block_4 - 1) / units_per_block_4;
+    if (g > h->gmax) g = h->gmax;
+    if (g < 1) g = 1;
+    g = (g + NXCD - 1) / NXCD * NXCD;
+    return (int)g;
+}
+
+static inline int grid_ell(const psc_hier* h, long long nslices) { return grid_of(h, 4, nslices); }
+static inline int grid_vec(const psc_hier* h, long long n) { return grid_of(h, 1024, n); }
+
+// ---------------------------------------------------------------------------
+// timing
+// ---------------------------------------------------------------------------
+
+struct TimeScope {
+    psc_hier* h;
+    int kind;
+    size_t idx = (size_t)-1;
+    TimeScope(psc_hier* hh, int k) : h(hh), kind(k) {
+        if (!h->timing) return;
+        if (h->ev_used >= h->ev_pool.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return;
+            if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+            h->ev_pool.push_back({a, b});
+            h->ev_kind.push_back(0);
+        }
+        idx = h->ev_used++;
+        h->ev_kind[idx] = kind;
+        (void)hipEventRecord(h->ev_pool[idx].first, h->stream);
+    }
+    ~TimeScope() {
+        if (idx != (size_t)-1) (void)hipEventRecord(h->ev_pool[idx].second, h->stream);
+    }
+};
+
+static void timing_collect(psc_hier* h) {
+    if (!h->timing || h->ev_used == 0) return;
+    (void)hipStreamSynchronize(h->stream);
+    for (size_t i = 0; i < h->ev_used; i++) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->ev_pool[i].first, h->ev_pool[i].second) == hipSuccess) {
+            h->t_count[h->ev_kind[i]] += 1;
+            h->t_ms[h->ev_kind[i]] += ms;
+        }
+    }
+    h->ev_used = 0;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle
+// ---------------------------------------------------------------------------
+
+static Red red_of(psc_hier* h, int fin, int gmode = GATE_DONE) {
+    return Red{h->part, h->ctl, h->hctl_dev, fin, gmode};
+}
+
+// second reduction stage for a kernel launched with `grid` workgroups
+static void finish(psc_hier* h, const Red& R, int grid) {
+    if (R.fin != FIN_NONE) k_finish<<<1, WG, 0, h->stream>>>(R, grid);
+}
+
+// z = B r on level 0. prec: PSC_FP64 / PSC_FP32. fin/d: optional fused dot
+// z.d at level 0 with finaliser fin. g gates every kernel (g.ctl == NULL:
+// standalone V-cycle, always runs, no fused dot).
+static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin, const double* d,
+                   Gate g) {
+    hipStream_t st = h->stream;
+    const int L = (int)h->lev.size();
+    Red R = red_of(h, fin, g.ctl ? g.mode : GATE_NONE);
+    Red R0 = R;
+    R0.fin = FIN_NONE;
+    TimeScope whole(h, 6);
+    if (L == 1) {
+        k_coarse<double, double><<<1, WG, 0, st>>>(h->coarse_n, h->coarse_invT, r0, z0, g);
+        if (fin != FIN_NONE) {
+            int gr = grid_vec(h, h->lev[0].n);
+            k_dot<<<gr, WG, 0, st>>>(h->lev[0].n, z0, d, R);
+            finish(h, R, gr);
+        }
+        return;
+    }
+    if (prec == PSC_FP64) {
+        for (int l = 0; l < L - 1; l++) {
+            DevLevel& V = h->lev[l];
+            const double* b = l == 0 ? r0 : V.b;
+            {
+                TimeScope t(h, l == 0 ? 2 : 7);
+                k_pre<double, double><<<grid_ell(h, V.A.nslices), WG, 0, st>>>(V.A.view(), V.minv, b, V.r, g);
+            }
+            {
+                TimeScope t(h, l == 0 ? 3 : 7);
+                k_spmv<double><<<grid_ell(h, V.R.nslices), WG, 0, st>>>(V.R.view(), V.r, h->lev[l + 1].b, g);
+            }
+        }
+        DevLevel& C = h->lev[L - 1];
+        {
+            TimeScope t(h, 7);
+            k_coarse<double, double><<<1, WG, 0, st>>>(h->coarse_n, h->coarse_invT, C.b, C.x, g);
+        }
+        for (int l = L - 2; l >= 0; l--) {
+            DevLevel& V = h->lev[l];
+            const double* b = l == 0 ? r0 : V.b;
+            double* x = l == 0 ? z0 : V.x;
+            {
+                TimeScope t(h, l == 0 ? 4 : 7);
+                k_post<double, double, double><<<grid_ell(h, V.A.nslices), WG, 0, st>>>(
+                    V.A.view(), V.minv, b, V.agg, V.pval, h->lev[l + 1].x, x, l == 0 ? d : nullptr,
+                    l == 0 ? R : R0);
+            }
+            if (l == 0) finish(h, R, grid_ell(h, V.A.nslices));
+        }
+    } else {
+        for (int l = 0; l < L - 1; l++) {
+            DevLevel& V = h->lev[l];
+            {
+                TimeScope t(h, l == 0 ? 2 : 7);
+                if (l == 0)
+                    k_pre<float, double><<<grid_ell(h, V.A.nslices), WG, 0, st>>>(V.A.view32(), V.minv32, r0, V.r32, g);
+                else
+                    k_pre<float, float><<<grid_ell(h, V.A.nslices), WG, 0, st>>>(V.A.view32(), V.minv32, V.b32, V.r32, g);
+            }
+            {
+                TimeScope t(h, l == 0 ? 3 : 7);
+                k_spmv<float><<<grid_ell(h, V.R.nslices), WG, 0, st>>>(V.R.view32(), V.r32, h->lev[l + 1].b32, g);
+            }
+        }
+        DevLevel& C = h->lev[L - 1];
+        {
+            TimeScope t(h, 7);
+            k_coarse<float, float><<<1, WG, 0, st>>>(h->coarse_n, h->coarse_invT, C.b32, C.x32, g);
+        }
+        for (int l = L - 2; l >= 0; l--) {
+            DevLevel& V = h->lev[l];
+            if (l == 0) {
+                {
+                    TimeScope t(h, 4);
+                    k_post<float, double, double><<<grid_ell(h, V.A.nslices), WG, 0, st>>>(
+                        V.A.view32(), V.minv32, r0, V.agg, V.pval32, h->lev[1].x32, z0, d, R);
+                }
+                finish(h, R, grid_ell(h, V.A.nslices));
+            } else {
+                TimeScope t(h, 7);
+                k_post<float, float, float><<<grid_ell(h, V.A.nslices), WG, 0, st>>>(
+                    V.A.view32(), V.minv32, V.b32, V.agg, V.pval32, h->lev[l + 1].x32, V.x32, nullptr, R0);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// solve loops
+// ---------------------------------------------------------------------------
+
+static const int LAG = 2;     // iterations the GPU may run ahead of the host check
+static const int RING = 8;
+
+// forms: 0 PCG + FP64 V-cycle; 1 FCG(1) + FP64 V-cycle; 2 FCG(1) + FP32
+// V-cycle; 3 / 4: forms 1 / 2 with the learned network on odd iterations.
+static inline bool form_fcg(int form) { return form != 0; }
+static inline bool form_net(int form) { return form >= 3; }
+static inline int form_prec(int form) { return (form == 2 || form == 4) ? PSC_FP32 : PSC_FP64; }
+
+__global__ void k_iter_begin(Ctl* c, HostCtl* hc, int has_net) {
+    if (threadIdx.x != 0 || c->done) return;
+    const int odd = c->iter & 1;
+    c->use_net = has_net && c->net_on && odd;
+    if (has_net && !c->net_on && odd) c->fallbacks += 1;
+    if (hc) hc->fallbacks = c->fallbacks;
+}
+
+// partials (z.r, z.q) of a network step
+__global__ __launch_bounds__(WG) void k_dot2(long long n, const double* __restrict__ z,
+                                             const double* __restrict__ r, const double* __restrict__ q,
+                                             Red R) {
+    if (skip_red(R)) return;
+    long long lo, hi;
+    chunk_range(n, lo, hi);
+    double s0 = 0.0, s1 = 0.0;
+    for (long long i = lo + threadIdx.x; i < hi; i += WG) {
+        double zi = z[i];
+        s0 += zi * r[i];
+        s1 += zi * q[i];
+    }
+    block_partial(s0, s1, R.part);
+}
+
+// Issue one iteration of the given form. Every kernel exits at entry once
+// the control block says the solve is over.
+static int issue_iteration(psc_hier* h, int form, psc_net* net) {
+    hipStream_t st = h->stream;
+    DevLevel& L0 = h->lev[0];
+    const long long n = L0.n;
+    const int ge = grid_ell(h, L0.A.nslices), gv = grid_vec(h, n);
+    const Gate gd{h->ctl, GATE_DONE};
+    if (form == 0) {
+        {
+            TimeScope t(h, 0);
+            k_spmv_dot<<<ge, WG, 0, st>>>(L0.A.view(), h->p, h->q, nullptr, red_of(h, FIN_ALPHA_PCG));
+        }
+        finish(h, red_of(h, FIN_ALPHA_PCG), ge);
+        {
+            TimeScope t(h, 1);
+            k_update<<<gv, WG, 0, st>>>(n, h->xs, h->r, h->p, h->q, red_of(h, FIN_UPDATE_PCG));
+        }
+        finish(h, red_of(h, FIN_UPDATE_PCG), gv);
+        vcycle(h, PSC_FP64, h->r, h->z, FIN_RHO, h->r, gd);
+        {
+            TimeScope t(h, 5);
+            k_pupdate<<<gv, WG, 0, st>>>(n, h->p, h->z, 0, gd);
+        }
+        return PSC_OK;
+    }
+    const int prec = form_prec(form);
+    if (form_net(form)) {
+        k_iter_begin<<<1, 64, 0, st>>>(h->ctl, h->hctl_dev, 1);
+        int rs = net_launch_apply(net, st, h->r, h->z, &h->ctl->rr, n, Gate{h->ctl, GATE_NET});
+        if (rs) return rs;
+        Red Rn = red_of(h, FIN_NETCHECK, GATE_NET);
+        k_dot2<<<gv, WG, 0, st>>>(n, h->z, h->r, h->q, Rn);
+        finish(h, Rn, gv);
+        vcycle(h, prec, h->r, h->z, FIN_BETA_FCG, h->q, Gate{h->ctl, GATE_VC});
+    } else {
+        vcycle(h, prec, h->r, h->z, FIN_BETA_FCG, h->q, gd);
+    }
+    {
+        TimeScope t(h, 5);
+        k_pupdate<<<gv, WG, 0, st>>>(n, h->p, h->z, 1, gd);
+    }
+    {
+        TimeScope t(h, 0);
+        k_spmv_dot<<<ge, WG, 0, st>>>(L0.A.view(), h->p, h->q, h->r, red_of(h, FIN_ALPHA_FCG));
+    }
+    finish(h, red_of(h, FIN_ALPHA_FCG), ge);
+    {
+        TimeScope t(h, 1);
+        k_update<<<gv, WG, 0, st>>>(n, h->xs, h->r, h->p, h->q, red_of(h, FIN_UPDATE_FCG));
+    }
+    finish(h, red_of(h, FIN_UPDATE_FCG), gv);
+    k_resid<<<ge, WG, 0, st>>>(L0.A.view(), h->bs, h->xs, h->r, 1, red_of(h, FIN_TRUE));
+    finish(h, red_of(h, FIN_TRUE), ge);
+    return PSC_OK;
+}
+
+static int get_graph(psc_hier* h, int form, psc_net* net, hipGraphExec_t* out) {
+    const uint64_t gen = net ? net_generation(net) : 0;
+    for (auto& e : h->graphs)
+        if (e.form == form && e.net == net && e.gen == gen) { *out = e.exec; return PSC_OK; }
+    hipGraph_t g;
+    HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
+    int rs = issue_iteration(h, form, net);
+    hipError_t ec = hipStreamEndCapture(h->stream, &g);
+    if (rs) return rs;
+    if (ec != hipSuccess) return fail(PSC_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    hipGraphExec_t ge;
+    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(PSC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    h->graphs.push_back(GraphEntry{form, net, gen, ge});
+    *out = ge;
+    return PSC_OK;
+}
+
+static void drop_graphs(psc_hier* h) {
+    for (auto& e : h->graphs) (void)hipGraphExecDestroy(e.exec);
+    h->graphs.clear();
+}
+
+static int read_ctl(psc_hier* h, Ctl* c) {
+    HIPCHK(hipMemcpyAsync(c, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return PSC_OK;
+}
+
+// Common start of a solve: internal copies of b and x0, control block,
+// r = b - A x0 with ||b||^2 and ||r||^2. Returns the control block.
+static int solve_begin(psc_hier* h, int form, const double* b_dev, const double* x_dev, double rtol,
+                       int32_t maxit, Ctl* c) {
+    hipStream_t st = h->stream;
+    DevLevel& L0 = h->lev[0];
+    const long long n = L0.n;
+    const int ge = grid_ell(h, L0.A.nslices);
+    HIPCHK(hipMemcpyAsync(h->bs, b_dev, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(h->xs, x_dev, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    k_ctl_init<<<1, 64, 0, st>>>(h->ctl, h->hctl_dev, rtol, maxit, form);
+    k_resid<<<ge, WG, 0, st>>>(L0.A.view(), h->bs, h->xs, h->r, 0, red_of(h, FIN_INIT));
+    finish(h, red_of(h, FIN_INIT), ge);
+    HIPCHK(hipGetLastError());
+    return read_ctl(h, c);
+}
+
+// Shared driver of psc_pcg_solve (form 0) and psc_fcg_solve (forms 1-4).
+static int solve_impl(psc_hier* h, int form, psc_net* net, const double* b_dev, double* x_dev,
+                      double rtol, int32_t maxit, int32_t* iters, double* relres, int32_t* fallbacks) {
+    if (!b_dev || !x_dev || !iters || !relres) return fail(PSC_ERR_ARG, "NULL argument");
+    if (!(rtol > 0.0) || maxit < 0) return fail(PSC_ERR_ARG, "rtol must be > 0 and maxit >= 0");
+    if (form_prec(form) == PSC_FP32 && !h->has32) return fail(PSC_ERR_STATE, "FP32 V-cycle needs build_fp32");
+    hipStream_t st = h->stream;
+    DevLevel& L0 = h->lev[0];
+    const long long n = L0.n;
+    const int gv = grid_vec(h, n), ge = grid_ell(h, L0.A.nslices);
+    if (form_net(form)) {
+        int rs = net_check_grid(net, n);
+        if (rs) return rs;
+    }
+    Ctl c;
+    int rs = solve_begin(h, form, b_dev, x_dev, rtol, maxit, &c);
+    if (rs) return rs;
+    if (c.status == PSC_ERR_NAN) return fail(PSC_ERR_NAN, "NaN or Inf in the right-hand side or initial guess");
+    if (c.nb2 == 0.0) {
+        k_fill<double><<<gv, WG, 0, st>>>(n, x_dev, 0.0);
+        HIPCHK(hipStreamSynchronize(st));
+        *iters = 0;
+        *relres = 0.0;
+        if (fallbacks) *fallbacks = 0;
+        return PSC_OK;
+    }
+    const bool use_graph = h->opts.use_graph && !h->timing;
+    if (!c.done) {
+        const Gate gd{h->ctl, GATE_DONE};
+        if (form == 0) {
+            vcycle(h, PSC_FP64, h->r, h->z, FIN_RHO_INIT, h->r, gd);
+            k_copy<double, double><<<gv, WG, 0, st>>>(n, h->p, h->z, gd);
+        } else {
+            k_fill<double><<<gv, WG, 0, st>>>(n, h->q, 0.0);
+            if (form_net(form)) k_set_net_on<<<1, 64, 0, st>>>(h->ctl);
+        }
+        hipGraphExec_t gexec = nullptr;
+        if (use_graph) {
+            rs = get_graph(h, form, net, &gexec);
+            if (rs) return rs;
+        }
+        for (int k = 0; k < maxit; k++) {
+            if (use_graph) HIPCHK(hipGraphLaunch(gexec, st));
+            else if ((rs = issue_iteration(h, form, net))) return rs;
+            HIPCHK(hipEventRecord(h->ring[k % RING], st));
+            if (k >= LAG) {
+                HIPCHK(hipEventSynchronize(h->ring[(k - LAG) % RING]));
+                if (h->hctl->done) break;
+            }
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        timing_collect(h);
+        rs = read_ctl(h, &c);
+        if (rs) return rs;
+    }
+    // true residual in FP64 (ungated: runs after convergence)
+    {
+        Red Rs{h->part, h->ctl, nullptr, FIN_STORE, GATE_NONE};
+        k_resid<<<ge, WG, 0, st>>>(L0.A.view(), h->bs, h->xs, h->q, 0, Rs);
+        finish(h, Rs, ge);
+    }
+    HIPCHK(hipMemcpyAsync(x_dev, h->xs, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    Ctl c2;
+    rs = read_ctl(h, &c2);
+    if (rs) return rs;
+    int status = c.status;
+    if (status == PSC_ERR_NAN) return fail(PSC_ERR_NAN, "NaN met during the iteration");
+    if (status == PSC_ERR_NOT_SPD) return fail(PSC_ERR_NOT_SPD, "CG breakdown (p.q <= 0 or r.z <= 0)");
+    *iters = c.iter;
+    *relres = std::sqrt(c2.out1) / std::sqrt(c2.out0);
+    if (fallbacks) *fallbacks = c.fallbacks;
+    if (c.done == 0) status = PSC_NOCONV;
+    if (status == PSC_NOCONV) g_err = "maximum number of iterations reached";
+    return status;
+}
+
+static int solve(psc_hier* h, int form, psc_net* net, const double* b_dev, double* x_dev, double rtol,
+                 int32_t maxit, int32_t* iters, double* relres, int32_t* fallbacks) {
+    if (!h) return fail(PSC_ERR_ARG, "NULL handle");
+    if (!h->ctl) return fail(PSC_ERR_STATE, "hierarchy was built host-only");
+    HIPCHK(hipSetDevice(h->device));
+    int st = join_in(h);
+    if (st) return st;
+    st = solve_impl(h, form, net, b_dev, x_dev, rtol, maxit, iters, relres, fallbacks);
+    int j = join_out(h);
+    return st ? st : j;
+}
+
+// Scaled crops (r/s, z/s), s = sqrt(rr/N), of the current PCG pair. One
+// thread per crop cell; origins holds cpi (z, y, x) corners.
+__global__ __launch_bounds__(WG) void k_crop(const double* __restrict__ r, const double* __restrict__ z,
+                                             const double* rr, long long N, int nx, int ny,
+                                             const int* __restrict__ origins, int cpi, int crop,
+                                             float* __restrict__ out_r, float* __restrict__ out_z,
+                                             Gate g) {
+    if (gate_skip(g)) return;
+    const long long per = (long long)crop * crop * crop;
+    const long long t = (long long)blockIdx.x * WG + threadIdx.x;
+    if (t >= per * cpi) return;
+    const int c = (int)(t / per);
+    const long long w = t % per;
+    const int cx = (int)(w % crop), cy = (int)((w / crop) % crop), cz = (int)(w / ((long long)crop * crop));
+    const long long gi = ((long long)(origins[3 * c] + cz) * ny + (origins[3 * c + 1] + cy)) * nx +
+                         (origins[3 * c + 2] + cx);
+    const double s = sqrt(*rr / (double)N);
+    const double inv = s > 0.0 ? 1.0 / s : 0.0;
+    out_r[t] = (float)(r[gi] * inv);
+    out_z[t] = (float)(z[gi] * inv);
+}
+
+static int pairs_impl(psc_hier* h, const double* b_dev, int nx, int ny, int nz, double rtol, int maxit,
+                      int crop, int cpi, const int32_t* origins, int n_origins, float* r_out,
+                      float* z_out, int capacity, int32_t* count) {
+    hipStream_t st = h->stream;
+    DevLevel& L0 = h->lev[0];
+    const long long n = L0.n;
+    const int gv = grid_vec(h, n);
+    int* d_orig = nullptr;
+    HIPCHK(hipMallocAsync((void**)&d_orig, sizeof(int) * 3 * (size_t)n_origins, st));
+    std::unique_ptr<int, std::function<void(int*)>> guard(d_orig, [st](int* p) { (void)hipFreeAsync(p, st); });
+    HIPCHK(hipMemcpyAsync(d_orig, origins, sizeof(int) * 3 * (size_t)n_origins, hipMemcpyHostToDevice, st));
+    double* x0 = nullptr;
+    HIPCHK(hipMallocAsync((void**)&x0, sizeof(double) * n, st));
+    std::unique_ptr<double, std::function<void(double*)>> guard2(x0, [st](double* p) { (void)hipFreeAsync(p, st); });
+    k_fill<double><<<gv, WG, 0, st>>>(n, x0, 0.0);
+    Ctl c;
+    int rs = solve_begin(h, 0, b_dev, x0, rtol, maxit, &c);
+    if (rs) return rs;
+    if (c.status == PSC_ERR_NAN) return fail(PSC_ERR_NAN, "NaN or Inf in the right-hand side");
+    if (c.done) return PSC_OK;
+    const Gate gd{h->ctl, GATE_DONE};
+    vcycle(h, PSC_FP64, h->r, h->z, FIN_RHO_INIT, h->r, gd);
+    k_copy<double, double><<<gv, WG, 0, st>>>(n, h->p, h->z, gd);
+    const long long per = (long long)crop * crop * crop;
+    for (int k = 0;; k++) {
+        // the pair (r_k, B r_k) is in (h->r, h->z)
+        if ((k + 1) * cpi <= n_origins && *count + cpi <= capacity) {
+            long long tot = per * cpi;
+            k_crop<<<(unsigned)((tot + WG - 1) / WG), WG, 0, st>>>(
+                h->r, h->z, &h->ctl->rr, n, nx, ny, d_orig + 3 * (size_t)k * cpi, cpi, crop,
+                r_out + per * (*count), z_out + per * (*count), gd);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(st));
+            if (h->hctl->done) break;
+            *count += cpi;
+        }
+        if (k >= maxit) break;
+        if ((rs = issue_iteration(h, 0, nullptr))) return rs;
+        HIPCHK(hipStreamSynchronize(st));
+        if (h->hctl->done) break;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return PSC_OK;
+}
+
+}  // namespace psc
+
+using namespace psc;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* psc_last_error(void) { return g_err.c_str(); }
+
+void psc_amg_opts_default(psc_amg_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->sweeps = 2;
+    o->coarse_max = 200;
+    o->max_levels = 30;
+    o->build_fp32 = 0;
+    o->use_graph = 1;
+}
+
+void psc_hier_free(psc_hier* h) {
+    if (!h) return;
+    if (h->opts.host_only) { delete h; return; }
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (auto& e : h->ev_pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto& e : h->ring) (void)hipEventDestroy(e);
+    for (auto& e : h->ev_join)
+        if (e) (void)hipEventDestroy(e);
+    if (h->stream) (void)hipStreamDestroy(h->stream);
+    for (void* p : h->allocs) (void)hipFree(p);
+    if (h->hctl) (void)hipHostFree(h->hctl);
+    delete h;
+}
+
+int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double* v,
+                  const psc_amg_opts* opts, void* hip_stream, psc_hier** out) {
+    if (!out) return fail(PSC_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    auto t0 = std::chrono::steady_clock::now();
+    std::string err;
+    int st = validate_csr(n, rp, ci, v, err);
+    if (st) return fail(st, err);
+    std::unique_ptr<psc_hier, void (*)(psc_hier*)> h(new psc_hier(), psc_hier_free);
+    if (opts) h->opts = *opts;
+    else psc_amg_opts_default(&h->opts);
+    h->user_stream = (hipStream_t)hip_stream;
+    if (!h->opts.host_only) {
+        HIPCHK(hipGetDevice(&h->device));
+        HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+        for (auto& e : h->ev_join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HIPCHK(hipStreamSynchronize(h->user_stream));
+    }
+    SetupOpts so;
+    so.sweeps = h->opts.sweeps;
+    so.coarse_max = h->opts.coarse_max;
+    so.max_levels = h->opts.max_levels;
+    st = build_hierarchy(n, rp, ci, v, so, h->host, err);
+    if (st) return fail(st, err);
+    const bool f32 = h->opts.build_fp32 != 0;
+    h->has32 = f32;
+    const int L = (int)h->host.lev.size();
+    h->lev.resize(L);
+    if (h->opts.host_only) {
+        for (int l = 0; l < L; l++) {
+            h->lev[l].n = h->host.lev[l].n;
+            h->lev[l].nc = h->host.lev[l].nc;
+            h->lev[l].nnz = h->host.lev[l].rp[h->host.lev[l].n];
+        }
+        h->coarse_n = (int)h->host.lev[L - 1].n;
+        h->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *out = h.release();
+        return PSC_OK;
+    }
+    for (int l = 0; l < L; l++) {
+        HostLevel& H = h->host.lev[l];
+        DevLevel& D = h->lev[l];
+        D.n = H.n;
+        D.nc = H.nc;
+        D.nnz = H.rp[H.n];
+        if ((st = upload_ell(h.get(), D.A, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32))) return st;
+        if ((st = upload(h.get(), &D.minv, H.minv.data(), H.n))) return st;
+        if (f32) {
+            auto m32 = to32(H.minv);
+            if ((st = upload(h.get(), &D.minv32, m32.data(), m32.size()))) return st;
+        }
+        if (l > 0) {
+            if ((st = dalloc(h.get(), (void**)&D.b, H.n * sizeof(double)))) return st;
+            if ((st = dalloc(h.get(), (void**)&D.x, H.n * sizeof(double)))) return st;
+            if (f32) {
+                if ((st = dalloc(h.get(), (void**)&D.b32, H.n * sizeof(float)))) return st;
+                if ((st = dalloc(h.get(), (void**)&D.x32, H.n * sizeof(float)))) return st;
+            }
+        }
+        if (l < L - 1) {
+            if ((st = dalloc(h.get(), (void**)&D.r, H.n * sizeof(double)))) return st;
+            if (f32 && (st = dalloc(h.get(), (void**)&D.r32, H.n * sizeof(float)))) return st;
+            if ((st = upload(h.get(), &D.agg, H.agg.data(), H.n))) return st;
+            if ((st = upload(h.get(), &D.pval, H.p.data(), H.n))) return st;
+            if (f32) {
+                auto p32 = to32(H.p);
+                if ((st = upload(h.get(), &D.pval32, p32.data(), p32.size()))) return st;
+            }
+            // R = P^T as CSR over coarse rows: members ascending, values p_i
+            std::vector<int32_t> rrp(H.nc + 1, 0), rci(H.n);
+            std::vector<double> rv(H.n);
+            for (int64_t i = 0; i < H.n; i++) rrp[H.agg[i] + 1]++;
+            for (int64_t I = 0; I < H.nc; I++) rrp[I + 1] += rrp[I];
+            std::vector<int32_t> pos(rrp.begin(), rrp.end() - 1);
+            for (int64_t i = 0; i < H.n; i++) {
+                int32_t o = pos[H.agg[i]]++;
+                rci[o] = (int32_t)i;
+                rv[o] = H.p[i];
+            }
+            if ((st = upload_ell(h.get(), D.R, H.nc, rrp.data(), rci.data(), rv.data(), f32))) return st;
+        }
+    }
+    // coarsest inverse, stored transposed for coalesced reads
+    {
+        int nc = (int)h->host.lev[L - 1].n;
+        h->coarse_n = nc;
+        std::vector<double> invT((size_t)nc * nc);
+        for (int i = 0; i < nc; i++)
+            for (int k = 0; k < nc; k++) invT[(size_t)k * nc + i] = h->host.coarse_inv[(size_t)i * nc + k];
+        if ((st = upload(h.get(), &h->coarse_invT, invT.data(), invT.size()))) return st;
+    }
+    // solver workspace
+    const int64_t N = n;
+    if ((st = dalloc(h.get(), (void**)&h->ctl, sizeof(Ctl)))) return st;
+    if ((st = dalloc(h.get(), (void**)&h->part, 2 * GMAX * sizeof(double)))) return st;
+    for (double** p : {&h->xs, &h->bs, &h->r, &h->z, &h->p, &h->q})
+        if ((st = dalloc(h.get(), (void**)p, N * sizeof(double)))) return st;
+    HIPCHK(hipHostMalloc((void**)&h->hctl, sizeof(HostCtl), hipHostMallocMapped | hipHostMallocCoherent));
+    std::memset(h->hctl, 0, sizeof(HostCtl));
+    HIPCHK(hipHostGetDevicePointer((void**)&h->hctl_dev, h->hctl, 0));
+    h->ring.resize(RING);
+    for (auto& e : h->ring) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    k_ctl_init<<<1, 64, 0, h->stream>>>(h->ctl, h->hctl_dev, 1e-6, 1, 0);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = h.release();
+    return PSC_OK;
+}
+
+int psc_pcg_solve(psc_hier* h, const double* b, double* x, double rtol, int32_t maxit,
+                  int32_t* iters, double* relres) {
+    return solve(h, 0, nullptr, b, x, rtol, maxit, iters, relres, nullptr);
+}
+
+int psc_fcg_solve(psc_hier* h, psc_net* net, int32_t vprec, const double* b, double* x,
+                  double rtol, int32_t maxit, int32_t* iters, double* relres, int32_t* fallbacks) {
+    if (vprec != PSC_FP64 && vprec != PSC_FP32) return fail(PSC_ERR_ARG, "vcycle_prec must be PSC_FP64 or PSC_FP32");
+    int form = (vprec == PSC_FP32 ? 2 : 1) + (net ? 2 : 0);
+    return solve(h, form, net, b, x, rtol, maxit, iters, relres, fallbacks);
+}
+
+int psc_pairs_collect(psc_hier* h, const double* b, int32_t nx, int32_t ny, int32_t nz, double rtol,
+                      int32_t maxit, int32_t crop, int32_t cpi, const int32_t* origins, int32_t n_origins,
+                      float* r_out, float* z_out, int32_t capacity, int32_t* count) {
+    if (!h || !b || !origins || !r_out || !z_out || !count) return fail(PSC_ERR_ARG, "NULL argument");
+    if (!h->ctl) return fail(PSC_ERR_STATE, "hierarchy was built host-only");
+    if ((long long)nx * ny * nz != h->lev[0].n) return fail(PSC_ERR_ARG, "grid does not match the matrix size");
+    if (crop < 1 || crop > nx || crop > ny || crop > nz || cpi < 1 || n_origins < 0 || capacity < 0 ||
+        *count < 0 || *count > capacity || maxit < 0 || !(rtol > 0.0))
+        return fail(PSC_ERR_ARG, "bad crop, count or capacity");
+    for (int i = 0; i < n_origins; i++) {
+        const int dims[3] = {nz, ny, nx};
+        for (int a = 0; a < 3; a++)
+            if (origins[3 * i + a] < 0 || origins[3 * i + a] + crop > dims[a])
+                return fail(PSC_ERR_ARG, "crop origin out of range");
+    }
+    HIPCHK(hipSetDevice(h->device));
+    int st = join_in(h);
+    if (st) return st;
+    st = pairs_impl(h, b, nx, ny, nz, rtol, maxit, crop, cpi, origins, n_origins, r_out, z_out, capacity, count);
+    int j = join_out(h);
+    return st ? st : j;
+}
+
+int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
+    if (!h || !s) return fail(PSC_ERR_ARG, "NULL argument");
+    std::memset(s, 0, sizeof(*s));
+    const int L = (int)h->lev.size();
+    s->levels = L;
+    double z0 = (double)h->lev[0].nnz, zs = 0.0, vb64 = 0.0, vb32 = 0.0;
+    for (int l = 0; l < L; l++) {
+        const DevLevel& D = h->lev[l];
+        s->rows[l] = D.n;
+        s->nnz[l] = D.nnz;
+        s->ell_slots[l] = D.A.slots;
+        zs += (double)D.nnz;
+        if (l < L - 1) {
+            // pre: A, b and minv gathered, r written; restriction: R, r, b_c;
+            // post: A, b, minv, p, agg, x_c gathered, x written
+            double Z = (double)D.nnz, N = (double)D.n, Nc = (double)D.nc;
+            vb64 += 2 * Z * 12 + N * 12 * 2 /* P and R */ + N * (8 * 8) + Nc * 8 * 2;
+            vb32 += 2 * Z * 8 + N * 8 * 2 + N * (8 * 4) + Nc * 4 * 2;
+        } else {
+            double n2 = (double)D.n * D.n;
+            vb64 += 8 * n2;
+            vb32 += 8 * n2;
+        }
+    }
+    s->operator_complexity = zs / z0;
+    s->vcycle_bytes_fp64 = vb64;
+    s->vcycle_bytes_fp32 = vb32;
+    s->spmv_bytes_fp64 = z0 * 12 + 2 * 8 * (double)h->lev[0].n;
+    s->setup_seconds = h->setup_seconds;
+    s->device_bytes = h->device_bytes;
+    return PSC_OK;
+}
+
+int psc_hier_export_level(const psc_hier* h, int32_t l, int32_t* agg, double* p, double* minv,
+                          int32_t* rp, int32_t* ci, double* v) {
+    if (!h || l < 0 || l >= (int)h->host.lev.size()) return fail(PSC_ERR_ARG, "bad level");
+    const HostLevel& H = h->host.lev[l];
+    if (agg && !H.agg.empty()) std::memcpy(agg, H.agg.data(), H.n * sizeof(int32_t));
+    if (p && !H.p.empty()) std::memcpy(p, H.p.data(), H.n * sizeof(double));
+    if (minv) std::memcpy(minv, H.minv.data(), H.n * sizeof(double));
+    if (rp) std::memcpy(rp, H.rp.data(), (H.n + 1) * sizeof(int32_t));
+    if (ci) std::memcpy(ci, H.ci.data(), H.ci.size() * sizeof(int32_t));
+    if (v) std::memcpy(v, H.v.data(), H.v.size() * sizeof(double));
+    return PSC_OK;
+}
+
+int psc_vcycle_apply(psc_hier* h, int32_t prec, const double* r, double* z) {
+    if (!h || !r || !z) return fail(PSC_ERR_ARG, "NULL argument");
+    if (!h->ctl) return fail(PSC_ERR_STATE, "hierarchy was built host-only");
+    if (prec != PSC_FP64 && prec != PSC_FP32) return fail(PSC_ERR_ARG, "prec must be PSC_FP64 or PSC_FP32");
+    if (prec == PSC_FP32 && !h->has32) return fail(PSC_ERR_STATE, "FP32 V-cycle needs build_fp32");
+    HIPCHK(hipSetDevice(h->device));
+    int st = join_in(h);
+    if (st) return st;
+    vcycle(h, prec, r, z, FIN_NONE, nullptr, Gate{nullptr, GATE_NONE});
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+    timing_collect(h);
+    return join_out(h);
+}
+
+int psc_spmv(psc_hier* h, int32_t l, int32_t prec, const void* x, void* y) {
+    if (!h || !x || !y || l < 0 || l >= (int)h->lev.size()) return fail(PSC_ERR_ARG, "bad argument");
+    if (prec == PSC_FP32 && !h->has32) return fail(PSC_ERR_STATE, "FP32 copies not built");
+    if (!h->ctl) return fail(PSC_ERR_STATE, "hierarchy was built host-only");
+    HIPCHK(hipSetDevice(h->device));
+    int st = join_in(h);
+    if (st) return st;
+    DevLevel& D = h->lev[l];
+    {
+        TimeScope t(h, l == 0 ? 0 : 7);
+        if (prec == PSC_FP64)
+            k_spmv<double><<<grid_ell(h, D.A.nslices), WG, 0, h->stream>>>(D.A.view(), (const double*)x, (double*)y, Gate{nullptr, GATE_NONE});
+        else
+            k_spmv<float><<<grid_ell(h, D.A.nslices), WG, 0, h->stream>>>(D.A.view32(), (const float*)x, (float*)y, Gate{nullptr, GATE_NONE});
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+    timing_collect(h);
+    return join_out(h);
+}
+
+int psc_timing_enable(psc_hier* h, int32_t on) {
+    if (!h) return fail(PSC_ERR_ARG, "NULL handle");
+    h->timing = on != 0;
+    return PSC_OK;
+}
+
+int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms) {
+    if (!h) return fail(PSC_ERR_ARG, "NULL handle");
+    timing_collect(h);
+    for (int k = 0; k < PSC_TIMING_KERNELS; k++) {
+        if (counts) counts[k] = h->t_count[k];
+        if (total_ms) total_ms[k] = h->t_ms[k];
+        h->t_count[k] = 0;
+        h->t_ms[k] = 0.0;
+    }
+    return PSC_OK;
+}
+
+int psc_tune(psc_hier* h, int32_t key, int32_t value) {
+    if (!h) return fail(PSC_ERR_ARG, "NULL handle");
+    if (key == PSC_TUNE_GRID_MAX) {
+        if (value < NXCD || value > GMAX || value % NXCD) return fail(PSC_ERR_ARG, "grid cap must be a multiple of 8 in [8, 65536]");
+        h->gmax = value;
+        drop_graphs(h);
+        return PSC_OK;
+    }
+    return fail(PSC_ERR_ARG, "unknown tuning key");
+}
+
+}  // extern "C"
+

@@ -1,0 +1,54 @@
+// kernels.h -- device-side building blocks shared by the HIP sources of libpsc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psc {
+
+constexpr int WG = 256;        // threads per workgroup: 4 wavefronts of 64
+constexpr int SLICE = 64;      // rows per hacked-ELL slice: one wavefront
+constexpr int NXCD = 8;        // accelerator complex dies; workgroups are dealt round-robin
+constexpr int GMAX = 65536;    // largest grid of the streaming kernels
+
+// Solver control block, device resident. Scalars of the Krylov recurrence
+// live here so no host round trip is needed between kernels.
+struct Ctl {
+    double rtol, nb2, rr, rr_old, rho, alpha, beta, pq, pr, zq, zr, pq_prev, out0, out1;
+    int done, iter, status, maxit;
+    int check, have_prev, net_on, use_net, fallbacks, form;
+};
+
+// Which kernels of an iteration run: GATE_NONE always; GATE_DONE until the
+// solve is over; GATE_NET only on a network step; GATE_VC only on a V-cycle
+// step (the choice is made on the device, see ctl->use_net).
+enum GateMode { GATE_NONE = 0, GATE_DONE = 1, GATE_NET = 2, GATE_VC = 3 };
+struct Gate {
+    const Ctl* ctl;
+    int mode;
+};
+__device__ __forceinline__ bool gate_skip(const Gate& g) {
+    if (!g.ctl || g.mode == GATE_NONE) return false;
+    if (g.ctl->done) return true;
+    if (g.mode == GATE_NET) return !g.ctl->use_net;
+    if (g.mode == GATE_VC) return g.ctl->use_net != 0;
+    return false;
+}
+
+// Host-mapped mirror polled by the host loop.
+struct HostCtl {
+    int done, iter, status, fallbacks;
+};
+
+// Hacked-ELL operator: slices of 64 rows; slice s holds its w_s columns
+// column-major at [off[s], off[s+1]) (w_s = (off[s+1]-off[s])/64).
+template <typename T>
+struct Ell {
+    const long long* off;
+    const T* val;
+    const int* col;
+    long long nrows;
+    long long nslices;
+};
+
+}  // namespace psc

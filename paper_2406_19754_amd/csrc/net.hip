@@ -1,0 +1,758 @@
+// net.hip -- learned convolutional preconditioner for flexible CG on gfx950.
+//
+// Network (3 layers, 3x3x3 taps, 16 channels, zero padding, bias):
+//   u = bf16(r / s), s = ||r|| / sqrt(N)
+//   h1 = bf16(GELU(W1 * u + b1))           1 -> 16, FP32 vector FMA
+//   h2 = bf16(GELU(W2 * h1 + b2))          16 -> 16, MFMA v_mfma_f32_16x16x32_bf16
+//   out = W3 * h2 + b3,  z = s out         16 -> 1, FP32 vector FMA
+// GELU(t) = t Phi(t). Activations are channel-last bfloat16 (32 bytes per
+// cell), weights an FP32 master copy plus a bfloat16 working copy that is
+// refreshed after every optimiser step.
+//
+// The 16 -> 16 layer is an implicit GEMM: one wavefront computes 16
+// consecutive cells of an x-row times 16 output channels; the K dimension
+// is (tap, input channel) = 27 x 16 = 432, covered by 14 MFMA steps of K=32
+// (two taps per step, the last half empty). Lane l of the A operand holds
+// the 8 input channels 8*((l>>4)&1).. of cell (l & 15) at tap 2t + (l>>5):
+// one 16-byte load of the channel-last activations. The B operand (weights)
+// is pre-arranged per step and lane once per weight update.
+//
+// Backward: the 16 -> 16 data gradient is the same MFMA kernel with the
+// channel-transposed, tap-flipped weights; weight gradients are per-block
+// FP32 partial sums over cells reduced in a fixed order (deterministic).
+// Adam runs on the FP32 master copy.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/psc.h"
+#include "kernels.h"
+#include "net.h"
+
+namespace psc {
+
+extern thread_local std::string g_err;
+
+static int nfail(int st, const std::string& m) {
+    g_err = m;
+    return st;
+}
+
+#define NHIPCHK(call)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return nfail(PSC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int NC = 16;                       // channels
+constexpr int NP = 7809;                     // parameters
+constexpr int OW1 = 0, OB1 = 432, OW2 = 448, OB2 = 7360, OW3 = 7376, OB3 = 7808;
+constexpr int KSTEPS = 14;                   // ceil(27 * 16 / 32) MFMA steps
+constexpr int WGRAD_BLOCKS = 512;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short bf16r;                // raw bfloat16 bits
+
+// float -> bfloat16, round to nearest even (NaN kept quiet)
+__host__ __device__ inline bf16r f2bf(float f) {
+    unsigned u;
+    __builtin_memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) {
+        if (u & 0x007fffffu) u |= 0x00400000u;
+        return (bf16r)(u >> 16);
+    }
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (bf16r)(u >> 16);
+}
+__device__ inline float bf2f(bf16r b) { return __uint_as_float((unsigned)b << 16); }
+__device__ inline float gelu(float t) { return 0.5f * t * (1.0f + erff(t * 0.70710678118654752f)); }
+__device__ inline float gelu_d(float t) {
+    return 0.5f * (1.0f + erff(t * 0.70710678118654752f)) + t * expf(-0.5f * t * t) * 0.39894228040143268f;
+}
+
+// B samples of D x H x W cells (x fastest); cell c = ((b*D + z)*H + y)*W + x
+struct Dims {
+    int B, D, H, W;
+    __host__ __device__ long long cells() const { return (long long)B * D * H * W; }
+};
+
+struct Cell {
+    int b, z, y, x;
+};
+__device__ inline Cell cell_of(const Dims& d, long long c) {
+    Cell r;
+    r.x = (int)(c % d.W);
+    long long t = c / d.W;
+    r.y = (int)(t % d.H);
+    t /= d.H;
+    r.z = (int)(t % d.D);
+    r.b = (int)(t / d.D);
+    return r;
+}
+// neighbour at offset (dz-1, dy-1, dx-1) * sgn of tap t; -1 outside the sample
+__device__ inline long long nbr(const Dims& d, const Cell& c, int t, int sgn) {
+    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+    const int zz = c.z + sgn * dz, yy = c.y + sgn * dy, xx = c.x + sgn * dx;
+    if (zz < 0 || zz >= d.D || yy < 0 || yy >= d.H || xx < 0 || xx >= d.W) return -1;
+    return (((long long)c.b * d.D + zz) * d.H + yy) * d.W + xx;
+}
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// forward kernels
+// ---------------------------------------------------------------------------
+
+// u = bf16(r / s) (FP64 field, s = sqrt(*rr / N); s = 0 gives u = 0) or bf16(in).
+template <bool FROM64>
+__global__ __launch_bounds__(WG) void k_prep_u(long long n, const double* __restrict__ r64,
+                                               const float* __restrict__ in32, const double* rr,
+                                               long long N, bf16r* __restrict__ u, Gate g) {
+    if (gate_skip(g)) return;
+    const long long c = (long long)blockIdx.x * WG + threadIdx.x;
+    if (c >= n) return;
+    if (FROM64) {
+        const double s = sqrt(*rr / (double)N);
+        u[c] = s > 0.0 ? f2bf((float)(r64[c] / s)) : (bf16r)0;
+    } else {
+        u[c] = f2bf(in32[c]);
+    }
+}
+
+// h1 = bf16(GELU(W1 * u + b1)); a1 = pre-activation (training only)
+__global__ __launch_bounds__(WG) void k_conv1(Dims d, const bf16r* __restrict__ u, const float* __restrict__ wr,
+                                              bf16r* __restrict__ h1, float* __restrict__ a1, Gate g) {
+    if (gate_skip(g)) return;
+    __shared__ float w[NC * 27 + NC];
+    for (int i = threadIdx.x; i < NC * 27 + NC; i += WG) w[i] = wr[OW1 + i];
+    __syncthreads();
+    const long long c = (long long)blockIdx.x * WG + threadIdx.x;
+    if (c >= d.cells()) return;
+    const Cell cc = cell_of(d, c);
+    float acc[NC];
+#pragma unroll
+    for (int co = 0; co < NC; co++) acc[co] = w[NC * 27 + co];
+    for (int t = 0; t < 27; t++) {
+        const long long nb = nbr(d, cc, t, 1);
+        if (nb < 0) continue;
+        const float v = bf2f(u[nb]);
+#pragma unroll
+        for (int co = 0; co < NC; co++) acc[co] += w[co * 27 + t] * v;
+    }
+    unsigned pk[NC / 2];
+#pragma unroll
+    for (int k = 0; k < NC / 2; k++)
+        pk[k] = (unsigned)f2bf(gelu(acc[2 * k])) | ((unsigned)f2bf(gelu(acc[2 * k + 1])) << 16);
+    u32x4* hp = (u32x4*)(h1 + c * NC);
+    hp[0] = u32x4{pk[0], pk[1], pk[2], pk[3]};
+    hp[1] = u32x4{pk[4], pk[5], pk[6], pk[7]};
+    if (a1) {
+        f32x4* ap = (f32x4*)(a1 + c * NC);
+#pragma unroll
+        for (int k = 0; k < 4; k++) ap[k] = f32x4{acc[4 * k], acc[4 * k + 1], acc[4 * k + 2], acc[4 * k + 3]};
+    }
+}
+
+// 16 -> 16 convolution on MFMA. MODE 0 (forward): out = bias + W * in,
+// aout = out (may be NULL), hout = bf16(GELU(out)). MODE 1 (data gradient
+// with tap-flipped, channel-transposed weights): aout = (W' * in) * GELU'(aprev).
+template <int MODE>
+__global__ __launch_bounds__(WG) void k_conv2(Dims d, const bf16r* __restrict__ in,
+                                              const bf16x8* __restrict__ frag, const float* __restrict__ wr,
+                                              const float* __restrict__ aprev, float* __restrict__ aout,
+                                              bf16r* __restrict__ hout, Gate g) {
+    if (gate_skip(g)) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tpr = (d.W + 15) / 16;
+    const long long ntiles = (long long)d.B * d.D * d.H * tpr;
+    const long long T = (long long)blockIdx.x * (WG / 64) + wv;
+    if (T >= ntiles) return;   // uniform per wavefront
+    const long long row = T / tpr;
+    const int x0 = (int)(T % tpr) * 16;
+    Cell cc;
+    cc.y = (int)(row % d.H);
+    cc.z = (int)((row / d.H) % d.D);
+    cc.b = (int)(row / ((long long)d.H * d.D));
+    cc.x = x0 + (lane & 15);
+    const int half = (lane >> 4) & 1, tsel = lane >> 5;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int t = 0; t < KSTEPS; t++) {
+        const int tap = 2 * t + tsel;
+        u32x4 av = {0u, 0u, 0u, 0u};
+        if (tap < 27 && cc.x < d.W) {
+            const long long nb = nbr(d, cc, tap, 1);
+            if (nb >= 0) av = *(const u32x4*)(in + nb * NC + half * 8);
+        }
+        const bf16x8 A = __builtin_bit_cast(bf16x8, av);
+        const bf16x8 Bm = frag[t * 64 + lane];
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bm, acc, 0, 0, 0);
+    }
+    // lane holds rows 4*(lane>>4)+i (cells) of column lane&15 (channel)
+    const int co = lane & 15;
+    const long long rowbase = row * d.W;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const int xx = x0 + 4 * (lane >> 4) + i;
+        if (xx >= d.W) continue;
+        const long long c = rowbase + xx;
+        float v = acc[i];
+        if (MODE == 0) {
+            v += wr[OB2 + co];
+            if (aout) aout[c * NC + co] = v;
+            hout[c * NC + co] = f2bf(gelu(v));
+        } else {
+            aout[c * NC + co] = v * gelu_d(aprev[c * NC + co]);
+        }
+    }
+}
+
+// out = W3 * h2 + b3; TO64: z = s * out with s = sqrt(*rr / N), else out32.
+template <bool TO64>
+__global__ __launch_bounds__(WG) void k_conv3(Dims d, const bf16r* __restrict__ h2, const float* __restrict__ wr,
+                                              const double* rr, long long N, double* __restrict__ z64,
+                                              float* __restrict__ out32, Gate g) {
+    if (gate_skip(g)) return;
+    __shared__ float w[NC * 27 + 1];
+    for (int i = threadIdx.x; i < NC * 27 + 1; i += WG) w[i] = wr[OW3 + i];
+    __syncthreads();
+    const long long c = (long long)blockIdx.x * WG + threadIdx.x;
+    if (c >= d.cells()) return;
+    const Cell cc = cell_of(d, c);
+    float acc = w[NC * 27];
+    for (int t = 0; t < 27; t++) {
+        const long long nb = nbr(d, cc, t, 1);
+        if (nb < 0) continue;
+        const u32x4* hp = (const u32x4*)(h2 + nb * NC);
+        const u32x4 v0 = hp[0], v1 = hp[1];
+        const unsigned pk[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            acc += w[(2 * k) * 27 + t] * __uint_as_float(pk[k] << 16);
+            acc += w[(2 * k + 1) * 27 + t] * __uint_as_float(pk[k] & 0xffff0000u);
+        }
+    }
+    if (TO64) {
+        const double s = sqrt(*rr / (double)N);
+        z64[c] = s * (double)acc;
+    } else {
+        out32[c] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// loss and backward kernels
+// ---------------------------------------------------------------------------
+
+// g3 = 2 (out - target) / cnt on interior cells (0 elsewhere); partial sum of squares.
+__global__ __launch_bounds__(WG) void k_loss(Dims d, int margin, double cnt, const float* __restrict__ out,
+                                             const float* __restrict__ tgt, float* __restrict__ g3,
+                                             double* __restrict__ part) {
+    __shared__ double red[WG / 64];
+    const long long c = (long long)blockIdx.x * WG + threadIdx.x;
+    double sq = 0.0;
+    if (c < d.cells()) {
+        const Cell cc = cell_of(d, c);
+        const bool in = cc.z >= margin && cc.z < d.D - margin && cc.y >= margin && cc.y < d.H - margin &&
+                        cc.x >= margin && cc.x < d.W - margin;
+        const float df = in ? out[c] - tgt[c] : 0.0f;
+        g3[c] = (float)(2.0 * (double)df / cnt);
+        sq = (double)df * (double)df;
+    }
+    sq = wave_sum_d(sq);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// sum of partials in a fixed order, times `scale`, into *dst
+__global__ __launch_bounds__(WG) void k_sum_partials(const double* __restrict__ part, int n, double scale,
+                                                     double* dst, float* dst32) {
+    __shared__ double red[WG / 64];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += WG) a += part[i];
+    a = wave_sum_d(a);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double s = ((red[0] + red[1]) + (red[2] + red[3])) * scale;
+        if (dst) *dst = s;
+        if (dst32) *dst32 = (float)s;
+    }
+}
+
+// partial sums of r.r over blocks
+__global__ __launch_bounds__(WG) void k_sumsq(long long n, const double* __restrict__ r, double* __restrict__ part) {
+    __shared__ double red[WG / 64];
+    double a = 0.0;
+    for (long long i = (long long)blockIdx.x * WG + threadIdx.x; i < n; i += (long long)gridDim.x * WG)
+        a += r[i] * r[i];
+    a = wave_sum_d(a);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// ga2 = (W3^T * g3) * GELU'(a2): FP32 copy (weight gradient) and bfloat16 copy (MFMA data gradient)
+__global__ __launch_bounds__(WG) void k_conv3_bwd(Dims d, const float* __restrict__ g3, const float* __restrict__ wr,
+                                                  const float* __restrict__ a2, float* __restrict__ ga2f,
+                                                  bf16r* __restrict__ ga2b) {
+    __shared__ float w[NC * 27];
+    for (int i = threadIdx.x; i < NC * 27; i += WG) w[i] = wr[OW3 + i];
+    __syncthreads();
+    const long long c = (long long)blockIdx.x * WG + threadIdx.x;
+    if (c >= d.cells()) return;
+    const Cell cc = cell_of(d, c);
+    float acc[NC];
+#pragma unroll
+    for (int ci = 0; ci < NC; ci++) acc[ci] = 0.f;
+    for (int t = 0; t < 27; t++) {
+        const long long nb = nbr(d, cc, t, -1);
+        if (nb < 0) continue;
+        const float gv = g3[nb];
+#pragma unroll
+        for (int ci = 0; ci < NC; ci++) acc[ci] += w[ci * 27 + t] * gv;
+    }
+    unsigned pk[NC / 2];
+#pragma unroll
+    for (int ci = 0; ci < NC; ci++) acc[ci] *= gelu_d(a2[c * NC + ci]);
+#pragma unroll
+    for (int k = 0; k < NC / 2; k++) pk[k] = (unsigned)f2bf(acc[2 * k]) | ((unsigned)f2bf(acc[2 * k + 1]) << 16);
+    u32x4* hp = (u32x4*)(ga2b + c * NC);
+    hp[0] = u32x4{pk[0], pk[1], pk[2], pk[3]};
+    hp[1] = u32x4{pk[4], pk[5], pk[6], pk[7]};
+    f32x4* ap = (f32x4*)(ga2f + c * NC);
+#pragma unroll
+    for (int k = 0; k < 4; k++) ap[k] = f32x4{acc[4 * k], acc[4 * k + 1], acc[4 * k + 2], acc[4 * k + 3]};
+}
+
+// Weight-gradient partials of one layer: dW[co][ci][t] = sum_c gout[c][co] in[c+off_t][ci],
+// db[co] = sum_c gout[c][co]. Thread = (pair (co,ci), cell group); block = chunk of cells.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(WG) void k_wgrad(Dims d, const bf16r* __restrict__ in, const float* __restrict__ gout,
+                                              float* __restrict__ part) {
+    constexpr int NPAIR = CIN * COUT, G = WG / NPAIR, NW = NPAIR * 27, STRIDE = NW + COUT;
+    __shared__ float red[WG * 28];
+    const int tid = threadIdx.x, pair = tid % NPAIR, grp = tid / NPAIR;
+    const int co = pair / CIN, ci = pair % CIN;
+    float acc[27];
+#pragma unroll
+    for (int t = 0; t < 27; t++) acc[t] = 0.f;
+    float accb = 0.f;
+    const long long n = d.cells();
+    const long long per = (n + gridDim.x - 1) / gridDim.x;
+    const long long lo = (long long)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+    if (grp < G) {
+        for (long long c = lo + grp; c < hi; c += G) {
+            const float gv = gout[c * COUT + co];
+            const Cell cc = cell_of(d, c);
+#pragma unroll
+            for (int t = 0; t < 27; t++) {
+                const long long nb = nbr(d, cc, t, 1);
+                if (nb >= 0) acc[t] += gv * bf2f(in[nb * CIN + ci]);
+            }
+            accb += gv;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 27; t++) red[tid * 28 + t] = acc[t];
+    red[tid * 28 + 27] = accb;
+    __syncthreads();
+    if (tid < NPAIR) {
+        float* dst = part + (size_t)blockIdx.x * STRIDE;
+        for (int t = 0; t < 28; t++) {
+            float s = 0.f;
+            for (int g2 = 0; g2 < G; g2++) s += red[(g2 * NPAIR + tid) * 28 + t];
+            if (t < 27) dst[tid * 27 + t] = s;
+            else if (ci == 0) dst[NW + co] = s;
+        }
+    }
+}
+
+// grad[ow + w] / grad[ob + co] = sum over blocks (fixed order) of the partials
+__global__ __launch_bounds__(WG) void k_wreduce(const float* __restrict__ part, int nblk, int nw, int cout,
+                                                int ow, int ob, float* __restrict__ grad) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= nw + cout) return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; b++) s += part[(size_t)b * (nw + cout) + i];
+    grad[i < nw ? ow + i : ob + (i - nw)] = s;
+}
+
+__global__ __launch_bounds__(WG) void k_adam(int np, float* __restrict__ p, float* __restrict__ m,
+                                             float* __restrict__ v, const float* __restrict__ g, float lr,
+                                             float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= np) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__device__ inline bool is_weight(int i) {
+    return (i >= OW1 && i < OB1) || (i >= OW2 && i < OB2) || (i >= OW3 && i < OB3);
+}
+
+// Working copy: weights rounded to bfloat16 (held as float), biases FP32;
+// MFMA B-operand fragments of W2 (forward) and of the tap-flipped,
+// channel-transposed W2 (data gradient).
+__global__ __launch_bounds__(WG) void k_refresh(const float* __restrict__ master, float* __restrict__ wr,
+                                                bf16r* __restrict__ ffwd, bf16r* __restrict__ fbwd) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i < NP) wr[i] = is_weight(i) ? __uint_as_float((unsigned)f2bf(master[i]) << 16) : master[i];
+    if (i < KSTEPS * 64 * 8) {
+        const int j = i & 7, l = (i >> 3) & 63, t = i >> 9;
+        const int tap = 2 * t + (l >> 5);
+        const int a = l & 15, bch = 8 * ((l >> 4) & 1) + j;
+        bf16r vf = 0, vb = 0;
+        if (tap < 27) {
+            vf = f2bf(master[OW2 + (a * NC + bch) * 27 + tap]);          // W2[co=a][ci=bch][tap]
+            vb = f2bf(master[OW2 + (bch * NC + a) * 27 + (26 - tap)]);   // W2[co=bch][ci=a][26-tap]
+        }
+        ffwd[i] = vf;
+        fbwd[i] = vb;
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_gather(long long per, const float* __restrict__ src,
+                                               const int* __restrict__ ids, int B, float* __restrict__ dst) {
+    const long long t = (long long)blockIdx.x * WG + threadIdx.x;
+    if (t >= per * B) return;
+    const int b = (int)(t / per);
+    dst[t] = src[(long long)ids[b] * per + (t % per)];
+}
+
+static inline unsigned blocks_for(long long n) { return (unsigned)((n + WG - 1) / WG); }
+
+}  // namespace psc
+
+using namespace psc;
+
+struct psc_net {
+    hipStream_t user_stream = nullptr, stream = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int device = 0;
+    float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *wr = nullptr;
+    bf16r *ffwd = nullptr, *fbwd = nullptr;
+    long long adam_t = 0;
+    // inference grid
+    int gx = 0, gy = 0, gz = 0;
+    long long gcells = 0;
+    bf16r *u = nullptr, *h1 = nullptr, *h2 = nullptr;
+    double* rr = nullptr;
+    double* dpart = nullptr;        // 4096 doubles of reduction partials
+    uint64_t gen = 1;
+    // training buffers, sized for tcells cells
+    long long tcells = 0;
+    float *in_b = nullptr, *tgt_b = nullptr, *out_b = nullptr, *a1 = nullptr, *a2 = nullptr, *g3 = nullptr,
+          *ga2f = nullptr, *ga1 = nullptr;
+    bf16r *tu = nullptr, *th1 = nullptr, *th2 = nullptr, *ga2b = nullptr;
+    double* lpart = nullptr;        // one loss partial per workgroup of the batch
+    float* wpart = nullptr;
+    double* loss_dev = nullptr;
+};
+
+namespace psc {
+
+static void net_free_train(psc_net* n) {
+    for (void* p : {(void*)n->in_b, (void*)n->tgt_b, (void*)n->out_b, (void*)n->a1, (void*)n->a2, (void*)n->g3,
+                    (void*)n->ga2f, (void*)n->ga1, (void*)n->tu, (void*)n->th1, (void*)n->th2, (void*)n->ga2b,
+                    (void*)n->lpart})
+        if (p) (void)hipFree(p);
+    n->in_b = n->tgt_b = n->out_b = n->a1 = n->a2 = n->g3 = n->ga2f = n->ga1 = nullptr;
+    n->tu = n->th1 = n->th2 = n->ga2b = nullptr;
+    n->lpart = nullptr;
+    n->tcells = 0;
+}
+
+static int net_train_buffers(psc_net* n, long long cells) {
+    if (cells <= n->tcells) return PSC_OK;
+    NHIPCHK(hipStreamSynchronize(n->stream));
+    net_free_train(n);
+    const size_t c = (size_t)cells;
+    NHIPCHK(hipMalloc(&n->in_b, c * 4));
+    NHIPCHK(hipMalloc(&n->tgt_b, c * 4));
+    NHIPCHK(hipMalloc(&n->out_b, c * 4));
+    NHIPCHK(hipMalloc(&n->g3, c * 4));
+    NHIPCHK(hipMalloc(&n->a1, c * NC * 4));
+    NHIPCHK(hipMalloc(&n->a2, c * NC * 4));
+    NHIPCHK(hipMalloc(&n->ga2f, c * NC * 4));
+    NHIPCHK(hipMalloc(&n->ga1, c * NC * 4));
+    NHIPCHK(hipMalloc(&n->tu, c * 2));
+    NHIPCHK(hipMalloc(&n->th1, c * NC * 2));
+    NHIPCHK(hipMalloc(&n->th2, c * NC * 2));
+    NHIPCHK(hipMalloc(&n->ga2b, c * NC * 2));
+    NHIPCHK(hipMalloc(&n->lpart, (c / WG + 2) * sizeof(double)));
+    n->tcells = cells;
+    return PSC_OK;
+}
+
+static void refresh(psc_net* n, hipStream_t st) {
+    k_refresh<<<blocks_for(KSTEPS * 64 * 8 > NP ? KSTEPS * 64 * 8 : NP), WG, 0, st>>>(n->master, n->wr, n->ffwd, n->fbwd);
+}
+
+// Forward on B samples: input (FP64 r with *rr, or float in32) -> out.
+static void forward(psc_net* n, hipStream_t st, const Dims& d, const double* r64, const float* in32,
+                    const double* rr, long long N, bf16r* u, bf16r* h1, bf16r* h2, float* a1, float* a2,
+                    double* z64, float* out32, Gate g) {
+    const long long cells = d.cells();
+    if (r64) k_prep_u<true><<<blocks_for(cells), WG, 0, st>>>(cells, r64, nullptr, rr, N, u, g);
+    else k_prep_u<false><<<blocks_for(cells), WG, 0, st>>>(cells, nullptr, in32, nullptr, 1, u, g);
+    k_conv1<<<blocks_for(cells), WG, 0, st>>>(d, u, n->wr, h1, a1, g);
+    const long long tiles = (long long)d.B * d.D * d.H * ((d.W + 15) / 16);
+    k_conv2<0><<<(unsigned)((tiles + 3) / 4), WG, 0, st>>>(d, h1, (const bf16x8*)n->ffwd, n->wr, nullptr, a2, h2, g);
+    if (z64) k_conv3<true><<<blocks_for(cells), WG, 0, st>>>(d, h2, n->wr, rr, N, z64, nullptr, g);
+    else k_conv3<false><<<blocks_for(cells), WG, 0, st>>>(d, h2, n->wr, nullptr, 1, nullptr, out32, g);
+}
+
+// Loss and gradient of the current batch (in_b, tgt_b) into n->grad; loss
+// (mean) into *loss_dst (device double) and, if given, loss32 (device float).
+static void loss_grad(psc_net* n, hipStream_t st, const Dims& d, int margin, double* loss_dst, float* loss32) {
+    const long long cells = d.cells();
+    const Gate g0{nullptr, GATE_NONE};
+    forward(n, st, d, nullptr, n->in_b, nullptr, 1, n->tu, n->th1, n->th2, n->a1, n->a2, nullptr, n->out_b, g0);
+    const double cnt = (double)d.B * (d.D - 2 * margin) * (d.H - 2 * margin) * (d.W - 2 * margin);
+    const unsigned nb = blocks_for(cells);
+    k_loss<<<nb, WG, 0, st>>>(d, margin, cnt, n->out_b, n->tgt_b, n->g3, n->lpart);
+    k_sum_partials<<<1, WG, 0, st>>>(n->lpart, (int)nb, 1.0 / cnt, loss_dst, loss32);
+    // layer 3: data gradient into ga2 and weight gradient
+    k_conv3_bwd<<<nb, WG, 0, st>>>(d, n->g3, n->wr, n->a2, n->ga2f, n->ga2b);
+    k_wgrad<NC, 1><<<WGRAD_BLOCKS, WG, 0, st>>>(d, n->th2, n->g3, n->wpart);
+    k_wreduce<<<blocks_for(NC * 27 + 1), WG, 0, st>>>(n->wpart, WGRAD_BLOCKS, NC * 27, 1, OW3, OB3, n->grad);
+    // layer 2: data gradient (MFMA) into ga1, weight gradient
+    const long long tiles = (long long)d.B * d.D * d.H * ((d.W + 15) / 16);
+    k_conv2<1><<<(unsigned)((tiles + 3) / 4), WG, 0, st>>>(d, n->ga2b, (const bf16x8*)n->fbwd, n->wr, n->a1, n->ga1,
+                                                           nullptr, g0);
+    k_wgrad<NC, NC><<<WGRAD_BLOCKS, WG, 0, st>>>(d, n->th1, n->ga2f, n->wpart);
+    k_wreduce<<<blocks_for(NC * NC * 27 + NC), WG, 0, st>>>(n->wpart, WGRAD_BLOCKS, NC * NC * 27, NC, OW2, OB2, n->grad);
+    // layer 1: weight gradient
+    k_wgrad<1, NC><<<WGRAD_BLOCKS, WG, 0, st>>>(d, n->tu, n->ga1, n->wpart);
+    k_wreduce<<<blocks_for(NC * 27 + NC), WG, 0, st>>>(n->wpart, WGRAD_BLOCKS, NC * 27, NC, OW1, OB1, n->grad);
+}
+
+static int join_in(psc_net* n) {
+    NHIPCHK(hipSetDevice(n->device));
+    NHIPCHK(hipEventRecord(n->ev[0], n->user_stream));
+    NHIPCHK(hipStreamWaitEvent(n->stream, n->ev[0], 0));
+    return PSC_OK;
+}
+static int join_out(psc_net* n) {
+    NHIPCHK(hipEventRecord(n->ev[1], n->stream));
+    NHIPCHK(hipStreamWaitEvent(n->user_stream, n->ev[1], 0));
+    return PSC_OK;
+}
+
+int net_launch_apply(psc_net* n, hipStream_t st, const double* r, double* z, const double* rr_dev, long long N,
+                     Gate g) {
+    if (!n || n->gcells != N) return nfail(PSC_ERR_ARG, "network grid does not match the vector size");
+    Dims d{1, n->gz, n->gy, n->gx};
+    forward(n, st, d, r, nullptr, rr_dev, N, n->u, n->h1, n->h2, nullptr, nullptr, z, nullptr, g);
+    return PSC_OK;
+}
+
+int net_check_grid(const psc_net* n, long long N) {
+    if (!n) return nfail(PSC_ERR_ARG, "NULL network");
+    if (n->gcells != N) return nfail(PSC_ERR_STATE, "psc_net_set_grid must give nx*ny*nz = n before a solve");
+    return PSC_OK;
+}
+
+uint64_t net_generation(const psc_net* n) { return n ? n->gen : 0; }
+
+}  // namespace psc
+
+extern "C" {
+
+int32_t psc_net_param_count(void) { return NP; }
+
+void psc_net_free(psc_net* n) {
+    if (!n) return;
+    (void)hipSetDevice(n->device);
+    if (n->stream) (void)hipStreamSynchronize(n->stream);
+    net_free_train(n);
+    for (void* p : {(void*)n->master, (void*)n->m, (void*)n->v, (void*)n->grad, (void*)n->wr, (void*)n->ffwd,
+                    (void*)n->fbwd, (void*)n->u, (void*)n->h1, (void*)n->h2, (void*)n->rr, (void*)n->dpart,
+                    (void*)n->wpart, (void*)n->loss_dev})
+        if (p) (void)hipFree(p);
+    for (auto& e : n->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (n->stream) (void)hipStreamDestroy(n->stream);
+    delete n;
+}
+
+int psc_net_create(const float* params, void* hip_stream, psc_net** out) {
+    if (!params || !out) return nfail(PSC_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    psc_net* n = new psc_net();
+    auto bail = [&](int st) { psc_net_free(n); return st; };
+    n->user_stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&n->device) != hipSuccess) return bail(nfail(PSC_ERR_HIP, "hipGetDevice failed"));
+    if (hipStreamCreateWithFlags(&n->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&n->ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&n->ev[1], hipEventDisableTiming) != hipSuccess)
+        return bail(nfail(PSC_ERR_HIP, "stream or event creation failed"));
+    for (float** p : {&n->master, &n->m, &n->v, &n->grad, &n->wr})
+        if (hipMalloc((void**)p, NP * sizeof(float)) != hipSuccess) return bail(nfail(PSC_ERR_OOM, "hipMalloc failed"));
+    if (hipMalloc((void**)&n->ffwd, KSTEPS * 64 * 8 * 2) != hipSuccess ||
+        hipMalloc((void**)&n->fbwd, KSTEPS * 64 * 8 * 2) != hipSuccess ||
+        hipMalloc((void**)&n->rr, sizeof(double) * 2) != hipSuccess ||
+        hipMalloc((void**)&n->dpart, sizeof(double) * 4096) != hipSuccess ||
+        hipMalloc((void**)&n->loss_dev, sizeof(double) * 2) != hipSuccess ||
+        hipMalloc((void**)&n->wpart, sizeof(float) * (size_t)WGRAD_BLOCKS * (NC * NC * 27 + NC)) != hipSuccess)
+        return bail(nfail(PSC_ERR_OOM, "hipMalloc failed"));
+    std::vector<float> zero(NP, 0.f);
+    if (hipMemcpy(n->master, params, NP * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(n->m, zero.data(), NP * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(n->v, zero.data(), NP * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(nfail(PSC_ERR_HIP, "parameter upload failed"));
+    if (hipStreamSynchronize(n->user_stream) != hipSuccess) return bail(nfail(PSC_ERR_HIP, "stream sync failed"));
+    refresh(n, n->stream);
+    if (hipStreamSynchronize(n->stream) != hipSuccess) return bail(nfail(PSC_ERR_HIP, "weight refresh failed"));
+    *out = n;
+    return PSC_OK;
+}
+
+int psc_net_get_params(const psc_net* n, float* params) {
+    if (!n || !params) return nfail(PSC_ERR_ARG, "NULL argument");
+    NHIPCHK(hipSetDevice(n->device));
+    NHIPCHK(hipStreamSynchronize(n->stream));
+    NHIPCHK(hipMemcpy(params, n->master, NP * sizeof(float), hipMemcpyDeviceToHost));
+    return PSC_OK;
+}
+
+int psc_net_set_params(psc_net* n, const float* params) {
+    if (!n || !params) return nfail(PSC_ERR_ARG, "NULL argument");
+    int st = join_in(n);
+    if (st) return st;
+    NHIPCHK(hipMemcpyAsync(n->master, params, NP * sizeof(float), hipMemcpyHostToDevice, n->stream));
+    NHIPCHK(hipMemsetAsync(n->m, 0, NP * sizeof(float), n->stream));
+    NHIPCHK(hipMemsetAsync(n->v, 0, NP * sizeof(float), n->stream));
+    n->adam_t = 0;
+    refresh(n, n->stream);
+    NHIPCHK(hipStreamSynchronize(n->stream));
+    return join_out(n);
+}
+
+int psc_net_set_grid(psc_net* n, int32_t nx, int32_t ny, int32_t nz) {
+    if (!n || nx < 1 || ny < 1 || nz < 1) return nfail(PSC_ERR_ARG, "bad grid");
+    const long long cells = (long long)nx * ny * nz;
+    if (n->gx == nx && n->gy == ny && n->gz == nz) return PSC_OK;
+    NHIPCHK(hipSetDevice(n->device));
+    NHIPCHK(hipStreamSynchronize(n->stream));
+    for (bf16r** p : {&n->u, &n->h1, &n->h2})
+        if (*p) { (void)hipFree(*p); *p = nullptr; }
+    n->gx = n->gy = n->gz = 0;
+    n->gcells = 0;
+    NHIPCHK(hipMalloc((void**)&n->u, (size_t)cells * 2));
+    NHIPCHK(hipMalloc((void**)&n->h1, (size_t)cells * NC * 2));
+    NHIPCHK(hipMalloc((void**)&n->h2, (size_t)cells * NC * 2));
+    n->gx = nx;
+    n->gy = ny;
+    n->gz = nz;
+    n->gcells = cells;
+    n->gen += 1;
+    return PSC_OK;
+}
+
+int psc_net_apply(psc_net* n, const double* r, double* z, int32_t nx, int32_t ny, int32_t nz) {
+    if (!n || !r || !z) return nfail(PSC_ERR_ARG, "NULL argument");
+    int st = psc_net_set_grid(n, nx, ny, nz);
+    if (st) return st;
+    st = join_in(n);
+    if (st) return st;
+    const long long N = n->gcells;
+    const unsigned nb = 1024;
+    k_sumsq<<<nb, WG, 0, n->stream>>>(N, r, n->dpart);
+    k_sum_partials<<<1, WG, 0, n->stream>>>(n->dpart, (int)nb, 1.0, n->rr, nullptr);
+    net_launch_apply(n, n->stream, r, z, n->rr, N, Gate{nullptr, GATE_NONE});
+    NHIPCHK(hipGetLastError());
+    NHIPCHK(hipStreamSynchronize(n->stream));
+    return join_out(n);
+}
+
+int psc_net_forward_batch(psc_net* n, const float* in, float* out, int32_t B, int32_t D) {
+    if (!n || !in || !out || B < 1 || D < 1) return nfail(PSC_ERR_ARG, "bad argument");
+    Dims d{B, D, D, D};
+    int st = join_in(n);
+    if (st) return st;
+    st = net_train_buffers(n, d.cells());
+    if (st) return st;
+    forward(n, n->stream, d, nullptr, in, nullptr, 1, n->tu, n->th1, n->th2, nullptr, nullptr, nullptr, out,
+            Gate{nullptr, GATE_NONE});
+    NHIPCHK(hipGetLastError());
+    NHIPCHK(hipStreamSynchronize(n->stream));
+    return join_out(n);
+}
+
+int psc_net_loss_grad(psc_net* n, const float* in, const float* tgt, int32_t B, int32_t D, int32_t margin,
+                      float* loss, float* grad_host) {
+    if (!n || !in || !tgt || !loss || !grad_host || B < 1 || D < 1 || margin < 0 || 2 * margin >= D)
+        return nfail(PSC_ERR_ARG, "bad argument");
+    Dims d{B, D, D, D};
+    int st = join_in(n);
+    if (st) return st;
+    st = net_train_buffers(n, d.cells());
+    if (st) return st;
+    const size_t bytes = (size_t)d.cells() * 4;
+    NHIPCHK(hipMemcpyAsync(n->in_b, in, bytes, hipMemcpyDeviceToDevice, n->stream));
+    NHIPCHK(hipMemcpyAsync(n->tgt_b, tgt, bytes, hipMemcpyDeviceToDevice, n->stream));
+    loss_grad(n, n->stream, d, margin, n->loss_dev, nullptr);
+    NHIPCHK(hipGetLastError());
+    double l = 0.0;
+    NHIPCHK(hipMemcpyAsync(&l, n->loss_dev, sizeof(double), hipMemcpyDeviceToHost, n->stream));
+    NHIPCHK(hipMemcpyAsync(grad_host, n->grad, NP * sizeof(float), hipMemcpyDeviceToHost, n->stream));
+    NHIPCHK(hipStreamSynchronize(n->stream));
+    *loss = (float)l;
+    return join_out(n);
+}
+
+int psc_net_train(psc_net* n, const float* r_crops, const float* z_crops, int32_t ncrops, int32_t crop,
+                  int32_t margin, const int32_t* order, int32_t steps, int32_t batch, float lr, float beta1,
+                  float beta2, float eps, float* losses_host) {
+    if (!n || !r_crops || !z_crops || !order || ncrops < 1 || crop < 1 || steps < 0 || batch < 1 ||
+        margin < 0 || 2 * margin >= crop || !(lr > 0.f))
+        return nfail(PSC_ERR_ARG, "bad argument");
+    for (long long i = 0; i < (long long)steps * batch; i++)
+        if (order[i] < 0 || order[i] >= ncrops) return nfail(PSC_ERR_ARG, "crop index out of range");
+    Dims d{batch, crop, crop, crop};
+    int st = join_in(n);
+    if (st) return st;
+    st = net_train_buffers(n, d.cells());
+    if (st) return st;
+    int* ids = nullptr;
+    float* ldev = nullptr;
+    NHIPCHK(hipMalloc((void**)&ids, sizeof(int) * (size_t)steps * batch + 4));
+    NHIPCHK(hipMalloc((void**)&ldev, sizeof(float) * (size_t)steps + 4));
+    NHIPCHK(hipMemcpyAsync(ids, order, sizeof(int) * (size_t)steps * batch, hipMemcpyHostToDevice, n->stream));
+    const long long per = (long long)crop * crop * crop;
+    for (int s = 0; s < steps; s++) {
+        k_gather<<<blocks_for(per * batch), WG, 0, n->stream>>>(per, r_crops, ids + (size_t)s * batch, batch, n->in_b);
+        k_gather<<<blocks_for(per * batch), WG, 0, n->stream>>>(per, z_crops, ids + (size_t)s * batch, batch, n->tgt_b);
+        loss_grad(n, n->stream, d, margin, n->loss_dev, ldev + s);
+        n->adam_t += 1;
+        const float c1 = 1.f - powf(beta1, (float)n->adam_t), c2 = 1.f - powf(beta2, (float)n->adam_t);
+        k_adam<<<blocks_for(NP), WG, 0, n->stream>>>(NP, n->master, n->m, n->v, n->grad, lr, beta1, beta2, eps, c1, c2);
+        refresh(n, n->stream);
+    }
+    NHIPCHK(hipGetLastError());
+    if (losses_host && steps > 0)
+        NHIPCHK(hipMemcpyAsync(losses_host, ldev, sizeof(float) * steps, hipMemcpyDeviceToHost, n->stream));
+    NHIPCHK(hipStreamSynchronize(n->stream));
+    (void)hipFree(ids);
+    (void)hipFree(ldev);
+    return join_out(n);
+}
+
+}  // extern "C"

@@ -1,0 +1,502 @@
+// setup.cpp -- host-side construction of the matching-based AMG hierarchy.
+//
+// Follows the paper's Section "AMG4PSBLAS" (Galerkin coarse operators),
+// Section "Aggregation strategies" (coupled aggregation by compatible
+// weighted matching, tentative prolongator of eq. (prolongator), k matching
+// sweeps) and Section "GPU enabled smoothers" (l1-Jacobi diagonal). The
+// paper leaves the edge weights, the matching algorithm's tie order and the
+// graph of later sweeps to its references; this file takes the readings:
+//   * edge weight of {i,j} on the scaled operator S = diag(w) A diag(w):
+//       c = 1 - 2 S_ij / (S_ii + S_jj), taken from the entry of the row
+//       min(i,j), quantised q = llround(c 2^30); only q > 0 is eligible;
+//   * the matching is the unique locally-dominant matching under the strict
+//     order (q desc, min(i,j) asc, max(i,j) asc), a 1/2-approximate
+//     maximum-weight matching; it is computed here by parallel rounds of
+//     mutual "heaviest free neighbour" proposals;
+//   * sweep s+1 matches the graph of the block sums of S over the aggregates
+//     of sweep s; aggregates are numbered by ascending smallest member;
+//   * w_{l+1}[I] = sqrt(sum_{i in I} w_i^2), p_i = w_i / w_{l+1}[agg_i];
+//   * Galerkin sums C[I,J] = sum_{i in I asc} sum_{j in row i asc,
+//     agg j = J} (s_i a_ij) s_j, with every reached (I,J) stored.
+// Setup is not part of the solve time; it is parallel with OpenMP.
+#include "setup.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <omp.h>
+
+#include "../../include/psc.h"
+
+namespace psc {
+
+namespace {
+
+struct Csr {
+    int64_t n = 0;
+    std::vector<int32_t> rp, ci;
+    std::vector<double> v;
+};
+
+// exclusive prefix sum of cnt[0..n) into off[0..n], returns total
+int64_t prefix(const std::vector<int64_t>& cnt, std::vector<int64_t>& off) {
+    off.resize(cnt.size() + 1);
+    off[0] = 0;
+    for (size_t i = 0; i < cnt.size(); i++) off[i + 1] = off[i] + cnt[i];
+    return off.back();
+}
+
+// Members of each aggregate in ascending order (counting sort, stable).
+void members_of(const std::vector<int32_t>& agg, int64_t nc, std::vector<int64_t>& start,
+                std::vector<int32_t>& mem) {
+    std::vector<int64_t> cnt(nc, 0);
+    for (size_t i = 0; i < agg.size(); i++) cnt[agg[i]]++;
+    prefix(cnt, start);
+    mem.resize(agg.size());
+    std::vector<int64_t> pos(start.begin(), start.end() - 1);
+    for (size_t i = 0; i < agg.size(); i++) mem[pos[agg[i]]++] = (int32_t)i;
+}
+
+// Galerkin sum in canonical order (see file header). s == nullptr means s = 1.
+void galerkin(const Csr& a, const std::vector<int32_t>& agg, int64_t nc, const double* s,
+              Csr& c) {
+    std::vector<int64_t> start;
+    std::vector<int32_t> mem;
+    members_of(agg, nc, start, mem);
+    std::vector<int64_t> len(nc, 0);
+    // pass 1: row lengths; pass 2: values. A row's contributions are few, so
+    // a short list with linear search keeps them in arrival order.
+    for (int pass = 0; pass < 2; pass++) {
+        std::vector<int64_t> off;
+        if (pass == 1) {
+            prefix(len, off);
+            c.n = nc;
+            c.rp.resize(nc + 1);
+            for (int64_t I = 0; I <= nc; I++) c.rp[I] = (int32_t)off[I];
+            c.ci.resize(off[nc]);
+            c.v.resize(off[nc]);
+        }
+#pragma omp parallel
+        {
+            std::vector<int32_t> cols;
+            std::vector<double> vals;
+            std::vector<std::pair<int32_t, double>> tmp;
+#pragma omp for schedule(dynamic, 4096)
+            for (int64_t I = 0; I < nc; I++) {
+                cols.clear();
+                vals.clear();
+                for (int64_t m = start[I]; m < start[I + 1]; m++) {
+                    int32_t i = mem[m];
+                    double si = s ? s[i] : 1.0;
+                    for (int32_t k = a.rp[i]; k < a.rp[i + 1]; k++) {
+                        int32_t j = a.ci[k];
+                        int32_t J = agg[j];
+                        double t = s ? (si * a.v[k]) * s[j] : a.v[k];
+                        size_t q = 0;
+                        while (q < cols.size() && cols[q] != J) q++;
+                        if (q == cols.size()) { cols.push_back(J); vals.push_back(t); }
+                        else vals[q] += t;
+                    }
+                }
+                if (pass == 0) { len[I] = (int64_t)cols.size(); continue; }
+                tmp.resize(cols.size());
+                for (size_t q = 0; q < cols.size(); q++) tmp[q] = {cols[q], vals[q]};
+                std::sort(tmp.begin(), tmp.end(),
+                          [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
+                              return x.first < y.first;
+                          });
+                int64_t o = off[I];
+                for (size_t q = 0; q < tmp.size(); q++) { c.ci[o + q] = tmp[q].first; c.v[o + q] = tmp[q].second; }
+            }
+        }
+    }
+}
+
+// position of column j in row i (binary search), -1 if absent
+inline int64_t find_col(const Csr& a, int32_t i, int32_t j) {
+    const int32_t* b = a.ci.data() + a.rp[i];
+    const int32_t* e = a.ci.data() + a.rp[i + 1];
+    const int32_t* f = std::lower_bound(b, e, j);
+    return (f != e && *f == j) ? (int64_t)(f - a.ci.data()) : -1;
+}
+
+// Strict edge order: does edge {i,a} with key qa come before {i,b} with key qb?
+inline bool edge_first(int64_t qa, int32_t i, int32_t a, int64_t qb, int32_t b) {
+    if (qa != qb) return qa > qb;
+    int32_t amin = std::min(i, a), amax = std::max(i, a);
+    int32_t bmin = std::min(i, b), bmax = std::max(i, b);
+    if (amin != bmin) return amin < bmin;
+    return amax < bmax;
+}
+
+// Locally-dominant matching of the graph of S. mate[i] = partner or -1.
+void ld_matching(const Csr& S, std::vector<int32_t>& mate) {
+    const int64_t n = S.n;
+    const int64_t nnz = S.rp[n];
+    std::vector<double> dg(n, 0.0);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        int64_t k = find_col(S, (int32_t)i, (int32_t)i);
+        dg[i] = k >= 0 ? S.v[k] : 0.0;
+    }
+    // key of each stored entry; the key of {i,j} is computed from the entry
+    // of row min(i,j) so both rows see the same value
+    std::vector<int64_t> key(nnz);
+#pragma omp parallel for schedule(dynamic, 2048)
+    for (int64_t i = 0; i < n; i++) {
+        for (int32_t k = S.rp[i]; k < S.rp[i + 1]; k++) {
+            int32_t j = S.ci[k];
+            if (j == i) { key[k] = -1; continue; }
+            int32_t lo = std::min<int32_t>((int32_t)i, j), hi = std::max<int32_t>((int32_t)i, j);
+            int64_t kk = (j > i) ? k : find_col(S, lo, hi);
+            if (kk < 0) { key[k] = -1; continue; }
+            double sij = S.v[kk];
+            double c = 1.0 - 2.0 * sij / (dg[lo] + dg[hi]);
+            long long q = llround(c * 1073741824.0);
+            key[k] = q > 0 ? (int64_t)q : -1;
+        }
+    }
+    mate.assign(n, -1);
+    std::vector<int32_t> cand(n, -1);
+    auto best_free = [&](int64_t i) -> int32_t {
+        int32_t best = -1;
+        int64_t bq = 0;
+        for (int32_t k = S.rp[i]; k < S.rp[i + 1]; k++) {
+            if (key[k] < 0) continue;
+            int32_t j = S.ci[k];
+            if (mate[j] >= 0) continue;
+            if (best < 0 || edge_first(key[k], (int32_t)i, j, bq, best)) { best = j; bq = key[k]; }
+        }
+        return best;
+    };
+    std::vector<int32_t> active(n);
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t i = 0; i < n; i++) { cand[i] = best_free(i); active[i] = (int32_t)i; }
+    std::vector<uint8_t> is_active(n, 1), dirty(n, 0);
+    int nt = omp_get_max_threads();
+    std::vector<std::vector<int32_t>> tl_matched(nt), tl_dirty(nt);
+    while (!active.empty()) {
+        // 1) match mutual proposals among the active vertices
+        int64_t na = (int64_t)active.size();
+#pragma omp parallel
+        {
+            auto& out = tl_matched[omp_get_thread_num()];
+            out.clear();
+#pragma omp for schedule(static)
+            for (int64_t t = 0; t < na; t++) {
+                int32_t i = active[t];
+                int32_t j = cand[i];
+                if (j < 0 || cand[j] != i) continue;
+                // record the pair once: by the smaller end, or by i if j is not active
+                if (i < j || !is_active[j]) {
+                    mate[i] = j;
+                    mate[j] = i;
+                    out.push_back(i);
+                    out.push_back(j);
+                }
+            }
+        }
+        size_t newly = 0;
+        for (auto& v : tl_matched) newly += v.size();
+        for (int32_t i : active) is_active[i] = 0;
+        if (newly == 0) break;
+        // 2) free neighbours that proposed to a newly matched vertex re-propose
+#pragma omp parallel
+        {
+            auto& out = tl_dirty[omp_get_thread_num()];
+            out.clear();
+            for (int t = 0; t < nt; t++) {
+                const auto& ml = tl_matched[t];
+#pragma omp for schedule(static) nowait
+                for (int64_t q = 0; q < (int64_t)ml.size(); q++) {
+                    int32_t m = ml[q];
+                    for (int32_t k = S.rp[m]; k < S.rp[m + 1]; k++) {
+                        int32_t u = S.ci[k];
+                        if (mate[u] >= 0 || cand[u] != m) continue;
+                        if (__atomic_exchange_n(&dirty[u], (uint8_t)1, __ATOMIC_RELAXED) == 0) out.push_back(u);
+                    }
+                }
+            }
+        }
+        active.clear();
+        for (auto& v : tl_dirty) active.insert(active.end(), v.begin(), v.end());
+        int64_t nd = (int64_t)active.size();
+#pragma omp parallel for schedule(dynamic, 1024)
+        for (int64_t t = 0; t < nd; t++) {
+            int32_t u = active[t];
+            cand[u] = best_free(u);
+            dirty[u] = 0;
+            is_active[u] = 1;
+        }
+    }
+}
+
+// Aggregates of a matching, numbered by ascending smallest member.
+int64_t pairs_to_aggs(const std::vector<int32_t>& mate, std::vector<int32_t>& agg) {
+    const int64_t n = (int64_t)mate.size();
+    agg.assign(n, -1);
+    int64_t nc = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int32_t m = mate[i];
+        if (m < 0 || m > i) agg[i] = (int32_t)nc++;
+        else agg[i] = agg[m];
+    }
+    return nc;
+}
+
+int coarsen(const Csr& A, const std::vector<double>& w, int sweeps, std::vector<int32_t>& agg,
+            int64_t& nc_out) {
+    const int64_t n = A.n;
+    // S = diag(w) A diag(w), same pattern as A
+    Csr S;
+    S.n = n;
+    S.rp = A.rp;
+    S.ci = A.ci;
+    S.v.resize(A.v.size());
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t i = 0; i < n; i++)
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++) S.v[k] = (w[i] * A.v[k]) * w[A.ci[k]];
+    agg.resize(n);
+    for (int64_t i = 0; i < n; i++) agg[i] = (int32_t)i;
+    int64_t ncur = n;
+    for (int s = 0; s < sweeps; s++) {
+        std::vector<int32_t> mate, a2;
+        ld_matching(S, mate);
+        int64_t nnew = pairs_to_aggs(mate, a2);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; i++) agg[i] = a2[agg[i]];
+        if (s + 1 < sweeps) {
+            Csr S2;
+            galerkin(S, a2, nnew, nullptr, S2);
+            S = std::move(S2);
+        }
+        ncur = nnew;
+    }
+    // explicit renumbering by ascending smallest level-l member
+    std::vector<int32_t> ren(ncur, -1);
+    int64_t nc = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int32_t& r = ren[agg[i]];
+        if (r < 0) r = (int32_t)nc++;
+        agg[i] = r;
+    }
+    nc_out = nc;
+    return PSC_OK;
+}
+
+int l1_inverse_diag(const Csr& A, std::vector<double>& minv) {
+    minv.resize(A.n);
+    std::atomic<int> bad(0);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < A.n; i++) {
+        double d = 0.0, off = 0.0;
+        bool has = false;
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++) {
+            if (A.ci[k] == i) { d = A.v[k]; has = true; }
+            else off += std::fabs(A.v[k]);
+        }
+        if (!has || !(d > 0.0)) { bad = 1; minv[i] = 0.0; }
+        else minv[i] = 1.0 / (d + off);
+    }
+    return bad ? PSC_ERR_NOT_SPD : PSC_OK;
+}
+
+// Dense Cholesky of the coarsest matrix and its explicit inverse
+// inv = L^-T L^-1 (applied as one matrix-vector product on the device).
+int coarse_inverse(const Csr& A, std::vector<double>& inv) {
+    const int64_t n = A.n;
+    std::vector<double> L((size_t)n * n, 0.0);
+    for (int64_t i = 0; i < n; i++)
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++)
+            if (A.ci[k] <= i) L[(size_t)i * n + A.ci[k]] = A.v[k];
+    for (int64_t j = 0; j < n; j++) {
+        double d = L[(size_t)j * n + j];
+        for (int64_t k = 0; k < j; k++) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(d > 0.0)) return PSC_ERR_NOT_SPD;
+        double ljj = std::sqrt(d);
+        L[(size_t)j * n + j] = ljj;
+        for (int64_t i = j + 1; i < n; i++) {
+            double s = L[(size_t)i * n + j];
+            for (int64_t k = 0; k < j; k++) s -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = s / ljj;
+        }
+    }
+    inv.assign((size_t)n * n, 0.0);
+    std::vector<double> y(n);
+    for (int64_t c = 0; c < n; c++) {
+        for (int64_t i = 0; i < n; i++) {                 // L y = e_c
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int64_t k = 0; k < i; k++) s -= L[(size_t)i * n + k] * y[k];
+            y[i] = s / L[(size_t)i * n + i];
+        }
+        for (int64_t i = n - 1; i >= 0; i--) {            // L^T x = y
+            double s = y[i];
+            for (int64_t k = i + 1; k < n; k++) s -= L[(size_t)k * n + i] * y[k];
+            y[i] = s / L[(size_t)i * n + i];
+        }
+        for (int64_t i = 0; i < n; i++) inv[(size_t)i * n + c] = y[i];
+    }
+    return PSC_OK;
+}
+
+}  // namespace
+
+void pack_ell(int64_t nrows, const int32_t* rp, const int32_t* ci, const double* v,
+              std::vector<long long>& off, std::vector<double>& val, std::vector<int>& col) {
+    const int S = 64;
+    int64_t ns = (nrows + S - 1) / S;
+    off.assign(ns + 1, 0);
+    std::vector<long long> width(ns, 0);
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < ns; s++) {
+        int wmax = 0;
+        for (int64_t r = s * S; r < std::min<int64_t>(nrows, (s + 1) * S); r++)
+            wmax = std::max(wmax, rp[r + 1] - rp[r]);
+        width[s] = wmax;
+    }
+    for (int64_t s = 0; s < ns; s++) off[s + 1] = off[s] + width[s] * S;
+    val.resize(off[ns]);
+    col.resize(off[ns]);
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < ns; s++) {
+        int w = (int)width[s];
+        for (int lane = 0; lane < S; lane++) {
+            int64_t r = s * S + lane;
+            int len = r < nrows ? rp[r + 1] - rp[r] : 0;
+            int last = (r < nrows && len > 0) ? ci[rp[r + 1] - 1] : 0;
+            for (int k = 0; k < w; k++) {
+                long long slot = off[s] + (long long)k * S + lane;
+                if (k < len) { val[slot] = v[rp[r] + k]; col[slot] = ci[rp[r] + k]; }
+                else { val[slot] = 0.0; col[slot] = last; }
+            }
+        }
+    }
+}
+
+int validate_csr(int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
+                 std::string& err) {
+    if (n <= 0 || !rp || !ci || !v) { err = "n must be positive and arrays non-NULL"; return PSC_ERR_ARG; }
+    if (rp[0] != 0) { err = "rowptr[0] must be 0"; return PSC_ERR_ARG; }
+    for (int64_t i = 0; i < n; i++)
+        if (rp[i + 1] < rp[i]) { err = "rowptr must be non-decreasing"; return PSC_ERR_ARG; }
+    std::atomic<int> st(PSC_OK);
+    std::atomic<int64_t> bad_row(-1);
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t i = 0; i < n; i++) {
+        bool diag = false;
+        int local = PSC_OK;
+        for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
+            int32_t j = ci[k];
+            if (j < 0 || j >= n) { local = PSC_ERR_ARG; break; }
+            if (k > rp[i] && ci[k - 1] >= j) { local = PSC_ERR_ARG; break; }
+            if (!std::isfinite(v[k])) { local = PSC_ERR_ARG; break; }
+            if (j == i) { diag = true; if (!(v[k] > 0.0)) local = PSC_ERR_NOT_SPD; }
+        }
+        if (local == PSC_OK && !diag) local = PSC_ERR_NOT_SPD;
+        if (local != PSC_OK) { st = local; bad_row = i; }
+    }
+    if (st != PSC_OK) {
+        err = (st == PSC_ERR_ARG ? "malformed CSR row " : "missing or non-positive diagonal in row ") +
+              std::to_string(bad_row.load());
+        return st;
+    }
+    // structural symmetry (the matching reads each edge from its upper entry)
+    std::atomic<int64_t> asym(-1);
+    Csr view;
+    view.n = n;
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t i = 0; i < n; i++) {
+        for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
+            int32_t j = ci[k];
+            const int32_t* b = ci + rp[j];
+            const int32_t* e = ci + rp[j + 1];
+            const int32_t* f = std::lower_bound(b, e, (int32_t)i);
+            if (f == e || *f != i) { asym = i; break; }
+        }
+    }
+    if (asym >= 0) {
+        err = "matrix is not structurally symmetric (row " + std::to_string(asym.load()) + ")";
+        return PSC_ERR_ARG;
+    }
+    return PSC_OK;
+}
+
+int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
+                    const SetupOpts& o, HostHier& H, std::string& err) {
+    if (o.sweeps < 1 || o.sweeps > 8 || o.coarse_max < 1 || o.max_levels < 1 ||
+        o.max_levels > PSC_MAX_LEVELS) {
+        err = "invalid hierarchy options";
+        return PSC_ERR_ARG;
+    }
+    H.lev.clear();
+    H.lev.emplace_back();
+    {
+        HostLevel& L0 = H.lev[0];
+        L0.n = n;
+        L0.rp.assign(rp, rp + n + 1);
+        L0.ci.assign(ci, ci + rp[n]);
+        L0.v.assign(v, v + rp[n]);
+        L0.w.assign(n, 1.0);
+    }
+    for (int l = 0;; l++) {
+        Csr A;
+        A.n = H.lev[l].n;
+        A.rp.swap(H.lev[l].rp);
+        A.ci.swap(H.lev[l].ci);
+        A.v.swap(H.lev[l].v);
+        int st = l1_inverse_diag(A, H.lev[l].minv);
+        if (st != PSC_OK) { err = "non-positive l1 diagonal on level " + std::to_string(l); return st; }
+        bool coarsest = (A.n <= o.coarse_max) || (l + 1 >= o.max_levels);
+        if (l > 0 && (double)A.n > 0.9 * (double)H.lev[l - 1].n) {
+            if (A.n <= 2000) coarsest = true;
+            else {
+                err = "coarsening stalled at level " + std::to_string(l) + " with " + std::to_string(A.n) + " rows";
+                return PSC_ERR_COARSEN;
+            }
+        }
+        if (coarsest) {
+            if (A.n > 4096) { err = "coarsest level too large for a dense solve"; return PSC_ERR_COARSEN; }
+            H.lev[l].nc = 0;
+            st = coarse_inverse(A, H.coarse_inv);
+            H.lev[l].rp.swap(A.rp);
+            H.lev[l].ci.swap(A.ci);
+            H.lev[l].v.swap(A.v);
+            if (st != PSC_OK) { err = "Cholesky breakdown on the coarsest level"; return st; }
+            break;
+        }
+        int64_t nc = 0;
+        std::vector<int32_t> agg;
+        coarsen(A, H.lev[l].w, o.sweeps, agg, nc);
+        H.lev.emplace_back();
+        HostLevel& F = H.lev[l];
+        HostLevel& Cl = H.lev[l + 1];
+        F.nc = nc;
+        F.agg.swap(agg);
+        Cl.n = nc;
+        std::vector<int64_t> start;
+        std::vector<int32_t> mem;
+        members_of(F.agg, nc, start, mem);
+        Cl.w.resize(nc);
+#pragma omp parallel for schedule(static)
+        for (int64_t I = 0; I < nc; I++) {
+            double s = 0.0;
+            for (int64_t m = start[I]; m < start[I + 1]; m++) s += F.w[mem[m]] * F.w[mem[m]];
+            Cl.w[I] = std::sqrt(s);
+        }
+        F.p.resize(F.n);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < F.n; i++) F.p[i] = F.w[i] / Cl.w[F.agg[i]];
+        Csr Ac;
+        galerkin(A, F.agg, nc, F.p.data(), Ac);
+        Cl.rp.swap(Ac.rp);
+        Cl.ci.swap(Ac.ci);
+        Cl.v.swap(Ac.v);
+        F.rp.swap(A.rp);
+        F.ci.swap(A.ci);
+        F.v.swap(A.v);
+    }
+    return PSC_OK;
+}
+
+}  // namespace psc

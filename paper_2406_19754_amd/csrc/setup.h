@@ -1,0 +1,45 @@
+// setup.h -- host-side AMG hierarchy construction (internal to libpsc).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace psc {
+
+// One level of the host hierarchy. A_l is CSR with ascending columns.
+struct HostLevel {
+    int64_t n = 0;
+    std::vector<int32_t> rp, ci;
+    std::vector<double> v;
+    std::vector<double> w;      // near-kernel sample vector at this level
+    std::vector<double> minv;   // l1-Jacobi inverse diagonal
+    int64_t nc = 0;             // rows of the next level (0 at the coarsest)
+    std::vector<int32_t> agg;   // aggregate of each row
+    std::vector<double> p;      // the single prolongator entry of each row
+};
+
+struct HostHier {
+    std::vector<HostLevel> lev;
+    std::vector<double> coarse_inv;   // dense inverse of the coarsest A, row-major
+};
+
+struct SetupOpts {
+    int sweeps = 2;
+    int coarse_max = 200;
+    int max_levels = 30;
+};
+
+// Status codes follow psc.h.
+int validate_csr(int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
+                 std::string& err);
+int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
+                    const SetupOpts& o, HostHier& H, std::string& err);
+
+// Pack CSR rows into hacked ELL with 64-row slices (column-major in a
+// slice). Padding slots carry value 0 and repeat the row's last column (0 for
+// rows past the end), so every slot reads a valid, usually cached, entry.
+void pack_ell(int64_t nrows, const int32_t* rp, const int32_t* ci, const double* v,
+              std::vector<long long>& off, std::vector<double>& val, std::vector<int>& col);
+
+}  // namespace psc

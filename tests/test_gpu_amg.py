@@ -1,0 +1,205 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Sizes are ones the oracle finishes in seconds but that still span many
+64-row slices, several levels and a ragged last slice. Tolerances:
+  * SpMV and the FP64 V-cycle: 1e-12 relative (FMA and summation order only);
+  * FP32 V-cycle: 1e-5 relative to the oracle's FP32 V-cycle;
+  * full solves: iteration counts within +-1 and, at equal iteration count,
+    ||x_gpu - x_orc|| / ||x_orc|| <= 1e-8 (FP64), true residual <= rtol.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle
+from paper_2406_19754_amd import problems as P
+
+
+@pytest.fixture(scope="module")
+def psc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_19754_amd import psc as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+CASES = {
+    "poisson32": lambda: P.poisson7(32),
+    "poisson13": lambda: P.poisson7(13),                      # odd size: singletons, ragged slices
+    "diffusion20_az100": lambda: P.diffusion7(20, seed=0, az=100.0),
+    "random_long_rows": lambda: P.random_spd_csr(700, 5, density=0.01, maxrow=90),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_hierarchy_matches_oracle(psc, case):
+    rp, c, v = CASES[case]()
+    cm = 40 if case == "random_long_rows" else 200
+    h = psc.Hierarchy(rp, c, v, coarse_max=cm)
+    o = oracle.Hierarchy(rp, c, v, coarse_max=cm)
+    inf = h.info()
+    assert inf["rows"] == o.sizes()
+    for l in range(inf["levels"]):
+        a, b = h.export_level(l), o.level(l)
+        assert np.array_equal(a["col"], b["col"]) and np.array_equal(a["rowptr"], b["rowptr"])
+        np.testing.assert_allclose(a["val"], b["val"], rtol=1e-13, atol=0)
+        if l < inf["levels"] - 1:
+            assert np.array_equal(a["agg"], b["agg"])
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_spmv_matches_oracle(psc, case):
+    rp, c, v = CASES[case]()
+    h = psc.Hierarchy(rp, c, v, build_fp32=True, coarse_max=40)
+    x = np.random.default_rng(1).standard_normal(len(rp) - 1)
+    ref = oracle.spmv(rp, c, v, x)
+    y = torch.empty(len(x), dtype=torch.float64, device="cuda")
+    h.spmv(dev(x), y)
+    got = y.cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    # FP32 copy on the same operator
+    y32 = torch.empty(len(x), dtype=torch.float32, device="cuda")
+    h.spmv(dev(x.astype(np.float32)), y32, prec=psc.FP32)
+    ref32 = oracle.spmv(rp, c, v.astype(np.float32).astype(np.float64), x.astype(np.float32).astype(np.float64))
+    assert np.abs(y32.cpu().numpy() - ref32).max() <= 1e-5 * np.abs(ref32).max()
+    # every level's operator
+    o = oracle.Hierarchy(rp, c, v, coarse_max=40)
+    for l in range(1, o.nlevels):
+        L = o.level(l)
+        xl = np.random.default_rng(l).standard_normal(L["n"])
+        yl = torch.empty(L["n"], dtype=torch.float64, device="cuda")
+        h.spmv(dev(xl), yl, level=l)
+        refl = oracle.spmv(L["rowptr"], L["col"], L["val"], xl)
+        assert np.abs(yl.cpu().numpy() - refl).max() <= 1e-13 * np.abs(refl).max()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_vcycle_matches_oracle(psc, case):
+    rp, c, v = CASES[case]()
+    h = psc.Hierarchy(rp, c, v, build_fp32=True)
+    o = oracle.Hierarchy(rp, c, v)
+    r = np.random.default_rng(2).standard_normal(len(rp) - 1)
+    z = torch.empty(len(r), dtype=torch.float64, device="cuda")
+    h.vcycle(dev(r), z)
+    ref = o.vcycle(r)
+    assert np.linalg.norm(z.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+    h.vcycle(dev(r), z, prec=psc.FP32)
+    ref32 = o.vcycle32(r)
+    assert np.linalg.norm(z.cpu().numpy() - ref32) <= 1e-5 * np.linalg.norm(ref32)
+    assert np.linalg.norm(z.cpu().numpy() - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+def _solve_pair(psc, rp, c, v, b, form, maxit=1000, use_graph=True):
+    h = psc.Hierarchy(rp, c, v, build_fp32=True, use_graph=use_graph)
+    o = oracle.Hierarchy(rp, c, v)
+    x = torch.zeros(len(b), dtype=torch.float64, device="cuda")
+    if form == "pcg":
+        g = h.pcg(dev(b), x, rtol=1e-6, maxit=maxit)
+        r = o.pcg(b, rtol=1e-6, maxit=maxit)
+    else:
+        prec = psc.FP32 if form == "fcg32" else psc.FP64
+        g = h.fcg(dev(b), x, rtol=1e-6, maxit=maxit, prec=prec)
+        r = o.fcg(b, rtol=1e-6, maxit=maxit, form=1 if form == "fcg32" else 0)
+    return h, o, g, x.cpu().numpy(), r
+
+
+@pytest.mark.parametrize("form", ["pcg", "fcg64", "fcg32"])
+@pytest.mark.parametrize("case", ["poisson32", "diffusion20_az100"])
+def test_solve_matches_oracle(psc, case, form):
+    rp, c, v = CASES[case]()
+    b = P.rhs_from_solution(rp, c, v, P.x_true(len(rp) - 1, 0))
+    h, o, g, xg, r = _solve_pair(psc, rp, c, v, b, form)
+    assert g["status"] == psc.OK and r["status"] == oracle.OK
+    assert abs(g["iters"] - r["iters"]) <= 1
+    assert g["relres"] <= 1e-6
+    k = min(g["iters"], r["iters"])
+    if form == "fcg32":
+        # FP32 V-cycle: judged by the true FP64 residual; the error to the
+        # FP64 oracle solution is stated, not bounded tightly
+        assert np.linalg.norm(xg - r["x"]) <= 1e-4 * np.linalg.norm(r["x"])
+        return
+    # equal iteration count comparison
+    x = torch.zeros(len(b), dtype=torch.float64, device="cuda")
+    if form == "pcg":
+        h.pcg(dev(b), x, rtol=1e-30, maxit=k)
+        ref = o.pcg(b, rtol=1e-30, maxit=k)["x"]
+    else:
+        h.fcg(dev(b), x, rtol=1e-30, maxit=k)
+        ref = o.fcg(b, rtol=1e-30, maxit=k, form=0)["x"]
+    assert np.linalg.norm(x.cpu().numpy() - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_graph_and_stream_launch_agree_bitwise(psc):
+    rp, c, v = P.poisson7(24)
+    b = P.rhs_uniform(24 ** 3, 3)
+    xs = []
+    for use_graph in (True, False, True):
+        h = psc.Hierarchy(rp, c, v, use_graph=use_graph)
+        x = torch.zeros(len(b), dtype=torch.float64, device="cuda")
+        g = h.pcg(dev(b), x)
+        xs.append((g["iters"], x.cpu().numpy()))
+    assert xs[0][0] == xs[1][0] == xs[2][0]
+    assert np.array_equal(xs[0][1], xs[1][1]) and np.array_equal(xs[0][1], xs[2][1])
+
+
+def test_repeated_solves_reuse_hierarchy(psc):
+    rp, c, v = P.poisson7(20)
+    h = psc.Hierarchy(rp, c, v, build_fp32=True)
+    o = oracle.Hierarchy(rp, c, v)
+    for seed in range(3):
+        b = P.rhs_uniform(20 ** 3, seed)
+        for fn in ("pcg", "fcg"):
+            x = torch.zeros(len(b), dtype=torch.float64, device="cuda")
+            g = getattr(h, fn)(dev(b), x)
+            r = o.pcg(b) if fn == "pcg" else o.fcg(b)
+            assert abs(g["iters"] - r["iters"]) <= 1 and g["relres"] <= 1e-6
+
+
+def test_single_level_and_initial_guess(psc):
+    rp, c, v = P.poisson7(5)                     # 125 rows: the coarsest level is level 0
+    h = psc.Hierarchy(rp, c, v)
+    assert h.info()["levels"] == 1
+    b = P.rhs_uniform(125, 1)
+    x = torch.zeros(125, dtype=torch.float64, device="cuda")
+    g = h.pcg(dev(b), x, rtol=1e-10)
+    assert g["iters"] == 1 and g["relres"] <= 1e-12
+    # a converged initial guess takes zero iterations
+    g2 = h.pcg(dev(b), x, rtol=1e-6)
+    assert g2["iters"] == 0 and g2["status"] == psc.OK
+
+
+def test_failure_paths(psc):
+    rp, c, v = P.poisson7(12)
+    h = psc.Hierarchy(rp, c, v)
+    n = 12 ** 3
+    x = torch.full((n,), 5.0, dtype=torch.float64, device="cuda")
+    g = h.pcg(torch.zeros(n, dtype=torch.float64, device="cuda"), x)
+    assert g["iters"] == 0 and g["status"] == psc.OK and not x.any()
+    b = P.rhs_uniform(n, 0)
+    x.zero_()
+    g = h.pcg(dev(b), x, rtol=1e-12, maxit=1)
+    assert g["status"] == psc.NOCONV and g["iters"] == 1 and 0 < g["relres"] < 1
+    bn = b.copy()
+    bn[7] = np.nan
+    with pytest.raises(psc.PscError) as e:
+        h.pcg(dev(bn), x)
+    assert e.value.status == psc.ERR_NAN
+    with pytest.raises(psc.PscError) as e:
+        h.fcg(dev(b), x, prec=psc.FP32)              # FP32 copies were not built
+    assert e.value.status == psc.ERR_STATE
+    v2 = v.copy()
+    v2[rp[3] + list(c[rp[3]:rp[4]]).index(3)] = -6.0
+    with pytest.raises(psc.PscError) as e:
+        psc.Hierarchy(rp, c, v2)
+    assert e.value.status == psc.ERR_NOT_SPD
+    c2 = c.copy()
+    c2[1], c2[0] = c[0], c[1]                       # unsorted row
+    with pytest.raises(psc.PscError) as e:
+        psc.Hierarchy(rp, c2, v)
+    assert e.value.status == psc.ERR_ARG

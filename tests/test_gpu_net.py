@@ -1,0 +1,153 @@
+"""GPU parity of the learned preconditioner's kernels against the CPU oracle.
+
+Both sides round the same operands to bfloat16; the GPU accumulates in FP32
+(MFMA for the 16 -> 16 layer) and the oracle in FP64, so an activation can
+land on the other side of a bfloat16 rounding boundary. Tolerances: forward
+outputs 1e-2 relative (norm), gradients 3e-2 relative per parameter group.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle
+from paper_2406_19754_amd import problems as P
+
+GROUPS = {"W1": (0, 432), "b1": (432, 448), "W2": (448, 7360), "b2": (7360, 7376), "W3": (7376, 7808), "b3": (7808, 7809)}
+
+
+@pytest.fixture(scope="module")
+def psc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_19754_amd import psc as m
+    return m
+
+
+def params(seed, scale=0.7):
+    p = P.net_init(seed).astype(np.float64)
+    p += 0.05 * np.random.default_rng(seed + 7).standard_normal(p.size)
+    return (p * scale).astype(np.float32)
+
+
+def relerr(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("B,D", [(2, 10), (3, 20), (1, 33)])
+def test_forward_batch_matches_oracle(psc, B, D):
+    p = params(1)
+    u = np.random.default_rng(B * D).standard_normal((B, D, D, D)).astype(np.float32)
+    net = psc.Net(p)
+    out = torch.empty(B, D, D, D, dtype=torch.float32, device="cuda")
+    net.forward_batch(torch.from_numpy(u).cuda(), out)
+    ref = oracle.net_forward(p.astype(np.float64), u.astype(np.float64), round_bf16=True)
+    assert relerr(out.cpu().numpy(), ref) <= 1e-2
+
+
+def test_loss_and_gradients_match_oracle(psc):
+    p = params(2)
+    rng = np.random.default_rng(3)
+    B, D, margin = 2, 12, 2
+    u = rng.standard_normal((B, D, D, D)).astype(np.float32)
+    y = rng.standard_normal((B, D, D, D)).astype(np.float32)
+    net = psc.Net(p)
+    loss, g = net.loss_grad(torch.from_numpy(u).cuda(), torch.from_numpy(y).cuda(), margin)
+    lref, gref = oracle.net_loss_grad(p.astype(np.float64), u.astype(np.float64), y.astype(np.float64), margin,
+                                      round_bf16=True)
+    assert abs(loss - lref) <= 1e-3 * lref
+    for name, (a, b) in GROUPS.items():
+        assert relerr(g[a:b], gref[a:b]) <= 3e-2, name
+
+
+def test_adam_step_and_training_lowers_loss(psc):
+    p = params(4)
+    rng = np.random.default_rng(5)
+    ncrops, D, margin = 8, 12, 2
+    r = rng.standard_normal((ncrops, D, D, D)).astype(np.float32)
+    z = (0.3 * r).astype(np.float32)            # a learnable target: a scaled identity
+    rd, zd = torch.from_numpy(r).cuda(), torch.from_numpy(z).cuda()
+    net = psc.Net(p)
+    order = np.array([0, 1], np.int32)
+    _, g = net.loss_grad(rd[:2].contiguous(), zd[:2].contiguous(), margin)
+    net.train(rd, zd, order, steps=1, batch=2, margin=margin, lr=1e-3)
+    p1 = net.params()
+    ref, _, _ = oracle.adam_step(p.astype(np.float64), np.zeros(p.size), np.zeros(p.size), g.astype(np.float64), 1, lr=1e-3)
+    np.testing.assert_allclose(p1, ref, rtol=0, atol=2e-6)
+    order = np.random.default_rng(6).integers(0, ncrops, 2 * 60).astype(np.int32)
+    losses = net.train(rd, zd, order, steps=60, batch=2, margin=margin, lr=3e-3)
+    assert np.mean(losses[-10:]) < 0.5 * np.mean(losses[:5])
+
+
+def test_net_apply_matches_oracle(psc):
+    p = params(8)
+    dims = (9, 10, 12)                              # (nz, ny, nx), not cubic
+    N = int(np.prod(dims))
+    r = np.random.default_rng(9).standard_normal(N)
+    net = psc.Net(p)
+    z = torch.empty(N, dtype=torch.float64, device="cuda")
+    net.apply(torch.from_numpy(r).cuda(), z, dims)
+    ref = oracle.net_apply(p.astype(np.float64), r, dims)
+    assert relerr(z.cpu().numpy(), ref) <= 1e-2
+
+
+def test_zero_network_falls_back_to_vcycle(psc):
+    n = 16
+    rp, c, v = P.poisson7(n)
+    h = psc.Hierarchy(rp, c, v)
+    net = psc.Net(np.zeros(psc.net_param_count(), np.float32))
+    net.set_grid((n, n, n))
+    b = torch.from_numpy(P.rhs_uniform(n ** 3, 1)).cuda()
+    x = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+    g = h.fcg(b, x, net=net)
+    x2 = torch.zeros_like(x)
+    g0 = h.fcg(b, x2)
+    assert g["status"] == psc.OK and g["relres"] <= 1e-6 and g["fallbacks"] >= 1
+    assert g["iters"] == g0["iters"]
+    assert torch.equal(x, x2)
+
+
+def test_learned_fcg_matches_oracle(psc):
+    n = 16
+    rp, c, v = P.poisson7(n)
+    p = params(11, scale=0.3)
+    h = psc.Hierarchy(rp, c, v)
+    o = oracle.Hierarchy(rp, c, v)
+    net = psc.Net(p)
+    net.set_grid((n, n, n))
+    b = P.rhs_uniform(n ** 3, 12)
+    x = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+    g = h.fcg(torch.from_numpy(b).cuda(), x, net=net)
+    r = o.fcg(b, params=p.astype(np.float64), dims=(n, n, n))
+    assert g["status"] == psc.OK and r["status"] == oracle.OK
+    assert g["relres"] <= 1e-6
+    assert abs(g["iters"] - r["iters"]) <= 2
+    # graph replay and stream launch give the same iterates
+    h2 = psc.Hierarchy(rp, c, v, use_graph=False)
+    x2 = torch.zeros_like(x)
+    g2 = h2.fcg(torch.from_numpy(b).cuda(), x2, net=net)
+    assert g2["iters"] == g["iters"] and torch.equal(x, x2)
+
+
+def test_pairs_collect_first_pair_matches_oracle(psc):
+    n, crop, cpi = 16, 8, 2
+    rp, c, v = P.poisson7(n)
+    h = psc.Hierarchy(rp, c, v)
+    o = oracle.Hierarchy(rp, c, v)
+    b = P.rhs_uniform(n ** 3, 21)
+    origins = P.crop_origins(22, 200, (n, n, n), crop)
+    cap = 64
+    rout = torch.zeros(cap, crop, crop, crop, dtype=torch.float32, device="cuda")
+    zout = torch.zeros_like(rout)
+    cnt = psc.pairs_collect(h, torch.from_numpy(b).cuda(), (n, n, n), crop, cpi, origins, rout, zout)
+    iters = o.pcg(b)["iters"]
+    assert cnt == cpi * iters                       # pairs (r_k, B r_k), k = 0 .. iters-1
+    s0 = np.linalg.norm(b) / np.sqrt(n ** 3)
+    z0 = o.vcycle(b)
+    for k in range(cpi):
+        oz, oy, ox = origins[k]
+        sl = (slice(oz, oz + crop), slice(oy, oy + crop), slice(ox, ox + crop))
+        np.testing.assert_allclose(rout[k].cpu().numpy(), (b.reshape(n, n, n)[sl] / s0).astype(np.float32),
+                                   rtol=1e-6, atol=1e-6)
+        np.testing.assert_allclose(zout[k].cpu().numpy(), (z0.reshape(n, n, n)[sl] / s0), rtol=1e-5, atol=1e-6)

@@ -1,0 +1,63 @@
+"""Host setup of the library (locally-dominant matching, canonical Galerkin
+sums) against the oracle (sorted-greedy matching): the hierarchies must be
+bit-identical. Runs on the CPU through the C ABI with host_only=1."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_19754_amd import problems as P
+from paper_2406_19754_amd import psc
+
+CASES = {
+    "poisson32": (lambda: P.poisson7(32), 200, 2),
+    "poisson9": (lambda: P.poisson7(9), 200, 2),
+    "poisson24_aggr8": (lambda: P.poisson7(24), 200, 3),
+    "diffusion16_lognormal_az100": (lambda: P.diffusion7(16, seed=0, az=100.0), 200, 2),
+    "diffusion14_lognormal_az0.01": (lambda: P.diffusion7(14, seed=2, az=0.01), 100, 2),
+    "random_spd": (lambda: P.random_spd_csr(500, 3, density=0.02, maxrow=50), 40, 2),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_host_hierarchy_bit_identical_to_oracle(case):
+    mk, cm, sweeps = CASES[case]
+    rp, c, v = mk()
+    h = psc.Hierarchy(rp, c, v, host_only=True, coarse_max=cm, sweeps=sweeps)
+    o = oracle.Hierarchy(rp, c, v, coarse_max=cm, sweeps=sweeps)
+    inf = h.info()
+    assert inf["rows"] == o.sizes()
+    assert inf["nnz"] == o.nnzs()
+    assert abs(inf["operator_complexity"] - o.operator_complexity()) < 1e-15
+    for l in range(inf["levels"]):
+        a, b = h.export_level(l), o.level(l)
+        for key in ["rowptr", "col", "val", "minv"]:
+            assert np.array_equal(a[key], b[key]), (l, key)
+        if l < inf["levels"] - 1:
+            assert np.array_equal(a["agg"], b["agg"]) and np.array_equal(a["p"], b["p"]), l
+
+
+def test_host_only_handle_refuses_solves():
+    rp, c, v = P.poisson7(8)
+    h = psc.Hierarchy(rp, c, v, host_only=True)
+    with pytest.raises(psc.PscError) as e:
+        h.pcg(0, 0)
+    assert e.value.status == psc.ERR_STATE
+
+
+def test_malformed_csr_is_rejected():
+    rp, c, v = P.poisson7(6)
+    bad = c.copy()
+    bad[5] = 10 ** 6                                   # column out of range
+    with pytest.raises(psc.PscError) as e:
+        psc.Hierarchy(rp, bad, v, host_only=True)
+    assert e.value.status == psc.ERR_ARG
+    rp2 = rp.copy()
+    rp2[3] = rp2[4] + 1                                # decreasing row pointer
+    with pytest.raises(psc.PscError) as e:
+        psc.Hierarchy(rp2, c, v, host_only=True)
+    assert e.value.status == psc.ERR_ARG
+    v2 = v.copy()
+    v2[0] = 0.0                                        # zero diagonal
+    with pytest.raises(psc.PscError) as e:
+        psc.Hierarchy(rp, c, v2, host_only=True)
+    assert e.value.status == psc.ERR_NOT_SPD
