@@ -1,21 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the AMG-PCG solve phase on one MI355X.
 
-A step is one full solve to rtol 1e-6 from x0 = 0 of the 7-point 3D Poisson
-problem on a 256^3 grid (16.8M unknowns, 117M nonzeros, b = A x_true with
-x_true ~ U[0,1) seed 0): FP64 preconditioned CG with the FP64 AMG V-cycle.
-The V-cycle in FP32 inside FP64 flexible CG (and, when a trained network is
-available, the learned form) is timed on the same problem and reported
-beside it, each judged by its true FP64 residual.
+Default workload (one step = one full solve to rtol 1e-6 from x0 = 0): the
+7-point 3D Poisson problem on a 256^3 grid (16.8M unknowns, 117M nonzeros,
+b = A x_true with x_true ~ U[0,1) seed 0), FP64 preconditioned CG with the
+FP64 AMG V-cycle. On the same problem and GPU the FP32 V-cycle inside FP64
+flexible CG and, when trained weights are present, the learned form are
+timed and reported beside it, each judged by its true FP64 residual.
 
-Printed: one JSON line with the time to solution (ms per step), the
-per-kernel HBM roofline of the dominant kernel measured with HIP events on
-the library's stream during the timed steps, and the CPU oracle timed on a
-bounded sample of the same workload.
+Printed: one JSON line with the time to solution (ms per step), the HBM
+roofline of the dominant kernel (average duration from HIP events recorded
+on the library's stream around every launch during the timed steps), and
+the CPU oracle timed on a bounded sample of the same workload.
+
+Other workloads (not the headline line): --workload diffusion256 (lognormal
+coefficients, --az anisotropy), poisson384, learned128 (collect pairs, train
+the network, evaluate on held-out right-hand sides).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,22 +28,72 @@ import time
 
 METRIC = "time-to-rtol 1e-6 + SpMV/V-cycle HBM GB/s: FP64 vs mixed vs learned"
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(ROOT, "paper_2406_19754_amd", "weights", "net_poisson128.f32")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_poisson256.json")
 
 
-def kernel_bytes(info, form="fp64"):
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(info, form="fp64", fused=False):
     """Algorithmic bytes per launch of the level-0 kernels (each array once, no padding)."""
     N = info["rows"][0]
     Z = info["nnz"][0]
     Nc = info["rows"][1] if info["levels"] > 1 else 0
     v = 8 if form == "fp64" else 4
+    if fused:
+        return {
+            # A; z and p_old gathered; p_new, q written; x read and written
+            "spmv_dot": Z * 12 + 2 * 8 * N + 2 * 8 * N + 2 * 8 * N,
+            # A; r_old, q, minv gathered; r_new and the level-0 residual written
+            "pre_smooth_l0": Z * 12 + 3 * 8 * N + 2 * 8 * N,
+            "restrict_l0": N * 12 + 8 * N + 8 * Nc,
+            "post_smooth_l0": Z * 12 + 8 * N + 8 * N + 8 * N + 4 * N + 8 * Nc + 8 * N,
+        }
     return {
-        "spmv_dot": Z * 12 + 2 * 8 * N,                       # A, p gathered, q written
-        "cg_update": 6 * 8 * N,                               # x, r, p, q read; x, r written
-        "pre_smooth_l0": Z * (v + 4) + 8 * N + v * N + v * N,  # A, b (FP64 r), minv, r_l written
-        "restrict_l0": N * (v + 4) + v * N + v * Nc,          # R, r_l gathered, b_1 written
+        "spmv_dot": Z * 12 + 2 * 8 * N,                        # A, p gathered, q written
+        "cg_update": 6 * 8 * N,                                # x, r, p, q read; x, r written
+        "pre_smooth_l0": Z * (v + 4) + 8 * N + v * N + v * N,  # A, b (FP64 r), minv, r_0 written
+        "restrict_l0": N * (v + 4) + v * N + v * Nc,           # R, r_0 gathered, b_1 written
         "post_smooth_l0": Z * (v + 4) + 8 * N + v * N + v * N + 4 * N + v * Nc + 8 * N,
-        "dir_update": 3 * 8 * N,                              # z, p read; p written
+        "dir_update": 3 * 8 * N,                               # z, p read; p written
     }
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ["amg.hip", "kernels.h"]:
+        h.update(open(os.path.join(ROOT, "paper_2406_19754_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel):
+    """Per-launch HBM bytes of `kernel` from committed PMC counters, or None
+    when the counters were taken on other kernel sources."""
+    try:
+        t = json.load(open(TRAFFIC))
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def problem(workload, n, az, seed=0):
+    from paper_2406_19754_amd import problems as P
+    if workload.startswith("diffusion"):
+        rp, col, val = P.diffusion7(n, seed=seed, sigma=1.5, az=az)
+        desc = (f"3D lognormal diffusion -div(k grad u), FV 7-point, {n}^3, log k ~ N(0,1.5^2) seed {seed}, "
+                f"a_z = {az}")
+    else:
+        rp, col, val = P.poisson7(n)
+        desc = f"3D Poisson 7-point {n}^3"
+    xt = P.x_true(n ** 3, 0)
+    b = P.rhs_from_solution(rp, col, val, xt)
+    return rp, col, val, xt, b, desc
 
 
 def main():
@@ -46,50 +101,69 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=256, help="grid size per axis")
+    ap.add_argument("--workload", default="poisson256",
+                    choices=["poisson256", "poisson384", "diffusion256", "learned128"])
+    ap.add_argument("--n", type=int, default=0, help="grid size per axis (default from the workload)")
+    ap.add_argument("--az", type=float, default=1.0, help="z anisotropy of the diffusion workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3, help="oracle PCG iterations in the CPU sample")
     ap.add_argument("--spmv-reps", type=int, default=50)
     ap.add_argument("--grid-max", type=int, default=0, help="workgroup cap of the streaming kernels")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--unfused", action="store_true", help="one kernel per CG operation instead of the fused PCG iteration")
+    ap.add_argument("--train-epochs", type=int, default=2)
+    ap.add_argument("--crops", type=int, default=20000)
+    ap.add_argument("--save-weights", default="")
+    ap.add_argument("--profile-mix", action="store_true",
+                    help="run the kernel mix used for rocprofv3 counter passes: a plain 1 GiB device copy "
+                         "(counter calibration), 10 SpMVs on A_0, one FP64 PCG and one mixed FCG solve")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the path is not sharded "
-                                   "across GPUs (see the sharding notes in the design document)",
+        print(json.dumps({"error": "this build runs on one GPU only; the solve is not sharded across GPUs "
+                                   "(the sharding design is described in the design notes)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "learned128":
+        return learned(args)
+    if args.profile_mix:
+        return profile_mix(args)
 
     import numpy as np
     import torch
-    from paper_2406_19754_amd import problems as P
     from paper_2406_19754_amd import psc
 
-    def log(*a):
-        print("[bench]", *a, file=sys.stderr, flush=True)
-
-    n = args.n
+    n = args.n or {"poisson256": 256, "poisson384": 384, "diffusion256": 256}[args.workload]
     N = n ** 3
     t0 = time.time()
-    rp, col, val = P.poisson7(n)
-    xt = P.x_true(N, 0)
-    b = P.rhs_from_solution(rp, col, val, xt)
-    log(f"problem {n}^3 built in {time.time() - t0:.1f}s")
+    rp, col, val, xt, b, desc = problem(args.workload, n, args.az)
+    log(f"problem {desc} built in {time.time() - t0:.1f}s")
     t0 = time.time()
     h = psc.Hierarchy(rp, col, val, build_fp32=not args.no_mixed, use_graph=not args.no_graph)
     if args.grid_max:
         h.tune(psc.TUNE_GRID_MAX, args.grid_max)
+    if args.unfused:
+        h.tune(psc.TUNE_FUSED_PCG, 0)
     info = h.info()
     log(f"hierarchy {info['rows']} built in {time.time() - t0:.1f}s, opcx {info['operator_complexity']:.4f}")
     dev = torch.device("cuda:0")
     bd = torch.from_numpy(b).to(dev)
     x = torch.zeros(N, dtype=torch.float64, device=dev)
+    net = None
+    if not args.no_learned and os.path.exists(WEIGHTS) and not args.workload.startswith("diffusion"):
+        net = psc.Net(np.fromfile(WEIGHTS, dtype=np.float32))
+        net.set_grid((n, n, n))
 
     def run(form):
         x.zero_()
         if form == "fp64":
             return h.pcg(bd, x, rtol=1e-6, maxit=500)
-        return h.fcg(bd, x, rtol=1e-6, maxit=500, prec=psc.FP32)
+        if form == "mixed":
+            return h.fcg(bd, x, rtol=1e-6, maxit=500, prec=psc.FP32)
+        if form == "fcg64":
+            return h.fcg(bd, x, rtol=1e-6, maxit=500)
+        return h.fcg(bd, x, rtol=1e-6, maxit=500, net=net)
 
     def timed(form, steps, warmup, events):
         for _ in range(warmup):
@@ -110,13 +184,12 @@ def main():
     # headline: FP64 PCG; kernel durations from HIP events on the library stream
     ms64, r64, kt64 = timed("fp64", args.steps, args.warmup, True)
     log(f"fp64 pcg: {ms64:.2f} ms/solve, {r64['iters']} its, relres {r64['relres']:.2e}")
-    # same solves with graph replay and no events (reported, not the headline)
     ms64g, _, _ = timed("fp64", max(2, args.steps // 2), 1, False)
     log(f"fp64 pcg graph replay, no events: {ms64g:.2f} ms/solve")
     xg = x.cpu().numpy()
     err_true = float(np.linalg.norm(xg - xt) / np.linalg.norm(xt))
 
-    kb = kernel_bytes(info, "fp64")
+    kb = kernel_bytes(info, "fp64", fused=not args.unfused and info["levels"] > 1)
     kernels = {}
     for name, (cnt, tot) in kt64.items():
         if cnt and name in kb:
@@ -128,7 +201,7 @@ def main():
     vc_cnt, vc_ms = kt64["vcycle"]
     vcycle_gbs = info["vcycle_bytes_fp64"] / (vc_ms / vc_cnt * 1e-3) / 1e9 if vc_cnt else None
 
-    # isolated SpMV loop on A_0 (same kernel family, 100 back-to-back launches)
+    # isolated SpMV loop on A_0 (the same kernel family)
     xs = torch.rand(N, dtype=torch.float64, device=dev)
     ys = torch.empty_like(xs)
     h.spmv(xs, ys)
@@ -142,16 +215,25 @@ def main():
     spmv_gbs = info["spmv_bytes_fp64"] / (spmv_ms * 1e-3) / 1e9
 
     forms = {"fp64": {"ms": ms64, "iters": r64["iters"], "relres": r64["relres"],
-                      "err_vs_x_true": err_true, "ms_graph_no_events": ms64g}}
+                      "err_vs_x_true": err_true, "ms_graph_no_events": ms64g,
+                      "vcycle_gbs": vcycle_gbs}}
     if not args.no_mixed:
-        ms32, r32, kt32 = timed("fp32", args.steps, args.warmup, True)
-        log(f"mixed fcg: {ms32:.2f} ms/solve, {r32['iters']} its, relres {r32['relres']:.2e}")
+        ms32, r32, kt32 = timed("mixed", args.steps, args.warmup, True)
+        ms32g, _, _ = timed("mixed", max(2, args.steps // 2), 1, False)
+        log(f"mixed fcg: {ms32:.2f} ms/solve ({ms32g:.2f} graph), {r32['iters']} its, relres {r32['relres']:.2e}")
         vc_cnt32, vc_ms32 = kt32["vcycle"]
-        forms["mixed"] = {"ms": ms32, "iters": r32["iters"], "relres": r32["relres"],
+        forms["mixed"] = {"ms": ms32, "ms_graph_no_events": ms32g, "iters": r32["iters"], "relres": r32["relres"],
                           "speedup_vs_fp64": ms64 / ms32,
+                          "speedup_vs_fp64_graph": ms64g / ms32g,
                           "vcycle_gbs": info["vcycle_bytes_fp32"] / (vc_ms32 / vc_cnt32 * 1e-3) / 1e9
                           if vc_cnt32 else None,
                           "err_vs_fp64_x": float(np.linalg.norm(x.cpu().numpy() - xg) / np.linalg.norm(xg))}
+    if net is not None:
+        msl, rl, _ = timed("learned", args.steps, args.warmup, False)
+        log(f"learned fcg: {msl:.2f} ms/solve, {rl['iters']} its, relres {rl['relres']:.2e}, "
+            f"fallbacks {rl['fallbacks']}")
+        forms["learned"] = {"ms": msl, "iters": rl["iters"], "relres": rl["relres"], "fallbacks": rl["fallbacks"],
+                            "speedup_vs_fp64_graph": ms64g / msl, "weights": os.path.relpath(WEIGHTS, ROOT)}
 
     cpu = None
     if not args.no_cpu:
@@ -161,15 +243,15 @@ def main():
         t_setup = time.time() - t0
         k = args.cpu_iters
         t0 = time.perf_counter()
-        ro = o.pcg(b, rtol=1e-30, maxit=k)
+        o.pcg(b, rtol=1e-30, maxit=k)
         t_k = time.perf_counter() - t0
-        per_it = t_k / k
-        est = per_it * r64["iters"] * 1e3
+        est = t_k / k * r64["iters"] * 1e3
         cpu = {"value": est, "unit": "ms", "cores": 1, "kind": "oracle",
                "sample": f"oracle PCG, {k} of {r64['iters']} iterations on the same {n}^3 problem "
-                         f"({t_k:.1f}s), scaled to {r64['iters']}; oracle setup {t_setup:.1f}s excluded",
+                         f"({t_k:.1f}s, single thread), scaled to {r64['iters']}; oracle setup {t_setup:.1f}s "
+                         "excluded like the GPU setup",
                "gpu_speedup": est / ms64}
-        log(f"cpu oracle: {per_it:.2f} s/iter -> {est / 1e3:.1f} s/solve (setup {t_setup:.1f}s)")
+        log(f"cpu oracle: {t_k / k:.2f} s/iter -> {est / 1e3:.1f} s/solve (setup {t_setup:.1f}s)")
 
     out = {
         "metric": METRIC,
@@ -184,9 +266,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"3D Poisson 7-point {n}^3 ({N} unknowns, {info['nnz'][0]} nnz), "
-                               "FP64 PCG + matching AMG V(1,1) l1-Jacobi, rtol 1e-6, "
-                               "b = A x_true, x_true ~ U[0,1) seed 0, x0 = 0",
+        "config": {"workload": f"{desc} ({N} unknowns, {info['nnz'][0]} nnz), FP64 PCG + matching-AMG "
+                               "V(1,1) l1-Jacobi, aggregates <= 4, rtol 1e-6, b = A x_true, "
+                               "x_true ~ U[0,1) seed 0, x0 = 0",
                    "levels": info["levels"], "rows": info["rows"],
                    "operator_complexity": info["operator_complexity"],
                    "setup_s": info["setup_seconds"]},
@@ -198,11 +280,81 @@ def main():
         "forms": forms,
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": traffic_for(dom),
                      "alg_bytes_per_launch": d["alg_bytes"], "avg_ms": d["avg_ms"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def profile_mix(args):
+    import torch
+    from paper_2406_19754_amd import psc
+    n = args.n or 256
+    N = n ** 3
+    rp, col, val, xt, b, desc = problem(args.workload, n, args.az)
+    h = psc.Hierarchy(rp, col, val, build_fp32=True)
+    src = torch.rand(2 ** 27, dtype=torch.float64, device="cuda")   # 1 GiB read + 1 GiB written per copy
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    xs = torch.rand(N, dtype=torch.float64, device="cuda")
+    ys = torch.empty_like(xs)
+    for _ in range(10):
+        h.spmv(xs, ys)
+    x = torch.zeros(N, dtype=torch.float64, device="cuda")
+    bd = torch.from_numpy(b).cuda()
+    r1 = h.pcg(bd, x)
+    x.zero_()
+    r2 = h.fcg(bd, x, prec=psc.FP32)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_mix": desc, "copy_bytes_read": 2 ** 30, "copy_bytes_written": 2 ** 30,
+                      "pcg": r1, "mixed": r2}), flush=True)
+
+
+def learned(args):
+    """Collect pairs on 128^3 Poisson, train the network, evaluate on held-out seeds."""
+    import numpy as np
+    import torch
+    from paper_2406_19754_amd import learned as LR
+    from paper_2406_19754_amd import problems as P
+    from paper_2406_19754_amd import psc
+    n = args.n or 128
+    rp, col, val = P.poisson7(n)
+    h = psc.Hierarchy(rp, col, val)
+    t0 = time.time()
+    r, z = LR.collect_pairs(h, n, range(1, 65), range(101, 133), crops=args.crops, crop=40, seed=0)
+    t_collect = time.time() - t0
+    log(f"collected {r.shape[0]} crops in {t_collect:.1f}s")
+    net = psc.Net(P.net_init(0))
+    t0 = time.time()
+    losses, v0, v1 = LR.train(net, r, z, epochs=args.train_epochs, batch=16, margin=3, lr=1e-3, seed=0, log=log)
+    t_train = time.time() - t0
+    log(f"trained {len(losses)} steps in {t_train:.1f}s; validation MSE {v0:.4e} -> {v1:.4e}")
+    if args.save_weights:
+        os.makedirs(os.path.dirname(os.path.abspath(args.save_weights)), exist_ok=True)
+        net.params().tofile(args.save_weights)
+    net.set_grid((n, n, n))
+    del r, z
+    torch.cuda.empty_cache()
+    ev = LR.evaluate(h, net, n, range(1001, 1009), kinds=("uniform",), reps=3)
+    untrained = psc.Net(P.net_init(0))
+    untrained.set_grid((n, n, n))
+    ev_u = LR.evaluate(h, untrained, n, range(1001, 1003), kinds=("uniform",), reps=1)
+    summary = {
+        "workload": f"learned preconditioner, 3D Poisson 7-point {n}^3, held-out RHS U[-1,1] seeds 1001-1008",
+        "crops": int(losses.size and args.crops), "collect_s": t_collect, "train_s": t_train,
+        "train_steps": int(losses.size), "loss_first": float(losses[:20].mean()) if losses.size else None,
+        "loss_last": float(losses[-20:].mean()) if losses.size else None, "val_mse_before": v0, "val_mse_after": v1,
+        "pcg_iters": [e["pcg"]["iters"] for e in ev], "learned_iters": [e["learned"]["iters"] for e in ev],
+        "pcg_ms": float(np.mean([e["pcg"]["ms"] for e in ev])),
+        "learned_ms": float(np.mean([e["learned"]["ms"] for e in ev])),
+        "learned_relres": max(e["learned"]["relres"] for e in ev),
+        "learned_fallbacks": [e["learned"]["fallbacks"] for e in ev],
+        "untrained_iters": [e["learned"]["iters"] for e in ev_u],
+    }
+    summary["speedup_learned_vs_pcg"] = summary["pcg_ms"] / summary["learned_ms"]
+    print(json.dumps(summary), flush=True)
 
 
 if __name__ == "__main__":

@@ -195,11 +195,16 @@ int psc_timing_enable(psc_hier* h, int32_t on);
 int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
 
 /*
- * Launch-shape tuning. PSC_TUNE_GRID_MAX caps the number of workgroups of
- * the streaming kernels (multiple of 8, at most 65536; default 4096).
- * Invalidates captured graphs.
+ * Tuning. PSC_TUNE_GRID_MAX caps the number of workgroups of the streaming
+ * kernels (multiple of 8, at most 65536; default 4096; invalidates captured
+ * graphs). PSC_TUNE_FUSED_PCG (default 1) selects the fused PCG iteration:
+ * the direction update and the (deferred) x update ride in the SpMV pass,
+ * the residual update rides in the level-0 pre-smoothing pass; 0 selects
+ * the one-kernel-per-operation sequence. Both give the same iterates up to
+ * rounding.
  */
 #define PSC_TUNE_GRID_MAX 1
+#define PSC_TUNE_FUSED_PCG 2
 int psc_tune(psc_hier* h, int32_t key, int32_t value);
 
 void psc_hier_free(psc_hier* h);

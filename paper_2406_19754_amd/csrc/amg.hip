@@ -131,8 +131,8 @@ __device__ void finalize(int fin, double s0, double s1, Ctl* c, HostCtl* hc) {
         break;
     case FIN_ALPHA_PCG:
         c->pq = s0;
-        if (isnan(s0)) { c->status = PSC_ERR_NAN; c->done = 1; }
-        else if (!(s0 > 0.0)) { c->status = PSC_ERR_NOT_SPD; c->done = 1; }
+        if (isnan(s0)) { c->status = PSC_ERR_NAN; c->done = 1; c->alpha = 0.0; }
+        else if (!(s0 > 0.0)) { c->status = PSC_ERR_NOT_SPD; c->done = 1; c->alpha = 0.0; }
         else c->alpha = c->rho / s0;
         break;
     case FIN_ALPHA_FCG:
@@ -169,6 +169,7 @@ __device__ void finalize(int fin, double s0, double s1, Ctl* c, HostCtl* hc) {
         c->beta = c->have_prev ? s0 / c->pq_prev : 0.0;
         break;
     case FIN_TRUE:
+        if (!c->check) break;          // no true-residual check was due this iteration
         c->check = 0;
         if (isnan(s0)) { c->status = PSC_ERR_NAN; c->done = 1; }
         else if (sqrt(s0) <= c->rtol * sqrt(c->nb2)) { c->status = PSC_OK; c->done = 1; }
@@ -243,7 +244,10 @@ __global__ __launch_bounds__(WG) void k_finish(Red R, int nblk) {
 }
 
 // Row sum over one hacked-ELL row: sum_k val[k] * g(col[k]) in slot order
-// (ascending column order of the CSR input; padded slots carry 0).
+// (ascending column order of the CSR input; padded slots carry 0). Slices of
+// width <= 8 (every stencil slice) issue all value and index loads before
+// the first gather, so a wavefront keeps up to 16 streaming loads and 8
+// gathers in flight; wider slices take the general loop.
 template <typename T, typename G>
 __device__ __forceinline__ T ell_row(const Ell<T>& A, long long s, int lane, G g) {
     const long long o = A.off[s];
@@ -251,6 +255,25 @@ __device__ __forceinline__ T ell_row(const Ell<T>& A, long long s, int lane, G g
     const T* vp = A.val + o + lane;
     const int* cp = A.col + o + lane;
     T acc = T(0);
+    if (w <= 8) {
+        T v[8];
+        int c[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            if (k < w) {
+                v[k] = ntload(vp + k * SLICE);
+                c[k] = ntload(cp + k * SLICE);
+            }
+        }
+        T gv[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (k < w) gv[k] = g(c[k]);
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (k < w) acc += v[k] * gv[k];
+        return acc;
+    }
     int k = 0;
     for (; k + 4 <= w; k += 4) {
         T v0 = ntload(vp + 0 * SLICE), v1 = ntload(vp + 1 * SLICE);
@@ -275,6 +298,17 @@ __device__ __forceinline__ T ell_row(const Ell<T>& A, long long s, int lane, G g
     return acc;
 }
 
+// Vector range of this workgroup, in whole 512-element units so that the
+// bulk is walked with 16-byte (2 x FP64) loads.
+__device__ __forceinline__ void vchunk_range(long long total, long long& lo, long long& hi) {
+    const int lb = logical_block();
+    long long per = (total + gridDim.x - 1) / gridDim.x;
+    per = (per + 2 * WG - 1) / (2 * WG) * (2 * WG);
+    lo = (long long)lb * per;
+    hi = lo + per;
+    if (hi > total) hi = total;
+    if (lo > total) lo = total;
+}
 
 // ---------------------------------------------------------------------------
 // kernels
@@ -350,12 +384,24 @@ __global__ __launch_bounds__(WG) void k_update(long long n, double* __restrict__
     if (skip_red(R)) return;
     const double alpha = R.ctl->alpha;
     long long lo, hi;
-    chunk_range(n, lo, hi);
+    vchunk_range(n, lo, hi);
     double s0 = 0.0;
-    for (long long i = lo + threadIdx.x; i < hi; i += WG) {
-        double xi = x[i] + alpha * p[i];
-        double ri = r[i] - alpha * q[i];
-        x[i] = xi;
+    long long i = lo + 2 * threadIdx.x;
+    for (; i + 1 < hi; i += 2 * WG) {
+        const double2 pp = *(const double2*)(p + i), qq = *(const double2*)(q + i);
+        double2 xx = *(const double2*)(x + i), rr = *(const double2*)(r + i);
+        xx.x += alpha * pp.x;
+        xx.y += alpha * pp.y;
+        rr.x -= alpha * qq.x;
+        rr.y -= alpha * qq.y;
+        *(double2*)(x + i) = xx;
+        *(double2*)(r + i) = rr;
+        s0 += rr.x * rr.x;
+        s0 += rr.y * rr.y;
+    }
+    if (i < hi) {   // odd tail (last element of the vector)
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
         r[i] = ri;
         s0 += ri * ri;
     }
@@ -366,17 +412,86 @@ __global__ __launch_bounds__(WG) void k_update(long long n, double* __restrict__
 __global__ __launch_bounds__(WG) void k_pupdate(long long n, double* __restrict__ p,
                                                 const double* __restrict__ z, int fcg, Gate g) {
     if (gate_skip(g)) return;
-    const double beta = g.ctl->beta;
     const int keep = fcg ? g.ctl->have_prev : 1;
+    const double beta = keep ? (fcg ? -g.ctl->beta : g.ctl->beta) : 0.0;
+    long long lo, hi;
+    vchunk_range(n, lo, hi);
+    long long i = lo + 2 * threadIdx.x;
+    if (!keep) {
+        for (; i + 1 < hi; i += 2 * WG) *(double2*)(p + i) = *(const double2*)(z + i);
+        if (i < hi) p[i] = z[i];
+        return;
+    }
+    for (; i + 1 < hi; i += 2 * WG) {
+        const double2 zz = *(const double2*)(z + i);
+        double2 pp = *(const double2*)(p + i);
+        pp.x = zz.x + beta * pp.x;
+        pp.y = zz.y + beta * pp.y;
+        *(double2*)(p + i) = pp;
+    }
+    if (i < hi) p[i] = z[i] + beta * p[i];
+}
+
+// Fused PCG, first pass: p_new = z + beta p_old (own row, and recomputed
+// for every gathered neighbour), q = A p_new, the x update deferred from the
+// previous iteration x += alpha_prev p_old, and the partial p_new.q.
+// alpha in the control block still holds alpha_prev here (0 at the start).
+__global__ __launch_bounds__(WG) void k_spmv_pfuse(Ell<double> A, const double* __restrict__ z,
+                                                   const double* __restrict__ pold, double* __restrict__ pnew,
+                                                   double* __restrict__ q, double* __restrict__ x, Red R) {
+    if (skip_red(R)) return;
+    const double beta = R.ctl->beta, alpha_prev = R.ctl->alpha;
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double s0 = 0.0;
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        double acc = ell_row(A, s, lane, [&](int c) { return fma(beta, pold[c], z[c]); });
+        long long row = s * SLICE + lane;
+        if (row < A.nrows) {
+            const double po = pold[row];
+            const double pn = fma(beta, po, z[row]);
+            pnew[row] = pn;
+            q[row] = acc;
+            x[row] = fma(alpha_prev, po, x[row]);
+            s0 += pn * acc;
+        }
+    }
+    block_partial(s0, 0.0, R.part);
+}
+
+// Fused PCG, second pass: r_new = r_old - alpha q (own row, and recomputed for
+// every gathered neighbour), the level-0 pre-smoothing residual
+// r0 = r_new - A (minv .* r_new), and the partial ||r_new||^2.
+__global__ __launch_bounds__(WG) void k_update_pre(Ell<double> A, const double* __restrict__ minv,
+                                                   const double* __restrict__ rold, const double* __restrict__ q,
+                                                   double* __restrict__ rnew, double* __restrict__ r0, Red R) {
+    if (skip_red(R)) return;
+    const double nalpha = -R.ctl->alpha;
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double s0 = 0.0;
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        double acc = ell_row(A, s, lane, [&](int c) { return minv[c] * fma(nalpha, q[c], rold[c]); });
+        long long row = s * SLICE + lane;
+        if (row < A.nrows) {
+            const double rn = fma(nalpha, q[row], rold[row]);
+            rnew[row] = rn;
+            r0[row] = rn - acc;
+            s0 += rn * rn;
+        }
+    }
+    block_partial(s0, 0.0, R.part);
+}
+
+// x += alpha p once the fused iteration has stopped (its last x update is deferred).
+__global__ __launch_bounds__(WG) void k_final_axpy(long long n, double* __restrict__ x, const double* __restrict__ p,
+                                                   const Ctl* ctl) {
+    const double alpha = ctl->alpha;
     long long lo, hi;
     chunk_range(n, lo, hi);
-    if (!keep) {
-        for (long long i = lo + threadIdx.x; i < hi; i += WG) p[i] = z[i];
-    } else if (fcg) {
-        for (long long i = lo + threadIdx.x; i < hi; i += WG) p[i] = z[i] - beta * p[i];
-    } else {
-        for (long long i = lo + threadIdx.x; i < hi; i += WG) p[i] = z[i] + beta * p[i];
-    }
+    for (long long i = lo + threadIdx.x; i < hi; i += WG) x[i] = fma(alpha, p[i], x[i]);
 }
 
 // partials (a.b, 0) for a dot product not fused elsewhere
@@ -542,6 +657,8 @@ struct psc_hier {
     psc::HostCtl* hctl_dev = nullptr;
     double* part = nullptr;
     double *xs = nullptr, *bs = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    double *r2 = nullptr, *p2 = nullptr;  // second buffers of the fused PCG iteration
+    bool fused_pcg = true;                // PCG form: fused two-pass iteration
     std::vector<void*> allocs;
     int64_t device_bytes = 0;
     double setup_seconds = 0.0;
@@ -686,7 +803,7 @@ static void finish(psc_hier* h, const Red& R, int grid) {
 // z.d at level 0 with finaliser fin. g gates every kernel (g.ctl == NULL:
 // standalone V-cycle, always runs, no fused dot).
 static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin, const double* d,
-                   Gate g) {
+                   Gate g, bool skip_pre0 = false) {
     hipStream_t st = h->stream;
     const int L = (int)h->lev.size();
     Red R = red_of(h, fin, g.ctl ? g.mode : GATE_NONE);
@@ -706,7 +823,7 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
         for (int l = 0; l < L - 1; l++) {
             DevLevel& V = h->lev[l];
             const double* b = l == 0 ? r0 : V.b;
-            {
+            if (!(l == 0 && skip_pre0)) {
                 TimeScope t(h, l == 0 ? 2 : 7);
                 k_pre<double, double><<<grid_ell(h, V.A.nslices), WG, 0, st>>>(V.A.view(), V.minv, b, V.r, g);
             }
@@ -779,8 +896,8 @@ static const int RING = 8;
 
 // forms: 0 PCG + FP64 V-cycle; 1 FCG(1) + FP64 V-cycle; 2 FCG(1) + FP32
 // V-cycle; 3 / 4: forms 1 / 2 with the learned network on odd iterations.
-static inline bool form_fcg(int form) { return form != 0; }
-static inline bool form_net(int form) { return form >= 3; }
+static const int FORM_FUSED = 5;   // PCG, fused two-pass iteration, issued two iterations at a time
+static inline bool form_net(int form) { return form == 3 || form == 4; }
 static inline int form_prec(int form) { return (form == 2 || form == 4) ? PSC_FP32 : PSC_FP64; }
 
 __global__ void k_iter_begin(Ctl* c, HostCtl* hc, int has_net) {
@@ -815,6 +932,27 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
     const long long n = L0.n;
     const int ge = grid_ell(h, L0.A.nslices), gv = grid_vec(h, n);
     const Gate gd{h->ctl, GATE_DONE};
+    if (form == FORM_FUSED) {
+        // two iterations (even, odd) with the p and r buffers swapped between them
+        for (int parity = 0; parity < 2; parity++) {
+            double* pold = parity ? h->p2 : h->p;
+            double* pnew = parity ? h->p : h->p2;
+            double* rold = parity ? h->r2 : h->r;
+            double* rnew = parity ? h->r : h->r2;
+            {
+                TimeScope t(h, 0);
+                k_spmv_pfuse<<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, red_of(h, FIN_ALPHA_PCG));
+            }
+            finish(h, red_of(h, FIN_ALPHA_PCG), ge);
+            {
+                TimeScope t(h, 2);
+                k_update_pre<<<ge, WG, 0, st>>>(L0.A.view(), L0.minv, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_PCG));
+            }
+            finish(h, red_of(h, FIN_UPDATE_PCG), ge);
+            vcycle(h, PSC_FP64, rnew, h->z, FIN_RHO, rnew, gd, true);
+        }
+        return PSC_OK;
+    }
     if (form == 0) {
         {
             TimeScope t(h, 0);
@@ -938,9 +1076,14 @@ static int solve_impl(psc_hier* h, int form, psc_net* net, const double* b_dev, 
         return PSC_OK;
     }
     const bool use_graph = h->opts.use_graph && !h->timing;
+    const bool fused = form == 0 && h->fused_pcg && h->lev.size() > 1;
+    if (fused) form = FORM_FUSED;
     if (!c.done) {
         const Gate gd{h->ctl, GATE_DONE};
-        if (form == 0) {
+        if (fused) {
+            vcycle(h, PSC_FP64, h->r, h->z, FIN_RHO_INIT, h->r, gd);
+            k_fill<double><<<gv, WG, 0, st>>>(n, h->p, 0.0);   // p_old of the first iteration (beta = 0)
+        } else if (form == 0) {
             vcycle(h, PSC_FP64, h->r, h->z, FIN_RHO_INIT, h->r, gd);
             k_copy<double, double><<<gv, WG, 0, st>>>(n, h->p, h->z, gd);
         } else {
@@ -952,7 +1095,8 @@ static int solve_impl(psc_hier* h, int form, psc_net* net, const double* b_dev, 
             rs = get_graph(h, form, net, &gexec);
             if (rs) return rs;
         }
-        for (int k = 0; k < maxit; k++) {
+        const int per_launch = fused ? 2 : 1;
+        for (int k = 0; k * per_launch < maxit; k++) {
             if (use_graph) HIPCHK(hipGraphLaunch(gexec, st));
             else if ((rs = issue_iteration(h, form, net))) return rs;
             HIPCHK(hipEventRecord(h->ring[k % RING], st));
@@ -966,6 +1110,10 @@ static int solve_impl(psc_hier* h, int form, psc_net* net, const double* b_dev, 
         timing_collect(h);
         rs = read_ctl(h, &c);
         if (rs) return rs;
+        if (fused) {
+            // the last iteration's x update is deferred: x += alpha p_last
+            k_final_axpy<<<gv, WG, 0, st>>>(n, h->xs, (c.iter & 1) ? h->p2 : h->p, h->ctl);
+        }
     }
     // true residual in FP64 (ungated: runs after convergence)
     {
@@ -1200,7 +1348,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     const int64_t N = n;
     if ((st = dalloc(h.get(), (void**)&h->ctl, sizeof(Ctl)))) return st;
     if ((st = dalloc(h.get(), (void**)&h->part, 2 * GMAX * sizeof(double)))) return st;
-    for (double** p : {&h->xs, &h->bs, &h->r, &h->z, &h->p, &h->q})
+    for (double** p : {&h->xs, &h->bs, &h->r, &h->z, &h->p, &h->q, &h->r2, &h->p2})
         if ((st = dalloc(h.get(), (void**)p, N * sizeof(double)))) return st;
     HIPCHK(hipHostMalloc((void**)&h->hctl, sizeof(HostCtl), hipHostMallocMapped | hipHostMallocCoherent));
     std::memset(h->hctl, 0, sizeof(HostCtl));
@@ -1352,6 +1500,10 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms) {
 
 int psc_tune(psc_hier* h, int32_t key, int32_t value) {
     if (!h) return fail(PSC_ERR_ARG, "NULL handle");
+    if (key == PSC_TUNE_FUSED_PCG) {
+        h->fused_pcg = value != 0;
+        return PSC_OK;
+    }
     if (key == PSC_TUNE_GRID_MAX) {
         if (value < NXCD || value > GMAX || value % NXCD) return fail(PSC_ERR_ARG, "grid cap must be a multiple of 8 in [8, 65536]");
         h->gmax = value;

@@ -203,3 +203,21 @@ def test_failure_paths(psc):
     with pytest.raises(psc.PscError) as e:
         psc.Hierarchy(rp, c2, v)
     assert e.value.status == psc.ERR_ARG
+
+
+@pytest.mark.parametrize("case", ["poisson32", "diffusion20_az100", "random_long_rows"])
+def test_fused_and_unfused_pcg_agree(psc, case):
+    rp, c, v = CASES[case]()
+    cm = 40 if case == "random_long_rows" else 200
+    b = P.rhs_from_solution(rp, c, v, P.x_true(len(rp) - 1, 1))
+    out = []
+    for fused in (1, 0):
+        h = psc.Hierarchy(rp, c, v, coarse_max=cm)
+        h.tune(psc.TUNE_FUSED_PCG, fused)
+        x = torch.zeros(len(b), dtype=torch.float64, device="cuda")
+        g = h.pcg(dev(b), x)
+        out.append((g, x.cpu().numpy()))
+    (g1, x1), (g0, x0) = out
+    assert g1["status"] == g0["status"] == psc.OK
+    assert g1["iters"] == g0["iters"] and g1["relres"] <= 1e-6
+    assert np.linalg.norm(x1 - x0) <= 1e-10 * np.linalg.norm(x0)
