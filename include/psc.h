@@ -196,15 +196,21 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
 
 /*
  * Tuning. PSC_TUNE_GRID_MAX caps the number of workgroups of the streaming
- * kernels (multiple of 8, at most 65536; default 4096; invalidates captured
+ * kernels (multiple of 8, at most 65536; default 65536; invalidates captured
  * graphs). PSC_TUNE_FUSED_PCG (default 1) selects the fused PCG iteration:
  * the direction update and the (deferred) x update ride in the SpMV pass,
  * the residual update rides in the level-0 pre-smoothing pass; 0 selects
  * the one-kernel-per-operation sequence. Both give the same iterates up to
- * rounding.
+ * rounding. PSC_TUNE_UNROLL4 (default 0): the FP64 post-smoothing and fused
+ * update kernels gather a 7-point row in two batches of four slots (fewer
+ * registers, more waves) instead of one batch of eight.
  */
 #define PSC_TUNE_GRID_MAX 1
 #define PSC_TUNE_FUSED_PCG 2
+#define PSC_TUNE_UNROLL4 3
+/* PSC_TUNE_BUFLOAD (default 0): the hacked-ELL kernels read the matrix and
+ * gather vectors through buffer descriptors (32-bit offsets). */
+#define PSC_TUNE_BUFLOAD 4
 int psc_tune(psc_hier* h, int32_t key, int32_t value);
 
 void psc_hier_free(psc_hier* h);

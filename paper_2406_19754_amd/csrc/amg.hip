@@ -221,7 +221,30 @@ __device__ void block_partial(double s0, double s1, double* part) {
     }
 }
 
-// Second stage: one workgroup adds the nblk partial pairs in a fixed order
+// Optional middle stage for large grids: workgroup f adds the partial pairs
+// [f*per, (f+1)*per) in order into out[2f], out[2f+1].
+__global__ __launch_bounds__(WG) void k_finish_mid(Red R, int nblk, double* __restrict__ out) {
+    if (skip_red(R)) return;
+    __shared__ double red[2][WG / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int per = (nblk + gridDim.x - 1) / gridDim.x;
+    const int lo = blockIdx.x * per, hi = min(nblk, lo + per);
+    double a = 0.0, b = 0.0;
+    for (int i = lo + threadIdx.x; i < hi; i += WG) {
+        a += R.part[2 * i];
+        b += R.part[2 * i + 1];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) { red[0][w] = a; red[1][w] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        out[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    }
+}
+
+// Last stage: one workgroup adds the nblk partial pairs in a fixed order
 // and runs the finaliser on the control block.
 __global__ __launch_bounds__(WG) void k_finish(Red R, int nblk) {
     if (skip_red(R)) return;
@@ -248,13 +271,36 @@ __global__ __launch_bounds__(WG) void k_finish(Red R, int nblk) {
 // width <= 8 (every stencil slice) issue all value and index loads before
 // the first gather, so a wavefront keeps up to 16 streaming loads and 8
 // gathers in flight; wider slices take the general loop.
-template <typename T, typename G>
+template <typename T, typename G, int U = 8>
 __device__ __forceinline__ T ell_row(const Ell<T>& A, long long s, int lane, G g) {
     const long long o = A.off[s];
     const int w = (int)((A.off[s + 1] - o) >> 6);
     const T* vp = A.val + o + lane;
     const int* cp = A.col + o + lane;
     T acc = T(0);
+    if (U == 4 && w <= 8) {
+        // two batches of four slots: fewer live registers, higher occupancy
+#pragma unroll
+        for (int b0 = 0; b0 < 8; b0 += 4) {
+            T v[4];
+            int c[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                if (b0 + k < w) {
+                    v[k] = ntload(vp + (b0 + k) * SLICE);
+                    c[k] = ntload(cp + (b0 + k) * SLICE);
+                }
+            }
+            T gv[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                if (b0 + k < w) gv[k] = g(c[k]);
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                if (b0 + k < w) acc += v[k] * gv[k];
+        }
+        return acc;
+    }
     if (w <= 8) {
         T v[8];
         int c[8];
@@ -298,6 +344,89 @@ __device__ __forceinline__ T ell_row(const Ell<T>& A, long long s, int lane, G g
     return acc;
 }
 
+// ---- buffer-load path ------------------------------------------------------
+// Raw buffer loads address memory as a scalar descriptor (base, byte size)
+// plus a 32-bit per-lane byte offset: one VGPR per gathered address instead
+// of a 64-bit pointer pair, an immediate offset for the slot stride, and a
+// zero (not a fault) for an offset past the end. Descriptor word 3 for the
+// gfx9 family is 0x00020000; aux bit 1 is the non-temporal hint.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ __forceinline__ rsrc_t brsrc(const void* p, long long bytes) {
+    const long long cap = 0xffffffffll;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)(bytes < cap ? bytes : cap),
+                                             0x00020000);
+}
+template <typename T, int AUX>
+struct BLoad;
+template <int AUX>
+struct BLoad<double, AUX> {
+    static __device__ __forceinline__ double f(rsrc_t r, unsigned off) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, AUX));
+    }
+};
+template <int AUX>
+struct BLoad<float, AUX> {
+    static __device__ __forceinline__ float f(rsrc_t r, unsigned off) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, AUX));
+    }
+};
+template <int AUX>
+struct BLoad<int, AUX> {
+    static __device__ __forceinline__ int f(rsrc_t r, unsigned off) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, AUX);
+    }
+};
+// aux 0: default caching (gathers); aux 2: non-temporal (matrix streams)
+template <typename T, int AUX = 0>
+__device__ __forceinline__ T bload(rsrc_t r, unsigned off) {
+    return BLoad<T, AUX>::f(r, off);
+}
+// gathered vector element: g[c]
+template <typename T>
+struct BVec {
+    rsrc_t r;
+    __device__ __forceinline__ T operator[](int c) const { return bload<T>(r, (unsigned)c * sizeof(T)); }
+};
+template <typename T>
+__device__ __forceinline__ BVec<T> bvec(const T* p, long long n) { return BVec<T>{brsrc(p, n * (long long)sizeof(T))}; }
+
+// ell_row with the slice's values and columns read through per-slice
+// descriptors (s must be wave-uniform).
+template <typename T, typename G>
+__device__ __forceinline__ T ell_row_buf(const Ell<T>& A, long long s, int lane, G g) {
+    const long long o = A.off[s];
+    const int w = (int)((A.off[s + 1] - o) >> 6);
+    const rsrc_t rv = brsrc(A.val + o, (long long)w * SLICE * sizeof(T));
+    const rsrc_t rc = brsrc(A.col + o, (long long)w * SLICE * 4);
+    const unsigned lv = (unsigned)lane * sizeof(T), lc = (unsigned)lane * 4u;
+    T acc = T(0);
+    if (w <= 8) {
+        T v[8];
+        int c[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            if (k < w) {
+                v[k] = bload<T, 2>(rv, lv + k * SLICE * sizeof(T));
+                c[k] = bload<int, 2>(rc, lc + k * SLICE * 4);
+            }
+        }
+        T gv[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (k < w) gv[k] = g(c[k]);
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (k < w) acc += v[k] * gv[k];
+        return acc;
+    }
+    for (int k = 0; k < w; k++)
+        acc += bload<T, 2>(rv, lv + (unsigned)k * SLICE * sizeof(T)) * g(bload<int, 2>(rc, lc + (unsigned)k * SLICE * 4));
+    return acc;
+}
+
+// wave-uniform wave index of this thread within its workgroup
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // Vector range of this workgroup, in whole 512-element units so that the
 // bulk is walked with 16-byte (2 x FP64) loads.
 __device__ __forceinline__ void vchunk_range(long long total, long long& lo, long long& hi) {
@@ -315,15 +444,18 @@ __device__ __forceinline__ void vchunk_range(long long total, long long& lo, lon
 // ---------------------------------------------------------------------------
 
 // y = A x
-template <typename T>
+template <typename T, bool BUF = false>
 __global__ __launch_bounds__(WG) void k_spmv(Ell<T> A, const T* __restrict__ x, T* __restrict__ y,
                                              Gate g) {
     if (gate_skip(g)) return;
     long long lo, hi;
     chunk_range(A.nslices, lo, hi);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const BVec<T> bx = bvec(x, A.ncols);
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        T acc = ell_row(A, s, lane, [&](int c) { return x[c]; });
+        T acc;
+        if constexpr (BUF) acc = ell_row_buf(A, s, lane, [&](int c) { return bx[c]; });
+        else acc = ell_row(A, s, lane, [&](int c) { return x[c]; });
         long long row = s * SLICE + lane;
         if (row < A.nrows) y[row] = acc;
     }
@@ -436,6 +568,7 @@ __global__ __launch_bounds__(WG) void k_pupdate(long long n, double* __restrict_
 // for every gathered neighbour), q = A p_new, the x update deferred from the
 // previous iteration x += alpha_prev p_old, and the partial p_new.q.
 // alpha in the control block still holds alpha_prev here (0 at the start).
+template <bool BUF = false>
 __global__ __launch_bounds__(WG) void k_spmv_pfuse(Ell<double> A, const double* __restrict__ z,
                                                    const double* __restrict__ pold, double* __restrict__ pnew,
                                                    double* __restrict__ q, double* __restrict__ x, Red R) {
@@ -443,10 +576,13 @@ __global__ __launch_bounds__(WG) void k_spmv_pfuse(Ell<double> A, const double* 
     const double beta = R.ctl->beta, alpha_prev = R.ctl->alpha;
     long long lo, hi;
     chunk_range(A.nslices, lo, hi);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const BVec<double> bz = bvec(z, A.ncols), bp = bvec(pold, A.ncols);
     double s0 = 0.0;
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        double acc = ell_row(A, s, lane, [&](int c) { return fma(beta, pold[c], z[c]); });
+        double acc;
+        if constexpr (BUF) acc = ell_row_buf(A, s, lane, [&](int c) { return fma(beta, bp[c], bz[c]); });
+        else acc = ell_row(A, s, lane, [&](int c) { return fma(beta, pold[c], z[c]); });
         long long row = s * SLICE + lane;
         if (row < A.nrows) {
             const double po = pold[row];
@@ -463,6 +599,7 @@ __global__ __launch_bounds__(WG) void k_spmv_pfuse(Ell<double> A, const double* 
 // Fused PCG, second pass: r_new = r_old - alpha q (own row, and recomputed for
 // every gathered neighbour), the level-0 pre-smoothing residual
 // r0 = r_new - A (minv .* r_new), and the partial ||r_new||^2.
+template <int U = 8, bool BUF = false>
 __global__ __launch_bounds__(WG) void k_update_pre(Ell<double> A, const double* __restrict__ minv,
                                                    const double* __restrict__ rold, const double* __restrict__ q,
                                                    double* __restrict__ rnew, double* __restrict__ r0, Red R) {
@@ -470,10 +607,17 @@ __global__ __launch_bounds__(WG) void k_update_pre(Ell<double> A, const double* 
     const double nalpha = -R.ctl->alpha;
     long long lo, hi;
     chunk_range(A.nslices, lo, hi);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const BVec<double> bm = bvec(minv, A.ncols), bq = bvec(q, A.ncols), br = bvec(rold, A.ncols);
     double s0 = 0.0;
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        double acc = ell_row(A, s, lane, [&](int c) { return minv[c] * fma(nalpha, q[c], rold[c]); });
+        double acc;
+        if constexpr (BUF) {
+            acc = ell_row_buf(A, s, lane, [&](int c) { return bm[c] * fma(nalpha, bq[c], br[c]); });
+        } else {
+            auto g = [&](int c) { return minv[c] * fma(nalpha, q[c], rold[c]); };
+            acc = ell_row<double, decltype(g), U>(A, s, lane, g);
+        }
         long long row = s * SLICE + lane;
         if (row < A.nrows) {
             const double rn = fma(nalpha, q[row], rold[row]);
@@ -546,15 +690,19 @@ __global__ void k_set_net_on(Ctl* c) {
 
 // Pre-smoothing from a zero guess and its residual, one pass:
 //   r_i = b_i - sum_j a_ij (minv_j b_j)       (the iterate M^-1 b is not stored)
-template <typename T, typename TB>
+template <typename T, typename TB, bool BUF = false>
 __global__ __launch_bounds__(WG) void k_pre(Ell<T> A, const T* __restrict__ minv,
                                             const TB* __restrict__ b, T* __restrict__ r, Gate g) {
     if (gate_skip(g)) return;
     long long lo, hi;
     chunk_range(A.nslices, lo, hi);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const BVec<T> bm = bvec(minv, A.ncols);
+    const BVec<TB> bb = bvec(b, A.ncols);
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        T acc = ell_row(A, s, lane, [&](int c) { return minv[c] * (T)b[c]; });
+        T acc;
+        if constexpr (BUF) acc = ell_row_buf(A, s, lane, [&](int c) { return bm[c] * (T)bb[c]; });
+        else acc = ell_row(A, s, lane, [&](int c) { return minv[c] * (T)b[c]; });
         long long row = s * SLICE + lane;
         if (row < A.nrows) r[row] = (T)b[row] - acc;
     }
@@ -564,19 +712,24 @@ __global__ __launch_bounds__(WG) void k_pre(Ell<T> A, const T* __restrict__ minv
 //   xs_j = minv_j b_j + p_j xc[agg_j]   (pre-smoothed iterate + coarse correction)
 //   x_i  = xs_i + minv_i (b_i - sum_j a_ij xs_j)
 // With R.fin != FIN_NONE, also the partial sum of x_i * d_i.
-template <typename T, typename TB, typename TX>
+template <typename T, typename TB, typename TX, int U = 8, bool BUF = false>
 __global__ __launch_bounds__(WG) void k_post(Ell<T> A, const T* __restrict__ minv,
                                              const TB* __restrict__ b, const int* __restrict__ agg,
-                                             const T* __restrict__ pv, const T* __restrict__ xc,
+                                             const T* __restrict__ pv, const T* __restrict__ xc, long long nc,
                                              TX* __restrict__ x, const double* __restrict__ d, Red R) {
     if (skip_red(R)) return;
     long long lo, hi;
     chunk_range(A.nslices, lo, hi);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const BVec<T> bm = bvec(minv, A.ncols), bp = bvec(pv, A.ncols), bx = bvec(xc, nc);
+    const BVec<TB> bb = bvec(b, A.ncols);
+    const BVec<int> ba = bvec(agg, A.ncols);
     double s0 = 0.0;
+    auto xs = [&](int c) { return minv[c] * (T)b[c] + pv[c] * xc[agg[c]]; };
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        auto xs = [&](int c) { return minv[c] * (T)b[c] + pv[c] * xc[agg[c]]; };
-        T acc = ell_row(A, s, lane, xs);
+        T acc;
+        if constexpr (BUF) acc = ell_row_buf(A, s, lane, [&](int c) { return bm[c] * (T)bb[c] + bp[c] * bx[ba[c]]; });
+        else acc = ell_row<T, decltype(xs), U>(A, s, lane, xs);
         long long row = s * SLICE + lane;
         if (row < A.nrows) {
             int i = (int)row;
@@ -621,9 +774,9 @@ struct DevEll {
     T* val = nullptr;
     int* col = nullptr;
     float* val32 = nullptr;
-    long long nrows = 0, nslices = 0, slots = 0;
-    Ell<T> view() const { return Ell<T>{off, val, col, nrows, nslices}; }
-    Ell<float> view32() const { return Ell<float>{off, val32, col, nrows, nslices}; }
+    long long nrows = 0, nslices = 0, slots = 0, ncols = 0;
+    Ell<T> view() const { return Ell<T>{off, val, col, nrows, nslices, ncols}; }
+    Ell<float> view32() const { return Ell<float>{off, val32, col, nrows, nslices, ncols}; }
 };
 
 struct DevLevel {
@@ -656,13 +809,16 @@ struct psc_hier {
     psc::HostCtl* hctl = nullptr;
     psc::HostCtl* hctl_dev = nullptr;
     double* part = nullptr;
+    double* part2 = nullptr;              // middle-stage partials (2 x 256 doubles)
     double *xs = nullptr, *bs = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
     double *r2 = nullptr, *p2 = nullptr;  // second buffers of the fused PCG iteration
     bool fused_pcg = true;                // PCG form: fused two-pass iteration
+    bool unroll4 = false;                 // gather in batches of 4 in the FP64 post / update+pre kernels
+    bool bufload = false;                 // matrix streams and gathers through buffer descriptors
     std::vector<void*> allocs;
     int64_t device_bytes = 0;
     double setup_seconds = 0.0;
-    int gmax = 4096;                      // workgroup cap of the streaming kernels
+    int gmax = psc::GMAX;                 // workgroup cap of the streaming kernels
     // captured iterations, one per (form, network, network generation)
     std::vector<psc::GraphEntry> graphs;
     // timing
@@ -707,13 +863,14 @@ static int upload(psc_hier* h, T** d, const T* src, size_t count) {
     return PSC_OK;
 }
 
-static int upload_ell(psc_hier* h, DevEll<double>& E, int64_t nrows, const int32_t* rp,
+static int upload_ell(psc_hier* h, DevEll<double>& E, int64_t nrows, int64_t ncols, const int32_t* rp,
                       const int32_t* ci, const double* v, bool fp32) {
     std::vector<long long> off;
     std::vector<double> val;
     std::vector<int> col;
     pack_ell(nrows, rp, ci, v, off, val, col);
     E.nrows = nrows;
+    E.ncols = ncols;
     E.nslices = (long long)off.size() - 1;
     E.slots = off.back();
     int st;
@@ -787,6 +944,33 @@ static void timing_collect(psc_hier* h) {
 }
 
 // ---------------------------------------------------------------------------
+// launch helpers (variant selection)
+// ---------------------------------------------------------------------------
+
+template <typename T, typename TB>
+static void launch_pre(psc_hier* h, const Ell<T>& A, const T* minv, const TB* b, T* r, Gate g) {
+    const int gr = grid_ell(h, A.nslices);
+    if (h->bufload) k_pre<T, TB, true><<<gr, WG, 0, h->stream>>>(A, minv, b, r, g);
+    else k_pre<T, TB, false><<<gr, WG, 0, h->stream>>>(A, minv, b, r, g);
+}
+
+template <typename T>
+static void launch_spmv(psc_hier* h, const Ell<T>& A, const T* x, T* y, Gate g) {
+    const int gr = grid_ell(h, A.nslices);
+    if (h->bufload) k_spmv<T, true><<<gr, WG, 0, h->stream>>>(A, x, y, g);
+    else k_spmv<T, false><<<gr, WG, 0, h->stream>>>(A, x, y, g);
+}
+
+template <typename T, typename TB, typename TX>
+static void launch_post(psc_hier* h, const Ell<T>& A, const T* minv, const TB* b, const int* agg, const T* pv,
+                        const T* xc, long long nc, TX* x, const double* d, const Red& R) {
+    const int gr = grid_ell(h, A.nslices);
+    if (h->bufload) k_post<T, TB, TX, 8, true><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
+    else if (h->unroll4) k_post<T, TB, TX, 4, false><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
+    else k_post<T, TB, TX, 8, false><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
+}
+
+// ---------------------------------------------------------------------------
 // V-cycle
 // ---------------------------------------------------------------------------
 
@@ -794,9 +978,20 @@ static Red red_of(psc_hier* h, int fin, int gmode = GATE_DONE) {
     return Red{h->part, h->ctl, h->hctl_dev, fin, gmode};
 }
 
-// second reduction stage for a kernel launched with `grid` workgroups
+// Remaining reduction stages for a kernel launched with `grid` workgroups:
+// up to 1024 partial pairs are added by one workgroup; more go through a
+// middle stage of up to 256 workgroups first (fixed order either way).
 static void finish(psc_hier* h, const Red& R, int grid) {
-    if (R.fin != FIN_NONE) k_finish<<<1, WG, 0, h->stream>>>(R, grid);
+    if (R.fin == FIN_NONE) return;
+    if (grid <= 1024) {
+        k_finish<<<1, WG, 0, h->stream>>>(R, grid);
+        return;
+    }
+    const int mid = std::min(256, (grid + WG - 1) / WG);
+    k_finish_mid<<<mid, WG, 0, h->stream>>>(R, grid, h->part2);
+    Red R2 = R;
+    R2.part = h->part2;
+    k_finish<<<1, WG, 0, h->stream>>>(R2, mid);
 }
 
 // z = B r on level 0. prec: PSC_FP64 / PSC_FP32. fin/d: optional fused dot
@@ -825,11 +1020,11 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
             const double* b = l == 0 ? r0 : V.b;
             if (!(l == 0 && skip_pre0)) {
                 TimeScope t(h, l == 0 ? 2 : 7);
-                k_pre<double, double><<<grid_ell(h, V.A.nslices), WG, 0, st>>>(V.A.view(), V.minv, b, V.r, g);
+                launch_pre(h, V.A.view(), V.minv, b, V.r, g);
             }
             {
                 TimeScope t(h, l == 0 ? 3 : 7);
-                k_spmv<double><<<grid_ell(h, V.R.nslices), WG, 0, st>>>(V.R.view(), V.r, h->lev[l + 1].b, g);
+                launch_spmv(h, V.R.view(), (const double*)V.r, h->lev[l + 1].b, g);
             }
         }
         DevLevel& C = h->lev[L - 1];
@@ -843,9 +1038,8 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
             double* x = l == 0 ? z0 : V.x;
             {
                 TimeScope t(h, l == 0 ? 4 : 7);
-                k_post<double, double, double><<<grid_ell(h, V.A.nslices), WG, 0, st>>>(
-                    V.A.view(), V.minv, b, V.agg, V.pval, h->lev[l + 1].x, x, l == 0 ? d : nullptr,
-                    l == 0 ? R : R0);
+                launch_post(h, V.A.view(), (const double*)V.minv, b, V.agg, (const double*)V.pval,
+                            (const double*)h->lev[l + 1].x, V.nc, x, l == 0 ? d : nullptr, l == 0 ? R : R0);
             }
             if (l == 0) finish(h, R, grid_ell(h, V.A.nslices));
         }
@@ -854,14 +1048,12 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
             DevLevel& V = h->lev[l];
             {
                 TimeScope t(h, l == 0 ? 2 : 7);
-                if (l == 0)
-                    k_pre<float, double><<<grid_ell(h, V.A.nslices), WG, 0, st>>>(V.A.view32(), V.minv32, r0, V.r32, g);
-                else
-                    k_pre<float, float><<<grid_ell(h, V.A.nslices), WG, 0, st>>>(V.A.view32(), V.minv32, V.b32, V.r32, g);
+                if (l == 0) launch_pre(h, V.A.view32(), (const float*)V.minv32, r0, V.r32, g);
+                else launch_pre(h, V.A.view32(), (const float*)V.minv32, (const float*)V.b32, V.r32, g);
             }
             {
                 TimeScope t(h, l == 0 ? 3 : 7);
-                k_spmv<float><<<grid_ell(h, V.R.nslices), WG, 0, st>>>(V.R.view32(), V.r32, h->lev[l + 1].b32, g);
+                launch_spmv(h, V.R.view32(), (const float*)V.r32, h->lev[l + 1].b32, g);
             }
         }
         DevLevel& C = h->lev[L - 1];
@@ -874,14 +1066,15 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
             if (l == 0) {
                 {
                     TimeScope t(h, 4);
-                    k_post<float, double, double><<<grid_ell(h, V.A.nslices), WG, 0, st>>>(
-                        V.A.view32(), V.minv32, r0, V.agg, V.pval32, h->lev[1].x32, z0, d, R);
+                    launch_post(h, V.A.view32(), (const float*)V.minv32, r0, V.agg, (const float*)V.pval32,
+                                (const float*)h->lev[1].x32, V.nc, z0, d, R);
                 }
                 finish(h, R, grid_ell(h, V.A.nslices));
             } else {
                 TimeScope t(h, 7);
-                k_post<float, float, float><<<grid_ell(h, V.A.nslices), WG, 0, st>>>(
-                    V.A.view32(), V.minv32, V.b32, V.agg, V.pval32, h->lev[l + 1].x32, V.x32, nullptr, R0);
+                launch_post(h, V.A.view32(), (const float*)V.minv32, (const float*)V.b32, V.agg,
+                            (const float*)V.pval32, (const float*)h->lev[l + 1].x32, V.nc, V.x32,
+                            (const double*)nullptr, R0);
             }
         }
     }
@@ -941,12 +1134,20 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             double* rnew = parity ? h->r : h->r2;
             {
                 TimeScope t(h, 0);
-                k_spmv_pfuse<<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, red_of(h, FIN_ALPHA_PCG));
+                if (h->bufload)
+                    k_spmv_pfuse<true><<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, red_of(h, FIN_ALPHA_PCG));
+                else
+                    k_spmv_pfuse<false><<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, red_of(h, FIN_ALPHA_PCG));
             }
             finish(h, red_of(h, FIN_ALPHA_PCG), ge);
             {
                 TimeScope t(h, 2);
-                k_update_pre<<<ge, WG, 0, st>>>(L0.A.view(), L0.minv, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_PCG));
+                if (h->bufload)
+                    k_update_pre<8, true><<<ge, WG, 0, st>>>(L0.A.view(), L0.minv, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_PCG));
+                else if (h->unroll4)
+                    k_update_pre<4><<<ge, WG, 0, st>>>(L0.A.view(), L0.minv, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_PCG));
+                else
+                    k_update_pre<8><<<ge, WG, 0, st>>>(L0.A.view(), L0.minv, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_PCG));
             }
             finish(h, red_of(h, FIN_UPDATE_PCG), ge);
             vcycle(h, PSC_FP64, rnew, h->z, FIN_RHO, rnew, gd, true);
@@ -1298,7 +1499,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
         D.n = H.n;
         D.nc = H.nc;
         D.nnz = H.rp[H.n];
-        if ((st = upload_ell(h.get(), D.A, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32))) return st;
+        if ((st = upload_ell(h.get(), D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32))) return st;
         if ((st = upload(h.get(), &D.minv, H.minv.data(), H.n))) return st;
         if (f32) {
             auto m32 = to32(H.minv);
@@ -1332,7 +1533,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
                 rci[o] = (int32_t)i;
                 rv[o] = H.p[i];
             }
-            if ((st = upload_ell(h.get(), D.R, H.nc, rrp.data(), rci.data(), rv.data(), f32))) return st;
+            if ((st = upload_ell(h.get(), D.R, H.nc, H.n, rrp.data(), rci.data(), rv.data(), f32))) return st;
         }
     }
     // coarsest inverse, stored transposed for coalesced reads
@@ -1348,6 +1549,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     const int64_t N = n;
     if ((st = dalloc(h.get(), (void**)&h->ctl, sizeof(Ctl)))) return st;
     if ((st = dalloc(h.get(), (void**)&h->part, 2 * GMAX * sizeof(double)))) return st;
+    if ((st = dalloc(h.get(), (void**)&h->part2, 2 * 256 * sizeof(double)))) return st;
     for (double** p : {&h->xs, &h->bs, &h->r, &h->z, &h->p, &h->q, &h->r2, &h->p2})
         if ((st = dalloc(h.get(), (void**)p, N * sizeof(double)))) return st;
     HIPCHK(hipHostMalloc((void**)&h->hctl, sizeof(HostCtl), hipHostMallocMapped | hipHostMallocCoherent));
@@ -1470,9 +1672,9 @@ int psc_spmv(psc_hier* h, int32_t l, int32_t prec, const void* x, void* y) {
     {
         TimeScope t(h, l == 0 ? 0 : 7);
         if (prec == PSC_FP64)
-            k_spmv<double><<<grid_ell(h, D.A.nslices), WG, 0, h->stream>>>(D.A.view(), (const double*)x, (double*)y, Gate{nullptr, GATE_NONE});
+            launch_spmv(h, D.A.view(), (const double*)x, (double*)y, Gate{nullptr, GATE_NONE});
         else
-            k_spmv<float><<<grid_ell(h, D.A.nslices), WG, 0, h->stream>>>(D.A.view32(), (const float*)x, (float*)y, Gate{nullptr, GATE_NONE});
+            launch_spmv(h, D.A.view32(), (const float*)x, (float*)y, Gate{nullptr, GATE_NONE});
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -1500,8 +1702,19 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms) {
 
 int psc_tune(psc_hier* h, int32_t key, int32_t value) {
     if (!h) return fail(PSC_ERR_ARG, "NULL handle");
+    if (key == PSC_TUNE_BUFLOAD) {
+        h->bufload = value != 0;
+        drop_graphs(h);
+        return PSC_OK;
+    }
+    if (key == PSC_TUNE_UNROLL4) {
+        h->unroll4 = value != 0;
+        drop_graphs(h);
+        return PSC_OK;
+    }
     if (key == PSC_TUNE_FUSED_PCG) {
         h->fused_pcg = value != 0;
+        drop_graphs(h);
         return PSC_OK;
     }
     if (key == PSC_TUNE_GRID_MAX) {

@@ -49,6 +49,7 @@ struct Ell {
     const int* col;
     long long nrows;
     long long nslices;
+    long long ncols;
 };
 
 }  // namespace psc

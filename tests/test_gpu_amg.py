@@ -221,3 +221,35 @@ def test_fused_and_unfused_pcg_agree(psc, case):
     assert g1["status"] == g0["status"] == psc.OK
     assert g1["iters"] == g0["iters"] and g1["relres"] <= 1e-6
     assert np.linalg.norm(x1 - x0) <= 1e-10 * np.linalg.norm(x0)
+
+
+@pytest.mark.parametrize("knob", ["bufload", "unroll4", "grid256"])
+@pytest.mark.parametrize("case", ["poisson13", "random_long_rows", "diffusion20_az100"])
+def test_kernel_variants_match_oracle(psc, case, knob):
+    rp, c, v = CASES[case]()
+    cm = 40 if case == "random_long_rows" else 200
+    h = psc.Hierarchy(rp, c, v, coarse_max=cm, build_fp32=True)
+    if knob == "bufload":
+        h.tune(psc.TUNE_BUFLOAD, 1)
+    elif knob == "unroll4":
+        h.tune(psc.TUNE_UNROLL4, 1)
+    else:
+        h.tune(psc.TUNE_GRID_MAX, 256)               # several slices per wavefront
+    o = oracle.Hierarchy(rp, c, v, coarse_max=cm)
+    n = len(rp) - 1
+    x = np.random.default_rng(3).standard_normal(n)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.spmv(dev(x), y)
+    ref = oracle.spmv(rp, c, v, x)
+    assert np.abs(y.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
+    h.vcycle(dev(x), y)
+    ref = o.vcycle(x)
+    assert np.linalg.norm(y.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+    h.vcycle(dev(x), y, prec=psc.FP32)
+    ref = o.vcycle32(x)
+    assert np.linalg.norm(y.cpu().numpy() - ref) <= 1e-5 * np.linalg.norm(ref)
+    b = P.rhs_uniform(n, 4)
+    xg = torch.zeros(n, dtype=torch.float64, device="cuda")
+    g = h.pcg(dev(b), xg)
+    r = o.pcg(b)
+    assert abs(g["iters"] - r["iters"]) <= 1 and g["relres"] <= 1e-6
