@@ -113,7 +113,8 @@ def main():
     ap.add_argument("--grid-max", type=int, default=0, help="workgroup cap of the streaming kernels")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--unfused", action="store_true", help="one kernel per CG operation instead of the fused PCG iteration")
-    ap.add_argument("--train-epochs", type=int, default=2)
+    ap.add_argument("--train-epochs", type=int, default=6)
+    ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--crops", type=int, default=20000)
     ap.add_argument("--save-weights", default="")
     ap.add_argument("--profile-mix", action="store_true",
@@ -328,7 +329,8 @@ def learned(args):
     log(f"collected {r.shape[0]} crops in {t_collect:.1f}s")
     net = psc.Net(P.net_init(0))
     t0 = time.time()
-    losses, v0, v1 = LR.train(net, r, z, epochs=args.train_epochs, batch=16, margin=3, lr=1e-3, seed=0, log=log)
+    losses, v0, v1 = LR.train(net, r, z, epochs=args.train_epochs, batch=16, margin=3, lr=args.lr, seed=0, log=log,
+                              lr_min=args.lr * 0.02)
     t_train = time.time() - t0
     log(f"trained {len(losses)} steps in {t_train:.1f}s; validation MSE {v0:.4e} -> {v1:.4e}")
     if args.save_weights:
@@ -338,6 +340,20 @@ def learned(args):
     del r, z
     torch.cuda.empty_cache()
     ev = LR.evaluate(h, net, n, range(1001, 1009), kinds=("uniform",), reps=3)
+    # cost of one network application vs one V-cycle on the same grid
+    rr = torch.from_numpy(P.rhs_uniform(n ** 3, 5)).cuda()
+    zz = torch.empty_like(rr)
+    for fn in (lambda: net.apply(rr, zz, (n, n, n)), lambda: h.vcycle(rr, zz)):
+        fn()
+    t_net = t_vc = 0.0
+    for name in ("net", "vc"):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(20):
+            net.apply(rr, zz, (n, n, n)) if name == "net" else h.vcycle(rr, zz)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) * 1e3 / 20
+        t_net, t_vc = (dt, t_vc) if name == "net" else (t_net, dt)
     untrained = psc.Net(P.net_init(0))
     untrained.set_grid((n, n, n))
     ev_u = LR.evaluate(h, untrained, n, range(1001, 1003), kinds=("uniform",), reps=1)
@@ -352,6 +368,7 @@ def learned(args):
         "learned_relres": max(e["learned"]["relres"] for e in ev),
         "learned_fallbacks": [e["learned"]["fallbacks"] for e in ev],
         "untrained_iters": [e["learned"]["iters"] for e in ev_u],
+        "net_apply_ms": t_net, "vcycle_ms": t_vc,
     }
     summary["speedup_learned_vs_pcg"] = summary["pcg_ms"] / summary["learned_ms"]
     print(json.dumps(summary), flush=True)

@@ -197,11 +197,11 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
 /*
  * Tuning. PSC_TUNE_GRID_MAX caps the number of workgroups of the streaming
  * kernels (multiple of 8, at most 65536; default 65536; invalidates captured
- * graphs). PSC_TUNE_FUSED_PCG (default 1) selects the fused PCG iteration:
- * the direction update and the (deferred) x update ride in the SpMV pass,
- * the residual update rides in the level-0 pre-smoothing pass; 0 selects
- * the one-kernel-per-operation sequence. Both give the same iterates up to
- * rounding. PSC_TUNE_UNROLL4 (default 0): the FP64 post-smoothing and fused
+ * graphs). PSC_TUNE_FUSED_PCG (default 1) selects the fused CG / FCG(1)
+ * iteration (V-cycle-only forms): the direction update and the (deferred)
+ * x update ride in the SpMV pass, the residual update rides in the level-0
+ * pre-smoothing pass; 0 selects the one-kernel-per-operation sequence. Both
+ * give the same iterates up to rounding. PSC_TUNE_UNROLL4 (default 0): the FP64 post-smoothing and fused
  * update kernels gather a 7-point row in two batches of four slots (fewer
  * registers, more waves) instead of one batch of eight.
  */

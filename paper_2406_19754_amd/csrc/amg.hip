@@ -147,6 +147,7 @@ __device__ void finalize(int fin, double s0, double s1, Ctl* c, HostCtl* hc) {
         c->rr_old = c->rr;
         c->rr = s0;
         c->iter += 1;
+        c->redo = 0;
         if (c->use_net && sqrt(s0) > 0.9 * sqrt(c->rr_old)) c->net_on = 0;   // network stagnates
         if (isnan(s0)) { c->status = PSC_ERR_NAN; c->done = 1; }
         else if (sqrt(s0) <= c->rtol * sqrt(c->nb2)) {
@@ -176,6 +177,7 @@ __device__ void finalize(int fin, double s0, double s1, Ctl* c, HostCtl* hc) {
         else {
             c->have_prev = 0;
             c->rr = s0;
+            c->redo = 1;
             if (c->iter >= c->maxit) { c->status = PSC_NOCONV; c->done = 1; }
         }
         break;
@@ -629,6 +631,92 @@ __global__ __launch_bounds__(WG) void k_update_pre(Ell<double> A, const double* 
     block_partial(s0, 0.0, R.part);
 }
 
+// Fused FCG(1), first pass: p_new = z - beta p_old (p_new = z without a
+// previous direction), q = A p_new, the deferred x += alpha_prev p_old, and
+// the partials (p_new.q, p_new.r_old).
+template <bool BUF = false>
+__global__ __launch_bounds__(WG) void k_spmv_pfuse_fcg(Ell<double> A, const double* __restrict__ z,
+                                                       const double* __restrict__ pold, double* __restrict__ pnew,
+                                                       double* __restrict__ q, double* __restrict__ x,
+                                                       const double* __restrict__ rold, Red R) {
+    if (skip_red(R)) return;
+    const double nb = R.ctl->have_prev ? -R.ctl->beta : 0.0, alpha_prev = R.ctl->alpha;
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const BVec<double> bz = bvec(z, A.ncols), bp = bvec(pold, A.ncols);
+    double s0 = 0.0, s1 = 0.0;
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        double acc;
+        if constexpr (BUF) acc = ell_row_buf(A, s, lane, [&](int c) { return fma(nb, bp[c], bz[c]); });
+        else acc = ell_row(A, s, lane, [&](int c) { return fma(nb, pold[c], z[c]); });
+        long long row = s * SLICE + lane;
+        if (row < A.nrows) {
+            const double po = pold[row];
+            const double pn = fma(nb, po, z[row]);
+            pnew[row] = pn;
+            q[row] = acc;
+            x[row] = fma(alpha_prev, po, x[row]);
+            s0 += pn * acc;
+            s1 += pn * rold[row];
+        }
+    }
+    block_partial(s0, s1, R.part);
+}
+
+// Fused update + level-0 pre-smoothing in the V-cycle's precision T:
+// r_new = r_old - alpha q (FP64), r0 = (T)r_new - A_T ((T)minv .* (T)r_new).
+template <typename T, bool BUF = false>
+__global__ __launch_bounds__(WG) void k_update_pre_t(Ell<T> A, const T* __restrict__ minv,
+                                                     const double* __restrict__ rold, const double* __restrict__ q,
+                                                     double* __restrict__ rnew, T* __restrict__ r0, Red R) {
+    if (skip_red(R)) return;
+    const double nalpha = -R.ctl->alpha;
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const BVec<T> bm = bvec(minv, A.ncols);
+    const BVec<double> bq = bvec(q, A.ncols), br = bvec(rold, A.ncols);
+    double s0 = 0.0;
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        T acc;
+        if constexpr (BUF) acc = ell_row_buf(A, s, lane, [&](int c) { return bm[c] * (T)fma(nalpha, bq[c], br[c]); });
+        else acc = ell_row(A, s, lane, [&](int c) { return minv[c] * (T)fma(nalpha, q[c], rold[c]); });
+        long long row = s * SLICE + lane;
+        if (row < A.nrows) {
+            const double rn = fma(nalpha, q[row], rold[row]);
+            rnew[row] = rn;
+            r0[row] = (T)rn - acc;
+            s0 += rn * rn;
+        }
+    }
+    block_partial(s0, 0.0, R.part);
+}
+
+// Fused FCG true residual (only when the recursive test passed): x lags by
+// its last update, so r = b - A (x + alpha p) with the sum formed for every
+// gathered neighbour; the partial ||r||^2 feeds FIN_TRUE.
+__global__ __launch_bounds__(WG) void k_resid_lag(Ell<double> A, const double* __restrict__ b,
+                                                  const double* __restrict__ x, const double* __restrict__ p,
+                                                  double* __restrict__ r, Red R) {
+    if (skip_red(R) || !R.ctl->check) return;
+    const double alpha = R.ctl->alpha;
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    double s0 = 0.0;
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        double acc = ell_row(A, s, lane, [&](int c) { return fma(alpha, p[c], x[c]); });
+        long long row = s * SLICE + lane;
+        if (row < A.nrows) {
+            const double ri = b[row] - acc;
+            r[row] = ri;
+            s0 += ri * ri;
+        }
+    }
+    block_partial(s0, 0.0, R.part);
+}
+
 // x += alpha p once the fused iteration has stopped (its last x update is deferred).
 __global__ __launch_bounds__(WG) void k_final_axpy(long long n, double* __restrict__ x, const double* __restrict__ p,
                                                    const Ctl* ctl) {
@@ -680,6 +768,7 @@ __global__ void k_ctl_init(Ctl* c, HostCtl* hc, double rtol, int maxit, int form
         c->use_net = 0;
         c->fallbacks = 0;
         c->form = form;
+        c->redo = 0;
         publish(c, hc);
     }
 }
@@ -1046,7 +1135,7 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
     } else {
         for (int l = 0; l < L - 1; l++) {
             DevLevel& V = h->lev[l];
-            {
+            if (!(l == 0 && skip_pre0)) {
                 TimeScope t(h, l == 0 ? 2 : 7);
                 if (l == 0) launch_pre(h, V.A.view32(), (const float*)V.minv32, r0, V.r32, g);
                 else launch_pre(h, V.A.view32(), (const float*)V.minv32, (const float*)V.b32, V.r32, g);
@@ -1089,9 +1178,12 @@ static const int RING = 8;
 
 // forms: 0 PCG + FP64 V-cycle; 1 FCG(1) + FP64 V-cycle; 2 FCG(1) + FP32
 // V-cycle; 3 / 4: forms 1 / 2 with the learned network on odd iterations.
-static const int FORM_FUSED = 5;   // PCG, fused two-pass iteration, issued two iterations at a time
+static const int FORM_FUSED = 5;     // PCG, fused two-pass iteration, issued two iterations at a time
+static const int FORM_FFUSED64 = 6;  // FCG(1) + FP64 V-cycle, fused, two iterations at a time
+static const int FORM_FFUSED32 = 7;  // FCG(1) + FP32 V-cycle, fused, two iterations at a time
 static inline bool form_net(int form) { return form == 3 || form == 4; }
-static inline int form_prec(int form) { return (form == 2 || form == 4) ? PSC_FP32 : PSC_FP64; }
+static inline bool form_fused(int form) { return form >= FORM_FUSED; }
+static inline int form_prec(int form) { return (form == 2 || form == 4 || form == FORM_FFUSED32) ? PSC_FP32 : PSC_FP64; }
 
 __global__ void k_iter_begin(Ctl* c, HostCtl* hc, int has_net) {
     if (threadIdx.x != 0 || c->done) return;
@@ -1151,6 +1243,46 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             }
             finish(h, red_of(h, FIN_UPDATE_PCG), ge);
             vcycle(h, PSC_FP64, rnew, h->z, FIN_RHO, rnew, gd, true);
+        }
+        return PSC_OK;
+    }
+    if (form == FORM_FFUSED64 || form == FORM_FFUSED32) {
+        const bool f32 = form == FORM_FFUSED32;
+        for (int parity = 0; parity < 2; parity++) {
+            double* pold = parity ? h->p2 : h->p;
+            double* pnew = parity ? h->p : h->p2;
+            double* rold = parity ? h->r2 : h->r;
+            double* rnew = parity ? h->r : h->r2;
+            {
+                TimeScope t(h, 0);
+                if (h->bufload)
+                    k_spmv_pfuse_fcg<true><<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, rold, red_of(h, FIN_ALPHA_FCG));
+                else
+                    k_spmv_pfuse_fcg<false><<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, rold, red_of(h, FIN_ALPHA_FCG));
+            }
+            finish(h, red_of(h, FIN_ALPHA_FCG), ge);
+            {
+                TimeScope t(h, 2);
+                if (f32) {
+                    if (h->bufload)
+                        k_update_pre_t<float, true><<<ge, WG, 0, st>>>(L0.A.view32(), L0.minv32, rold, h->q, rnew, L0.r32, red_of(h, FIN_UPDATE_FCG));
+                    else
+                        k_update_pre_t<float, false><<<ge, WG, 0, st>>>(L0.A.view32(), L0.minv32, rold, h->q, rnew, L0.r32, red_of(h, FIN_UPDATE_FCG));
+                } else {
+                    if (h->bufload)
+                        k_update_pre_t<double, true><<<ge, WG, 0, st>>>(L0.A.view(), L0.minv, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_FCG));
+                    else
+                        k_update_pre_t<double, false><<<ge, WG, 0, st>>>(L0.A.view(), L0.minv, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_FCG));
+                }
+            }
+            finish(h, red_of(h, FIN_UPDATE_FCG), ge);
+            k_resid_lag<<<ge, WG, 0, st>>>(L0.A.view(), h->bs, h->xs, pnew, rnew, red_of(h, FIN_TRUE));
+            finish(h, red_of(h, FIN_TRUE), ge);
+            // after a residual replacement, redo the level-0 pre-smoothing from the true residual
+            const Gate gr{h->ctl, GATE_REDO};
+            if (f32) launch_pre(h, L0.A.view32(), (const float*)L0.minv32, (const double*)rnew, L0.r32, gr);
+            else launch_pre(h, L0.A.view(), (const double*)L0.minv, (const double*)rnew, L0.r, gr);
+            vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, gd, true);
         }
         return PSC_OK;
     }
@@ -1277,13 +1409,17 @@ static int solve_impl(psc_hier* h, int form, psc_net* net, const double* b_dev, 
         return PSC_OK;
     }
     const bool use_graph = h->opts.use_graph && !h->timing;
-    const bool fused = form == 0 && h->fused_pcg && h->lev.size() > 1;
-    if (fused) form = FORM_FUSED;
+    const bool fused = (form == 0 || form == 1 || form == 2) && h->fused_pcg && h->lev.size() > 1;
+    if (fused) form = form == 0 ? FORM_FUSED : (form == 1 ? FORM_FFUSED64 : FORM_FFUSED32);
     if (!c.done) {
         const Gate gd{h->ctl, GATE_DONE};
-        if (fused) {
+        if (form == FORM_FUSED) {
             vcycle(h, PSC_FP64, h->r, h->z, FIN_RHO_INIT, h->r, gd);
             k_fill<double><<<gv, WG, 0, st>>>(n, h->p, 0.0);   // p_old of the first iteration (beta = 0)
+        } else if (fused) {
+            k_fill<double><<<gv, WG, 0, st>>>(n, h->q, 0.0);
+            k_fill<double><<<gv, WG, 0, st>>>(n, h->p, 0.0);
+            vcycle(h, form_prec(form), h->r, h->z, FIN_BETA_FCG, h->q, gd);   // z = B r0, beta = 0
         } else if (form == 0) {
             vcycle(h, PSC_FP64, h->r, h->z, FIN_RHO_INIT, h->r, gd);
             k_copy<double, double><<<gv, WG, 0, st>>>(n, h->p, h->z, gd);

@@ -17,12 +17,14 @@ struct Ctl {
     double rtol, nb2, rr, rr_old, rho, alpha, beta, pq, pr, zq, zr, pq_prev, out0, out1;
     int done, iter, status, maxit;
     int check, have_prev, net_on, use_net, fallbacks, form;
+    int redo;      // fused FCG: the residual was replaced, redo the level-0 pre-smoothing
+    int pad_;
 };
 
 // Which kernels of an iteration run: GATE_NONE always; GATE_DONE until the
 // solve is over; GATE_NET only on a network step; GATE_VC only on a V-cycle
 // step (the choice is made on the device, see ctl->use_net).
-enum GateMode { GATE_NONE = 0, GATE_DONE = 1, GATE_NET = 2, GATE_VC = 3 };
+enum GateMode { GATE_NONE = 0, GATE_DONE = 1, GATE_NET = 2, GATE_VC = 3, GATE_REDO = 4 };
 struct Gate {
     const Ctl* ctl;
     int mode;
@@ -32,6 +34,7 @@ __device__ __forceinline__ bool gate_skip(const Gate& g) {
     if (g.ctl->done) return true;
     if (g.mode == GATE_NET) return !g.ctl->use_net;
     if (g.mode == GATE_VC) return g.ctl->use_net != 0;
+    if (g.mode == GATE_REDO) return !g.ctl->redo;
     return false;
 }
 

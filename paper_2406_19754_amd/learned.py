@@ -40,8 +40,14 @@ def collect_pairs(h, n, uniform_seeds, bump_seeds, crops, crop=40, seed=0, maxit
     return r[:count], z[:count]
 
 
-def train(net, r, z, epochs=2, batch=16, margin=3, lr=1e-3, seed=0, holdout=0.05, log=None):
-    """Adam on the stored crops; returns (train losses, validation loss before, after)."""
+def train(net, r, z, epochs=2, batch=16, margin=3, lr=1e-3, seed=0, holdout=0.05, log=None, lr_min=None,
+          chunks_per_epoch=8):
+    """Adam on the stored crops; returns (train losses, validation loss before, after).
+
+    With lr_min set, the learning rate follows a cosine from lr to lr_min over
+    the run, changed between chunks of an epoch (each chunk is one
+    psc_net_train call).
+    """
     count = r.shape[0]
     rng = np.random.default_rng(seed)
     perm = rng.permutation(count)
@@ -62,9 +68,21 @@ def train(net, r, z, epochs=2, batch=16, margin=3, lr=1e-3, seed=0, holdout=0.05
     losses = []
     t0 = time.time()
     steps_per_epoch = len(tr) // batch
+    total = epochs * chunks_per_epoch
+    k = 0
     for ep in range(epochs):
         order = tr[rng.permutation(len(tr))][:steps_per_epoch * batch].astype(np.int32)
-        losses.append(net.train(r, z, order, steps=steps_per_epoch, batch=batch, margin=margin, lr=lr))
+        bounds = np.linspace(0, steps_per_epoch, chunks_per_epoch + 1).astype(int)
+        ep_losses = []
+        for c in range(chunks_per_epoch):
+            lr_k = lr if lr_min is None else lr_min + 0.5 * (lr - lr_min) * (1 + np.cos(np.pi * k / max(total - 1, 1)))
+            k += 1
+            s0, s1 = bounds[c], bounds[c + 1]
+            if s1 <= s0:
+                continue
+            ep_losses.append(net.train(r, z, order[s0 * batch:s1 * batch], steps=s1 - s0, batch=batch,
+                                       margin=margin, lr=float(lr_k)))
+        losses.append(np.concatenate(ep_losses))
         if log:
             log(f"epoch {ep}: mean loss {losses[-1].mean():.4e} ({time.time() - t0:.1f}s)")
     v1 = val_loss()

@@ -205,17 +205,21 @@ def test_failure_paths(psc):
     assert e.value.status == psc.ERR_ARG
 
 
+@pytest.mark.parametrize("form", ["pcg", "fcg64", "fcg32"])
 @pytest.mark.parametrize("case", ["poisson32", "diffusion20_az100", "random_long_rows"])
-def test_fused_and_unfused_pcg_agree(psc, case):
+def test_fused_and_unfused_iterations_agree(psc, case, form):
     rp, c, v = CASES[case]()
     cm = 40 if case == "random_long_rows" else 200
     b = P.rhs_from_solution(rp, c, v, P.x_true(len(rp) - 1, 1))
     out = []
     for fused in (1, 0):
-        h = psc.Hierarchy(rp, c, v, coarse_max=cm)
+        h = psc.Hierarchy(rp, c, v, coarse_max=cm, build_fp32=True)
         h.tune(psc.TUNE_FUSED_PCG, fused)
         x = torch.zeros(len(b), dtype=torch.float64, device="cuda")
-        g = h.pcg(dev(b), x)
+        if form == "pcg":
+            g = h.pcg(dev(b), x)
+        else:
+            g = h.fcg(dev(b), x, prec=psc.FP32 if form == "fcg32" else psc.FP64)
         out.append((g, x.cpu().numpy()))
     (g1, x1), (g0, x0) = out
     assert g1["status"] == g0["status"] == psc.OK
@@ -253,3 +257,20 @@ def test_kernel_variants_match_oracle(psc, case, knob):
     g = h.pcg(dev(b), xg)
     r = o.pcg(b)
     assert abs(g["iters"] - r["iters"]) <= 1 and g["relres"] <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fcg_tight_tolerance_residual_replacement(psc, prec):
+    """At rtol 1e-11 the recursive residual can pass before the true one;
+    the FCG forms then replace r by b - A x and continue (fused and not)."""
+    rp, c, v = P.diffusion7(24, seed=3, az=0.01)
+    b = P.rhs_from_solution(rp, c, v, P.x_true(24 ** 3, 2))
+    res = []
+    for fused in (1, 0):
+        h = psc.Hierarchy(rp, c, v, build_fp32=True)
+        h.tune(psc.TUNE_FUSED_PCG, fused)
+        x = torch.zeros(len(b), dtype=torch.float64, device="cuda")
+        g = h.fcg(dev(b), x, rtol=1e-11, maxit=400, prec=psc.FP32 if prec == "fp32" else psc.FP64)
+        assert g["status"] == psc.OK and g["relres"] <= 1e-11
+        res.append(g["iters"])
+    assert abs(res[0] - res[1]) <= 3
