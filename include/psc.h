@@ -208,8 +208,9 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
 #define PSC_TUNE_GRID_MAX 1
 #define PSC_TUNE_FUSED_PCG 2
 #define PSC_TUNE_UNROLL4 3
-/* PSC_TUNE_BUFLOAD (default 0): the hacked-ELL kernels read the matrix and
- * gather vectors through buffer descriptors (32-bit offsets). */
+/* PSC_TUNE_BUFLOAD: which hacked-ELL kernels read the matrix and gather
+ * vectors through buffer descriptors (32-bit offsets, fewer registers):
+ * 0 none, 1 all, 2 (default) the prolongation + post-smoothing kernel. */
 #define PSC_TUNE_BUFLOAD 4
 int psc_tune(psc_hier* h, int32_t key, int32_t value);
 

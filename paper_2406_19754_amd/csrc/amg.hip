@@ -94,8 +94,10 @@ __device__ __forceinline__ T ntload(const T* p) {
     return __builtin_nontemporal_load(p);
 }
 
+// Mirror the stop flag to host-mapped memory. Only the final state is
+// needed by the host loop, so the system-scope fence is paid once per solve.
 __device__ __forceinline__ void publish(Ctl* c, HostCtl* hc) {
-    if (hc) {
+    if (hc && c->done) {
         hc->done = c->done;
         hc->iter = c->iter;
         hc->status = c->status;
@@ -769,7 +771,13 @@ __global__ void k_ctl_init(Ctl* c, HostCtl* hc, double rtol, int maxit, int form
         c->fallbacks = 0;
         c->form = form;
         c->redo = 0;
-        publish(c, hc);
+        if (hc) {
+            hc->done = 0;
+            hc->iter = 0;
+            hc->status = PSC_NOCONV;
+            hc->fallbacks = 0;
+            __threadfence_system();
+        }
     }
 }
 
@@ -903,7 +911,7 @@ struct psc_hier {
     double *r2 = nullptr, *p2 = nullptr;  // second buffers of the fused PCG iteration
     bool fused_pcg = true;                // PCG form: fused two-pass iteration
     bool unroll4 = false;                 // gather in batches of 4 in the FP64 post / update+pre kernels
-    bool bufload = false;                 // matrix streams and gathers through buffer descriptors
+    int bufload = 2;                      // buffer descriptors: 0 none, 1 all ELL kernels, 2 post-smoothing only
     std::vector<void*> allocs;
     int64_t device_bytes = 0;
     double setup_seconds = 0.0;
@@ -1039,14 +1047,14 @@ static void timing_collect(psc_hier* h) {
 template <typename T, typename TB>
 static void launch_pre(psc_hier* h, const Ell<T>& A, const T* minv, const TB* b, T* r, Gate g) {
     const int gr = grid_ell(h, A.nslices);
-    if (h->bufload) k_pre<T, TB, true><<<gr, WG, 0, h->stream>>>(A, minv, b, r, g);
+    if (h->bufload == 1) k_pre<T, TB, true><<<gr, WG, 0, h->stream>>>(A, minv, b, r, g);
     else k_pre<T, TB, false><<<gr, WG, 0, h->stream>>>(A, minv, b, r, g);
 }
 
 template <typename T>
 static void launch_spmv(psc_hier* h, const Ell<T>& A, const T* x, T* y, Gate g) {
     const int gr = grid_ell(h, A.nslices);
-    if (h->bufload) k_spmv<T, true><<<gr, WG, 0, h->stream>>>(A, x, y, g);
+    if (h->bufload == 1) k_spmv<T, true><<<gr, WG, 0, h->stream>>>(A, x, y, g);
     else k_spmv<T, false><<<gr, WG, 0, h->stream>>>(A, x, y, g);
 }
 
@@ -1054,7 +1062,7 @@ template <typename T, typename TB, typename TX>
 static void launch_post(psc_hier* h, const Ell<T>& A, const T* minv, const TB* b, const int* agg, const T* pv,
                         const T* xc, long long nc, TX* x, const double* d, const Red& R) {
     const int gr = grid_ell(h, A.nslices);
-    if (h->bufload) k_post<T, TB, TX, 8, true><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
+    if (h->bufload >= 1) k_post<T, TB, TX, 8, true><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
     else if (h->unroll4) k_post<T, TB, TX, 4, false><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
     else k_post<T, TB, TX, 8, false><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
 }
@@ -1190,7 +1198,6 @@ __global__ void k_iter_begin(Ctl* c, HostCtl* hc, int has_net) {
     const int odd = c->iter & 1;
     c->use_net = has_net && c->net_on && odd;
     if (has_net && !c->net_on && odd) c->fallbacks += 1;
-    if (hc) hc->fallbacks = c->fallbacks;
 }
 
 // partials (z.r, z.q) of a network step
@@ -1226,7 +1233,7 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             double* rnew = parity ? h->r : h->r2;
             {
                 TimeScope t(h, 0);
-                if (h->bufload)
+                if (h->bufload == 1)
                     k_spmv_pfuse<true><<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, red_of(h, FIN_ALPHA_PCG));
                 else
                     k_spmv_pfuse<false><<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, red_of(h, FIN_ALPHA_PCG));
@@ -1234,7 +1241,7 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             finish(h, red_of(h, FIN_ALPHA_PCG), ge);
             {
                 TimeScope t(h, 2);
-                if (h->bufload)
+                if (h->bufload == 1)
                     k_update_pre<8, true><<<ge, WG, 0, st>>>(L0.A.view(), L0.minv, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_PCG));
                 else if (h->unroll4)
                     k_update_pre<4><<<ge, WG, 0, st>>>(L0.A.view(), L0.minv, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_PCG));
@@ -1255,7 +1262,7 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             double* rnew = parity ? h->r : h->r2;
             {
                 TimeScope t(h, 0);
-                if (h->bufload)
+                if (h->bufload == 1)
                     k_spmv_pfuse_fcg<true><<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, rold, red_of(h, FIN_ALPHA_FCG));
                 else
                     k_spmv_pfuse_fcg<false><<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, rold, red_of(h, FIN_ALPHA_FCG));
@@ -1264,12 +1271,12 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             {
                 TimeScope t(h, 2);
                 if (f32) {
-                    if (h->bufload)
+                    if (h->bufload == 1)
                         k_update_pre_t<float, true><<<ge, WG, 0, st>>>(L0.A.view32(), L0.minv32, rold, h->q, rnew, L0.r32, red_of(h, FIN_UPDATE_FCG));
                     else
                         k_update_pre_t<float, false><<<ge, WG, 0, st>>>(L0.A.view32(), L0.minv32, rold, h->q, rnew, L0.r32, red_of(h, FIN_UPDATE_FCG));
                 } else {
-                    if (h->bufload)
+                    if (h->bufload == 1)
                         k_update_pre_t<double, true><<<ge, WG, 0, st>>>(L0.A.view(), L0.minv, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_FCG));
                     else
                         k_update_pre_t<double, false><<<ge, WG, 0, st>>>(L0.A.view(), L0.minv, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_FCG));
@@ -1839,7 +1846,8 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms) {
 int psc_tune(psc_hier* h, int32_t key, int32_t value) {
     if (!h) return fail(PSC_ERR_ARG, "NULL handle");
     if (key == PSC_TUNE_BUFLOAD) {
-        h->bufload = value != 0;
+        if (value < 0 || value > 2) return fail(PSC_ERR_ARG, "buffer-load mode must be 0, 1 or 2");
+        h->bufload = value;
         drop_graphs(h);
         return PSC_OK;
     }

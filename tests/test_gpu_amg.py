@@ -227,15 +227,18 @@ def test_fused_and_unfused_iterations_agree(psc, case, form):
     assert np.linalg.norm(x1 - x0) <= 1e-10 * np.linalg.norm(x0)
 
 
-@pytest.mark.parametrize("knob", ["bufload", "unroll4", "grid256"])
+@pytest.mark.parametrize("knob", ["bufload_all", "bufload_none", "unroll4", "grid256"])
 @pytest.mark.parametrize("case", ["poisson13", "random_long_rows", "diffusion20_az100"])
 def test_kernel_variants_match_oracle(psc, case, knob):
     rp, c, v = CASES[case]()
     cm = 40 if case == "random_long_rows" else 200
     h = psc.Hierarchy(rp, c, v, coarse_max=cm, build_fp32=True)
-    if knob == "bufload":
+    if knob == "bufload_all":
         h.tune(psc.TUNE_BUFLOAD, 1)
+    elif knob == "bufload_none":
+        h.tune(psc.TUNE_BUFLOAD, 0)
     elif knob == "unroll4":
+        h.tune(psc.TUNE_BUFLOAD, 0)
         h.tune(psc.TUNE_UNROLL4, 1)
     else:
         h.tune(psc.TUNE_GRID_MAX, 256)               # several slices per wavefront
