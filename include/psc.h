@@ -60,6 +60,12 @@ typedef struct psc_net  psc_net;    /* opaque: owns the learned preconditioner  
  *   coarse_max = 200 a level with at most this many rows is the coarsest one
  *                    and is solved exactly by dense Cholesky.
  *   max_levels = 30  hard cap on the number of levels.
+ *   coarse_sweeps = 30  when coarsening stalls (a level keeps more than 0.9
+ *                    of the rows of the level above) that level becomes the
+ *                    coarsest; with at most 2000 rows it is factored, else
+ *                    it is solved by this many FP64 l1-Jacobi sweeps from a
+ *                    zero guess (the l1-Jacobi coarsest solver of Section
+ *                    "GPU enabled smoothers"). 0 makes such a stall an error.
  *   build_fp32 = 0   also build the FP32 copies of the level operators that
  *                    the mixed-precision V-cycle needs.
  *   use_graph = 1    capture the per-iteration kernel sequence as a HIP
@@ -76,7 +82,8 @@ typedef struct {
     int32_t build_fp32;
     int32_t use_graph;
     int32_t host_only;
-    int32_t reserved[10];
+    int32_t coarse_sweeps;
+    int32_t reserved[9];
 } psc_amg_opts;
 
 void psc_amg_opts_default(psc_amg_opts* opts);
@@ -97,8 +104,10 @@ void psc_amg_opts_default(psc_amg_opts* opts);
  *   out         receives the handle; release with psc_hier_free
  * The setup runs on the host (as in the paper, where the hierarchy build is
  * mostly host-side) and ends with one host-to-device copy of every level.
- * Errors: PSC_ERR_ARG (malformed CSR), PSC_ERR_NOT_SPD (diagonal <= 0 or
- * coarsest Cholesky breakdown), PSC_ERR_COARSEN, PSC_ERR_OOM, PSC_ERR_HIP.
+ * Errors: PSC_ERR_ARG (malformed CSR or options), PSC_ERR_NOT_SPD
+ * (diagonal <= 0 or coarsest Cholesky breakdown), PSC_ERR_COARSEN (a stall
+ * above 2000 rows with coarse_sweeps = 0, or a coarsest level forced by
+ * max_levels above 4096 rows), PSC_ERR_OOM, PSC_ERR_HIP.
  * Symmetry is assumed, not checked.
  */
 int psc_amg_build(int32_t n, const int32_t* rowptr_host, const int32_t* col_host,
@@ -107,7 +116,7 @@ int psc_amg_build(int32_t n, const int32_t* rowptr_host, const int32_t* col_host
 
 /*
  * Preconditioned conjugate gradient with the FP64 V-cycle (one l1-Jacobi
- * pre- and post-sweep, exact coarsest solve; Section "AMG4PSBLAS",
+ * pre- and post-sweep, coarsest solve as chosen at build; Section "AMG4PSBLAS",
  * eq. (amg)) as the preconditioner. Stops when the recursive residual
  * satisfies ||r||_2 <= rtol ||b||_2 (Section "Numerical Example").
  *   b_dev    n FP64, right-hand side
@@ -158,6 +167,7 @@ typedef struct {
     double  spmv_bytes_fp64;                 /* algorithmic bytes of y = A_0 x */
     double  setup_seconds;                   /* host setup wall time */
     int64_t device_bytes;                    /* device memory held by the handle */
+    int32_t coarse_sweeps;                   /* 0: coarsest factored, else l1-Jacobi sweeps */
 } psc_hier_stats;
 
 int psc_hier_info(const psc_hier* h, psc_hier_stats* s);
@@ -212,6 +222,9 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
  * vectors through buffer descriptors (32-bit offsets, fewer registers):
  * 0 none, 1 all, 2 (default) the prolongation + post-smoothing kernel. */
 #define PSC_TUNE_BUFLOAD 4
+/* PSC_TUNE_SPMV2 (default 0): the plain SpMV and the restriction process two
+ * slices per wavefront concurrently. */
+#define PSC_TUNE_SPMV2 5
 int psc_tune(psc_hier* h, int32_t key, int32_t value);
 
 void psc_hier_free(psc_hier* h);

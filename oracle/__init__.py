@@ -54,7 +54,9 @@ def lib():
     L.orc_edge_key.restype = C.c_longlong
     L.orc_match.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p]
     L.orc_match.restype = C.c_int
-    L.orc_build.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_int, C.c_int, C.POINTER(vp)]
+    L.orc_build.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(vp)]
+    L.orc_coarse_sweeps.argtypes = [vp]
+    L.orc_coarse_sweeps.restype = C.c_int
     L.orc_build.restype = C.c_int
     L.orc_free.argtypes = [vp]
     L.orc_free.restype = None
@@ -124,11 +126,11 @@ def match(rowptr, col, S):
 class Hierarchy:
     """Oracle AMG hierarchy (C.2 of the readings): levels of (A_l, agg, p, w, minv)."""
 
-    def __init__(self, rowptr, col, val, sweeps=2, coarse_max=200, max_levels=30):
+    def __init__(self, rowptr, col, val, sweeps=2, coarse_max=200, max_levels=30, coarse_sweeps=30):
         self._rowptr, self._col, self._val = _i32(rowptr), _i32(col), _f64(val)
         h = C.c_void_p()
         st = lib().orc_build(len(rowptr) - 1, self._rowptr, self._col, self._val,
-                             sweeps, coarse_max, max_levels, C.byref(h))
+                             sweeps, coarse_max, max_levels, coarse_sweeps, C.byref(h))
         self.status = st
         if st != OK:
             raise RuntimeError(f"oracle build failed with status {st}")
@@ -143,6 +145,11 @@ class Hierarchy:
     @property
     def nlevels(self):
         return lib().orc_nlevels(self._h)
+
+    @property
+    def coarse_sweeps(self):
+        """0 when the coarsest level is factored, else the l1-Jacobi sweep count."""
+        return lib().orc_coarse_sweeps(self._h)
 
     def level_info(self, l):
         n, nnz, nc = C.c_int(), C.c_longlong(), C.c_int()

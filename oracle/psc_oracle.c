@@ -239,6 +239,7 @@ typedef struct {
 typedef struct {
     int nlev;
     int sweeps;
+    int coarse_sweeps;   /* > 0: the coarsest level is solved by this many l1-Jacobi sweeps */
     orc_level lev[ORC_MAXLEV];
 } orc_hier;
 
@@ -376,11 +377,12 @@ static int csr_copy(int n, const int *rp, const int *ci, const double *v, csr *a
  * prolongator value p_i = w_i / w_{l+1}[agg_i] (eq. prolongator: the column
  * of an aggregate is w restricted to it, normalised), the Galerkin operator
  * A_{l+1} = P^T A_l P (eq. amg context), and the l1-Jacobi diagonal.
- * Stall guard: if n_{l+1} > 0.9 n_l, level l+1 becomes the coarsest when
- * it has at most 2000 rows, else ORC_ERR_COARSEN.
+ * Stall guard: if n_{l+1} > 0.9 n_l, level l+1 becomes the coarsest; it is
+ * factored when it has at most 2000 rows, otherwise it is solved by
+ * coarse_sweeps l1-Jacobi sweeps (ORC_ERR_COARSEN when coarse_sweeps < 1).
  */
 int orc_build(int n, const int *rp, const int *ci, const double *v,
-              int sweeps, int coarse_max, int max_levels, orc_hier **out) {
+              int sweeps, int coarse_max, int max_levels, int coarse_sweeps, orc_hier **out) {
     *out = NULL;
     if (n <= 0 || sweeps < 1 || max_levels < 1 || max_levels > ORC_MAXLEV) return ORC_ERR_ARG;
     orc_hier *h = calloc(1, sizeof(orc_hier));
@@ -397,15 +399,22 @@ int orc_build(int n, const int *rp, const int *ci, const double *v,
         st = l1_diag_inv(&L->A, L->minv);
         if (st) { orc_free(h); return st; }
         int force_coarsest = (l + 1 >= max_levels);
+        int stalled = 0;
         if (l > 0) {
             int nprev = h->lev[l - 1].A.n;
-            if ((double)nl > 0.9 * (double)nprev) {
-                if (nl <= 2000) force_coarsest = 1;
-                else { orc_free(h); return ORC_ERR_COARSEN; }
-            }
+            if ((double)nl > 0.9 * (double)nprev) { force_coarsest = 1; stalled = 1; }
         }
         if (nl <= coarse_max || force_coarsest) {
             L->nc = 0;
+            if (stalled && nl > 2000) {
+                /* coarsening stalled on a level too large for a dense factor:
+                 * it is solved by a fixed number of l1-Jacobi sweeps from zero
+                 * (the paper's l1-Jacobi coarsest solver, Section "GPU enabled
+                 * smoothers", Fig. prec_build), a fixed SPD operator */
+                if (coarse_sweeps < 1) { orc_free(h); return ORC_ERR_COARSEN; }
+                h->coarse_sweeps = coarse_sweeps;
+                break;
+            }
             L->L = malloc(sizeof(double) * (size_t)nl * nl);
             st = dense_cholesky(&L->A, L->L);
             if (st) { orc_free(h); return st; }
@@ -462,19 +471,37 @@ int orc_level_get(const orc_hier *h, int l, int *rp, int *ci, double *v,
 int orc_coarse_factor(const orc_hier *h, double *Lout) {
     const orc_level *L = &h->lev[h->nlev - 1];
     int n = L->A.n;
+    if (!L->L) return ORC_ERR_ARG;
     memcpy(Lout, L->L, sizeof(double) * (size_t)n * n);
     return ORC_OK;
 }
 
+int orc_coarse_sweeps(const orc_hier *h) { return h->coarse_sweeps; }
+
+/* Coarsest-level solve in FP64: dense Cholesky, or l1-Jacobi sweeps from
+ * x = 0 (x <- x + M^{-1}(b - A x)) when the hierarchy says so. */
+static void coarse_solve(const orc_hier *h, const double *b, double *x) {
+    const orc_level *L = &h->lev[h->nlev - 1];
+    int n = L->A.n;
+    if (!h->coarse_sweeps) { chol_solve(n, L->L, b, x); return; }
+    double *t = malloc(sizeof(double) * (size_t)n);
+    for (int i = 0; i < n; i++) x[i] = 0.0;
+    for (int k = 0; k < h->coarse_sweeps; k++) {
+        orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, t);
+        for (int i = 0; i < n; i++) x[i] += L->minv[i] * (b[i] - t[i]);
+    }
+    free(t);
+}
+
 /* ------------------------------------------------------------------------ */
 /* V-cycle (eq. amg): one pre-sweep from a zero guess, coarse correction,   */
-/* one post-sweep; the coarsest level is solved exactly by Cholesky.        */
+/* one post-sweep; the coarsest level is solved by coarse_solve.            */
 /* ------------------------------------------------------------------------ */
 
 static void vcycle_level(const orc_hier *h, int l, const double *b, double *x) {
     const orc_level *L = &h->lev[l];
     int n = L->A.n;
-    if (l == h->nlev - 1) { chol_solve(n, L->L, b, x); return; }
+    if (l == h->nlev - 1) { coarse_solve(h, b, x); return; }
     int nc = L->nc;
     double *r = malloc(sizeof(double) * (size_t)n);
     double *bc = malloc(sizeof(double) * (size_t)nc);
@@ -515,7 +542,7 @@ static void vcycle32_level(const orc_hier *h, int l, const float *b, float *x) {
         double *bd = malloc(sizeof(double) * (size_t)n);
         double *xd = malloc(sizeof(double) * (size_t)n);
         for (int i = 0; i < n; i++) bd[i] = (double)b[i];
-        chol_solve(n, L->L, bd, xd);
+        coarse_solve(h, bd, xd);
         for (int i = 0; i < n; i++) x[i] = (float)xd[i];
         free(bd); free(xd);
         return;

@@ -348,6 +348,45 @@ __device__ __forceinline__ T ell_row(const Ell<T>& A, long long s, int lane, G g
     return acc;
 }
 
+// Two rows of two different slices (s1, s2, both of width <= 8) computed
+// together: all value and index loads of both slices are issued before the
+// first gather, doubling the loads a wavefront keeps in flight.
+template <typename T, typename G>
+__device__ __forceinline__ void ell_row2(const Ell<T>& A, long long s1, long long s2, int lane, G g, T& a1, T& a2) {
+    const long long o1 = A.off[s1], o2 = A.off[s2];
+    const int w1 = (int)((A.off[s1 + 1] - o1) >> 6), w2 = (int)((A.off[s2 + 1] - o2) >> 6);
+    if (w1 > 8 || w2 > 8) {
+        a1 = ell_row(A, s1, lane, g);
+        a2 = ell_row(A, s2, lane, g);
+        return;
+    }
+    const T* vp1 = A.val + o1 + lane;
+    const int* cp1 = A.col + o1 + lane;
+    const T* vp2 = A.val + o2 + lane;
+    const int* cp2 = A.col + o2 + lane;
+    T v1[8], v2[8];
+    int c1[8], c2[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        if (k < w1) { v1[k] = ntload(vp1 + k * SLICE); c1[k] = ntload(cp1 + k * SLICE); }
+        if (k < w2) { v2[k] = ntload(vp2 + k * SLICE); c2[k] = ntload(cp2 + k * SLICE); }
+    }
+    T g1[8], g2[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        if (k < w1) g1[k] = g(c1[k]);
+        if (k < w2) g2[k] = g(c2[k]);
+    }
+    T acc1 = T(0), acc2 = T(0);
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        if (k < w1) acc1 += v1[k] * g1[k];
+        if (k < w2) acc2 += v2[k] * g2[k];
+    }
+    a1 = acc1;
+    a2 = acc2;
+}
+
 // ---- buffer-load path ------------------------------------------------------
 // Raw buffer loads address memory as a scalar descriptor (base, byte size)
 // plus a 32-bit per-lane byte offset: one VGPR per gathered address instead
@@ -462,6 +501,30 @@ __global__ __launch_bounds__(WG) void k_spmv(Ell<T> A, const T* __restrict__ x, 
         else acc = ell_row(A, s, lane, [&](int c) { return x[c]; });
         long long row = s * SLICE + lane;
         if (row < A.nrows) y[row] = acc;
+    }
+}
+
+// y = A x, two slices per wavefront in flight (slices s and s + 4 of the
+// workgroup's chunk).
+template <typename T>
+__global__ __launch_bounds__(WG) void k_spmv2(Ell<T> A, const T* __restrict__ x, T* __restrict__ y, Gate g) {
+    if (gate_skip(g)) return;
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    auto gx = [&](int c) { return x[c]; };
+    long long s = lo + w;
+    for (; s + WG / 64 < hi; s += 2 * (WG / 64)) {
+        T a1, a2;
+        ell_row2(A, s, s + WG / 64, lane, gx, a1, a2);
+        const long long r1 = s * SLICE + lane, r2 = (s + WG / 64) * SLICE + lane;
+        if (r1 < A.nrows) y[r1] = a1;
+        if (r2 < A.nrows) y[r2] = a2;
+    }
+    if (s < hi) {
+        T a = ell_row(A, s, lane, gx);
+        const long long r1 = s * SLICE + lane;
+        if (r1 < A.nrows) y[r1] = a;
     }
 }
 
@@ -854,6 +917,29 @@ __global__ __launch_bounds__(WG) void k_coarse(int n, const double* __restrict__
     }
 }
 
+// Coarsest level solved by l1-Jacobi sweeps in FP64 (used when coarsening
+// stalls above the dense-factor limit). One sweep from x_in:
+//   x_out_i = x_in_i + minv_i (b_i - sum_j a_ij x_in_j);
+// x_in == nullptr stands for the zero guess (x_out = minv b).
+template <typename TB, typename TX>
+__global__ __launch_bounds__(WG) void k_jacobi(Ell<double> A, const double* __restrict__ minv,
+                                               const TB* __restrict__ b, const double* __restrict__ xin,
+                                               TX* __restrict__ xout, Gate g) {
+    if (gate_skip(g)) return;
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        const long long row = s * SLICE + lane;
+        if (!xin) {
+            if (row < A.nrows) xout[row] = (TX)(minv[row] * (double)b[row]);
+            continue;
+        }
+        double acc = ell_row(A, s, lane, [&](int c) { return xin[c]; });
+        if (row < A.nrows) xout[row] = (TX)(xin[row] + minv[row] * ((double)b[row] - acc));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
@@ -912,6 +998,7 @@ struct psc_hier {
     bool fused_pcg = true;                // PCG form: fused two-pass iteration
     bool unroll4 = false;                 // gather in batches of 4 in the FP64 post / update+pre kernels
     int bufload = 2;                      // buffer descriptors: 0 none, 1 all ELL kernels, 2 post-smoothing only
+    bool spmv2 = false;                   // plain SpMV / restriction: two slices per wavefront
     std::vector<void*> allocs;
     int64_t device_bytes = 0;
     double setup_seconds = 0.0;
@@ -1053,6 +1140,12 @@ static void launch_pre(psc_hier* h, const Ell<T>& A, const T* minv, const TB* b,
 
 template <typename T>
 static void launch_spmv(psc_hier* h, const Ell<T>& A, const T* x, T* y, Gate g) {
+    if (h->spmv2) {
+        // two slices per wavefront: half the workgroups of the one-slice grid
+        const int gr = grid_of(h, 8, A.nslices);
+        k_spmv2<T><<<gr, WG, 0, h->stream>>>(A, x, y, g);
+        return;
+    }
     const int gr = grid_ell(h, A.nslices);
     if (h->bufload == 1) k_spmv<T, true><<<gr, WG, 0, h->stream>>>(A, x, y, g);
     else k_spmv<T, false><<<gr, WG, 0, h->stream>>>(A, x, y, g);
@@ -1091,6 +1184,29 @@ static void finish(psc_hier* h, const Red& R, int grid) {
     k_finish<<<1, WG, 0, h->stream>>>(R2, mid);
 }
 
+// Coarsest solve x = B_L b: the explicit dense inverse, or coarse_sweeps
+// l1-Jacobi sweeps in FP64 from zero. The sweeps alternate between the
+// level's FP64 x and r buffers so that the last one lands in x (TX = double)
+// or is rounded into the FP32 x32 (TX = float).
+template <typename TB, typename TX>
+static void coarse_solve(psc_hier* h, const TB* b, TX* x, Gate g) {
+    DevLevel& C = h->lev.back();
+    const int K = h->host.coarse_sweeps;
+    if (K == 0) {
+        k_coarse<TB, TX><<<1, WG, 0, h->stream>>>(h->coarse_n, h->coarse_invT, b, x, g);
+        return;
+    }
+    const Ell<double> A = C.A.view();
+    const int gr = grid_ell(h, A.nslices);
+    const double* xin = nullptr;
+    for (int k = 1; k < K; k++) {
+        double* xo = ((K - k) % 2 == 0) ? C.x : C.r;
+        k_jacobi<TB, double><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, xo, g);
+        xin = xo;
+    }
+    k_jacobi<TB, TX><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, x, g);
+}
+
 // z = B r on level 0. prec: PSC_FP64 / PSC_FP32. fin/d: optional fused dot
 // z.d at level 0 with finaliser fin. g gates every kernel (g.ctl == NULL:
 // standalone V-cycle, always runs, no fused dot).
@@ -1127,7 +1243,7 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
         DevLevel& C = h->lev[L - 1];
         {
             TimeScope t(h, 7);
-            k_coarse<double, double><<<1, WG, 0, st>>>(h->coarse_n, h->coarse_invT, C.b, C.x, g);
+            coarse_solve<double, double>(h, C.b, C.x, g);
         }
         for (int l = L - 2; l >= 0; l--) {
             DevLevel& V = h->lev[l];
@@ -1156,7 +1272,7 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
         DevLevel& C = h->lev[L - 1];
         {
             TimeScope t(h, 7);
-            k_coarse<float, float><<<1, WG, 0, st>>>(h->coarse_n, h->coarse_invT, C.b32, C.x32, g);
+            coarse_solve<float, float>(h, C.b32, C.x32, g);
         }
         for (int l = L - 2; l >= 0; l--) {
             DevLevel& V = h->lev[l];
@@ -1579,6 +1695,7 @@ void psc_amg_opts_default(psc_amg_opts* o) {
     o->max_levels = 30;
     o->build_fp32 = 0;
     o->use_graph = 1;
+    o->coarse_sweeps = 30;
 }
 
 void psc_hier_free(psc_hier* h) {
@@ -1619,6 +1736,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     so.sweeps = h->opts.sweeps;
     so.coarse_max = h->opts.coarse_max;
     so.max_levels = h->opts.max_levels;
+    so.coarse_sweeps = h->opts.coarse_sweeps;
     st = build_hierarchy(n, rp, ci, v, so, h->host, err);
     if (st) return fail(st, err);
     const bool f32 = h->opts.build_fp32 != 0;
@@ -1656,6 +1774,9 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
                 if ((st = dalloc(h.get(), (void**)&D.x32, H.n * sizeof(float)))) return st;
             }
         }
+        if (l == L - 1 && l > 0 && h->host.coarse_sweeps > 0) {
+            if ((st = dalloc(h.get(), (void**)&D.r, H.n * sizeof(double)))) return st;
+        }
         if (l < L - 1) {
             if ((st = dalloc(h.get(), (void**)&D.r, H.n * sizeof(double)))) return st;
             if (f32 && (st = dalloc(h.get(), (void**)&D.r32, H.n * sizeof(float)))) return st;
@@ -1680,9 +1801,9 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
         }
     }
     // coarsest inverse, stored transposed for coalesced reads
-    {
-        int nc = (int)h->host.lev[L - 1].n;
-        h->coarse_n = nc;
+    h->coarse_n = (int)h->host.lev[L - 1].n;
+    if (h->host.coarse_sweeps == 0) {
+        int nc = h->coarse_n;
         std::vector<double> invT((size_t)nc * nc);
         for (int i = 0; i < nc; i++)
             for (int k = 0; k < nc; k++) invT[(size_t)k * nc + i] = h->host.coarse_inv[(size_t)i * nc + k];
@@ -1761,6 +1882,11 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
             double Z = (double)D.nnz, N = (double)D.n, Nc = (double)D.nc;
             vb64 += 2 * Z * 12 + N * 12 * 2 /* P and R */ + N * (8 * 8) + Nc * 8 * 2;
             vb32 += 2 * Z * 8 + N * 8 * 2 + N * (8 * 4) + Nc * 4 * 2;
+        } else if (h->host.coarse_sweeps > 0) {
+            // sweeps: A and x gathered, b and minv read, x written
+            double K = h->host.coarse_sweeps, Z = (double)D.nnz, N = (double)D.n;
+            vb64 += (K - 1) * (Z * 12 + N * 8 * 4) + N * 8 * 3;
+            vb32 += (K - 1) * (Z * 12 + N * 8 * 3 + N * 4) + N * (8 + 4 + 4);
         } else {
             double n2 = (double)D.n * D.n;
             vb64 += 8 * n2;
@@ -1773,6 +1899,7 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
     s->spmv_bytes_fp64 = z0 * 12 + 2 * 8 * (double)h->lev[0].n;
     s->setup_seconds = h->setup_seconds;
     s->device_bytes = h->device_bytes;
+    s->coarse_sweeps = h->host.coarse_sweeps;
     return PSC_OK;
 }
 
@@ -1848,6 +1975,11 @@ int psc_tune(psc_hier* h, int32_t key, int32_t value) {
     if (key == PSC_TUNE_BUFLOAD) {
         if (value < 0 || value > 2) return fail(PSC_ERR_ARG, "buffer-load mode must be 0, 1 or 2");
         h->bufload = value;
+        drop_graphs(h);
+        return PSC_OK;
+    }
+    if (key == PSC_TUNE_SPMV2) {
+        h->spmv2 = value != 0;
         drop_graphs(h);
         return PSC_OK;
     }

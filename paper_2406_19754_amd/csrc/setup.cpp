@@ -425,7 +425,7 @@ int validate_csr(int64_t n, const int32_t* rp, const int32_t* ci, const double* 
 int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
                     const SetupOpts& o, HostHier& H, std::string& err) {
     if (o.sweeps < 1 || o.sweeps > 8 || o.coarse_max < 1 || o.max_levels < 1 ||
-        o.max_levels > PSC_MAX_LEVELS) {
+        o.max_levels > PSC_MAX_LEVELS || o.coarse_sweeps < 0 || o.coarse_sweeps > 1000) {
         err = "invalid hierarchy options";
         return PSC_ERR_ARG;
     }
@@ -448,16 +448,26 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
         int st = l1_inverse_diag(A, H.lev[l].minv);
         if (st != PSC_OK) { err = "non-positive l1 diagonal on level " + std::to_string(l); return st; }
         bool coarsest = (A.n <= o.coarse_max) || (l + 1 >= o.max_levels);
-        if (l > 0 && (double)A.n > 0.9 * (double)H.lev[l - 1].n) {
-            if (A.n <= 2000) coarsest = true;
-            else {
+        bool stalled = l > 0 && (double)A.n > 0.9 * (double)H.lev[l - 1].n;
+        if (stalled && A.n > 2000) {
+            // Coarsening stalled above the dense-factor limit: this level is
+            // the coarsest and is solved by a fixed number of l1-Jacobi sweeps.
+            if (o.coarse_sweeps < 1) {
                 err = "coarsening stalled at level " + std::to_string(l) + " with " + std::to_string(A.n) + " rows";
                 return PSC_ERR_COARSEN;
             }
+            H.lev[l].nc = 0;
+            H.coarse_sweeps = o.coarse_sweeps;
+            H.coarse_inv.clear();
+            H.lev[l].rp.swap(A.rp);
+            H.lev[l].ci.swap(A.ci);
+            H.lev[l].v.swap(A.v);
+            break;
         }
-        if (coarsest) {
+        if (coarsest || stalled) {
             if (A.n > 4096) { err = "coarsest level too large for a dense solve"; return PSC_ERR_COARSEN; }
             H.lev[l].nc = 0;
+            H.coarse_sweeps = 0;
             st = coarse_inverse(A, H.coarse_inv);
             H.lev[l].rp.swap(A.rp);
             H.lev[l].ci.swap(A.ci);

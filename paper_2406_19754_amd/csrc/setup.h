@@ -22,12 +22,14 @@ struct HostLevel {
 struct HostHier {
     std::vector<HostLevel> lev;
     std::vector<double> coarse_inv;   // dense inverse of the coarsest A, row-major
+    int coarse_sweeps = 0;            // > 0: coarsest solved by l1-Jacobi sweeps instead
 };
 
 struct SetupOpts {
     int sweeps = 2;
     int coarse_max = 200;
     int max_levels = 30;
+    int coarse_sweeps = 30;
 };
 
 // Status codes follow psc.h.

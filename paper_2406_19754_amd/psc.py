@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpsc.so")
 OK, NOCONV = 0, 1
 ERR_ARG, ERR_NOT_SPD, ERR_NAN, ERR_HIP, ERR_OOM, ERR_COARSEN, ERR_STATE = -1, -2, -3, -4, -5, -6, -7
 FP64, FP32 = 0, 1
-TUNE_GRID_MAX, TUNE_FUSED_PCG, TUNE_UNROLL4, TUNE_BUFLOAD = 1, 2, 3, 4
+TUNE_GRID_MAX, TUNE_FUSED_PCG, TUNE_UNROLL4, TUNE_BUFLOAD, TUNE_SPMV2 = 1, 2, 3, 4, 5
 MAX_LEVELS = 32
 TIMING_KERNELS = 8
 TIMING_NAMES = ["spmv_dot", "cg_update", "pre_smooth_l0", "restrict_l0", "post_smooth_l0",
@@ -39,7 +39,7 @@ class PscError(RuntimeError):
 class AmgOpts(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
                 ("build_fp32", C.c_int32), ("use_graph", C.c_int32), ("host_only", C.c_int32),
-                ("reserved", C.c_int32 * 10)]
+                ("coarse_sweeps", C.c_int32), ("reserved", C.c_int32 * 9)]
 
 
 class HierStats(C.Structure):
@@ -48,7 +48,8 @@ class HierStats(C.Structure):
                 ("ell_slots", C.c_int64 * MAX_LEVELS),
                 ("operator_complexity", C.c_double), ("vcycle_bytes_fp64", C.c_double),
                 ("vcycle_bytes_fp32", C.c_double), ("spmv_bytes_fp64", C.c_double),
-                ("setup_seconds", C.c_double), ("device_bytes", C.c_int64)]
+                ("setup_seconds", C.c_double), ("device_bytes", C.c_int64),
+                ("coarse_sweeps", C.c_int32)]
 
 
 def _load():
@@ -136,11 +137,12 @@ class Hierarchy:
     """AMG hierarchy handle (psc_amg_build)."""
 
     def __init__(self, rowptr, col, val, sweeps=2, coarse_max=200, max_levels=30,
-                 build_fp32=False, use_graph=True, host_only=False, stream=None):
+                 build_fp32=False, use_graph=True, host_only=False, stream=None, coarse_sweeps=30):
         import torch
         o = AmgOpts()
         _lib.psc_amg_opts_default(C.byref(o))
         o.sweeps, o.coarse_max, o.max_levels = sweeps, coarse_max, max_levels
+        o.coarse_sweeps = coarse_sweeps
         o.build_fp32, o.use_graph, o.host_only = int(build_fp32), int(use_graph), int(host_only)
         rp, prp = _hptr(rowptr, np.int32)
         ci, pci = _hptr(col, np.int32)
@@ -165,7 +167,8 @@ class Hierarchy:
         return dict(levels=L, rows=list(s.rows[:L]), nnz=list(s.nnz[:L]), ell_slots=list(s.ell_slots[:L]),
                     operator_complexity=s.operator_complexity, vcycle_bytes_fp64=s.vcycle_bytes_fp64,
                     vcycle_bytes_fp32=s.vcycle_bytes_fp32, spmv_bytes_fp64=s.spmv_bytes_fp64,
-                    setup_seconds=s.setup_seconds, device_bytes=s.device_bytes)
+                    setup_seconds=s.setup_seconds, device_bytes=s.device_bytes,
+                    coarse_sweeps=s.coarse_sweeps)
 
     def export_level(self, l):
         inf = self.info()

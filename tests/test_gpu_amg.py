@@ -34,6 +34,8 @@ CASES = {
     "poisson13": lambda: P.poisson7(13),                      # odd size: singletons, ragged slices
     "diffusion20_az100": lambda: P.diffusion7(20, seed=0, az=100.0),
     "random_long_rows": lambda: P.random_spd_csr(700, 5, density=0.01, maxrow=90),
+    # coarsening stalls above 2000 rows: coarsest solved by 30 l1-Jacobi sweeps
+    "diffusion48_lognormal": lambda: P.diffusion7(48, seed=0),
 }
 
 
@@ -95,6 +97,22 @@ def test_vcycle_matches_oracle(psc, case):
     assert np.linalg.norm(z.cpu().numpy() - ref) <= 1e-4 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("K", [1, 2, 7])
+def test_jacobi_coarsest_sweep_counts_match_oracle(psc, K):
+    rp, c, v = P.diffusion7(48, seed=0)
+    h = psc.Hierarchy(rp, c, v, build_fp32=True, coarse_sweeps=K)
+    o = oracle.Hierarchy(rp, c, v, coarse_sweeps=K)
+    assert h.info()["coarse_sweeps"] == K == o.coarse_sweeps
+    r = np.random.default_rng(K).standard_normal(len(rp) - 1)
+    z = torch.empty(len(r), dtype=torch.float64, device="cuda")
+    h.vcycle(dev(r), z)
+    ref = o.vcycle(r)
+    assert np.linalg.norm(z.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+    h.vcycle(dev(r), z, prec=psc.FP32)
+    ref32 = o.vcycle32(r)
+    assert np.linalg.norm(z.cpu().numpy() - ref32) <= 1e-5 * np.linalg.norm(ref32)
+
+
 def _solve_pair(psc, rp, c, v, b, form, maxit=1000, use_graph=True):
     h = psc.Hierarchy(rp, c, v, build_fp32=True, use_graph=use_graph)
     o = oracle.Hierarchy(rp, c, v)
@@ -110,7 +128,7 @@ def _solve_pair(psc, rp, c, v, b, form, maxit=1000, use_graph=True):
 
 
 @pytest.mark.parametrize("form", ["pcg", "fcg64", "fcg32"])
-@pytest.mark.parametrize("case", ["poisson32", "diffusion20_az100"])
+@pytest.mark.parametrize("case", ["poisson32", "diffusion20_az100", "diffusion48_lognormal"])
 def test_solve_matches_oracle(psc, case, form):
     rp, c, v = CASES[case]()
     b = P.rhs_from_solution(rp, c, v, P.x_true(len(rp) - 1, 0))
@@ -227,7 +245,7 @@ def test_fused_and_unfused_iterations_agree(psc, case, form):
     assert np.linalg.norm(x1 - x0) <= 1e-10 * np.linalg.norm(x0)
 
 
-@pytest.mark.parametrize("knob", ["bufload_all", "bufload_none", "unroll4", "grid256"])
+@pytest.mark.parametrize("knob", ["bufload_all", "bufload_none", "unroll4", "grid256", "spmv2"])
 @pytest.mark.parametrize("case", ["poisson13", "random_long_rows", "diffusion20_az100"])
 def test_kernel_variants_match_oracle(psc, case, knob):
     rp, c, v = CASES[case]()
@@ -240,6 +258,8 @@ def test_kernel_variants_match_oracle(psc, case, knob):
     elif knob == "unroll4":
         h.tune(psc.TUNE_BUFLOAD, 0)
         h.tune(psc.TUNE_UNROLL4, 1)
+    elif knob == "spmv2":
+        h.tune(psc.TUNE_SPMV2, 1)
     else:
         h.tune(psc.TUNE_GRID_MAX, 256)               # several slices per wavefront
     o = oracle.Hierarchy(rp, c, v, coarse_max=cm)

@@ -15,6 +15,7 @@ CASES = {
     "diffusion16_lognormal_az100": (lambda: P.diffusion7(16, seed=0, az=100.0), 200, 2),
     "diffusion14_lognormal_az0.01": (lambda: P.diffusion7(14, seed=2, az=0.01), 100, 2),
     "random_spd": (lambda: P.random_spd_csr(500, 3, density=0.02, maxrow=50), 40, 2),
+    "diffusion48_lognormal_stalls": (lambda: P.diffusion7(48, seed=0), 200, 2),
 }
 
 
@@ -28,6 +29,7 @@ def test_host_hierarchy_bit_identical_to_oracle(case):
     assert inf["rows"] == o.sizes()
     assert inf["nnz"] == o.nnzs()
     assert abs(inf["operator_complexity"] - o.operator_complexity()) < 1e-15
+    assert inf["coarse_sweeps"] == o.coarse_sweeps
     for l in range(inf["levels"]):
         a, b = h.export_level(l), o.level(l)
         for key in ["rowptr", "col", "val", "minv"]:
@@ -61,3 +63,17 @@ def test_malformed_csr_is_rejected():
     with pytest.raises(psc.PscError) as e:
         psc.Hierarchy(rp, c, v2, host_only=True)
     assert e.value.status == psc.ERR_NOT_SPD
+
+
+def test_stall_above_dense_limit_uses_jacobi_or_fails_without_sweeps():
+    rp, c, v = P.diffusion7(48, seed=0)
+    h = psc.Hierarchy(rp, c, v, host_only=True, coarse_sweeps=7)
+    inf = h.info()
+    assert inf["coarse_sweeps"] == 7 and inf["rows"][-1] > 2000
+    assert inf["rows"][-1] > 0.9 * inf["rows"][-2]
+    with pytest.raises(psc.PscError) as e:
+        psc.Hierarchy(rp, c, v, host_only=True, coarse_sweeps=0)
+    assert e.value.status == psc.ERR_COARSEN
+    with pytest.raises(psc.PscError) as e:
+        psc.Hierarchy(rp, c, v, host_only=True, coarse_sweeps=-1)
+    assert e.value.status == psc.ERR_ARG

@@ -323,6 +323,78 @@ def test_vcycle_two_level_matches_error_propagation_formula():
     assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
 
 
+def _stall_matrix(n, chain, seed):
+    """SPD matrix that is diagonal except for a 1-D chain on its first rows,
+    so one coarsening step removes at most 3/4 of the chain rows and stalls."""
+    rng = np.random.default_rng(seed)
+    d = 2.5 + rng.random(n)
+    off = np.zeros(n - 1)
+    off[:chain - 1] = -(0.2 + 0.8 * rng.random(chain - 1))
+    A = sp.diags(d) + sp.diags(off, 1, shape=(n, n)) + sp.diags(off, -1, shape=(n, n))
+    A = sp.csr_matrix(A)
+    A.eliminate_zeros()
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.copy()
+
+
+@pytest.mark.parametrize("K", [1, 5, 30])
+def test_stalled_coarsest_jacobi_matches_spectral_closed_form(K):
+    # Coarsening stalls (about 2060 rows after 2200) above the dense-factor limit, so
+    # the coarsest level is solved by K l1-Jacobi sweeps from zero. With
+    # S = M^-1/2 A_c M^-1/2 = U diag(lam) U^T, K sweeps apply
+    # B_c = M^-1/2 U diag((1 - (1 - lam)^K) / lam) U^T M^-1/2 (Richardson
+    # polynomial); the two-level V-cycle is then (I - E) A^-1 with E of eq. (amg).
+    rp, c, v = _stall_matrix(2200, 200, seed=3)
+    h = oracle.Hierarchy(rp, c, v, coarse_sweeps=K)
+    s = h.sizes()
+    assert len(s) == 2 and 2000 < s[1] and s[1] > 0.9 * s[0] and h.coarse_sweeps == K
+    L0, L1 = h.level(0), h.level(1)
+    A = dense(rp, c, v)
+    Ac = dense(L1["rowptr"], L1["col"], L1["val"])
+    ms = np.sqrt(L1["minv"])
+    lam, U = np.linalg.eigh(ms[:, None] * Ac * ms[None, :])
+    assert lam.min() > 0 and lam.max() <= 1 + 1e-14
+    Bc = ms[:, None] * (U * ((1 - (1 - lam) ** K) / lam)) @ U.T * ms[None, :]
+    Pm = prolongator(L0)
+    Mi = L0["minv"]
+    n = s[0]
+    I = np.eye(n)
+    S0 = I - Mi[:, None] * A
+    E = S0 @ (I - Pm @ (Bc @ (Pm.T @ A))) @ S0
+    rng = np.random.default_rng(K)
+    for _ in range(4):
+        b = rng.standard_normal(n)
+        ref = (I - E) @ np.linalg.solve(A, b)
+        np.testing.assert_allclose(h.vcycle(b), ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+def test_stall_below_dense_limit_is_factored_and_above_without_sweeps_fails():
+    rp, c, v = _stall_matrix(1800, 200, seed=4)      # stalls below 2000 rows: dense factor
+    h = oracle.Hierarchy(rp, c, v)
+    s = h.sizes()
+    assert len(s) == 2 and s[1] > 0.9 * s[0] and s[1] <= 2000 and h.coarse_sweeps == 0
+    Lf = h.coarse_factor()
+    Ac = dense(*(h.level(1)[k] for k in ("rowptr", "col", "val")))
+    np.testing.assert_allclose(Lf @ Lf.T, Ac, rtol=0, atol=1e-13)
+    rp, c, v = _stall_matrix(2200, 200, seed=4)
+    with pytest.raises(RuntimeError):
+        oracle.Hierarchy(rp, c, v, coarse_sweeps=0)
+
+
+def test_lognormal_diffusion_stalls_and_pcg_converges():
+    rp, c, v = P.diffusion7(48, seed=0)
+    h = oracle.Hierarchy(rp, c, v)
+    s = h.sizes()
+    assert s[-1] > 2000 and s[-1] > 0.9 * s[-2] and h.coarse_sweeps == 30
+    rng = np.random.default_rng(0)
+    u, w = rng.standard_normal(s[0]), rng.standard_normal(s[0])
+    assert abs(u @ h.vcycle(w) - w @ h.vcycle(u)) <= 1e-12 * abs(u @ h.vcycle(w))
+    b = P.rhs_from_solution(rp, c, v, P.x_true(s[0], 0))
+    r = h.pcg(b)
+    assert r["status"] == oracle.OK and r["relres"] <= 1e-6
+
+
 def test_vcycle_multilevel_symmetric_positive():
     rp, c, v = P.poisson7(16)
     h = oracle.Hierarchy(rp, c, v, coarse_max=30)
