@@ -37,27 +37,43 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(info, form="fp64", fused=False):
-    """Algorithmic bytes per launch of the level-0 kernels (each array once, no padding)."""
+def kernel_bytes(info, form="fp64", fused=False, split=True, dia=True):
+    """Algorithmic bytes per launch of the level-0 kernels (each array once, no padding).
+
+    split: smoothing through A M^-1 (pre) and A P (post), the library default.
+    dia: A and A M^-1 read from hacked DIA (8 bytes per FP64 entry, 4 per FP32
+    entry) instead of hacked ELL (value + 4-byte index), when level 0 has it.
+    """
     N = info["rows"][0]
     Z = info["nnz"][0]
+    Zp = info["ap_nnz"][0] if info["levels"] > 1 else 0
     Nc = info["rows"][1] if info["levels"] > 1 else 0
     v = 8 if form == "fp64" else 4
+    dia = dia and info["dia_slots"][0] > 0
+    a64 = 8 if dia else 12          # the outer operator is always FP64
+    av = v if dia else v + 4        # A M^-1 in the V-cycle's precision
+    if split:
+        # pre: A M^-1, r gathered (fused: r_old and q gathered, r_new written), r_0 written
+        pre = Z * av + 8 * N + v * N if not fused else Z * av + 2 * 8 * N + 8 * N + v * N
+        # post: A P; b (FP64), minv, r_0, p, agg read; x_c gathered; z (FP64) written
+        post = Zp * (v + 4) + 8 * N + 3 * v * N + 4 * N + v * Nc + 8 * N
+    else:
+        pre = Z * (v + 4) + 8 * N + v * N + v * N if not fused else Z * (v + 4) + 2 * 8 * N + v * N + 8 * N + v * N
+        post = Z * (v + 4) + 8 * N + v * N + v * N + 4 * N + v * Nc + 8 * N
     if fused:
         return {
             # A; z and p_old gathered; p_new, q written; x read and written
-            "spmv_dot": Z * 12 + 2 * 8 * N + 2 * 8 * N + 2 * 8 * N,
-            # A; r_old, q, minv gathered; r_new and the level-0 residual written
-            "pre_smooth_l0": Z * 12 + 3 * 8 * N + 2 * 8 * N,
-            "restrict_l0": N * 12 + 8 * N + 8 * Nc,
-            "post_smooth_l0": Z * 12 + 8 * N + 8 * N + 8 * N + 4 * N + 8 * Nc + 8 * N,
+            "spmv_dot": Z * a64 + 2 * 8 * N + 2 * 8 * N + 2 * 8 * N,
+            "pre_smooth_l0": pre,
+            "restrict_l0": N * (v + 4) + v * N + v * Nc,
+            "post_smooth_l0": post,
         }
     return {
-        "spmv_dot": Z * 12 + 2 * 8 * N,                        # A, p gathered, q written
+        "spmv_dot": Z * a64 + 2 * 8 * N,                       # A, p gathered, q written
         "cg_update": 6 * 8 * N,                                # x, r, p, q read; x, r written
-        "pre_smooth_l0": Z * (v + 4) + 8 * N + v * N + v * N,  # A, b (FP64 r), minv, r_0 written
+        "pre_smooth_l0": pre,
         "restrict_l0": N * (v + 4) + v * N + v * Nc,           # R, r_0 gathered, b_1 written
-        "post_smooth_l0": Z * (v + 4) + 8 * N + v * N + v * N + 4 * N + v * Nc + 8 * N,
+        "post_smooth_l0": post,
         "dir_update": 3 * 8 * N,                               # z, p read; p written
     }
 
@@ -112,6 +128,9 @@ def main():
     ap.add_argument("--spmv-reps", type=int, default=50)
     ap.add_argument("--grid-max", type=int, default=0, help="workgroup cap of the streaming kernels")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-dia", action="store_true", help="read level operators from hacked ELL only")
+    ap.add_argument("--no-split", action="store_true",
+                    help="smoothing sweeps gather through A, M^-1 and P instead of A M^-1 and A P")
     ap.add_argument("--unfused", action="store_true", help="one kernel per CG operation instead of the fused PCG iteration")
     ap.add_argument("--train-epochs", type=int, default=6)
     ap.add_argument("--lr", type=float, default=2e-3)
@@ -146,6 +165,10 @@ def main():
         h.tune(psc.TUNE_GRID_MAX, args.grid_max)
     if args.unfused:
         h.tune(psc.TUNE_FUSED_PCG, 0)
+    if args.no_split:
+        h.tune(psc.TUNE_SPLIT, 0)
+    if args.no_dia:
+        h.tune(psc.TUNE_DIA, 0)
     info = h.info()
     log(f"hierarchy {info['rows']} built in {time.time() - t0:.1f}s, opcx {info['operator_complexity']:.4f}")
     dev = torch.device("cuda:0")
@@ -195,7 +218,8 @@ def main():
     xg = x.cpu().numpy()
     err_true = float(np.linalg.norm(xg - xt) / np.linalg.norm(xt))
 
-    kb = kernel_bytes(info, "fp64", fused=not args.unfused and info["levels"] > 1)
+    kb = kernel_bytes(info, "fp64", fused=not args.unfused and info["levels"] > 1, split=not args.no_split,
+                      dia=not args.no_dia)
     kernels = {}
     for name, (cnt, tot) in kt64.items():
         if cnt and name in kb:

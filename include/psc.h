@@ -162,12 +162,15 @@ typedef struct {
     int64_t nnz[PSC_MAX_LEVELS];
     int64_t ell_slots[PSC_MAX_LEVELS];       /* padded hacked-ELL slots of A_l */
     double  operator_complexity;             /* sum nnz(A_l) / nnz(A_0) */
-    double  vcycle_bytes_fp64;               /* algorithmic bytes of one V-cycle */
+    double  vcycle_bytes_fp64;               /* algorithmic bytes of one V-cycle (current kernels) */
     double  vcycle_bytes_fp32;
-    double  spmv_bytes_fp64;                 /* algorithmic bytes of y = A_0 x */
+    double  spmv_bytes_fp64;                 /* algorithmic bytes of y = A_0 x: nnz x (8 + 4 in
+                                                hacked ELL, 8 in hacked DIA) + 16 n */
     double  setup_seconds;                   /* host setup wall time */
     int64_t device_bytes;                    /* device memory held by the handle */
     int32_t coarse_sweeps;                   /* 0: coarsest factored, else l1-Jacobi sweeps */
+    int64_t ap_nnz[PSC_MAX_LEVELS];          /* nonzeros of A_l P_l (0 at the coarsest) */
+    int64_t dia_slots[PSC_MAX_LEVELS];       /* hacked-DIA slots of A_l, 0 when A_l has no DIA copy */
 } psc_hier_stats;
 
 int psc_hier_info(const psc_hier* h, psc_hier_stats* s);
@@ -225,6 +228,18 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
 /* PSC_TUNE_SPMV2 (default 0): the plain SpMV and the restriction process two
  * slices per wavefront concurrently. */
 #define PSC_TUNE_SPMV2 5
+/* PSC_TUNE_SPLIT (default 1): the smoothing sweeps use two operators stored
+ * at build, A M^-1 (pre-smoothing, one gathered vector) and A P
+ * (post-smoothing with prolongation: with r = b - A M^-1 b,
+ * x = M^-1 b + P x_c + M^-1 (r - A P x_c)), the same sweeps up to rounding;
+ * 0 gathers through A, M^-1, P and the aggregate map instead. Both paths take
+ * the other tuning keys' kernels only when 0. */
+#define PSC_TUNE_SPLIT 6
+/* PSC_TUNE_DIA (default 1): kernels that support it read a level operator
+ * (and A M^-1) from its hacked-DIA copy, which the build keeps for a level
+ * when its diagonal slots are at most 4/3 of its ELL slots (7-point
+ * stencils: 8 bytes per entry instead of 12); 0 reads hacked ELL. */
+#define PSC_TUNE_DIA 7
 int psc_tune(psc_hier* h, int32_t key, int32_t value);
 
 void psc_hier_free(psc_hier* h);

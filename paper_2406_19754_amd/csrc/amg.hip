@@ -38,6 +38,7 @@
 #include <functional>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/psc.h"
@@ -482,14 +483,61 @@ __device__ __forceinline__ void vchunk_range(long long total, long long& lo, lon
     if (lo > total) lo = total;
 }
 
+// Row sum over one hacked-DIA row: sum_k val[k] * g(row + offs[k]) in
+// ascending offset (= column) order. Offsets are wave-uniform (scalar
+// loads); a column that falls outside [0, ncols) belongs to a zero value and
+// is clamped to a valid index. Slices of at most 8 diagonals issue every
+// value load before the first gather.
+template <typename T, typename G>
+__device__ __forceinline__ T dia_row(const Dia<T>& A, long long s, int lane, G g) {
+    const int k0 = A.start[s];
+    const int nd = A.start[s + 1] - k0;
+    const int row = (int)(s * SLICE) + lane;
+    const int cmax = (int)A.ncols - 1;
+    const T* vp = A.val + (long long)k0 * SLICE + lane;
+    const int* op = A.offs + k0;
+    T acc = T(0);
+    if (nd <= 8) {
+        T v[8];
+        int c[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            if (k < nd) {
+                v[k] = ntload(vp + k * SLICE);
+                c[k] = min(max(row + op[k], 0), cmax);
+            }
+        }
+        T gv[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (k < nd) gv[k] = g(c[k]);
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (k < nd) acc += v[k] * gv[k];
+        return acc;
+    }
+    for (int k = 0; k < nd; k++) {
+        const T v0 = ntload(vp + k * SLICE);
+        acc += v0 * g(min(max(row + op[k], 0), cmax));
+    }
+    return acc;
+}
+
+// Row sum of either storage format.
+template <typename T, typename G>
+__device__ __forceinline__ T mat_row(const Ell<T>& A, long long s, int lane, G g) { return ell_row(A, s, lane, g); }
+template <typename T, typename G>
+__device__ __forceinline__ T mat_row(const Dia<T>& A, long long s, int lane, G g) { return dia_row(A, s, lane, g); }
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
 
 // y = A x
-template <typename T, bool BUF = false>
-__global__ __launch_bounds__(WG) void k_spmv(Ell<T> A, const T* __restrict__ x, T* __restrict__ y,
-                                             Gate g) {
+template <typename M, bool BUF = false>
+__global__ __launch_bounds__(WG) void k_spmv(M A, const typename M::value_type* __restrict__ x,
+                                             typename M::value_type* __restrict__ y, Gate g) {
+    using T = typename M::value_type;
     if (gate_skip(g)) return;
     long long lo, hi;
     chunk_range(A.nslices, lo, hi);
@@ -498,7 +546,7 @@ __global__ __launch_bounds__(WG) void k_spmv(Ell<T> A, const T* __restrict__ x, 
     for (long long s = lo + w; s < hi; s += WG / 64) {
         T acc;
         if constexpr (BUF) acc = ell_row_buf(A, s, lane, [&](int c) { return bx[c]; });
-        else acc = ell_row(A, s, lane, [&](int c) { return x[c]; });
+        else acc = mat_row(A, s, lane, [&](int c) { return x[c]; });
         long long row = s * SLICE + lane;
         if (row < A.nrows) y[row] = acc;
     }
@@ -529,7 +577,8 @@ __global__ __launch_bounds__(WG) void k_spmv2(Ell<T> A, const T* __restrict__ x,
 }
 
 // q = A p with partials (p.q, p.r); r may be NULL.
-__global__ __launch_bounds__(WG) void k_spmv_dot(Ell<double> A, const double* __restrict__ p,
+template <typename M>
+__global__ __launch_bounds__(WG) void k_spmv_dot(M A, const double* __restrict__ p,
                                                  double* __restrict__ q, const double* __restrict__ r,
                                                  Red R) {
     if (skip_red(R)) return;
@@ -538,7 +587,7 @@ __global__ __launch_bounds__(WG) void k_spmv_dot(Ell<double> A, const double* __
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double s0 = 0.0, s1 = 0.0;
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        double acc = ell_row(A, s, lane, [&](int c) { return p[c]; });
+        double acc = mat_row(A, s, lane, [&](int c) { return p[c]; });
         long long row = s * SLICE + lane;
         if (row < A.nrows) {
             q[row] = acc;
@@ -552,7 +601,8 @@ __global__ __launch_bounds__(WG) void k_spmv_dot(Ell<double> A, const double* __
 
 // r = b - A x with partials (b.b, r.r). With only_if_check, runs only when
 // the control block asks for a true-residual check.
-__global__ __launch_bounds__(WG) void k_resid(Ell<double> A, const double* __restrict__ b,
+template <typename M>
+__global__ __launch_bounds__(WG) void k_resid(M A, const double* __restrict__ b,
                                               const double* __restrict__ x, double* __restrict__ r,
                                               int only_if_check, Red R) {
     if (skip_red(R)) return;
@@ -562,7 +612,7 @@ __global__ __launch_bounds__(WG) void k_resid(Ell<double> A, const double* __res
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double s0 = 0.0, s1 = 0.0;
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        double acc = ell_row(A, s, lane, [&](int c) { return x[c]; });
+        double acc = mat_row(A, s, lane, [&](int c) { return x[c]; });
         long long row = s * SLICE + lane;
         if (row < A.nrows) {
             double bi = b[row];
@@ -635,8 +685,8 @@ __global__ __launch_bounds__(WG) void k_pupdate(long long n, double* __restrict_
 // for every gathered neighbour), q = A p_new, the x update deferred from the
 // previous iteration x += alpha_prev p_old, and the partial p_new.q.
 // alpha in the control block still holds alpha_prev here (0 at the start).
-template <bool BUF = false>
-__global__ __launch_bounds__(WG) void k_spmv_pfuse(Ell<double> A, const double* __restrict__ z,
+template <typename M, bool BUF = false>
+__global__ __launch_bounds__(WG) void k_spmv_pfuse(M A, const double* __restrict__ z,
                                                    const double* __restrict__ pold, double* __restrict__ pnew,
                                                    double* __restrict__ q, double* __restrict__ x, Red R) {
     if (skip_red(R)) return;
@@ -649,7 +699,7 @@ __global__ __launch_bounds__(WG) void k_spmv_pfuse(Ell<double> A, const double* 
     for (long long s = lo + w; s < hi; s += WG / 64) {
         double acc;
         if constexpr (BUF) acc = ell_row_buf(A, s, lane, [&](int c) { return fma(beta, bp[c], bz[c]); });
-        else acc = ell_row(A, s, lane, [&](int c) { return fma(beta, pold[c], z[c]); });
+        else acc = mat_row(A, s, lane, [&](int c) { return fma(beta, pold[c], z[c]); });
         long long row = s * SLICE + lane;
         if (row < A.nrows) {
             const double po = pold[row];
@@ -699,8 +749,8 @@ __global__ __launch_bounds__(WG) void k_update_pre(Ell<double> A, const double* 
 // Fused FCG(1), first pass: p_new = z - beta p_old (p_new = z without a
 // previous direction), q = A p_new, the deferred x += alpha_prev p_old, and
 // the partials (p_new.q, p_new.r_old).
-template <bool BUF = false>
-__global__ __launch_bounds__(WG) void k_spmv_pfuse_fcg(Ell<double> A, const double* __restrict__ z,
+template <typename M, bool BUF = false>
+__global__ __launch_bounds__(WG) void k_spmv_pfuse_fcg(M A, const double* __restrict__ z,
                                                        const double* __restrict__ pold, double* __restrict__ pnew,
                                                        double* __restrict__ q, double* __restrict__ x,
                                                        const double* __restrict__ rold, Red R) {
@@ -714,7 +764,7 @@ __global__ __launch_bounds__(WG) void k_spmv_pfuse_fcg(Ell<double> A, const doub
     for (long long s = lo + w; s < hi; s += WG / 64) {
         double acc;
         if constexpr (BUF) acc = ell_row_buf(A, s, lane, [&](int c) { return fma(nb, bp[c], bz[c]); });
-        else acc = ell_row(A, s, lane, [&](int c) { return fma(nb, pold[c], z[c]); });
+        else acc = mat_row(A, s, lane, [&](int c) { return fma(nb, pold[c], z[c]); });
         long long row = s * SLICE + lane;
         if (row < A.nrows) {
             const double po = pold[row];
@@ -761,7 +811,8 @@ __global__ __launch_bounds__(WG) void k_update_pre_t(Ell<T> A, const T* __restri
 // Fused FCG true residual (only when the recursive test passed): x lags by
 // its last update, so r = b - A (x + alpha p) with the sum formed for every
 // gathered neighbour; the partial ||r||^2 feeds FIN_TRUE.
-__global__ __launch_bounds__(WG) void k_resid_lag(Ell<double> A, const double* __restrict__ b,
+template <typename M>
+__global__ __launch_bounds__(WG) void k_resid_lag(M A, const double* __restrict__ b,
                                                   const double* __restrict__ x, const double* __restrict__ p,
                                                   double* __restrict__ r, Red R) {
     if (skip_red(R) || !R.ctl->check) return;
@@ -771,7 +822,7 @@ __global__ __launch_bounds__(WG) void k_resid_lag(Ell<double> A, const double* _
     const int lane = threadIdx.x & 63, w = wave_id();
     double s0 = 0.0;
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        double acc = ell_row(A, s, lane, [&](int c) { return fma(alpha, p[c], x[c]); });
+        double acc = mat_row(A, s, lane, [&](int c) { return fma(alpha, p[c], x[c]); });
         long long row = s * SLICE + lane;
         if (row < A.nrows) {
             const double ri = b[row] - acc;
@@ -901,6 +952,82 @@ __global__ __launch_bounds__(WG) void k_post(Ell<T> A, const T* __restrict__ min
     if (R.fin != FIN_NONE) block_partial(s0, 0.0, R.part);
 }
 
+// ---- split-operator forms of the smoothing sweeps --------------------------
+// With the scaled operator AM = A M^-1 (values a_ij minv_j in A's layout) the
+// pre-smoothing residual gathers one vector; with the prolongated operator
+// AP = A P (aggregate columns) and that residual r = b - A M^-1 b, the
+// post-smoothing sweep gathers only the coarse correction:
+//   A (M^-1 b + P xc) = b - r + AP xc,  so
+//   x_i = minv_i b_i + p_i xc[agg_i] + minv_i (r_i - sum_J ap_iJ xc_J).
+// These give the sweeps of k_pre / k_post up to rounding.
+
+// r_i = b_i - sum_j am_ij b_j
+template <typename M, typename TB>
+__global__ __launch_bounds__(WG) void k_pre_s(M AM, const TB* __restrict__ b, typename M::value_type* __restrict__ r,
+                                              Gate g) {
+    using T = typename M::value_type;
+    if (gate_skip(g)) return;
+    long long lo, hi;
+    chunk_range(AM.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        const T acc = mat_row(AM, s, lane, [&](int c) { return (T)b[c]; });
+        const long long row = s * SLICE + lane;
+        if (row < AM.nrows) r[row] = (T)b[row] - acc;
+    }
+}
+
+// Fused update + level-0 pre-smoothing with AM in precision T:
+// r_new = r_old - alpha q (FP64), r0 = (T)r_new - AM_T (T)r_new, partial ||r_new||^2.
+template <typename M>
+__global__ __launch_bounds__(WG) void k_update_pre_s(M AM, const double* __restrict__ rold,
+                                                     const double* __restrict__ q, double* __restrict__ rnew,
+                                                     typename M::value_type* __restrict__ r0, Red R) {
+    using T = typename M::value_type;
+    if (skip_red(R)) return;
+    const double nalpha = -R.ctl->alpha;
+    long long lo, hi;
+    chunk_range(AM.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    double s0 = 0.0;
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        const T acc = mat_row(AM, s, lane, [&](int c) { return (T)fma(nalpha, q[c], rold[c]); });
+        const long long row = s * SLICE + lane;
+        if (row < AM.nrows) {
+            const double rn = fma(nalpha, q[row], rold[row]);
+            rnew[row] = rn;
+            r0[row] = (T)rn - acc;
+            s0 += rn * rn;
+        }
+    }
+    block_partial(s0, 0.0, R.part);
+}
+
+// Post-smoothing with prolongation through AP (see above); with
+// R.fin != FIN_NONE also the partial sum of x_i * d_i.
+template <typename T, typename TB, typename TX>
+__global__ __launch_bounds__(WG) void k_post_s(Ell<T> AP, const T* __restrict__ minv, const TB* __restrict__ b,
+                                               const T* __restrict__ r, const int* __restrict__ agg,
+                                               const T* __restrict__ pv, const T* __restrict__ xc,
+                                               TX* __restrict__ x, const double* __restrict__ d, Red R) {
+    if (skip_red(R)) return;
+    long long lo, hi;
+    chunk_range(AP.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    double s0 = 0.0;
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        const T acc = ell_row(AP, s, lane, [&](int c) { return xc[c]; });
+        const long long row = s * SLICE + lane;
+        if (row < AP.nrows) {
+            const T mi = minv[row];
+            const T xi = mi * (T)b[row] + pv[row] * xc[agg[row]] + mi * (r[row] - acc);
+            x[row] = (TX)xi;
+            if (d) s0 += (double)(TX)xi * d[row];
+        }
+    }
+    if (R.fin != FIN_NONE) block_partial(s0, 0.0, R.part);
+}
+
 // Coarsest level: x = A_L^{-1} b with the explicit inverse (column-major), FP64.
 template <typename TB, typename TX>
 __global__ __launch_bounds__(WG) void k_coarse(int n, const double* __restrict__ invT,
@@ -921,8 +1048,8 @@ __global__ __launch_bounds__(WG) void k_coarse(int n, const double* __restrict__
 // stalls above the dense-factor limit). One sweep from x_in:
 //   x_out_i = x_in_i + minv_i (b_i - sum_j a_ij x_in_j);
 // x_in == nullptr stands for the zero guess (x_out = minv b).
-template <typename TB, typename TX>
-__global__ __launch_bounds__(WG) void k_jacobi(Ell<double> A, const double* __restrict__ minv,
+template <typename M, typename TB, typename TX>
+__global__ __launch_bounds__(WG) void k_jacobi(M A, const double* __restrict__ minv,
                                                const TB* __restrict__ b, const double* __restrict__ xin,
                                                TX* __restrict__ xout, Gate g) {
     if (gate_skip(g)) return;
@@ -935,7 +1062,7 @@ __global__ __launch_bounds__(WG) void k_jacobi(Ell<double> A, const double* __re
             if (row < A.nrows) xout[row] = (TX)(minv[row] * (double)b[row]);
             continue;
         }
-        double acc = ell_row(A, s, lane, [&](int c) { return xin[c]; });
+        double acc = mat_row(A, s, lane, [&](int c) { return xin[c]; });
         if (row < A.nrows) xout[row] = (TX)(xin[row] + minv[row] * ((double)b[row] - acc));
     }
 }
@@ -957,14 +1084,35 @@ struct DevEll {
     T* val = nullptr;
     int* col = nullptr;
     float* val32 = nullptr;
-    long long nrows = 0, nslices = 0, slots = 0, ncols = 0;
+    long long nrows = 0, nslices = 0, slots = 0, ncols = 0, nnz = 0;
     Ell<T> view() const { return Ell<T>{off, val, col, nrows, nslices, ncols}; }
     Ell<float> view32() const { return Ell<float>{off, val32, col, nrows, nslices, ncols}; }
 };
 
+// Hacked-DIA copy of a level operator; the scaled operator A M^-1 shares
+// its start and offset arrays.
+struct DevDia {
+    int* start = nullptr;
+    int* offs = nullptr;
+    double* val = nullptr;
+    float* val32 = nullptr;
+    long long nrows = 0, nslices = 0, ncols = 0, slots = 0;
+    bool on() const { return start != nullptr; }
+    Dia<double> view(const double* v) const { return Dia<double>{start, offs, v, nrows, nslices, ncols}; }
+    Dia<float> view32(const float* v) const { return Dia<float>{start, offs, v, nrows, nslices, ncols}; }
+};
+
 struct DevLevel {
     long long n = 0, nc = 0, nnz = 0;
+    DevDia Ad;                            // A in hacked DIA when that stores fewer bytes
+    double* amd = nullptr;                // A M^-1 values in Ad's layout
+    float* amd32 = nullptr;
     DevEll<double> A, R;                  // R = P^T (coarse rows, members as columns)
+    DevEll<double> AP;                    // A P (rows of A, aggregate columns)
+    double* am = nullptr;                 // A M^-1 values in A's hacked-ELL layout
+    float* am32 = nullptr;
+    Ell<double> am_view() const { Ell<double> e = A.view(); e.val = am; return e; }
+    Ell<float> am_view32() const { Ell<float> e = A.view32(); e.val = am32; return e; }
     double* minv = nullptr;
     float* minv32 = nullptr;
     int* agg = nullptr;
@@ -999,6 +1147,8 @@ struct psc_hier {
     bool unroll4 = false;                 // gather in batches of 4 in the FP64 post / update+pre kernels
     int bufload = 2;                      // buffer descriptors: 0 none, 1 all ELL kernels, 2 post-smoothing only
     bool spmv2 = false;                   // plain SpMV / restriction: two slices per wavefront
+    bool split = true;                    // smoothing sweeps through A M^-1 and A P
+    bool dia = true;                      // use the hacked-DIA copies where a level has them
     std::vector<void*> allocs;
     int64_t device_bytes = 0;
     double setup_seconds = 0.0;
@@ -1057,6 +1207,7 @@ static int upload_ell(psc_hier* h, DevEll<double>& E, int64_t nrows, int64_t nco
     E.ncols = ncols;
     E.nslices = (long long)off.size() - 1;
     E.slots = off.back();
+    E.nnz = rp[nrows];
     int st;
     if ((st = upload(h, &E.off, off.data(), off.size()))) return st;
     if ((st = upload(h, &E.val, val.data(), val.size()))) return st;
@@ -1086,6 +1237,30 @@ static int grid_of(const psc_hier* h, long long units_per_block_4, long long tot
 }
 
 static inline int grid_ell(const psc_hier* h, long long nslices) { return grid_of(h, 4, nslices); }
+
+// Call f with the level operator (FP64 / FP32) or its scaled form A M^-1 in
+// the storage the level uses: hacked DIA when present and enabled, else
+// hacked ELL. Both have the same slices, so grids do not change.
+template <typename F>
+static void with_A(const psc_hier* h, const DevLevel& V, F f) {
+    if (h->dia && V.Ad.on()) f(V.Ad.view(V.Ad.val));
+    else f(V.A.view());
+}
+template <typename F>
+static void with_A32(const psc_hier* h, const DevLevel& V, F f) {
+    if (h->dia && V.Ad.on()) f(V.Ad.view32(V.Ad.val32));
+    else f(V.A.view32());
+}
+template <typename F>
+static void with_AM(const psc_hier* h, const DevLevel& V, F f) {
+    if (h->dia && V.Ad.on()) f(V.Ad.view(V.amd));
+    else f(V.am_view());
+}
+template <typename F>
+static void with_AM32(const psc_hier* h, const DevLevel& V, F f) {
+    if (h->dia && V.Ad.on()) f(V.Ad.view32(V.amd32));
+    else f(V.am_view32());
+}
 static inline int grid_vec(const psc_hier* h, long long n) { return grid_of(h, 1024, n); }
 
 // ---------------------------------------------------------------------------
@@ -1131,31 +1306,52 @@ static void timing_collect(psc_hier* h) {
 // launch helpers (variant selection)
 // ---------------------------------------------------------------------------
 
+// Pre-smoothing from zero and its residual on level V, in the V-cycle's
+// precision T (r = b - A M^-1 b).
 template <typename T, typename TB>
-static void launch_pre(psc_hier* h, const Ell<T>& A, const T* minv, const TB* b, T* r, Gate g) {
-    const int gr = grid_ell(h, A.nslices);
+static void launch_pre(psc_hier* h, const DevLevel& V, const TB* b, T* r, Gate g) {
+    const int gr = grid_ell(h, V.A.nslices);
+    constexpr bool f32 = std::is_same<T, float>::value;
+    if (h->split) {
+        auto go = [&](auto AM) { k_pre_s<decltype(AM), TB><<<gr, WG, 0, h->stream>>>(AM, b, r, g); };
+        if constexpr (f32) with_AM32(h, V, go);
+        else with_AM(h, V, go);
+        return;
+    }
+    const T* minv;
+    Ell<T> A;
+    if constexpr (f32) { minv = V.minv32; A = V.A.view32(); }
+    else { minv = V.minv; A = V.A.view(); }
     if (h->bufload == 1) k_pre<T, TB, true><<<gr, WG, 0, h->stream>>>(A, minv, b, r, g);
     else k_pre<T, TB, false><<<gr, WG, 0, h->stream>>>(A, minv, b, r, g);
 }
 
-template <typename T>
-static void launch_spmv(psc_hier* h, const Ell<T>& A, const T* x, T* y, Gate g) {
-    if (h->spmv2) {
-        // two slices per wavefront: half the workgroups of the one-slice grid
-        const int gr = grid_of(h, 8, A.nslices);
-        k_spmv2<T><<<gr, WG, 0, h->stream>>>(A, x, y, g);
-        return;
-    }
+// y = A x for an operator in either storage; the variant knobs apply to ELL.
+template <typename M>
+static void launch_spmv(psc_hier* h, const M& A, const typename M::value_type* x, typename M::value_type* y,
+                        Gate g) {
+    using T = typename M::value_type;
     const int gr = grid_ell(h, A.nslices);
-    if (h->bufload == 1) k_spmv<T, true><<<gr, WG, 0, h->stream>>>(A, x, y, g);
-    else k_spmv<T, false><<<gr, WG, 0, h->stream>>>(A, x, y, g);
+    if constexpr (std::is_same<M, Ell<T>>::value) {
+        if (h->spmv2) {
+            // two slices per wavefront: half the workgroups of the one-slice grid
+            k_spmv2<T><<<grid_of(h, 8, A.nslices), WG, 0, h->stream>>>(A, x, y, g);
+            return;
+        }
+        if (h->bufload == 1) {
+            k_spmv<M, true><<<gr, WG, 0, h->stream>>>(A, x, y, g);
+            return;
+        }
+    }
+    k_spmv<M, false><<<gr, WG, 0, h->stream>>>(A, x, y, g);
 }
 
 template <typename T, typename TB, typename TX>
-static void launch_post(psc_hier* h, const Ell<T>& A, const T* minv, const TB* b, const int* agg, const T* pv,
-                        const T* xc, long long nc, TX* x, const double* d, const Red& R) {
+static void launch_post(psc_hier* h, const Ell<T>& A, const Ell<T>& AP, const T* minv, const TB* b, const T* r,
+                        const int* agg, const T* pv, const T* xc, long long nc, TX* x, const double* d, const Red& R) {
     const int gr = grid_ell(h, A.nslices);
-    if (h->bufload >= 1) k_post<T, TB, TX, 8, true><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
+    if (h->split) k_post_s<T, TB, TX><<<gr, WG, 0, h->stream>>>(AP, minv, b, r, agg, pv, xc, x, d, R);
+    else if (h->bufload >= 1) k_post<T, TB, TX, 8, true><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
     else if (h->unroll4) k_post<T, TB, TX, 4, false><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
     else k_post<T, TB, TX, 8, false><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
 }
@@ -1196,15 +1392,17 @@ static void coarse_solve(psc_hier* h, const TB* b, TX* x, Gate g) {
         k_coarse<TB, TX><<<1, WG, 0, h->stream>>>(h->coarse_n, h->coarse_invT, b, x, g);
         return;
     }
-    const Ell<double> A = C.A.view();
-    const int gr = grid_ell(h, A.nslices);
-    const double* xin = nullptr;
-    for (int k = 1; k < K; k++) {
-        double* xo = ((K - k) % 2 == 0) ? C.x : C.r;
-        k_jacobi<TB, double><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, xo, g);
-        xin = xo;
-    }
-    k_jacobi<TB, TX><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, x, g);
+    const int gr = grid_ell(h, C.A.nslices);
+    with_A(h, C, [&](auto A) {
+        using M = decltype(A);
+        const double* xin = nullptr;
+        for (int k = 1; k < K; k++) {
+            double* xo = ((K - k) % 2 == 0) ? C.x : C.r;
+            k_jacobi<M, TB, double><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, xo, g);
+            xin = xo;
+        }
+        k_jacobi<M, TB, TX><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, x, g);
+    });
 }
 
 // z = B r on level 0. prec: PSC_FP64 / PSC_FP32. fin/d: optional fused dot
@@ -1233,7 +1431,7 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
             const double* b = l == 0 ? r0 : V.b;
             if (!(l == 0 && skip_pre0)) {
                 TimeScope t(h, l == 0 ? 2 : 7);
-                launch_pre(h, V.A.view(), V.minv, b, V.r, g);
+                launch_pre(h, V, b, V.r, g);
             }
             {
                 TimeScope t(h, l == 0 ? 3 : 7);
@@ -1251,8 +1449,9 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
             double* x = l == 0 ? z0 : V.x;
             {
                 TimeScope t(h, l == 0 ? 4 : 7);
-                launch_post(h, V.A.view(), (const double*)V.minv, b, V.agg, (const double*)V.pval,
-                            (const double*)h->lev[l + 1].x, V.nc, x, l == 0 ? d : nullptr, l == 0 ? R : R0);
+                launch_post(h, V.A.view(), V.AP.view(), (const double*)V.minv, b, (const double*)V.r, V.agg,
+                            (const double*)V.pval, (const double*)h->lev[l + 1].x, V.nc, x, l == 0 ? d : nullptr,
+                            l == 0 ? R : R0);
             }
             if (l == 0) finish(h, R, grid_ell(h, V.A.nslices));
         }
@@ -1261,8 +1460,8 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
             DevLevel& V = h->lev[l];
             if (!(l == 0 && skip_pre0)) {
                 TimeScope t(h, l == 0 ? 2 : 7);
-                if (l == 0) launch_pre(h, V.A.view32(), (const float*)V.minv32, r0, V.r32, g);
-                else launch_pre(h, V.A.view32(), (const float*)V.minv32, (const float*)V.b32, V.r32, g);
+                if (l == 0) launch_pre(h, V, r0, V.r32, g);
+                else launch_pre(h, V, (const float*)V.b32, V.r32, g);
             }
             {
                 TimeScope t(h, l == 0 ? 3 : 7);
@@ -1279,15 +1478,15 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
             if (l == 0) {
                 {
                     TimeScope t(h, 4);
-                    launch_post(h, V.A.view32(), (const float*)V.minv32, r0, V.agg, (const float*)V.pval32,
-                                (const float*)h->lev[1].x32, V.nc, z0, d, R);
+                    launch_post(h, V.A.view32(), V.AP.view32(), (const float*)V.minv32, r0, (const float*)V.r32, V.agg,
+                                (const float*)V.pval32, (const float*)h->lev[1].x32, V.nc, z0, d, R);
                 }
                 finish(h, R, grid_ell(h, V.A.nslices));
             } else {
                 TimeScope t(h, 7);
-                launch_post(h, V.A.view32(), (const float*)V.minv32, (const float*)V.b32, V.agg,
-                            (const float*)V.pval32, (const float*)h->lev[l + 1].x32, V.nc, V.x32,
-                            (const double*)nullptr, R0);
+                launch_post(h, V.A.view32(), V.AP.view32(), (const float*)V.minv32, (const float*)V.b32,
+                            (const float*)V.r32, V.agg, (const float*)V.pval32, (const float*)h->lev[l + 1].x32, V.nc,
+                            V.x32, (const double*)nullptr, R0);
             }
         }
     }
@@ -1350,14 +1549,20 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             {
                 TimeScope t(h, 0);
                 if (h->bufload == 1)
-                    k_spmv_pfuse<true><<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, red_of(h, FIN_ALPHA_PCG));
+                    k_spmv_pfuse<Ell<double>, true><<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, red_of(h, FIN_ALPHA_PCG));
                 else
-                    k_spmv_pfuse<false><<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, red_of(h, FIN_ALPHA_PCG));
+                    with_A(h, L0, [&](auto A) {
+                        k_spmv_pfuse<decltype(A)><<<ge, WG, 0, st>>>(A, h->z, pold, pnew, h->q, h->xs, red_of(h, FIN_ALPHA_PCG));
+                    });
             }
             finish(h, red_of(h, FIN_ALPHA_PCG), ge);
             {
                 TimeScope t(h, 2);
-                if (h->bufload == 1)
+                if (h->split)
+                    with_AM(h, L0, [&](auto AM) {
+                        k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_PCG));
+                    });
+                else if (h->bufload == 1)
                     k_update_pre<8, true><<<ge, WG, 0, st>>>(L0.A.view(), L0.minv, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_PCG));
                 else if (h->unroll4)
                     k_update_pre<4><<<ge, WG, 0, st>>>(L0.A.view(), L0.minv, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_PCG));
@@ -1379,14 +1584,25 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             {
                 TimeScope t(h, 0);
                 if (h->bufload == 1)
-                    k_spmv_pfuse_fcg<true><<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, rold, red_of(h, FIN_ALPHA_FCG));
+                    k_spmv_pfuse_fcg<Ell<double>, true><<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, rold, red_of(h, FIN_ALPHA_FCG));
                 else
-                    k_spmv_pfuse_fcg<false><<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, rold, red_of(h, FIN_ALPHA_FCG));
+                    with_A(h, L0, [&](auto A) {
+                        k_spmv_pfuse_fcg<decltype(A)><<<ge, WG, 0, st>>>(A, h->z, pold, pnew, h->q, h->xs, rold, red_of(h, FIN_ALPHA_FCG));
+                    });
             }
             finish(h, red_of(h, FIN_ALPHA_FCG), ge);
             {
                 TimeScope t(h, 2);
-                if (f32) {
+                if (h->split) {
+                    if (f32)
+                        with_AM32(h, L0, [&](auto AM) {
+                            k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, L0.r32, red_of(h, FIN_UPDATE_FCG));
+                        });
+                    else
+                        with_AM(h, L0, [&](auto AM) {
+                            k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_FCG));
+                        });
+                } else if (f32) {
                     if (h->bufload == 1)
                         k_update_pre_t<float, true><<<ge, WG, 0, st>>>(L0.A.view32(), L0.minv32, rold, h->q, rnew, L0.r32, red_of(h, FIN_UPDATE_FCG));
                     else
@@ -1399,12 +1615,14 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
                 }
             }
             finish(h, red_of(h, FIN_UPDATE_FCG), ge);
-            k_resid_lag<<<ge, WG, 0, st>>>(L0.A.view(), h->bs, h->xs, pnew, rnew, red_of(h, FIN_TRUE));
+            with_A(h, L0, [&](auto A) {
+                k_resid_lag<decltype(A)><<<ge, WG, 0, st>>>(A, h->bs, h->xs, pnew, rnew, red_of(h, FIN_TRUE));
+            });
             finish(h, red_of(h, FIN_TRUE), ge);
             // after a residual replacement, redo the level-0 pre-smoothing from the true residual
             const Gate gr{h->ctl, GATE_REDO};
-            if (f32) launch_pre(h, L0.A.view32(), (const float*)L0.minv32, (const double*)rnew, L0.r32, gr);
-            else launch_pre(h, L0.A.view(), (const double*)L0.minv, (const double*)rnew, L0.r, gr);
+            if (f32) launch_pre(h, L0, (const double*)rnew, L0.r32, gr);
+            else launch_pre(h, L0, (const double*)rnew, L0.r, gr);
             vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, gd, true);
         }
         return PSC_OK;
@@ -1412,7 +1630,9 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
     if (form == 0) {
         {
             TimeScope t(h, 0);
-            k_spmv_dot<<<ge, WG, 0, st>>>(L0.A.view(), h->p, h->q, nullptr, red_of(h, FIN_ALPHA_PCG));
+            with_A(h, L0, [&](auto A) {
+                k_spmv_dot<decltype(A)><<<ge, WG, 0, st>>>(A, h->p, h->q, nullptr, red_of(h, FIN_ALPHA_PCG));
+            });
         }
         finish(h, red_of(h, FIN_ALPHA_PCG), ge);
         {
@@ -1445,7 +1665,9 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
     }
     {
         TimeScope t(h, 0);
-        k_spmv_dot<<<ge, WG, 0, st>>>(L0.A.view(), h->p, h->q, h->r, red_of(h, FIN_ALPHA_FCG));
+        with_A(h, L0, [&](auto A) {
+            k_spmv_dot<decltype(A)><<<ge, WG, 0, st>>>(A, h->p, h->q, h->r, red_of(h, FIN_ALPHA_FCG));
+        });
     }
     finish(h, red_of(h, FIN_ALPHA_FCG), ge);
     {
@@ -1453,7 +1675,9 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
         k_update<<<gv, WG, 0, st>>>(n, h->xs, h->r, h->p, h->q, red_of(h, FIN_UPDATE_FCG));
     }
     finish(h, red_of(h, FIN_UPDATE_FCG), gv);
-    k_resid<<<ge, WG, 0, st>>>(L0.A.view(), h->bs, h->xs, h->r, 1, red_of(h, FIN_TRUE));
+    with_A(h, L0, [&](auto A) {
+        k_resid<decltype(A)><<<ge, WG, 0, st>>>(A, h->bs, h->xs, h->r, 1, red_of(h, FIN_TRUE));
+    });
     finish(h, red_of(h, FIN_TRUE), ge);
     return PSC_OK;
 }
@@ -1499,7 +1723,9 @@ static int solve_begin(psc_hier* h, int form, const double* b_dev, const double*
     HIPCHK(hipMemcpyAsync(h->bs, b_dev, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(h->xs, x_dev, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     k_ctl_init<<<1, 64, 0, st>>>(h->ctl, h->hctl_dev, rtol, maxit, form);
-    k_resid<<<ge, WG, 0, st>>>(L0.A.view(), h->bs, h->xs, h->r, 0, red_of(h, FIN_INIT));
+    with_A(h, L0, [&](auto A) {
+        k_resid<decltype(A)><<<ge, WG, 0, st>>>(A, h->bs, h->xs, h->r, 0, red_of(h, FIN_INIT));
+    });
     finish(h, red_of(h, FIN_INIT), ge);
     HIPCHK(hipGetLastError());
     return read_ctl(h, c);
@@ -1578,7 +1804,9 @@ static int solve_impl(psc_hier* h, int form, psc_net* net, const double* b_dev, 
     // true residual in FP64 (ungated: runs after convergence)
     {
         Red Rs{h->part, h->ctl, nullptr, FIN_STORE, GATE_NONE};
-        k_resid<<<ge, WG, 0, st>>>(L0.A.view(), h->bs, h->xs, h->q, 0, Rs);
+        with_A(h, L0, [&](auto A) {
+            k_resid<decltype(A)><<<ge, WG, 0, st>>>(A, h->bs, h->xs, h->q, 0, Rs);
+        });
         finish(h, Rs, ge);
     }
     HIPCHK(hipMemcpyAsync(x_dev, h->xs, n * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -1762,6 +1990,38 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
         D.nnz = H.rp[H.n];
         if ((st = upload_ell(h.get(), D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32))) return st;
         if ((st = upload(h.get(), &D.minv, H.minv.data(), H.n))) return st;
+        // hacked-DIA copy when it stores at most 4/3 of the ELL slots (8 instead
+        // of 12 bytes per slot: at least 11 % fewer bytes); A M^-1 shares its layout
+        std::vector<int32_t> dstart, doffs;
+        std::vector<double> dval;
+        if (pack_dia(H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), D.A.slots * 4 / 3, dstart, doffs, dval)) {
+            DevDia& G = D.Ad;
+            G.nrows = H.n;
+            G.ncols = H.n;
+            G.nslices = (long long)dstart.size() - 1;
+            G.slots = (long long)dval.size();
+            if ((st = upload(h.get(), &G.start, dstart.data(), dstart.size()))) return st;
+            if ((st = upload(h.get(), &G.offs, doffs.data(), doffs.size()))) return st;
+            if ((st = upload(h.get(), &G.val, dval.data(), dval.size()))) return st;
+            if (f32) {
+                auto v32 = to32(dval);
+                if ((st = upload(h.get(), &G.val32, v32.data(), v32.size()))) return st;
+            }
+            if (l < L - 1) {
+                std::vector<double> sv(H.rp[H.n]);
+#pragma omp parallel for schedule(static)
+                for (int64_t i = 0; i < H.n; i++)
+                    for (int32_t k = H.rp[i]; k < H.rp[i + 1]; k++) sv[k] = H.v[k] * H.minv[H.ci[k]];
+                std::vector<int32_t> s2, o2;
+                std::vector<double> sval;
+                pack_dia(H.n, H.n, H.rp.data(), H.ci.data(), sv.data(), D.A.slots * 4 / 3, s2, o2, sval);
+                if ((st = upload(h.get(), &D.amd, sval.data(), sval.size()))) return st;
+                if (f32) {
+                    auto s32 = to32(sval);
+                    if ((st = upload(h.get(), &D.amd32, s32.data(), s32.size()))) return st;
+                }
+            }
+        }
         if (f32) {
             auto m32 = to32(H.minv);
             if ((st = upload(h.get(), &D.minv32, m32.data(), m32.size()))) return st;
@@ -1798,6 +2058,25 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
                 rv[o] = H.p[i];
             }
             if ((st = upload_ell(h.get(), D.R, H.nc, H.n, rrp.data(), rci.data(), rv.data(), f32))) return st;
+            // A P for the split post-smoothing sweep
+            std::vector<int32_t> aprp, apci;
+            std::vector<double> apv;
+            prolongated_operator(H, aprp, apci, apv);
+            if ((st = upload_ell(h.get(), D.AP, H.n, H.nc, aprp.data(), apci.data(), apv.data(), f32))) return st;
+            // A M^-1 values, packed in A's layout
+            std::vector<double> sv(H.rp[H.n]);
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < H.n; i++)
+                for (int32_t k = H.rp[i]; k < H.rp[i + 1]; k++) sv[k] = H.v[k] * H.minv[H.ci[k]];
+            std::vector<long long> soff;
+            std::vector<double> sval;
+            std::vector<int> scol;
+            pack_ell(H.n, H.rp.data(), H.ci.data(), sv.data(), soff, sval, scol);
+            if ((st = upload(h.get(), &D.am, sval.data(), sval.size()))) return st;
+            if (f32) {
+                auto s32 = to32(sval);
+                if ((st = upload(h.get(), &D.am32, s32.data(), s32.size()))) return st;
+            }
         }
     }
     // coarsest inverse, stored transposed for coalesced reads
@@ -1875,18 +2154,32 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
         s->rows[l] = D.n;
         s->nnz[l] = D.nnz;
         s->ell_slots[l] = D.A.slots;
+        s->dia_slots[l] = D.Ad.slots;
         zs += (double)D.nnz;
+        // bytes per stored entry of A (and A M^-1) in the storage the kernels read
+        const bool dia = h->dia && D.Ad.on();
+        const double m64 = dia ? 8 : 12, m32 = dia ? 4 : 8;
         if (l < L - 1) {
-            // pre: A, b and minv gathered, r written; restriction: R, r, b_c;
-            // post: A, b, minv, p, agg, x_c gathered, x written
-            double Z = (double)D.nnz, N = (double)D.n, Nc = (double)D.nc;
-            vb64 += 2 * Z * 12 + N * 12 * 2 /* P and R */ + N * (8 * 8) + Nc * 8 * 2;
-            vb32 += 2 * Z * 8 + N * 8 * 2 + N * (8 * 4) + Nc * 4 * 2;
+            double Z = (double)D.nnz, N = (double)D.n, Nc = (double)D.nc, Zp = (double)D.AP.nnz;
+            s->ap_nnz[l] = D.AP.nnz;
+            // level 0 reads b and writes x in FP64 in both forms
+            const double e0 = l == 0 ? 1.0 : 0.0;
+            if (h->split) {
+                // pre: A M^-1, b gathered, r written; restriction: R, r, b_c;
+                // post: A P, b, minv, r, p, agg, x_c read, x written
+                vb64 += Z * m64 + 16 * N + N * 12 + 8 * N + 8 * Nc + Zp * 12 + 44 * N + 8 * Nc;
+                vb32 += Z * m32 + 8 * N + N * 8 + 4 * N + 4 * Nc + Zp * 8 + 24 * N + 4 * Nc + e0 * 12 * N;
+            } else {
+                // pre: A, b and minv gathered, r written; restriction: R, r, b_c;
+                // post: A, b, minv, p, agg, x_c gathered, x written
+                vb64 += 2 * Z * 12 + N * 12 * 2 /* P and R */ + N * (8 * 8) + Nc * 8 * 2;
+                vb32 += 2 * Z * 8 + N * 8 * 2 + N * (8 * 4) + Nc * 4 * 2 + e0 * 12 * N;
+            }
         } else if (h->host.coarse_sweeps > 0) {
             // sweeps: A and x gathered, b and minv read, x written
             double K = h->host.coarse_sweeps, Z = (double)D.nnz, N = (double)D.n;
-            vb64 += (K - 1) * (Z * 12 + N * 8 * 4) + N * 8 * 3;
-            vb32 += (K - 1) * (Z * 12 + N * 8 * 3 + N * 4) + N * (8 + 4 + 4);
+            vb64 += (K - 1) * (Z * m64 + N * 8 * 4) + N * 8 * 3;
+            vb32 += (K - 1) * (Z * m64 + N * 8 * 3 + N * 4) + N * (8 + 4 + 4);
         } else {
             double n2 = (double)D.n * D.n;
             vb64 += 8 * n2;
@@ -1896,7 +2189,7 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
     s->operator_complexity = zs / z0;
     s->vcycle_bytes_fp64 = vb64;
     s->vcycle_bytes_fp32 = vb32;
-    s->spmv_bytes_fp64 = z0 * 12 + 2 * 8 * (double)h->lev[0].n;
+    s->spmv_bytes_fp64 = z0 * ((h->dia && h->lev[0].Ad.on()) ? 8 : 12) + 2 * 8 * (double)h->lev[0].n;
     s->setup_seconds = h->setup_seconds;
     s->device_bytes = h->device_bytes;
     s->coarse_sweeps = h->host.coarse_sweeps;
@@ -1942,9 +2235,9 @@ int psc_spmv(psc_hier* h, int32_t l, int32_t prec, const void* x, void* y) {
     {
         TimeScope t(h, l == 0 ? 0 : 7);
         if (prec == PSC_FP64)
-            launch_spmv(h, D.A.view(), (const double*)x, (double*)y, Gate{nullptr, GATE_NONE});
+            with_A(h, D, [&](auto A) { launch_spmv(h, A, (const double*)x, (double*)y, Gate{nullptr, GATE_NONE}); });
         else
-            launch_spmv(h, D.A.view32(), (const float*)x, (float*)y, Gate{nullptr, GATE_NONE});
+            with_A32(h, D, [&](auto A) { launch_spmv(h, A, (const float*)x, (float*)y, Gate{nullptr, GATE_NONE}); });
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -1975,6 +2268,16 @@ int psc_tune(psc_hier* h, int32_t key, int32_t value) {
     if (key == PSC_TUNE_BUFLOAD) {
         if (value < 0 || value > 2) return fail(PSC_ERR_ARG, "buffer-load mode must be 0, 1 or 2");
         h->bufload = value;
+        drop_graphs(h);
+        return PSC_OK;
+    }
+    if (key == PSC_TUNE_DIA) {
+        h->dia = value != 0;
+        drop_graphs(h);
+        return PSC_OK;
+    }
+    if (key == PSC_TUNE_SPLIT) {
+        h->split = value != 0;
         drop_graphs(h);
         return PSC_OK;
     }

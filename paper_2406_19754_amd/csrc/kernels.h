@@ -47,9 +47,26 @@ struct HostCtl {
 // column-major at [off[s], off[s+1]) (w_s = (off[s+1]-off[s])/64).
 template <typename T>
 struct Ell {
+    using value_type = T;
     const long long* off;
     const T* val;
     const int* col;
+    long long nrows;
+    long long nslices;
+    long long ncols;
+};
+
+// Hacked-DIA operator (the hacked diagonal format of the PSBLAS extensions):
+// slice s of 64 rows holds the diagonals start[s] .. start[s+1]-1, with
+// offsets offs[k] = column - row (ascending) and values at val[k*64 + lane],
+// zero where the row stores nothing on that diagonal. A 7-point stencil slice
+// keeps 7 diagonals: 8 bytes per entry instead of 12 for hacked ELL.
+template <typename T>
+struct Dia {
+    using value_type = T;
+    const int* start;
+    const int* offs;
+    const T* val;
     long long nrows;
     long long nslices;
     long long ncols;

@@ -509,4 +509,103 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
     return PSC_OK;
 }
 
+// AP = A_l P_l as CSR over the rows of A_l with aggregate columns:
+//   (AP)_iJ = sum over stored j of row i with agg[j] = J of a_ij p_j,
+// added in ascending column order j; row columns ascending.
+void prolongated_operator(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
+                          std::vector<double>& v) {
+    const int64_t n = H.n;
+    rp.assign(n + 1, 0);
+#pragma omp parallel
+    {
+        std::vector<int32_t> js;
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; i++) {
+            js.clear();
+            for (int32_t k = H.rp[i]; k < H.rp[i + 1]; k++) js.push_back(H.agg[H.ci[k]]);
+            std::sort(js.begin(), js.end());
+            rp[i + 1] = (int32_t)(std::unique(js.begin(), js.end()) - js.begin());
+        }
+    }
+    for (int64_t i = 0; i < n; i++) rp[i + 1] += rp[i];
+    ci.resize(rp[n]);
+    v.resize(rp[n]);
+#pragma omp parallel
+    {
+        std::vector<std::pair<int32_t, int32_t>> e;   // (aggregate, slot), slots ascending
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; i++) {
+            e.clear();
+            for (int32_t k = H.rp[i]; k < H.rp[i + 1]; k++) e.emplace_back(H.agg[H.ci[k]], k);
+            std::stable_sort(e.begin(), e.end(),
+                             [](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& b) {
+                                 return a.first < b.first;
+                             });
+            int32_t o = rp[i] - 1, last = -1;
+            for (const auto& jk : e) {
+                const double t = H.v[jk.second] * H.p[H.ci[jk.second]];
+                if (jk.first != last) {
+                    ci[++o] = jk.first;
+                    v[o] = t;
+                    last = jk.first;
+                } else {
+                    v[o] += t;
+                }
+            }
+        }
+    }
+}
+
+bool pack_dia(int64_t nrows, int64_t ncols, const int32_t* rp, const int32_t* ci, const double* v,
+              long long max_slots, std::vector<int32_t>& start, std::vector<int32_t>& offs,
+              std::vector<double>& val) {
+    start.clear();
+    offs.clear();
+    val.clear();
+    if (nrows + 64 + ncols >= (int64_t)1 << 30) return false;
+    const int64_t ns = (nrows + 63) / 64;
+    std::vector<int64_t> cnt(ns + 1, 0);
+    auto slice_offsets = [&](int64_t s, std::vector<int32_t>& o) {
+        o.clear();
+        const int64_t r1 = std::min<int64_t>(nrows, (s + 1) * 64);
+        for (int64_t i = s * 64; i < r1; i++)
+            for (int32_t k = rp[i]; k < rp[i + 1]; k++) o.push_back((int32_t)(ci[k] - i));
+        std::sort(o.begin(), o.end());
+        o.erase(std::unique(o.begin(), o.end()), o.end());
+    };
+#pragma omp parallel
+    {
+        std::vector<int32_t> o;
+#pragma omp for schedule(static)
+        for (int64_t s = 0; s < ns; s++) {
+            slice_offsets(s, o);
+            cnt[s + 1] = (int64_t)o.size();
+        }
+    }
+    for (int64_t s = 0; s < ns; s++) cnt[s + 1] += cnt[s];
+    if (cnt[ns] * 64 > max_slots || cnt[ns] >= ((int64_t)1 << 31)) return false;
+    start.resize(ns + 1);
+    for (int64_t s = 0; s <= ns; s++) start[s] = (int32_t)cnt[s];
+    offs.resize(cnt[ns]);
+    val.assign((size_t)cnt[ns] * 64, 0.0);
+#pragma omp parallel
+    {
+        std::vector<int32_t> o;
+#pragma omp for schedule(static)
+        for (int64_t s = 0; s < ns; s++) {
+            slice_offsets(s, o);
+            std::copy(o.begin(), o.end(), offs.begin() + cnt[s]);
+            const int64_t r1 = std::min<int64_t>(nrows, (s + 1) * 64);
+            for (int64_t i = s * 64; i < r1; i++) {
+                for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
+                    const int32_t d = (int32_t)(ci[k] - i);
+                    const int64_t kk = std::lower_bound(o.begin(), o.end(), d) - o.begin();
+                    val[(size_t)(cnt[s] + kk) * 64 + (size_t)(i - s * 64)] = v[k];
+                }
+            }
+        }
+    }
+    return true;
+}
+
 }  // namespace psc

@@ -38,6 +38,20 @@ int validate_csr(int64_t n, const int32_t* rp, const int32_t* ci, const double* 
 int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
                     const SetupOpts& o, HostHier& H, std::string& err);
 
+// AP = A_l P_l (rows of A_l, aggregate columns) of a level below the
+// coarsest, CSR with ascending columns; each entry sums a_ij p_j over the
+// row's stored columns j of that aggregate in ascending j.
+void prolongated_operator(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
+                          std::vector<double>& v);
+
+// Pack CSR rows into hacked DIA with 64-row slices (offsets ascending per
+// slice, values diagonal-major in a slice, zeros where a row has no entry).
+// Returns false and packs nothing when the diagonal slots would exceed
+// max_ratio times max_slots, or when row + offset could leave int32.
+bool pack_dia(int64_t nrows, int64_t ncols, const int32_t* rp, const int32_t* ci, const double* v,
+              long long max_slots, std::vector<int32_t>& start, std::vector<int32_t>& offs,
+              std::vector<double>& val);
+
 // Pack CSR rows into hacked ELL with 64-row slices (column-major in a
 // slice). Padding slots carry value 0 and repeat the row's last column (0 for
 // rows past the end), so every slot reads a valid, usually cached, entry.

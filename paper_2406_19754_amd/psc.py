@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpsc.so")
 OK, NOCONV = 0, 1
 ERR_ARG, ERR_NOT_SPD, ERR_NAN, ERR_HIP, ERR_OOM, ERR_COARSEN, ERR_STATE = -1, -2, -3, -4, -5, -6, -7
 FP64, FP32 = 0, 1
-TUNE_GRID_MAX, TUNE_FUSED_PCG, TUNE_UNROLL4, TUNE_BUFLOAD, TUNE_SPMV2 = 1, 2, 3, 4, 5
+TUNE_GRID_MAX, TUNE_FUSED_PCG, TUNE_UNROLL4, TUNE_BUFLOAD, TUNE_SPMV2, TUNE_SPLIT, TUNE_DIA = 1, 2, 3, 4, 5, 6, 7
 MAX_LEVELS = 32
 TIMING_KERNELS = 8
 TIMING_NAMES = ["spmv_dot", "cg_update", "pre_smooth_l0", "restrict_l0", "post_smooth_l0",
@@ -49,7 +49,8 @@ class HierStats(C.Structure):
                 ("operator_complexity", C.c_double), ("vcycle_bytes_fp64", C.c_double),
                 ("vcycle_bytes_fp32", C.c_double), ("spmv_bytes_fp64", C.c_double),
                 ("setup_seconds", C.c_double), ("device_bytes", C.c_int64),
-                ("coarse_sweeps", C.c_int32)]
+                ("coarse_sweeps", C.c_int32), ("ap_nnz", C.c_int64 * MAX_LEVELS),
+                ("dia_slots", C.c_int64 * MAX_LEVELS)]
 
 
 def _load():
@@ -168,7 +169,7 @@ class Hierarchy:
                     operator_complexity=s.operator_complexity, vcycle_bytes_fp64=s.vcycle_bytes_fp64,
                     vcycle_bytes_fp32=s.vcycle_bytes_fp32, spmv_bytes_fp64=s.spmv_bytes_fp64,
                     setup_seconds=s.setup_seconds, device_bytes=s.device_bytes,
-                    coarse_sweeps=s.coarse_sweeps)
+                    coarse_sweeps=s.coarse_sweeps, ap_nnz=list(s.ap_nnz[:L]), dia_slots=list(s.dia_slots[:L]))
 
     def export_level(self, l):
         inf = self.info()

@@ -245,12 +245,21 @@ def test_fused_and_unfused_iterations_agree(psc, case, form):
     assert np.linalg.norm(x1 - x0) <= 1e-10 * np.linalg.norm(x0)
 
 
-@pytest.mark.parametrize("knob", ["bufload_all", "bufload_none", "unroll4", "grid256", "spmv2"])
+@pytest.mark.parametrize("knob", ["dia_off", "split_off", "bufload_all", "bufload_none", "unroll4", "grid256", "spmv2"])
 @pytest.mark.parametrize("case", ["poisson13", "random_long_rows", "diffusion20_az100"])
 def test_kernel_variants_match_oracle(psc, case, knob):
     rp, c, v = CASES[case]()
     cm = 40 if case == "random_long_rows" else 200
     h = psc.Hierarchy(rp, c, v, coarse_max=cm, build_fp32=True)
+    dia = h.info()["dia_slots"]
+    if case == "random_long_rows":
+        assert dia[0] == 0                           # no diagonal structure: ELL only
+    else:
+        assert all(d > 0 for d in dia)               # stencil levels keep a hacked-DIA copy
+    if knob == "dia_off":
+        h.tune(psc.TUNE_DIA, 0)
+    if knob in ("split_off", "bufload_all", "bufload_none", "unroll4"):
+        h.tune(psc.TUNE_SPLIT, 0)                    # sweeps gather through A, M^-1, P
     if knob == "bufload_all":
         h.tune(psc.TUNE_BUFLOAD, 1)
     elif knob == "bufload_none":
@@ -279,6 +288,10 @@ def test_kernel_variants_match_oracle(psc, case, knob):
     xg = torch.zeros(n, dtype=torch.float64, device="cuda")
     g = h.pcg(dev(b), xg)
     r = o.pcg(b)
+    assert abs(g["iters"] - r["iters"]) <= 1 and g["relres"] <= 1e-6
+    xg.zero_()
+    g = h.fcg(dev(b), xg, prec=psc.FP32)
+    r = o.fcg(b, form=1)
     assert abs(g["iters"] - r["iters"]) <= 1 and g["relres"] <= 1e-6
 
 
