@@ -46,7 +46,7 @@ def kernel_bytes(info, form="fp64", fused=False, split=True, dia=True):
     """
     N = info["rows"][0]
     Z = info["nnz"][0]
-    Zp = info["ap_nnz"][0] if info["levels"] > 1 else 0
+    Zp = info["sp_nnz"][0] if info["levels"] > 1 else 0
     Nc = info["rows"][1] if info["levels"] > 1 else 0
     v = 8 if form == "fp64" else 4
     dia = dia and info["dia_slots"][0] > 0
@@ -55,8 +55,8 @@ def kernel_bytes(info, form="fp64", fused=False, split=True, dia=True):
     if split:
         # pre: A M^-1, r gathered (fused: r_old and q gathered, r_new written), r_0 written
         pre = Z * av + 8 * N + v * N if not fused else Z * av + 2 * 8 * N + 8 * N + v * N
-        # post: A P; b (FP64), minv, r_0, p, agg read; x_c gathered; z (FP64) written
-        post = Zp * (v + 4) + 8 * N + 3 * v * N + 4 * N + v * Nc + 8 * N
+        # post: S P; b (FP64), minv, r_0 read; x_c gathered; z (FP64) written
+        post = Zp * (v + 4) + 8 * N + 2 * v * N + v * Nc + 8 * N
     else:
         pre = Z * (v + 4) + 8 * N + v * N + v * N if not fused else Z * (v + 4) + 2 * 8 * N + v * N + 8 * N + v * N
         post = Z * (v + 4) + 8 * N + v * N + v * N + 4 * N + v * Nc + 8 * N

@@ -169,7 +169,8 @@ typedef struct {
     double  setup_seconds;                   /* host setup wall time */
     int64_t device_bytes;                    /* device memory held by the handle */
     int32_t coarse_sweeps;                   /* 0: coarsest factored, else l1-Jacobi sweeps */
-    int64_t ap_nnz[PSC_MAX_LEVELS];          /* nonzeros of A_l P_l (0 at the coarsest) */
+    int64_t sp_nnz[PSC_MAX_LEVELS];          /* nonzeros of the smoothed prolongator
+                                                (I - M_l^-1 A_l) P_l (0 at the coarsest) */
     int64_t dia_slots[PSC_MAX_LEVELS];       /* hacked-DIA slots of A_l, 0 when A_l has no DIA copy */
 } psc_hier_stats;
 
@@ -229,11 +230,11 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
  * slices per wavefront concurrently. */
 #define PSC_TUNE_SPMV2 5
 /* PSC_TUNE_SPLIT (default 1): the smoothing sweeps use two operators stored
- * at build, A M^-1 (pre-smoothing, one gathered vector) and A P
- * (post-smoothing with prolongation: with r = b - A M^-1 b,
- * x = M^-1 b + P x_c + M^-1 (r - A P x_c)), the same sweeps up to rounding;
- * 0 gathers through A, M^-1, P and the aggregate map instead. Both paths take
- * the other tuning keys' kernels only when 0. */
+ * at build, A M^-1 (pre-smoothing r = b - A M^-1 b, one gathered vector) and
+ * the smoothed prolongator S P = (I - M^-1 A) P (post-smoothing with
+ * prolongation, x = M^-1 (b + r) + S P x_c), the same sweeps up to rounding;
+ * 0 gathers through A, M^-1, P and the aggregate map instead. The BUFLOAD
+ * and UNROLL4 keys select among the gathering kernels only. */
 #define PSC_TUNE_SPLIT 6
 /* PSC_TUNE_DIA (default 1): kernels that support it read a level operator
  * (and A M^-1) from its hacked-DIA copy, which the build keeps for a level

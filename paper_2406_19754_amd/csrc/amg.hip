@@ -954,11 +954,11 @@ __global__ __launch_bounds__(WG) void k_post(Ell<T> A, const T* __restrict__ min
 
 // ---- split-operator forms of the smoothing sweeps --------------------------
 // With the scaled operator AM = A M^-1 (values a_ij minv_j in A's layout) the
-// pre-smoothing residual gathers one vector; with the prolongated operator
-// AP = A P (aggregate columns) and that residual r = b - A M^-1 b, the
-// post-smoothing sweep gathers only the coarse correction:
-//   A (M^-1 b + P xc) = b - r + AP xc,  so
-//   x_i = minv_i b_i + p_i xc[agg_i] + minv_i (r_i - sum_J ap_iJ xc_J).
+// pre-smoothing residual r = b - AM b gathers one vector. Post-smoothing of
+// xs = M^-1 b + P xc is x = xs + M^-1 (b - A xs) = M^-1 (b + r) + S P xc with
+// S = I - M^-1 A, so with the smoothed prolongator SP = P - M^-1 A P (rows of
+// A, aggregate columns) it gathers only the coarse correction:
+//   x_i = minv_i (b_i + r_i) + sum_J sp_iJ xc_J.
 // These give the sweeps of k_pre / k_post up to rounding.
 
 // r_i = b_i - sum_j am_ij b_j
@@ -1003,24 +1003,22 @@ __global__ __launch_bounds__(WG) void k_update_pre_s(M AM, const double* __restr
     block_partial(s0, 0.0, R.part);
 }
 
-// Post-smoothing with prolongation through AP (see above); with
+// Post-smoothing with prolongation through SP (see above); with
 // R.fin != FIN_NONE also the partial sum of x_i * d_i.
 template <typename T, typename TB, typename TX>
-__global__ __launch_bounds__(WG) void k_post_s(Ell<T> AP, const T* __restrict__ minv, const TB* __restrict__ b,
-                                               const T* __restrict__ r, const int* __restrict__ agg,
-                                               const T* __restrict__ pv, const T* __restrict__ xc,
+__global__ __launch_bounds__(WG) void k_post_s(Ell<T> SP, const T* __restrict__ minv, const TB* __restrict__ b,
+                                               const T* __restrict__ r, const T* __restrict__ xc,
                                                TX* __restrict__ x, const double* __restrict__ d, Red R) {
     if (skip_red(R)) return;
     long long lo, hi;
-    chunk_range(AP.nslices, lo, hi);
+    chunk_range(SP.nslices, lo, hi);
     const int lane = threadIdx.x & 63, w = wave_id();
     double s0 = 0.0;
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        const T acc = ell_row(AP, s, lane, [&](int c) { return xc[c]; });
+        const T acc = ell_row(SP, s, lane, [&](int c) { return xc[c]; });
         const long long row = s * SLICE + lane;
-        if (row < AP.nrows) {
-            const T mi = minv[row];
-            const T xi = mi * (T)b[row] + pv[row] * xc[agg[row]] + mi * (r[row] - acc);
+        if (row < SP.nrows) {
+            const T xi = minv[row] * ((T)b[row] + r[row]) + acc;
             x[row] = (TX)xi;
             if (d) s0 += (double)(TX)xi * d[row];
         }
@@ -1108,7 +1106,7 @@ struct DevLevel {
     double* amd = nullptr;                // A M^-1 values in Ad's layout
     float* amd32 = nullptr;
     DevEll<double> A, R;                  // R = P^T (coarse rows, members as columns)
-    DevEll<double> AP;                    // A P (rows of A, aggregate columns)
+    DevEll<double> SP;                    // smoothed prolongator P - M^-1 A P
     double* am = nullptr;                 // A M^-1 values in A's hacked-ELL layout
     float* am32 = nullptr;
     Ell<double> am_view() const { Ell<double> e = A.view(); e.val = am; return e; }
@@ -1347,10 +1345,10 @@ static void launch_spmv(psc_hier* h, const M& A, const typename M::value_type* x
 }
 
 template <typename T, typename TB, typename TX>
-static void launch_post(psc_hier* h, const Ell<T>& A, const Ell<T>& AP, const T* minv, const TB* b, const T* r,
+static void launch_post(psc_hier* h, const Ell<T>& A, const Ell<T>& SP, const T* minv, const TB* b, const T* r,
                         const int* agg, const T* pv, const T* xc, long long nc, TX* x, const double* d, const Red& R) {
     const int gr = grid_ell(h, A.nslices);
-    if (h->split) k_post_s<T, TB, TX><<<gr, WG, 0, h->stream>>>(AP, minv, b, r, agg, pv, xc, x, d, R);
+    if (h->split) k_post_s<T, TB, TX><<<gr, WG, 0, h->stream>>>(SP, minv, b, r, xc, x, d, R);
     else if (h->bufload >= 1) k_post<T, TB, TX, 8, true><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
     else if (h->unroll4) k_post<T, TB, TX, 4, false><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
     else k_post<T, TB, TX, 8, false><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
@@ -1449,7 +1447,7 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
             double* x = l == 0 ? z0 : V.x;
             {
                 TimeScope t(h, l == 0 ? 4 : 7);
-                launch_post(h, V.A.view(), V.AP.view(), (const double*)V.minv, b, (const double*)V.r, V.agg,
+                launch_post(h, V.A.view(), V.SP.view(), (const double*)V.minv, b, (const double*)V.r, V.agg,
                             (const double*)V.pval, (const double*)h->lev[l + 1].x, V.nc, x, l == 0 ? d : nullptr,
                             l == 0 ? R : R0);
             }
@@ -1478,13 +1476,13 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
             if (l == 0) {
                 {
                     TimeScope t(h, 4);
-                    launch_post(h, V.A.view32(), V.AP.view32(), (const float*)V.minv32, r0, (const float*)V.r32, V.agg,
+                    launch_post(h, V.A.view32(), V.SP.view32(), (const float*)V.minv32, r0, (const float*)V.r32, V.agg,
                                 (const float*)V.pval32, (const float*)h->lev[1].x32, V.nc, z0, d, R);
                 }
                 finish(h, R, grid_ell(h, V.A.nslices));
             } else {
                 TimeScope t(h, 7);
-                launch_post(h, V.A.view32(), V.AP.view32(), (const float*)V.minv32, (const float*)V.b32,
+                launch_post(h, V.A.view32(), V.SP.view32(), (const float*)V.minv32, (const float*)V.b32,
                             (const float*)V.r32, V.agg, (const float*)V.pval32, (const float*)h->lev[l + 1].x32, V.nc,
                             V.x32, (const double*)nullptr, R0);
             }
@@ -2058,11 +2056,11 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
                 rv[o] = H.p[i];
             }
             if ((st = upload_ell(h.get(), D.R, H.nc, H.n, rrp.data(), rci.data(), rv.data(), f32))) return st;
-            // A P for the split post-smoothing sweep
-            std::vector<int32_t> aprp, apci;
-            std::vector<double> apv;
-            prolongated_operator(H, aprp, apci, apv);
-            if ((st = upload_ell(h.get(), D.AP, H.n, H.nc, aprp.data(), apci.data(), apv.data(), f32))) return st;
+            // smoothed prolongator for the split post-smoothing sweep
+            std::vector<int32_t> sprp, spci;
+            std::vector<double> spv;
+            smoothed_prolongator(H, sprp, spci, spv);
+            if ((st = upload_ell(h.get(), D.SP, H.n, H.nc, sprp.data(), spci.data(), spv.data(), f32))) return st;
             // A M^-1 values, packed in A's layout
             std::vector<double> sv(H.rp[H.n]);
 #pragma omp parallel for schedule(static)
@@ -2160,15 +2158,15 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
         const bool dia = h->dia && D.Ad.on();
         const double m64 = dia ? 8 : 12, m32 = dia ? 4 : 8;
         if (l < L - 1) {
-            double Z = (double)D.nnz, N = (double)D.n, Nc = (double)D.nc, Zp = (double)D.AP.nnz;
-            s->ap_nnz[l] = D.AP.nnz;
+            double Z = (double)D.nnz, N = (double)D.n, Nc = (double)D.nc, Zp = (double)D.SP.nnz;
+            s->sp_nnz[l] = D.SP.nnz;
             // level 0 reads b and writes x in FP64 in both forms
             const double e0 = l == 0 ? 1.0 : 0.0;
             if (h->split) {
                 // pre: A M^-1, b gathered, r written; restriction: R, r, b_c;
-                // post: A P, b, minv, r, p, agg, x_c read, x written
-                vb64 += Z * m64 + 16 * N + N * 12 + 8 * N + 8 * Nc + Zp * 12 + 44 * N + 8 * Nc;
-                vb32 += Z * m32 + 8 * N + N * 8 + 4 * N + 4 * Nc + Zp * 8 + 24 * N + 4 * Nc + e0 * 12 * N;
+                // post: S P, b, minv, r read, x_c gathered, x written
+                vb64 += Z * m64 + 16 * N + N * 12 + 8 * N + 8 * Nc + Zp * 12 + 32 * N + 8 * Nc;
+                vb32 += Z * m32 + 8 * N + N * 8 + 4 * N + 4 * Nc + Zp * 8 + 16 * N + 4 * Nc + e0 * 12 * N;
             } else {
                 // pre: A, b and minv gathered, r written; restriction: R, r, b_c;
                 // post: A, b, minv, p, agg, x_c gathered, x written

@@ -509,10 +509,12 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
     return PSC_OK;
 }
 
-// AP = A_l P_l as CSR over the rows of A_l with aggregate columns:
-//   (AP)_iJ = sum over stored j of row i with agg[j] = J of a_ij p_j,
-// added in ascending column order j; row columns ascending.
-void prolongated_operator(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
+// Smoothed prolongator SP = (I - M^-1 A_l) P_l as CSR over the rows of A_l
+// with aggregate columns: with ap_iJ = sum over stored j of row i with
+// agg[j] = J of a_ij p_j (added in ascending j),
+//   sp_iJ = [J = agg[i]] p_i - minv_i ap_iJ;
+// row columns ascending (agg[i] is always present: a_ii is stored).
+void smoothed_prolongator(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
                           std::vector<double>& v) {
     const int64_t n = H.n;
     rp.assign(n + 1, 0);
@@ -551,6 +553,10 @@ void prolongated_operator(const HostLevel& H, std::vector<int32_t>& rp, std::vec
                 } else {
                     v[o] += t;
                 }
+            }
+            for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
+                const double pk = ci[k] == H.agg[i] ? H.p[i] : 0.0;
+                v[k] = pk - H.minv[i] * v[k];
             }
         }
     }

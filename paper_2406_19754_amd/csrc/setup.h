@@ -38,10 +38,9 @@ int validate_csr(int64_t n, const int32_t* rp, const int32_t* ci, const double* 
 int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
                     const SetupOpts& o, HostHier& H, std::string& err);
 
-// AP = A_l P_l (rows of A_l, aggregate columns) of a level below the
-// coarsest, CSR with ascending columns; each entry sums a_ij p_j over the
-// row's stored columns j of that aggregate in ascending j.
-void prolongated_operator(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
+// Smoothed prolongator SP = (I - M_l^-1 A_l) P_l of a level below the
+// coarsest (rows of A_l, aggregate columns), CSR with ascending columns.
+void smoothed_prolongator(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
                           std::vector<double>& v);
 
 // Pack CSR rows into hacked DIA with 64-row slices (offsets ascending per

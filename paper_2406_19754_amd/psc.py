@@ -49,7 +49,7 @@ class HierStats(C.Structure):
                 ("operator_complexity", C.c_double), ("vcycle_bytes_fp64", C.c_double),
                 ("vcycle_bytes_fp32", C.c_double), ("spmv_bytes_fp64", C.c_double),
                 ("setup_seconds", C.c_double), ("device_bytes", C.c_int64),
-                ("coarse_sweeps", C.c_int32), ("ap_nnz", C.c_int64 * MAX_LEVELS),
+                ("coarse_sweeps", C.c_int32), ("sp_nnz", C.c_int64 * MAX_LEVELS),
                 ("dia_slots", C.c_int64 * MAX_LEVELS)]
 
 
@@ -169,7 +169,7 @@ class Hierarchy:
                     operator_complexity=s.operator_complexity, vcycle_bytes_fp64=s.vcycle_bytes_fp64,
                     vcycle_bytes_fp32=s.vcycle_bytes_fp32, spmv_bytes_fp64=s.spmv_bytes_fp64,
                     setup_seconds=s.setup_seconds, device_bytes=s.device_bytes,
-                    coarse_sweeps=s.coarse_sweeps, ap_nnz=list(s.ap_nnz[:L]), dia_slots=list(s.dia_slots[:L]))
+                    coarse_sweeps=s.coarse_sweeps, sp_nnz=list(s.sp_nnz[:L]), dia_slots=list(s.dia_slots[:L]))
 
     def export_level(self, l):
         inf = self.info()
