@@ -66,6 +66,14 @@ typedef struct psc_net  psc_net;    /* opaque: owns the learned preconditioner  
  *                    it is solved by this many FP64 l1-Jacobi sweeps from a
  *                    zero guess (the l1-Jacobi coarsest solver of Section
  *                    "GPU enabled smoothers"). 0 makes such a stall an error.
+ *   smoothed_prol = 0  1: the smoothed prolongator P = (I - omega D^-1 A) P^
+ *                    of the tentative P^, D = diag(A), omega = 1/||D^-1 A||_inf
+ *                    (Section "Aggregation strategies"), with the general
+ *                    Galerkin product A_{l+1} = P^T A_l P; with sweeps = 3 and
+ *                    smoother_sweeps = 4 this is the paper's SMATCH setting.
+ *   smoother_sweeps = 1  l1-Jacobi sweeps before and after the coarse
+ *                    correction on every level (1..16; the paper's examples
+ *                    use 4).
  *   build_fp32 = 0   also build the FP32 copies of the level operators that
  *                    the mixed-precision V-cycle needs.
  *   use_graph = 1    capture the per-iteration kernel sequence as a HIP
@@ -83,7 +91,9 @@ typedef struct {
     int32_t use_graph;
     int32_t host_only;
     int32_t coarse_sweeps;
-    int32_t reserved[9];
+    int32_t smoothed_prol;
+    int32_t smoother_sweeps;
+    int32_t reserved[7];
 } psc_amg_opts;
 
 void psc_amg_opts_default(psc_amg_opts* opts);
@@ -172,6 +182,10 @@ typedef struct {
     int64_t sp_nnz[PSC_MAX_LEVELS];          /* nonzeros of the smoothed prolongator
                                                 (I - M_l^-1 A_l) P_l (0 at the coarsest) */
     int64_t dia_slots[PSC_MAX_LEVELS];       /* hacked-DIA slots of A_l, 0 when A_l has no DIA copy */
+    int64_t p_nnz[PSC_MAX_LEVELS];           /* nonzeros of the prolongator P_l (0 at the coarsest) */
+    double  omega[PSC_MAX_LEVELS];           /* smoothed prolongator damping per level (0: tentative) */
+    int32_t smoother_sweeps;
+    int32_t smoothed_prol;
 } psc_hier_stats;
 
 int psc_hier_info(const psc_hier* h, psc_hier_stats* s);
@@ -187,6 +201,15 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s);
 int psc_hier_export_level(const psc_hier* h, int32_t level, int32_t* agg_host,
                           double* p_host, double* minv_host, int32_t* rowptr_host,
                           int32_t* col_host, double* val_host);
+
+/*
+ * Copy the prolongator P_l the V-cycle uses (the tentative one, or the
+ * smoothed one) as CSR with aggregate columns: rowptr_host rows[l]+1 int32,
+ * col_host / val_host p_nnz[l] entries. Levels below the coarsest only
+ * (else PSC_ERR_ARG).
+ */
+int psc_hier_export_prolongator(const psc_hier* h, int32_t level, int32_t* rowptr_host,
+                                int32_t* col_host, double* val_host);
 
 /* z = B r: one V-cycle (FP64 or FP32 form) on device vectors of size n. */
 int psc_vcycle_apply(psc_hier* h, int32_t prec, const double* r_dev, double* z_dev);
@@ -229,7 +252,8 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
 /* PSC_TUNE_SPMV2 (default 0): the plain SpMV and the restriction process two
  * slices per wavefront concurrently. */
 #define PSC_TUNE_SPMV2 5
-/* PSC_TUNE_SPLIT (default 1): the smoothing sweeps use two operators stored
+/* PSC_TUNE_SPLIT (default 1; must stay 1 for smoothed prolongators or more
+ * than one smoothing sweep, else PSC_ERR_ARG): the smoothing sweeps use two operators stored
  * at build, A M^-1 (pre-smoothing r = b - A M^-1 b, one gathered vector) and
  * the smoothed prolongator S P = (I - M^-1 A) P (post-smoothing with
  * prolongation, x = M^-1 (b + r) + S P x_c), the same sweeps up to rounding;

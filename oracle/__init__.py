@@ -54,7 +54,12 @@ def lib():
     L.orc_edge_key.restype = C.c_longlong
     L.orc_match.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p]
     L.orc_match.restype = C.c_int
-    L.orc_build.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(vp)]
+    L.orc_build.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                            C.POINTER(vp)]
+    L.orc_prol_nnz.argtypes = [vp, C.c_int]
+    L.orc_prol_nnz.restype = C.c_longlong
+    L.orc_prol_get.argtypes = [vp, C.c_int, _i32p, _i32p, _f64p, C.POINTER(C.c_double)]
+    L.orc_prol_get.restype = C.c_int
     L.orc_coarse_sweeps.argtypes = [vp]
     L.orc_coarse_sweeps.restype = C.c_int
     L.orc_build.restype = C.c_int
@@ -126,11 +131,12 @@ def match(rowptr, col, S):
 class Hierarchy:
     """Oracle AMG hierarchy (C.2 of the readings): levels of (A_l, agg, p, w, minv)."""
 
-    def __init__(self, rowptr, col, val, sweeps=2, coarse_max=200, max_levels=30, coarse_sweeps=30):
+    def __init__(self, rowptr, col, val, sweeps=2, coarse_max=200, max_levels=30, coarse_sweeps=30,
+                 prol=0, nu=1):
         self._rowptr, self._col, self._val = _i32(rowptr), _i32(col), _f64(val)
         h = C.c_void_p()
         st = lib().orc_build(len(rowptr) - 1, self._rowptr, self._col, self._val,
-                             sweeps, coarse_max, max_levels, coarse_sweeps, C.byref(h))
+                             sweeps, coarse_max, max_levels, coarse_sweeps, prol, nu, C.byref(h))
         self.status = st
         if st != OK:
             raise RuntimeError(f"oracle build failed with status {st}")
@@ -145,6 +151,17 @@ class Hierarchy:
     @property
     def nlevels(self):
         return lib().orc_nlevels(self._h)
+
+    def prolongator(self, l):
+        """(rowptr, col, val, omega) of the prolongator of level l."""
+        n = self.level_info(l)[0]
+        nnz = lib().orc_prol_nnz(self._h, l)
+        if nnz < 0:
+            raise ValueError("no prolongator at the coarsest level")
+        rp, ci, v = np.empty(n + 1, np.int32), np.empty(nnz, np.int32), np.empty(nnz)
+        om = C.c_double()
+        lib().orc_prol_get(self._h, l, rp, ci, v, C.byref(om))
+        return rp, ci, v, om.value
 
     @property
     def coarse_sweeps(self):

@@ -14,7 +14,8 @@
  *   - Coupled aggregation by compatible weighted matching, the tentative
  *     prolongator P^ = blockdiag(w_e) (+) diag(w_s/|w_s|) and k matching
  *     sweeps giving aggregates of size <= 2^k: Section "Aggregation
- *     strategies", eq. (prolongator).
+ *     strategies", eq. (prolongator); optionally the smoothed prolongator
+ *     P = (I - omega D^-1 A) P^, omega = 1/||D^-1 A||_inf (same section).
  *   - l1-Jacobi smoother M_l = diag(A_l) + diag(sum_{j!=i} |a_ij|):
  *     Section "GPU enabled smoothers".
  *   - Conjugate gradient / flexible CG to a relative residual tolerance:
@@ -232,7 +233,9 @@ typedef struct {
     double *minv;   /* l1-Jacobi: 1 / (a_ii + sum_{j!=i} |a_ij|) */
     int nc;         /* next level size (0 at the coarsest) */
     int *agg;       /* aggregate of each row */
-    double *p;      /* value of the single nonzero of row i of P */
+    double *p;      /* value of row i of the tentative prolongator P^ */
+    csr P;          /* prolongator used by the V-cycle: P^ itself, or smoothed */
+    double omega;   /* smoothed prolongator: damping 1 / ||D^-1 A||_inf */
     double *L;      /* coarsest only: dense lower Cholesky factor, row-major */
 } orc_level;
 
@@ -240,6 +243,8 @@ typedef struct {
     int nlev;
     int sweeps;
     int coarse_sweeps;   /* > 0: the coarsest level is solved by this many l1-Jacobi sweeps */
+    int prol;            /* 0: tentative prolongator, 1: smoothed */
+    int nu;              /* l1-Jacobi sweeps before and after the coarse correction */
     orc_level lev[ORC_MAXLEV];
 } orc_hier;
 
@@ -249,6 +254,7 @@ void orc_free(orc_hier *h) {
         orc_level *L = &h->lev[l];
         csr_free(&L->A);
         free(L->w); free(L->minv); free(L->agg); free(L->p); free(L->L);
+        csr_free(&L->P);
     }
     free(h);
 }
@@ -312,6 +318,162 @@ static void chol_solve(int n, const double *L, const double *b, double *x) {
  * normalisation, which the edge weight does not see). The final aggregates
  * are numbered by ascending smallest level-l member.
  */
+/*
+ * Smoothed prolongator (Section "Aggregation strategies"): P = (I - omega
+ * D^-1 A) P^ with D = diag(A), omega = 1 / ||D^-1 A||_inf, and P^ the
+ * tentative prolongator (row i: value p_i in column agg_i). Row i:
+ *   t_J  = sum over stored j of row i (ascending) with agg_j = J of a_ij p_j,
+ *   P_iJ = [J = agg_i] p_i - (omega / a_ii) t_J,
+ * every reached J stored, columns ascending.
+ */
+static int smoothed_prolongator(const csr *A, const int *agg, const double *p, int nc,
+                                double omega, csr *P) {
+    int n = A->n;
+    double *acc = calloc((size_t)(nc > 0 ? nc : 1), sizeof(double));
+    int *mark = malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+    int *list = malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+    int *rp = malloc(sizeof(int) * (size_t)(n + 1));
+    if (!acc || !mark || !list || !rp) { free(acc); free(mark); free(list); free(rp); return ORC_ERR_OOM; }
+    for (int J = 0; J < nc; J++) mark[J] = -1;
+    rp[0] = 0;
+    for (int i = 0; i < n; i++) {
+        int len = 0;
+        for (int k = A->rp[i]; k < A->rp[i + 1]; k++) {
+            int J = agg[A->ci[k]];
+            if (mark[J] != i) { mark[J] = i; len++; }
+        }
+        rp[i + 1] = rp[i] + len;
+    }
+    int nnz = rp[n];
+    int *ci = malloc(sizeof(int) * (size_t)(nnz > 0 ? nnz : 1));
+    double *v = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    for (int J = 0; J < nc; J++) mark[J] = -1;
+    for (int i = 0; i < n; i++) {
+        int len = 0;
+        double aii = 0.0;
+        for (int k = A->rp[i]; k < A->rp[i + 1]; k++) {
+            int j = A->ci[k], J = agg[j];
+            if (j == i) aii = A->v[k];
+            double t = A->v[k] * p[j];
+            if (mark[J] != i) { mark[J] = i; acc[J] = t; list[len++] = J; }
+            else acc[J] += t;
+        }
+        for (int x = 1; x < len; x++) {
+            int key = list[x], y = x - 1;
+            while (y >= 0 && list[y] > key) { list[y + 1] = list[y]; y--; }
+            list[y + 1] = key;
+        }
+        for (int x = 0; x < len; x++) {
+            int J = list[x];
+            double pk = (J == agg[i]) ? p[i] : 0.0;
+            ci[rp[i] + x] = J;
+            v[rp[i] + x] = pk - (omega / aii) * acc[J];
+        }
+    }
+    free(acc); free(mark); free(list);
+    P->n = n; P->rp = rp; P->ci = ci; P->v = v;
+    return ORC_OK;
+}
+
+/*
+ * General Galerkin product A_c = P^T (A P) (Section "AMG4PSBLAS") for a
+ * prolongator with several nonzeros per row, in a fixed order:
+ *   T[i,J] = sum over stored j of row i (ascending), then entries (J, p_jJ)
+ *            of row j of P (ascending), of a_ij p_jJ;
+ *   C[I,J] = sum over rows i ascending with P_iI stored, of P_iI T[i,J].
+ * Every structurally reached entry is stored; rows of C ascending.
+ */
+static int galerkin_general(const csr *A, const csr *P, int nc, csr *C) {
+    int n = A->n;
+    double *acc = calloc((size_t)(nc > 0 ? nc : 1), sizeof(double));
+    int *mark = malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+    int *list = malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+    /* T = A P, row by row */
+    csr T;
+    T.n = n;
+    T.rp = malloc(sizeof(int) * (size_t)(n + 1));
+    T.rp[0] = 0;
+    size_t cap = (size_t)(A->rp[n] > 0 ? A->rp[n] : 1) * 4, used = 0;
+    T.ci = malloc(sizeof(int) * cap);
+    T.v = malloc(sizeof(double) * cap);
+    for (int J = 0; J < nc; J++) mark[J] = -1;
+    for (int i = 0; i < n; i++) {
+        int len = 0;
+        for (int k = A->rp[i]; k < A->rp[i + 1]; k++) {
+            int j = A->ci[k];
+            for (int m = P->rp[j]; m < P->rp[j + 1]; m++) {
+                int J = P->ci[m];
+                double t = A->v[k] * P->v[m];
+                if (mark[J] != i) { mark[J] = i; acc[J] = t; list[len++] = J; }
+                else acc[J] += t;
+            }
+        }
+        for (int x = 1; x < len; x++) {
+            int key = list[x], y = x - 1;
+            while (y >= 0 && list[y] > key) { list[y + 1] = list[y]; y--; }
+            list[y + 1] = key;
+        }
+        if (used + (size_t)len > cap) {
+            while (used + (size_t)len > cap) cap *= 2;
+            T.ci = realloc(T.ci, sizeof(int) * cap);
+            T.v = realloc(T.v, sizeof(double) * cap);
+        }
+        for (int x = 0; x < len; x++) { T.ci[used] = list[x]; T.v[used] = acc[list[x]]; used++; }
+        T.rp[i + 1] = (int)used;
+    }
+    /* rows of P^T: for each coarse I the fine rows i ascending with P_iI */
+    int *tc = calloc((size_t)nc + 1, sizeof(int));
+    for (int m = 0; m < P->rp[n]; m++) tc[P->ci[m] + 1]++;
+    for (int I = 0; I < nc; I++) tc[I + 1] += tc[I];
+    int *fill = malloc(sizeof(int) * (size_t)(nc + 1));
+    memcpy(fill, tc, sizeof(int) * (size_t)(nc + 1));
+    int *ti = malloc(sizeof(int) * (size_t)(P->rp[n] > 0 ? P->rp[n] : 1));
+    double *tv = malloc(sizeof(double) * (size_t)(P->rp[n] > 0 ? P->rp[n] : 1));
+    for (int i = 0; i < n; i++)
+        for (int m = P->rp[i]; m < P->rp[i + 1]; m++) {
+            int o = fill[P->ci[m]]++;
+            ti[o] = i;
+            tv[o] = P->v[m];
+        }
+    free(fill);
+    /* C = P^T T */
+    int *crp = malloc(sizeof(int) * (size_t)(nc + 1));
+    crp[0] = 0;
+    size_t ccap = (size_t)(nc > 0 ? nc : 1) * 8, cused = 0;
+    int *cci = malloc(sizeof(int) * ccap);
+    double *cv = malloc(sizeof(double) * ccap);
+    for (int J = 0; J < nc; J++) mark[J] = -1;
+    for (int I = 0; I < nc; I++) {
+        int len = 0;
+        for (int o = tc[I]; o < tc[I + 1]; o++) {
+            int i = ti[o];
+            double pi = tv[o];
+            for (int m = T.rp[i]; m < T.rp[i + 1]; m++) {
+                int J = T.ci[m];
+                double t = pi * T.v[m];
+                if (mark[J] != I) { mark[J] = I; acc[J] = t; list[len++] = J; }
+                else acc[J] += t;
+            }
+        }
+        for (int x = 1; x < len; x++) {
+            int key = list[x], y = x - 1;
+            while (y >= 0 && list[y] > key) { list[y + 1] = list[y]; y--; }
+            list[y + 1] = key;
+        }
+        if (cused + (size_t)len > ccap) {
+            while (cused + (size_t)len > ccap) ccap *= 2;
+            cci = realloc(cci, sizeof(int) * ccap);
+            cv = realloc(cv, sizeof(double) * ccap);
+        }
+        for (int x = 0; x < len; x++) { cci[cused] = list[x]; cv[cused] = acc[list[x]]; cused++; }
+        crp[I + 1] = (int)cused;
+    }
+    free(tc); free(ti); free(tv); csr_free(&T);
+    free(acc); free(mark); free(list);
+    C->n = nc; C->rp = crp; C->ci = cci; C->v = cv;
+    return ORC_OK;
+}
+
 static int coarsen(const csr *A, const double *w, int sweeps, int *agg, int *nc_out) {
     int n = A->n;
     /* S = diag(w) A diag(w) */
@@ -382,11 +544,16 @@ static int csr_copy(int n, const int *rp, const int *ci, const double *v, csr *a
  * coarse_sweeps l1-Jacobi sweeps (ORC_ERR_COARSEN when coarse_sweeps < 1).
  */
 int orc_build(int n, const int *rp, const int *ci, const double *v,
-              int sweeps, int coarse_max, int max_levels, int coarse_sweeps, orc_hier **out) {
+              int sweeps, int coarse_max, int max_levels, int coarse_sweeps, int prol, int nu,
+              orc_hier **out) {
     *out = NULL;
-    if (n <= 0 || sweeps < 1 || max_levels < 1 || max_levels > ORC_MAXLEV) return ORC_ERR_ARG;
+    if (n <= 0 || sweeps < 1 || max_levels < 1 || max_levels > ORC_MAXLEV || prol < 0 || prol > 1 ||
+        nu < 1)
+        return ORC_ERR_ARG;
     orc_hier *h = calloc(1, sizeof(orc_hier));
     h->sweeps = sweeps;
+    h->prol = prol;
+    h->nu = nu;
     int st = csr_copy(n, rp, ci, v, &h->lev[0].A);
     if (st) { orc_free(h); return st; }
     h->lev[0].w = malloc(sizeof(double) * (size_t)n);
@@ -432,7 +599,30 @@ int orc_build(int n, const int *rp, const int *ci, const double *v,
         for (int I = 0; I < nc; I++) C->w[I] = sqrt(C->w[I]);
         L->p = malloc(sizeof(double) * (size_t)nl);
         for (int i = 0; i < nl; i++) L->p[i] = L->w[i] / C->w[L->agg[i]];
-        st = galerkin(&L->A, L->agg, nc, L->p, &C->A);
+        if (prol == 0) {
+            /* tentative: P = P^, one entry per row; canonical Galerkin sum */
+            L->P.n = nl;
+            L->P.rp = malloc(sizeof(int) * (size_t)(nl + 1));
+            L->P.ci = malloc(sizeof(int) * (size_t)(nl > 0 ? nl : 1));
+            L->P.v = malloc(sizeof(double) * (size_t)(nl > 0 ? nl : 1));
+            for (int i = 0; i < nl; i++) { L->P.rp[i] = i; L->P.ci[i] = L->agg[i]; L->P.v[i] = L->p[i]; }
+            L->P.rp[nl] = nl;
+            st = galerkin(&L->A, L->agg, nc, L->p, &C->A);
+        } else {
+            /* omega = 1 / max_i sum_j |a_ij| / a_ii */
+            double norm = 0.0;
+            for (int i = 0; i < nl; i++) {
+                double s = 0.0, aii = 0.0;
+                for (int k = L->A.rp[i]; k < L->A.rp[i + 1]; k++) {
+                    s += fabs(L->A.v[k]);
+                    if (L->A.ci[k] == i) aii = L->A.v[k];
+                }
+                if (s / aii > norm) norm = s / aii;
+            }
+            L->omega = 1.0 / norm;
+            st = smoothed_prolongator(&L->A, L->agg, L->p, nc, L->omega, &L->P);
+            if (!st) st = galerkin_general(&L->A, &L->P, nc, &C->A);
+        }
         if (st) { orc_free(h); return st; }
         h->nlev = l + 2;
     }
@@ -478,6 +668,22 @@ int orc_coarse_factor(const orc_hier *h, double *Lout) {
 
 int orc_coarse_sweeps(const orc_hier *h) { return h->coarse_sweeps; }
 
+/* The prolongator of level l (below the coarsest) as CSR; nnz via orc_prol_nnz. */
+long long orc_prol_nnz(const orc_hier *h, int l) {
+    if (l < 0 || l >= h->nlev - 1) return -1;
+    return h->lev[l].P.rp[h->lev[l].P.n];
+}
+
+int orc_prol_get(const orc_hier *h, int l, int *rp, int *ci, double *v, double *omega) {
+    if (l < 0 || l >= h->nlev - 1) return ORC_ERR_ARG;
+    const csr *P = &h->lev[l].P;
+    memcpy(rp, P->rp, sizeof(int) * (size_t)(P->n + 1));
+    memcpy(ci, P->ci, sizeof(int) * (size_t)P->rp[P->n]);
+    memcpy(v, P->v, sizeof(double) * (size_t)P->rp[P->n]);
+    if (omega) *omega = h->lev[l].omega;
+    return ORC_OK;
+}
+
 /* Coarsest-level solve in FP64: dense Cholesky, or l1-Jacobi sweeps from
  * x = 0 (x <- x + M^{-1}(b - A x)) when the hierarchy says so. */
 static void coarse_solve(const orc_hier *h, const double *b, double *x) {
@@ -494,8 +700,8 @@ static void coarse_solve(const orc_hier *h, const double *b, double *x) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* V-cycle (eq. amg): one pre-sweep from a zero guess, coarse correction,   */
-/* one post-sweep; the coarsest level is solved by coarse_solve.            */
+/* V-cycle (eq. amg, with nu sweeps): nu pre-sweeps from a zero guess,     */
+/* coarse correction, nu post-sweeps; coarsest level by coarse_solve.       */
 /* ------------------------------------------------------------------------ */
 
 static void vcycle_level(const orc_hier *h, int l, const double *b, double *x) {
@@ -503,23 +709,36 @@ static void vcycle_level(const orc_hier *h, int l, const double *b, double *x) {
     int n = L->A.n;
     if (l == h->nlev - 1) { coarse_solve(h, b, x); return; }
     int nc = L->nc;
+    const csr *P = &L->P;
     double *r = malloc(sizeof(double) * (size_t)n);
     double *bc = malloc(sizeof(double) * (size_t)nc);
     double *xc = malloc(sizeof(double) * (size_t)nc);
-    /* pre-smoothing from x = 0: x = M^{-1} b */
+    /* pre-smoothing from x = 0: x = M^{-1} b, then nu - 1 sweeps
+     * x += M^{-1} (b - A x) */
     for (int i = 0; i < n; i++) x[i] = L->minv[i] * b[i];
+    for (int k = 1; k < h->nu; k++) {
+        orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
+        for (int i = 0; i < n; i++) x[i] += L->minv[i] * (b[i] - r[i]);
+    }
     /* residual r = b - A x */
     orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
     for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
-    /* restriction b_c = P^T r (members of each aggregate ascending) */
+    /* restriction b_c = P^T r (fine rows ascending, then row entries) */
     for (int I = 0; I < nc; I++) bc[I] = 0.0;
-    for (int i = 0; i < n; i++) bc[L->agg[i]] += L->p[i] * r[i];
+    for (int i = 0; i < n; i++)
+        for (int m = P->rp[i]; m < P->rp[i + 1]; m++) bc[P->ci[m]] += P->v[m] * r[i];
     vcycle_level(h, l + 1, bc, xc);
     /* prolongation and correction x += P x_c */
-    for (int i = 0; i < n; i++) x[i] += L->p[i] * xc[L->agg[i]];
-    /* post-smoothing x += M^{-1} (b - A x) */
-    orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
-    for (int i = 0; i < n; i++) x[i] += L->minv[i] * (b[i] - r[i]);
+    for (int i = 0; i < n; i++) {
+        double s = 0.0;
+        for (int m = P->rp[i]; m < P->rp[i + 1]; m++) s += P->v[m] * xc[P->ci[m]];
+        x[i] += s;
+    }
+    /* nu post-smoothing sweeps x += M^{-1} (b - A x) */
+    for (int k = 0; k < h->nu; k++) {
+        orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
+        for (int i = 0; i < n; i++) x[i] += L->minv[i] * (b[i] - r[i]);
+    }
     free(r); free(bc); free(xc);
 }
 
@@ -548,25 +767,41 @@ static void vcycle32_level(const orc_hier *h, int l, const float *b, float *x) {
         return;
     }
     int nc = L->nc;
+    const csr *P = &L->P;
     float *r = malloc(sizeof(float) * (size_t)n);
     float *bc = malloc(sizeof(float) * (size_t)nc);
     float *xc = malloc(sizeof(float) * (size_t)nc);
     for (int i = 0; i < n; i++) x[i] = (float)L->minv[i] * b[i];
+    for (int k = 1; k < h->nu; k++) {
+        for (int i = 0; i < n; i++) {
+            float s = 0.0f;
+            for (int q = L->A.rp[i]; q < L->A.rp[i + 1]; q++) s += (float)L->A.v[q] * x[L->A.ci[q]];
+            r[i] = s;
+        }
+        for (int i = 0; i < n; i++) x[i] += (float)L->minv[i] * (b[i] - r[i]);
+    }
     for (int i = 0; i < n; i++) {
         float s = 0.0f;
-        for (int k = L->A.rp[i]; k < L->A.rp[i + 1]; k++) s += (float)L->A.v[k] * x[L->A.ci[k]];
+        for (int q = L->A.rp[i]; q < L->A.rp[i + 1]; q++) s += (float)L->A.v[q] * x[L->A.ci[q]];
         r[i] = b[i] - s;
     }
     for (int I = 0; I < nc; I++) bc[I] = 0.0f;
-    for (int i = 0; i < n; i++) bc[L->agg[i]] += (float)L->p[i] * r[i];
+    for (int i = 0; i < n; i++)
+        for (int m = P->rp[i]; m < P->rp[i + 1]; m++) bc[P->ci[m]] += (float)P->v[m] * r[i];
     vcycle32_level(h, l + 1, bc, xc);
-    for (int i = 0; i < n; i++) x[i] += (float)L->p[i] * xc[L->agg[i]];
     for (int i = 0; i < n; i++) {
         float s = 0.0f;
-        for (int k = L->A.rp[i]; k < L->A.rp[i + 1]; k++) s += (float)L->A.v[k] * x[L->A.ci[k]];
-        r[i] = s;
+        for (int m = P->rp[i]; m < P->rp[i + 1]; m++) s += (float)P->v[m] * xc[P->ci[m]];
+        x[i] += s;
     }
-    for (int i = 0; i < n; i++) x[i] += (float)L->minv[i] * (b[i] - r[i]);
+    for (int k = 0; k < h->nu; k++) {
+        for (int i = 0; i < n; i++) {
+            float s = 0.0f;
+            for (int q = L->A.rp[i]; q < L->A.rp[i + 1]; q++) s += (float)L->A.v[q] * x[L->A.ci[q]];
+            r[i] = s;
+        }
+        for (int i = 0; i < n; i++) x[i] += (float)L->minv[i] * (b[i] - r[i]);
+    }
     free(r); free(bc); free(xc);
 }
 

@@ -1026,6 +1026,55 @@ __global__ __launch_bounds__(WG) void k_post_s(Ell<T> SP, const T* __restrict__ 
     if (R.fin != FIN_NONE) block_partial(s0, 0.0, R.part);
 }
 
+// Pre-smoothing sweep k >= 2 from a zero guess, carried as the running sum
+// s_k = b + r_1 + ... + r_{k-1} (so x_k = M^-1 s_k): with s_k = s_{k-1} + r_{k-1}
+// formed for the own row and every gathered neighbour,
+//   r_k = b - AM s_k,   and s_k, r_k are stored.
+template <typename M, typename TB, typename TS>
+__global__ __launch_bounds__(WG) void k_presweep(M AM, const TB* __restrict__ b, const TS* __restrict__ sprev,
+                                                 const typename M::value_type* __restrict__ rprev,
+                                                 typename M::value_type* __restrict__ sout,
+                                                 typename M::value_type* __restrict__ rout, Gate g) {
+    using T = typename M::value_type;
+    if (gate_skip(g)) return;
+    long long lo, hi;
+    chunk_range(AM.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        const T acc = mat_row(AM, s, lane, [&](int c) { return (T)sprev[c] + rprev[c]; });
+        const long long row = s * SLICE + lane;
+        if (row < AM.nrows) {
+            sout[row] = (T)sprev[row] + rprev[row];
+            rout[row] = (T)b[row] - acc;
+        }
+    }
+}
+
+// One l1-Jacobi sweep x_out = x_in + M^-1 (b - A x_in) (post-smoothing sweeps
+// after the first); with R.fin != FIN_NONE also the partial sum of x_out * d.
+template <typename M, typename TB, typename TX>
+__global__ __launch_bounds__(WG) void k_sweep(M A, const typename M::value_type* __restrict__ minv,
+                                              const TB* __restrict__ b,
+                                              const typename M::value_type* __restrict__ xin, TX* __restrict__ xout,
+                                              const double* __restrict__ d, Red R) {
+    using T = typename M::value_type;
+    if (skip_red(R)) return;
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    double s0 = 0.0;
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        const T acc = mat_row(A, s, lane, [&](int c) { return xin[c]; });
+        const long long row = s * SLICE + lane;
+        if (row < A.nrows) {
+            const T xi = xin[row] + minv[row] * ((T)b[row] - acc);
+            xout[row] = (TX)xi;
+            if (d) s0 += (double)(TX)xi * d[row];
+        }
+    }
+    if (R.fin != FIN_NONE) block_partial(s0, 0.0, R.part);
+}
+
 // Coarsest level: x = A_L^{-1} b with the explicit inverse (column-major), FP64.
 template <typename TB, typename TX>
 __global__ __launch_bounds__(WG) void k_coarse(int n, const double* __restrict__ invT,
@@ -1118,6 +1167,46 @@ struct DevLevel {
     float* pval32 = nullptr;
     double *b = nullptr, *x = nullptr, *r = nullptr;      // level vectors (FP64 form)
     float *b32 = nullptr, *x32 = nullptr, *r32 = nullptr; // level vectors (FP32 form)
+    // more than one smoothing sweep: second residual buffer, running sums
+    // s (two buffers) and two post-smoothing iterates, per precision
+    double *rb = nullptr, *s = nullptr, *sb = nullptr, *xt = nullptr, *xt2 = nullptr;
+    float *rb32 = nullptr, *s32 = nullptr, *sb32 = nullptr, *xt32 = nullptr, *xt232 = nullptr;
+};
+
+// Per-precision views of a level's vectors and operators.
+template <typename T>
+struct LV;
+template <>
+struct LV<double> {
+    static double* b(DevLevel& V) { return V.b; }
+    static double* x(DevLevel& V) { return V.x; }
+    static double* r(DevLevel& V) { return V.r; }
+    static double* rb(DevLevel& V) { return V.rb; }
+    static double* s(DevLevel& V) { return V.s; }
+    static double* sb(DevLevel& V) { return V.sb; }
+    static double* xt(DevLevel& V) { return V.xt; }
+    static double* xt2(DevLevel& V) { return V.xt2; }
+    static const double* minv(const DevLevel& V) { return V.minv; }
+    static Ell<double> R(const DevLevel& V) { return V.R.view(); }
+    static Ell<double> SP(const DevLevel& V) { return V.SP.view(); }
+    static Ell<double> A(const DevLevel& V) { return V.A.view(); }
+    static const double* pv(const DevLevel& V) { return V.pval; }
+};
+template <>
+struct LV<float> {
+    static float* b(DevLevel& V) { return V.b32; }
+    static float* x(DevLevel& V) { return V.x32; }
+    static float* r(DevLevel& V) { return V.r32; }
+    static float* rb(DevLevel& V) { return V.rb32; }
+    static float* s(DevLevel& V) { return V.s32; }
+    static float* sb(DevLevel& V) { return V.sb32; }
+    static float* xt(DevLevel& V) { return V.xt32; }
+    static float* xt2(DevLevel& V) { return V.xt232; }
+    static const float* minv(const DevLevel& V) { return V.minv32; }
+    static Ell<float> R(const DevLevel& V) { return V.R.view32(); }
+    static Ell<float> SP(const DevLevel& V) { return V.SP.view32(); }
+    static Ell<float> A(const DevLevel& V) { return V.A.view32(); }
+    static const float* pv(const DevLevel& V) { return V.pval32; }
 };
 
 }  // namespace psc
@@ -1147,6 +1236,7 @@ struct psc_hier {
     bool spmv2 = false;                   // plain SpMV / restriction: two slices per wavefront
     bool split = true;                    // smoothing sweeps through A M^-1 and A P
     bool dia = true;                      // use the hacked-DIA copies where a level has them
+    int nu = 1;                           // l1-Jacobi sweeps before and after the coarse correction
     std::vector<void*> allocs;
     int64_t device_bytes = 0;
     double setup_seconds = 0.0;
@@ -1258,6 +1348,16 @@ template <typename F>
 static void with_AM32(const psc_hier* h, const DevLevel& V, F f) {
     if (h->dia && V.Ad.on()) f(V.Ad.view32(V.amd32));
     else f(V.am_view32());
+}
+template <typename T, typename F>
+static void with_A_t(const psc_hier* h, const DevLevel& V, F f) {
+    if constexpr (std::is_same<T, float>::value) with_A32(h, V, f);
+    else with_A(h, V, f);
+}
+template <typename T, typename F>
+static void with_AM_t(const psc_hier* h, const DevLevel& V, F f) {
+    if constexpr (std::is_same<T, float>::value) with_AM32(h, V, f);
+    else with_AM(h, V, f);
 }
 static inline int grid_vec(const psc_hier* h, long long n) { return grid_of(h, 1024, n); }
 
@@ -1403,6 +1503,115 @@ static void coarse_solve(psc_hier* h, const TB* b, TX* x, Gate g) {
     });
 }
 
+// Residual buffer of pre-smoothing sweep k (1..nu) on a level: the buffers
+// alternate so that the last sweep's residual lands in r (read by the
+// restriction and the first post-smoothing sweep).
+template <typename T>
+static T* pre_rbuf(const psc_hier* h, DevLevel& V, int k) {
+    return ((h->nu - k) % 2 == 0) ? LV<T>::r(V) : LV<T>::rb(V);
+}
+
+// nu pre-smoothing sweeps from zero on level V (b: the level's right-hand
+// side, FP64 at level 0). Sweep 1 is skipped when a fused kernel has done it.
+template <typename T, typename TB>
+static void pre_sweeps(psc_hier* h, DevLevel& V, const TB* b, bool skip1, Gate g) {
+    const int gr = grid_ell(h, V.A.nslices);
+    if (!skip1) launch_pre(h, V, b, pre_rbuf<T>(h, V, 1), g);
+    const T* rp = pre_rbuf<T>(h, V, 1);
+    const T* sp = nullptr;
+    for (int k = 2; k <= h->nu; k++) {
+        T* so = ((h->nu - k) % 2 == 0) ? LV<T>::s(V) : LV<T>::sb(V);
+        T* ro = pre_rbuf<T>(h, V, k);
+        with_AM_t<T>(h, V, [&](auto AM) {
+            using M = decltype(AM);
+            if (k == 2) k_presweep<M, TB, TB><<<gr, WG, 0, h->stream>>>(AM, b, b, rp, so, ro, g);
+            else k_presweep<M, TB, T><<<gr, WG, 0, h->stream>>>(AM, b, sp, rp, so, ro, g);
+        });
+        sp = so;
+        rp = ro;
+    }
+}
+
+// nu post-smoothing sweeps on level V after the coarse correction xc; the
+// first is fused with the prolongation (x = M^-1 (s_nu + r_nu) + S P xc,
+// with s_1 = b), the others are plain sweeps through two scratch iterates.
+// The last writes out (FP64 z at level 0) with the reduction Rf.
+template <typename T, typename TB, typename TX>
+static void post_sweeps(psc_hier* h, DevLevel& V, const TB* b, TX* out, const T* xc, const double* d,
+                        const Red& Rf) {
+    const int gr = grid_ell(h, V.A.nslices);
+    Red Rn = Rf;
+    Rn.fin = FIN_NONE;
+    const Ell<T> SP = LV<T>::SP(V);
+    const T* r = LV<T>::r(V);
+    const T* minv = LV<T>::minv(V);
+    if (h->nu == 1) {
+        k_post_s<T, TB, TX><<<gr, WG, 0, h->stream>>>(SP, minv, b, r, xc, out, d, Rf);
+        return;
+    }
+    T* ta = LV<T>::xt(V);
+    T* tb = LV<T>::xt2(V);
+    k_post_s<T, T, T><<<gr, WG, 0, h->stream>>>(SP, minv, (const T*)LV<T>::s(V), r, xc, ta, nullptr, Rn);
+    const T* xin = ta;
+    for (int k = 2; k <= h->nu; k++) {
+        with_A_t<T>(h, V, [&](auto A) {
+            using M = decltype(A);
+            if (k == h->nu) {
+                k_sweep<M, TB, TX><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, out, d, Rf);
+            } else {
+                T* xo = xin == ta ? tb : ta;
+                k_sweep<M, TB, T><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, xo, nullptr, Rn);
+                xin = xo;
+            }
+        });
+    }
+}
+
+// The V-cycle below level 0's right-hand side r0 in precision T (split sweeps).
+template <typename T>
+static void vcycle_t(psc_hier* h, const double* r0, double* z0, const double* d, const Red& R, Gate g,
+                     bool skip_pre0) {
+    const int L = (int)h->lev.size();
+    Red R0 = R;
+    R0.fin = FIN_NONE;
+    for (int l = 0; l < L - 1; l++) {
+        DevLevel& V = h->lev[l];
+        {
+            TimeScope t(h, l == 0 ? 2 : 7);
+            if (l == 0) pre_sweeps<T, double>(h, V, r0, skip_pre0, g);
+            else pre_sweeps<T, T>(h, V, (const T*)LV<T>::b(V), false, g);
+        }
+        {
+            TimeScope t(h, l == 0 ? 3 : 7);
+            launch_spmv(h, LV<T>::R(V), (const T*)LV<T>::r(V), LV<T>::b(h->lev[l + 1]), g);
+        }
+    }
+    DevLevel& C = h->lev[L - 1];
+    {
+        TimeScope t(h, 7);
+        coarse_solve<T, T>(h, (const T*)LV<T>::b(C), LV<T>::x(C), g);
+    }
+    for (int l = L - 2; l >= 0; l--) {
+        DevLevel& V = h->lev[l];
+        const T* xc = LV<T>::x(h->lev[l + 1]);
+        if (l == 0) {
+            {
+                TimeScope t(h, 4);
+                if (h->split) post_sweeps<T, double, double>(h, V, r0, z0, xc, d, R);
+                else launch_post(h, LV<T>::A(V), LV<T>::SP(V), LV<T>::minv(V), r0, (const T*)LV<T>::r(V), V.agg,
+                                 LV<T>::pv(V), xc, V.nc, z0, d, R);
+            }
+            finish(h, R, grid_ell(h, V.A.nslices));
+        } else {
+            TimeScope t(h, 7);
+            if (h->split) post_sweeps<T, T, T>(h, V, (const T*)LV<T>::b(V), LV<T>::x(V), xc, nullptr, R0);
+            else launch_post(h, LV<T>::A(V), LV<T>::SP(V), LV<T>::minv(V), (const T*)LV<T>::b(V),
+                             (const T*)LV<T>::r(V), V.agg, LV<T>::pv(V), xc, V.nc, LV<T>::x(V), (const double*)nullptr,
+                             R0);
+        }
+    }
+}
+
 // z = B r on level 0. prec: PSC_FP64 / PSC_FP32. fin/d: optional fused dot
 // z.d at level 0 with finaliser fin. g gates every kernel (g.ctl == NULL:
 // standalone V-cycle, always runs, no fused dot).
@@ -1423,71 +1632,8 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
         }
         return;
     }
-    if (prec == PSC_FP64) {
-        for (int l = 0; l < L - 1; l++) {
-            DevLevel& V = h->lev[l];
-            const double* b = l == 0 ? r0 : V.b;
-            if (!(l == 0 && skip_pre0)) {
-                TimeScope t(h, l == 0 ? 2 : 7);
-                launch_pre(h, V, b, V.r, g);
-            }
-            {
-                TimeScope t(h, l == 0 ? 3 : 7);
-                launch_spmv(h, V.R.view(), (const double*)V.r, h->lev[l + 1].b, g);
-            }
-        }
-        DevLevel& C = h->lev[L - 1];
-        {
-            TimeScope t(h, 7);
-            coarse_solve<double, double>(h, C.b, C.x, g);
-        }
-        for (int l = L - 2; l >= 0; l--) {
-            DevLevel& V = h->lev[l];
-            const double* b = l == 0 ? r0 : V.b;
-            double* x = l == 0 ? z0 : V.x;
-            {
-                TimeScope t(h, l == 0 ? 4 : 7);
-                launch_post(h, V.A.view(), V.SP.view(), (const double*)V.minv, b, (const double*)V.r, V.agg,
-                            (const double*)V.pval, (const double*)h->lev[l + 1].x, V.nc, x, l == 0 ? d : nullptr,
-                            l == 0 ? R : R0);
-            }
-            if (l == 0) finish(h, R, grid_ell(h, V.A.nslices));
-        }
-    } else {
-        for (int l = 0; l < L - 1; l++) {
-            DevLevel& V = h->lev[l];
-            if (!(l == 0 && skip_pre0)) {
-                TimeScope t(h, l == 0 ? 2 : 7);
-                if (l == 0) launch_pre(h, V, r0, V.r32, g);
-                else launch_pre(h, V, (const float*)V.b32, V.r32, g);
-            }
-            {
-                TimeScope t(h, l == 0 ? 3 : 7);
-                launch_spmv(h, V.R.view32(), (const float*)V.r32, h->lev[l + 1].b32, g);
-            }
-        }
-        DevLevel& C = h->lev[L - 1];
-        {
-            TimeScope t(h, 7);
-            coarse_solve<float, float>(h, C.b32, C.x32, g);
-        }
-        for (int l = L - 2; l >= 0; l--) {
-            DevLevel& V = h->lev[l];
-            if (l == 0) {
-                {
-                    TimeScope t(h, 4);
-                    launch_post(h, V.A.view32(), V.SP.view32(), (const float*)V.minv32, r0, (const float*)V.r32, V.agg,
-                                (const float*)V.pval32, (const float*)h->lev[1].x32, V.nc, z0, d, R);
-                }
-                finish(h, R, grid_ell(h, V.A.nslices));
-            } else {
-                TimeScope t(h, 7);
-                launch_post(h, V.A.view32(), V.SP.view32(), (const float*)V.minv32, (const float*)V.b32,
-                            (const float*)V.r32, V.agg, (const float*)V.pval32, (const float*)h->lev[l + 1].x32, V.nc,
-                            V.x32, (const double*)nullptr, R0);
-            }
-        }
-    }
+    if (prec == PSC_FP64) vcycle_t<double>(h, r0, z0, d, R, g, skip_pre0);
+    else vcycle_t<float>(h, r0, z0, d, R, g, skip_pre0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1558,7 +1704,8 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
                 TimeScope t(h, 2);
                 if (h->split)
                     with_AM(h, L0, [&](auto AM) {
-                        k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_PCG));
+                        k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, pre_rbuf<double>(h, L0, 1),
+                                                                        red_of(h, FIN_UPDATE_PCG));
                     });
                 else if (h->bufload == 1)
                     k_update_pre<8, true><<<ge, WG, 0, st>>>(L0.A.view(), L0.minv, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_PCG));
@@ -1594,11 +1741,13 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
                 if (h->split) {
                     if (f32)
                         with_AM32(h, L0, [&](auto AM) {
-                            k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, L0.r32, red_of(h, FIN_UPDATE_FCG));
+                            k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, pre_rbuf<float>(h, L0, 1),
+                                                                            red_of(h, FIN_UPDATE_FCG));
                         });
                     else
                         with_AM(h, L0, [&](auto AM) {
-                            k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_FCG));
+                            k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, pre_rbuf<double>(h, L0, 1),
+                                                                            red_of(h, FIN_UPDATE_FCG));
                         });
                 } else if (f32) {
                     if (h->bufload == 1)
@@ -1619,8 +1768,8 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             finish(h, red_of(h, FIN_TRUE), ge);
             // after a residual replacement, redo the level-0 pre-smoothing from the true residual
             const Gate gr{h->ctl, GATE_REDO};
-            if (f32) launch_pre(h, L0, (const double*)rnew, L0.r32, gr);
-            else launch_pre(h, L0, (const double*)rnew, L0.r, gr);
+            if (f32) launch_pre(h, L0, (const double*)rnew, pre_rbuf<float>(h, L0, 1), gr);
+            else launch_pre(h, L0, (const double*)rnew, pre_rbuf<double>(h, L0, 1), gr);
             vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, gd, true);
         }
         return PSC_OK;
@@ -1922,6 +2071,8 @@ void psc_amg_opts_default(psc_amg_opts* o) {
     o->build_fp32 = 0;
     o->use_graph = 1;
     o->coarse_sweeps = 30;
+    o->smoothed_prol = 0;
+    o->smoother_sweeps = 1;
 }
 
 void psc_hier_free(psc_hier* h) {
@@ -1963,6 +2114,11 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     so.coarse_max = h->opts.coarse_max;
     so.max_levels = h->opts.max_levels;
     so.coarse_sweeps = h->opts.coarse_sweeps;
+    so.prol = h->opts.smoothed_prol;
+    if (h->opts.smoother_sweeps < 1 || h->opts.smoother_sweeps > 16 || h->opts.smoothed_prol < 0 ||
+        h->opts.smoothed_prol > 1)
+        return fail(PSC_ERR_ARG, "smoother_sweeps must be 1..16 and smoothed_prol 0 or 1");
+    h->nu = h->opts.smoother_sweeps;
     st = build_hierarchy(n, rp, ci, v, so, h->host, err);
     if (st) return fail(st, err);
     const bool f32 = h->opts.build_fp32 != 0;
@@ -2035,6 +2191,13 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
         if (l == L - 1 && l > 0 && h->host.coarse_sweeps > 0) {
             if ((st = dalloc(h.get(), (void**)&D.r, H.n * sizeof(double)))) return st;
         }
+        if (l < L - 1 && h->nu > 1) {
+            for (double** q : {&D.rb, &D.s, &D.sb, &D.xt, &D.xt2})
+                if ((st = dalloc(h.get(), (void**)q, H.n * sizeof(double)))) return st;
+            if (f32)
+                for (float** q : {&D.rb32, &D.s32, &D.sb32, &D.xt32, &D.xt232})
+                    if ((st = dalloc(h.get(), (void**)q, H.n * sizeof(float)))) return st;
+        }
         if (l < L - 1) {
             if ((st = dalloc(h.get(), (void**)&D.r, H.n * sizeof(double)))) return st;
             if (f32 && (st = dalloc(h.get(), (void**)&D.r32, H.n * sizeof(float)))) return st;
@@ -2044,22 +2207,25 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
                 auto p32 = to32(H.p);
                 if ((st = upload(h.get(), &D.pval32, p32.data(), p32.size()))) return st;
             }
-            // R = P^T as CSR over coarse rows: members ascending, values p_i
-            std::vector<int32_t> rrp(H.nc + 1, 0), rci(H.n);
-            std::vector<double> rv(H.n);
-            for (int64_t i = 0; i < H.n; i++) rrp[H.agg[i] + 1]++;
+            // R = P^T as CSR over coarse rows: fine rows ascending
+            const size_t pn = H.pci.size();
+            std::vector<int32_t> rrp(H.nc + 1, 0), rci(pn);
+            std::vector<double> rv(pn);
+            for (size_t m = 0; m < pn; m++) rrp[H.pci[m] + 1]++;
             for (int64_t I = 0; I < H.nc; I++) rrp[I + 1] += rrp[I];
             std::vector<int32_t> pos(rrp.begin(), rrp.end() - 1);
             for (int64_t i = 0; i < H.n; i++) {
-                int32_t o = pos[H.agg[i]]++;
-                rci[o] = (int32_t)i;
-                rv[o] = H.p[i];
+                for (int32_t m = H.prp[i]; m < H.prp[i + 1]; m++) {
+                    int32_t o = pos[H.pci[m]]++;
+                    rci[o] = (int32_t)i;
+                    rv[o] = H.pv[m];
+                }
             }
             if ((st = upload_ell(h.get(), D.R, H.nc, H.n, rrp.data(), rci.data(), rv.data(), f32))) return st;
             // smoothed prolongator for the split post-smoothing sweep
             std::vector<int32_t> sprp, spci;
             std::vector<double> spv;
-            smoothed_prolongator(H, sprp, spci, spv);
+            jacobi_smoothed_prolongator(H, sprp, spci, spv);
             if ((st = upload_ell(h.get(), D.SP, H.n, H.nc, sprp.data(), spci.data(), spv.data(), f32))) return st;
             // A M^-1 values, packed in A's layout
             std::vector<double> sv(H.rp[H.n]);
@@ -2153,6 +2319,10 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
         s->nnz[l] = D.nnz;
         s->ell_slots[l] = D.A.slots;
         s->dia_slots[l] = D.Ad.slots;
+        if (l + 1 < L) {
+            s->p_nnz[l] = (int64_t)h->host.lev[l].pci.size();
+            s->omega[l] = h->host.lev[l].omega;
+        }
         zs += (double)D.nnz;
         // bytes per stored entry of A (and A M^-1) in the storage the kernels read
         const bool dia = h->dia && D.Ad.on();
@@ -2163,10 +2333,16 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
             // level 0 reads b and writes x in FP64 in both forms
             const double e0 = l == 0 ? 1.0 : 0.0;
             if (h->split) {
-                // pre: A M^-1, b gathered, r written; restriction: R, r, b_c;
-                // post: S P, b, minv, r read, x_c gathered, x written
-                vb64 += Z * m64 + 16 * N + N * 12 + 8 * N + 8 * Nc + Zp * 12 + 32 * N + 8 * Nc;
-                vb32 += Z * m32 + 8 * N + N * 8 + 4 * N + 4 * Nc + Zp * 8 + 16 * N + 4 * Nc + e0 * 12 * N;
+                // pre sweep 1: A M^-1, b gathered, r written; sweeps 2..nu: A M^-1,
+                // s and r gathered, b read, s and r written; restriction: R
+                // (nnz(P) entries), r, b_c; post sweep 1: S P, s (or b), minv, r
+                // read, x_c gathered, x written; sweeps 2..nu: A, x gathered, b and
+                // minv read, x written
+                const double Zr = (double)h->host.lev[l].pci.size(), nu = h->nu;
+                vb64 += Z * m64 + 16 * N + (nu - 1) * (Z * m64 + 40 * N) + Zr * 12 + 8 * N + 8 * Nc +
+                        Zp * 12 + 32 * N + 8 * Nc + (nu - 1) * (Z * m64 + 32 * N);
+                vb32 += Z * m32 + 8 * N + (nu - 1) * (Z * m32 + 20 * N) + Zr * 8 + 4 * N + 4 * Nc + Zp * 8 +
+                        16 * N + 4 * Nc + (nu - 1) * (Z * m32 + 16 * N) + e0 * 12 * N;
             } else {
                 // pre: A, b and minv gathered, r written; restriction: R, r, b_c;
                 // post: A, b, minv, p, agg, x_c gathered, x written
@@ -2191,6 +2367,8 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
     s->setup_seconds = h->setup_seconds;
     s->device_bytes = h->device_bytes;
     s->coarse_sweeps = h->host.coarse_sweeps;
+    s->smoother_sweeps = h->nu;
+    s->smoothed_prol = h->opts.smoothed_prol;
     return PSC_OK;
 }
 
@@ -2204,6 +2382,15 @@ int psc_hier_export_level(const psc_hier* h, int32_t l, int32_t* agg, double* p,
     if (rp) std::memcpy(rp, H.rp.data(), (H.n + 1) * sizeof(int32_t));
     if (ci) std::memcpy(ci, H.ci.data(), H.ci.size() * sizeof(int32_t));
     if (v) std::memcpy(v, H.v.data(), H.v.size() * sizeof(double));
+    return PSC_OK;
+}
+
+int psc_hier_export_prolongator(const psc_hier* h, int32_t l, int32_t* rp, int32_t* ci, double* v) {
+    if (!h || l < 0 || l + 1 >= (int)h->host.lev.size()) return fail(PSC_ERR_ARG, "bad level");
+    const HostLevel& H = h->host.lev[l];
+    if (rp) std::memcpy(rp, H.prp.data(), H.prp.size() * sizeof(int32_t));
+    if (ci) std::memcpy(ci, H.pci.data(), H.pci.size() * sizeof(int32_t));
+    if (v) std::memcpy(v, H.pv.data(), H.pv.size() * sizeof(double));
     return PSC_OK;
 }
 
@@ -2275,6 +2462,8 @@ int psc_tune(psc_hier* h, int32_t key, int32_t value) {
         return PSC_OK;
     }
     if (key == PSC_TUNE_SPLIT) {
+        if (value == 0 && (h->nu > 1 || h->opts.smoothed_prol))
+            return fail(PSC_ERR_ARG, "the gathering sweeps support only one sweep with the tentative prolongator");
         h->split = value != 0;
         drop_graphs(h);
         return PSC_OK;

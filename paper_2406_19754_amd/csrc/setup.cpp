@@ -58,6 +58,79 @@ void members_of(const std::vector<int32_t>& agg, int64_t nc, std::vector<int64_t
     for (size_t i = 0; i < agg.size(); i++) mem[pos[agg[i]]++] = (int32_t)i;
 }
 
+// C = A B (B has ncols columns). Row i of C sums, for each stored a_ij in
+// ascending j and then each entry (J, b_jJ) of row j of B in ascending J, the
+// product a_ij b_jJ into C[i,J] in that arrival order; columns ascending,
+// every reached entry stored.
+void spgemm(const Csr& A, const Csr& B, int64_t ncols, Csr& C) {
+    const int64_t n = A.n;
+    C.n = n;
+    C.rp.assign(n + 1, 0);
+    (void)ncols;
+    auto row = [&](int64_t i, std::vector<std::pair<int32_t, double>>& e) {
+        e.clear();
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++) {
+            const int32_t j = A.ci[k];
+            for (int32_t m = B.rp[j]; m < B.rp[j + 1]; m++) e.emplace_back(B.ci[m], A.v[k] * B.v[m]);
+        }
+        std::stable_sort(e.begin(), e.end(),
+                         [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+                             return a.first < b.first;
+                         });
+    };
+#pragma omp parallel
+    {
+        std::vector<std::pair<int32_t, double>> e;
+#pragma omp for schedule(dynamic, 1024)
+        for (int64_t i = 0; i < n; i++) {
+            row(i, e);
+            int32_t cnt = 0, last = -1;
+            for (const auto& x : e)
+                if (x.first != last) { cnt++; last = x.first; }
+            C.rp[i + 1] = cnt;
+        }
+    }
+    for (int64_t i = 0; i < n; i++) C.rp[i + 1] += C.rp[i];
+    C.ci.resize(C.rp[n]);
+    C.v.resize(C.rp[n]);
+#pragma omp parallel
+    {
+        std::vector<std::pair<int32_t, double>> e;
+#pragma omp for schedule(dynamic, 1024)
+        for (int64_t i = 0; i < n; i++) {
+            row(i, e);
+            int32_t o = C.rp[i] - 1, last = -1;
+            for (const auto& x : e) {
+                if (x.first != last) {
+                    C.ci[++o] = x.first;
+                    C.v[o] = x.second;
+                    last = x.first;
+                } else {
+                    C.v[o] += x.second;
+                }
+            }
+        }
+    }
+}
+
+// Transpose of an n x ncols CSR: row J lists (i, v_iJ) for i ascending.
+void transpose(const Csr& P, int64_t ncols, Csr& R) {
+    const int64_t n = P.n;
+    R.n = ncols;
+    R.rp.assign(ncols + 1, 0);
+    for (int64_t m = 0; m < P.rp[n]; m++) R.rp[P.ci[m] + 1]++;
+    for (int64_t J = 0; J < ncols; J++) R.rp[J + 1] += R.rp[J];
+    R.ci.resize(P.rp[n]);
+    R.v.resize(P.rp[n]);
+    std::vector<int32_t> pos(R.rp.begin(), R.rp.end() - 1);
+    for (int64_t i = 0; i < n; i++)
+        for (int32_t m = P.rp[i]; m < P.rp[i + 1]; m++) {
+            const int32_t o = pos[P.ci[m]]++;
+            R.ci[o] = (int32_t)i;
+            R.v[o] = P.v[m];
+        }
+}
+
 // Galerkin sum in canonical order (see file header). s == nullptr means s = 1.
 void galerkin(const Csr& a, const std::vector<int32_t>& agg, int64_t nc, const double* s,
               Csr& c) {
@@ -498,7 +571,56 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < F.n; i++) F.p[i] = F.w[i] / Cl.w[F.agg[i]];
         Csr Ac;
-        galerkin(A, F.agg, nc, F.p.data(), Ac);
+        if (o.prol == 0) {
+            // tentative: one entry per row, canonical Galerkin sum
+            F.prp.resize(F.n + 1);
+            for (int64_t i = 0; i <= F.n; i++) F.prp[i] = (int32_t)i;
+            F.pci = F.agg;
+            F.pv = F.p;
+            galerkin(A, F.agg, nc, F.p.data(), Ac);
+        } else {
+            // smoothed: omega = 1 / max_i sum_j |a_ij| / a_ii, then
+            // P_iJ = [J = agg_i] p_i - (omega / a_ii) (A P^)_iJ and C = P^T (A P)
+            double norm = 0.0;
+            for (int64_t i = 0; i < A.n; i++) {
+                double sabs = 0.0, aii = 0.0;
+                for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++) {
+                    sabs += std::fabs(A.v[k]);
+                    if (A.ci[k] == i) aii = A.v[k];
+                }
+                if (sabs / aii > norm) norm = sabs / aii;
+            }
+            F.omega = 1.0 / norm;
+            Csr Ph, T;
+            Ph.n = F.n;
+            Ph.rp.resize(F.n + 1);
+            for (int64_t i = 0; i <= F.n; i++) Ph.rp[i] = (int32_t)i;
+            Ph.ci = F.agg;
+            Ph.v = F.p;
+            spgemm(A, Ph, nc, T);
+            Csr Pm;
+            Pm.n = F.n;
+            Pm.rp = T.rp;
+            Pm.ci = T.ci;
+            Pm.v.resize(T.v.size());
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < F.n; i++) {
+                double aii = 0.0;
+                for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++)
+                    if (A.ci[k] == i) aii = A.v[k];
+                for (int32_t m = T.rp[i]; m < T.rp[i + 1]; m++) {
+                    const double pk = T.ci[m] == F.agg[i] ? F.p[i] : 0.0;
+                    Pm.v[m] = pk - (F.omega / aii) * T.v[m];
+                }
+            }
+            Csr AP, R;
+            spgemm(A, Pm, nc, AP);
+            transpose(Pm, nc, R);
+            spgemm(R, AP, nc, Ac);
+            F.prp.swap(Pm.rp);
+            F.pci.swap(Pm.ci);
+            F.pv.swap(Pm.v);
+        }
         Cl.rp.swap(Ac.rp);
         Cl.ci.swap(Ac.ci);
         Cl.v.swap(Ac.v);
@@ -509,57 +631,34 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
     return PSC_OK;
 }
 
-// Smoothed prolongator SP = (I - M^-1 A_l) P_l as CSR over the rows of A_l
-// with aggregate columns: with ap_iJ = sum over stored j of row i with
-// agg[j] = J of a_ij p_j (added in ascending j),
-//   sp_iJ = [J = agg[i]] p_i - minv_i ap_iJ;
-// row columns ascending (agg[i] is always present: a_ii is stored).
-void smoothed_prolongator(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
-                          std::vector<double>& v) {
-    const int64_t n = H.n;
-    rp.assign(n + 1, 0);
-#pragma omp parallel
-    {
-        std::vector<int32_t> js;
-#pragma omp for schedule(static)
-        for (int64_t i = 0; i < n; i++) {
-            js.clear();
-            for (int32_t k = H.rp[i]; k < H.rp[i + 1]; k++) js.push_back(H.agg[H.ci[k]]);
-            std::sort(js.begin(), js.end());
-            rp[i + 1] = (int32_t)(std::unique(js.begin(), js.end()) - js.begin());
+// S P = (I - M^-1 A_l) P_l as CSR over the rows of A_l with aggregate
+// columns: with (A P)_iJ from spgemm (ascending j, then row j of P),
+//   sp_iJ = P_iJ - minv_i (A P)_iJ
+// (the columns of row i of P are among those of row i of A P: a_ii is stored).
+void jacobi_smoothed_prolongator(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
+                                 std::vector<double>& v) {
+    Csr A, Pm, T;
+    A.n = H.n;
+    A.rp = H.rp;
+    A.ci = H.ci;
+    A.v = H.v;
+    Pm.n = H.n;
+    Pm.rp = H.prp;
+    Pm.ci = H.pci;
+    Pm.v = H.pv;
+    spgemm(A, Pm, H.nc, T);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < H.n; i++) {
+        int32_t m = Pm.rp[i];
+        for (int32_t k = T.rp[i]; k < T.rp[i + 1]; k++) {
+            double pk = 0.0;
+            if (m < Pm.rp[i + 1] && Pm.ci[m] == T.ci[k]) pk = Pm.v[m++];
+            T.v[k] = pk - H.minv[i] * T.v[k];
         }
     }
-    for (int64_t i = 0; i < n; i++) rp[i + 1] += rp[i];
-    ci.resize(rp[n]);
-    v.resize(rp[n]);
-#pragma omp parallel
-    {
-        std::vector<std::pair<int32_t, int32_t>> e;   // (aggregate, slot), slots ascending
-#pragma omp for schedule(static)
-        for (int64_t i = 0; i < n; i++) {
-            e.clear();
-            for (int32_t k = H.rp[i]; k < H.rp[i + 1]; k++) e.emplace_back(H.agg[H.ci[k]], k);
-            std::stable_sort(e.begin(), e.end(),
-                             [](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& b) {
-                                 return a.first < b.first;
-                             });
-            int32_t o = rp[i] - 1, last = -1;
-            for (const auto& jk : e) {
-                const double t = H.v[jk.second] * H.p[H.ci[jk.second]];
-                if (jk.first != last) {
-                    ci[++o] = jk.first;
-                    v[o] = t;
-                    last = jk.first;
-                } else {
-                    v[o] += t;
-                }
-            }
-            for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
-                const double pk = ci[k] == H.agg[i] ? H.p[i] : 0.0;
-                v[k] = pk - H.minv[i] * v[k];
-            }
-        }
-    }
+    rp.swap(T.rp);
+    ci.swap(T.ci);
+    v.swap(T.v);
 }
 
 bool pack_dia(int64_t nrows, int64_t ncols, const int32_t* rp, const int32_t* ci, const double* v,

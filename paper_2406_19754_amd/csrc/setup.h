@@ -16,7 +16,12 @@ struct HostLevel {
     std::vector<double> minv;   // l1-Jacobi inverse diagonal
     int64_t nc = 0;             // rows of the next level (0 at the coarsest)
     std::vector<int32_t> agg;   // aggregate of each row
-    std::vector<double> p;      // the single prolongator entry of each row
+    std::vector<double> p;      // the entry of row i of the tentative prolongator
+    // prolongator the V-cycle uses (CSR, aggregate columns): the tentative one,
+    // or the smoothed (I - omega D^-1 A) P^ with omega = 1/||D^-1 A||_inf
+    std::vector<int32_t> prp, pci;
+    std::vector<double> pv;
+    double omega = 0.0;
 };
 
 struct HostHier {
@@ -30,6 +35,7 @@ struct SetupOpts {
     int coarse_max = 200;
     int max_levels = 30;
     int coarse_sweeps = 30;
+    int prol = 0;               // 0 tentative prolongator, 1 smoothed
 };
 
 // Status codes follow psc.h.
@@ -38,10 +44,10 @@ int validate_csr(int64_t n, const int32_t* rp, const int32_t* ci, const double* 
 int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
                     const SetupOpts& o, HostHier& H, std::string& err);
 
-// Smoothed prolongator SP = (I - M_l^-1 A_l) P_l of a level below the
-// coarsest (rows of A_l, aggregate columns), CSR with ascending columns.
-void smoothed_prolongator(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
-                          std::vector<double>& v);
+// S P = (I - M_l^-1 A_l) P_l, the level's prolongator after one l1-Jacobi
+// sweep (rows of A_l, aggregate columns), CSR with ascending columns.
+void jacobi_smoothed_prolongator(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
+                                 std::vector<double>& v);
 
 // Pack CSR rows into hacked DIA with 64-row slices (offsets ascending per
 // slice, values diagonal-major in a slice, zeros where a row has no entry).

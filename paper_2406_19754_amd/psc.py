@@ -39,7 +39,8 @@ class PscError(RuntimeError):
 class AmgOpts(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
                 ("build_fp32", C.c_int32), ("use_graph", C.c_int32), ("host_only", C.c_int32),
-                ("coarse_sweeps", C.c_int32), ("reserved", C.c_int32 * 9)]
+                ("coarse_sweeps", C.c_int32), ("smoothed_prol", C.c_int32), ("smoother_sweeps", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
 
 
 class HierStats(C.Structure):
@@ -50,7 +51,8 @@ class HierStats(C.Structure):
                 ("vcycle_bytes_fp32", C.c_double), ("spmv_bytes_fp64", C.c_double),
                 ("setup_seconds", C.c_double), ("device_bytes", C.c_int64),
                 ("coarse_sweeps", C.c_int32), ("sp_nnz", C.c_int64 * MAX_LEVELS),
-                ("dia_slots", C.c_int64 * MAX_LEVELS)]
+                ("dia_slots", C.c_int64 * MAX_LEVELS), ("p_nnz", C.c_int64 * MAX_LEVELS),
+                ("omega", C.c_double * MAX_LEVELS), ("smoother_sweeps", C.c_int32), ("smoothed_prol", C.c_int32)]
 
 
 def _load():
@@ -69,6 +71,7 @@ def _load():
         "psc_fcg_solve": ([vp, vp, i32, vp, vp, f64, i32, P(i32), P(f64), P(i32)], C.c_int),
         "psc_hier_info": ([vp, P(HierStats)], C.c_int),
         "psc_hier_export_level": ([vp, i32, vp, vp, vp, vp, vp, vp], C.c_int),
+        "psc_hier_export_prolongator": ([vp, i32, vp, vp, vp], C.c_int),
         "psc_vcycle_apply": ([vp, i32, vp, vp], C.c_int),
         "psc_spmv": ([vp, i32, i32, vp, vp], C.c_int),
         "psc_timing_enable": ([vp, i32], C.c_int),
@@ -138,12 +141,14 @@ class Hierarchy:
     """AMG hierarchy handle (psc_amg_build)."""
 
     def __init__(self, rowptr, col, val, sweeps=2, coarse_max=200, max_levels=30,
-                 build_fp32=False, use_graph=True, host_only=False, stream=None, coarse_sweeps=30):
+                 build_fp32=False, use_graph=True, host_only=False, stream=None, coarse_sweeps=30,
+                 smoothed_prol=False, smoother_sweeps=1):
         import torch
         o = AmgOpts()
         _lib.psc_amg_opts_default(C.byref(o))
         o.sweeps, o.coarse_max, o.max_levels = sweeps, coarse_max, max_levels
         o.coarse_sweeps = coarse_sweeps
+        o.smoothed_prol, o.smoother_sweeps = int(smoothed_prol), smoother_sweeps
         o.build_fp32, o.use_graph, o.host_only = int(build_fp32), int(use_graph), int(host_only)
         rp, prp = _hptr(rowptr, np.int32)
         ci, pci = _hptr(col, np.int32)
@@ -169,7 +174,9 @@ class Hierarchy:
                     operator_complexity=s.operator_complexity, vcycle_bytes_fp64=s.vcycle_bytes_fp64,
                     vcycle_bytes_fp32=s.vcycle_bytes_fp32, spmv_bytes_fp64=s.spmv_bytes_fp64,
                     setup_seconds=s.setup_seconds, device_bytes=s.device_bytes,
-                    coarse_sweeps=s.coarse_sweeps, sp_nnz=list(s.sp_nnz[:L]), dia_slots=list(s.dia_slots[:L]))
+                    coarse_sweeps=s.coarse_sweeps, sp_nnz=list(s.sp_nnz[:L]), dia_slots=list(s.dia_slots[:L]),
+                    p_nnz=list(s.p_nnz[:L]), omega=list(s.omega[:L]), smoother_sweeps=s.smoother_sweeps,
+                    smoothed_prol=s.smoothed_prol)
 
     def export_level(self, l):
         inf = self.info()
@@ -184,6 +191,15 @@ class Hierarchy:
         ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
         _check(_lib.psc_hier_export_level(self._h, l, ptr(agg), ptr(p), ptr(minv), ptr(rp), ptr(ci), ptr(v)))
         return dict(n=n, nnz=nnz, agg=agg, p=p, minv=minv, rowptr=rp, col=ci, val=v)
+
+    def export_prolongator(self, l):
+        """(rowptr, col, val) of the prolongator P_l the V-cycle uses."""
+        inf = self.info()
+        n, nnz = inf["rows"][l], inf["p_nnz"][l]
+        rp, ci, v = np.empty(n + 1, np.int32), np.empty(nnz, np.int32), np.empty(nnz)
+        _check(_lib.psc_hier_export_prolongator(self._h, l, rp.ctypes.data_as(C.c_void_p),
+                                                ci.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p)))
+        return rp, ci, v
 
     def pcg(self, b, x, rtol=1e-6, maxit=1000):
         it, rr = C.c_int32(), C.c_double()

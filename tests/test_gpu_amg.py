@@ -310,3 +310,54 @@ def test_fcg_tight_tolerance_residual_replacement(psc, prec):
         assert g["status"] == psc.OK and g["relres"] <= 1e-11
         res.append(g["iters"])
     assert abs(res[0] - res[1]) <= 3
+
+
+SMOOTHING = {
+    # name: (matching sweeps, smoothed prolongator, smoother sweeps)
+    "smatch": (3, True, 4),
+    "tentative_nu2": (2, False, 2),
+    "smoothed_nu1": (2, True, 1),
+    "smoothed_nu3": (3, True, 3),
+}
+
+
+@pytest.mark.parametrize("cfg", list(SMOOTHING))
+@pytest.mark.parametrize("case", ["poisson24", "diffusion20_az100", "random_long_rows"])
+def test_smoothing_configurations_match_oracle(psc, case, cfg):
+    sweeps, smoothed, nu = SMOOTHING[cfg]
+    rp, c, v = P.poisson7(24) if case == "poisson24" else CASES[case]()
+    cm = 40 if case == "random_long_rows" else 200
+    h = psc.Hierarchy(rp, c, v, coarse_max=cm, sweeps=sweeps, build_fp32=True, smoothed_prol=smoothed,
+                      smoother_sweeps=nu)
+    o = oracle.Hierarchy(rp, c, v, coarse_max=cm, sweeps=sweeps, prol=int(smoothed), nu=nu)
+    assert h.info()["rows"] == o.sizes()
+    n = len(rp) - 1
+    x = np.random.default_rng(5).standard_normal(n)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.vcycle(dev(x), y)
+    ref = o.vcycle(x)
+    assert np.linalg.norm(y.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+    h.vcycle(dev(x), y, prec=psc.FP32)
+    ref32 = o.vcycle32(x)
+    assert np.linalg.norm(y.cpu().numpy() - ref32) <= 1e-5 * np.linalg.norm(ref32)
+    b = P.rhs_from_solution(rp, c, v, P.x_true(n, 1))
+    xg = torch.zeros(n, dtype=torch.float64, device="cuda")
+    r = o.pcg(b)
+    for fused in (1, 0):
+        h.tune(psc.TUNE_FUSED_PCG, fused)
+        xg.zero_()
+        g = h.pcg(dev(b), xg)
+        assert g["status"] == psc.OK and abs(g["iters"] - r["iters"]) <= 1 and g["relres"] <= 1e-6
+    k = min(g["iters"], r["iters"])
+    xg.zero_()
+    h.pcg(dev(b), xg, rtol=1e-30, maxit=k)
+    refk = o.pcg(b, rtol=1e-30, maxit=k)["x"]
+    assert np.linalg.norm(xg.cpu().numpy() - refk) <= 1e-8 * np.linalg.norm(refk)
+    h.tune(psc.TUNE_FUSED_PCG, 1)
+    r32 = o.fcg(b, form=1)
+    xg.zero_()
+    g = h.fcg(dev(b), xg, prec=psc.FP32)
+    assert abs(g["iters"] - r32["iters"]) <= 1 and g["relres"] <= 1e-6
+    if nu > 1 or smoothed:
+        with pytest.raises(psc.PscError):
+            h.tune(psc.TUNE_SPLIT, 0)

@@ -18,6 +18,15 @@ CASES = {
     "diffusion48_lognormal_stalls": (lambda: P.diffusion7(48, seed=0), 200, 2),
 }
 
+# smoothed prolongator (general Galerkin product); aggregates <= 8 is the
+# paper's SMATCH setting
+SMOOTHED = {
+    "poisson24_smatch": (lambda: P.poisson7(24), 200, 3),
+    "poisson9_smoothed": (lambda: P.poisson7(9), 40, 2),
+    "diffusion12_az100_smoothed": (lambda: P.diffusion7(12, seed=0, az=100.0), 100, 3),
+    "random_spd_smoothed": (lambda: P.random_spd_csr(400, 3, density=0.02, maxrow=40), 40, 2),
+}
+
 
 @pytest.mark.parametrize("case", list(CASES))
 def test_host_hierarchy_bit_identical_to_oracle(case):
@@ -77,3 +86,36 @@ def test_stall_above_dense_limit_uses_jacobi_or_fails_without_sweeps():
     with pytest.raises(psc.PscError) as e:
         psc.Hierarchy(rp, c, v, host_only=True, coarse_sweeps=-1)
     assert e.value.status == psc.ERR_ARG
+
+
+@pytest.mark.parametrize("case", list(SMOOTHED))
+def test_smoothed_hierarchy_bit_identical_to_oracle(case):
+    mk, cm, sweeps = SMOOTHED[case]
+    rp, c, v = mk()
+    h = psc.Hierarchy(rp, c, v, host_only=True, coarse_max=cm, sweeps=sweeps, smoothed_prol=True,
+                      smoother_sweeps=4)
+    o = oracle.Hierarchy(rp, c, v, coarse_max=cm, sweeps=sweeps, prol=1, nu=4)
+    inf = h.info()
+    assert inf["smoothed_prol"] == 1 and inf["smoother_sweeps"] == 4
+    assert inf["rows"] == o.sizes() and inf["nnz"] == o.nnzs()
+    for l in range(inf["levels"]):
+        a, b = h.export_level(l), o.level(l)
+        for key in ["rowptr", "col", "val", "minv"]:
+            assert np.array_equal(a[key], b[key]), (l, key)
+        if l < inf["levels"] - 1:
+            assert np.array_equal(a["agg"], b["agg"]) and np.array_equal(a["p"], b["p"]), l
+            prp, pci, pv = h.export_prolongator(l)
+            orp, oci, ov, om = o.prolongator(l)
+            assert np.array_equal(prp, orp) and np.array_equal(pci, oci) and np.array_equal(pv, ov), l
+            assert inf["omega"][l] == om and inf["p_nnz"][l] == len(ov)
+
+
+def test_tentative_prolongator_export_is_the_aggregate_map():
+    rp, c, v = P.poisson7(10)
+    h = psc.Hierarchy(rp, c, v, host_only=True)
+    L0 = h.export_level(0)
+    prp, pci, pv = h.export_prolongator(0)
+    assert np.array_equal(prp, np.arange(1001)) and np.array_equal(pci, L0["agg"]) and np.array_equal(pv, L0["p"])
+    assert h.info()["omega"][0] == 0.0
+    with pytest.raises(psc.PscError):
+        psc.Hierarchy(rp, c, v, host_only=True, smoother_sweeps=0)

@@ -395,6 +395,107 @@ def test_lognormal_diffusion_stalls_and_pcg_converges():
     assert r["status"] == oracle.OK and r["relres"] <= 1e-6
 
 
+def _laplace1d(n):
+    A = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1], format="csr")
+    A.sort_indices()
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.copy()
+
+
+def test_smoothed_prolongator_1d_closed_form():
+    # 1-D Laplacian (2, -1): all matching weights tie, so one sweep pairs
+    # (0,1), (2,3), ...; P^ = 1/sqrt(2) on each pair; ||D^-1 A||_inf = 2 gives
+    # omega = 1/2 and P = (I - A/4) P^: the classic smoothed-aggregation
+    # columns (1/4, 3/4, 3/4, 1/4) / sqrt(2).
+    n = 16
+    rp, c, v = _laplace1d(n)
+    h = oracle.Hierarchy(rp, c, v, sweeps=1, coarse_max=4, prol=1)
+    L0 = h.level(0)
+    assert np.array_equal(L0["agg"], np.arange(n) // 2)
+    prp, pci, pv, omega = h.prolongator(0)
+    assert omega == 0.5
+    Pm = sp.csr_matrix((pv, pci, prp), shape=(n, n // 2)).toarray()
+    ref = np.zeros((n, n // 2))
+    for J in range(n // 2):
+        ref[2 * J, J] = ref[2 * J + 1, J] = 0.75
+        if 2 * J - 1 >= 0:
+            ref[2 * J - 1, J] = 0.25
+        if 2 * J + 2 < n:
+            ref[2 * J + 2, J] = 0.25
+    np.testing.assert_allclose(Pm, ref / np.sqrt(2), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("case", ["poisson10_aggr8", "poisson9odd", "diffusion10", "random"])
+def test_smoothed_hierarchy_galerkin_matches_dense(case):
+    if case == "poisson10_aggr8":
+        rp, c, v = P.poisson7(10)
+        sweeps = 3
+    elif case == "poisson9odd":
+        rp, c, v = P.poisson7(9)
+        sweeps = 2
+    elif case == "diffusion10":
+        rp, c, v = P.diffusion7(10, seed=1, az=100.0)
+        sweeps = 2
+    else:
+        rp, c, v = P.random_spd_csr(300, 7, density=0.02, maxrow=30)
+        sweeps = 2
+    h = oracle.Hierarchy(rp, c, v, sweeps=sweeps, coarse_max=40, prol=1)
+    assert h.nlevels >= 2
+    for l in range(h.nlevels - 1):
+        L, C = h.level(l), h.level(l + 1)
+        A = dense(L["rowptr"], L["col"], L["val"])
+        prp, pci, pv, omega = h.prolongator(l)
+        Pm = sp.csr_matrix((pv, pci, prp), shape=(L["n"], L["nc"])).toarray()
+        # omega from its definition, P = (I - omega D^-1 A) P^ densely
+        d = np.diag(A)
+        assert omega == pytest.approx(1.0 / (np.abs(A).sum(axis=1) / d).max(), rel=1e-15)
+        Ph = prolongator(L)
+        np.testing.assert_allclose(Pm, Ph - omega * (A / d[:, None]) @ Ph, rtol=0, atol=1e-14)
+        Ac = dense(C["rowptr"], C["col"], C["val"])
+        scale = np.abs(A).max()
+        np.testing.assert_allclose(Ac, Pm.T @ A @ Pm, rtol=0, atol=1e-13 * scale)
+        assert np.abs(Ac - Ac.T).max() <= 1e-13 * np.abs(Ac).max()
+        if L["nc"] <= 1500:
+            assert np.linalg.eigvalsh(Ac).min() > 0
+        counts = np.bincount(L["agg"], minlength=L["nc"])
+        assert counts.max() <= 2 ** sweeps and counts.min() >= 1
+
+
+@pytest.mark.parametrize("prol,nu", [(0, 2), (1, 1), (1, 3)])
+def test_vcycle_nu_sweeps_two_level_formula(prol, nu):
+    # eq. (amg) with nu smoothing sweeps: E = S^nu (I - P A_c^-1 P^T A) S^nu,
+    # S = I - M^-1 A, and B = (I - E) A^-1.
+    n = 8
+    rp, c, v = P.poisson7(n)
+    h = oracle.Hierarchy(rp, c, v, prol=prol, nu=nu)
+    assert h.nlevels == 2
+    L0, L1 = h.level(0), h.level(1)
+    A = dense(rp, c, v)
+    Ac = dense(L1["rowptr"], L1["col"], L1["val"])
+    prp, pci, pv, _ = h.prolongator(0)
+    Pm = sp.csr_matrix((pv, pci, prp), shape=(512, L0["nc"])).toarray()
+    I = np.eye(512)
+    S = I - L0["minv"][:, None] * A
+    Snu = np.linalg.matrix_power(S, nu)
+    E = Snu @ (I - Pm @ np.linalg.solve(Ac, Pm.T @ A)) @ Snu
+    Bref = (I - E) @ np.linalg.inv(A)
+    B = np.stack([h.vcycle(I[:, j]) for j in range(512)], axis=1)
+    np.testing.assert_allclose(B, Bref, rtol=0, atol=1e-12)
+    assert np.abs(B - B.T).max() < 1e-13
+    B32 = np.stack([h.vcycle32(I[:, j]) for j in range(0, 512, 37)], axis=1)
+    assert np.abs(B32 - Bref[:, ::37]).max() <= 1e-5 * np.abs(Bref).max()
+
+
+def test_smatch_beats_tentative_in_iterations():
+    # SMATCH-style (aggregates <= 8, smoothed prolongator, 4 sweeps) against
+    # the tentative V(1,1) of the main path on the same problem
+    rp, c, v = P.poisson7(32)
+    b = P.rhs_from_solution(rp, c, v, P.x_true(32 ** 3, 0))
+    sm = oracle.Hierarchy(rp, c, v, sweeps=3, prol=1, nu=4).pcg(b)
+    vm = oracle.Hierarchy(rp, c, v).pcg(b)
+    assert sm["status"] == vm["status"] == oracle.OK
+    assert sm["iters"] < vm["iters"] and sm["relres"] <= 1e-6
+
+
 def test_vcycle_multilevel_symmetric_positive():
     rp, c, v = P.poisson7(16)
     h = oracle.Hierarchy(rp, c, v, coarse_max=30)
