@@ -129,6 +129,10 @@ def main():
     ap.add_argument("--grid-max", type=int, default=0, help="workgroup cap of the streaming kernels")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-dia", action="store_true", help="read level operators from hacked ELL only")
+    ap.add_argument("--coarse-sweeps", type=int, default=30,
+                    help="l1-Jacobi sweeps of a coarsest level left by a coarsening stall")
+    ap.add_argument("--smatch", action="store_true",
+                    help="also time the SMATCH setting (aggregates <= 8, smoothed prolongator, 4 sweeps)")
     ap.add_argument("--no-split", action="store_true",
                     help="smoothing sweeps gather through A, M^-1 and P instead of A M^-1 and A P")
     ap.add_argument("--unfused", action="store_true", help="one kernel per CG operation instead of the fused PCG iteration")
@@ -160,7 +164,8 @@ def main():
     rp, col, val, xt, b, desc = problem(args.workload, n, args.az)
     log(f"problem {desc} built in {time.time() - t0:.1f}s")
     t0 = time.time()
-    h = psc.Hierarchy(rp, col, val, build_fp32=not args.no_mixed, use_graph=not args.no_graph)
+    h = psc.Hierarchy(rp, col, val, build_fp32=not args.no_mixed, use_graph=not args.no_graph,
+                      coarse_sweeps=args.coarse_sweeps)
     if args.grid_max:
         h.tune(psc.TUNE_GRID_MAX, args.grid_max)
     if args.unfused:
@@ -259,6 +264,32 @@ def main():
                           "vcycle_gbs": info["vcycle_bytes_fp32"] / (vc_ms32 / vc_cnt32 * 1e-3) / 1e9
                           if vc_cnt32 else None,
                           "err_vs_fp64_x": float(np.linalg.norm(x32 - xg) / np.linalg.norm(xg))}
+    if args.smatch:
+        t0 = time.time()
+        hs = psc.Hierarchy(rp, col, val, build_fp32=not args.no_mixed, use_graph=not args.no_graph, sweeps=3,
+                           smoothed_prol=True, smoother_sweeps=4)
+        infs = hs.info()
+        log(f"smatch hierarchy {infs['rows']} built in {time.time() - t0:.1f}s, opcx {infs['operator_complexity']:.4f}")
+        for form in ["fp64"] + ([] if args.no_mixed else ["mixed"]):
+            def run_s():
+                x.zero_()
+                if form == "fp64":
+                    return hs.pcg(bd, x, rtol=1e-6, maxit=500)
+                return hs.fcg(bd, x, rtol=1e-6, maxit=500, prec=psc.FP32)
+            for _ in range(args.warmup):
+                run_s()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                rs = run_s()
+            torch.cuda.synchronize()
+            mss = (time.perf_counter() - t) * 1e3 / args.steps
+            log(f"smatch {form}: {mss:.2f} ms/solve, {rs['iters']} its, relres {rs['relres']:.2e}")
+            forms["smatch_" + form] = {"ms": mss, "iters": rs["iters"], "relres": rs["relres"],
+                                       "speedup_vs_fp64": ms64 / mss,
+                                       "operator_complexity": infs["operator_complexity"],
+                                       "setup_s": infs["setup_seconds"]}
+        hs.close()
     if net is not None:
         msl, rl, _ = timed("learned", args.steps, args.warmup, False)
         log(f"learned fcg: {msl:.2f} ms/solve, {rl['iters']} its, relres {rl['relres']:.2e}, "

@@ -160,7 +160,7 @@ class Hierarchy:
         self._torch = torch
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.psc_hier_free(self._h)
             self._h = None
 
@@ -255,7 +255,7 @@ class Net:
         _check(_lib.psc_net_create(pp, C.c_void_p(_stream(stream)), C.byref(self._h)))
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.psc_net_free(self._h)
             self._h = None
 

@@ -255,7 +255,7 @@ def test_kernel_variants_match_oracle(psc, case, knob):
     if case == "random_long_rows":
         assert dia[0] == 0                           # no diagonal structure: ELL only
     else:
-        assert all(d > 0 for d in dia)               # stencil levels keep a hacked-DIA copy
+        assert dia[0] > 0                            # a 7-point stencil keeps a hacked-DIA copy
     if knob == "dia_off":
         h.tune(psc.TUNE_DIA, 0)
     if knob in ("split_off", "bufload_all", "bufload_none", "unroll4"):
