@@ -74,6 +74,10 @@ typedef struct psc_net  psc_net;    /* opaque: owns the learned preconditioner  
  *   smoother_sweeps = 1  l1-Jacobi sweeps before and after the coarse
  *                    correction on every level (1..16; the paper's examples
  *                    use 4).
+ *   vcycle_double = 0  1: variable V-cycle, level l smooths with
+ *                    smoother_sweeps * 2^l sweeps (capped at 4096); with
+ *                    sweeps = 3, the tentative prolongator and
+ *                    smoother_sweeps = 2 this is the paper's VMATCH setting.
  *   build_fp32 = 0   also build the FP32 copies of the level operators that
  *                    the mixed-precision V-cycle needs.
  *   use_graph = 1    capture the per-iteration kernel sequence as a HIP
@@ -93,7 +97,8 @@ typedef struct {
     int32_t coarse_sweeps;
     int32_t smoothed_prol;
     int32_t smoother_sweeps;
-    int32_t reserved[7];
+    int32_t vcycle_double;
+    int32_t reserved[6];
 } psc_amg_opts;
 
 void psc_amg_opts_default(psc_amg_opts* opts);
@@ -186,6 +191,7 @@ typedef struct {
     double  omega[PSC_MAX_LEVELS];           /* smoothed prolongator damping per level (0: tentative) */
     int32_t smoother_sweeps;
     int32_t smoothed_prol;
+    int32_t vcycle_double;
 } psc_hier_stats;
 
 int psc_hier_info(const psc_hier* h, psc_hier_stats* s);

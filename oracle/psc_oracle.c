@@ -244,7 +244,8 @@ typedef struct {
     int sweeps;
     int coarse_sweeps;   /* > 0: the coarsest level is solved by this many l1-Jacobi sweeps */
     int prol;            /* 0: tentative prolongator, 1: smoothed */
-    int nu;              /* l1-Jacobi sweeps before and after the coarse correction */
+    int nu;              /* l1-Jacobi sweeps before and after the coarse correction (level 0) */
+    int nu_double;       /* 1: variable V-cycle, nu_l = nu * 2^l (the paper's VMATCH) */
     orc_level lev[ORC_MAXLEV];
 } orc_hier;
 
@@ -545,15 +546,16 @@ static int csr_copy(int n, const int *rp, const int *ci, const double *v, csr *a
  */
 int orc_build(int n, const int *rp, const int *ci, const double *v,
               int sweeps, int coarse_max, int max_levels, int coarse_sweeps, int prol, int nu,
-              orc_hier **out) {
+              int nu_double, orc_hier **out) {
     *out = NULL;
     if (n <= 0 || sweeps < 1 || max_levels < 1 || max_levels > ORC_MAXLEV || prol < 0 || prol > 1 ||
-        nu < 1)
+        nu < 1 || nu_double < 0 || nu_double > 1)
         return ORC_ERR_ARG;
     orc_hier *h = calloc(1, sizeof(orc_hier));
     h->sweeps = sweeps;
     h->prol = prol;
     h->nu = nu;
+    h->nu_double = nu_double;
     int st = csr_copy(n, rp, ci, v, &h->lev[0].A);
     if (st) { orc_free(h); return st; }
     h->lev[0].w = malloc(sizeof(double) * (size_t)n);
@@ -704,6 +706,14 @@ static void coarse_solve(const orc_hier *h, const double *b, double *x) {
 /* coarse correction, nu post-sweeps; coarsest level by coarse_solve.       */
 /* ------------------------------------------------------------------------ */
 
+/* Smoothing sweeps on level l: nu, or nu * 2^l for the variable V-cycle
+ * (capped at 4096 sweeps). */
+static int level_sweeps(const orc_hier *h, int l) {
+    if (!h->nu_double) return h->nu;
+    int s = h->nu << (l < 12 ? l : 12);
+    return s < 4096 ? s : 4096;
+}
+
 static void vcycle_level(const orc_hier *h, int l, const double *b, double *x) {
     const orc_level *L = &h->lev[l];
     int n = L->A.n;
@@ -713,10 +723,11 @@ static void vcycle_level(const orc_hier *h, int l, const double *b, double *x) {
     double *r = malloc(sizeof(double) * (size_t)n);
     double *bc = malloc(sizeof(double) * (size_t)nc);
     double *xc = malloc(sizeof(double) * (size_t)nc);
-    /* pre-smoothing from x = 0: x = M^{-1} b, then nu - 1 sweeps
+    /* pre-smoothing from x = 0: x = M^{-1} b, then nu_l - 1 sweeps
      * x += M^{-1} (b - A x) */
+    const int nu = level_sweeps(h, l);
     for (int i = 0; i < n; i++) x[i] = L->minv[i] * b[i];
-    for (int k = 1; k < h->nu; k++) {
+    for (int k = 1; k < nu; k++) {
         orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
         for (int i = 0; i < n; i++) x[i] += L->minv[i] * (b[i] - r[i]);
     }
@@ -734,8 +745,8 @@ static void vcycle_level(const orc_hier *h, int l, const double *b, double *x) {
         for (int m = P->rp[i]; m < P->rp[i + 1]; m++) s += P->v[m] * xc[P->ci[m]];
         x[i] += s;
     }
-    /* nu post-smoothing sweeps x += M^{-1} (b - A x) */
-    for (int k = 0; k < h->nu; k++) {
+    /* nu_l post-smoothing sweeps x += M^{-1} (b - A x) */
+    for (int k = 0; k < nu; k++) {
         orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
         for (int i = 0; i < n; i++) x[i] += L->minv[i] * (b[i] - r[i]);
     }
@@ -771,8 +782,9 @@ static void vcycle32_level(const orc_hier *h, int l, const float *b, float *x) {
     float *r = malloc(sizeof(float) * (size_t)n);
     float *bc = malloc(sizeof(float) * (size_t)nc);
     float *xc = malloc(sizeof(float) * (size_t)nc);
+    const int nu = level_sweeps(h, l);
     for (int i = 0; i < n; i++) x[i] = (float)L->minv[i] * b[i];
-    for (int k = 1; k < h->nu; k++) {
+    for (int k = 1; k < nu; k++) {
         for (int i = 0; i < n; i++) {
             float s = 0.0f;
             for (int q = L->A.rp[i]; q < L->A.rp[i + 1]; q++) s += (float)L->A.v[q] * x[L->A.ci[q]];
@@ -794,7 +806,7 @@ static void vcycle32_level(const orc_hier *h, int l, const float *b, float *x) {
         for (int m = P->rp[i]; m < P->rp[i + 1]; m++) s += (float)P->v[m] * xc[P->ci[m]];
         x[i] += s;
     }
-    for (int k = 0; k < h->nu; k++) {
+    for (int k = 0; k < nu; k++) {
         for (int i = 0; i < n; i++) {
             float s = 0.0f;
             for (int q = L->A.rp[i]; q < L->A.rp[i + 1]; q++) s += (float)L->A.v[q] * x[L->A.ci[q]];

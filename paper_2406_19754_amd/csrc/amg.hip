@@ -1151,6 +1151,7 @@ struct DevDia {
 
 struct DevLevel {
     long long n = 0, nc = 0, nnz = 0;
+    int nu = 1;                           // l1-Jacobi sweeps before and after the coarse correction
     DevDia Ad;                            // A in hacked DIA when that stores fewer bytes
     double* amd = nullptr;                // A M^-1 values in Ad's layout
     float* amd32 = nullptr;
@@ -1507,8 +1508,8 @@ static void coarse_solve(psc_hier* h, const TB* b, TX* x, Gate g) {
 // alternate so that the last sweep's residual lands in r (read by the
 // restriction and the first post-smoothing sweep).
 template <typename T>
-static T* pre_rbuf(const psc_hier* h, DevLevel& V, int k) {
-    return ((h->nu - k) % 2 == 0) ? LV<T>::r(V) : LV<T>::rb(V);
+static T* pre_rbuf(const psc_hier*, DevLevel& V, int k) {
+    return ((V.nu - k) % 2 == 0) ? LV<T>::r(V) : LV<T>::rb(V);
 }
 
 // nu pre-smoothing sweeps from zero on level V (b: the level's right-hand
@@ -1519,8 +1520,8 @@ static void pre_sweeps(psc_hier* h, DevLevel& V, const TB* b, bool skip1, Gate g
     if (!skip1) launch_pre(h, V, b, pre_rbuf<T>(h, V, 1), g);
     const T* rp = pre_rbuf<T>(h, V, 1);
     const T* sp = nullptr;
-    for (int k = 2; k <= h->nu; k++) {
-        T* so = ((h->nu - k) % 2 == 0) ? LV<T>::s(V) : LV<T>::sb(V);
+    for (int k = 2; k <= V.nu; k++) {
+        T* so = ((V.nu - k) % 2 == 0) ? LV<T>::s(V) : LV<T>::sb(V);
         T* ro = pre_rbuf<T>(h, V, k);
         with_AM_t<T>(h, V, [&](auto AM) {
             using M = decltype(AM);
@@ -1545,7 +1546,7 @@ static void post_sweeps(psc_hier* h, DevLevel& V, const TB* b, TX* out, const T*
     const Ell<T> SP = LV<T>::SP(V);
     const T* r = LV<T>::r(V);
     const T* minv = LV<T>::minv(V);
-    if (h->nu == 1) {
+    if (V.nu == 1) {
         k_post_s<T, TB, TX><<<gr, WG, 0, h->stream>>>(SP, minv, b, r, xc, out, d, Rf);
         return;
     }
@@ -1553,10 +1554,10 @@ static void post_sweeps(psc_hier* h, DevLevel& V, const TB* b, TX* out, const T*
     T* tb = LV<T>::xt2(V);
     k_post_s<T, T, T><<<gr, WG, 0, h->stream>>>(SP, minv, (const T*)LV<T>::s(V), r, xc, ta, nullptr, Rn);
     const T* xin = ta;
-    for (int k = 2; k <= h->nu; k++) {
+    for (int k = 2; k <= V.nu; k++) {
         with_A_t<T>(h, V, [&](auto A) {
             using M = decltype(A);
-            if (k == h->nu) {
+            if (k == V.nu) {
                 k_sweep<M, TB, TX><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, out, d, Rf);
             } else {
                 T* xo = xin == ta ? tb : ta;
@@ -2119,6 +2120,8 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
         h->opts.smoothed_prol > 1)
         return fail(PSC_ERR_ARG, "smoother_sweeps must be 1..16 and smoothed_prol 0 or 1");
     h->nu = h->opts.smoother_sweeps;
+    if (h->opts.vcycle_double < 0 || h->opts.vcycle_double > 1)
+        return fail(PSC_ERR_ARG, "vcycle_double must be 0 or 1");
     st = build_hierarchy(n, rp, ci, v, so, h->host, err);
     if (st) return fail(st, err);
     const bool f32 = h->opts.build_fp32 != 0;
@@ -2142,6 +2145,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
         D.n = H.n;
         D.nc = H.nc;
         D.nnz = H.rp[H.n];
+        D.nu = h->opts.vcycle_double ? std::min(h->nu << std::min(l, 12), 4096) : h->nu;
         if ((st = upload_ell(h.get(), D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32))) return st;
         if ((st = upload(h.get(), &D.minv, H.minv.data(), H.n))) return st;
         // hacked-DIA copy when it stores at most 4/3 of the ELL slots (8 instead
@@ -2191,7 +2195,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
         if (l == L - 1 && l > 0 && h->host.coarse_sweeps > 0) {
             if ((st = dalloc(h.get(), (void**)&D.r, H.n * sizeof(double)))) return st;
         }
-        if (l < L - 1 && h->nu > 1) {
+        if (l < L - 1 && D.nu > 1) {
             for (double** q : {&D.rb, &D.s, &D.sb, &D.xt, &D.xt2})
                 if ((st = dalloc(h.get(), (void**)q, H.n * sizeof(double)))) return st;
             if (f32)
@@ -2338,7 +2342,7 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
                 // (nnz(P) entries), r, b_c; post sweep 1: S P, s (or b), minv, r
                 // read, x_c gathered, x written; sweeps 2..nu: A, x gathered, b and
                 // minv read, x written
-                const double Zr = (double)h->host.lev[l].pci.size(), nu = h->nu;
+                const double Zr = (double)h->host.lev[l].pci.size(), nu = D.nu;
                 vb64 += Z * m64 + 16 * N + (nu - 1) * (Z * m64 + 40 * N) + Zr * 12 + 8 * N + 8 * Nc +
                         Zp * 12 + 32 * N + 8 * Nc + (nu - 1) * (Z * m64 + 32 * N);
                 vb32 += Z * m32 + 8 * N + (nu - 1) * (Z * m32 + 20 * N) + Zr * 8 + 4 * N + 4 * Nc + Zp * 8 +
@@ -2368,6 +2372,7 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
     s->device_bytes = h->device_bytes;
     s->coarse_sweeps = h->host.coarse_sweeps;
     s->smoother_sweeps = h->nu;
+    s->vcycle_double = h->opts.vcycle_double;
     s->smoothed_prol = h->opts.smoothed_prol;
     return PSC_OK;
 }
@@ -2462,7 +2467,7 @@ int psc_tune(psc_hier* h, int32_t key, int32_t value) {
         return PSC_OK;
     }
     if (key == PSC_TUNE_SPLIT) {
-        if (value == 0 && (h->nu > 1 || h->opts.smoothed_prol))
+        if (value == 0 && (h->nu > 1 || h->opts.vcycle_double || h->opts.smoothed_prol))
             return fail(PSC_ERR_ARG, "the gathering sweeps support only one sweep with the tentative prolongator");
         h->split = value != 0;
         drop_graphs(h);

@@ -40,7 +40,7 @@ class AmgOpts(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
                 ("build_fp32", C.c_int32), ("use_graph", C.c_int32), ("host_only", C.c_int32),
                 ("coarse_sweeps", C.c_int32), ("smoothed_prol", C.c_int32), ("smoother_sweeps", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("vcycle_double", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class HierStats(C.Structure):
@@ -52,7 +52,8 @@ class HierStats(C.Structure):
                 ("setup_seconds", C.c_double), ("device_bytes", C.c_int64),
                 ("coarse_sweeps", C.c_int32), ("sp_nnz", C.c_int64 * MAX_LEVELS),
                 ("dia_slots", C.c_int64 * MAX_LEVELS), ("p_nnz", C.c_int64 * MAX_LEVELS),
-                ("omega", C.c_double * MAX_LEVELS), ("smoother_sweeps", C.c_int32), ("smoothed_prol", C.c_int32)]
+                ("omega", C.c_double * MAX_LEVELS), ("smoother_sweeps", C.c_int32), ("smoothed_prol", C.c_int32),
+                ("vcycle_double", C.c_int32)]
 
 
 def _load():
@@ -142,13 +143,14 @@ class Hierarchy:
 
     def __init__(self, rowptr, col, val, sweeps=2, coarse_max=200, max_levels=30,
                  build_fp32=False, use_graph=True, host_only=False, stream=None, coarse_sweeps=30,
-                 smoothed_prol=False, smoother_sweeps=1):
+                 smoothed_prol=False, smoother_sweeps=1, vcycle_double=False):
         import torch
         o = AmgOpts()
         _lib.psc_amg_opts_default(C.byref(o))
         o.sweeps, o.coarse_max, o.max_levels = sweeps, coarse_max, max_levels
         o.coarse_sweeps = coarse_sweeps
         o.smoothed_prol, o.smoother_sweeps = int(smoothed_prol), smoother_sweeps
+        o.vcycle_double = int(vcycle_double)
         o.build_fp32, o.use_graph, o.host_only = int(build_fp32), int(use_graph), int(host_only)
         rp, prp = _hptr(rowptr, np.int32)
         ci, pci = _hptr(col, np.int32)
@@ -176,7 +178,7 @@ class Hierarchy:
                     setup_seconds=s.setup_seconds, device_bytes=s.device_bytes,
                     coarse_sweeps=s.coarse_sweeps, sp_nnz=list(s.sp_nnz[:L]), dia_slots=list(s.dia_slots[:L]),
                     p_nnz=list(s.p_nnz[:L]), omega=list(s.omega[:L]), smoother_sweeps=s.smoother_sweeps,
-                    smoothed_prol=s.smoothed_prol)
+                    smoothed_prol=s.smoothed_prol, vcycle_double=s.vcycle_double)
 
     def export_level(self, l):
         inf = self.info()

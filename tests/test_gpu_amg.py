@@ -313,23 +313,24 @@ def test_fcg_tight_tolerance_residual_replacement(psc, prec):
 
 
 SMOOTHING = {
-    # name: (matching sweeps, smoothed prolongator, smoother sweeps)
-    "smatch": (3, True, 4),
-    "tentative_nu2": (2, False, 2),
-    "smoothed_nu1": (2, True, 1),
-    "smoothed_nu3": (3, True, 3),
+    # name: (matching sweeps, smoothed prolongator, smoother sweeps, variable V-cycle)
+    "smatch": (3, True, 4, False),
+    "vmatch": (3, False, 2, True),
+    "tentative_nu2": (2, False, 2, False),
+    "smoothed_nu1": (2, True, 1, False),
+    "smoothed_nu3": (3, True, 3, False),
 }
 
 
 @pytest.mark.parametrize("cfg", list(SMOOTHING))
 @pytest.mark.parametrize("case", ["poisson24", "diffusion20_az100", "random_long_rows"])
 def test_smoothing_configurations_match_oracle(psc, case, cfg):
-    sweeps, smoothed, nu = SMOOTHING[cfg]
+    sweeps, smoothed, nu, double = SMOOTHING[cfg]
     rp, c, v = P.poisson7(24) if case == "poisson24" else CASES[case]()
     cm = 40 if case == "random_long_rows" else 200
     h = psc.Hierarchy(rp, c, v, coarse_max=cm, sweeps=sweeps, build_fp32=True, smoothed_prol=smoothed,
-                      smoother_sweeps=nu)
-    o = oracle.Hierarchy(rp, c, v, coarse_max=cm, sweeps=sweeps, prol=int(smoothed), nu=nu)
+                      smoother_sweeps=nu, vcycle_double=double)
+    o = oracle.Hierarchy(rp, c, v, coarse_max=cm, sweeps=sweeps, prol=int(smoothed), nu=nu, nu_double=double)
     assert h.info()["rows"] == o.sizes()
     n = len(rp) - 1
     x = np.random.default_rng(5).standard_normal(n)
@@ -358,6 +359,6 @@ def test_smoothing_configurations_match_oracle(psc, case, cfg):
     xg.zero_()
     g = h.fcg(dev(b), xg, prec=psc.FP32)
     assert abs(g["iters"] - r32["iters"]) <= 1 and g["relres"] <= 1e-6
-    if nu > 1 or smoothed:
+    if nu > 1 or smoothed or double:
         with pytest.raises(psc.PscError):
             h.tune(psc.TUNE_SPLIT, 0)

@@ -110,6 +110,14 @@ def test_smoothed_hierarchy_bit_identical_to_oracle(case):
             assert inf["omega"][l] == om and inf["p_nnz"][l] == len(ov)
 
 
+def test_vmatch_options_reported():
+    rp, c, v = P.poisson7(16)
+    h = psc.Hierarchy(rp, c, v, host_only=True, sweeps=3, smoother_sweeps=2, vcycle_double=True)
+    inf = h.info()
+    assert inf["vcycle_double"] == 1 and inf["smoother_sweeps"] == 2
+    assert inf["rows"] == oracle.Hierarchy(rp, c, v, sweeps=3, nu=2, nu_double=True).sizes()
+
+
 def test_tentative_prolongator_export_is_the_aggregate_map():
     rp, c, v = P.poisson7(10)
     h = psc.Hierarchy(rp, c, v, host_only=True)

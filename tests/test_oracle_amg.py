@@ -485,6 +485,30 @@ def test_vcycle_nu_sweeps_two_level_formula(prol, nu):
     assert np.abs(B32 - Bref[:, ::37]).max() <= 1e-5 * np.abs(Bref).max()
 
 
+def test_variable_vcycle_three_levels_recursive_formula():
+    # variable V-cycle (nu_l = nu 2^l): eq. (amg) applied recursively,
+    # B_l = (I - E_l) A_l^-1 with E_l = S_l^nu_l (I - P_l B_{l+1} P_l^T A_l) S_l^nu_l
+    # and B_L = A_L^-1 on the coarsest level.
+    rp, c, v = P.poisson7(8)
+    h = oracle.Hierarchy(rp, c, v, sweeps=3, coarse_max=10, nu=2, nu_double=True)
+    assert h.sizes() == [512, 64, 8]
+    B = None
+    for l in range(h.nlevels - 1, -1, -1):
+        L = h.level(l)
+        A = dense(L["rowptr"], L["col"], L["val"])
+        if l == h.nlevels - 1:
+            B = np.linalg.inv(A)
+            continue
+        prp, pci, pv, _ = h.prolongator(l)
+        Pm = sp.csr_matrix((pv, pci, prp), shape=(L["n"], L["nc"])).toarray()
+        I = np.eye(L["n"])
+        Snu = np.linalg.matrix_power(I - L["minv"][:, None] * A, 2 * 2 ** l)
+        E = Snu @ (I - Pm @ B @ Pm.T @ A) @ Snu
+        B = (I - E) @ np.linalg.inv(A)
+    V = np.stack([h.vcycle(np.eye(512)[:, j]) for j in range(0, 512, 7)], axis=1)
+    np.testing.assert_allclose(V, B[:, ::7], rtol=0, atol=1e-12)
+
+
 def test_smatch_beats_tentative_in_iterations():
     # SMATCH-style (aggregates <= 8, smoothed prolongator, 4 sweeps) against
     # the tentative V(1,1) of the main path on the same problem
