@@ -131,8 +131,10 @@ def main():
     ap.add_argument("--no-dia", action="store_true", help="read level operators from hacked ELL only")
     ap.add_argument("--coarse-sweeps", type=int, default=30,
                     help="l1-Jacobi sweeps of a coarsest level left by a coarsening stall")
-    ap.add_argument("--smatch", action="store_true",
-                    help="also time the SMATCH setting (aggregates <= 8, smoothed prolongator, 4 sweeps)")
+    ap.add_argument("--configs", default="",
+                    help="comma-separated extra preconditioner settings to time with the same problem: "
+                         "smatch (aggregates <= 8, smoothed prolongator, 4 sweeps), "
+                         "vmatch (aggregates <= 8, tentative prolongator, 2 sweeps doubled per level)")
     ap.add_argument("--no-split", action="store_true",
                     help="smoothing sweeps gather through A, M^-1 and P instead of A M^-1 and A P")
     ap.add_argument("--unfused", action="store_true", help="one kernel per CG operation instead of the fused PCG iteration")
@@ -264,12 +266,14 @@ def main():
                           "vcycle_gbs": info["vcycle_bytes_fp32"] / (vc_ms32 / vc_cnt32 * 1e-3) / 1e9
                           if vc_cnt32 else None,
                           "err_vs_fp64_x": float(np.linalg.norm(x32 - xg) / np.linalg.norm(xg))}
-    if args.smatch:
+    extra = {"smatch": dict(sweeps=3, smoothed_prol=True, smoother_sweeps=4),
+             "vmatch": dict(sweeps=3, smoother_sweeps=2, vcycle_double=True)}
+    for cfg in [c for c in args.configs.split(",") if c]:
         t0 = time.time()
-        hs = psc.Hierarchy(rp, col, val, build_fp32=not args.no_mixed, use_graph=not args.no_graph, sweeps=3,
-                           smoothed_prol=True, smoother_sweeps=4)
+        hs = psc.Hierarchy(rp, col, val, build_fp32=not args.no_mixed, use_graph=not args.no_graph, **extra[cfg])
         infs = hs.info()
-        log(f"smatch hierarchy {infs['rows']} built in {time.time() - t0:.1f}s, opcx {infs['operator_complexity']:.4f}")
+        log(f"{cfg} hierarchy {infs['rows']} built in {time.time() - t0:.1f}s, "
+            f"opcx {infs['operator_complexity']:.4f}")
         for form in ["fp64"] + ([] if args.no_mixed else ["mixed"]):
             def run_s():
                 x.zero_()
@@ -284,8 +288,8 @@ def main():
                 rs = run_s()
             torch.cuda.synchronize()
             mss = (time.perf_counter() - t) * 1e3 / args.steps
-            log(f"smatch {form}: {mss:.2f} ms/solve, {rs['iters']} its, relres {rs['relres']:.2e}")
-            forms["smatch_" + form] = {"ms": mss, "iters": rs["iters"], "relres": rs["relres"],
+            log(f"{cfg} {form}: {mss:.2f} ms/solve, {rs['iters']} its, relres {rs['relres']:.2e}")
+            forms[cfg + "_" + form] = {"ms": mss, "iters": rs["iters"], "relres": rs["relres"],
                                        "speedup_vs_fp64": ms64 / mss,
                                        "operator_complexity": infs["operator_complexity"],
                                        "setup_s": infs["setup_seconds"]}

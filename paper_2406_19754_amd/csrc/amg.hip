@@ -276,7 +276,7 @@ __global__ __launch_bounds__(WG) void k_finish(Red R, int nblk) {
 // width <= 8 (every stencil slice) issue all value and index loads before
 // the first gather, so a wavefront keeps up to 16 streaming loads and 8
 // gathers in flight; wider slices take the general loop.
-template <typename T, typename G, int U = 8>
+template <typename T, typename G, int U = 8, int GB = 4>
 __device__ __forceinline__ T ell_row(const Ell<T>& A, long long s, int lane, G g) {
     const long long o = A.off[s];
     const int w = (int)((A.off[s + 1] - o) >> 6);
@@ -325,19 +325,25 @@ __device__ __forceinline__ T ell_row(const Ell<T>& A, long long s, int lane, G g
             if (k < w) acc += v[k] * gv[k];
         return acc;
     }
+    // wider rows: batches of GB slots, every load of a batch issued before
+    // its gathers (GB = 8 for operators with wide rows -- restriction and the
+    // coarse operators of smoothed hierarchies -- at the price of registers)
     int k = 0;
-    for (; k + 4 <= w; k += 4) {
-        T v0 = ntload(vp + 0 * SLICE), v1 = ntload(vp + 1 * SLICE);
-        T v2 = ntload(vp + 2 * SLICE), v3 = ntload(vp + 3 * SLICE);
-        int c0 = ntload(cp + 0 * SLICE), c1 = ntload(cp + 1 * SLICE);
-        int c2 = ntload(cp + 2 * SLICE), c3 = ntload(cp + 3 * SLICE);
-        T g0 = g(c0), g1 = g(c1), g2 = g(c2), g3 = g(c3);
-        acc += v0 * g0;
-        acc += v1 * g1;
-        acc += v2 * g2;
-        acc += v3 * g3;
-        vp += 4 * SLICE;
-        cp += 4 * SLICE;
+    for (; k + GB <= w; k += GB) {
+        T v[GB];
+        int c[GB];
+#pragma unroll
+        for (int j = 0; j < GB; j++) {
+            v[j] = ntload(vp + j * SLICE);
+            c[j] = ntload(cp + j * SLICE);
+        }
+        T gv[GB];
+#pragma unroll
+        for (int j = 0; j < GB; j++) gv[j] = g(c[j]);
+#pragma unroll
+        for (int j = 0; j < GB; j++) acc += v[j] * gv[j];
+        vp += GB * SLICE;
+        cp += GB * SLICE;
     }
     for (; k < w; k++) {
         T v0 = ntload(vp);
@@ -488,7 +494,7 @@ __device__ __forceinline__ void vchunk_range(long long total, long long& lo, lon
 // loads); a column that falls outside [0, ncols) belongs to a zero value and
 // is clamped to a valid index. Slices of at most 8 diagonals issue every
 // value load before the first gather.
-template <typename T, typename G>
+template <typename T, typename G, int GB = 4>
 __device__ __forceinline__ T dia_row(const Dia<T>& A, long long s, int lane, G g) {
     const int k0 = A.start[s];
     const int nd = A.start[s + 1] - k0;
@@ -516,25 +522,44 @@ __device__ __forceinline__ T dia_row(const Dia<T>& A, long long s, int lane, G g
             if (k < nd) acc += v[k] * gv[k];
         return acc;
     }
-    for (int k = 0; k < nd; k++) {
+    int k = 0;
+    for (; k + GB <= nd; k += GB) {
+        T v[GB];
+        int c[GB];
+#pragma unroll
+        for (int j = 0; j < GB; j++) {
+            v[j] = ntload(vp + (k + j) * SLICE);
+            c[j] = min(max(row + op[k + j], 0), cmax);
+        }
+        T gv[GB];
+#pragma unroll
+        for (int j = 0; j < GB; j++) gv[j] = g(c[j]);
+#pragma unroll
+        for (int j = 0; j < GB; j++) acc += v[j] * gv[j];
+    }
+    for (; k < nd; k++) {
         const T v0 = ntload(vp + k * SLICE);
         acc += v0 * g(min(max(row + op[k], 0), cmax));
     }
     return acc;
 }
 
-// Row sum of either storage format.
-template <typename T, typename G>
-__device__ __forceinline__ T mat_row(const Ell<T>& A, long long s, int lane, G g) { return ell_row(A, s, lane, g); }
-template <typename T, typename G>
-__device__ __forceinline__ T mat_row(const Dia<T>& A, long long s, int lane, G g) { return dia_row(A, s, lane, g); }
+// Row sum of either storage format; GB is the batch of the wide-row path.
+template <int GB = 4, typename T, typename G>
+__device__ __forceinline__ T mat_row(const Ell<T>& A, long long s, int lane, G g) {
+    return ell_row<T, G, 8, GB>(A, s, lane, g);
+}
+template <int GB = 4, typename T, typename G>
+__device__ __forceinline__ T mat_row(const Dia<T>& A, long long s, int lane, G g) {
+    return dia_row<T, G, GB>(A, s, lane, g);
+}
 
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
 
 // y = A x
-template <typename M, bool BUF = false>
+template <typename M, bool BUF = false, int GB = 4>
 __global__ __launch_bounds__(WG) void k_spmv(M A, const typename M::value_type* __restrict__ x,
                                              typename M::value_type* __restrict__ y, Gate g) {
     using T = typename M::value_type;
@@ -546,7 +571,7 @@ __global__ __launch_bounds__(WG) void k_spmv(M A, const typename M::value_type* 
     for (long long s = lo + w; s < hi; s += WG / 64) {
         T acc;
         if constexpr (BUF) acc = ell_row_buf(A, s, lane, [&](int c) { return bx[c]; });
-        else acc = mat_row(A, s, lane, [&](int c) { return x[c]; });
+        else acc = mat_row<GB>(A, s, lane, [&](int c) { return x[c]; });
         long long row = s * SLICE + lane;
         if (row < A.nrows) y[row] = acc;
     }
@@ -962,7 +987,7 @@ __global__ __launch_bounds__(WG) void k_post(Ell<T> A, const T* __restrict__ min
 // These give the sweeps of k_pre / k_post up to rounding.
 
 // r_i = b_i - sum_j am_ij b_j
-template <typename M, typename TB>
+template <typename M, typename TB, int GB = 4>
 __global__ __launch_bounds__(WG) void k_pre_s(M AM, const TB* __restrict__ b, typename M::value_type* __restrict__ r,
                                               Gate g) {
     using T = typename M::value_type;
@@ -971,7 +996,7 @@ __global__ __launch_bounds__(WG) void k_pre_s(M AM, const TB* __restrict__ b, ty
     chunk_range(AM.nslices, lo, hi);
     const int lane = threadIdx.x & 63, w = wave_id();
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        const T acc = mat_row(AM, s, lane, [&](int c) { return (T)b[c]; });
+        const T acc = mat_row<GB>(AM, s, lane, [&](int c) { return (T)b[c]; });
         const long long row = s * SLICE + lane;
         if (row < AM.nrows) r[row] = (T)b[row] - acc;
     }
@@ -1005,7 +1030,7 @@ __global__ __launch_bounds__(WG) void k_update_pre_s(M AM, const double* __restr
 
 // Post-smoothing with prolongation through SP (see above); with
 // R.fin != FIN_NONE also the partial sum of x_i * d_i.
-template <typename T, typename TB, typename TX>
+template <typename T, typename TB, typename TX, int GB = 4>
 __global__ __launch_bounds__(WG) void k_post_s(Ell<T> SP, const T* __restrict__ minv, const TB* __restrict__ b,
                                                const T* __restrict__ r, const T* __restrict__ xc,
                                                TX* __restrict__ x, const double* __restrict__ d, Red R) {
@@ -1015,7 +1040,7 @@ __global__ __launch_bounds__(WG) void k_post_s(Ell<T> SP, const T* __restrict__ 
     const int lane = threadIdx.x & 63, w = wave_id();
     double s0 = 0.0;
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        const T acc = ell_row(SP, s, lane, [&](int c) { return xc[c]; });
+        const T acc = mat_row<GB>(SP, s, lane, [&](int c) { return xc[c]; });
         const long long row = s * SLICE + lane;
         if (row < SP.nrows) {
             const T xi = minv[row] * ((T)b[row] + r[row]) + acc;
@@ -1030,7 +1055,7 @@ __global__ __launch_bounds__(WG) void k_post_s(Ell<T> SP, const T* __restrict__ 
 // s_k = b + r_1 + ... + r_{k-1} (so x_k = M^-1 s_k): with s_k = s_{k-1} + r_{k-1}
 // formed for the own row and every gathered neighbour,
 //   r_k = b - AM s_k,   and s_k, r_k are stored.
-template <typename M, typename TB, typename TS>
+template <typename M, typename TB, typename TS, int GB = 4>
 __global__ __launch_bounds__(WG) void k_presweep(M AM, const TB* __restrict__ b, const TS* __restrict__ sprev,
                                                  const typename M::value_type* __restrict__ rprev,
                                                  typename M::value_type* __restrict__ sout,
@@ -1041,7 +1066,7 @@ __global__ __launch_bounds__(WG) void k_presweep(M AM, const TB* __restrict__ b,
     chunk_range(AM.nslices, lo, hi);
     const int lane = threadIdx.x & 63, w = wave_id();
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        const T acc = mat_row(AM, s, lane, [&](int c) { return (T)sprev[c] + rprev[c]; });
+        const T acc = mat_row<GB>(AM, s, lane, [&](int c) { return (T)sprev[c] + rprev[c]; });
         const long long row = s * SLICE + lane;
         if (row < AM.nrows) {
             sout[row] = (T)sprev[row] + rprev[row];
@@ -1052,7 +1077,7 @@ __global__ __launch_bounds__(WG) void k_presweep(M AM, const TB* __restrict__ b,
 
 // One l1-Jacobi sweep x_out = x_in + M^-1 (b - A x_in) (post-smoothing sweeps
 // after the first); with R.fin != FIN_NONE also the partial sum of x_out * d.
-template <typename M, typename TB, typename TX>
+template <typename M, typename TB, typename TX, int GB = 4>
 __global__ __launch_bounds__(WG) void k_sweep(M A, const typename M::value_type* __restrict__ minv,
                                               const TB* __restrict__ b,
                                               const typename M::value_type* __restrict__ xin, TX* __restrict__ xout,
@@ -1064,7 +1089,7 @@ __global__ __launch_bounds__(WG) void k_sweep(M A, const typename M::value_type*
     const int lane = threadIdx.x & 63, w = wave_id();
     double s0 = 0.0;
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        const T acc = mat_row(A, s, lane, [&](int c) { return xin[c]; });
+        const T acc = mat_row<GB>(A, s, lane, [&](int c) { return xin[c]; });
         const long long row = s * SLICE + lane;
         if (row < A.nrows) {
             const T xi = xin[row] + minv[row] * ((T)b[row] - acc);
@@ -1095,7 +1120,7 @@ __global__ __launch_bounds__(WG) void k_coarse(int n, const double* __restrict__
 // stalls above the dense-factor limit). One sweep from x_in:
 //   x_out_i = x_in_i + minv_i (b_i - sum_j a_ij x_in_j);
 // x_in == nullptr stands for the zero guess (x_out = minv b).
-template <typename M, typename TB, typename TX>
+template <typename M, typename TB, typename TX, int GB = 4>
 __global__ __launch_bounds__(WG) void k_jacobi(M A, const double* __restrict__ minv,
                                                const TB* __restrict__ b, const double* __restrict__ xin,
                                                TX* __restrict__ xout, Gate g) {
@@ -1109,7 +1134,7 @@ __global__ __launch_bounds__(WG) void k_jacobi(M A, const double* __restrict__ m
             if (row < A.nrows) xout[row] = (TX)(minv[row] * (double)b[row]);
             continue;
         }
-        double acc = mat_row(A, s, lane, [&](int c) { return xin[c]; });
+        double acc = mat_row<GB>(A, s, lane, [&](int c) { return xin[c]; });
         if (row < A.nrows) xout[row] = (TX)(xin[row] + minv[row] * ((double)b[row] - acc));
     }
 }
@@ -1132,6 +1157,7 @@ struct DevEll {
     int* col = nullptr;
     float* val32 = nullptr;
     long long nrows = 0, nslices = 0, slots = 0, ncols = 0, nnz = 0;
+    int wmax = 0;                          // widest slice (entries per row)
     Ell<T> view() const { return Ell<T>{off, val, col, nrows, nslices, ncols}; }
     Ell<float> view32() const { return Ell<float>{off, val32, col, nrows, nslices, ncols}; }
 };
@@ -1144,6 +1170,7 @@ struct DevDia {
     double* val = nullptr;
     float* val32 = nullptr;
     long long nrows = 0, nslices = 0, ncols = 0, slots = 0;
+    int ndmax = 0;                         // most diagonals in one slice
     bool on() const { return start != nullptr; }
     Dia<double> view(const double* v) const { return Dia<double>{start, offs, v, nrows, nslices, ncols}; }
     Dia<float> view32(const float* v) const { return Dia<float>{start, offs, v, nrows, nslices, ncols}; }
@@ -1297,6 +1324,7 @@ static int upload_ell(psc_hier* h, DevEll<double>& E, int64_t nrows, int64_t nco
     E.nslices = (long long)off.size() - 1;
     E.slots = off.back();
     E.nnz = rp[nrows];
+    for (size_t q = 0; q + 1 < off.size(); q++) E.wmax = std::max(E.wmax, (int)((off[q + 1] - off[q]) / SLICE));
     int st;
     if ((st = upload(h, &E.off, off.data(), off.size()))) return st;
     if ((st = upload(h, &E.val, val.data(), val.size()))) return st;
@@ -1360,6 +1388,11 @@ static void with_AM_t(const psc_hier* h, const DevLevel& V, F f) {
     if constexpr (std::is_same<T, float>::value) with_AM32(h, V, f);
     else with_AM(h, V, f);
 }
+// Rows wider than 8 entries take the 8-slot batch kernels (more registers,
+// more loads in flight); stencil operators keep the 4-slot ones.
+static bool wide_A(const psc_hier* h, const DevLevel& V) {
+    return (h->dia && V.Ad.on()) ? V.Ad.ndmax > 8 : V.A.wmax > 8;
+}
 static inline int grid_vec(const psc_hier* h, long long n) { return grid_of(h, 1024, n); }
 
 // ---------------------------------------------------------------------------
@@ -1408,11 +1441,15 @@ static void timing_collect(psc_hier* h) {
 // Pre-smoothing from zero and its residual on level V, in the V-cycle's
 // precision T (r = b - A M^-1 b).
 template <typename T, typename TB>
-static void launch_pre(psc_hier* h, const DevLevel& V, const TB* b, T* r, Gate g) {
-    const int gr = grid_ell(h, V.A.nslices);
+static void launch_pre(psc_hier* h, const DevLevel& V, const TB* b, T* r, Gate g, int grid = 0) {
+    const int gr = grid ? grid : grid_ell(h, V.A.nslices);
     constexpr bool f32 = std::is_same<T, float>::value;
     if (h->split) {
-        auto go = [&](auto AM) { k_pre_s<decltype(AM), TB><<<gr, WG, 0, h->stream>>>(AM, b, r, g); };
+        const bool wide = wide_A(h, V);
+        auto go = [&](auto AM) {
+            if (wide) k_pre_s<decltype(AM), TB, 8><<<gr, WG, 0, h->stream>>>(AM, b, r, g);
+            else k_pre_s<decltype(AM), TB, 4><<<gr, WG, 0, h->stream>>>(AM, b, r, g);
+        };
         if constexpr (f32) with_AM32(h, V, go);
         else with_AM(h, V, go);
         return;
@@ -1428,7 +1465,7 @@ static void launch_pre(psc_hier* h, const DevLevel& V, const TB* b, T* r, Gate g
 // y = A x for an operator in either storage; the variant knobs apply to ELL.
 template <typename M>
 static void launch_spmv(psc_hier* h, const M& A, const typename M::value_type* x, typename M::value_type* y,
-                        Gate g) {
+                        Gate g, bool wide = false) {
     using T = typename M::value_type;
     const int gr = grid_ell(h, A.nslices);
     if constexpr (std::is_same<M, Ell<T>>::value) {
@@ -1442,7 +1479,8 @@ static void launch_spmv(psc_hier* h, const M& A, const typename M::value_type* x
             return;
         }
     }
-    k_spmv<M, false><<<gr, WG, 0, h->stream>>>(A, x, y, g);
+    if (wide) k_spmv<M, false, 8><<<gr, WG, 0, h->stream>>>(A, x, y, g);
+    else k_spmv<M, false, 4><<<gr, WG, 0, h->stream>>>(A, x, y, g);
 }
 
 template <typename T, typename TB, typename TX>
@@ -1492,15 +1530,18 @@ static void coarse_solve(psc_hier* h, const TB* b, TX* x, Gate g) {
         return;
     }
     const int gr = grid_ell(h, C.A.nslices);
+    const bool wide = wide_A(h, C);
     with_A(h, C, [&](auto A) {
         using M = decltype(A);
         const double* xin = nullptr;
         for (int k = 1; k < K; k++) {
             double* xo = ((K - k) % 2 == 0) ? C.x : C.r;
-            k_jacobi<M, TB, double><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, xo, g);
+            if (wide) k_jacobi<M, TB, double, 8><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, xo, g);
+            else k_jacobi<M, TB, double, 4><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, xo, g);
             xin = xo;
         }
-        k_jacobi<M, TB, TX><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, x, g);
+        if (wide) k_jacobi<M, TB, TX, 8><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, x, g);
+        else k_jacobi<M, TB, TX, 4><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, x, g);
     });
 }
 
@@ -1523,10 +1564,16 @@ static void pre_sweeps(psc_hier* h, DevLevel& V, const TB* b, bool skip1, Gate g
     for (int k = 2; k <= V.nu; k++) {
         T* so = ((V.nu - k) % 2 == 0) ? LV<T>::s(V) : LV<T>::sb(V);
         T* ro = pre_rbuf<T>(h, V, k);
+        const bool wide = wide_A(h, V);
         with_AM_t<T>(h, V, [&](auto AM) {
             using M = decltype(AM);
-            if (k == 2) k_presweep<M, TB, TB><<<gr, WG, 0, h->stream>>>(AM, b, b, rp, so, ro, g);
-            else k_presweep<M, TB, T><<<gr, WG, 0, h->stream>>>(AM, b, sp, rp, so, ro, g);
+            if (k == 2) {
+                if (wide) k_presweep<M, TB, TB, 8><<<gr, WG, 0, h->stream>>>(AM, b, b, rp, so, ro, g);
+                else k_presweep<M, TB, TB, 4><<<gr, WG, 0, h->stream>>>(AM, b, b, rp, so, ro, g);
+            } else {
+                if (wide) k_presweep<M, TB, T, 8><<<gr, WG, 0, h->stream>>>(AM, b, sp, rp, so, ro, g);
+                else k_presweep<M, TB, T, 4><<<gr, WG, 0, h->stream>>>(AM, b, sp, rp, so, ro, g);
+            }
         });
         sp = so;
         rp = ro;
@@ -1546,22 +1593,28 @@ static void post_sweeps(psc_hier* h, DevLevel& V, const TB* b, TX* out, const T*
     const Ell<T> SP = LV<T>::SP(V);
     const T* r = LV<T>::r(V);
     const T* minv = LV<T>::minv(V);
+    const bool wsp = V.SP.wmax > 8, wa = wide_A(h, V);
     if (V.nu == 1) {
-        k_post_s<T, TB, TX><<<gr, WG, 0, h->stream>>>(SP, minv, b, r, xc, out, d, Rf);
+        if (wsp) k_post_s<T, TB, TX, 8><<<gr, WG, 0, h->stream>>>(SP, minv, b, r, xc, out, d, Rf);
+        else k_post_s<T, TB, TX, 4><<<gr, WG, 0, h->stream>>>(SP, minv, b, r, xc, out, d, Rf);
         return;
     }
     T* ta = LV<T>::xt(V);
     T* tb = LV<T>::xt2(V);
-    k_post_s<T, T, T><<<gr, WG, 0, h->stream>>>(SP, minv, (const T*)LV<T>::s(V), r, xc, ta, nullptr, Rn);
+    const T* sn = LV<T>::s(V);
+    if (wsp) k_post_s<T, T, T, 8><<<gr, WG, 0, h->stream>>>(SP, minv, sn, r, xc, ta, nullptr, Rn);
+    else k_post_s<T, T, T, 4><<<gr, WG, 0, h->stream>>>(SP, minv, sn, r, xc, ta, nullptr, Rn);
     const T* xin = ta;
     for (int k = 2; k <= V.nu; k++) {
         with_A_t<T>(h, V, [&](auto A) {
             using M = decltype(A);
             if (k == V.nu) {
-                k_sweep<M, TB, TX><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, out, d, Rf);
+                if (wa) k_sweep<M, TB, TX, 8><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, out, d, Rf);
+                else k_sweep<M, TB, TX, 4><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, out, d, Rf);
             } else {
                 T* xo = xin == ta ? tb : ta;
-                k_sweep<M, TB, T><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, xo, nullptr, Rn);
+                if (wa) k_sweep<M, TB, T, 8><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, xo, nullptr, Rn);
+                else k_sweep<M, TB, T, 4><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, xo, nullptr, Rn);
                 xin = xo;
             }
         });
@@ -1577,14 +1630,14 @@ static void vcycle_t(psc_hier* h, const double* r0, double* z0, const double* d,
     R0.fin = FIN_NONE;
     for (int l = 0; l < L - 1; l++) {
         DevLevel& V = h->lev[l];
-        {
+        if (!(l == 0 && skip_pre0 && V.nu == 1)) {
             TimeScope t(h, l == 0 ? 2 : 7);
             if (l == 0) pre_sweeps<T, double>(h, V, r0, skip_pre0, g);
             else pre_sweeps<T, T>(h, V, (const T*)LV<T>::b(V), false, g);
         }
         {
             TimeScope t(h, l == 0 ? 3 : 7);
-            launch_spmv(h, LV<T>::R(V), (const T*)LV<T>::r(V), LV<T>::b(h->lev[l + 1]), g);
+            launch_spmv(h, LV<T>::R(V), (const T*)LV<T>::r(V), LV<T>::b(h->lev[l + 1]), g, V.R.wmax > 8);
         }
     }
     DevLevel& C = h->lev[L - 1];
@@ -1722,6 +1775,11 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
     }
     if (form == FORM_FFUSED64 || form == FORM_FFUSED32) {
         const bool f32 = form == FORM_FFUSED32;
+        // The true residual and the redo of the pre-smoothing run only in the
+        // iterations whose recursive residual passed the test, but are launched
+        // in every one: on a grid of at most 1024 workgroups their early exit
+        // costs a few microseconds instead of tens.
+        const int gq = std::min(ge, 1024);
         for (int parity = 0; parity < 2; parity++) {
             double* pold = parity ? h->p2 : h->p;
             double* pnew = parity ? h->p : h->p2;
@@ -1764,13 +1822,13 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             }
             finish(h, red_of(h, FIN_UPDATE_FCG), ge);
             with_A(h, L0, [&](auto A) {
-                k_resid_lag<decltype(A)><<<ge, WG, 0, st>>>(A, h->bs, h->xs, pnew, rnew, red_of(h, FIN_TRUE));
+                k_resid_lag<decltype(A)><<<gq, WG, 0, st>>>(A, h->bs, h->xs, pnew, rnew, red_of(h, FIN_TRUE));
             });
-            finish(h, red_of(h, FIN_TRUE), ge);
+            finish(h, red_of(h, FIN_TRUE), gq);
             // after a residual replacement, redo the level-0 pre-smoothing from the true residual
             const Gate gr{h->ctl, GATE_REDO};
-            if (f32) launch_pre(h, L0, (const double*)rnew, pre_rbuf<float>(h, L0, 1), gr);
-            else launch_pre(h, L0, (const double*)rnew, pre_rbuf<double>(h, L0, 1), gr);
+            if (f32) launch_pre(h, L0, (const double*)rnew, pre_rbuf<float>(h, L0, 1), gr, gq);
+            else launch_pre(h, L0, (const double*)rnew, pre_rbuf<double>(h, L0, 1), gr, gq);
             vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, gd, true);
         }
         return PSC_OK;
@@ -2158,6 +2216,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
             G.ncols = H.n;
             G.nslices = (long long)dstart.size() - 1;
             G.slots = (long long)dval.size();
+            for (size_t q = 0; q + 1 < dstart.size(); q++) G.ndmax = std::max(G.ndmax, dstart[q + 1] - dstart[q]);
             if ((st = upload(h.get(), &G.start, dstart.data(), dstart.size()))) return st;
             if ((st = upload(h.get(), &G.offs, doffs.data(), doffs.size()))) return st;
             if ((st = upload(h.get(), &G.val, dval.data(), dval.size()))) return st;
@@ -2425,9 +2484,13 @@ int psc_spmv(psc_hier* h, int32_t l, int32_t prec, const void* x, void* y) {
     {
         TimeScope t(h, l == 0 ? 0 : 7);
         if (prec == PSC_FP64)
-            with_A(h, D, [&](auto A) { launch_spmv(h, A, (const double*)x, (double*)y, Gate{nullptr, GATE_NONE}); });
+            with_A(h, D, [&](auto A) {
+                launch_spmv(h, A, (const double*)x, (double*)y, Gate{nullptr, GATE_NONE}, wide_A(h, D));
+            });
         else
-            with_A32(h, D, [&](auto A) { launch_spmv(h, A, (const float*)x, (float*)y, Gate{nullptr, GATE_NONE}); });
+            with_A32(h, D, [&](auto A) {
+                launch_spmv(h, A, (const float*)x, (float*)y, Gate{nullptr, GATE_NONE}, wide_A(h, D));
+            });
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->stream));
