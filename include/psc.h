@@ -78,6 +78,15 @@ typedef struct psc_net  psc_net;    /* opaque: owns the learned preconditioner  
  *                    smoother_sweeps * 2^l sweeps (capped at 4096); with
  *                    sweeps = 3, the tentative prolongator and
  *                    smoother_sweeps = 2 this is the paper's VMATCH setting.
+ *   aggregation = 0  PSC_AGGR_MATCHING: coupled aggregation by compatible
+ *                    weighted matching (sweeps matching sweeps per level);
+ *                    PSC_AGGR_VBM: decoupled Vanek-Mandel-Brezina
+ *                    aggregation of strongly coupled neighbourhoods,
+ *                    |a_ij| >= vbm_theta sqrt(a_ii a_jj), with
+ *                    P^_{i,agg(i)} = w_i (Section "Aggregation strategies");
+ *                    with smoothed_prol = 1 and smoother_sweeps = 4 this is
+ *                    the paper's VBM setting. sweeps is ignored for VBM.
+ *   vbm_theta = 0.01 strength threshold of PSC_AGGR_VBM, in [0, 1).
  *   build_fp32 = 0   also build the FP32 copies of the level operators that
  *                    the mixed-precision V-cycle needs.
  *   use_graph = 1    capture the per-iteration kernel sequence as a HIP
@@ -87,6 +96,9 @@ typedef struct psc_net  psc_net;    /* opaque: owns the learned preconditioner  
  *                    psc_hier_export_level on machines without a GPU);
  *                    solve and apply calls then return PSC_ERR_STATE.
  */
+#define PSC_AGGR_MATCHING 0
+#define PSC_AGGR_VBM 1
+
 typedef struct {
     int32_t sweeps;
     int32_t coarse_max;
@@ -98,7 +110,9 @@ typedef struct {
     int32_t smoothed_prol;
     int32_t smoother_sweeps;
     int32_t vcycle_double;
-    int32_t reserved[6];
+    int32_t aggregation;
+    int32_t reserved[5];
+    double  vbm_theta;
 } psc_amg_opts;
 
 void psc_amg_opts_default(psc_amg_opts* opts);
@@ -192,6 +206,7 @@ typedef struct {
     int32_t smoother_sweeps;
     int32_t smoothed_prol;
     int32_t vcycle_double;
+    int32_t aggregation;
 } psc_hier_stats;
 
 int psc_hier_info(const psc_hier* h, psc_hier_stats* s);

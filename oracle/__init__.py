@@ -55,7 +55,7 @@ def lib():
     L.orc_match.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p]
     L.orc_match.restype = C.c_int
     L.orc_build.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
-                            C.c_int, C.POINTER(vp)]
+                            C.c_int, C.c_int, C.c_double, C.POINTER(vp)]
     L.orc_prol_nnz.argtypes = [vp, C.c_int]
     L.orc_prol_nnz.restype = C.c_longlong
     L.orc_prol_get.argtypes = [vp, C.c_int, _i32p, _i32p, _f64p, C.POINTER(C.c_double)]
@@ -132,11 +132,12 @@ class Hierarchy:
     """Oracle AMG hierarchy (C.2 of the readings): levels of (A_l, agg, p, w, minv)."""
 
     def __init__(self, rowptr, col, val, sweeps=2, coarse_max=200, max_levels=30, coarse_sweeps=30,
-                 prol=0, nu=1, nu_double=False):
+                 prol=0, nu=1, nu_double=False, aggr=0, theta=0.01):
         self._rowptr, self._col, self._val = _i32(rowptr), _i32(col), _f64(val)
         h = C.c_void_p()
         st = lib().orc_build(len(rowptr) - 1, self._rowptr, self._col, self._val,
-                             sweeps, coarse_max, max_levels, coarse_sweeps, prol, nu, int(nu_double), C.byref(h))
+                             sweeps, coarse_max, max_levels, coarse_sweeps, prol, nu, int(nu_double), aggr, theta,
+                             C.byref(h))
         self.status = st
         if st != OK:
             raise RuntimeError(f"oracle build failed with status {st}")

@@ -246,6 +246,8 @@ typedef struct {
     int prol;            /* 0: tentative prolongator, 1: smoothed */
     int nu;              /* l1-Jacobi sweeps before and after the coarse correction (level 0) */
     int nu_double;       /* 1: variable V-cycle, nu_l = nu * 2^l (the paper's VMATCH) */
+    int aggr;            /* 0: coupled matching aggregation, 1: decoupled VBM */
+    double theta;        /* VBM strength threshold */
     orc_level lev[ORC_MAXLEV];
 } orc_hier;
 
@@ -319,6 +321,64 @@ static void chol_solve(int n, const double *L, const double *b, double *x) {
  * normalisation, which the edge weight does not see). The final aggregates
  * are numbered by ascending smallest level-l member.
  */
+/*
+ * Decoupled Vanek-Mandel-Brezina aggregation (Section "Aggregation
+ * strategies"): j is strongly coupled to i when j != i and
+ * |a_ij| >= theta sqrt(a_ii a_jj). In ascending node order:
+ *   1. a node whose strong neighbours are all unaggregated forms an
+ *      aggregate with them;
+ *   2. each node still unaggregated joins the aggregate (from step 1) of its
+ *      strong neighbour with the largest |a_ij| (ties: smaller j);
+ *   3. each node still unaggregated forms an aggregate with its
+ *      unaggregated strong neighbours.
+ * Aggregates are numbered in order of creation.
+ */
+static int vbm_aggregate(const csr *A, double theta, int *agg, int *nc_out) {
+    int n = A->n, nc = 0;
+    double *d = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int *a1 = malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    if (!d || !a1) { free(d); free(a1); return ORC_ERR_OOM; }
+    for (int i = 0; i < n; i++) {
+        d[i] = 0.0;
+        for (int k = A->rp[i]; k < A->rp[i + 1]; k++) if (A->ci[k] == i) d[i] = A->v[k];
+        agg[i] = -1;
+    }
+#define STRONG(i, k) (A->ci[k] != (i) && fabs(A->v[k]) >= theta * sqrt(d[i] * d[A->ci[k]]))
+    for (int i = 0; i < n; i++) {
+        if (agg[i] != -1) continue;
+        int free_all = 1;
+        for (int k = A->rp[i]; k < A->rp[i + 1]; k++)
+            if (STRONG(i, k) && agg[A->ci[k]] != -1) { free_all = 0; break; }
+        if (!free_all) continue;
+        agg[i] = nc;
+        for (int k = A->rp[i]; k < A->rp[i + 1]; k++) if (STRONG(i, k)) agg[A->ci[k]] = nc;
+        nc++;
+    }
+    memcpy(a1, agg, sizeof(int) * (size_t)n);
+    for (int i = 0; i < n; i++) {
+        if (a1[i] != -1) continue;
+        int best = -1;
+        double bv = -1.0;
+        for (int k = A->rp[i]; k < A->rp[i + 1]; k++) {
+            if (!STRONG(i, k) || a1[A->ci[k]] == -1) continue;
+            double v = fabs(A->v[k]);
+            if (v > bv) { bv = v; best = a1[A->ci[k]]; }     /* columns ascending: ties keep the smaller j */
+        }
+        if (best != -1) agg[i] = best;
+    }
+    for (int i = 0; i < n; i++) {
+        if (agg[i] != -1) continue;
+        agg[i] = nc;
+        for (int k = A->rp[i]; k < A->rp[i + 1]; k++)
+            if (STRONG(i, k) && agg[A->ci[k]] == -1) agg[A->ci[k]] = nc;
+        nc++;
+    }
+#undef STRONG
+    free(d); free(a1);
+    *nc_out = nc;
+    return ORC_OK;
+}
+
 /*
  * Smoothed prolongator (Section "Aggregation strategies"): P = (I - omega
  * D^-1 A) P^ with D = diag(A), omega = 1 / ||D^-1 A||_inf, and P^ the
@@ -546,16 +606,18 @@ static int csr_copy(int n, const int *rp, const int *ci, const double *v, csr *a
  */
 int orc_build(int n, const int *rp, const int *ci, const double *v,
               int sweeps, int coarse_max, int max_levels, int coarse_sweeps, int prol, int nu,
-              int nu_double, orc_hier **out) {
+              int nu_double, int aggr, double theta, orc_hier **out) {
     *out = NULL;
     if (n <= 0 || sweeps < 1 || max_levels < 1 || max_levels > ORC_MAXLEV || prol < 0 || prol > 1 ||
-        nu < 1 || nu_double < 0 || nu_double > 1)
+        nu < 1 || nu_double < 0 || nu_double > 1 || aggr < 0 || aggr > 1 || !(theta >= 0.0 && theta < 1.0))
         return ORC_ERR_ARG;
     orc_hier *h = calloc(1, sizeof(orc_hier));
     h->sweeps = sweeps;
     h->prol = prol;
     h->nu = nu;
     h->nu_double = nu_double;
+    h->aggr = aggr;
+    h->theta = theta;
     int st = csr_copy(n, rp, ci, v, &h->lev[0].A);
     if (st) { orc_free(h); return st; }
     h->lev[0].w = malloc(sizeof(double) * (size_t)n);
@@ -591,16 +653,24 @@ int orc_build(int n, const int *rp, const int *ci, const double *v,
         }
         L->agg = malloc(sizeof(int) * (size_t)nl);
         int nc = 0;
-        st = coarsen(&L->A, L->w, sweeps, L->agg, &nc);
+        if (aggr == 0) st = coarsen(&L->A, L->w, sweeps, L->agg, &nc);
+        else st = vbm_aggregate(&L->A, theta, L->agg, &nc);
         if (st) { orc_free(h); return st; }
         L->nc = nc;
         orc_level *C = &h->lev[l + 1];
         C->w = malloc(sizeof(double) * (size_t)nc);
-        for (int I = 0; I < nc; I++) C->w[I] = 0.0;
-        for (int i = 0; i < nl; i++) C->w[L->agg[i]] += L->w[i] * L->w[i];
-        for (int I = 0; I < nc; I++) C->w[I] = sqrt(C->w[I]);
         L->p = malloc(sizeof(double) * (size_t)nl);
-        for (int i = 0; i < nl; i++) L->p[i] = L->w[i] / C->w[L->agg[i]];
+        if (aggr == 0) {
+            /* matching: P^ columns are the normalised restrictions of w */
+            for (int I = 0; I < nc; I++) C->w[I] = 0.0;
+            for (int i = 0; i < nl; i++) C->w[L->agg[i]] += L->w[i] * L->w[i];
+            for (int I = 0; I < nc; I++) C->w[I] = sqrt(C->w[I]);
+            for (int i = 0; i < nl; i++) L->p[i] = L->w[i] / C->w[L->agg[i]];
+        } else {
+            /* VBM, eq. (prolongator_vbm): P^_{i,agg_i} = w_i; the coarse sample is 1 */
+            for (int I = 0; I < nc; I++) C->w[I] = 1.0;
+            for (int i = 0; i < nl; i++) L->p[i] = L->w[i];
+        }
         if (prol == 0) {
             /* tentative: P = P^, one entry per row; canonical Galerkin sum */
             L->P.n = nl;

@@ -2132,6 +2132,8 @@ void psc_amg_opts_default(psc_amg_opts* o) {
     o->coarse_sweeps = 30;
     o->smoothed_prol = 0;
     o->smoother_sweeps = 1;
+    o->aggregation = PSC_AGGR_MATCHING;
+    o->vbm_theta = 0.01;
 }
 
 void psc_hier_free(psc_hier* h) {
@@ -2174,6 +2176,8 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     so.max_levels = h->opts.max_levels;
     so.coarse_sweeps = h->opts.coarse_sweeps;
     so.prol = h->opts.smoothed_prol;
+    so.aggr = h->opts.aggregation;
+    so.theta = h->opts.vbm_theta;
     if (h->opts.smoother_sweeps < 1 || h->opts.smoother_sweeps > 16 || h->opts.smoothed_prol < 0 ||
         h->opts.smoothed_prol > 1)
         return fail(PSC_ERR_ARG, "smoother_sweeps must be 1..16 and smoothed_prol 0 or 1");
@@ -2432,6 +2436,7 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
     s->coarse_sweeps = h->host.coarse_sweeps;
     s->smoother_sweeps = h->nu;
     s->vcycle_double = h->opts.vcycle_double;
+    s->aggregation = h->opts.aggregation;
     s->smoothed_prol = h->opts.smoothed_prol;
     return PSC_OK;
 }

@@ -318,6 +318,60 @@ int64_t pairs_to_aggs(const std::vector<int32_t>& mate, std::vector<int32_t>& ag
     return nc;
 }
 
+// Decoupled Vanek-Mandel-Brezina aggregation (Section "Aggregation
+// strategies"): j is strongly coupled to i when j != i and
+// |a_ij| >= theta sqrt(a_ii a_jj). Sequential, ascending node order:
+//   1. a node whose strong neighbours are all unaggregated forms an
+//      aggregate with them;
+//   2. each node still unaggregated joins the aggregate (from step 1) of its
+//      strong neighbour with the largest |a_ij| (ties: smaller j);
+//   3. each node still unaggregated forms an aggregate with its unaggregated
+//      strong neighbours.
+// Aggregates are numbered in order of creation.
+void vbm_aggregate(const Csr& A, double theta, std::vector<int32_t>& agg, int64_t& nc_out) {
+    const int64_t n = A.n;
+    std::vector<double> d(n, 0.0);
+    for (int64_t i = 0; i < n; i++)
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++)
+            if (A.ci[k] == i) d[i] = A.v[k];
+    auto strong = [&](int64_t i, int32_t k) {
+        return A.ci[k] != i && std::fabs(A.v[k]) >= theta * std::sqrt(d[i] * d[A.ci[k]]);
+    };
+    agg.assign(n, -1);
+    int32_t nc = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (agg[i] != -1) continue;
+        bool free_all = true;
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++)
+            if (strong(i, k) && agg[A.ci[k]] != -1) { free_all = false; break; }
+        if (!free_all) continue;
+        agg[i] = nc;
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++)
+            if (strong(i, k)) agg[A.ci[k]] = nc;
+        nc++;
+    }
+    const std::vector<int32_t> a1 = agg;
+    for (int64_t i = 0; i < n; i++) {
+        if (a1[i] != -1) continue;
+        int32_t best = -1;
+        double bv = -1.0;
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++) {
+            if (!strong(i, k) || a1[A.ci[k]] == -1) continue;
+            const double v = std::fabs(A.v[k]);
+            if (v > bv) { bv = v; best = a1[A.ci[k]]; }
+        }
+        if (best != -1) agg[i] = best;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        if (agg[i] != -1) continue;
+        agg[i] = nc;
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++)
+            if (strong(i, k) && agg[A.ci[k]] == -1) agg[A.ci[k]] = nc;
+        nc++;
+    }
+    nc_out = nc;
+}
+
 int coarsen(const Csr& A, const std::vector<double>& w, int sweeps, std::vector<int32_t>& agg,
             int64_t& nc_out) {
     const int64_t n = A.n;
@@ -498,7 +552,8 @@ int validate_csr(int64_t n, const int32_t* rp, const int32_t* ci, const double* 
 int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
                     const SetupOpts& o, HostHier& H, std::string& err) {
     if (o.sweeps < 1 || o.sweeps > 8 || o.coarse_max < 1 || o.max_levels < 1 ||
-        o.max_levels > PSC_MAX_LEVELS || o.coarse_sweeps < 0 || o.coarse_sweeps > 1000) {
+        o.max_levels > PSC_MAX_LEVELS || o.coarse_sweeps < 0 || o.coarse_sweeps > 1000 || o.aggr < 0 ||
+        o.aggr > 1 || !(o.theta >= 0.0 && o.theta < 1.0)) {
         err = "invalid hierarchy options";
         return PSC_ERR_ARG;
     }
@@ -550,7 +605,8 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
         }
         int64_t nc = 0;
         std::vector<int32_t> agg;
-        coarsen(A, H.lev[l].w, o.sweeps, agg, nc);
+        if (o.aggr == 0) coarsen(A, H.lev[l].w, o.sweeps, agg, nc);
+        else vbm_aggregate(A, o.theta, agg, nc);
         H.lev.emplace_back();
         HostLevel& F = H.lev[l];
         HostLevel& Cl = H.lev[l + 1];
@@ -561,15 +617,22 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
         std::vector<int32_t> mem;
         members_of(F.agg, nc, start, mem);
         Cl.w.resize(nc);
-#pragma omp parallel for schedule(static)
-        for (int64_t I = 0; I < nc; I++) {
-            double s = 0.0;
-            for (int64_t m = start[I]; m < start[I + 1]; m++) s += F.w[mem[m]] * F.w[mem[m]];
-            Cl.w[I] = std::sqrt(s);
-        }
         F.p.resize(F.n);
+        if (o.aggr == 0) {
+            // matching: P^ columns are the normalised restrictions of w
 #pragma omp parallel for schedule(static)
-        for (int64_t i = 0; i < F.n; i++) F.p[i] = F.w[i] / Cl.w[F.agg[i]];
+            for (int64_t I = 0; I < nc; I++) {
+                double s = 0.0;
+                for (int64_t m = start[I]; m < start[I + 1]; m++) s += F.w[mem[m]] * F.w[mem[m]];
+                Cl.w[I] = std::sqrt(s);
+            }
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < F.n; i++) F.p[i] = F.w[i] / Cl.w[F.agg[i]];
+        } else {
+            // VBM, eq. (prolongator_vbm): P^_{i,agg_i} = w_i; the coarse sample is 1
+            std::fill(Cl.w.begin(), Cl.w.end(), 1.0);
+            for (int64_t i = 0; i < F.n; i++) F.p[i] = F.w[i];
+        }
         Csr Ac;
         if (o.prol == 0) {
             // tentative: one entry per row, canonical Galerkin sum

@@ -36,6 +36,8 @@ struct SetupOpts {
     int max_levels = 30;
     int coarse_sweeps = 30;
     int prol = 0;               // 0 tentative prolongator, 1 smoothed
+    int aggr = 0;               // 0 coupled matching, 1 decoupled VBM
+    double theta = 0.01;        // VBM strength threshold
 };
 
 // Status codes follow psc.h.

@@ -20,6 +20,7 @@ OK, NOCONV = 0, 1
 ERR_ARG, ERR_NOT_SPD, ERR_NAN, ERR_HIP, ERR_OOM, ERR_COARSEN, ERR_STATE = -1, -2, -3, -4, -5, -6, -7
 FP64, FP32 = 0, 1
 TUNE_GRID_MAX, TUNE_FUSED_PCG, TUNE_UNROLL4, TUNE_BUFLOAD, TUNE_SPMV2, TUNE_SPLIT, TUNE_DIA = 1, 2, 3, 4, 5, 6, 7
+AGGR_MATCHING, AGGR_VBM = 0, 1
 MAX_LEVELS = 32
 TIMING_KERNELS = 8
 TIMING_NAMES = ["spmv_dot", "cg_update", "pre_smooth_l0", "restrict_l0", "post_smooth_l0",
@@ -40,7 +41,8 @@ class AmgOpts(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
                 ("build_fp32", C.c_int32), ("use_graph", C.c_int32), ("host_only", C.c_int32),
                 ("coarse_sweeps", C.c_int32), ("smoothed_prol", C.c_int32), ("smoother_sweeps", C.c_int32),
-                ("vcycle_double", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("vcycle_double", C.c_int32), ("aggregation", C.c_int32), ("reserved", C.c_int32 * 5),
+                ("vbm_theta", C.c_double)]
 
 
 class HierStats(C.Structure):
@@ -53,7 +55,7 @@ class HierStats(C.Structure):
                 ("coarse_sweeps", C.c_int32), ("sp_nnz", C.c_int64 * MAX_LEVELS),
                 ("dia_slots", C.c_int64 * MAX_LEVELS), ("p_nnz", C.c_int64 * MAX_LEVELS),
                 ("omega", C.c_double * MAX_LEVELS), ("smoother_sweeps", C.c_int32), ("smoothed_prol", C.c_int32),
-                ("vcycle_double", C.c_int32)]
+                ("vcycle_double", C.c_int32), ("aggregation", C.c_int32)]
 
 
 def _load():
@@ -143,7 +145,7 @@ class Hierarchy:
 
     def __init__(self, rowptr, col, val, sweeps=2, coarse_max=200, max_levels=30,
                  build_fp32=False, use_graph=True, host_only=False, stream=None, coarse_sweeps=30,
-                 smoothed_prol=False, smoother_sweeps=1, vcycle_double=False):
+                 smoothed_prol=False, smoother_sweeps=1, vcycle_double=False, aggregation=0, vbm_theta=0.01):
         import torch
         o = AmgOpts()
         _lib.psc_amg_opts_default(C.byref(o))
@@ -151,6 +153,7 @@ class Hierarchy:
         o.coarse_sweeps = coarse_sweeps
         o.smoothed_prol, o.smoother_sweeps = int(smoothed_prol), smoother_sweeps
         o.vcycle_double = int(vcycle_double)
+        o.aggregation, o.vbm_theta = aggregation, vbm_theta
         o.build_fp32, o.use_graph, o.host_only = int(build_fp32), int(use_graph), int(host_only)
         rp, prp = _hptr(rowptr, np.int32)
         ci, pci = _hptr(col, np.int32)
@@ -178,7 +181,7 @@ class Hierarchy:
                     setup_seconds=s.setup_seconds, device_bytes=s.device_bytes,
                     coarse_sweeps=s.coarse_sweeps, sp_nnz=list(s.sp_nnz[:L]), dia_slots=list(s.dia_slots[:L]),
                     p_nnz=list(s.p_nnz[:L]), omega=list(s.omega[:L]), smoother_sweeps=s.smoother_sweeps,
-                    smoothed_prol=s.smoothed_prol, vcycle_double=s.vcycle_double)
+                    smoothed_prol=s.smoothed_prol, vcycle_double=s.vcycle_double, aggregation=s.aggregation)
 
     def export_level(self, l):
         inf = self.info()

@@ -313,24 +313,28 @@ def test_fcg_tight_tolerance_residual_replacement(psc, prec):
 
 
 SMOOTHING = {
-    # name: (matching sweeps, smoothed prolongator, smoother sweeps, variable V-cycle)
-    "smatch": (3, True, 4, False),
-    "vmatch": (3, False, 2, True),
-    "tentative_nu2": (2, False, 2, False),
-    "smoothed_nu1": (2, True, 1, False),
-    "smoothed_nu3": (3, True, 3, False),
+    # name: options of both the library and the oracle
+    "smatch": dict(sweeps=3, prol=1, nu=4),
+    "vmatch": dict(sweeps=3, nu=2, double=True),
+    "vbm": dict(aggr=1, prol=1, nu=4),
+    "tentative_nu2": dict(nu=2),
+    "smoothed_nu1": dict(prol=1),
+    "smoothed_nu3": dict(sweeps=3, prol=1, nu=3),
 }
 
 
 @pytest.mark.parametrize("cfg", list(SMOOTHING))
 @pytest.mark.parametrize("case", ["poisson24", "diffusion20_az100", "random_long_rows"])
 def test_smoothing_configurations_match_oracle(psc, case, cfg):
-    sweeps, smoothed, nu, double = SMOOTHING[cfg]
+    o_ = dict(sweeps=2, prol=0, nu=1, double=False, aggr=0)
+    o_.update(SMOOTHING[cfg])
+    sweeps, smoothed, nu, double, aggr = o_["sweeps"], o_["prol"], o_["nu"], o_["double"], o_["aggr"]
     rp, c, v = P.poisson7(24) if case == "poisson24" else CASES[case]()
     cm = 40 if case == "random_long_rows" else 200
-    h = psc.Hierarchy(rp, c, v, coarse_max=cm, sweeps=sweeps, build_fp32=True, smoothed_prol=smoothed,
-                      smoother_sweeps=nu, vcycle_double=double)
-    o = oracle.Hierarchy(rp, c, v, coarse_max=cm, sweeps=sweeps, prol=int(smoothed), nu=nu, nu_double=double)
+    h = psc.Hierarchy(rp, c, v, coarse_max=cm, sweeps=sweeps, build_fp32=True, smoothed_prol=bool(smoothed),
+                      smoother_sweeps=nu, vcycle_double=double, aggregation=aggr, vbm_theta=0.05)
+    o = oracle.Hierarchy(rp, c, v, coarse_max=cm, sweeps=sweeps, prol=smoothed, nu=nu, nu_double=double,
+                         aggr=aggr, theta=0.05)
     assert h.info()["rows"] == o.sizes()
     n = len(rp) - 1
     x = np.random.default_rng(5).standard_normal(n)

@@ -110,6 +110,35 @@ def test_smoothed_hierarchy_bit_identical_to_oracle(case):
             assert inf["omega"][l] == om and inf["p_nnz"][l] == len(ov)
 
 
+VBM = {
+    "poisson20_vbm_smoothed": (lambda: P.poisson7(20), 1, 0.01),
+    "poisson9_vbm_tentative": (lambda: P.poisson7(9), 0, 0.01),
+    "diffusion12_az100_vbm": (lambda: P.diffusion7(12, seed=0, az=100.0), 1, 0.08),
+    "random_spd_vbm": (lambda: P.random_spd_csr(400, 3, density=0.02, maxrow=40), 1, 0.05),
+}
+
+
+@pytest.mark.parametrize("case", list(VBM))
+def test_vbm_hierarchy_bit_identical_to_oracle(case):
+    mk, prol, theta = VBM[case]
+    rp, c, v = mk()
+    h = psc.Hierarchy(rp, c, v, host_only=True, coarse_max=40, smoothed_prol=bool(prol), smoother_sweeps=4,
+                      aggregation=psc.AGGR_VBM, vbm_theta=theta)
+    o = oracle.Hierarchy(rp, c, v, coarse_max=40, prol=prol, nu=4, aggr=1, theta=theta)
+    inf = h.info()
+    assert inf["aggregation"] == psc.AGGR_VBM
+    assert inf["rows"] == o.sizes() and inf["nnz"] == o.nnzs()
+    for l in range(inf["levels"]):
+        a, b = h.export_level(l), o.level(l)
+        for key in ["rowptr", "col", "val", "minv"]:
+            assert np.array_equal(a[key], b[key]), (l, key)
+        if l < inf["levels"] - 1:
+            assert np.array_equal(a["agg"], b["agg"]) and np.array_equal(a["p"], b["p"]), l
+            prp, pci, pv = h.export_prolongator(l)
+            orp, oci, ov, om = o.prolongator(l)
+            assert np.array_equal(prp, orp) and np.array_equal(pci, oci) and np.array_equal(pv, ov), l
+
+
 def test_vmatch_options_reported():
     rp, c, v = P.poisson7(16)
     h = psc.Hierarchy(rp, c, v, host_only=True, sweeps=3, smoother_sweeps=2, vcycle_double=True)

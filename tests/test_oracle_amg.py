@@ -509,6 +509,62 @@ def test_variable_vcycle_three_levels_recursive_formula():
     np.testing.assert_allclose(V, B[:, ::7], rtol=0, atol=1e-12)
 
 
+def test_vbm_aggregates_1d_closed_form():
+    # 1-D Laplacian: every off-diagonal is strong (|a_ij| / sqrt(a_ii a_jj) =
+    # 1/2 >= theta). Step 1 in ascending order takes {0,1}, then the
+    # neighbourhoods {2,3,4}, {5,6,7}, ... of every third node, and {14,15}.
+    n = 16
+    rp, c, v = _laplace1d(n)
+    h = oracle.Hierarchy(rp, c, v, aggr=1, theta=0.01, coarse_max=4)
+    agg = h.level(0)["agg"]
+    assert list(agg) == [0, 0, 1, 1, 1, 2, 2, 2, 3, 3, 3, 4, 4, 4, 5, 5]
+    # P^_{i,agg_i} = w_i = 1 (no normalisation) and the smoothed P keeps P^ 1 = 1
+    assert np.all(h.level(0)["p"] == 1.0)
+
+
+def test_vbm_threshold_and_invariants():
+    # theta above every coupling ratio (1/6 for the 7-point stencil): no strong
+    # neighbours, every node is its own aggregate
+    rp, c, v = P.poisson7(6)
+    h = oracle.Hierarchy(rp, c, v, aggr=1, theta=0.5, coarse_max=100)
+    assert np.array_equal(h.level(0)["agg"], np.arange(216))
+    for case in ["poisson12", "diffusion10", "random"]:
+        if case == "poisson12":
+            rp, c, v = P.poisson7(12)
+        elif case == "diffusion10":
+            rp, c, v = P.diffusion7(10, seed=2, az=100.0)
+        else:
+            rp, c, v = P.random_spd_csr(300, 7, density=0.02, maxrow=30)
+        h = oracle.Hierarchy(rp, c, v, aggr=1, theta=0.05, coarse_max=40, prol=1)
+        for l in range(h.nlevels - 1):
+            L = h.level(l)
+            A = dense(L["rowptr"], L["col"], L["val"])
+            agg = L["agg"]
+            assert agg.min() == 0 and agg.max() == L["nc"] - 1
+            d = np.diag(A)
+            strong = (np.abs(A) >= 0.05 * np.sqrt(np.outer(d, d))) & ~np.eye(L["n"], dtype=bool)
+            # every aggregate is connected in the strength graph, or a singleton
+            for J in range(L["nc"]):
+                mem = np.flatnonzero(agg == J)
+                if len(mem) == 1:
+                    continue
+                seen, todo = {mem[0]}, [mem[0]]
+                while todo:
+                    i = todo.pop()
+                    for j in mem[strong[i, mem]]:
+                        if j not in seen:
+                            seen.add(j)
+                            todo.append(j)
+                assert len(seen) == len(mem), (case, l, J)
+            prp, pci, pv, omega = h.prolongator(l)
+            Pm = sp.csr_matrix((pv, pci, prp), shape=(L["n"], L["nc"])).toarray()
+            Ph = prolongator(L)
+            np.testing.assert_allclose(Pm, Ph - omega * (A / d[:, None]) @ Ph, rtol=0, atol=1e-14)
+            C = h.level(l + 1)
+            Ac = dense(C["rowptr"], C["col"], C["val"])
+            np.testing.assert_allclose(Ac, Pm.T @ A @ Pm, rtol=0, atol=1e-13 * np.abs(A).max())
+
+
 def test_smatch_beats_tentative_in_iterations():
     # SMATCH-style (aggregates <= 8, smoothed prolongator, 4 sweeps) against
     # the tentative V(1,1) of the main path on the same problem
@@ -656,3 +712,20 @@ def test_vmatch_operator_complexity_matches_paper():
     rp, c, v = P.poisson7(200)                 # 8e6 unknowns, one GPU's share
     h = oracle.Hierarchy(rp, c, v, sweeps=3)   # aggregates <= 8, tentative prolongator
     assert abs(h.operator_complexity() - ref) <= 0.01
+
+
+@pytest.mark.slow
+def test_vbm_operator_complexity_near_paper():
+    # The paper does not state its VBM strength threshold; for the 7-point
+    # stencil every coupling ratio is 1/6, so any theta < 1/6 gives the same
+    # aggregates. The oracle's 1.592 at 200^3 is within 0.02 of the printed
+    # 1.575; the remaining gap comes from unpublished details of the toolkit's
+    # aggregation (boundary treatment, order of the passes), so the bound is
+    # loose but still separates VBM from the tentative (1.22) or matching-based
+    # (1.14 / 2.2) hierarchies.
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "paper_operator_complexity.txt"))
+            if l.strip() and not l.startswith("#")]
+    ref = float([r for r in rows if r[0] == "VBM" and r[1] == "1"][0][2])
+    rp, c, v = P.poisson7(200)
+    h = oracle.Hierarchy(rp, c, v, aggr=1, theta=0.01, prol=1, nu=4)
+    assert abs(h.operator_complexity() - ref) <= 0.02
