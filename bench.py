@@ -134,7 +134,8 @@ def main():
     ap.add_argument("--configs", default="",
                     help="comma-separated extra preconditioner settings to time with the same problem: "
                          "smatch (aggregates <= 8, smoothed prolongator, 4 sweeps), "
-                         "vmatch (aggregates <= 8, tentative prolongator, 2 sweeps doubled per level)")
+                         "vmatch (aggregates <= 8, tentative prolongator, 2 sweeps doubled per level), "
+                         "vbm (strength-based aggregation, smoothed prolongator, 4 sweeps)")
     ap.add_argument("--no-split", action="store_true",
                     help="smoothing sweeps gather through A, M^-1 and P instead of A M^-1 and A P")
     ap.add_argument("--unfused", action="store_true", help="one kernel per CG operation instead of the fused PCG iteration")
@@ -267,7 +268,8 @@ def main():
                           if vc_cnt32 else None,
                           "err_vs_fp64_x": float(np.linalg.norm(x32 - xg) / np.linalg.norm(xg))}
     extra = {"smatch": dict(sweeps=3, smoothed_prol=True, smoother_sweeps=4),
-             "vmatch": dict(sweeps=3, smoother_sweeps=2, vcycle_double=True)}
+             "vmatch": dict(sweeps=3, smoother_sweeps=2, vcycle_double=True),
+             "vbm": dict(aggregation=psc.AGGR_VBM, vbm_theta=0.01, smoothed_prol=True, smoother_sweeps=4)}
     for cfg in [c for c in args.configs.split(",") if c]:
         t0 = time.time()
         hs = psc.Hierarchy(rp, col, val, build_fp32=not args.no_mixed, use_graph=not args.no_graph, **extra[cfg])
