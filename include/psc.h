@@ -87,6 +87,14 @@ typedef struct psc_net  psc_net;    /* opaque: owns the learned preconditioner  
  *                    with smoothed_prol = 1 and smoother_sweeps = 4 this is
  *                    the paper's VBM setting. sweeps is ignored for VBM.
  *   vbm_theta = 0.01 strength threshold of PSC_AGGR_VBM, in [0, 1).
+ *   setup_device = 1  coarsen on the GPU where the setting allows it
+ *                    (matching aggregation with the tentative prolongator):
+ *                    matching, aggregates, prolongator and Galerkin product
+ *                    are computed by device kernels in the host setup's
+ *                    arithmetic order, so the hierarchy is the same bit for
+ *                    bit; levels the kernels cannot take (a coarse row with
+ *                    more than 64 distinct columns) fall back to the host.
+ *                    Ignored (host setup) with host_only.
  *   build_fp32 = 0   also build the FP32 copies of the level operators that
  *                    the mixed-precision V-cycle needs.
  *   use_graph = 1    capture the per-iteration kernel sequence as a HIP
@@ -111,7 +119,8 @@ typedef struct {
     int32_t smoother_sweeps;
     int32_t vcycle_double;
     int32_t aggregation;
-    int32_t reserved[5];
+    int32_t setup_device;
+    int32_t reserved[4];
     double  vbm_theta;
 } psc_amg_opts;
 

@@ -11,7 +11,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpsc.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-HIP_SOURCES = ["amg.hip", "net.hip"]
+HIP_SOURCES = ["amg.hip", "net.hip", "gsetup.hip"]
 CXX_SOURCES = ["setup.cpp"]
 HEADERS = ["kernels.h", "setup.h", "net.h"]
 

@@ -2134,6 +2134,7 @@ void psc_amg_opts_default(psc_amg_opts* o) {
     o->smoother_sweeps = 1;
     o->aggregation = PSC_AGGR_MATCHING;
     o->vbm_theta = 0.01;
+    o->setup_device = 1;
 }
 
 void psc_hier_free(psc_hier* h) {
@@ -2178,6 +2179,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     so.prol = h->opts.smoothed_prol;
     so.aggr = h->opts.aggregation;
     so.theta = h->opts.vbm_theta;
+    so.device = h->opts.setup_device != 0 && !h->opts.host_only;
     if (h->opts.smoother_sweeps < 1 || h->opts.smoother_sweeps > 16 || h->opts.smoothed_prol < 0 ||
         h->opts.smoothed_prol > 1)
         return fail(PSC_ERR_ARG, "smoother_sweeps must be 1..16 and smoothed_prol 0 or 1");

@@ -1,0 +1,554 @@
+// gsetup.hip -- coarsening of one hierarchy level on the GPU.
+//
+// Computes, for the default setting (coupled aggregation by compatible
+// weighted matching with the tentative prolongator; Section "Aggregation
+// strategies", eq. (prolongator); Section "AMG4PSBLAS" for the Galerkin
+// product), exactly what the host functions coarsen(), the w/p loop and
+// galerkin() in setup.cpp compute:
+//   * matching keys q = llround((1 - 2 s_ij / (s_ii + s_jj)) 2^30) of the
+//     scaled operator S = diag(w) A diag(w), and the unique locally-dominant
+//     matching under the order (q desc, min asc, max asc), found by rounds of
+//     mutual proposals in which only vertices whose partner was taken
+//     propose again;
+//   * aggregates numbered by ascending smallest member, k sweeps on the
+//     block sums of S;
+//   * w_{l+1}[I] = sqrt(sum over members ascending of w_i^2),
+//     p_i = w_i / w_{l+1}[agg_i], and A_{l+1}[I,J] = sum over members i of I
+//     ascending, then row entries ascending, of (p_i a_ij) p_j, with the
+//     columns of a coarse row sorted.
+// Every floating-point step is an explicit round-to-nearest operation in
+// the host's order, so the hierarchy is bit-identical to the host one.
+// Member lists come from merging the sorted pairs of each sweep (an
+// aggregate has at most 2^sweeps members); the only other primitive is an
+// integer exclusive scan. Rows with more than GS_MAXC distinct coarse
+// columns are reported so the caller can build that level on the host.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/psc.h"
+#include "setup.h"
+
+namespace psc {
+
+namespace {
+
+constexpr int GS_WG = 256;
+constexpr int GS_MAXC = 64;      // distinct coarse columns one coarse row may collect
+
+#define GS_CHK(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            err = std::string(#call) + ": " + hipGetErrorString(e_);                  \
+            return PSC_ERR_HIP;                                                       \
+        }                                                                             \
+    } while (0)
+
+__device__ __forceinline__ long long gs_llround(double x) {
+    // round half away from zero: t = trunc(x) and |x - t| are exact
+    const double t = trunc(x);
+    long long r = (long long)t;
+    if (fabs(__dsub_rn(x, t)) >= 0.5) r += x > 0.0 ? 1 : -1;
+    return r;
+}
+
+// strict edge order of the matching: does {i,a} (key qa) come before {i,b} (key qb)?
+__device__ __forceinline__ bool gs_edge_first(long long qa, int i, int a, long long qb, int b) {
+    if (qa != qb) return qa > qb;
+    const int amin = min(i, a), amax = max(i, a), bmin = min(i, b), bmax = max(i, b);
+    if (amin != bmin) return amin < bmin;
+    return amax < bmax;
+}
+
+__device__ __forceinline__ int gs_find(const int* rp, const int* ci, int i, int j) {
+    int lo = rp[i], hi = rp[i + 1];
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ci[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < rp[i + 1] && ci[lo] == j) ? lo : -1;
+}
+
+__global__ void k_gs_scale(int n, const int* rp, const int* ci, const double* v, const double* w, double* s) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        for (int k = rp[i]; k < rp[i + 1]; k++) s[k] = __dmul_rn(__dmul_rn(w[i], v[k]), w[ci[k]]);
+}
+
+__global__ void k_gs_diag(int n, const int* rp, const int* ci, const double* v, double* dg) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int k = gs_find(rp, ci, i, i);
+        dg[i] = k >= 0 ? v[k] : 0.0;
+    }
+}
+
+// key of every stored entry, computed from the entry of row min(i,j)
+__global__ void k_gs_keys(int n, const int* rp, const int* ci, const double* v, const double* dg, long long* key) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        for (int k = rp[i]; k < rp[i + 1]; k++) {
+            const int j = ci[k];
+            if (j == i) { key[k] = -1; continue; }
+            const int lo = min(i, j), hi = max(i, j);
+            const int kk = j > i ? k : gs_find(rp, ci, lo, hi);
+            if (kk < 0) { key[k] = -1; continue; }
+            const double c = __dsub_rn(1.0, __ddiv_rn(__dmul_rn(2.0, v[kk]), __dadd_rn(dg[lo], dg[hi])));
+            const long long q = gs_llround(__dmul_rn(c, 1073741824.0));
+            key[k] = q > 0 ? q : -1;
+        }
+    }
+}
+
+__device__ __forceinline__ int gs_best_free(int i, const int* rp, const int* ci, const long long* key,
+                                            const int* mate) {
+    int best = -1;
+    long long bq = 0;
+    for (int k = rp[i]; k < rp[i + 1]; k++) {
+        if (key[k] < 0) continue;
+        const int j = ci[k];
+        if (mate[j] >= 0) continue;
+        if (best < 0 || gs_edge_first(key[k], i, j, bq, best)) {
+            best = j;
+            bq = key[k];
+        }
+    }
+    return best;
+}
+
+__global__ void k_gs_unmatch(int n, int* mate) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) mate[i] = -1;
+}
+
+__global__ void k_gs_cand_all(int n, const int* rp, const int* ci, const long long* key, const int* mate, int* cand) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        cand[i] = gs_best_free(i, rp, ci, key, mate);
+}
+
+// a free vertex whose proposed partner was taken proposes again (mate is
+// not written in this kernel, so every vertex sees the same state)
+__global__ void k_gs_propose(int n, const int* rp, const int* ci, const long long* key, const int* mate, int* cand) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if (mate[i] >= 0) continue;
+        const int c = cand[i];
+        if (c >= 0 && mate[c] >= 0) cand[i] = gs_best_free(i, rp, ci, key, mate);
+    }
+}
+
+// mutual proposals become matched pairs; the smaller end writes both mates
+// (no other thread can write either entry: each vertex proposes to one)
+__global__ void k_gs_match(int n, const int* cand, int* mate, int* count) {
+    int local = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if (mate[i] >= 0) continue;
+        const int u = cand[i];
+        if (u > i && cand[u] == i) {
+            mate[i] = u;
+            mate[u] = i;
+            local++;
+        }
+    }
+    if (local) atomicAdd(count, local);
+}
+
+// ---- integer exclusive scan (three passes, fixed order: exact) ------------
+__global__ void k_gs_scan_block(int n, const int* in, int* out, int* bsum) {
+    __shared__ int sh[GS_WG];
+    const int i = blockIdx.x * GS_WG + threadIdx.x;
+    const int x = i < n ? in[i] : 0;
+    sh[threadIdx.x] = x;
+    __syncthreads();
+    for (int o = 1; o < GS_WG; o <<= 1) {
+        const int t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (i < n) out[i] = sh[threadIdx.x] - x;
+    if (threadIdx.x == GS_WG - 1) bsum[blockIdx.x] = sh[GS_WG - 1];
+}
+
+__global__ void k_gs_scan_sums(int nb, int* bsum, int* total) {
+    // one workgroup: sequential chunks, each scanned in shared memory
+    __shared__ int sh[GS_WG];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += GS_WG) {
+        const int i = base + threadIdx.x;
+        const int x = i < nb ? bsum[i] : 0;
+        sh[threadIdx.x] = x;
+        __syncthreads();
+        for (int o = 1; o < GS_WG; o <<= 1) {
+            const int t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nb) bsum[i] = carry + sh[threadIdx.x] - x;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += sh[GS_WG - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void k_gs_scan_add(int n, int* out, const int* bsum) {
+    const int i = blockIdx.x * GS_WG + threadIdx.x;
+    if (i < n) out[i] += bsum[blockIdx.x];
+}
+
+// ---- aggregates of one matching sweep --------------------------------------
+__global__ void k_gs_rep(int n, const int* mate, int* rep) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        rep[i] = (mate[i] < 0 || mate[i] > i) ? 1 : 0;
+}
+
+// a2[v]: aggregate of vertex v (numbered by smallest member); first[I]: that member
+__global__ void k_gs_pairs(int n, const int* mate, const int* scan, int* a2, int* first) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int m = mate[i];
+        if (m < 0 || m > i) {
+            a2[i] = scan[i];
+            first[scan[i]] = i;
+        } else {
+            a2[i] = scan[m];
+        }
+    }
+}
+
+// fine members of the new aggregates: merge the sorted lists of the (one or
+// two) vertices joined by the sweep; lists are padded with -1
+__global__ void k_gs_merge(int nc, int stride, const int* first, const int* mate, const int* mem_in, int* mem_out) {
+    for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < nc; I += gridDim.x * blockDim.x) {
+        const int a = first[I], b = mate[a];
+        const int* la = mem_in + (long long)a * stride;
+        int* o = mem_out + (long long)I * 2 * stride;
+        int x = 0, y = 0, k = 0;
+        if (b < 0) {
+            for (; x < stride; x++) o[k++] = la[x];
+        } else {
+            const int* lb = mem_in + (long long)b * stride;
+            while (x < stride || y < stride) {
+                const int va = x < stride ? la[x] : -1, vb = y < stride ? lb[y] : -1;
+                if (va < 0 && vb < 0) break;
+                if (vb < 0 || (va >= 0 && va < vb)) { o[k++] = va; x++; }
+                else { o[k++] = vb; y++; }
+            }
+        }
+        for (; k < 2 * stride; k++) o[k] = -1;
+    }
+}
+
+__global__ void k_gs_compose(int n, int* agg, const int* a2) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) agg[i] = a2[agg[i]];
+}
+
+// w_{l+1} and p from the member lists
+__global__ void k_gs_wp(int nc, int stride, const int* mem, const double* w, double* wc) {
+    for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < nc; I += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int m = 0; m < stride; m++) {
+            const int i = mem[(long long)I * stride + m];
+            if (i < 0) break;
+            s = __dadd_rn(s, __dmul_rn(w[i], w[i]));
+        }
+        wc[I] = __dsqrt_rn(s);
+    }
+}
+
+__global__ void k_gs_p(int n, const double* w, const double* wc, const int* agg, double* p) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        p[i] = __ddiv_rn(w[i], wc[agg[i]]);
+}
+
+// Galerkin product in the canonical order. Members of coarse row I come from
+// mem (stride entries, -1 padded). s == nullptr: t = a_ij, else
+// t = (s_i a_ij) s_j. pass 0 writes the row lengths, pass 1 the sorted row.
+__global__ void k_gs_galerkin(int nc, int stride, const int* mem, const int* rp, const int* ci, const double* v,
+                              const int* agg, const double* s, int pass, int* len, const int* crp, int* cci,
+                              double* cv, int* overflow) {
+    for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < nc; I += gridDim.x * blockDim.x) {
+        int cols[GS_MAXC];
+        double vals[GS_MAXC];
+        int nq = 0;
+        bool over = false;
+        for (int m = 0; m < stride && !over; m++) {
+            const int i = mem[(long long)I * stride + m];
+            if (i < 0) break;
+            const double si = s ? s[i] : 1.0;
+            for (int k = rp[i]; k < rp[i + 1]; k++) {
+                const int j = ci[k];
+                const int J = agg[j];
+                const double t = s ? __dmul_rn(__dmul_rn(si, v[k]), s[j]) : v[k];
+                int q = 0;
+                while (q < nq && cols[q] != J) q++;
+                if (q == nq) {
+                    if (nq == GS_MAXC) { over = true; break; }
+                    cols[nq] = J;
+                    vals[nq] = t;
+                    nq++;
+                } else {
+                    vals[q] = __dadd_rn(vals[q], t);
+                }
+            }
+        }
+        if (over) {
+            atomicOr(overflow, 1);
+            if (pass == 0) len[I] = 0;
+            continue;
+        }
+        if (pass == 0) {
+            len[I] = nq;
+            continue;
+        }
+        // insertion sort by column (columns are distinct)
+        for (int x = 1; x < nq; x++) {
+            const int c = cols[x];
+            const double cvv = vals[x];
+            int y = x - 1;
+            while (y >= 0 && cols[y] > c) {
+                cols[y + 1] = cols[y];
+                vals[y + 1] = vals[y];
+                y--;
+            }
+            cols[y + 1] = c;
+            vals[y + 1] = cvv;
+        }
+        const int o = crp[I];
+        for (int x = 0; x < nq; x++) {
+            cci[o + x] = cols[x];
+            cv[o + x] = vals[x];
+        }
+    }
+}
+
+__global__ void k_gs_pairs_members(int nc, const int* first, const int* mate, int* mem2) {
+    for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < nc; I += gridDim.x * blockDim.x) {
+        const int a = first[I], b = mate[a];
+        mem2[2 * I] = a;
+        mem2[2 * I + 1] = b > a ? b : -1;
+    }
+}
+
+__global__ void k_gs_iota(int n, int* mem) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) mem[i] = i;
+}
+
+// device buffer that frees itself
+template <typename T>
+struct DBuf {
+    T* p = nullptr;
+    ~DBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t count) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        return hipMalloc((void**)&p, (count > 0 ? count : 1) * sizeof(T));
+    }
+};
+
+inline int gs_grid(long long n) {
+    long long g = (n + GS_WG - 1) / GS_WG;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+// exclusive scan of in[0..n) into out, total into *total_host
+int gs_scan(hipStream_t st, int n, const int* in, int* out, int& total_host, std::string& err) {
+    const int nb = (n + GS_WG - 1) / GS_WG;
+    DBuf<int> bsum, tot;
+    GS_CHK(bsum.alloc(nb > 0 ? nb : 1));
+    GS_CHK(tot.alloc(1));
+    if (n > 0) k_gs_scan_block<<<nb, GS_WG, 0, st>>>(n, in, out, bsum.p);
+    k_gs_scan_sums<<<1, GS_WG, 0, st>>>(nb, bsum.p, tot.p);
+    if (n > 0) k_gs_scan_add<<<nb, GS_WG, 0, st>>>(n, out, bsum.p);
+    GS_CHK(hipGetLastError());
+    GS_CHK(hipMemcpyAsync(&total_host, tot.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    GS_CHK(hipStreamSynchronize(st));
+    return PSC_OK;
+}
+
+// Galerkin product on the device; returns PSC_ERR_STATE when a coarse row
+// collects more than GS_MAXC columns
+int gs_galerkin(hipStream_t st, int nc, int stride, const int* mem, int n, const int* rp, const int* ci,
+                const double* v, const int* agg, const double* s, DBuf<int>& crp, DBuf<int>& cci,
+                DBuf<double>& cv, int& cnnz, std::string& err) {
+    DBuf<int> len, over;
+    GS_CHK(len.alloc(nc));
+    GS_CHK(over.alloc(1));
+    GS_CHK(hipMemsetAsync(over.p, 0, sizeof(int), st));
+    k_gs_galerkin<<<gs_grid(nc), GS_WG, 0, st>>>(nc, stride, mem, rp, ci, v, agg, s, 0, len.p, nullptr, nullptr,
+                                                 nullptr, over.p);
+    GS_CHK(hipGetLastError());
+    int ov = 0;
+    GS_CHK(hipMemcpyAsync(&ov, over.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    GS_CHK(hipStreamSynchronize(st));
+    if (ov) return PSC_ERR_STATE;
+    GS_CHK(crp.alloc(nc + 1));
+    int total = 0;
+    int r = gs_scan(st, nc, len.p, crp.p, total, err);
+    if (r) return r;
+    GS_CHK(hipMemcpyAsync(crp.p + nc, &total, sizeof(int), hipMemcpyHostToDevice, st));
+    GS_CHK(cci.alloc(total));
+    GS_CHK(cv.alloc(total));
+    k_gs_galerkin<<<gs_grid(nc), GS_WG, 0, st>>>(nc, stride, mem, rp, ci, v, agg, s, 1, nullptr, crp.p, cci.p,
+                                                 cv.p, over.p);
+    GS_CHK(hipGetLastError());
+    GS_CHK(hipStreamSynchronize(st));
+    cnnz = total;
+    return PSC_OK;
+}
+
+}  // namespace
+
+int gpu_coarsen_level(int64_t n64, const int32_t* hrp, const int32_t* hci, const double* hv, const double* hw,
+                      int sweeps, std::vector<int32_t>& agg_out, int64_t& nc_out, std::vector<double>& p_out,
+                      std::vector<double>& wc_out, std::vector<int32_t>& crp_out, std::vector<int32_t>& cci_out,
+                      std::vector<double>& cv_out, std::string& err) {
+    const int64_t nnz64 = hrp[n64];
+    if (n64 >= ((int64_t)1 << 30) || nnz64 >= ((int64_t)1 << 31) || (sweeps < 1) || sweeps > 6) {
+        err = "level too large for device coarsening";
+        return PSC_ERR_STATE;
+    }
+    const int n = (int)n64, nnz = (int)nnz64;
+    hipStream_t st;
+    GS_CHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+    } guard{st};
+
+    DBuf<int> rp, ci, agg;
+    DBuf<double> v, w, S;
+    GS_CHK(rp.alloc(n + 1));
+    GS_CHK(ci.alloc(nnz));
+    GS_CHK(v.alloc(nnz));
+    GS_CHK(w.alloc(n));
+    GS_CHK(S.alloc(nnz));
+    GS_CHK(agg.alloc(n));
+    GS_CHK(hipMemcpyAsync(rp.p, hrp, (n + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+    GS_CHK(hipMemcpyAsync(ci.p, hci, (size_t)nnz * sizeof(int), hipMemcpyHostToDevice, st));
+    GS_CHK(hipMemcpyAsync(v.p, hv, (size_t)nnz * sizeof(double), hipMemcpyHostToDevice, st));
+    GS_CHK(hipMemcpyAsync(w.p, hw, (size_t)n * sizeof(double), hipMemcpyHostToDevice, st));
+    k_gs_scale<<<gs_grid(n), GS_WG, 0, st>>>(n, rp.p, ci.p, v.p, w.p, S.p);
+    k_gs_iota<<<gs_grid(n), GS_WG, 0, st>>>(n, agg.p);
+
+    // current matching graph (level rows at sweep 0, then block sums)
+    const int* grp = rp.p;
+    const int* gci = ci.p;
+    const double* gv = S.p;
+    int gn = n;
+    DBuf<int> g2rp, g2ci, g3rp, g3ci;
+    DBuf<double> g2v, g3v;
+    // member lists of the current graph's vertices (stride 1: the rows themselves)
+    DBuf<int> mem, mem2;
+    GS_CHK(mem.alloc(n));
+    k_gs_iota<<<gs_grid(n), GS_WG, 0, st>>>(n, mem.p);
+    int stride = 1;
+    int nc = n;
+    DBuf<int> count;
+    GS_CHK(count.alloc(1));
+    int* hcount = nullptr;
+    GS_CHK(hipHostMalloc((void**)&hcount, sizeof(int)));
+    struct HostGuard {
+        int* p;
+        ~HostGuard() { (void)hipHostFree(p); }
+    } hguard{hcount};
+
+    for (int sw = 0; sw < sweeps; sw++) {
+        DBuf<double> dg;
+        DBuf<long long> key;
+        DBuf<int> mate, cand, rep, scan, a2, first;
+        int enz = 0;
+        GS_CHK(hipMemcpyAsync(&enz, grp + gn, sizeof(int), hipMemcpyDeviceToHost, st));
+        GS_CHK(hipStreamSynchronize(st));
+        GS_CHK(dg.alloc(gn));
+        GS_CHK(key.alloc(enz));
+        GS_CHK(mate.alloc(gn));
+        GS_CHK(cand.alloc(gn));
+        k_gs_diag<<<gs_grid(gn), GS_WG, 0, st>>>(gn, grp, gci, gv, dg.p);
+        k_gs_keys<<<gs_grid(gn), GS_WG, 0, st>>>(gn, grp, gci, gv, dg.p, key.p);
+        k_gs_unmatch<<<gs_grid(gn), GS_WG, 0, st>>>(gn, mate.p);
+        k_gs_cand_all<<<gs_grid(gn), GS_WG, 0, st>>>(gn, grp, gci, key.p, mate.p, cand.p);
+        GS_CHK(hipGetLastError());
+        // rounds: match mutual proposals, re-propose where the partner was taken
+        for (int round = 0;; round++) {
+            GS_CHK(hipMemsetAsync(count.p, 0, sizeof(int), st));
+            k_gs_match<<<gs_grid(gn), GS_WG, 0, st>>>(gn, cand.p, mate.p, count.p);
+            k_gs_propose<<<gs_grid(gn), GS_WG, 0, st>>>(gn, grp, gci, key.p, mate.p, cand.p);
+            GS_CHK(hipMemcpyAsync(hcount, count.p, sizeof(int), hipMemcpyDeviceToHost, st));
+            GS_CHK(hipStreamSynchronize(st));
+            if (*hcount == 0) break;
+            if (round > gn) {
+                err = "device matching did not terminate";
+                return PSC_ERR_HIP;
+            }
+        }
+        // aggregates of this sweep, numbered by smallest member
+        GS_CHK(rep.alloc(gn));
+        GS_CHK(scan.alloc(gn));
+        k_gs_rep<<<gs_grid(gn), GS_WG, 0, st>>>(gn, mate.p, rep.p);
+        int nnew = 0;
+        int r = gs_scan(st, gn, rep.p, scan.p, nnew, err);
+        if (r) return r;
+        GS_CHK(a2.alloc(gn));
+        GS_CHK(first.alloc(nnew));
+        k_gs_pairs<<<gs_grid(gn), GS_WG, 0, st>>>(gn, mate.p, scan.p, a2.p, first.p);
+        k_gs_compose<<<gs_grid(n), GS_WG, 0, st>>>(n, agg.p, a2.p);
+        GS_CHK(mem2.alloc((size_t)nnew * 2 * stride));
+        k_gs_merge<<<gs_grid(nnew), GS_WG, 0, st>>>(nnew, stride, first.p, mate.p, mem.p, mem2.p);
+        GS_CHK(hipGetLastError());
+        std::swap(mem.p, mem2.p);
+        stride *= 2;
+        if (sw + 1 < sweeps) {
+            // block sums of the matching graph for the next sweep (s = 1)
+            DBuf<int> pm;
+            GS_CHK(pm.alloc((size_t)nnew * 2));
+            k_gs_pairs_members<<<gs_grid(nnew), GS_WG, 0, st>>>(nnew, first.p, mate.p, pm.p);
+            DBuf<int>& orp = (sw % 2 == 0) ? g2rp : g3rp;
+            DBuf<int>& oci = (sw % 2 == 0) ? g2ci : g3ci;
+            DBuf<double>& ov = (sw % 2 == 0) ? g2v : g3v;
+            int cnnz = 0;
+            r = gs_galerkin(st, nnew, 2, pm.p, gn, grp, gci, gv, a2.p, nullptr, orp, oci, ov, cnnz, err);
+            if (r) return r;
+            grp = orp.p;
+            gci = oci.p;
+            gv = ov.p;
+            gn = nnew;
+        }
+        nc = nnew;
+    }
+    // w_{l+1}, p and A_{l+1}
+    DBuf<double> wc, p;
+    GS_CHK(wc.alloc(nc));
+    GS_CHK(p.alloc(n));
+    k_gs_wp<<<gs_grid(nc), GS_WG, 0, st>>>(nc, stride, mem.p, w.p, wc.p);
+    k_gs_p<<<gs_grid(n), GS_WG, 0, st>>>(n, w.p, wc.p, agg.p, p.p);
+    GS_CHK(hipGetLastError());
+    DBuf<int> crp, cci;
+    DBuf<double> cv;
+    int cnnz = 0;
+    int r = gs_galerkin(st, nc, stride, mem.p, n, rp.p, ci.p, v.p, agg.p, p.p, crp, cci, cv, cnnz, err);
+    if (r) return r;
+    agg_out.resize(n);
+    p_out.resize(n);
+    wc_out.resize(nc);
+    crp_out.resize(nc + 1);
+    cci_out.resize(cnnz);
+    cv_out.resize(cnnz);
+    GS_CHK(hipMemcpyAsync(agg_out.data(), agg.p, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, st));
+    GS_CHK(hipMemcpyAsync(p_out.data(), p.p, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st));
+    GS_CHK(hipMemcpyAsync(wc_out.data(), wc.p, (size_t)nc * sizeof(double), hipMemcpyDeviceToHost, st));
+    GS_CHK(hipMemcpyAsync(crp_out.data(), crp.p, (size_t)(nc + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+    GS_CHK(hipMemcpyAsync(cci_out.data(), cci.p, (size_t)cnnz * sizeof(int), hipMemcpyDeviceToHost, st));
+    GS_CHK(hipMemcpyAsync(cv_out.data(), cv.p, (size_t)cnnz * sizeof(double), hipMemcpyDeviceToHost, st));
+    GS_CHK(hipStreamSynchronize(st));
+    nc_out = nc;
+    return PSC_OK;
+}
+
+}  // namespace psc

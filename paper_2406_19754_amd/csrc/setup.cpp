@@ -605,6 +605,36 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
         }
         int64_t nc = 0;
         std::vector<int32_t> agg;
+        if (o.device && o.aggr == 0 && o.prol == 0) {
+            // matching, tentative prolongator: the whole coarsening on the GPU
+            std::vector<double> gp, gwc, gcv;
+            std::vector<int32_t> gcrp, gcci;
+            st = gpu_coarsen_level(A.n, A.rp.data(), A.ci.data(), A.v.data(), H.lev[l].w.data(), o.sweeps, agg,
+                                   nc, gp, gwc, gcrp, gcci, gcv, err);
+            if (st == PSC_OK) {
+                H.lev.emplace_back();
+                HostLevel& F = H.lev[l];
+                HostLevel& Cl = H.lev[l + 1];
+                F.nc = nc;
+                F.agg.swap(agg);
+                F.p.swap(gp);
+                F.prp.resize(F.n + 1);
+                for (int64_t i = 0; i <= F.n; i++) F.prp[i] = (int32_t)i;
+                F.pci = F.agg;
+                F.pv = F.p;
+                Cl.n = nc;
+                Cl.w.swap(gwc);
+                Cl.rp.swap(gcrp);
+                Cl.ci.swap(gcci);
+                Cl.v.swap(gcv);
+                F.rp.swap(A.rp);
+                F.ci.swap(A.ci);
+                F.v.swap(A.v);
+                continue;
+            }
+            if (st != PSC_ERR_STATE) return st;
+            err.clear();
+        }
         if (o.aggr == 0) coarsen(A, H.lev[l].w, o.sweeps, agg, nc);
         else vbm_aggregate(A, o.theta, agg, nc);
         H.lev.emplace_back();

@@ -38,6 +38,7 @@ struct SetupOpts {
     int prol = 0;               // 0 tentative prolongator, 1 smoothed
     int aggr = 0;               // 0 coupled matching, 1 decoupled VBM
     double theta = 0.01;        // VBM strength threshold
+    bool device = false;        // coarsen matching / tentative levels on the GPU
 };
 
 // Status codes follow psc.h.
@@ -50,6 +51,15 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
 // sweep (rows of A_l, aggregate columns), CSR with ascending columns.
 void jacobi_smoothed_prolongator(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
                                  std::vector<double>& v);
+
+// One level's coarsening on the GPU (matching aggregation, tentative
+// prolongator): aggregates, p, the next sample vector and the Galerkin
+// product, bit-identical to the host path. Returns PSC_ERR_STATE when the
+// level does not fit the device kernels (the caller then uses the host).
+int gpu_coarsen_level(int64_t n, const int32_t* rp, const int32_t* ci, const double* v, const double* w,
+                      int sweeps, std::vector<int32_t>& agg, int64_t& nc, std::vector<double>& p,
+                      std::vector<double>& wc, std::vector<int32_t>& crp, std::vector<int32_t>& cci,
+                      std::vector<double>& cv, std::string& err);
 
 // Pack CSR rows into hacked DIA with 64-row slices (offsets ascending per
 // slice, values diagonal-major in a slice, zeros where a row has no entry).

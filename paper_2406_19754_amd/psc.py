@@ -41,8 +41,8 @@ class AmgOpts(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
                 ("build_fp32", C.c_int32), ("use_graph", C.c_int32), ("host_only", C.c_int32),
                 ("coarse_sweeps", C.c_int32), ("smoothed_prol", C.c_int32), ("smoother_sweeps", C.c_int32),
-                ("vcycle_double", C.c_int32), ("aggregation", C.c_int32), ("reserved", C.c_int32 * 5),
-                ("vbm_theta", C.c_double)]
+                ("vcycle_double", C.c_int32), ("aggregation", C.c_int32), ("setup_device", C.c_int32),
+                ("reserved", C.c_int32 * 4), ("vbm_theta", C.c_double)]
 
 
 class HierStats(C.Structure):
@@ -145,7 +145,8 @@ class Hierarchy:
 
     def __init__(self, rowptr, col, val, sweeps=2, coarse_max=200, max_levels=30,
                  build_fp32=False, use_graph=True, host_only=False, stream=None, coarse_sweeps=30,
-                 smoothed_prol=False, smoother_sweeps=1, vcycle_double=False, aggregation=0, vbm_theta=0.01):
+                 smoothed_prol=False, smoother_sweeps=1, vcycle_double=False, aggregation=0, vbm_theta=0.01,
+                 setup_device=True):
         import torch
         o = AmgOpts()
         _lib.psc_amg_opts_default(C.byref(o))
@@ -154,6 +155,7 @@ class Hierarchy:
         o.smoothed_prol, o.smoother_sweeps = int(smoothed_prol), smoother_sweeps
         o.vcycle_double = int(vcycle_double)
         o.aggregation, o.vbm_theta = aggregation, vbm_theta
+        o.setup_device = int(setup_device)
         o.build_fp32, o.use_graph, o.host_only = int(build_fp32), int(use_graph), int(host_only)
         rp, prp = _hptr(rowptr, np.int32)
         ci, pci = _hptr(col, np.int32)

@@ -366,3 +366,20 @@ def test_smoothing_configurations_match_oracle(psc, case, cfg):
     if nu > 1 or smoothed or double:
         with pytest.raises(psc.PscError):
             h.tune(psc.TUNE_SPLIT, 0)
+
+
+@pytest.mark.parametrize("case,sweeps,cm", [("poisson32", 2, 200), ("poisson13", 2, 200), ("poisson24", 3, 200),
+                                            ("diffusion20_az100", 2, 200), ("random_long_rows", 2, 40),
+                                            ("diffusion48_lognormal", 2, 200)])
+def test_device_setup_bit_identical_to_host(psc, case, sweeps, cm):
+    rp, c, v = P.poisson7(24) if case == "poisson24" else CASES[case]()
+    hd = psc.Hierarchy(rp, c, v, sweeps=sweeps, coarse_max=cm, setup_device=True)
+    hh = psc.Hierarchy(rp, c, v, sweeps=sweeps, coarse_max=cm, setup_device=False, host_only=True)
+    a, b = hd.info(), hh.info()
+    assert a["rows"] == b["rows"] and a["nnz"] == b["nnz"] and a["coarse_sweeps"] == b["coarse_sweeps"]
+    for l in range(a["levels"]):
+        x, y = hd.export_level(l), hh.export_level(l)
+        for key in ["rowptr", "col", "val", "minv"]:
+            assert np.array_equal(x[key], y[key]), (l, key)
+        if l < a["levels"] - 1:
+            assert np.array_equal(x["agg"], y["agg"]) and np.array_equal(x["p"], y["p"]), l
