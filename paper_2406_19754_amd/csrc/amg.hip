@@ -151,7 +151,13 @@ __device__ void finalize(int fin, double s0, double s1, Ctl* c, HostCtl* hc) {
         c->rr = s0;
         c->iter += 1;
         c->redo = 0;
-        if (c->use_net && sqrt(s0) > 0.9 * sqrt(c->rr_old)) c->net_on = 0;   // network stagnates
+        if (c->use_net && c->net_on && sqrt(s0) > 0.9 * sqrt(c->rr_old)) {   // network stagnates
+            c->net_on = 0;
+            if (hc) {   // once per solve: lets the host drop the network kernels
+                hc->net_off = 1;
+                __threadfence_system();
+            }
+        }
         if (isnan(s0)) { c->status = PSC_ERR_NAN; c->done = 1; }
         else if (sqrt(s0) <= c->rtol * sqrt(c->nb2)) {
             if (fin == FIN_UPDATE_PCG) { c->status = PSC_OK; c->done = 1; }
@@ -915,6 +921,7 @@ __global__ void k_ctl_init(Ctl* c, HostCtl* hc, double rtol, int maxit, int form
             hc->iter = 0;
             hc->status = PSC_NOCONV;
             hc->fallbacks = 0;
+            hc->net_off = 0;
             __threadfence_system();
         }
     }
@@ -1702,9 +1709,13 @@ static const int RING = 8;
 static const int FORM_FUSED = 5;     // PCG, fused two-pass iteration, issued two iterations at a time
 static const int FORM_FFUSED64 = 6;  // FCG(1) + FP64 V-cycle, fused, two iterations at a time
 static const int FORM_FFUSED32 = 7;  // FCG(1) + FP32 V-cycle, fused, two iterations at a time
-static inline bool form_net(int form) { return form == 3 || form == 4; }
+static const int FORM_FNET64 = 8;    // FORM_FFUSED64 with the learned network on odd iterations
+static const int FORM_FNET32 = 9;    // FORM_FFUSED32 with the learned network on odd iterations
+static inline bool form_net(int form) { return form == 3 || form == 4 || form == FORM_FNET64 || form == FORM_FNET32; }
 static inline bool form_fused(int form) { return form >= FORM_FUSED; }
-static inline int form_prec(int form) { return (form == 2 || form == 4 || form == FORM_FFUSED32) ? PSC_FP32 : PSC_FP64; }
+static inline int form_prec(int form) {
+    return (form == 2 || form == 4 || form == FORM_FFUSED32 || form == FORM_FNET32) ? PSC_FP32 : PSC_FP64;
+}
 
 __global__ void k_iter_begin(Ctl* c, HostCtl* hc, int has_net) {
     if (threadIdx.x != 0 || c->done) return;
@@ -1773,8 +1784,9 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
         }
         return PSC_OK;
     }
-    if (form == FORM_FFUSED64 || form == FORM_FFUSED32) {
-        const bool f32 = form == FORM_FFUSED32;
+    if (form == FORM_FFUSED64 || form == FORM_FFUSED32 || form == FORM_FNET64 || form == FORM_FNET32) {
+        const bool f32 = form == FORM_FFUSED32 || form == FORM_FNET32;
+        const bool netf = form == FORM_FNET64 || form == FORM_FNET32;
         // The true residual and the redo of the pre-smoothing run only in the
         // iterations whose recursive residual passed the test, but are launched
         // in every one: on a grid of at most 1024 workgroups their early exit
@@ -1829,7 +1841,23 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             const Gate gr{h->ctl, GATE_REDO};
             if (f32) launch_pre(h, L0, (const double*)rnew, pre_rbuf<float>(h, L0, 1), gr, gq);
             else launch_pre(h, L0, (const double*)rnew, pre_rbuf<double>(h, L0, 1), gr, gq);
-            vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, gd, true);
+            if (!netf) {
+                vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, gd, true);
+                continue;
+            }
+            // learned form: odd iterations try z = net(r); the V-cycle (its
+            // level-0 pre-smoothing already done above) runs when the network
+            // step is not taken. net == NULL: the network was switched off for
+            // this solve, only the step accounting remains.
+            k_iter_begin<<<1, 64, 0, st>>>(h->ctl, h->hctl_dev, 1);
+            if (net) {
+                int rs = net_launch_apply(net, st, rnew, h->z, &h->ctl->rr, n, Gate{h->ctl, GATE_NET});
+                if (rs) return rs;
+                Red Rn = red_of(h, FIN_NETCHECK, GATE_NET);
+                k_dot2<<<gv, WG, 0, st>>>(n, h->z, rnew, h->q, Rn);
+                finish(h, Rn, gv);
+            }
+            vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, Gate{h->ctl, GATE_VC}, true);
         }
         return PSC_OK;
     }
@@ -1856,11 +1884,13 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
     const int prec = form_prec(form);
     if (form_net(form)) {
         k_iter_begin<<<1, 64, 0, st>>>(h->ctl, h->hctl_dev, 1);
-        int rs = net_launch_apply(net, st, h->r, h->z, &h->ctl->rr, n, Gate{h->ctl, GATE_NET});
-        if (rs) return rs;
-        Red Rn = red_of(h, FIN_NETCHECK, GATE_NET);
-        k_dot2<<<gv, WG, 0, st>>>(n, h->z, h->r, h->q, Rn);
-        finish(h, Rn, gv);
+        if (net) {   // NULL: the network was switched off for this solve
+            int rs = net_launch_apply(net, st, h->r, h->z, &h->ctl->rr, n, Gate{h->ctl, GATE_NET});
+            if (rs) return rs;
+            Red Rn = red_of(h, FIN_NETCHECK, GATE_NET);
+            k_dot2<<<gv, WG, 0, st>>>(n, h->z, h->r, h->q, Rn);
+            finish(h, Rn, gv);
+        }
         vcycle(h, prec, h->r, h->z, FIN_BETA_FCG, h->q, Gate{h->ctl, GATE_VC});
     } else {
         vcycle(h, prec, h->r, h->z, FIN_BETA_FCG, h->q, gd);
@@ -1964,8 +1994,9 @@ static int solve_impl(psc_hier* h, int form, psc_net* net, const double* b_dev, 
         return PSC_OK;
     }
     const bool use_graph = h->opts.use_graph && !h->timing;
-    const bool fused = (form == 0 || form == 1 || form == 2) && h->fused_pcg && h->lev.size() > 1;
-    if (fused) form = form == 0 ? FORM_FUSED : (form == 1 ? FORM_FFUSED64 : FORM_FFUSED32);
+    const bool fused = form <= 4 && h->fused_pcg && h->lev.size() > 1;
+    static const int fused_of[5] = {FORM_FUSED, FORM_FFUSED64, FORM_FFUSED32, FORM_FNET64, FORM_FNET32};
+    if (fused) form = fused_of[form];
     if (!c.done) {
         const Gate gd{h->ctl, GATE_DONE};
         if (form == FORM_FUSED) {
@@ -1975,6 +2006,7 @@ static int solve_impl(psc_hier* h, int form, psc_net* net, const double* b_dev, 
             k_fill<double><<<gv, WG, 0, st>>>(n, h->q, 0.0);
             k_fill<double><<<gv, WG, 0, st>>>(n, h->p, 0.0);
             vcycle(h, form_prec(form), h->r, h->z, FIN_BETA_FCG, h->q, gd);   // z = B r0, beta = 0
+            if (form_net(form)) k_set_net_on<<<1, 64, 0, st>>>(h->ctl);
         } else if (form == 0) {
             vcycle(h, PSC_FP64, h->r, h->z, FIN_RHO_INIT, h->r, gd);
             k_copy<double, double><<<gv, WG, 0, st>>>(n, h->p, h->z, gd);
@@ -1988,13 +2020,20 @@ static int solve_impl(psc_hier* h, int form, psc_net* net, const double* b_dev, 
             if (rs) return rs;
         }
         const int per_launch = fused ? 2 : 1;
+        psc_net* inet = net;
         for (int k = 0; k * per_launch < maxit; k++) {
             if (use_graph) HIPCHK(hipGraphLaunch(gexec, st));
-            else if ((rs = issue_iteration(h, form, net))) return rs;
+            else if ((rs = issue_iteration(h, form, inet))) return rs;
             HIPCHK(hipEventRecord(h->ring[k % RING], st));
             if (k >= LAG) {
                 HIPCHK(hipEventSynchronize(h->ring[(k - LAG) % RING]));
                 if (h->hctl->done) break;
+                if (inet && h->hctl->net_off) {
+                    // the network is off for the rest of this solve: replay
+                    // iterations without its kernels
+                    inet = nullptr;
+                    if (use_graph && (rs = get_graph(h, form, nullptr, &gexec))) return rs;
+                }
             }
         }
         HIPCHK(hipGetLastError());

@@ -41,6 +41,7 @@ __device__ __forceinline__ bool gate_skip(const Gate& g) {
 // Host-mapped mirror polled by the host loop.
 struct HostCtl {
     int done, iter, status, fallbacks;
+    int net_off;   // the learned network was switched off for the rest of the solve
 };
 
 // Hacked-ELL operator: slices of 64 rows; slice s holds its w_s columns

@@ -151,3 +151,32 @@ def test_pairs_collect_first_pair_matches_oracle(psc):
         np.testing.assert_allclose(rout[k].cpu().numpy(), (b.reshape(n, n, n)[sl] / s0).astype(np.float32),
                                    rtol=1e-6, atol=1e-6)
         np.testing.assert_allclose(zout[k].cpu().numpy(), (z0.reshape(n, n, n)[sl] / s0), rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_learned_fused_unfused_and_switch_off(psc, prec):
+    # A network that fails the progress test gets switched off for the rest of
+    # the solve; the host then replays iterations without its kernels. The
+    # fused and the one-kernel-per-operation learned iterations agree, and
+    # graph replay equals stream launch bit for bit.
+    n = 16
+    rp, c, v = P.poisson7(n)
+    pr = psc.FP32 if prec == "fp32" else psc.FP64
+    net = psc.Net(params(5, scale=0.5))
+    net.set_grid((n, n, n))
+    b = torch.from_numpy(P.rhs_uniform(n ** 3, 3)).cuda()
+    res = {}
+    for fused in (1, 0):
+        for graph in (True, False):
+            h = psc.Hierarchy(rp, c, v, build_fp32=True, use_graph=graph)
+            h.tune(psc.TUNE_FUSED_PCG, fused)
+            x = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+            g = h.fcg(b, x, net=net, prec=pr)
+            assert g["status"] == psc.OK and g["relres"] <= 1e-6
+            res[(fused, graph)] = (g, x.clone())
+    for fused in (1, 0):
+        (ga, xa), (gb, xb) = res[(fused, True)], res[(fused, False)]
+        assert ga["iters"] == gb["iters"] and ga["fallbacks"] == gb["fallbacks"] and torch.equal(xa, xb)
+    assert abs(res[(1, True)][0]["iters"] - res[(0, True)][0]["iters"]) <= 1
+    # scheduled network steps that ran the V-cycle are counted (also after the switch)
+    assert res[(1, True)][0]["fallbacks"] >= 1
