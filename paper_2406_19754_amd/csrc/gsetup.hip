@@ -16,8 +16,9 @@
 //     p_i = w_i / w_{l+1}[agg_i], and A_{l+1}[I,J] = sum over members i of I
 //     ascending, then row entries ascending, of (p_i a_ij) p_j, with the
 //     columns of a coarse row sorted.
-// Every floating-point step is an explicit round-to-nearest operation in
-// the host's order, so the hierarchy is bit-identical to the host one.
+// Every floating-point step is a separately rounded operation in the host's
+// order (no contraction in this file), so the hierarchy is bit-identical to
+// the host one.
 // Member lists come from merging the sorted pairs of each sweep (an
 // aggregate has at most 2^sweeps members); the only other primitive is an
 // integer exclusive scan. Rows with more than GS_MAXC distinct coarse
@@ -30,6 +31,10 @@
 
 #include "../../include/psc.h"
 #include "setup.h"
+
+// This file is compiled with -ffp-contract=off (the rest of the library
+// with contraction on): a multiply feeding an add must not become one fused
+// operation here, or sums differ from the host's.
 
 namespace psc {
 
