@@ -143,6 +143,8 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--crops", type=int, default=20000)
     ap.add_argument("--save-weights", default="")
+    ap.add_argument("--eval-only", action="store_true",
+                    help="learned128: evaluate the shipped weights without collecting pairs or training")
     ap.add_argument("--profile-mix", action="store_true",
                     help="run the kernel mix used for rocprofv3 counter passes: a plain 1 GiB device copy "
                          "(counter calibration), 10 SpMVs on A_0, one FP64 PCG and one mixed FCG solve")
@@ -195,6 +197,8 @@ def main():
             return h.fcg(bd, x, rtol=1e-6, maxit=500, prec=psc.FP32)
         if form == "fcg64":
             return h.fcg(bd, x, rtol=1e-6, maxit=500)
+        if form == "learned_mixed":
+            return h.fcg(bd, x, rtol=1e-6, maxit=500, net=net, prec=psc.FP32)
         return h.fcg(bd, x, rtol=1e-6, maxit=500, net=net)
 
     def timed(form, steps, warmup, events):
@@ -302,6 +306,11 @@ def main():
             f"fallbacks {rl['fallbacks']}")
         forms["learned"] = {"ms": msl, "iters": rl["iters"], "relres": rl["relres"], "fallbacks": rl["fallbacks"],
                             "speedup_vs_fp64": ms64 / msl, "weights": os.path.relpath(WEIGHTS, ROOT)}
+        if not args.no_mixed:
+            msm, rm, _ = timed("learned_mixed", args.steps, args.warmup, False)
+            log(f"learned fcg with FP32 V-cycle: {msm:.2f} ms/solve, {rm['iters']} its, fallbacks {rm['fallbacks']}")
+            forms["learned_mixed"] = {"ms": msm, "iters": rm["iters"], "relres": rm["relres"],
+                                      "fallbacks": rm["fallbacks"], "speedup_vs_fp64": ms64 / msm}
 
     cpu = None
     if not args.no_cpu:
@@ -389,23 +398,28 @@ def learned(args):
     from paper_2406_19754_amd import psc
     n = args.n or 128
     rp, col, val = P.poisson7(n)
-    h = psc.Hierarchy(rp, col, val)
-    t0 = time.time()
-    r, z = LR.collect_pairs(h, n, range(1, 65), range(101, 133), crops=args.crops, crop=40, seed=0)
-    t_collect = time.time() - t0
-    log(f"collected {r.shape[0]} crops in {t_collect:.1f}s")
-    net = psc.Net(P.net_init(0))
-    t0 = time.time()
-    losses, v0, v1 = LR.train(net, r, z, epochs=args.train_epochs, batch=16, margin=3, lr=args.lr, seed=0, log=log,
-                              lr_min=args.lr * 0.02)
-    t_train = time.time() - t0
-    log(f"trained {len(losses)} steps in {t_train:.1f}s; validation MSE {v0:.4e} -> {v1:.4e}")
-    if args.save_weights:
-        os.makedirs(os.path.dirname(os.path.abspath(args.save_weights)), exist_ok=True)
-        net.params().tofile(args.save_weights)
+    h = psc.Hierarchy(rp, col, val, build_fp32=True)
+    if args.eval_only:
+        # the shipped weights, no data collection or training
+        net = psc.Net(np.fromfile(WEIGHTS, dtype=np.float32))
+        losses, v0, v1, t_collect, t_train = np.zeros(0), None, None, 0.0, 0.0
+    else:
+        t0 = time.time()
+        r, z = LR.collect_pairs(h, n, range(1, 65), range(101, 133), crops=args.crops, crop=40, seed=0)
+        t_collect = time.time() - t0
+        log(f"collected {r.shape[0]} crops in {t_collect:.1f}s")
+        net = psc.Net(P.net_init(0))
+        t0 = time.time()
+        losses, v0, v1 = LR.train(net, r, z, epochs=args.train_epochs, batch=16, margin=3, lr=args.lr, seed=0,
+                                  log=log, lr_min=args.lr * 0.02)
+        t_train = time.time() - t0
+        log(f"trained {len(losses)} steps in {t_train:.1f}s; validation MSE {v0:.4e} -> {v1:.4e}")
+        if args.save_weights:
+            os.makedirs(os.path.dirname(os.path.abspath(args.save_weights)), exist_ok=True)
+            net.params().tofile(args.save_weights)
+        del r, z
+        torch.cuda.empty_cache()
     net.set_grid((n, n, n))
-    del r, z
-    torch.cuda.empty_cache()
     ev = LR.evaluate(h, net, n, range(1001, 1009), kinds=("uniform",), reps=3)
     # cost of one network application vs one V-cycle on the same grid
     rr = torch.from_numpy(P.rhs_uniform(n ** 3, 5)).cuda()
@@ -434,6 +448,9 @@ def learned(args):
         "learned_ms": float(np.mean([e["learned"]["ms"] for e in ev])),
         "learned_relres": max(e["learned"]["relres"] for e in ev),
         "learned_fallbacks": [e["learned"]["fallbacks"] for e in ev],
+        "mixed_ms": float(np.mean([e["mixed"]["ms"] for e in ev])),
+        "learned_mixed_ms": float(np.mean([e["learned_mixed"]["ms"] for e in ev])),
+        "learned_mixed_iters": [e["learned_mixed"]["iters"] for e in ev],
         "untrained_iters": [e["learned"]["iters"] for e in ev_u],
         "net_apply_ms": t_net, "vcycle_ms": t_vc,
     }

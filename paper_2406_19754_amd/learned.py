@@ -90,7 +90,10 @@ def train(net, r, z, epochs=2, batch=16, margin=3, lr=1e-3, seed=0, holdout=0.05
 
 
 def evaluate(h, net, n, seeds, kinds=("uniform",), rtol=1e-6, reps=1):
-    """Held-out solves: FP64 PCG vs learned FCG (and FP64 FCG), iterations and ms."""
+    """Held-out solves: FP64 PCG, learned FCG, and both FCG forms with the FP32 V-cycle; iterations and ms.
+
+    The hierarchy must have been built with build_fp32.
+    """
     import torch
     out = []
     x = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
@@ -103,7 +106,9 @@ def evaluate(h, net, n, seeds, kinds=("uniform",), rtol=1e-6, reps=1):
             bd = torch.from_numpy(b).cuda()
             row = {"kind": kind, "seed": s}
             for name, fn in [("pcg", lambda: h.pcg(bd, x, rtol=rtol)),
-                             ("learned", lambda: h.fcg(bd, x, rtol=rtol, net=net))]:
+                             ("learned", lambda: h.fcg(bd, x, rtol=rtol, net=net)),
+                             ("mixed", lambda: h.fcg(bd, x, rtol=rtol, prec=psc.FP32)),
+                             ("learned_mixed", lambda: h.fcg(bd, x, rtol=rtol, net=net, prec=psc.FP32))]:
                 x.zero_()
                 fn()
                 torch.cuda.synchronize()
