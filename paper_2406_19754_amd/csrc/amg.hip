@@ -1123,6 +1123,83 @@ __global__ __launch_bounds__(WG) void k_coarse(int n, const double* __restrict__
     }
 }
 
+// ---- the small levels in one workgroup -------------------------------------
+// Below a few thousand rows a level's pre-smoothing, restriction and
+// post-smoothing are dominated by launch and drain time, so levels t..L-1
+// (ending in the dense coarsest solve) run in one workgroup of 16 waves:
+// each wave takes whole 64-row slices, and a workgroup barrier separates the
+// steps (the waves share the CU's L1, and every vector is written before it
+// is first read in this kernel). Same arithmetic as k_pre_s, k_spmv on R,
+// k_coarse and k_post_s with one sweep.
+constexpr int TAIL_WG = 1024;
+constexpr int TAIL_MAX_ROWS = 4096;
+
+template <typename T>
+struct TailLevel {
+    Ell<T> am_ell;     // A M^-1 in hacked ELL (used when dia == 0)
+    Dia<T> am_dia;     // A M^-1 in hacked DIA
+    int dia;
+    Ell<T> R;          // restriction to the next level
+    Ell<T> SP;         // (I - M^-1 A) P
+    const T* minv;
+    T *b, *x, *r;
+};
+
+template <typename T>
+struct TailDesc {
+    int t, L, nL;
+    const double* invT;
+    TailLevel<T> lev[PSC_MAX_LEVELS];
+};
+
+template <typename T>
+__global__ __launch_bounds__(TAIL_WG) void k_tail(const TailDesc<T>* __restrict__ D, Gate g) {
+    if (gate_skip(g)) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = TAIL_WG / 64;
+    const int t = D->t, L = D->L;
+    for (int l = t; l < L - 1; l++) {
+        const TailLevel<T>& V = D->lev[l];
+        const T* b = V.b;
+        const long long ns = V.am_ell.nslices, n = V.am_ell.nrows;
+        for (long long s = wv; s < ns; s += nw) {
+            const T acc = V.dia ? dia_row(V.am_dia, s, lane, [&](int c) { return b[c]; })
+                                : ell_row(V.am_ell, s, lane, [&](int c) { return b[c]; });
+            const long long row = s * SLICE + lane;
+            if (row < n) V.r[row] = b[row] - acc;
+        }
+        __syncthreads();
+        const T* r = V.r;
+        T* bc = D->lev[l + 1].b;
+        for (long long s = wv; s < V.R.nslices; s += nw) {
+            const T acc = ell_row(V.R, s, lane, [&](int c) { return r[c]; });
+            const long long row = s * SLICE + lane;
+            if (row < V.R.nrows) bc[row] = acc;
+        }
+        __syncthreads();
+    }
+    {
+        const TailLevel<T>& C = D->lev[L - 1];
+        const int nL = D->nL;
+        for (int i = threadIdx.x; i < nL; i += TAIL_WG) {
+            double s = 0.0;
+            for (int k = 0; k < nL; k++) s += D->invT[(size_t)k * nL + i] * (double)C.b[k];
+            C.x[i] = (T)s;
+        }
+        __syncthreads();
+    }
+    for (int l = L - 2; l >= t; l--) {
+        const TailLevel<T>& V = D->lev[l];
+        const T* xc = D->lev[l + 1].x;
+        const long long ns = V.SP.nslices, n = V.SP.nrows;
+        for (long long s = wv; s < ns; s += nw) {
+            const T acc = ell_row(V.SP, s, lane, [&](int c) { return xc[c]; });
+            const long long row = s * SLICE + lane;
+            if (row < n) V.x[row] = V.minv[row] * (V.b[row] + V.r[row]) + acc;
+        }
+        __syncthreads();
+    }
+}
+
 // Coarsest level solved by l1-Jacobi sweeps in FP64 (used when coarsening
 // stalls above the dense-factor limit). One sweep from x_in:
 //   x_out_i = x_in_i + minv_i (b_i - sum_j a_ij x_in_j);
@@ -1271,6 +1348,11 @@ struct psc_hier {
     bool spmv2 = false;                   // plain SpMV / restriction: two slices per wavefront
     bool split = true;                    // smoothing sweeps through A M^-1 and A P
     bool dia = true;                      // use the hacked-DIA copies where a level has them
+    bool tail = true;                     // run the small levels in one workgroup (k_tail)
+    int tail_t = 0;                       // first level of the tail (0: no tail)
+    psc::TailDesc<double>* tail64 = nullptr;   // device descriptors (built at setup)
+    psc::TailDesc<float>* tail32 = nullptr;
+    bool tail_dia = true;                 // the DIA setting the descriptors were built with
     int nu = 1;                           // l1-Jacobi sweeps before and after the coarse correction
     std::vector<void*> allocs;
     int64_t device_bytes = 0;
@@ -1552,6 +1634,69 @@ static void coarse_solve(psc_hier* h, const TB* b, TX* x, Gate g) {
     });
 }
 
+// Descriptors of the small levels run by k_tail: levels t..L-1 with at most
+// TAIL_MAX_ROWS rows (t >= 1, at least one level above the coarsest), for a
+// V-cycle with one sweep, the split operators and a dense coarsest solve.
+template <typename T>
+static TailLevel<T> tail_level(const psc_hier* h, const DevLevel& V) {
+    TailLevel<T> e{};
+    constexpr bool f32 = std::is_same<T, float>::value;
+    if constexpr (f32) {
+        e.am_ell = V.am_view32();
+        if (V.Ad.on()) e.am_dia = V.Ad.view32(V.amd32);
+        e.R = V.R.view32();
+        e.SP = V.SP.view32();
+        e.minv = V.minv32;
+        e.b = V.b32;
+        e.x = V.x32;
+        e.r = V.r32;
+    } else {
+        e.am_ell = V.am_view();
+        if (V.Ad.on()) e.am_dia = V.Ad.view(V.amd);
+        e.R = V.R.view();
+        e.SP = V.SP.view();
+        e.minv = V.minv;
+        e.b = V.b;
+        e.x = V.x;
+        e.r = V.r;
+    }
+    e.dia = (h->dia && V.Ad.on()) ? 1 : 0;
+    return e;
+}
+
+static int build_tail(psc_hier* h) {
+    const int L = (int)h->lev.size();
+    h->tail_t = 0;
+    if (L < 3 || h->host.coarse_sweeps > 0 || !h->split || h->opts.vcycle_double || h->nu != 1) return PSC_OK;
+    int t = L - 1;
+    while (t - 1 >= 1 && h->lev[t - 1].n <= TAIL_MAX_ROWS) t--;
+    if (t > L - 2 || h->lev[L - 1].n > TAIL_MAX_ROWS) return PSC_OK;
+    TailDesc<double> d64{};
+    TailDesc<float> d32{};
+    d64.t = d32.t = t;
+    d64.L = d32.L = L;
+    d64.nL = d32.nL = h->coarse_n;
+    d64.invT = d32.invT = h->coarse_invT;
+    for (int l = t; l < L; l++) {
+        d64.lev[l] = tail_level<double>(h, h->lev[l]);
+        if (h->has32) d32.lev[l] = tail_level<float>(h, h->lev[l]);
+    }
+    int st;
+    if (!h->tail64 && (st = dalloc(h, (void**)&h->tail64, sizeof(TailDesc<double>)))) return st;
+    if (h->has32 && !h->tail32 && (st = dalloc(h, (void**)&h->tail32, sizeof(TailDesc<float>)))) return st;
+    HIPCHK(hipMemcpy(h->tail64, &d64, sizeof(d64), hipMemcpyHostToDevice));
+    if (h->has32) HIPCHK(hipMemcpy(h->tail32, &d32, sizeof(d32), hipMemcpyHostToDevice));
+    h->tail_dia = h->dia;
+    h->tail_t = t;
+    return PSC_OK;
+}
+
+template <typename T>
+static const TailDesc<T>* tail_desc(const psc_hier* h) {
+    if constexpr (std::is_same<T, float>::value) return h->tail32;
+    else return h->tail64;
+}
+
 // Residual buffer of pre-smoothing sweep k (1..nu) on a level: the buffers
 // alternate so that the last sweep's residual lands in r (read by the
 // restriction and the first post-smoothing sweep).
@@ -1635,7 +1780,10 @@ static void vcycle_t(psc_hier* h, const double* r0, double* z0, const double* d,
     const int L = (int)h->lev.size();
     Red R0 = R;
     R0.fin = FIN_NONE;
-    for (int l = 0; l < L - 1; l++) {
+    // levels from tl on run in one workgroup (k_tail) when that is set up
+    const bool tail = h->tail && h->tail_t > 0 && h->split && h->tail_dia == h->dia;
+    const int tl = tail ? h->tail_t : L - 1;
+    for (int l = 0; l < tl; l++) {
         DevLevel& V = h->lev[l];
         if (!(l == 0 && skip_pre0 && V.nu == 1)) {
             TimeScope t(h, l == 0 ? 2 : 7);
@@ -1647,12 +1795,15 @@ static void vcycle_t(psc_hier* h, const double* r0, double* z0, const double* d,
             launch_spmv(h, LV<T>::R(V), (const T*)LV<T>::r(V), LV<T>::b(h->lev[l + 1]), g, V.R.wmax > 8);
         }
     }
-    DevLevel& C = h->lev[L - 1];
-    {
+    if (tail) {
+        TimeScope t(h, 7);
+        k_tail<T><<<1, TAIL_WG, 0, h->stream>>>(tail_desc<T>(h), g);
+    } else {
+        DevLevel& C = h->lev[L - 1];
         TimeScope t(h, 7);
         coarse_solve<T, T>(h, (const T*)LV<T>::b(C), LV<T>::x(C), g);
     }
-    for (int l = L - 2; l >= 0; l--) {
+    for (int l = tl - 1; l >= 0; l--) {
         DevLevel& V = h->lev[l];
         const T* xc = LV<T>::x(h->lev[l + 1]);
         if (l == 0) {
@@ -2374,6 +2525,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     for (auto& e : h->ring) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     k_ctl_init<<<1, 64, 0, h->stream>>>(h->ctl, h->hctl_dev, 1e-6, 1, 0);
     HIPCHK(hipGetLastError());
+    if ((st = build_tail(h.get()))) return st;
     HIPCHK(hipStreamSynchronize(h->stream));
     h->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = h.release();
@@ -2573,12 +2725,18 @@ int psc_tune(psc_hier* h, int32_t key, int32_t value) {
     if (key == PSC_TUNE_DIA) {
         h->dia = value != 0;
         drop_graphs(h);
+        return build_tail(h);
+    }
+    if (key == PSC_TUNE_TAIL) {
+        h->tail = value != 0;
+        drop_graphs(h);
         return PSC_OK;
     }
     if (key == PSC_TUNE_SPLIT) {
         if (value == 0 && (h->nu > 1 || h->opts.vcycle_double || h->opts.smoothed_prol))
             return fail(PSC_ERR_ARG, "the gathering sweeps support only one sweep with the tentative prolongator");
         h->split = value != 0;
+        build_tail(h);
         drop_graphs(h);
         return PSC_OK;
     }

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpsc.so")
 OK, NOCONV = 0, 1
 ERR_ARG, ERR_NOT_SPD, ERR_NAN, ERR_HIP, ERR_OOM, ERR_COARSEN, ERR_STATE = -1, -2, -3, -4, -5, -6, -7
 FP64, FP32 = 0, 1
-TUNE_GRID_MAX, TUNE_FUSED_PCG, TUNE_UNROLL4, TUNE_BUFLOAD, TUNE_SPMV2, TUNE_SPLIT, TUNE_DIA = 1, 2, 3, 4, 5, 6, 7
+TUNE_GRID_MAX, TUNE_FUSED_PCG, TUNE_UNROLL4, TUNE_BUFLOAD, TUNE_SPMV2, TUNE_SPLIT, TUNE_DIA, TUNE_TAIL = 1, 2, 3, 4, 5, 6, 7, 8
 AGGR_MATCHING, AGGR_VBM = 0, 1
 MAX_LEVELS = 32
 TIMING_KERNELS = 8
