@@ -1403,7 +1403,8 @@ static int upload(psc_hier* h, T** d, const T* src, size_t count) {
 }
 
 static int upload_ell(psc_hier* h, DevEll<double>& E, int64_t nrows, int64_t ncols, const int32_t* rp,
-                      const int32_t* ci, const double* v, bool fp32) {
+                      const int32_t* ci, const double* v, bool fp32, const double* minv = nullptr,
+                      double** am = nullptr, float** am32 = nullptr) {
     std::vector<long long> off;
     std::vector<double> val;
     std::vector<int> col;
@@ -1418,10 +1419,23 @@ static int upload_ell(psc_hier* h, DevEll<double>& E, int64_t nrows, int64_t nco
     if ((st = upload(h, &E.off, off.data(), off.size()))) return st;
     if ((st = upload(h, &E.val, val.data(), val.size()))) return st;
     if ((st = upload(h, &E.col, col.data(), col.size()))) return st;
+    std::vector<float> v32;
     if (fp32) {
-        std::vector<float> v32(val.size());
+        v32.resize(val.size());
+#pragma omp parallel for schedule(static)
         for (size_t i = 0; i < val.size(); i++) v32[i] = (float)val[i];
         if ((st = upload(h, &E.val32, v32.data(), v32.size()))) return st;
+    }
+    if (minv) {
+        // A M^-1 in the same layout, in place: a_ij minv_j (padding stays 0)
+#pragma omp parallel for schedule(static)
+        for (size_t i = 0; i < val.size(); i++) val[i] = val[i] * minv[col[i]];
+        if ((st = upload(h, am, val.data(), val.size()))) return st;
+        if (fp32) {
+#pragma omp parallel for schedule(static)
+            for (size_t i = 0; i < val.size(); i++) v32[i] = (float)val[i];
+            if ((st = upload(h, am32, v32.data(), v32.size()))) return st;
+        }
     }
     return PSC_OK;
 }
@@ -2400,7 +2414,13 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
         D.nc = H.nc;
         D.nnz = H.rp[H.n];
         D.nu = h->opts.vcycle_double ? std::min(h->nu << std::min(l, 12), 4096) : h->nu;
-        if ((st = upload_ell(h.get(), D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32))) return st;
+        if (l < L - 1) {
+            if ((st = upload_ell(h.get(), D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32, H.minv.data(),
+                                 &D.am, &D.am32)))
+                return st;
+        } else if ((st = upload_ell(h.get(), D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32))) {
+            return st;
+        }
         if ((st = upload(h.get(), &D.minv, H.minv.data(), H.n))) return st;
         // hacked-DIA copy when it stores at most 4/3 of the ELL slots (8 instead
         // of 12 bytes per slot: at least 11 % fewer bytes); A M^-1 shares its layout
@@ -2421,16 +2441,20 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
                 if ((st = upload(h.get(), &G.val32, v32.data(), v32.size()))) return st;
             }
             if (l < L - 1) {
-                std::vector<double> sv(H.rp[H.n]);
+                // A M^-1 in place: a_ij minv_j on every stored diagonal slot
+                // (slots outside the matrix hold 0 and stay 0)
+                const int64_t ns = (int64_t)dstart.size() - 1;
 #pragma omp parallel for schedule(static)
-                for (int64_t i = 0; i < H.n; i++)
-                    for (int32_t k = H.rp[i]; k < H.rp[i + 1]; k++) sv[k] = H.v[k] * H.minv[H.ci[k]];
-                std::vector<int32_t> s2, o2;
-                std::vector<double> sval;
-                pack_dia(H.n, H.n, H.rp.data(), H.ci.data(), sv.data(), D.A.slots * 4 / 3, s2, o2, sval);
-                if ((st = upload(h.get(), &D.amd, sval.data(), sval.size()))) return st;
+                for (int64_t sl = 0; sl < ns; sl++)
+                    for (int32_t k = dstart[sl]; k < dstart[sl + 1]; k++)
+                        for (int lane = 0; lane < SLICE; lane++) {
+                            const int64_t c = sl * SLICE + lane + doffs[k];
+                            double& x = dval[(size_t)k * SLICE + lane];
+                            if (c >= 0 && c < H.n) x = x * H.minv[c];
+                        }
+                if ((st = upload(h.get(), &D.amd, dval.data(), dval.size()))) return st;
                 if (f32) {
-                    auto s32 = to32(sval);
+                    auto s32 = to32(dval);
                     if ((st = upload(h.get(), &D.amd32, s32.data(), s32.size()))) return st;
                 }
             }
@@ -2486,20 +2510,6 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
             std::vector<double> spv;
             jacobi_smoothed_prolongator(H, sprp, spci, spv);
             if ((st = upload_ell(h.get(), D.SP, H.n, H.nc, sprp.data(), spci.data(), spv.data(), f32))) return st;
-            // A M^-1 values, packed in A's layout
-            std::vector<double> sv(H.rp[H.n]);
-#pragma omp parallel for schedule(static)
-            for (int64_t i = 0; i < H.n; i++)
-                for (int32_t k = H.rp[i]; k < H.rp[i + 1]; k++) sv[k] = H.v[k] * H.minv[H.ci[k]];
-            std::vector<long long> soff;
-            std::vector<double> sval;
-            std::vector<int> scol;
-            pack_ell(H.n, H.rp.data(), H.ci.data(), sv.data(), soff, sval, scol);
-            if ((st = upload(h.get(), &D.am, sval.data(), sval.size()))) return st;
-            if (f32) {
-                auto s32 = to32(sval);
-                if ((st = upload(h.get(), &D.am32, s32.data(), s32.size()))) return st;
-            }
         }
     }
     // coarsest inverse, stored transposed for coalesced reads

@@ -62,16 +62,15 @@ void members_of(const std::vector<int32_t>& agg, int64_t nc, std::vector<int64_t
 // ascending j and then each entry (J, b_jJ) of row j of B in ascending J, the
 // product a_ij b_jJ into C[i,J] in that arrival order; columns ascending,
 // every reached entry stored.
-void spgemm(const Csr& A, const Csr& B, int64_t ncols, Csr& C) {
-    const int64_t n = A.n;
+void spgemm_raw(int64_t n, const int32_t* arp, const int32_t* aci, const double* av, const int32_t* brp,
+                const int32_t* bci, const double* bv, Csr& C) {
     C.n = n;
     C.rp.assign(n + 1, 0);
-    (void)ncols;
     auto row = [&](int64_t i, std::vector<std::pair<int32_t, double>>& e) {
         e.clear();
-        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++) {
-            const int32_t j = A.ci[k];
-            for (int32_t m = B.rp[j]; m < B.rp[j + 1]; m++) e.emplace_back(B.ci[m], A.v[k] * B.v[m]);
+        for (int32_t k = arp[i]; k < arp[i + 1]; k++) {
+            const int32_t j = aci[k];
+            for (int32_t m = brp[j]; m < brp[j + 1]; m++) e.emplace_back(bci[m], av[k] * bv[m]);
         }
         std::stable_sort(e.begin(), e.end(),
                          [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
@@ -111,6 +110,11 @@ void spgemm(const Csr& A, const Csr& B, int64_t ncols, Csr& C) {
             }
         }
     }
+}
+
+void spgemm(const Csr& A, const Csr& B, int64_t ncols, Csr& C) {
+    (void)ncols;
+    spgemm_raw(A.n, A.rp.data(), A.ci.data(), A.v.data(), B.rp.data(), B.ci.data(), B.v.data(), C);
 }
 
 // Transpose of an n x ncols CSR: row J lists (i, v_iJ) for i ascending.
@@ -730,22 +734,14 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
 // (the columns of row i of P are among those of row i of A P: a_ii is stored).
 void jacobi_smoothed_prolongator(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
                                  std::vector<double>& v) {
-    Csr A, Pm, T;
-    A.n = H.n;
-    A.rp = H.rp;
-    A.ci = H.ci;
-    A.v = H.v;
-    Pm.n = H.n;
-    Pm.rp = H.prp;
-    Pm.ci = H.pci;
-    Pm.v = H.pv;
-    spgemm(A, Pm, H.nc, T);
+    Csr T;
+    spgemm_raw(H.n, H.rp.data(), H.ci.data(), H.v.data(), H.prp.data(), H.pci.data(), H.pv.data(), T);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < H.n; i++) {
-        int32_t m = Pm.rp[i];
+        int32_t m = H.prp[i];
         for (int32_t k = T.rp[i]; k < T.rp[i + 1]; k++) {
             double pk = 0.0;
-            if (m < Pm.rp[i + 1] && Pm.ci[m] == T.ci[k]) pk = Pm.v[m++];
+            if (m < H.prp[i + 1] && H.pci[m] == T.ci[k]) pk = H.pv[m++];
             T.v[k] = pk - H.minv[i] * T.v[k];
         }
     }
