@@ -129,7 +129,8 @@ def main():
     ap.add_argument("--grid-max", type=int, default=0, help="workgroup cap of the streaming kernels")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-dia", action="store_true", help="read level operators from hacked ELL only")
-    ap.add_argument("--no-tail", action="store_true", help="launch the small levels' kernels one by one")
+    ap.add_argument("--tail-rows", type=int, default=-1,
+                    help="levels up to this many rows run in one workgroup (0: launch their kernels one by one)")
     ap.add_argument("--coarse-sweeps", type=int, default=30,
                     help="l1-Jacobi sweeps of a coarsest level left by a coarsening stall")
     ap.add_argument("--configs", default="",
@@ -180,8 +181,8 @@ def main():
         h.tune(psc.TUNE_SPLIT, 0)
     if args.no_dia:
         h.tune(psc.TUNE_DIA, 0)
-    if args.no_tail:
-        h.tune(psc.TUNE_TAIL, 0)
+    if args.tail_rows >= 0:
+        h.tune(psc.TUNE_TAIL, args.tail_rows)
     info = h.info()
     log(f"hierarchy {info['rows']} built in {time.time() - t0:.1f}s, opcx {info['operator_complexity']:.4f}")
     dev = torch.device("cuda:0")

@@ -1349,6 +1349,7 @@ struct psc_hier {
     bool split = true;                    // smoothing sweeps through A M^-1 and A P
     bool dia = true;                      // use the hacked-DIA copies where a level has them
     bool tail = true;                     // run the small levels in one workgroup (k_tail)
+    int tail_rows = psc::TAIL_MAX_ROWS;   // largest level (rows) the tail takes
     int tail_t = 0;                       // first level of the tail (0: no tail)
     psc::TailDesc<double>* tail64 = nullptr;   // device descriptors (built at setup)
     psc::TailDesc<float>* tail32 = nullptr;
@@ -1683,7 +1684,7 @@ static int build_tail(psc_hier* h) {
     h->tail_t = 0;
     if (L < 3 || h->host.coarse_sweeps > 0 || !h->split || h->opts.vcycle_double || h->nu != 1) return PSC_OK;
     int t = L - 1;
-    while (t - 1 >= 1 && h->lev[t - 1].n <= TAIL_MAX_ROWS) t--;
+    while (t - 1 >= 1 && h->lev[t - 1].n <= h->tail_rows) t--;
     if (t > L - 2 || h->lev[L - 1].n > TAIL_MAX_ROWS) return PSC_OK;
     TailDesc<double> d64{};
     TailDesc<float> d32{};
@@ -2738,9 +2739,11 @@ int psc_tune(psc_hier* h, int32_t key, int32_t value) {
         return build_tail(h);
     }
     if (key == PSC_TUNE_TAIL) {
+        if (value < 0 || value > TAIL_MAX_ROWS) return fail(PSC_ERR_ARG, "tail row limit must be 0..4096");
         h->tail = value != 0;
+        h->tail_rows = value;
         drop_graphs(h);
-        return PSC_OK;
+        return build_tail(h);
     }
     if (key == PSC_TUNE_SPLIT) {
         if (value == 0 && (h->nu > 1 || h->opts.vcycle_double || h->opts.smoothed_prol))

@@ -245,7 +245,7 @@ def test_fused_and_unfused_iterations_agree(psc, case, form):
     assert np.linalg.norm(x1 - x0) <= 1e-10 * np.linalg.norm(x0)
 
 
-@pytest.mark.parametrize("knob", ["tail_off", "dia_off", "split_off", "bufload_all", "bufload_none", "unroll4", "grid256",
+@pytest.mark.parametrize("knob", ["tail_off", "tail_4096", "dia_off", "split_off", "bufload_all", "bufload_none", "unroll4", "grid256",
                                   "spmv2"])
 @pytest.mark.parametrize("case", ["poisson13", "random_long_rows", "diffusion20_az100"])
 def test_kernel_variants_match_oracle(psc, case, knob):
@@ -261,6 +261,8 @@ def test_kernel_variants_match_oracle(psc, case, knob):
         h.tune(psc.TUNE_DIA, 0)
     if knob == "tail_off":
         h.tune(psc.TUNE_TAIL, 0)
+    if knob == "tail_4096":
+        h.tune(psc.TUNE_TAIL, 4096)
     if knob in ("split_off", "bufload_all", "bufload_none", "unroll4"):
         h.tune(psc.TUNE_SPLIT, 0)                    # sweeps gather through A, M^-1, P
     if knob == "bufload_all":
