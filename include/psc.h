@@ -295,9 +295,10 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
  * when its diagonal slots are at most 4/3 of its ELL slots (7-point
  * stencils: 8 bytes per entry instead of 12); 0 reads hacked ELL. */
 #define PSC_TUNE_DIA 7
-/* PSC_TUNE_TAIL: the levels with at most `value` rows (value <= 4096), down
- * to the dense coarsest solve, run in one kernel of one workgroup per V-cycle
- * (one sweep, split operators); 0 launches their kernels one by one. */
+/* PSC_TUNE_TAIL (default 0): the levels with at most `value` rows (value <=
+ * 4096), down to the dense coarsest solve, run in one kernel of one
+ * workgroup per V-cycle (one sweep, split operators); 0 launches their
+ * kernels one by one, which is as fast or faster under graph replay. */
 #define PSC_TUNE_TAIL 8
 int psc_tune(psc_hier* h, int32_t key, int32_t value);
 

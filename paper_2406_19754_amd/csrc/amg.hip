@@ -1123,10 +1123,10 @@ __global__ __launch_bounds__(WG) void k_coarse(int n, const double* __restrict__
     }
 }
 
-// ---- the small levels in one workgroup -------------------------------------
+// ---- the small levels in one workgroup (optional) --------------------------
 // Below a few thousand rows a level's pre-smoothing, restriction and
-// post-smoothing are dominated by launch and drain time, so levels t..L-1
-// (ending in the dense coarsest solve) run in one workgroup of 16 waves:
+// post-smoothing are dominated by launch and drain time; levels t..L-1
+// (ending in the dense coarsest solve) can run in one workgroup of 16 waves:
 // each wave takes whole 64-row slices, and a workgroup barrier separates the
 // steps (the waves share the CU's L1, and every vector is written before it
 // is first read in this kernel). Same arithmetic as k_pre_s, k_spmv on R,
@@ -1348,8 +1348,12 @@ struct psc_hier {
     bool spmv2 = false;                   // plain SpMV / restriction: two slices per wavefront
     bool split = true;                    // smoothing sweeps through A M^-1 and A P
     bool dia = true;                      // use the hacked-DIA copies where a level has them
-    bool tail = true;                     // run the small levels in one workgroup (k_tail)
-    int tail_rows = psc::TAIL_MAX_ROWS;   // largest level (rows) the tail takes
+    // Small levels in one workgroup (k_tail): off by default. Under graph
+    // replay each small kernel costs about as much as one latency-bound round
+    // inside the tail, so the per-level launches are as fast or faster
+    // (measured at 128^3 and 256^3); without graphs the tail saves launches.
+    bool tail = false;
+    int tail_rows = 0;                    // largest level (rows) the tail takes
     int tail_t = 0;                       // first level of the tail (0: no tail)
     psc::TailDesc<double>* tail64 = nullptr;   // device descriptors (built at setup)
     psc::TailDesc<float>* tail32 = nullptr;
