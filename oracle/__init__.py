@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _lib = None
 
 OK, NOCONV, ERR_ARG, ERR_NOT_SPD, ERR_NAN, ERR_OOM, ERR_COARSEN = 0, 1, -1, -2, -3, -5, -6
+SMOOTH_L1JACOBI, SMOOTH_AINV, SMOOTH_INVK = 0, 1, 2
 PREC_VCYCLE, PREC_NONE, PREC_L1JACOBI, PREC_JACOBI, PREC_VCYCLE32 = 0, 1, 2, 3, 4
 
 _i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
@@ -55,7 +56,20 @@ def lib():
     L.orc_match.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p]
     L.orc_match.restype = C.c_int
     L.orc_build.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
-                            C.c_int, C.c_int, C.c_double, C.POINTER(vp)]
+                            C.c_int, C.c_int, C.c_double, C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(vp)]
+    L.orc_fai_nnz.argtypes = [vp, C.c_int]
+    L.orc_fai_nnz.restype = C.c_longlong
+    L.orc_fai_get.argtypes = [vp, C.c_int, _i32p, _i32p, _f64p, _f64p]
+    L.orc_fai_get.restype = C.c_int
+    L.orc_fai_single.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_double, C.c_int, C.c_int,
+                                 C.POINTER(C.c_int)]
+    L.orc_fai_single.restype = vp
+    L.orc_fai_single_nnz.argtypes = [vp]
+    L.orc_fai_single_nnz.restype = C.c_longlong
+    L.orc_fai_single_get.argtypes = [vp, _i32p, _i32p, _f64p, _f64p]
+    L.orc_fai_single_get.restype = None
+    L.orc_fai_single_free.argtypes = [vp]
+    L.orc_fai_single_free.restype = None
     L.orc_prol_nnz.argtypes = [vp, C.c_int]
     L.orc_prol_nnz.restype = C.c_longlong
     L.orc_prol_get.argtypes = [vp, C.c_int, _i32p, _i32p, _f64p, C.POINTER(C.c_double)]
@@ -117,6 +131,24 @@ def spmv(rowptr, col, val, x):
     return y
 
 
+def fai_factor(rowptr, col, val, kind, tau=0.1, fill1=0, fill2=1):
+    """Stand-alone AINV (kind 1) or INVK (kind 2) of an SPD CSR matrix:
+    (zr, zi, zv, d) with Z by columns, A^-1 ~ Z diag(d)^-1 Z^T."""
+    rowptr, col, val = _i32(rowptr), _i32(col), _f64(val)
+    st = C.c_int()
+    S = lib().orc_fai_single(len(rowptr) - 1, rowptr, col, val, kind, tau, fill1, fill2, C.byref(st))
+    if not S:
+        raise RuntimeError(f"oracle factorisation failed with status {st.value}")
+    try:
+        n = len(rowptr) - 1
+        nnz = lib().orc_fai_single_nnz(S)
+        zr, zi, zv, d = np.empty(n + 1, np.int32), np.empty(nnz, np.int32), np.empty(nnz), np.empty(n)
+        lib().orc_fai_single_get(S, zr, zi, zv, d)
+    finally:
+        lib().orc_fai_single_free(S)
+    return zr, zi, zv, d
+
+
 def edge_key(sij, sii, sjj):
     return lib().orc_edge_key(sij, sii, sjj)
 
@@ -132,12 +164,13 @@ class Hierarchy:
     """Oracle AMG hierarchy (C.2 of the readings): levels of (A_l, agg, p, w, minv)."""
 
     def __init__(self, rowptr, col, val, sweeps=2, coarse_max=200, max_levels=30, coarse_sweeps=30,
-                 prol=0, nu=1, nu_double=False, aggr=0, theta=0.01):
+                 prol=0, nu=1, nu_double=False, aggr=0, theta=0.01, smoother=SMOOTH_L1JACOBI, ainv_tau=0.1,
+                 invk_fill=0, invk_inv_fill=1):
         self._rowptr, self._col, self._val = _i32(rowptr), _i32(col), _f64(val)
         h = C.c_void_p()
         st = lib().orc_build(len(rowptr) - 1, self._rowptr, self._col, self._val,
                              sweeps, coarse_max, max_levels, coarse_sweeps, prol, nu, int(nu_double), aggr, theta,
-                             C.byref(h))
+                             smoother, ainv_tau, invk_fill, invk_inv_fill, C.byref(h))
         self.status = st
         if st != OK:
             raise RuntimeError(f"oracle build failed with status {st}")
@@ -163,6 +196,16 @@ class Hierarchy:
         om = C.c_double()
         lib().orc_prol_get(self._h, l, rp, ci, v, C.byref(om))
         return rp, ci, v, om.value
+
+    def fai(self, l):
+        """AINV / INVK factor of level l: (zr, zi, zv, d), Z by columns, or None."""
+        nnz = lib().orc_fai_nnz(self._h, l)
+        if nnz < 0:
+            return None
+        n = self.level_info(l)[0]
+        zr, zi, zv, d = np.empty(n + 1, np.int32), np.empty(nnz, np.int32), np.empty(nnz), np.empty(n)
+        lib().orc_fai_get(self._h, l, zr, zi, zv, d)
+        return zr, zi, zv, d
 
     @property
     def coarse_sweeps(self):

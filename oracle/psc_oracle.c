@@ -18,6 +18,9 @@
  *     P = (I - omega D^-1 A) P^, omega = 1/||D^-1 A||_inf (same section).
  *   - l1-Jacobi smoother M_l = diag(A_l) + diag(sum_{j!=i} |a_ij|):
  *     Section "GPU enabled smoothers".
+ *   - AINV and INVK smoothers, G_l = Z D^-1 Z^T ~ A_l^-1 with Z unit upper
+ *     triangular (incomplete A-biconjugation with a drop tolerance; inverse
+ *     of an incomplete LDL^T factor with levels of fill): same section.
  *   - Conjugate gradient / flexible CG to a relative residual tolerance:
  *     Section "Numerical Example".
  * Readings where the paper is silent (edge weights, tie order, weight
@@ -224,6 +227,390 @@ static int pairs_to_aggregates(int n, const int *mate, int *agg) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Factored approximate inverse smoothers (Section "GPU enabled smoothers", */
+/* AINV and INVK): G = Z D^-1 Z^T ~ A^-1 with Z unit upper triangular, so   */
+/* that a sweep x <- x + G (b - A x) needs only products with A, Z^T and Z. */
+/* ------------------------------------------------------------------------ */
+
+/* Z stored by columns: column k holds rows zi[zr[k] .. zr[k+1]) (ascending)
+ * with values zv; d[k] > 0. n = 0 means "no such smoother". */
+typedef struct { int n; int *zr, *zi; double *zv, *d; } fai;
+
+static void fai_free(fai *s) { free(s->zr); free(s->zi); free(s->zv); free(s->d); s->n = 0; }
+
+/* growable column store */
+typedef struct { long long len, cap; int *idx; double *val; } colbuf;
+static int colbuf_push(colbuf *b, int i, double v) {
+    if (b->len == b->cap) {
+        long long nc = b->cap ? 2 * b->cap : 1024;
+        int *ni = realloc(b->idx, sizeof(int) * (size_t)nc);
+        if (!ni) return ORC_ERR_OOM;
+        b->idx = ni;
+        double *nv = realloc(b->val, sizeof(double) * (size_t)nc);
+        if (!nv) return ORC_ERR_OOM;
+        b->val = nv;
+        b->cap = nc;
+    }
+    b->idx[b->len] = i;
+    b->val[b->len] = v;
+    b->len++;
+    return ORC_OK;
+}
+
+/* binary heap of ints; sign = +1: smallest first, -1: largest first */
+typedef struct { int *a; int len; int sign; } iheap;
+static void heap_push(iheap *h, int x) {
+    int i = h->len++;
+    h->a[i] = x;
+    while (i > 0) {
+        int p = (i - 1) / 2;
+        if (h->sign * h->a[p] <= h->sign * h->a[i]) break;
+        int t = h->a[p]; h->a[p] = h->a[i]; h->a[i] = t;
+        i = p;
+    }
+}
+static int heap_pop(iheap *h) {
+    int top = h->a[0];
+    h->a[0] = h->a[--h->len];
+    int i = 0;
+    for (;;) {
+        int l = 2 * i + 1, r = l + 1, m = i;
+        if (l < h->len && h->sign * h->a[l] < h->sign * h->a[m]) m = l;
+        if (r < h->len && h->sign * h->a[r] < h->sign * h->a[m]) m = r;
+        if (m == i) break;
+        int t = h->a[m]; h->a[m] = h->a[i]; h->a[i] = t;
+        i = m;
+    }
+    return top;
+}
+
+/* AINV candidates reached from the support index s: every finished column
+ * i in (cur, k) with an entry in a row adjacent to s */
+static void ainv_reach(const csr *A, int s, int cur, int k, const int *rhead, const int *rnext,
+                       const int *rcol, int *mark, iheap *hp) {
+    for (int q = A->rp[s]; q < A->rp[s + 1]; q++)
+        for (int e = rhead[A->ci[q]]; e >= 0; e = rnext[e]) {
+            const int i = rcol[e];
+            if (i > cur && i < k && mark[i] != k) { mark[i] = k; heap_push(hp, i); }
+        }
+}
+
+static int int_cmp(const void *a, const void *b) {
+    int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+
+/* (A z)_r for the dense vector z: sum over row r of A in column order */
+static double row_dot(const csr *A, int r, const double *z) {
+    double s = 0.0;
+    for (int q = A->rp[r]; q < A->rp[r + 1]; q++) s += A->v[q] * z[A->ci[q]];
+    return s;
+}
+
+/*
+ * AINV: incomplete A-biconjugation of the SPD matrix A (W = Z by symmetry),
+ * in the stabilised form whose pivots are d_i = z_i^T A z_i > 0. The process
+ * starts from z_j = e_j; for i = 0, 1, ... the columns j > i are made
+ * A-conjugate to z_i: z_j <- z_j - (z_i^T A z_j / d_i) z_i whenever that
+ * coefficient is non-zero, and after each such update the entries r != j of
+ * z_j with |z_rj| sqrt(a_rr / a_jj) < tau are dropped (the drop tolerance
+ * applies to the matrix scaled to unit diagonal). Column k is final once
+ * the steps i < k have been applied to it, so it is formed here column by
+ * column, applying those steps in ascending i; a step whose coefficient is
+ * zero changes nothing and is skipped. The candidates i for column k are
+ * the columns with an entry in a row adjacent (in A) to an entry of z_k.
+ */
+static int ainv_build(const csr *A, double tau, fai *S) {
+    const int n = A->n;
+    int st = ORC_OK;
+    double *dg = malloc(sizeof(double) * (size_t)n);
+    double *z = calloc((size_t)n, sizeof(double));
+    char *in = calloc((size_t)n, 1);
+    int *sup = malloc(sizeof(int) * (size_t)n);
+    int *mark = malloc(sizeof(int) * (size_t)n);
+    iheap hp = {malloc(sizeof(int) * (size_t)n), 0, 1};
+    /* rows of the finished columns: for row r, the columns i with z_ri != 0 */
+    int *rhead = malloc(sizeof(int) * (size_t)n);
+    colbuf rl = {0, 0, NULL, NULL};   /* idx: column i, val unused; linked by rnext */
+    int *rnext = NULL;
+    long long rnext_cap = 0;
+    colbuf col = {0, 0, NULL, NULL};
+    S->n = n;
+    S->zr = malloc(sizeof(int) * (size_t)(n + 1));
+    S->d = malloc(sizeof(double) * (size_t)n);
+    if (!dg || !z || !in || !sup || !mark || !hp.a || !rhead || !S->zr || !S->d) { st = ORC_ERR_OOM; goto out; }
+    for (int i = 0; i < n; i++) {
+        dg[i] = 0.0;
+        for (int q = A->rp[i]; q < A->rp[i + 1]; q++) if (A->ci[q] == i) dg[i] = A->v[q];
+        if (!(dg[i] > 0.0)) { st = ORC_ERR_NOT_SPD; goto out; }
+        mark[i] = -1;
+        rhead[i] = -1;
+    }
+    S->zr[0] = 0;
+    for (int k = 0; k < n; k++) {
+        int ns = 0;
+        sup[ns++] = k;
+        in[k] = 1;
+        z[k] = 1.0;
+        hp.len = 0;
+        int cur = -1;   /* the step being applied; candidates must exceed it */
+        ainv_reach(A, k, cur, k, rhead, rnext, rl.idx, mark, &hp);
+        while (hp.len > 0) {
+            const int i = heap_pop(&hp);
+            cur = i;
+            /* coefficient z_i^T A z over the entries of column i */
+            double p = 0.0;
+            for (int e = S->zr[i]; e < S->zr[i + 1]; e++) p += col.val[e] * row_dot(A, col.idx[e], z);
+            if (p == 0.0) continue;
+            const double alpha = p / S->d[i];
+            for (int e = S->zr[i]; e < S->zr[i + 1]; e++) {
+                const int r = col.idx[e];
+                if (!in[r]) {
+                    in[r] = 1;
+                    z[r] = 0.0;
+                    sup[ns++] = r;
+                    ainv_reach(A, r, cur, k, rhead, rnext, rl.idx, mark, &hp);
+                }
+                z[r] -= alpha * col.val[e];
+            }
+            /* drop small entries (never the unit diagonal) */
+            int w = 0;
+            for (int t = 0; t < ns; t++) {
+                const int r = sup[t];
+                if (r != k && fabs(z[r]) * sqrt(dg[r] / dg[k]) < tau) { in[r] = 0; z[r] = 0.0; }
+                else sup[w++] = r;
+            }
+            ns = w;
+        }
+        qsort(sup, (size_t)ns, sizeof(int), int_cmp);
+        /* pivot d_k = z^T A z, rows ascending */
+        double dk = 0.0;
+        for (int t = 0; t < ns; t++) dk += z[sup[t]] * row_dot(A, sup[t], z);
+        if (!(dk > 0.0)) { st = ORC_ERR_NOT_SPD; goto out; }
+        S->d[k] = dk;
+        for (int t = 0; t < ns; t++) {
+            const int r = sup[t];
+            if ((st = colbuf_push(&col, r, z[r]))) goto out;
+            if ((st = colbuf_push(&rl, k, 0.0))) goto out;
+            if (rl.len > rnext_cap) {
+                rnext_cap = rl.cap;
+                int *nn = realloc(rnext, sizeof(int) * (size_t)rnext_cap);
+                if (!nn) { st = ORC_ERR_OOM; goto out; }
+                rnext = nn;
+            }
+            rnext[rl.len - 1] = rhead[r];
+            rhead[r] = (int)(rl.len - 1);
+        }
+        if (col.len > 2147483647LL) { st = ORC_ERR_OOM; goto out; }
+        S->zr[k + 1] = (int)col.len;
+        for (int t = 0; t < ns; t++) { in[sup[t]] = 0; z[sup[t]] = 0.0; }
+    }
+    S->zi = col.idx;
+    S->zv = col.val;
+    col.idx = NULL;
+    col.val = NULL;
+out:
+    free(dg); free(z); free(in); free(sup); free(mark); free(hp.a); free(rhead);
+    free(rl.idx); free(rl.val); free(rnext); free(col.idx); free(col.val);
+    if (st) fai_free(S);
+    return st;
+}
+
+/*
+ * INVK: an incomplete factorisation A ~ L D L^T with level-of-fill fill1
+ * (L unit lower triangular; original entries have level 0, a fill entry
+ * created through pivot m has level lev(i,m) + lev(j,m) + 1 and is kept when
+ * that is at most fill1), followed by the sparse inverse Z ~ L^-T whose
+ * column k solves L^T z = e_k on a limited pattern: z_k = 1 (level -1), and
+ * z_r = -sum_{j > r} l_jr z_j for r < k taken in descending order, an entry
+ * r being kept when its level, one more than the smallest level of the
+ * entries j it is computed from, is at most fill2. G = Z D^-1 Z^T.
+ * A non-positive pivot is a breakdown (ORC_ERR_NOT_SPD).
+ */
+static int invk_build(const csr *A, int fill1, int fill2, fai *S) {
+    const int n = A->n;
+    int st = ORC_OK;
+    /* L by rows (strictly lower part, ascending columns) */
+    int *lr = malloc(sizeof(int) * (size_t)(n + 1));
+    colbuf lrow = {0, 0, NULL, NULL};
+    double *w = calloc((size_t)n, sizeof(double));
+    int *lev = malloc(sizeof(int) * (size_t)n);
+    char *in = calloc((size_t)n, 1);
+    int *sup = malloc(sizeof(int) * (size_t)n);
+    int *mark = malloc(sizeof(int) * (size_t)n);
+    iheap hp = {malloc(sizeof(int) * (size_t)n), 0, 1};
+    colbuf col = {0, 0, NULL, NULL};
+    S->n = n;
+    S->zr = malloc(sizeof(int) * (size_t)(n + 1));
+    S->d = malloc(sizeof(double) * (size_t)n);
+    /* the factorisation needs column access to finished rows: a growable
+     * per-column list kept as a linked list of (row, value, level) */
+    int *chead = malloc(sizeof(int) * (size_t)n), *ctail = malloc(sizeof(int) * (size_t)n);
+    int *cnext = NULL, *crow = NULL, *clev = NULL;
+    double *cval = NULL;
+    long long clen = 0, ccap = 0;
+    if (!lr || !w || !lev || !in || !sup || !mark || !hp.a || !S->zr || !S->d || !chead || !ctail) {
+        st = ORC_ERR_OOM; goto out;
+    }
+    for (int i = 0; i < n; i++) { chead[i] = ctail[i] = -1; mark[i] = -1; }
+    lr[0] = 0;
+    for (int i = 0; i < n; i++) {
+        int ns = 0;
+        hp.len = 0;
+        for (int q = A->rp[i]; q < A->rp[i + 1]; q++) {
+            const int c = A->ci[q];
+            if (c > i) continue;
+            w[c] = A->v[q];
+            lev[c] = 0;
+            in[c] = 1;
+            sup[ns++] = c;
+            if (c < i) heap_push(&hp, c);
+        }
+        if (!in[i]) { st = ORC_ERR_NOT_SPD; goto out; }
+        /* symbolic pass: the row's final pattern, every level the minimum
+         * over all pivots (a pivot's own level is final when it is reached) */
+        while (hp.len > 0) {
+            const int m = heap_pop(&hp);
+            for (int e = chead[m]; e >= 0; e = cnext[e]) {
+                const int j = crow[e];
+                const int nl = lev[m] + clev[e] + 1;
+                if (in[j]) {
+                    if (nl < lev[j]) lev[j] = nl;
+                } else if (nl <= fill1) {
+                    in[j] = 1;
+                    w[j] = 0.0;
+                    lev[j] = nl;
+                    sup[ns++] = j;
+                    heap_push(&hp, j);
+                }
+            }
+        }
+        qsort(sup, (size_t)ns, sizeof(int), int_cmp);
+        /* numeric pass over that pattern, pivots ascending:
+         * l_im = w_m / d_m, w_j -= l_im d_m l_jm, w_i -= l_im d_m l_im */
+        for (int t = 0; t < ns && sup[t] < i; t++) {
+            const int m = sup[t];
+            const double lim = w[m] / S->d[m];
+            w[m] = lim;
+            for (int e = chead[m]; e >= 0; e = cnext[e])
+                if (in[crow[e]]) w[crow[e]] -= lim * S->d[m] * cval[e];
+            w[i] -= lim * S->d[m] * lim;
+        }
+        if (!(w[i] > 0.0)) { st = ORC_ERR_NOT_SPD; goto out; }
+        S->d[i] = w[i];
+        for (int t = 0; t < ns; t++) {
+            const int m = sup[t];
+            if (m == i) continue;
+            if ((st = colbuf_push(&lrow, m, w[m]))) goto out;
+            /* append (i, l_im) to column m (rows arrive in ascending order) */
+            if (clen == ccap) {
+                ccap = ccap ? 2 * ccap : 1024;
+                int *a1 = realloc(cnext, sizeof(int) * (size_t)ccap);
+                if (!a1) { st = ORC_ERR_OOM; goto out; }
+                cnext = a1;
+                int *a2 = realloc(crow, sizeof(int) * (size_t)ccap);
+                if (!a2) { st = ORC_ERR_OOM; goto out; }
+                crow = a2;
+                int *a3 = realloc(clev, sizeof(int) * (size_t)ccap);
+                if (!a3) { st = ORC_ERR_OOM; goto out; }
+                clev = a3;
+                double *a4 = realloc(cval, sizeof(double) * (size_t)ccap);
+                if (!a4) { st = ORC_ERR_OOM; goto out; }
+                cval = a4;
+            }
+            crow[clen] = i; cval[clen] = w[m]; clev[clen] = lev[m]; cnext[clen] = -1;
+            if (ctail[m] < 0) chead[m] = (int)clen; else cnext[ctail[m]] = (int)clen;
+            ctail[m] = (int)clen;
+            clen++;
+        }
+        lr[i + 1] = (int)lrow.len;
+        for (int t = 0; t < ns; t++) { in[sup[t]] = 0; w[sup[t]] = 0.0; }
+    }
+    /* Z = L^-T column by column (descending row order) */
+    {
+        iheap mh = {hp.a, 0, -1};
+        S->zr[0] = 0;
+        for (int k = 0; k < n; k++) {
+            int ns = 0;
+            w[k] = 1.0;
+            lev[k] = -1;
+            in[k] = 1;
+            sup[ns++] = k;
+            mh.len = 0;
+            for (int e = lr[k]; e < lr[k + 1]; e++) {
+                const int r = lrow.idx[e];
+                if (mark[r] != k) { mark[r] = k; heap_push(&mh, r); }
+            }
+            while (mh.len > 0) {
+                const int r = heap_pop(&mh);
+                double s = 0.0;
+                int lv = 2147483647;
+                for (int e = chead[r]; e >= 0; e = cnext[e]) {
+                    const int j = crow[e];
+                    if (j > k || !in[j]) continue;
+                    s += cval[e] * w[j];
+                    if (lev[j] + 1 < lv) lv = lev[j] + 1;
+                }
+                if (lv > fill2) continue;
+                w[r] = -s;
+                lev[r] = lv;
+                in[r] = 1;
+                sup[ns++] = r;
+                for (int e = lr[r]; e < lr[r + 1]; e++) {
+                    const int r2 = lrow.idx[e];
+                    if (mark[r2] != k) { mark[r2] = k; heap_push(&mh, r2); }
+                }
+            }
+            qsort(sup, (size_t)ns, sizeof(int), int_cmp);
+            for (int t = 0; t < ns; t++)
+                if ((st = colbuf_push(&col, sup[t], w[sup[t]]))) goto out;
+            if (col.len > 2147483647LL) { st = ORC_ERR_OOM; goto out; }
+            S->zr[k + 1] = (int)col.len;
+            for (int t = 0; t < ns; t++) { in[sup[t]] = 0; w[sup[t]] = 0.0; }
+        }
+        hp.a = mh.a;
+    }
+    S->zi = col.idx;
+    S->zv = col.val;
+    col.idx = NULL;
+    col.val = NULL;
+out:
+    free(lr); free(lrow.idx); free(lrow.val);
+    free(w); free(lev); free(in); free(sup); free(mark); free(hp.a); free(col.idx); free(col.val);
+    free(chead); free(ctail); free(cnext); free(crow); free(clev); free(cval);
+    if (st) fai_free(S);
+    return st;
+}
+
+/* u = Z D^-1 Z^T t: y_k = (sum over column k, rows ascending, of z_rk t_r)
+ * / d_k, then u_r = sum over k ascending of z_rk y_k. */
+static void fai_apply(const fai *S, const double *t, double *u, double *y) {
+    const int n = S->n;
+    for (int k = 0; k < n; k++) {
+        double s = 0.0;
+        for (int e = S->zr[k]; e < S->zr[k + 1]; e++) s += S->zv[e] * t[S->zi[e]];
+        y[k] = s / S->d[k];
+    }
+    for (int r = 0; r < n; r++) u[r] = 0.0;
+    for (int k = 0; k < n; k++)
+        for (int e = S->zr[k]; e < S->zr[k + 1]; e++) u[S->zi[e]] += S->zv[e] * y[k];
+}
+
+/* The same in float with float copies of the factors: y_k = sum of
+ * (float)(z_rk / d_k) t_r, u_r = sum of (float)z_rk y_k. */
+static void fai_apply32(const fai *S, const float *t, float *u, float *y) {
+    const int n = S->n;
+    for (int k = 0; k < n; k++) {
+        float s = 0.0f;
+        for (int e = S->zr[k]; e < S->zr[k + 1]; e++) s += (float)(S->zv[e] / S->d[k]) * t[S->zi[e]];
+        y[k] = s;
+    }
+    for (int r = 0; r < n; r++) u[r] = 0.0f;
+    for (int k = 0; k < n; k++)
+        for (int e = S->zr[k]; e < S->zr[k + 1]; e++) u[S->zi[e]] += (float)S->zv[e] * y[k];
+}
+
+/* ------------------------------------------------------------------------ */
 /* Hierarchy                                                                */
 /* ------------------------------------------------------------------------ */
 
@@ -237,6 +624,7 @@ typedef struct {
     csr P;          /* prolongator used by the V-cycle: P^ itself, or smoothed */
     double omega;   /* smoothed prolongator: damping 1 / ||D^-1 A||_inf */
     double *L;      /* coarsest only: dense lower Cholesky factor, row-major */
+    fai S;          /* AINV / INVK smoother (S.n = 0 with l1-Jacobi) */
 } orc_level;
 
 typedef struct {
@@ -248,6 +636,9 @@ typedef struct {
     int nu_double;       /* 1: variable V-cycle, nu_l = nu * 2^l (the paper's VMATCH) */
     int aggr;            /* 0: coupled matching aggregation, 1: decoupled VBM */
     double theta;        /* VBM strength threshold */
+    int smoother;        /* 0: l1-Jacobi, 1: AINV, 2: INVK (all levels above the coarsest) */
+    double tau;          /* AINV drop tolerance */
+    int fill1, fill2;    /* INVK fill levels of the factor and of its inverse */
     orc_level lev[ORC_MAXLEV];
 } orc_hier;
 
@@ -258,6 +649,7 @@ void orc_free(orc_hier *h) {
         csr_free(&L->A);
         free(L->w); free(L->minv); free(L->agg); free(L->p); free(L->L);
         csr_free(&L->P);
+        fai_free(&L->S);
     }
     free(h);
 }
@@ -606,10 +998,12 @@ static int csr_copy(int n, const int *rp, const int *ci, const double *v, csr *a
  */
 int orc_build(int n, const int *rp, const int *ci, const double *v,
               int sweeps, int coarse_max, int max_levels, int coarse_sweeps, int prol, int nu,
-              int nu_double, int aggr, double theta, orc_hier **out) {
+              int nu_double, int aggr, double theta, int smoother, double tau, int fill1, int fill2,
+              orc_hier **out) {
     *out = NULL;
     if (n <= 0 || sweeps < 1 || max_levels < 1 || max_levels > ORC_MAXLEV || prol < 0 || prol > 1 ||
-        nu < 1 || nu_double < 0 || nu_double > 1 || aggr < 0 || aggr > 1 || !(theta >= 0.0 && theta < 1.0))
+        nu < 1 || nu_double < 0 || nu_double > 1 || aggr < 0 || aggr > 1 || !(theta >= 0.0 && theta < 1.0) ||
+        smoother < 0 || smoother > 2 || !(tau >= 0.0) || fill1 < 0 || fill2 < 0)
         return ORC_ERR_ARG;
     orc_hier *h = calloc(1, sizeof(orc_hier));
     h->sweeps = sweeps;
@@ -618,6 +1012,10 @@ int orc_build(int n, const int *rp, const int *ci, const double *v,
     h->nu_double = nu_double;
     h->aggr = aggr;
     h->theta = theta;
+    h->smoother = smoother;
+    h->tau = tau;
+    h->fill1 = fill1;
+    h->fill2 = fill2;
     int st = csr_copy(n, rp, ci, v, &h->lev[0].A);
     if (st) { orc_free(h); return st; }
     h->lev[0].w = malloc(sizeof(double) * (size_t)n);
@@ -651,6 +1049,10 @@ int orc_build(int n, const int *rp, const int *ci, const double *v,
             if (st) { orc_free(h); return st; }
             break;
         }
+        /* smoother of a level that is not the coarsest */
+        if (smoother == 1) st = ainv_build(&L->A, tau, &L->S);
+        else if (smoother == 2) st = invk_build(&L->A, fill1, fill2, &L->S);
+        if (st) { orc_free(h); return st; }
         L->agg = malloc(sizeof(int) * (size_t)nl);
         int nc = 0;
         if (aggr == 0) st = coarsen(&L->A, L->w, sweeps, L->agg, &nc);
@@ -756,6 +1158,55 @@ int orc_prol_get(const orc_hier *h, int l, int *rp, int *ci, double *v, double *
     return ORC_OK;
 }
 
+/* The AINV / INVK factor of level l: nnz of Z (-1 when the level has none),
+ * then Z by columns (zr n+1, zi / zv nnz) and the pivots d (n). */
+long long orc_fai_nnz(const orc_hier *h, int l) {
+    if (l < 0 || l >= h->nlev || !h->lev[l].S.n) return -1;
+    return h->lev[l].S.zr[h->lev[l].S.n];
+}
+
+int orc_fai_get(const orc_hier *h, int l, int *zr, int *zi, double *zv, double *d) {
+    if (orc_fai_nnz(h, l) < 0) return ORC_ERR_ARG;
+    const fai *S = &h->lev[l].S;
+    memcpy(zr, S->zr, sizeof(int) * (size_t)(S->n + 1));
+    memcpy(zi, S->zi, sizeof(int) * (size_t)S->zr[S->n]);
+    memcpy(zv, S->zv, sizeof(double) * (size_t)S->zr[S->n]);
+    memcpy(d, S->d, sizeof(double) * (size_t)S->n);
+    return ORC_OK;
+}
+
+/* Stand-alone factorisations of an SPD CSR matrix (for the pins): kind 1
+ * AINV(tau), kind 2 INVK(fill1, fill2). The result is kept in a small
+ * handle read with orc_fai_single_get and released with orc_fai_single_free. */
+fai *orc_fai_single(int n, const int *rp, const int *ci, const double *v, int kind, double tau,
+                    int fill1, int fill2, int *status) {
+    csr a;
+    *status = csr_copy(n, rp, ci, v, &a);
+    if (*status) return NULL;
+    fai *S = calloc(1, sizeof(fai));
+    if (kind == 1) *status = ainv_build(&a, tau, S);
+    else if (kind == 2) *status = invk_build(&a, fill1, fill2, S);
+    else *status = ORC_ERR_ARG;
+    csr_free(&a);
+    if (*status) { free(S); return NULL; }
+    return S;
+}
+
+long long orc_fai_single_nnz(const fai *S) { return S->zr[S->n]; }
+
+void orc_fai_single_get(const fai *S, int *zr, int *zi, double *zv, double *d) {
+    memcpy(zr, S->zr, sizeof(int) * (size_t)(S->n + 1));
+    memcpy(zi, S->zi, sizeof(int) * (size_t)S->zr[S->n]);
+    memcpy(zv, S->zv, sizeof(double) * (size_t)S->zr[S->n]);
+    memcpy(d, S->d, sizeof(double) * (size_t)S->n);
+}
+
+void orc_fai_single_free(fai *S) {
+    if (!S) return;
+    fai_free(S);
+    free(S);
+}
+
 /* Coarsest-level solve in FP64: dense Cholesky, or l1-Jacobi sweeps from
  * x = 0 (x <- x + M^{-1}(b - A x)) when the hierarchy says so. */
 static void coarse_solve(const orc_hier *h, const double *b, double *x) {
@@ -794,12 +1245,25 @@ static void vcycle_level(const orc_hier *h, int l, const double *b, double *x) {
     double *bc = malloc(sizeof(double) * (size_t)nc);
     double *xc = malloc(sizeof(double) * (size_t)nc);
     /* pre-smoothing from x = 0: x = M^{-1} b, then nu_l - 1 sweeps
-     * x += M^{-1} (b - A x) */
+     * x += M^{-1} (b - A x); with AINV / INVK, M^{-1} is G = Z D^-1 Z^T */
     const int nu = level_sweeps(h, l);
-    for (int i = 0; i < n; i++) x[i] = L->minv[i] * b[i];
+    double *t = NULL, *y = NULL;
+    if (L->S.n) {
+        t = malloc(sizeof(double) * (size_t)n);
+        y = malloc(sizeof(double) * (size_t)n);
+        fai_apply(&L->S, b, x, y);
+    } else {
+        for (int i = 0; i < n; i++) x[i] = L->minv[i] * b[i];
+    }
     for (int k = 1; k < nu; k++) {
         orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
-        for (int i = 0; i < n; i++) x[i] += L->minv[i] * (b[i] - r[i]);
+        if (L->S.n) {
+            for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
+            fai_apply(&L->S, r, t, y);
+            for (int i = 0; i < n; i++) x[i] += t[i];
+        } else {
+            for (int i = 0; i < n; i++) x[i] += L->minv[i] * (b[i] - r[i]);
+        }
     }
     /* residual r = b - A x */
     orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
@@ -818,9 +1282,15 @@ static void vcycle_level(const orc_hier *h, int l, const double *b, double *x) {
     /* nu_l post-smoothing sweeps x += M^{-1} (b - A x) */
     for (int k = 0; k < nu; k++) {
         orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
-        for (int i = 0; i < n; i++) x[i] += L->minv[i] * (b[i] - r[i]);
+        if (L->S.n) {
+            for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
+            fai_apply(&L->S, r, t, y);
+            for (int i = 0; i < n; i++) x[i] += t[i];
+        } else {
+            for (int i = 0; i < n; i++) x[i] += L->minv[i] * (b[i] - r[i]);
+        }
     }
-    free(r); free(bc); free(xc);
+    free(r); free(bc); free(xc); free(t); free(y);
 }
 
 void orc_vcycle(const orc_hier *h, const double *b, double *x) {
@@ -853,14 +1323,27 @@ static void vcycle32_level(const orc_hier *h, int l, const float *b, float *x) {
     float *bc = malloc(sizeof(float) * (size_t)nc);
     float *xc = malloc(sizeof(float) * (size_t)nc);
     const int nu = level_sweeps(h, l);
-    for (int i = 0; i < n; i++) x[i] = (float)L->minv[i] * b[i];
+    float *t = NULL, *y = NULL;
+    if (L->S.n) {
+        t = malloc(sizeof(float) * (size_t)n);
+        y = malloc(sizeof(float) * (size_t)n);
+        fai_apply32(&L->S, b, x, y);
+    } else {
+        for (int i = 0; i < n; i++) x[i] = (float)L->minv[i] * b[i];
+    }
     for (int k = 1; k < nu; k++) {
         for (int i = 0; i < n; i++) {
             float s = 0.0f;
             for (int q = L->A.rp[i]; q < L->A.rp[i + 1]; q++) s += (float)L->A.v[q] * x[L->A.ci[q]];
             r[i] = s;
         }
-        for (int i = 0; i < n; i++) x[i] += (float)L->minv[i] * (b[i] - r[i]);
+        if (L->S.n) {
+            for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
+            fai_apply32(&L->S, r, t, y);
+            for (int i = 0; i < n; i++) x[i] += t[i];
+        } else {
+            for (int i = 0; i < n; i++) x[i] += (float)L->minv[i] * (b[i] - r[i]);
+        }
     }
     for (int i = 0; i < n; i++) {
         float s = 0.0f;
@@ -882,9 +1365,15 @@ static void vcycle32_level(const orc_hier *h, int l, const float *b, float *x) {
             for (int q = L->A.rp[i]; q < L->A.rp[i + 1]; q++) s += (float)L->A.v[q] * x[L->A.ci[q]];
             r[i] = s;
         }
-        for (int i = 0; i < n; i++) x[i] += (float)L->minv[i] * (b[i] - r[i]);
+        if (L->S.n) {
+            for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
+            fai_apply32(&L->S, r, t, y);
+            for (int i = 0; i < n; i++) x[i] += t[i];
+        } else {
+            for (int i = 0; i < n; i++) x[i] += (float)L->minv[i] * (b[i] - r[i]);
+        }
     }
-    free(r); free(bc); free(xc);
+    free(r); free(bc); free(xc); free(t); free(y);
 }
 
 void orc_vcycle32(const orc_hier *h, const double *b, double *x) {
