@@ -112,6 +112,58 @@ def problem(workload, n, az, seed=0):
     return rp, col, val, xt, b, desc
 
 
+def time_configs(args, psc, torch, rp, col, val, bd, x, ms64=None):
+    """Time FP64 PCG and mixed FCG(1) with each --configs setting on the
+    problem (b = bd); ms64: the headline FP64 time, for the speed-up."""
+    forms = {}
+    extra = {"smatch": dict(sweeps=3, smoothed_prol=True, smoother_sweeps=4),
+             "vmatch": dict(sweeps=3, smoother_sweeps=2, vcycle_double=True),
+             "vbm": dict(aggregation=psc.AGGR_VBM, vbm_theta=0.01, smoothed_prol=True, smoother_sweeps=4),
+             "ainv": dict(smoother=psc.SMOOTH_AINV, ainv_tau=0.1),
+             "invk": dict(smoother=psc.SMOOTH_INVK, invk_fill=0, invk_inv_fill=1),
+             "invk00": dict(smoother=psc.SMOOTH_INVK, invk_fill=0, invk_inv_fill=0)}
+    for cfg in [c for c in args.configs.split(",") if c]:
+        t0 = time.time()
+        hs = psc.Hierarchy(rp, col, val, build_fp32=not args.no_mixed, use_graph=not args.no_graph,
+                           setup_device=not args.config_host_setup, **extra[cfg])
+        infs = hs.info()
+        log(f"{cfg} hierarchy {infs['rows']} built in {time.time() - t0:.1f}s, "
+            f"opcx {infs['operator_complexity']:.4f}")
+        for form in ["fp64"] + ([] if args.no_mixed else ["mixed"]):
+            def run_s():
+                x.zero_()
+                if form == "fp64":
+                    return hs.pcg(bd, x, rtol=1e-6, maxit=500)
+                return hs.fcg(bd, x, rtol=1e-6, maxit=500, prec=psc.FP32)
+            for _ in range(args.warmup):
+                run_s()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                rs = run_s()
+            torch.cuda.synchronize()
+            mss = (time.perf_counter() - t) * 1e3 / args.steps
+            # one event-instrumented solve for the V-cycle's bandwidth
+            hs.timing(True)
+            run_s()
+            torch.cuda.synchronize()
+            vc_cnt, vc_ms = hs.timing_get()["vcycle"]
+            hs.timing(False)
+            vb = infs["vcycle_bytes_fp64" if form == "fp64" else "vcycle_bytes_fp32"]
+            vgbs = vb / (vc_ms / vc_cnt * 1e-3) / 1e9 if vc_cnt else None
+            log(f"{cfg} {form}: {mss:.2f} ms/solve, {rs['iters']} its, relres {rs['relres']:.2e}"
+                + (f", V-cycle {vc_ms / vc_cnt:.3f} ms at {vgbs:.0f} GB/s" if vc_cnt else ""))
+            forms[cfg + "_" + form] = {"ms": mss, "iters": rs["iters"], "relres": rs["relres"],
+                                       "speedup_vs_fp64": ms64 / mss if ms64 else None,
+                                       "operator_complexity": infs["operator_complexity"],
+                                       "setup_s": infs["setup_seconds"],
+                                       "vcycle_ms": vc_ms / vc_cnt if vc_cnt else None, "vcycle_gbs": vgbs}
+            if infs["smoother"]:
+                forms[cfg + "_" + form]["smoother_nnz_per_row"] = infs["smoother_nnz"][0] / infs["rows"][0]
+        hs.close()
+    return forms
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,7 +189,13 @@ def main():
                     help="comma-separated extra preconditioner settings to time with the same problem: "
                          "smatch (aggregates <= 8, smoothed prolongator, 4 sweeps), "
                          "vmatch (aggregates <= 8, tentative prolongator, 2 sweeps doubled per level), "
-                         "vbm (strength-based aggregation, smoothed prolongator, 4 sweeps)")
+                         "vbm (strength-based aggregation, smoothed prolongator, 4 sweeps), "
+                         "ainv (AINV smoother, drop tolerance 0.1), invk (INVK smoother, fill 0, inverse fill 1), "
+                         "invk00 (INVK, no inverse fill)")
+    ap.add_argument("--only-configs", action="store_true",
+                    help="time only the --configs settings (no headline solve; one JSON line of their results)")
+    ap.add_argument("--config-host-setup", action="store_true",
+                    help="build the --configs hierarchies with the host setup only")
     ap.add_argument("--no-split", action="store_true",
                     help="smoothing sweeps gather through A, M^-1 and P instead of A M^-1 and A P")
     ap.add_argument("--unfused", action="store_true", help="one kernel per CG operation instead of the fused PCG iteration")
@@ -170,6 +228,13 @@ def main():
     t0 = time.time()
     rp, col, val, xt, b, desc = problem(args.workload, n, args.az)
     log(f"problem {desc} built in {time.time() - t0:.1f}s")
+    if args.only_configs:
+        bd = torch.from_numpy(b).cuda()
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        forms = time_configs(args, psc, torch, rp, col, val, bd, x)
+        print(json.dumps({"mode": "configs", "workload": desc, "steps": args.steps, "warmup": args.warmup,
+                          "setup": "host" if args.config_host_setup else "device", "forms": forms}))
+        return
     t0 = time.time()
     h = psc.Hierarchy(rp, col, val, build_fp32=not args.no_mixed, use_graph=not args.no_graph,
                       coarse_sweeps=args.coarse_sweeps)
@@ -275,35 +340,7 @@ def main():
                           "vcycle_gbs": info["vcycle_bytes_fp32"] / (vc_ms32 / vc_cnt32 * 1e-3) / 1e9
                           if vc_cnt32 else None,
                           "err_vs_fp64_x": float(np.linalg.norm(x32 - xg) / np.linalg.norm(xg))}
-    extra = {"smatch": dict(sweeps=3, smoothed_prol=True, smoother_sweeps=4),
-             "vmatch": dict(sweeps=3, smoother_sweeps=2, vcycle_double=True),
-             "vbm": dict(aggregation=psc.AGGR_VBM, vbm_theta=0.01, smoothed_prol=True, smoother_sweeps=4)}
-    for cfg in [c for c in args.configs.split(",") if c]:
-        t0 = time.time()
-        hs = psc.Hierarchy(rp, col, val, build_fp32=not args.no_mixed, use_graph=not args.no_graph, **extra[cfg])
-        infs = hs.info()
-        log(f"{cfg} hierarchy {infs['rows']} built in {time.time() - t0:.1f}s, "
-            f"opcx {infs['operator_complexity']:.4f}")
-        for form in ["fp64"] + ([] if args.no_mixed else ["mixed"]):
-            def run_s():
-                x.zero_()
-                if form == "fp64":
-                    return hs.pcg(bd, x, rtol=1e-6, maxit=500)
-                return hs.fcg(bd, x, rtol=1e-6, maxit=500, prec=psc.FP32)
-            for _ in range(args.warmup):
-                run_s()
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            for _ in range(args.steps):
-                rs = run_s()
-            torch.cuda.synchronize()
-            mss = (time.perf_counter() - t) * 1e3 / args.steps
-            log(f"{cfg} {form}: {mss:.2f} ms/solve, {rs['iters']} its, relres {rs['relres']:.2e}")
-            forms[cfg + "_" + form] = {"ms": mss, "iters": rs["iters"], "relres": rs["relres"],
-                                       "speedup_vs_fp64": ms64 / mss,
-                                       "operator_complexity": infs["operator_complexity"],
-                                       "setup_s": infs["setup_seconds"]}
-        hs.close()
+    forms.update(time_configs(args, psc, torch, rp, col, val, bd, x, ms64))
     if net is not None:
         msl, rl, _ = timed("learned", args.steps, args.warmup, False)
         log(f"learned fcg: {msl:.2f} ms/solve, {rl['iters']} its, relres {rl['relres']:.2e}, "

@@ -99,6 +99,21 @@ typedef struct psc_net  psc_net;    /* opaque: owns the learned preconditioner  
  *                    the mixed-precision V-cycle needs.
  *   use_graph = 1    capture the per-iteration kernel sequence as a HIP
  *                    graph and replay it.
+ *   smoother = 0     PSC_SMOOTH_L1JACOBI; PSC_SMOOTH_AINV or PSC_SMOOTH_INVK
+ *                    replace M_l^-1 in every smoothing sweep of the levels
+ *                    above the coarsest by G_l = Z D^-1 Z^T ~ A_l^-1, Z unit
+ *                    upper triangular, D > 0 diagonal (Section "GPU enabled
+ *                    smoothers"): AINV by the stabilised incomplete
+ *                    A-biconjugation with drop tolerance ainv_tau (applied to
+ *                    the matrix scaled to unit diagonal); INVK by the inverse
+ *                    of an incomplete LDL^T factor with level of fill
+ *                    invk_fill, inverted on a pattern of level invk_inv_fill.
+ *                    A sweep is x <- x + Z (D^-1 Z^T (b - A x)): products with
+ *                    A, D^-1 Z^T and Z. The coarsest solve is unchanged. The
+ *                    factors are built on the host (setup_device does not
+ *                    apply to them); PSC_ERR_NOT_SPD on a non-positive pivot.
+ *   ainv_tau = 0.1   AINV drop tolerance (>= 0).
+ *   invk_fill = 0, invk_inv_fill = 1   INVK levels of fill (0..64).
  *   host_only = 0    build the hierarchy on the host only and make no HIP
  *                    call (for inspection with psc_hier_info and
  *                    psc_hier_export_level on machines without a GPU);
@@ -106,6 +121,9 @@ typedef struct psc_net  psc_net;    /* opaque: owns the learned preconditioner  
  */
 #define PSC_AGGR_MATCHING 0
 #define PSC_AGGR_VBM 1
+#define PSC_SMOOTH_L1JACOBI 0
+#define PSC_SMOOTH_AINV 1
+#define PSC_SMOOTH_INVK 2
 
 typedef struct {
     int32_t sweeps;
@@ -120,8 +138,12 @@ typedef struct {
     int32_t vcycle_double;
     int32_t aggregation;
     int32_t setup_device;
-    int32_t reserved[4];
+    int32_t smoother;
+    int32_t invk_fill;
+    int32_t invk_inv_fill;
+    int32_t reserved;
     double  vbm_theta;
+    double  ainv_tau;
 } psc_amg_opts;
 
 void psc_amg_opts_default(psc_amg_opts* opts);
@@ -216,6 +238,8 @@ typedef struct {
     int32_t smoothed_prol;
     int32_t vcycle_double;
     int32_t aggregation;
+    int32_t smoother;
+    int64_t smoother_nnz[PSC_MAX_LEVELS];    /* AINV / INVK: nonzeros of Z_l (0 otherwise) */
 } psc_hier_stats;
 
 int psc_hier_info(const psc_hier* h, psc_hier_stats* s);
@@ -240,6 +264,16 @@ int psc_hier_export_level(const psc_hier* h, int32_t level, int32_t* agg_host,
  */
 int psc_hier_export_prolongator(const psc_hier* h, int32_t level, int32_t* rowptr_host,
                                 int32_t* col_host, double* val_host);
+
+/*
+ * Copy the AINV / INVK factor of level l (levels above the coarsest of a
+ * hierarchy built with that smoother, else PSC_ERR_ARG): Z by columns,
+ * colptr_host rows[l]+1 int64, row_host / val_host smoother_nnz[l] entries
+ * (rows ascending in a column, the unit diagonal included), d_host rows[l]
+ * FP64 pivots; G_l = Z diag(d)^-1 Z^T. Any pointer may be NULL.
+ */
+int psc_hier_export_smoother(const psc_hier* h, int32_t level, int64_t* colptr_host, int32_t* row_host,
+                             double* val_host, double* d_host);
 
 /* z = B r: one V-cycle (FP64 or FP32 form) on device vectors of size n. */
 int psc_vcycle_apply(psc_hier* h, int32_t prec, const double* r_dev, double* z_dev);

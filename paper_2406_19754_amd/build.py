@@ -14,7 +14,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIP_SOURCES = ["amg.hip", "net.hip", "gsetup.hip"]
 # device setup reproduces the host setup bit for bit: no contraction there
 EXACT_SOURCES = ["gsetup.hip"]
-CXX_SOURCES = ["setup.cpp"]
+CXX_SOURCES = ["setup.cpp", "fai.cpp"]
 HEADERS = ["kernels.h", "setup.h", "net.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1227,6 +1227,98 @@ __global__ __launch_bounds__(WG) void k_jacobi(M A, const double* __restrict__ m
 // handle
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// Factored approximate inverse smoothers (AINV / INVK): a sweep is
+// x <- x + Z (W (b - A x)) with W = D^-1 Z^T, both stored as hacked ELL
+// over their rows. Four streaming kernels: the residual, the two factor
+// products and the prolongation; the V-cycle order is that of the l1-Jacobi
+// form.
+// ---------------------------------------------------------------------------
+
+// t = b - A x (x = NULL: t = b)
+template <typename M, typename TB, int GB = 4>
+__global__ __launch_bounds__(WG) void k_fres(M A, const TB* __restrict__ b, const typename M::value_type* __restrict__ x,
+                                             typename M::value_type* __restrict__ t, Gate g) {
+    using T = typename M::value_type;
+    if (gate_skip(g)) return;
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        const T acc = x ? mat_row<GB>(A, s, lane, [&](int c) { return x[c]; }) : T(0);
+        const long long row = s * SLICE + lane;
+        if (row < A.nrows) t[row] = (T)b[row] - acc;
+    }
+}
+
+// u = W t with the input read in its own precision TB and rounded to T
+template <typename T, typename TB, int GB = 4>
+__global__ __launch_bounds__(WG) void k_fw(Ell<T> W, const TB* __restrict__ t, T* __restrict__ u, Gate g) {
+    if (gate_skip(g)) return;
+    long long lo, hi;
+    chunk_range(W.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        const T acc = mat_row<GB>(W, s, lane, [&](int c) { return (T)t[c]; });
+        const long long row = s * SLICE + lane;
+        if (row < W.nrows) u[row] = acc;
+    }
+}
+
+// xout = xin + Z u (xin = NULL: xout = Z u); with R.fin != FIN_NONE also the
+// partial sum of xout * d
+template <typename T, typename TX, int GB = 4>
+__global__ __launch_bounds__(WG) void k_fz(Ell<T> Z, const T* __restrict__ u, const T* xin, TX* xout,
+                                           const double* __restrict__ d, Red R) {
+    if (skip_red(R)) return;
+    long long lo, hi;
+    chunk_range(Z.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    double s0 = 0.0;
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        const T acc = mat_row<GB>(Z, s, lane, [&](int c) { return u[c]; });
+        const long long row = s * SLICE + lane;
+        if (row < Z.nrows) {
+            const T xi = (xin ? xin[row] : T(0)) + acc;
+            xout[row] = (TX)xi;
+            if (d) s0 += (double)(TX)xi * d[row];
+        }
+    }
+    if (R.fin != FIN_NONE) block_partial(s0, 0.0, R.part);
+}
+
+// x += P xc (general prolongator, aggregate columns)
+template <typename T, int GB = 4>
+__global__ __launch_bounds__(WG) void k_fprol(Ell<T> P, const T* __restrict__ xc, T* __restrict__ x, Gate g) {
+    if (gate_skip(g)) return;
+    long long lo, hi;
+    chunk_range(P.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    for (long long s = lo + w; s < hi; s += WG / 64) {
+        const T acc = mat_row<GB>(P, s, lane, [&](int c) { return xc[c]; });
+        const long long row = s * SLICE + lane;
+        if (row < P.nrows) x[row] += acc;
+    }
+}
+
+// Fused-iteration residual update without pre-smoothing (the factored
+// smoothers start the V-cycle from r): r_new = r_old - alpha q, partial
+// ||r_new||^2 (same reduction layout as k_update_pre_s).
+__global__ __launch_bounds__(WG) void k_rupdate(long long nslices, long long n, const double* __restrict__ rold,
+                                                const double* __restrict__ q, double* __restrict__ rnew, Red R) {
+    if (skip_red(R)) return;
+    const double nalpha = -R.ctl->alpha;
+    long long lo, hi;
+    chunk_range(nslices, lo, hi);
+    double s0 = 0.0;
+    for (long long i = lo * SLICE + threadIdx.x; i < hi * SLICE && i < n; i += WG) {
+        const double rn = fma(nalpha, q[i], rold[i]);
+        rnew[i] = rn;
+        s0 += rn * rn;
+    }
+    block_partial(s0, 0.0, R.part);
+}
+
 struct GraphEntry {
     int form;
     const psc_net* net;
@@ -1283,6 +1375,11 @@ struct DevLevel {
     // s (two buffers) and two post-smoothing iterates, per precision
     double *rb = nullptr, *s = nullptr, *sb = nullptr, *xt = nullptr, *xt2 = nullptr;
     float *rb32 = nullptr, *s32 = nullptr, *sb32 = nullptr, *xt32 = nullptr, *xt232 = nullptr;
+    // AINV / INVK smoother: Z and W = D^-1 Z^T by rows, the prolongator P,
+    // and the sweep's residual t and factor product u
+    DevEll<double> Z, W, P;
+    double *ft = nullptr, *fu = nullptr;
+    float *ft32 = nullptr, *fu32 = nullptr;
 };
 
 // Per-precision views of a level's vectors and operators.
@@ -1303,6 +1400,11 @@ struct LV<double> {
     static Ell<double> SP(const DevLevel& V) { return V.SP.view(); }
     static Ell<double> A(const DevLevel& V) { return V.A.view(); }
     static const double* pv(const DevLevel& V) { return V.pval; }
+    static double* ft(DevLevel& V) { return V.ft; }
+    static double* fu(DevLevel& V) { return V.fu; }
+    static Ell<double> Z(const DevLevel& V) { return V.Z.view(); }
+    static Ell<double> W(const DevLevel& V) { return V.W.view(); }
+    static Ell<double> P(const DevLevel& V) { return V.P.view(); }
 };
 template <>
 struct LV<float> {
@@ -1319,6 +1421,11 @@ struct LV<float> {
     static Ell<float> SP(const DevLevel& V) { return V.SP.view32(); }
     static Ell<float> A(const DevLevel& V) { return V.A.view32(); }
     static const float* pv(const DevLevel& V) { return V.pval32; }
+    static float* ft(DevLevel& V) { return V.ft32; }
+    static float* fu(DevLevel& V) { return V.fu32; }
+    static Ell<float> Z(const DevLevel& V) { return V.Z.view32(); }
+    static Ell<float> W(const DevLevel& V) { return V.W.view32(); }
+    static Ell<float> P(const DevLevel& V) { return V.P.view32(); }
 };
 
 }  // namespace psc
@@ -1359,6 +1466,7 @@ struct psc_hier {
     psc::TailDesc<float>* tail32 = nullptr;
     bool tail_dia = true;                 // the DIA setting the descriptors were built with
     int nu = 1;                           // l1-Jacobi sweeps before and after the coarse correction
+    bool fai = false;                     // AINV / INVK smoother on the levels above the coarsest
     std::vector<void*> allocs;
     int64_t device_bytes = 0;
     double setup_seconds = 0.0;
@@ -1449,6 +1557,40 @@ static std::vector<float> to32(const std::vector<double>& a) {
     std::vector<float> r(a.size());
     for (size_t i = 0; i < a.size(); i++) r[i] = (float)a[i];
     return r;
+}
+
+// AINV / INVK factors of a level: W = D^-1 Z^T (row k = column k of Z over
+// d_k) and Z by rows, the prolongator P, and the sweep vectors.
+static int upload_fai(psc_hier* h, DevLevel& D, const HostLevel& H, bool f32) {
+    const HostFai& F = H.fai;
+    const int64_t n = H.n;
+    if ((int64_t)F.zr.size() != n + 1) return fail(PSC_ERR_STATE, "smoother factor missing on a level");
+    const size_t nz = F.zi.size();
+    std::vector<int32_t> wrp(n + 1), zrp(n + 1, 0), zci(nz);
+    std::vector<double> wv(nz), zv(nz);
+    for (int64_t k = 0; k <= n; k++) wrp[k] = (int32_t)F.zr[k];
+    for (int64_t k = 0; k < n; k++)
+        for (int64_t e = F.zr[k]; e < F.zr[k + 1]; e++) wv[e] = F.zv[e] / F.d[k];
+    // rows of Z: columns ascending within a row
+    for (size_t e = 0; e < nz; e++) zrp[F.zi[e] + 1]++;
+    for (int64_t r = 0; r < n; r++) zrp[r + 1] += zrp[r];
+    std::vector<int32_t> pos(zrp.begin(), zrp.end() - 1);
+    for (int64_t k = 0; k < n; k++)
+        for (int64_t e = F.zr[k]; e < F.zr[k + 1]; e++) {
+            const int32_t o = pos[F.zi[e]]++;
+            zci[o] = (int32_t)k;
+            zv[o] = F.zv[e];
+        }
+    int st;
+    if ((st = upload_ell(h, D.W, n, n, wrp.data(), F.zi.data(), wv.data(), f32))) return st;
+    if ((st = upload_ell(h, D.Z, n, n, zrp.data(), zci.data(), zv.data(), f32))) return st;
+    if ((st = upload_ell(h, D.P, n, H.nc, H.prp.data(), H.pci.data(), H.pv.data(), f32))) return st;
+    for (double** q : {&D.ft, &D.fu})
+        if ((st = dalloc(h, (void**)q, n * sizeof(double)))) return st;
+    if (f32)
+        for (float** q : {&D.ft32, &D.fu32})
+            if ((st = dalloc(h, (void**)q, n * sizeof(float)))) return st;
+    return PSC_OK;
 }
 
 static int grid_of(const psc_hier* h, long long units_per_block_4, long long total) {
@@ -1686,7 +1828,8 @@ static TailLevel<T> tail_level(const psc_hier* h, const DevLevel& V) {
 static int build_tail(psc_hier* h) {
     const int L = (int)h->lev.size();
     h->tail_t = 0;
-    if (L < 3 || h->host.coarse_sweeps > 0 || !h->split || h->opts.vcycle_double || h->nu != 1) return PSC_OK;
+    if (L < 3 || h->host.coarse_sweeps > 0 || !h->split || h->opts.vcycle_double || h->nu != 1 || h->fai)
+        return PSC_OK;
     int t = L - 1;
     while (t - 1 >= 1 && h->lev[t - 1].n <= h->tail_rows) t--;
     if (t > L - 2 || h->lev[L - 1].n > TAIL_MAX_ROWS) return PSC_OK;
@@ -1843,6 +1986,86 @@ static void vcycle_t(psc_hier* h, const double* r0, double* z0, const double* d,
     }
 }
 
+// The V-cycle with the AINV / INVK smoother in precision T: on each level
+// above the coarsest, nu sweeps x <- x + Z W (b - A x) from x = 0 (the first
+// is x = Z W b), the residual r = b - A x restricted; after the coarse
+// correction x += P x_c, nu more sweeps, the last one at level 0 writing z0
+// (FP64) with the fused dot z0 . d.
+template <typename T>
+static void vcycle_fai(psc_hier* h, const double* r0, double* z0, const double* d, const Red& R, Gate g) {
+    const int L = (int)h->lev.size();
+    Red R0 = R;
+    R0.fin = FIN_NONE;
+    hipStream_t st = h->stream;
+    auto wide = [](const DevEll<double>& E) { return E.wmax > 8; };
+    // t = b - A x
+    auto resid = [&](DevLevel& V, auto b, const T* x, T* t) {
+        using TB = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
+        const int gr = grid_ell(h, V.A.nslices);
+        const bool wa = wide_A(h, V);
+        with_A_t<T>(h, V, [&](auto A) {
+            using M = decltype(A);
+            if (wa) k_fres<M, TB, 8><<<gr, WG, 0, st>>>(A, b, x, t, g);
+            else k_fres<M, TB, 4><<<gr, WG, 0, st>>>(A, b, x, t, g);
+        });
+    };
+    auto wprod = [&](DevLevel& V, auto t, T* u) {
+        using TB = std::remove_const_t<std::remove_pointer_t<decltype(t)>>;
+        const int gr = grid_ell(h, V.W.nslices);
+        if (wide(V.W)) k_fw<T, TB, 8><<<gr, WG, 0, st>>>(LV<T>::W(V), t, u, g);
+        else k_fw<T, TB, 4><<<gr, WG, 0, st>>>(LV<T>::W(V), t, u, g);
+    };
+    auto zprod = [&](DevLevel& V, const T* u, const T* xin, auto xout, const double* dd, const Red& Rz) {
+        using TX = std::remove_pointer_t<decltype(xout)>;
+        const int gr = grid_ell(h, V.Z.nslices);
+        if (wide(V.Z)) k_fz<T, TX, 8><<<gr, WG, 0, st>>>(LV<T>::Z(V), u, xin, xout, dd, Rz);
+        else k_fz<T, TX, 4><<<gr, WG, 0, st>>>(LV<T>::Z(V), u, xin, xout, dd, Rz);
+    };
+    for (int l = 0; l < L - 1; l++) {
+        DevLevel& V = h->lev[l];
+        TimeScope ts(h, l == 0 ? 2 : 7);
+        T* x = LV<T>::x(V);
+        T* t = LV<T>::ft(V);
+        T* u = LV<T>::fu(V);
+        auto pre = [&](auto b) {
+            wprod(V, b, u);
+            zprod(V, u, (const T*)nullptr, x, nullptr, R0);
+            for (int k = 2; k <= V.nu; k++) {
+                resid(V, b, x, t);
+                wprod(V, (const T*)t, u);
+                zprod(V, u, x, x, nullptr, R0);
+            }
+            resid(V, b, x, LV<T>::r(V));
+        };
+        if (l == 0) pre(r0);
+        else pre((const T*)LV<T>::b(V));
+        launch_spmv(h, LV<T>::R(V), (const T*)LV<T>::r(V), LV<T>::b(h->lev[l + 1]), g, V.R.wmax > 8);
+    }
+    {
+        DevLevel& C = h->lev[L - 1];
+        TimeScope ts(h, 7);
+        coarse_solve<T, T>(h, (const T*)LV<T>::b(C), LV<T>::x(C), g);
+    }
+    for (int l = L - 2; l >= 0; l--) {
+        DevLevel& V = h->lev[l];
+        TimeScope ts(h, l == 0 ? 4 : 7);
+        T* x = LV<T>::x(V);
+        T* t = LV<T>::ft(V);
+        T* u = LV<T>::fu(V);
+        const int gp = grid_ell(h, V.P.nslices);
+        if (wide(V.P)) k_fprol<T, 8><<<gp, WG, 0, st>>>(LV<T>::P(V), LV<T>::x(h->lev[l + 1]), x, g);
+        else k_fprol<T, 4><<<gp, WG, 0, st>>>(LV<T>::P(V), LV<T>::x(h->lev[l + 1]), x, g);
+        for (int k = 1; k <= V.nu; k++) {
+            if (l == 0) resid(V, r0, x, t);
+            else resid(V, (const T*)LV<T>::b(V), x, t);
+            wprod(V, (const T*)t, u);
+            if (l == 0 && k == V.nu) zprod(V, u, x, z0, d, R);
+            else zprod(V, u, x, x, nullptr, R0);
+        }
+        if (l == 0) finish(h, R, grid_ell(h, V.Z.nslices));
+    }
+}
+
 // z = B r on level 0. prec: PSC_FP64 / PSC_FP32. fin/d: optional fused dot
 // z.d at level 0 with finaliser fin. g gates every kernel (g.ctl == NULL:
 // standalone V-cycle, always runs, no fused dot).
@@ -1861,6 +2084,12 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
             k_dot<<<gr, WG, 0, st>>>(h->lev[0].n, z0, d, R);
             finish(h, R, gr);
         }
+        return;
+    }
+    if (h->fai) {
+        // the factored smoothers start from r; no fused level-0 pre-smoothing
+        if (prec == PSC_FP64) vcycle_fai<double>(h, r0, z0, d, R, g);
+        else vcycle_fai<float>(h, r0, z0, d, R, g);
         return;
     }
     if (prec == PSC_FP64) vcycle_t<double>(h, r0, z0, d, R, g, skip_pre0);
@@ -1937,7 +2166,9 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             finish(h, red_of(h, FIN_ALPHA_PCG), ge);
             {
                 TimeScope t(h, 2);
-                if (h->split)
+                if (h->fai)
+                    k_rupdate<<<ge, WG, 0, st>>>(L0.A.nslices, n, rold, h->q, rnew, red_of(h, FIN_UPDATE_PCG));
+                else if (h->split)
                     with_AM(h, L0, [&](auto AM) {
                         k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, pre_rbuf<double>(h, L0, 1),
                                                                         red_of(h, FIN_UPDATE_PCG));
@@ -1979,7 +2210,9 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             finish(h, red_of(h, FIN_ALPHA_FCG), ge);
             {
                 TimeScope t(h, 2);
-                if (h->split) {
+                if (h->fai) {
+                    k_rupdate<<<ge, WG, 0, st>>>(L0.A.nslices, n, rold, h->q, rnew, red_of(h, FIN_UPDATE_FCG));
+                } else if (h->split) {
                     if (f32)
                         with_AM32(h, L0, [&](auto AM) {
                             k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, pre_rbuf<float>(h, L0, 1),
@@ -2009,8 +2242,13 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             finish(h, red_of(h, FIN_TRUE), gq);
             // after a residual replacement, redo the level-0 pre-smoothing from the true residual
             const Gate gr{h->ctl, GATE_REDO};
-            if (f32) launch_pre(h, L0, (const double*)rnew, pre_rbuf<float>(h, L0, 1), gr, gq);
-            else launch_pre(h, L0, (const double*)rnew, pre_rbuf<double>(h, L0, 1), gr, gq);
+            if (h->fai) {
+                // the factored smoothers have no fused pre-smoothing to redo
+            } else if (f32) {
+                launch_pre(h, L0, (const double*)rnew, pre_rbuf<float>(h, L0, 1), gr, gq);
+            } else {
+                launch_pre(h, L0, (const double*)rnew, pre_rbuf<double>(h, L0, 1), gr, gq);
+            }
             if (!netf) {
                 vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, gd, true);
                 continue;
@@ -2344,6 +2582,10 @@ void psc_amg_opts_default(psc_amg_opts* o) {
     o->aggregation = PSC_AGGR_MATCHING;
     o->vbm_theta = 0.01;
     o->setup_device = 1;
+    o->smoother = PSC_SMOOTH_L1JACOBI;
+    o->invk_fill = 0;
+    o->invk_inv_fill = 1;
+    o->ainv_tau = 0.1;
 }
 
 void psc_hier_free(psc_hier* h) {
@@ -2389,6 +2631,14 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     so.aggr = h->opts.aggregation;
     so.theta = h->opts.vbm_theta;
     so.device = h->opts.setup_device != 0 && !h->opts.host_only;
+    so.smoother = h->opts.smoother;
+    so.tau = h->opts.ainv_tau;
+    so.fill1 = h->opts.invk_fill;
+    so.fill2 = h->opts.invk_inv_fill;
+    if (so.smoother < 0 || so.smoother > 2 || !(so.tau >= 0.0) || so.fill1 < 0 || so.fill1 > 64 || so.fill2 < 0 ||
+        so.fill2 > 64)
+        return fail(PSC_ERR_ARG, "smoother must be 0..2, ainv_tau >= 0, INVK fill levels 0..64");
+    h->fai = so.smoother != 0;
     if (h->opts.smoother_sweeps < 1 || h->opts.smoother_sweeps > 16 || h->opts.smoothed_prol < 0 ||
         h->opts.smoothed_prol > 1)
         return fail(PSC_ERR_ARG, "smoother_sweeps must be 1..16 and smoothed_prol 0 or 1");
@@ -2468,6 +2718,11 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
             auto m32 = to32(H.minv);
             if ((st = upload(h.get(), &D.minv32, m32.data(), m32.size()))) return st;
         }
+        if (l == 0 && h->fai && L > 1) {
+            // the smoothed iterate of level 0 (the other levels keep it in x)
+            if ((st = dalloc(h.get(), (void**)&D.x, H.n * sizeof(double)))) return st;
+            if (f32 && (st = dalloc(h.get(), (void**)&D.x32, H.n * sizeof(float)))) return st;
+        }
         if (l > 0) {
             if ((st = dalloc(h.get(), (void**)&D.b, H.n * sizeof(double)))) return st;
             if ((st = dalloc(h.get(), (void**)&D.x, H.n * sizeof(double)))) return st;
@@ -2515,6 +2770,9 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
             std::vector<double> spv;
             jacobi_smoothed_prolongator(H, sprp, spci, spv);
             if ((st = upload_ell(h.get(), D.SP, H.n, H.nc, sprp.data(), spci.data(), spv.data(), f32))) return st;
+            if (h->fai) {
+                if ((st = upload_fai(h.get(), D, H, f32))) return st;
+            }
         }
     }
     // coarsest inverse, stored transposed for coalesced reads
@@ -2607,7 +2865,22 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
             s->sp_nnz[l] = D.SP.nnz;
             // level 0 reads b and writes x in FP64 in both forms
             const double e0 = l == 0 ? 1.0 : 0.0;
-            if (h->split) {
+            if (h->fai) {
+                // AINV / INVK: W and Z (Zf entries each, hacked ELL), A for the
+                // residuals, P and R for the transfers.
+                // pre: W b (b gathered, u written), Z u (u gathered, x written);
+                // sweeps 2..nu: residual (A, x gathered, b read, t written), W t,
+                // x += Z u (x read and written); residual r; restriction;
+                // post: x += P x_c, then nu sweeps of residual, W t, x += Z u
+                const double Zf = (double)D.Z.nnz, Zr = (double)h->host.lev[l].pci.size(), nu = D.nu;
+                const double res64 = Z * m64 + 24 * N, w64 = Zf * 12 + 16 * N, z64 = Zf * 12 + 24 * N;
+                const double res32 = Z * m32 + 12 * N, w32 = Zf * 8 + 8 * N, z32 = Zf * 8 + 12 * N;
+                s->smoother_nnz[l] = D.Z.nnz;
+                vb64 += w64 + (z64 - 8 * N) + (nu - 1) * (res64 + w64 + z64) + res64 + Zr * 12 + 8 * N + 8 * Nc +
+                        Zr * 12 + 8 * Nc + 16 * N + nu * (res64 + w64 + z64);
+                vb32 += w32 + (z32 - 4 * N) + (nu - 1) * (res32 + w32 + z32) + res32 + Zr * 8 + 4 * N + 4 * Nc +
+                        Zr * 8 + 4 * Nc + 8 * N + nu * (res32 + w32 + z32) + e0 * 4 * N * (2 * nu + 2);
+            } else if (h->split) {
                 // pre sweep 1: A M^-1, b gathered, r written; sweeps 2..nu: A M^-1,
                 // s and r gathered, b read, s and r written; restriction: R
                 // (nnz(P) entries), r, b_c; post sweep 1: S P, s (or b), minv, r
@@ -2646,6 +2919,21 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
     s->vcycle_double = h->opts.vcycle_double;
     s->aggregation = h->opts.aggregation;
     s->smoothed_prol = h->opts.smoothed_prol;
+    s->smoother = h->opts.smoother;
+    if (h->opts.host_only)
+        for (int l = 0; l + 1 < L; l++) s->smoother_nnz[l] = (int64_t)h->host.lev[l].fai.zi.size();
+    return PSC_OK;
+}
+
+int psc_hier_export_smoother(const psc_hier* h, int32_t l, int64_t* colptr, int32_t* row, double* val,
+                             double* d) {
+    if (!h || l < 0 || l + 1 >= (int)h->host.lev.size() || h->host.lev[l].fai.empty())
+        return fail(PSC_ERR_ARG, "level has no AINV / INVK factor");
+    const HostFai& F = h->host.lev[l].fai;
+    if (colptr) std::memcpy(colptr, F.zr.data(), F.zr.size() * sizeof(int64_t));
+    if (row) std::memcpy(row, F.zi.data(), F.zi.size() * sizeof(int32_t));
+    if (val) std::memcpy(val, F.zv.data(), F.zv.size() * sizeof(double));
+    if (d) std::memcpy(d, F.d.data(), F.d.size() * sizeof(double));
     return PSC_OK;
 }
 

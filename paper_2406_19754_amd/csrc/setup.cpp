@@ -557,7 +557,8 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
                     const SetupOpts& o, HostHier& H, std::string& err) {
     if (o.sweeps < 1 || o.sweeps > 8 || o.coarse_max < 1 || o.max_levels < 1 ||
         o.max_levels > PSC_MAX_LEVELS || o.coarse_sweeps < 0 || o.coarse_sweeps > 1000 || o.aggr < 0 ||
-        o.aggr > 1 || !(o.theta >= 0.0 && o.theta < 1.0)) {
+        o.aggr > 1 || !(o.theta >= 0.0 && o.theta < 1.0) || o.smoother < 0 || o.smoother > 2 ||
+        !(o.tau >= 0.0) || o.fill1 < 0 || o.fill1 > 64 || o.fill2 < 0 || o.fill2 > 64) {
         err = "invalid hierarchy options";
         return PSC_ERR_ARG;
     }
@@ -724,6 +725,19 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
         F.rp.swap(A.rp);
         F.ci.swap(A.ci);
         F.v.swap(A.v);
+    }
+    // AINV / INVK smoothers of the levels above the coarsest
+    if (o.smoother != 0) {
+        for (size_t l = 0; l + 1 < H.lev.size(); l++) {
+            HostLevel& F = H.lev[l];
+            const int st = o.smoother == 1
+                               ? build_ainv(F.n, F.rp.data(), F.ci.data(), F.v.data(), o.tau, F.fai, err)
+                               : build_invk(F.n, F.rp.data(), F.ci.data(), F.v.data(), o.fill1, o.fill2, F.fai, err);
+            if (st != PSC_OK) {
+                err += " (level " + std::to_string(l) + ")";
+                return st;
+            }
+        }
     }
     return PSC_OK;
 }

@@ -7,6 +7,16 @@
 
 namespace psc {
 
+// Factored approximate inverse G = Z D^-1 Z^T of a level (AINV / INVK
+// smoothers): Z unit upper triangular by columns (column k: rows
+// zi[zr[k] .. zr[k+1]) ascending, values zv), pivots d.
+struct HostFai {
+    std::vector<int64_t> zr;
+    std::vector<int32_t> zi;
+    std::vector<double> zv, d;
+    bool empty() const { return zr.size() < 2; }
+};
+
 // One level of the host hierarchy. A_l is CSR with ascending columns.
 struct HostLevel {
     int64_t n = 0;
@@ -22,6 +32,7 @@ struct HostLevel {
     std::vector<int32_t> prp, pci;
     std::vector<double> pv;
     double omega = 0.0;
+    HostFai fai;                // AINV / INVK smoother (empty with l1-Jacobi)
 };
 
 struct HostHier {
@@ -39,6 +50,9 @@ struct SetupOpts {
     int aggr = 0;               // 0 coupled matching, 1 decoupled VBM
     double theta = 0.01;        // VBM strength threshold
     bool device = false;        // coarsen matching / tentative levels on the GPU
+    int smoother = 0;           // 0 l1-Jacobi, 1 AINV, 2 INVK (levels above the coarsest)
+    double tau = 0.1;           // AINV drop tolerance
+    int fill1 = 0, fill2 = 1;   // INVK fill levels of the factor and of its inverse
 };
 
 // Status codes follow psc.h.
@@ -46,6 +60,12 @@ int validate_csr(int64_t n, const int32_t* rp, const int32_t* ci, const double* 
                  std::string& err);
 int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
                     const SetupOpts& o, HostHier& H, std::string& err);
+
+// AINV / INVK factors of one SPD CSR matrix (Section "GPU enabled smoothers").
+int build_ainv(int64_t n, const int32_t* rp, const int32_t* ci, const double* v, double tau, HostFai& F,
+               std::string& err);
+int build_invk(int64_t n, const int32_t* rp, const int32_t* ci, const double* v, int fill1, int fill2,
+               HostFai& F, std::string& err);
 
 // S P = (I - M_l^-1 A_l) P_l, the level's prolongator after one l1-Jacobi
 // sweep (rows of A_l, aggregate columns), CSR with ascending columns.

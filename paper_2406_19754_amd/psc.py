@@ -21,6 +21,7 @@ ERR_ARG, ERR_NOT_SPD, ERR_NAN, ERR_HIP, ERR_OOM, ERR_COARSEN, ERR_STATE = -1, -2
 FP64, FP32 = 0, 1
 TUNE_GRID_MAX, TUNE_FUSED_PCG, TUNE_UNROLL4, TUNE_BUFLOAD, TUNE_SPMV2, TUNE_SPLIT, TUNE_DIA, TUNE_TAIL = 1, 2, 3, 4, 5, 6, 7, 8
 AGGR_MATCHING, AGGR_VBM = 0, 1
+SMOOTH_L1JACOBI, SMOOTH_AINV, SMOOTH_INVK = 0, 1, 2
 MAX_LEVELS = 32
 TIMING_KERNELS = 8
 TIMING_NAMES = ["spmv_dot", "cg_update", "pre_smooth_l0", "restrict_l0", "post_smooth_l0",
@@ -42,7 +43,8 @@ class AmgOpts(C.Structure):
                 ("build_fp32", C.c_int32), ("use_graph", C.c_int32), ("host_only", C.c_int32),
                 ("coarse_sweeps", C.c_int32), ("smoothed_prol", C.c_int32), ("smoother_sweeps", C.c_int32),
                 ("vcycle_double", C.c_int32), ("aggregation", C.c_int32), ("setup_device", C.c_int32),
-                ("reserved", C.c_int32 * 4), ("vbm_theta", C.c_double)]
+                ("smoother", C.c_int32), ("invk_fill", C.c_int32), ("invk_inv_fill", C.c_int32),
+                ("reserved", C.c_int32), ("vbm_theta", C.c_double), ("ainv_tau", C.c_double)]
 
 
 class HierStats(C.Structure):
@@ -55,7 +57,8 @@ class HierStats(C.Structure):
                 ("coarse_sweeps", C.c_int32), ("sp_nnz", C.c_int64 * MAX_LEVELS),
                 ("dia_slots", C.c_int64 * MAX_LEVELS), ("p_nnz", C.c_int64 * MAX_LEVELS),
                 ("omega", C.c_double * MAX_LEVELS), ("smoother_sweeps", C.c_int32), ("smoothed_prol", C.c_int32),
-                ("vcycle_double", C.c_int32), ("aggregation", C.c_int32)]
+                ("vcycle_double", C.c_int32), ("aggregation", C.c_int32), ("smoother", C.c_int32),
+                ("smoother_nnz", C.c_int64 * MAX_LEVELS)]
 
 
 def _load():
@@ -75,6 +78,7 @@ def _load():
         "psc_hier_info": ([vp, P(HierStats)], C.c_int),
         "psc_hier_export_level": ([vp, i32, vp, vp, vp, vp, vp, vp], C.c_int),
         "psc_hier_export_prolongator": ([vp, i32, vp, vp, vp], C.c_int),
+        "psc_hier_export_smoother": ([vp, i32, vp, vp, vp, vp], C.c_int),
         "psc_vcycle_apply": ([vp, i32, vp, vp], C.c_int),
         "psc_spmv": ([vp, i32, i32, vp, vp], C.c_int),
         "psc_timing_enable": ([vp, i32], C.c_int),
@@ -146,7 +150,7 @@ class Hierarchy:
     def __init__(self, rowptr, col, val, sweeps=2, coarse_max=200, max_levels=30,
                  build_fp32=False, use_graph=True, host_only=False, stream=None, coarse_sweeps=30,
                  smoothed_prol=False, smoother_sweeps=1, vcycle_double=False, aggregation=0, vbm_theta=0.01,
-                 setup_device=True):
+                 setup_device=True, smoother=SMOOTH_L1JACOBI, ainv_tau=0.1, invk_fill=0, invk_inv_fill=1):
         import torch
         o = AmgOpts()
         _lib.psc_amg_opts_default(C.byref(o))
@@ -156,6 +160,7 @@ class Hierarchy:
         o.vcycle_double = int(vcycle_double)
         o.aggregation, o.vbm_theta = aggregation, vbm_theta
         o.setup_device = int(setup_device)
+        o.smoother, o.ainv_tau, o.invk_fill, o.invk_inv_fill = smoother, ainv_tau, invk_fill, invk_inv_fill
         o.build_fp32, o.use_graph, o.host_only = int(build_fp32), int(use_graph), int(host_only)
         rp, prp = _hptr(rowptr, np.int32)
         ci, pci = _hptr(col, np.int32)
@@ -183,7 +188,8 @@ class Hierarchy:
                     setup_seconds=s.setup_seconds, device_bytes=s.device_bytes,
                     coarse_sweeps=s.coarse_sweeps, sp_nnz=list(s.sp_nnz[:L]), dia_slots=list(s.dia_slots[:L]),
                     p_nnz=list(s.p_nnz[:L]), omega=list(s.omega[:L]), smoother_sweeps=s.smoother_sweeps,
-                    smoothed_prol=s.smoothed_prol, vcycle_double=s.vcycle_double, aggregation=s.aggregation)
+                    smoothed_prol=s.smoothed_prol, vcycle_double=s.vcycle_double, aggregation=s.aggregation,
+                    smoother=s.smoother, smoother_nnz=list(s.smoother_nnz[:L]))
 
     def export_level(self, l):
         inf = self.info()
@@ -207,6 +213,15 @@ class Hierarchy:
         _check(_lib.psc_hier_export_prolongator(self._h, l, rp.ctypes.data_as(C.c_void_p),
                                                 ci.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p)))
         return rp, ci, v
+
+    def export_smoother(self, l):
+        """(colptr, row, val, d): the AINV / INVK factor Z_l by columns and its pivots."""
+        inf = self.info()
+        n, nnz = inf["rows"][l], inf["smoother_nnz"][l]
+        zr, zi, zv, d = np.empty(n + 1, np.int64), np.empty(nnz, np.int32), np.empty(nnz), np.empty(n)
+        ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+        _check(_lib.psc_hier_export_smoother(self._h, l, ptr(zr), ptr(zi), ptr(zv), ptr(d)))
+        return zr, zi, zv, d
 
     def pcg(self, b, x, rtol=1e-6, maxit=1000):
         it, rr = C.c_int32(), C.c_double()

@@ -156,3 +156,49 @@ def test_tentative_prolongator_export_is_the_aggregate_map():
     assert h.info()["omega"][0] == 0.0
     with pytest.raises(psc.PscError):
         psc.Hierarchy(rp, c, v, host_only=True, smoother_sweeps=0)
+
+
+FAI = {
+    # name: (matrix, library options, oracle options)
+    "ainv_poisson12": (lambda: P.poisson7(12), dict(smoother=psc.SMOOTH_AINV), dict(smoother=oracle.SMOOTH_AINV)),
+    "ainv_tau003_diffusion10": (lambda: P.diffusion7(10, seed=1, az=100.0),
+                                dict(smoother=psc.SMOOTH_AINV, ainv_tau=0.03),
+                                dict(smoother=oracle.SMOOTH_AINV, ainv_tau=0.03)),
+    "invk_poisson12": (lambda: P.poisson7(12), dict(smoother=psc.SMOOTH_INVK), dict(smoother=oracle.SMOOTH_INVK)),
+    "invk12_random": (lambda: P.random_spd_csr(400, 4, density=0.01, maxrow=30),
+                      dict(smoother=psc.SMOOTH_INVK, invk_fill=1, invk_inv_fill=2, coarse_max=40),
+                      dict(smoother=oracle.SMOOTH_INVK, invk_fill=1, invk_inv_fill=2, coarse_max=40)),
+    "ainv_smoothed_prol": (lambda: P.poisson7(12), dict(smoother=psc.SMOOTH_AINV, smoothed_prol=True, sweeps=3),
+                           dict(smoother=oracle.SMOOTH_AINV, prol=1, sweeps=3)),
+}
+
+
+@pytest.mark.parametrize("case", list(FAI))
+def test_fai_factors_bit_identical_to_oracle(case):
+    mk, lo, oo = FAI[case]
+    rp, c, v = mk()
+    h = psc.Hierarchy(rp, c, v, host_only=True, **lo)
+    o = oracle.Hierarchy(rp, c, v, **oo)
+    inf = h.info()
+    assert inf["rows"] == o.sizes() and inf["smoother"] == lo["smoother"]
+    assert inf["levels"] >= 2
+    for l in range(inf["levels"] - 1):
+        zr, zi, zv, d = h.export_smoother(l)
+        ozr, ozi, ozv, od = o.fai(l)
+        assert np.array_equal(zr, ozr) and np.array_equal(zi, ozi)
+        assert np.array_equal(zv, ozv) and np.array_equal(d, od)
+        assert inf["smoother_nnz"][l] == len(zi)
+    with pytest.raises(psc.PscError):
+        h.export_smoother(inf["levels"] - 1)          # the coarsest level has no smoother
+
+
+def test_fai_options_validated():
+    rp, c, v = P.poisson7(6)
+    for kw in [dict(smoother=3), dict(smoother=psc.SMOOTH_AINV, ainv_tau=-0.5),
+               dict(smoother=psc.SMOOTH_INVK, invk_fill=65), dict(smoother=psc.SMOOTH_INVK, invk_inv_fill=-1)]:
+        with pytest.raises(psc.PscError) as e:
+            psc.Hierarchy(rp, c, v, host_only=True, **kw)
+        assert e.value.status == psc.ERR_ARG
+    h = psc.Hierarchy(rp, c, v, host_only=True)
+    with pytest.raises(psc.PscError):
+        h.export_smoother(0)                          # l1-Jacobi hierarchy: no factors
