@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _lib = None
 
 OK, NOCONV, ERR_ARG, ERR_NOT_SPD, ERR_NAN, ERR_OOM, ERR_COARSEN = 0, 1, -1, -2, -3, -5, -6
-SMOOTH_L1JACOBI, SMOOTH_AINV, SMOOTH_INVK = 0, 1, 2
+SMOOTH_L1JACOBI, SMOOTH_AINV, SMOOTH_INVK, SMOOTH_CHEB4 = 0, 1, 2, 3
 PREC_VCYCLE, PREC_NONE, PREC_L1JACOBI, PREC_JACOBI, PREC_VCYCLE32 = 0, 1, 2, 3, 4
 
 _i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
@@ -57,6 +57,8 @@ def lib():
     L.orc_match.restype = C.c_int
     L.orc_build.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                             C.c_int, C.c_int, C.c_double, C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(vp)]
+    L.orc_cheb4_apply.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, _f64p, _f64p]
+    L.orc_cheb4_apply.restype = None
     L.orc_fai_nnz.argtypes = [vp, C.c_int]
     L.orc_fai_nnz.restype = C.c_longlong
     L.orc_fai_get.argtypes = [vp, C.c_int, _i32p, _i32p, _f64p, _f64p]
@@ -147,6 +149,14 @@ def fai_factor(rowptr, col, val, kind, tau=0.1, fill1=0, fill2=1):
     finally:
         lib().orc_fai_single_free(S)
     return zr, zi, zv, d
+
+
+def cheb4_apply(rowptr, col, val, nu, b):
+    """Degree-nu fourth-kind Chebyshev smoother (l1-Jacobi preconditioned) from x = 0."""
+    rowptr, col, val, b = _i32(rowptr), _i32(col), _f64(val), _f64(b)
+    x = np.empty(len(b))
+    lib().orc_cheb4_apply(len(rowptr) - 1, rowptr, col, val, nu, b, x)
+    return x
 
 
 def edge_key(sij, sii, sjj):

@@ -21,6 +21,8 @@
  *   - AINV and INVK smoothers, G_l = Z D^-1 Z^T ~ A_l^-1 with Z unit upper
  *     triangular (incomplete A-biconjugation with a drop tolerance; inverse
  *     of an incomplete LDL^T factor with levels of fill): same section.
+ *   - A polynomial smoother (named as future work in the Conclusions): the
+ *     fourth-kind Chebyshev smoother on the l1-Jacobi preconditioned operator.
  *   - Conjugate gradient / flexible CG to a relative residual tolerance:
  *     Section "Numerical Example".
  * Readings where the paper is silent (edge weights, tie order, weight
@@ -636,7 +638,7 @@ typedef struct {
     int nu_double;       /* 1: variable V-cycle, nu_l = nu * 2^l (the paper's VMATCH) */
     int aggr;            /* 0: coupled matching aggregation, 1: decoupled VBM */
     double theta;        /* VBM strength threshold */
-    int smoother;        /* 0: l1-Jacobi, 1: AINV, 2: INVK (all levels above the coarsest) */
+    int smoother;        /* 0: l1-Jacobi, 1: AINV, 2: INVK, 3: Chebyshev polynomial (levels above the coarsest) */
     double tau;          /* AINV drop tolerance */
     int fill1, fill2;    /* INVK fill levels of the factor and of its inverse */
     orc_level lev[ORC_MAXLEV];
@@ -1003,7 +1005,7 @@ int orc_build(int n, const int *rp, const int *ci, const double *v,
     *out = NULL;
     if (n <= 0 || sweeps < 1 || max_levels < 1 || max_levels > ORC_MAXLEV || prol < 0 || prol > 1 ||
         nu < 1 || nu_double < 0 || nu_double > 1 || aggr < 0 || aggr > 1 || !(theta >= 0.0 && theta < 1.0) ||
-        smoother < 0 || smoother > 2 || !(tau >= 0.0) || fill1 < 0 || fill2 < 0)
+        smoother < 0 || smoother > 3 || !(tau >= 0.0) || fill1 < 0 || fill2 < 0)
         return ORC_ERR_ARG;
     orc_hier *h = calloc(1, sizeof(orc_hier));
     h->sweeps = sweeps;
@@ -1223,6 +1225,94 @@ static void coarse_solve(const orc_hier *h, const double *b, double *x) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Polynomial smoother (the paper names polynomial smoothers as GPU-friendly */
+/* future work without fixing one). Reading: the fourth-kind Chebyshev      */
+/* smoother of Lottes (2023, "Optimal polynomial smoothers for multigrid    */
+/* V-cycles") on the l1-Jacobi preconditioned operator M^-1 A, with the     */
+/* spectral bound rho = 1: A <= M holds for the l1 diagonal because M - A   */
+/* is diagonally dominant with a non-negative diagonal. Degree nu (= the    */
+/* sweep count) error propagation W_nu(I - 2 M^-1 A) / (2 nu + 1), W the    */
+/* Chebyshev polynomial of the fourth kind.                                 */
+/* ------------------------------------------------------------------------ */
+
+/* x <- x + q(M^-1 A) M^-1 (b - A x) by the three-term recurrence
+ *   r_0 = b - A x_0 (b when from_zero, x_0 = 0), d_0 = (4/3) M^-1 r_0,
+ *   x_k = x_{k-1} + d_{k-1}, r_k = r_{k-1} - A d_{k-1},
+ *   d_k = (2k-1)/(2k+3) d_{k-1} + (8k+4)/(2k+3) M^-1 r_k   (k = 1 .. nu-1),
+ *   x_nu = x_{nu-1} + d_{nu-1}.
+ * r, d, t: n-vectors of scratch. */
+static void cheb4_smooth(const orc_level *L, int nu, const double *b, double *x, int from_zero,
+                         double *r, double *d, double *t) {
+    const int n = L->A.n;
+    if (from_zero) {
+        for (int i = 0; i < n; i++) { x[i] = 0.0; r[i] = b[i]; }
+    } else {
+        orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, t);
+        for (int i = 0; i < n; i++) r[i] = b[i] - t[i];
+    }
+    for (int i = 0; i < n; i++) d[i] = (4.0 / 3.0) * L->minv[i] * r[i];
+    for (int k = 1; k < nu; k++) {
+        const double ak = (double)(2 * k - 1) / (double)(2 * k + 3);
+        const double bk = (double)(8 * k + 4) / (double)(2 * k + 3);
+        orc_spmv(n, L->A.rp, L->A.ci, L->A.v, d, t);
+        for (int i = 0; i < n; i++) {
+            x[i] += d[i];
+            r[i] -= t[i];
+            d[i] = ak * d[i] + bk * L->minv[i] * r[i];
+        }
+    }
+    for (int i = 0; i < n; i++) x[i] += d[i];
+}
+
+/* The same in float: level values rounded to float, coefficients computed
+ * in double and rounded to float. */
+static void cheb4_smooth32(const orc_level *L, int nu, const float *b, float *x, int from_zero,
+                           float *r, float *d, float *t) {
+    const int n = L->A.n;
+    if (from_zero) {
+        for (int i = 0; i < n; i++) { x[i] = 0.0f; r[i] = b[i]; }
+    } else {
+        for (int i = 0; i < n; i++) {
+            float s = 0.0f;
+            for (int q = L->A.rp[i]; q < L->A.rp[i + 1]; q++) s += (float)L->A.v[q] * x[L->A.ci[q]];
+            t[i] = s;
+        }
+        for (int i = 0; i < n; i++) r[i] = b[i] - t[i];
+    }
+    const float c0 = (float)(4.0 / 3.0);
+    for (int i = 0; i < n; i++) d[i] = c0 * (float)L->minv[i] * r[i];
+    for (int k = 1; k < nu; k++) {
+        const float ak = (float)((double)(2 * k - 1) / (double)(2 * k + 3));
+        const float bk = (float)((double)(8 * k + 4) / (double)(2 * k + 3));
+        for (int i = 0; i < n; i++) {
+            float s = 0.0f;
+            for (int q = L->A.rp[i]; q < L->A.rp[i + 1]; q++) s += (float)L->A.v[q] * d[L->A.ci[q]];
+            t[i] = s;
+        }
+        for (int i = 0; i < n; i++) {
+            x[i] += d[i];
+            r[i] -= t[i];
+            d[i] = ak * d[i] + bk * (float)L->minv[i] * r[i];
+        }
+    }
+    for (int i = 0; i < n; i++) x[i] += d[i];
+}
+
+/* The degree-nu smoother from x = 0 on one matrix, in FP64 (for the pins). */
+void orc_cheb4_apply(int n, const int *rp, const int *ci, const double *v, int nu, const double *b, double *x) {
+    orc_level L;
+    memset(&L, 0, sizeof(L));
+    csr_copy(n, rp, ci, v, &L.A);
+    L.minv = malloc(sizeof(double) * (size_t)n);
+    l1_diag_inv(&L.A, L.minv);
+    double *r = malloc(sizeof(double) * (size_t)n), *d = malloc(sizeof(double) * (size_t)n),
+           *t = malloc(sizeof(double) * (size_t)n);
+    cheb4_smooth(&L, nu, b, x, 1, r, d, t);
+    free(r); free(d); free(t); free(L.minv);
+    csr_free(&L.A);
+}
+
+/* ------------------------------------------------------------------------ */
 /* V-cycle (eq. amg, with nu sweeps): nu pre-sweeps from a zero guess,     */
 /* coarse correction, nu post-sweeps; coarsest level by coarse_solve.       */
 /* ------------------------------------------------------------------------ */
@@ -1248,14 +1338,19 @@ static void vcycle_level(const orc_hier *h, int l, const double *b, double *x) {
      * x += M^{-1} (b - A x); with AINV / INVK, M^{-1} is G = Z D^-1 Z^T */
     const int nu = level_sweeps(h, l);
     double *t = NULL, *y = NULL;
-    if (L->S.n) {
+    if (h->smoother == 3) {
+        /* polynomial smoother of degree nu from x = 0 (r, t, y as its scratch) */
+        t = malloc(sizeof(double) * (size_t)n);
+        y = malloc(sizeof(double) * (size_t)n);
+        cheb4_smooth(L, nu, b, x, 1, r, t, y);
+    } else if (L->S.n) {
         t = malloc(sizeof(double) * (size_t)n);
         y = malloc(sizeof(double) * (size_t)n);
         fai_apply(&L->S, b, x, y);
     } else {
         for (int i = 0; i < n; i++) x[i] = L->minv[i] * b[i];
     }
-    for (int k = 1; k < nu; k++) {
+    for (int k = 1; k < nu && h->smoother != 3; k++) {
         orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
         if (L->S.n) {
             for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
@@ -1279,8 +1374,10 @@ static void vcycle_level(const orc_hier *h, int l, const double *b, double *x) {
         for (int m = P->rp[i]; m < P->rp[i + 1]; m++) s += P->v[m] * xc[P->ci[m]];
         x[i] += s;
     }
-    /* nu_l post-smoothing sweeps x += M^{-1} (b - A x) */
-    for (int k = 0; k < nu; k++) {
+    /* nu_l post-smoothing sweeps x += M^{-1} (b - A x); the polynomial
+     * smoother of degree nu from the corrected x */
+    if (h->smoother == 3) cheb4_smooth(L, nu, b, x, 0, r, t, y);
+    for (int k = 0; k < nu && h->smoother != 3; k++) {
         orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
         if (L->S.n) {
             for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
@@ -1324,14 +1421,18 @@ static void vcycle32_level(const orc_hier *h, int l, const float *b, float *x) {
     float *xc = malloc(sizeof(float) * (size_t)nc);
     const int nu = level_sweeps(h, l);
     float *t = NULL, *y = NULL;
-    if (L->S.n) {
+    if (h->smoother == 3) {
+        t = malloc(sizeof(float) * (size_t)n);
+        y = malloc(sizeof(float) * (size_t)n);
+        cheb4_smooth32(L, nu, b, x, 1, r, t, y);
+    } else if (L->S.n) {
         t = malloc(sizeof(float) * (size_t)n);
         y = malloc(sizeof(float) * (size_t)n);
         fai_apply32(&L->S, b, x, y);
     } else {
         for (int i = 0; i < n; i++) x[i] = (float)L->minv[i] * b[i];
     }
-    for (int k = 1; k < nu; k++) {
+    for (int k = 1; k < nu && h->smoother != 3; k++) {
         for (int i = 0; i < n; i++) {
             float s = 0.0f;
             for (int q = L->A.rp[i]; q < L->A.rp[i + 1]; q++) s += (float)L->A.v[q] * x[L->A.ci[q]];
@@ -1359,7 +1460,8 @@ static void vcycle32_level(const orc_hier *h, int l, const float *b, float *x) {
         for (int m = P->rp[i]; m < P->rp[i + 1]; m++) s += (float)P->v[m] * xc[P->ci[m]];
         x[i] += s;
     }
-    for (int k = 0; k < nu; k++) {
+    if (h->smoother == 3) cheb4_smooth32(L, nu, b, x, 0, r, t, y);
+    for (int k = 0; k < nu && h->smoother != 3; k++) {
         for (int i = 0; i < n; i++) {
             float s = 0.0f;
             for (int q = L->A.rp[i]; q < L->A.rp[i + 1]; q++) s += (float)L->A.v[q] * x[L->A.ci[q]];
