@@ -240,6 +240,6 @@ def test_fai_smoothers_take_fewer_pcg_iterations(smoother):
 
 def test_fai_options_rejected():
     rp, c, v = P.poisson7(4)
-    for kw in [dict(smoother=3), dict(smoother=AINV, ainv_tau=-1.0), dict(smoother=INVK, invk_fill=-1)]:
+    for kw in [dict(smoother=4), dict(smoother=AINV, ainv_tau=-1.0), dict(smoother=INVK, invk_fill=-1)]:
         with pytest.raises(RuntimeError):
             oracle.Hierarchy(rp, c, v, **kw)
