@@ -121,7 +121,10 @@ def time_configs(args, psc, torch, rp, col, val, bd, x, ms64=None):
              "vbm": dict(aggregation=psc.AGGR_VBM, vbm_theta=0.01, smoothed_prol=True, smoother_sweeps=4),
              "ainv": dict(smoother=psc.SMOOTH_AINV, ainv_tau=0.1),
              "invk": dict(smoother=psc.SMOOTH_INVK, invk_fill=0, invk_inv_fill=1),
-             "invk00": dict(smoother=psc.SMOOTH_INVK, invk_fill=0, invk_inv_fill=0)}
+             "invk00": dict(smoother=psc.SMOOTH_INVK, invk_fill=0, invk_inv_fill=0),
+             "cheb1": dict(smoother=psc.SMOOTH_CHEB4, smoother_sweeps=1),
+             "cheb2": dict(smoother=psc.SMOOTH_CHEB4, smoother_sweeps=2),
+             "cheb3": dict(smoother=psc.SMOOTH_CHEB4, smoother_sweeps=3)}
     for cfg in [c for c in args.configs.split(",") if c]:
         t0 = time.time()
         hs = psc.Hierarchy(rp, col, val, build_fp32=not args.no_mixed, use_graph=not args.no_graph,
@@ -191,7 +194,8 @@ def main():
                          "vmatch (aggregates <= 8, tentative prolongator, 2 sweeps doubled per level), "
                          "vbm (strength-based aggregation, smoothed prolongator, 4 sweeps), "
                          "ainv (AINV smoother, drop tolerance 0.1), invk (INVK smoother, fill 0, inverse fill 1), "
-                         "invk00 (INVK, no inverse fill)")
+                         "invk00 (INVK, no inverse fill), cheb1/cheb2/cheb3 (fourth-kind Chebyshev "
+                         "polynomial smoother of degree 1/2/3)")
     ap.add_argument("--only-configs", action="store_true",
                     help="time only the --configs settings (no headline solve; one JSON line of their results)")
     ap.add_argument("--config-host-setup", action="store_true",

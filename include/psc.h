@@ -112,6 +112,14 @@ typedef struct psc_net  psc_net;    /* opaque: owns the learned preconditioner  
  *                    A, D^-1 Z^T and Z. The coarsest solve is unchanged. The
  *                    factors are built on the host (setup_device does not
  *                    apply to them); PSC_ERR_NOT_SPD on a non-positive pivot.
+ *                    PSC_SMOOTH_CHEB4: a polynomial smoother (polynomial
+ *                    smoothers are named as GPU-friendly future work in the
+ *                    Conclusions): the fourth-kind Chebyshev smoother of degree
+ *                    smoother_sweeps on the l1-Jacobi preconditioned operator
+ *                    M^-1 A with the bound 1 (A <= M for the l1 diagonal), so
+ *                    no eigenvalue estimate is needed; its error propagation is
+ *                    W_nu(I - 2 M^-1 A) / (2 nu + 1), W the Chebyshev polynomial
+ *                    of the fourth kind. Degree 1 is l1-Jacobi weighted 4/3.
  *   ainv_tau = 0.1   AINV drop tolerance (>= 0).
  *   invk_fill = 0, invk_inv_fill = 1   INVK levels of fill (0..64).
  *   host_only = 0    build the hierarchy on the host only and make no HIP
@@ -124,6 +132,7 @@ typedef struct psc_net  psc_net;    /* opaque: owns the learned preconditioner  
 #define PSC_SMOOTH_L1JACOBI 0
 #define PSC_SMOOTH_AINV 1
 #define PSC_SMOOTH_INVK 2
+#define PSC_SMOOTH_CHEB4 3
 
 typedef struct {
     int32_t sweeps;

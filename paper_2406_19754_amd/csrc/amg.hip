@@ -1301,6 +1301,82 @@ __global__ __launch_bounds__(WG) void k_fprol(Ell<T> P, const T* __restrict__ xc
     }
 }
 
+// ---------------------------------------------------------------------------
+// Polynomial smoother: the fourth-kind Chebyshev recurrence on M^-1 A with
+// the bound 1 (A <= M for the l1 diagonal). Step k (1-based) takes
+// (x, r, d) = (x_{k-1}, r_{k-1}, d_{k-1}) to
+//   r_k = r_{k-1} - A d_{k-1},  x_k = x_{k-1} + d_{k-1},
+//   d_k = a_k d_{k-1} + b_k M^-1 r_k,
+// with d_0 = c0 M^-1 r_0 formed on the fly for every gathered column in the
+// first step (FIRST: r_0 = sv, x_0 = xin or 0). fold: the last step of a
+// post-smoothing writes x_{k+1} = x_k + d_k to xout (with the partial sum of
+// xout * d when R.fin != FIN_NONE) and stores nothing else; otherwise r and x
+// are updated in place and d_k goes to dout (when not NULL).
+// ---------------------------------------------------------------------------
+template <typename M, typename TB, typename TX, bool FIRST, int GB = 4>
+__global__ __launch_bounds__(WG) void k_cheb(M A, const typename M::value_type* __restrict__ minv,
+                                             const TB* __restrict__ sv, const typename M::value_type* __restrict__ din,
+                                             const typename M::value_type* xin, typename M::value_type* r,
+                                             typename M::value_type* x, TX* xout,
+                                             typename M::value_type* __restrict__ dout, typename M::value_type c0,
+                                             typename M::value_type ak, typename M::value_type bk, int fold,
+                                             const double* __restrict__ d, Red R) {
+    using T = typename M::value_type;
+    if (skip_red(R)) return;
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    double s0 = 0.0;
+    for (long long sl = lo + w; sl < hi; sl += WG / 64) {
+        T ad;
+        if constexpr (FIRST) ad = mat_row<GB>(A, sl, lane, [&](int c) { return c0 * minv[c] * (T)sv[c]; });
+        else ad = mat_row<GB>(A, sl, lane, [&](int c) { return din[c]; });
+        const long long row = sl * SLICE + lane;
+        if (row < A.nrows) {
+            T dself, rprev, xprev;
+            if constexpr (FIRST) {
+                dself = c0 * minv[row] * (T)sv[row];
+                rprev = (T)sv[row];
+                xprev = xin ? xin[row] : T(0);
+            } else {
+                dself = din[row];
+                rprev = r[row];
+                xprev = x[row];
+            }
+            const T rk = rprev - ad;
+            const T xk = xprev + dself;
+            if (fold) {
+                const T xo = xk + (ak * dself + bk * minv[row] * rk);
+                xout[row] = (TX)xo;
+                if (d) s0 += (double)(TX)xo * d[row];
+            } else {
+                r[row] = rk;
+                x[row] = xk;
+                if (dout) dout[row] = ak * dself + bk * minv[row] * rk;
+            }
+        }
+    }
+    if (R.fin != FIN_NONE) block_partial(s0, 0.0, R.part);
+}
+
+// Degree-1 post-smoothing: xout = x + c0 M^-1 t (t = b - A x), with the
+// partial sum of xout * d when R.fin != FIN_NONE.
+template <typename T, typename TX>
+__global__ __launch_bounds__(WG) void k_cheb_fin(long long nslices, long long n, const T* __restrict__ x,
+                                                 const T* __restrict__ minv, const T* __restrict__ t, T c0,
+                                                 TX* xout, const double* __restrict__ d, Red R) {
+    if (skip_red(R)) return;
+    long long lo, hi;
+    chunk_range(nslices, lo, hi);
+    double s0 = 0.0;
+    for (long long i = lo * SLICE + threadIdx.x; i < hi * SLICE && i < n; i += WG) {
+        const T xo = x[i] + c0 * minv[i] * t[i];
+        xout[i] = (TX)xo;
+        if (d) s0 += (double)(TX)xo * d[i];
+    }
+    if (R.fin != FIN_NONE) block_partial(s0, 0.0, R.part);
+}
+
 // Fused-iteration residual update without pre-smoothing (the factored
 // smoothers start the V-cycle from r): r_new = r_old - alpha q, partial
 // ||r_new||^2 (same reduction layout as k_update_pre_s).
@@ -1380,6 +1456,8 @@ struct DevLevel {
     DevEll<double> Z, W, P;
     double *ft = nullptr, *fu = nullptr;
     float *ft32 = nullptr, *fu32 = nullptr;
+    double* fd = nullptr;                  // polynomial smoother: second direction buffer
+    float* fd32 = nullptr;
 };
 
 // Per-precision views of a level's vectors and operators.
@@ -1402,6 +1480,7 @@ struct LV<double> {
     static const double* pv(const DevLevel& V) { return V.pval; }
     static double* ft(DevLevel& V) { return V.ft; }
     static double* fu(DevLevel& V) { return V.fu; }
+    static double* fd(DevLevel& V) { return V.fd; }
     static Ell<double> Z(const DevLevel& V) { return V.Z.view(); }
     static Ell<double> W(const DevLevel& V) { return V.W.view(); }
     static Ell<double> P(const DevLevel& V) { return V.P.view(); }
@@ -1423,6 +1502,7 @@ struct LV<float> {
     static const float* pv(const DevLevel& V) { return V.pval32; }
     static float* ft(DevLevel& V) { return V.ft32; }
     static float* fu(DevLevel& V) { return V.fu32; }
+    static float* fd(DevLevel& V) { return V.fd32; }
     static Ell<float> Z(const DevLevel& V) { return V.Z.view32(); }
     static Ell<float> W(const DevLevel& V) { return V.W.view32(); }
     static Ell<float> P(const DevLevel& V) { return V.P.view32(); }
@@ -1467,6 +1547,7 @@ struct psc_hier {
     bool tail_dia = true;                 // the DIA setting the descriptors were built with
     int nu = 1;                           // l1-Jacobi sweeps before and after the coarse correction
     bool fai = false;                     // AINV / INVK smoother on the levels above the coarsest
+    bool cheb = false;                    // polynomial (fourth-kind Chebyshev) smoother
     std::vector<void*> allocs;
     int64_t device_bytes = 0;
     double setup_seconds = 0.0;
@@ -1564,6 +1645,17 @@ static std::vector<float> to32(const std::vector<double>& a) {
 static int upload_fai(psc_hier* h, DevLevel& D, const HostLevel& H, bool f32) {
     const HostFai& F = H.fai;
     const int64_t n = H.n;
+    int st;
+    if (h->cheb) {
+        // polynomial smoother: P and three work vectors per precision
+        if ((st = upload_ell(h, D.P, n, H.nc, H.prp.data(), H.pci.data(), H.pv.data(), f32))) return st;
+        for (double** q : {&D.ft, &D.fu, &D.fd})
+            if ((st = dalloc(h, (void**)q, n * sizeof(double)))) return st;
+        if (f32)
+            for (float** q : {&D.ft32, &D.fu32, &D.fd32})
+                if ((st = dalloc(h, (void**)q, n * sizeof(float)))) return st;
+        return PSC_OK;
+    }
     if ((int64_t)F.zr.size() != n + 1) return fail(PSC_ERR_STATE, "smoother factor missing on a level");
     const size_t nz = F.zi.size();
     std::vector<int32_t> wrp(n + 1), zrp(n + 1, 0), zci(nz);
@@ -1581,7 +1673,6 @@ static int upload_fai(psc_hier* h, DevLevel& D, const HostLevel& H, bool f32) {
             zci[o] = (int32_t)k;
             zv[o] = F.zv[e];
         }
-    int st;
     if ((st = upload_ell(h, D.W, n, n, wrp.data(), F.zi.data(), wv.data(), f32))) return st;
     if ((st = upload_ell(h, D.Z, n, n, zrp.data(), zci.data(), zv.data(), f32))) return st;
     if ((st = upload_ell(h, D.P, n, H.nc, H.prp.data(), H.pci.data(), H.pv.data(), f32))) return st;
@@ -1828,7 +1919,7 @@ static TailLevel<T> tail_level(const psc_hier* h, const DevLevel& V) {
 static int build_tail(psc_hier* h) {
     const int L = (int)h->lev.size();
     h->tail_t = 0;
-    if (L < 3 || h->host.coarse_sweeps > 0 || !h->split || h->opts.vcycle_double || h->nu != 1 || h->fai)
+    if (L < 3 || h->host.coarse_sweeps > 0 || !h->split || h->opts.vcycle_double || h->nu != 1 || h->fai || h->cheb)
         return PSC_OK;
     int t = L - 1;
     while (t - 1 >= 1 && h->lev[t - 1].n <= h->tail_rows) t--;
@@ -2066,6 +2157,121 @@ static void vcycle_fai(psc_hier* h, const double* r0, double* z0, const double* 
     }
 }
 
+// The V-cycle with the polynomial smoother in precision T: on each level
+// above the coarsest, nu recurrence steps from x = 0 (the last leaves r_nu for
+// the restriction); after x += P x_c and t = b - A x, nu more steps from x,
+// the last folded into the output (FP64 z0 with the fused dot at level 0).
+template <typename T>
+static void vcycle_cheb(psc_hier* h, const double* r0, double* z0, const double* d, const Red& R, Gate g) {
+    const int L = (int)h->lev.size();
+    Red R0 = R;
+    R0.fin = FIN_NONE;
+    hipStream_t st = h->stream;
+    const T c0 = (T)(4.0 / 3.0);
+    auto coef = [](int k, T& ak, T& bk) {
+        ak = (T)((double)(2 * k - 1) / (double)(2 * k + 3));
+        bk = (T)((double)(8 * k + 4) / (double)(2 * k + 3));
+    };
+    // one recurrence step on level V (FIRST: from r_0 = sv, x_0 = xin)
+    auto step = [&](DevLevel& V, bool first, auto sv, const T* din, const T* xin, auto xout, T* dout, int k,
+                    bool fold, const double* dd, const Red& Rs) {
+        using TB = std::remove_const_t<std::remove_pointer_t<decltype(sv)>>;
+        using TX = std::remove_pointer_t<decltype(xout)>;
+        T ak = T(0), bk = T(0);
+        if (fold || dout) coef(k, ak, bk);
+        const int gr = grid_ell(h, V.A.nslices);
+        const bool wa = wide_A(h, V);
+        T* r = LV<T>::r(V);
+        T* x = LV<T>::x(V);
+        const T* minv = LV<T>::minv(V);
+        with_A_t<T>(h, V, [&](auto A) {
+            using M = decltype(A);
+            if (first) {
+                if (wa) k_cheb<M, TB, TX, true, 8><<<gr, WG, 0, st>>>(A, minv, sv, din, xin, r, x, xout, dout, c0, ak, bk, fold, dd, Rs);
+                else k_cheb<M, TB, TX, true, 4><<<gr, WG, 0, st>>>(A, minv, sv, din, xin, r, x, xout, dout, c0, ak, bk, fold, dd, Rs);
+            } else {
+                if (wa) k_cheb<M, TB, TX, false, 8><<<gr, WG, 0, st>>>(A, minv, sv, din, xin, r, x, xout, dout, c0, ak, bk, fold, dd, Rs);
+                else k_cheb<M, TB, TX, false, 4><<<gr, WG, 0, st>>>(A, minv, sv, din, xin, r, x, xout, dout, c0, ak, bk, fold, dd, Rs);
+            }
+        });
+    };
+    for (int l = 0; l < L - 1; l++) {
+        DevLevel& V = h->lev[l];
+        TimeScope ts(h, l == 0 ? 2 : 7);
+        const int nu = V.nu;
+        T* da = LV<T>::fu(V);
+        T* db = LV<T>::fd(V);
+        auto pre = [&](auto b) {
+            step(V, true, b, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, nu > 1 ? da : (T*)nullptr, 1, false,
+                 nullptr, R0);
+            const T* cur = da;
+            for (int k = 2; k <= nu; k++) {
+                T* nxt = cur == da ? db : da;
+                step(V, false, (const T*)nullptr, cur, (const T*)nullptr, (T*)nullptr, k < nu ? nxt : (T*)nullptr, k,
+                     false, nullptr, R0);
+                cur = nxt;
+            }
+        };
+        if (l == 0) pre(r0);
+        else pre((const T*)LV<T>::b(V));
+        launch_spmv(h, LV<T>::R(V), (const T*)LV<T>::r(V), LV<T>::b(h->lev[l + 1]), g, V.R.wmax > 8);
+    }
+    {
+        DevLevel& C = h->lev[L - 1];
+        TimeScope ts(h, 7);
+        coarse_solve<T, T>(h, (const T*)LV<T>::b(C), LV<T>::x(C), g);
+    }
+    for (int l = L - 2; l >= 0; l--) {
+        DevLevel& V = h->lev[l];
+        TimeScope ts(h, l == 0 ? 4 : 7);
+        const int nu = V.nu;
+        T* x = LV<T>::x(V);
+        T* t = LV<T>::ft(V);
+        T* da = LV<T>::fu(V);
+        T* db = LV<T>::fd(V);
+        const int gr = grid_ell(h, V.A.nslices);
+        const int gp = grid_ell(h, V.P.nslices);
+        if (V.P.wmax > 8) k_fprol<T, 8><<<gp, WG, 0, st>>>(LV<T>::P(V), LV<T>::x(h->lev[l + 1]), x, g);
+        else k_fprol<T, 4><<<gp, WG, 0, st>>>(LV<T>::P(V), LV<T>::x(h->lev[l + 1]), x, g);
+        const bool wa = wide_A(h, V);
+        auto res = [&](auto b) {
+            using TB = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
+            with_A_t<T>(h, V, [&](auto A) {
+                using M = decltype(A);
+                if (wa) k_fres<M, TB, 8><<<gr, WG, 0, st>>>(A, b, x, t, g);
+                else k_fres<M, TB, 4><<<gr, WG, 0, st>>>(A, b, x, t, g);
+            });
+        };
+        if (l == 0) res(r0);
+        else res((const T*)LV<T>::b(V));
+        auto post = [&](auto out, const double* dd, const Red& Rz) {
+            using TX = std::remove_pointer_t<decltype(out)>;
+            if (nu == 1) {
+                k_cheb_fin<T, TX><<<gr, WG, 0, st>>>(V.A.nslices, V.n, x, LV<T>::minv(V), t, c0, out, dd, Rz);
+                return;
+            }
+            const T* cur = nullptr;
+            for (int k = 1; k <= nu - 1; k++) {
+                const bool fold = k == nu - 1;
+                T* nxt = cur == da ? db : da;
+                if (k == 1)
+                    step(V, true, (const T*)t, (const T*)nullptr, (const T*)x, out, fold ? (T*)nullptr : nxt, k, fold,
+                         fold ? dd : nullptr, fold ? Rz : R0);
+                else
+                    step(V, false, (const T*)nullptr, cur, (const T*)nullptr, out, fold ? (T*)nullptr : nxt, k, fold,
+                         fold ? dd : nullptr, fold ? Rz : R0);
+                cur = nxt;
+            }
+        };
+        if (l == 0) {
+            post(z0, d, R);
+            finish(h, R, gr);
+        } else {
+            post(x, nullptr, R0);
+        }
+    }
+}
+
 // z = B r on level 0. prec: PSC_FP64 / PSC_FP32. fin/d: optional fused dot
 // z.d at level 0 with finaliser fin. g gates every kernel (g.ctl == NULL:
 // standalone V-cycle, always runs, no fused dot).
@@ -2090,6 +2296,11 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
         // the factored smoothers start from r; no fused level-0 pre-smoothing
         if (prec == PSC_FP64) vcycle_fai<double>(h, r0, z0, d, R, g);
         else vcycle_fai<float>(h, r0, z0, d, R, g);
+        return;
+    }
+    if (h->cheb) {
+        if (prec == PSC_FP64) vcycle_cheb<double>(h, r0, z0, d, R, g);
+        else vcycle_cheb<float>(h, r0, z0, d, R, g);
         return;
     }
     if (prec == PSC_FP64) vcycle_t<double>(h, r0, z0, d, R, g, skip_pre0);
@@ -2166,7 +2377,7 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             finish(h, red_of(h, FIN_ALPHA_PCG), ge);
             {
                 TimeScope t(h, 2);
-                if (h->fai)
+                if (h->fai || h->cheb)
                     k_rupdate<<<ge, WG, 0, st>>>(L0.A.nslices, n, rold, h->q, rnew, red_of(h, FIN_UPDATE_PCG));
                 else if (h->split)
                     with_AM(h, L0, [&](auto AM) {
@@ -2210,7 +2421,7 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             finish(h, red_of(h, FIN_ALPHA_FCG), ge);
             {
                 TimeScope t(h, 2);
-                if (h->fai) {
+                if (h->fai || h->cheb) {
                     k_rupdate<<<ge, WG, 0, st>>>(L0.A.nslices, n, rold, h->q, rnew, red_of(h, FIN_UPDATE_FCG));
                 } else if (h->split) {
                     if (f32)
@@ -2242,8 +2453,8 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             finish(h, red_of(h, FIN_TRUE), gq);
             // after a residual replacement, redo the level-0 pre-smoothing from the true residual
             const Gate gr{h->ctl, GATE_REDO};
-            if (h->fai) {
-                // the factored smoothers have no fused pre-smoothing to redo
+            if (h->fai || h->cheb) {
+                // these smoothers have no fused pre-smoothing to redo
             } else if (f32) {
                 launch_pre(h, L0, (const double*)rnew, pre_rbuf<float>(h, L0, 1), gr, gq);
             } else {
@@ -2635,10 +2846,15 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     so.tau = h->opts.ainv_tau;
     so.fill1 = h->opts.invk_fill;
     so.fill2 = h->opts.invk_inv_fill;
-    if (so.smoother < 0 || so.smoother > 2 || !(so.tau >= 0.0) || so.fill1 < 0 || so.fill1 > 64 || so.fill2 < 0 ||
+    if (so.smoother < 0 || so.smoother > 3 || !(so.tau >= 0.0) || so.fill1 < 0 || so.fill1 > 64 || so.fill2 < 0 ||
         so.fill2 > 64)
-        return fail(PSC_ERR_ARG, "smoother must be 0..2, ainv_tau >= 0, INVK fill levels 0..64");
-    h->fai = so.smoother != 0;
+        return fail(PSC_ERR_ARG, "smoother must be 0..3, ainv_tau >= 0, INVK fill levels 0..64");
+    h->fai = so.smoother == PSC_SMOOTH_AINV || so.smoother == PSC_SMOOTH_INVK;
+    // The degree-1 polynomial smoother is l1-Jacobi weighted 4/3: it runs on
+    // the l1 path with the weight folded into M^-1 (and so into A M^-1 and
+    // (I - M^-1 A) P); higher degrees take the recurrence kernels.
+    const bool cheb1 = so.smoother == PSC_SMOOTH_CHEB4 && h->nu == 1 && !h->opts.vcycle_double;
+    h->cheb = so.smoother == PSC_SMOOTH_CHEB4 && !cheb1;
     if (h->opts.smoother_sweeps < 1 || h->opts.smoother_sweeps > 16 || h->opts.smoothed_prol < 0 ||
         h->opts.smoothed_prol > 1)
         return fail(PSC_ERR_ARG, "smoother_sweeps must be 1..16 and smoothed_prol 0 or 1");
@@ -2669,14 +2885,23 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
         D.nc = H.nc;
         D.nnz = H.rp[H.n];
         D.nu = h->opts.vcycle_double ? std::min(h->nu << std::min(l, 12), 4096) : h->nu;
+        // the smoother's inverse diagonal: M^-1, or (4/3) M^-1 for the degree-1
+        // polynomial smoother (never on the coarsest level, whose sweeps stay l1-Jacobi)
+        std::vector<double> wminv;
+        if (cheb1 && l < L - 1) {
+            wminv.resize(H.n);
+            const double c0 = 4.0 / 3.0;
+            for (int64_t i = 0; i < H.n; i++) wminv[i] = c0 * H.minv[i];
+        }
+        const std::vector<double>& mv = wminv.empty() ? H.minv : wminv;
         if (l < L - 1) {
-            if ((st = upload_ell(h.get(), D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32, H.minv.data(),
+            if ((st = upload_ell(h.get(), D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32, mv.data(),
                                  &D.am, &D.am32)))
                 return st;
         } else if ((st = upload_ell(h.get(), D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32))) {
             return st;
         }
-        if ((st = upload(h.get(), &D.minv, H.minv.data(), H.n))) return st;
+        if ((st = upload(h.get(), &D.minv, mv.data(), H.n))) return st;
         // hacked-DIA copy when it stores at most 4/3 of the ELL slots (8 instead
         // of 12 bytes per slot: at least 11 % fewer bytes); A M^-1 shares its layout
         std::vector<int32_t> dstart, doffs;
@@ -2705,7 +2930,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
                         for (int lane = 0; lane < SLICE; lane++) {
                             const int64_t c = sl * SLICE + lane + doffs[k];
                             double& x = dval[(size_t)k * SLICE + lane];
-                            if (c >= 0 && c < H.n) x = x * H.minv[c];
+                            if (c >= 0 && c < H.n) x = x * mv[c];
                         }
                 if ((st = upload(h.get(), &D.amd, dval.data(), dval.size()))) return st;
                 if (f32) {
@@ -2715,10 +2940,10 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
             }
         }
         if (f32) {
-            auto m32 = to32(H.minv);
+            auto m32 = to32(mv);
             if ((st = upload(h.get(), &D.minv32, m32.data(), m32.size()))) return st;
         }
-        if (l == 0 && h->fai && L > 1) {
+        if (l == 0 && (h->fai || h->cheb) && L > 1) {
             // the smoothed iterate of level 0 (the other levels keep it in x)
             if ((st = dalloc(h.get(), (void**)&D.x, H.n * sizeof(double)))) return st;
             if (f32 && (st = dalloc(h.get(), (void**)&D.x32, H.n * sizeof(float)))) return st;
@@ -2768,9 +2993,9 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
             // smoothed prolongator for the split post-smoothing sweep
             std::vector<int32_t> sprp, spci;
             std::vector<double> spv;
-            jacobi_smoothed_prolongator(H, sprp, spci, spv);
+            jacobi_smoothed_prolongator(H, mv.data(), sprp, spci, spv);
             if ((st = upload_ell(h.get(), D.SP, H.n, H.nc, sprp.data(), spci.data(), spv.data(), f32))) return st;
-            if (h->fai) {
+            if (h->fai || h->cheb) {
                 if ((st = upload_fai(h.get(), D, H, f32))) return st;
             }
         }
@@ -2880,6 +3105,18 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
                         Zr * 12 + 8 * Nc + 16 * N + nu * (res64 + w64 + z64);
                 vb32 += w32 + (z32 - 4 * N) + (nu - 1) * (res32 + w32 + z32) + res32 + Zr * 8 + 4 * N + 4 * Nc +
                         Zr * 8 + 4 * Nc + 8 * N + nu * (res32 + w32 + z32) + e0 * 4 * N * (2 * nu + 2);
+            } else if (h->cheb) {
+                // polynomial smoother: each recurrence step reads A and gathers the
+                // direction, reads and writes r and x, reads M^-1, writes d (48 N
+                // bytes of vectors in FP64); pre: nu steps; restriction; post:
+                // x += P x_c, t = b - A x, then nu - 1 steps (the last writes x
+                // once) or, for nu = 1, one vector pass
+                const double Zr = (double)h->host.lev[l].pci.size(), nu = D.nu;
+                const double st64 = Z * m64 + 48 * N, st32 = Z * m32 + 24 * N;
+                vb64 += nu * st64 + Zr * 12 + 8 * N + 8 * Nc + Zr * 12 + 8 * Nc + 16 * N + Z * m64 + 24 * N +
+                        (nu > 1 ? (nu - 1) * st64 : 32 * N);
+                vb32 += nu * st32 + Zr * 8 + 4 * N + 4 * Nc + Zr * 8 + 4 * Nc + 8 * N + Z * m32 + 12 * N +
+                        (nu > 1 ? (nu - 1) * st32 : 16 * N) + e0 * 12 * N;
             } else if (h->split) {
                 // pre sweep 1: A M^-1, b gathered, r written; sweeps 2..nu: A M^-1,
                 // s and r gathered, b read, s and r written; restriction: R

@@ -557,7 +557,7 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
                     const SetupOpts& o, HostHier& H, std::string& err) {
     if (o.sweeps < 1 || o.sweeps > 8 || o.coarse_max < 1 || o.max_levels < 1 ||
         o.max_levels > PSC_MAX_LEVELS || o.coarse_sweeps < 0 || o.coarse_sweeps > 1000 || o.aggr < 0 ||
-        o.aggr > 1 || !(o.theta >= 0.0 && o.theta < 1.0) || o.smoother < 0 || o.smoother > 2 ||
+        o.aggr > 1 || !(o.theta >= 0.0 && o.theta < 1.0) || o.smoother < 0 || o.smoother > 3 ||
         !(o.tau >= 0.0) || o.fill1 < 0 || o.fill1 > 64 || o.fill2 < 0 || o.fill2 > 64) {
         err = "invalid hierarchy options";
         return PSC_ERR_ARG;
@@ -727,7 +727,7 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
         F.v.swap(A.v);
     }
     // AINV / INVK smoothers of the levels above the coarsest
-    if (o.smoother != 0) {
+    if (o.smoother == 1 || o.smoother == 2) {
         for (size_t l = 0; l + 1 < H.lev.size(); l++) {
             HostLevel& F = H.lev[l];
             const int st = o.smoother == 1
@@ -746,8 +746,8 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
 // columns: with (A P)_iJ from spgemm (ascending j, then row j of P),
 //   sp_iJ = P_iJ - minv_i (A P)_iJ
 // (the columns of row i of P are among those of row i of A P: a_ii is stored).
-void jacobi_smoothed_prolongator(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
-                                 std::vector<double>& v) {
+void jacobi_smoothed_prolongator(const HostLevel& H, const double* minv, std::vector<int32_t>& rp,
+                                 std::vector<int32_t>& ci, std::vector<double>& v) {
     Csr T;
     spgemm_raw(H.n, H.rp.data(), H.ci.data(), H.v.data(), H.prp.data(), H.pci.data(), H.pv.data(), T);
 #pragma omp parallel for schedule(static)
@@ -756,7 +756,7 @@ void jacobi_smoothed_prolongator(const HostLevel& H, std::vector<int32_t>& rp, s
         for (int32_t k = T.rp[i]; k < T.rp[i + 1]; k++) {
             double pk = 0.0;
             if (m < H.prp[i + 1] && H.pci[m] == T.ci[k]) pk = H.pv[m++];
-            T.v[k] = pk - H.minv[i] * T.v[k];
+            T.v[k] = pk - minv[i] * T.v[k];
         }
     }
     rp.swap(T.rp);

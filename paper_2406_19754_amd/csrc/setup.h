@@ -50,7 +50,7 @@ struct SetupOpts {
     int aggr = 0;               // 0 coupled matching, 1 decoupled VBM
     double theta = 0.01;        // VBM strength threshold
     bool device = false;        // coarsen matching / tentative levels on the GPU
-    int smoother = 0;           // 0 l1-Jacobi, 1 AINV, 2 INVK (levels above the coarsest)
+    int smoother = 0;           // 0 l1-Jacobi, 1 AINV, 2 INVK, 3 polynomial (levels above the coarsest)
     double tau = 0.1;           // AINV drop tolerance
     int fill1 = 0, fill2 = 1;   // INVK fill levels of the factor and of its inverse
 };
@@ -67,10 +67,11 @@ int build_ainv(int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
 int build_invk(int64_t n, const int32_t* rp, const int32_t* ci, const double* v, int fill1, int fill2,
                HostFai& F, std::string& err);
 
-// S P = (I - M_l^-1 A_l) P_l, the level's prolongator after one l1-Jacobi
-// sweep (rows of A_l, aggregate columns), CSR with ascending columns.
-void jacobi_smoothed_prolongator(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
-                                 std::vector<double>& v);
+// S P = (I - M_l^-1 A_l) P_l, the level's prolongator after one (weighted)
+// l1-Jacobi sweep with the inverse diagonal minv (rows of A_l, aggregate
+// columns), CSR with ascending columns.
+void jacobi_smoothed_prolongator(const HostLevel& H, const double* minv, std::vector<int32_t>& rp,
+                                 std::vector<int32_t>& ci, std::vector<double>& v);
 
 // One level's coarsening on the GPU (matching aggregation, tentative
 // prolongator): aggregates, p, the next sample vector and the Galerkin

@@ -21,7 +21,7 @@ ERR_ARG, ERR_NOT_SPD, ERR_NAN, ERR_HIP, ERR_OOM, ERR_COARSEN, ERR_STATE = -1, -2
 FP64, FP32 = 0, 1
 TUNE_GRID_MAX, TUNE_FUSED_PCG, TUNE_UNROLL4, TUNE_BUFLOAD, TUNE_SPMV2, TUNE_SPLIT, TUNE_DIA, TUNE_TAIL = 1, 2, 3, 4, 5, 6, 7, 8
 AGGR_MATCHING, AGGR_VBM = 0, 1
-SMOOTH_L1JACOBI, SMOOTH_AINV, SMOOTH_INVK = 0, 1, 2
+SMOOTH_L1JACOBI, SMOOTH_AINV, SMOOTH_INVK, SMOOTH_CHEB4 = 0, 1, 2, 3
 MAX_LEVELS = 32
 TIMING_KERNELS = 8
 TIMING_NAMES = ["spmv_dot", "cg_update", "pre_smooth_l0", "restrict_l0", "post_smooth_l0",

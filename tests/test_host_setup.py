@@ -194,7 +194,7 @@ def test_fai_factors_bit_identical_to_oracle(case):
 
 def test_fai_options_validated():
     rp, c, v = P.poisson7(6)
-    for kw in [dict(smoother=3), dict(smoother=psc.SMOOTH_AINV, ainv_tau=-0.5),
+    for kw in [dict(smoother=4), dict(smoother=psc.SMOOTH_AINV, ainv_tau=-0.5),
                dict(smoother=psc.SMOOTH_INVK, invk_fill=65), dict(smoother=psc.SMOOTH_INVK, invk_inv_fill=-1)]:
         with pytest.raises(psc.PscError) as e:
             psc.Hierarchy(rp, c, v, host_only=True, **kw)
