@@ -2853,7 +2853,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     // The degree-1 polynomial smoother is l1-Jacobi weighted 4/3: it runs on
     // the l1 path with the weight folded into M^-1 (and so into A M^-1 and
     // (I - M^-1 A) P); higher degrees take the recurrence kernels.
-    const bool cheb1 = so.smoother == PSC_SMOOTH_CHEB4 && h->nu == 1 && !h->opts.vcycle_double;
+    const bool cheb1 = so.smoother == PSC_SMOOTH_CHEB4 && h->opts.smoother_sweeps == 1 && !h->opts.vcycle_double;
     h->cheb = so.smoother == PSC_SMOOTH_CHEB4 && !cheb1;
     if (h->opts.smoother_sweeps < 1 || h->opts.smoother_sweeps > 16 || h->opts.smoothed_prol < 0 ||
         h->opts.smoothed_prol > 1)
