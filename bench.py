@@ -198,6 +198,9 @@ def main():
                          "polynomial smoother of degree 1/2/3)")
     ap.add_argument("--only-configs", action="store_true",
                     help="time only the --configs settings (no headline solve; one JSON line of their results)")
+    ap.add_argument("--rebuild-timing", action="store_true",
+                    help="time a numeric-only rebuild (new coefficients on the same pattern) against the full "
+                         "build, then solve with the rebuilt hierarchy (one JSON line)")
     ap.add_argument("--config-host-setup", action="store_true",
                     help="build the --configs hierarchies with the host setup only")
     ap.add_argument("--no-split", action="store_true",
@@ -232,6 +235,40 @@ def main():
     t0 = time.time()
     rp, col, val, xt, b, desc = problem(args.workload, n, args.az)
     log(f"problem {desc} built in {time.time() - t0:.1f}s")
+    if args.rebuild_timing:
+        t0 = time.time()
+        h = psc.Hierarchy(rp, col, val, build_fp32=not args.no_mixed)
+        build_s = time.time() - t0
+        log(f"hierarchy built in {build_s:.2f}s")
+        # new coefficients on the same pattern: the operator scaled row and
+        # column by a smooth positive field (s_i a_ij s_j stays SPD)
+        sc = 1.0 + 0.5 * np.sin(np.arange(N) * (2 * np.pi / n))
+        rows = np.repeat(np.arange(N), np.diff(rp))
+        val2 = sc[rows] * val * sc[col]
+        t0 = time.time()
+        h.rebuild(val2)
+        rebuild_s = time.time() - t0
+        log(f"numeric rebuild in {rebuild_s:.2f}s ({build_s / rebuild_s:.1f}x faster than the build)")
+        import scipy.sparse as sps
+        A2 = sps.csr_matrix((val2, col, rp), shape=(N, N))
+        bb = A2 @ xt
+        bd = torch.from_numpy(bb).cuda()
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            x.zero_()
+            h.pcg(bd, x)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            x.zero_()
+            r = h.pcg(bd, x)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / args.steps
+        log(f"pcg on the rebuilt hierarchy: {ms:.2f} ms/solve, {r['iters']} its, relres {r['relres']:.2e}")
+        print(json.dumps({"mode": "rebuild", "workload": desc, "build_s": build_s, "rebuild_s": rebuild_s,
+                          "rebuild_seconds_lib": h.info()["rebuild_seconds"], "pcg_ms": ms, "iters": r["iters"],
+                          "relres": r["relres"]}))
+        return
     if args.only_configs:
         bd = torch.from_numpy(b).cuda()
         x = torch.zeros(N, dtype=torch.float64, device="cuda")

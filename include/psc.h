@@ -184,6 +184,27 @@ int psc_amg_build(int32_t n, const int32_t* rowptr_host, const int32_t* col_host
                   psc_hier** out);
 
 /*
+ * Numeric-only rebuild: replace the values of A (same n, rowptr and col as
+ * at psc_amg_build; val_host holds rowptr[n] FP64 values) and recompute
+ * everything that depends on them -- l1 diagonals, smoothed prolongators,
+ * Galerkin operators A_{l+1} = P_l^T A_l P_l, the coarsest factor, AINV /
+ * INVK factors -- while keeping the aggregates, the prolongator patterns and
+ * the level structure, so no matching runs (Section "GPU support": the
+ * toolkit updates the coefficients of an existing matrix whose structure is
+ * preserved, and splits the AMG build so that parts of it can be redone on
+ * an assembled hierarchy, because building is mostly host-side). The result is
+ * the hierarchy a build would give if it reached the same aggregates. Device
+ * copies are refreshed and captured iterations dropped; the handle's
+ * options, stream and workspace stay. Not thread-safe with work in flight on
+ * the handle (the call synchronizes its stream first).
+ * Errors: PSC_ERR_ARG (NULL), PSC_ERR_NOT_SPD (a diagonal <= 0 or a
+ * Cholesky / incomplete-factorisation breakdown), PSC_ERR_HIP, PSC_ERR_OOM.
+ * After an error the handle refuses solves and applies (PSC_ERR_STATE) until
+ * a rebuild succeeds.
+ */
+int psc_amg_rebuild(psc_hier* h, const double* val_host);
+
+/*
  * Preconditioned conjugate gradient with the FP64 V-cycle (one l1-Jacobi
  * pre- and post-sweep, coarsest solve as chosen at build; Section "AMG4PSBLAS",
  * eq. (amg)) as the preconditioner. Stops when the recursive residual
@@ -249,6 +270,7 @@ typedef struct {
     int32_t aggregation;
     int32_t smoother;
     int64_t smoother_nnz[PSC_MAX_LEVELS];    /* AINV / INVK: nonzeros of Z_l (0 otherwise) */
+    double  rebuild_seconds;                 /* wall time of the last psc_amg_rebuild (0: none) */
 } psc_hier_stats;
 
 int psc_hier_info(const psc_hier* h, psc_hier_stats* s);

@@ -1549,8 +1549,13 @@ struct psc_hier {
     bool fai = false;                     // AINV / INVK smoother on the levels above the coarsest
     bool cheb = false;                    // polynomial (fourth-kind Chebyshev) smoother
     std::vector<void*> allocs;
+    std::vector<void*> lev_allocs;        // per-level device data (released by a numeric rebuild)
+    int64_t lev_bytes = 0;
+    bool lev_phase = false;               // dalloc records into lev_allocs
     int64_t device_bytes = 0;
     double setup_seconds = 0.0;
+    double rebuild_seconds = 0.0;         // last numeric rebuild
+    bool stale = false;                   // a numeric rebuild failed: solves refused until one succeeds
     int gmax = psc::GMAX;                 // workgroup cap of the streaming kernels
     // captured iterations, one per (form, network, network generation)
     std::vector<psc::GraphEntry> graphs;
@@ -1570,7 +1575,8 @@ static int dalloc(psc_hier* h, void** p, size_t bytes) {
     if (bytes == 0) bytes = 64;
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) return fail(PSC_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-    h->allocs.push_back(*p);
+    (h->lev_phase ? h->lev_allocs : h->allocs).push_back(*p);
+    if (h->lev_phase) h->lev_bytes += (int64_t)bytes;
     h->device_bytes += (int64_t)bytes;
     return PSC_OK;
 }
@@ -2692,6 +2698,7 @@ static int solve(psc_hier* h, int form, psc_net* net, const double* b_dev, doubl
                  int32_t maxit, int32_t* iters, double* relres, int32_t* fallbacks) {
     if (!h) return fail(PSC_ERR_ARG, "NULL handle");
     if (!h->ctl) return fail(PSC_ERR_STATE, "hierarchy was built host-only");
+    if (h->stale) return fail(PSC_ERR_STATE, "the last numeric rebuild failed");
     HIPCHK(hipSetDevice(h->device));
     int st = join_in(h);
     if (st) return st;
@@ -2767,6 +2774,174 @@ static int pairs_impl(psc_hier* h, const double* b_dev, int nx, int ny, int nz, 
     return PSC_OK;
 }
 
+// Host setup options of a handle.
+static SetupOpts setup_opts_of(const psc_hier* h) {
+    SetupOpts so;
+    so.sweeps = h->opts.sweeps;
+    so.coarse_max = h->opts.coarse_max;
+    so.max_levels = h->opts.max_levels;
+    so.coarse_sweeps = h->opts.coarse_sweeps;
+    so.prol = h->opts.smoothed_prol;
+    so.aggr = h->opts.aggregation;
+    so.theta = h->opts.vbm_theta;
+    so.device = h->opts.setup_device != 0 && !h->opts.host_only;
+    so.smoother = h->opts.smoother;
+    so.tau = h->opts.ainv_tau;
+    so.fill1 = h->opts.invk_fill;
+    so.fill2 = h->opts.invk_inv_fill;
+    return so;
+}
+
+// Device copies of every level (operators, split operators, DIA copies,
+// smoother data, level vectors) and of the coarsest solve, from the host
+// hierarchy. Allocations go to h->lev_allocs so that a numeric rebuild can
+// release and redo them.
+static int upload_levels(psc_hier* h) {
+    const bool f32 = h->has32;
+    const int L = (int)h->host.lev.size();
+    const bool cheb1 = h->opts.smoother == PSC_SMOOTH_CHEB4 && !h->cheb;
+    h->lev.assign(L, DevLevel{});
+    h->coarse_invT = nullptr;
+    h->lev_phase = true;
+    struct PhaseEnd {
+        psc_hier* h;
+        ~PhaseEnd() { h->lev_phase = false; }
+    } phase_end{h};
+    int st = PSC_OK;
+    for (int l = 0; l < L; l++) {
+        HostLevel& H = h->host.lev[l];
+        DevLevel& D = h->lev[l];
+        D.n = H.n;
+        D.nc = H.nc;
+        D.nnz = H.rp[H.n];
+        D.nu = h->opts.vcycle_double ? std::min(h->nu << std::min(l, 12), 4096) : h->nu;
+        // the smoother's inverse diagonal: M^-1, or (4/3) M^-1 for the degree-1
+        // polynomial smoother (never on the coarsest level, whose sweeps stay l1-Jacobi)
+        std::vector<double> wminv;
+        if (cheb1 && l < L - 1) {
+            wminv.resize(H.n);
+            const double c0 = 4.0 / 3.0;
+            for (int64_t i = 0; i < H.n; i++) wminv[i] = c0 * H.minv[i];
+        }
+        const std::vector<double>& mv = wminv.empty() ? H.minv : wminv;
+        if (l < L - 1) {
+            if ((st = upload_ell(h, D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32, mv.data(),
+                                 &D.am, &D.am32)))
+                return st;
+        } else if ((st = upload_ell(h, D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32))) {
+            return st;
+        }
+        if ((st = upload(h, &D.minv, mv.data(), H.n))) return st;
+        // hacked-DIA copy when it stores at most 4/3 of the ELL slots (8 instead
+        // of 12 bytes per slot: at least 11 % fewer bytes); A M^-1 shares its layout
+        std::vector<int32_t> dstart, doffs;
+        std::vector<double> dval;
+        if (pack_dia(H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), D.A.slots * 4 / 3, dstart, doffs, dval)) {
+            DevDia& G = D.Ad;
+            G.nrows = H.n;
+            G.ncols = H.n;
+            G.nslices = (long long)dstart.size() - 1;
+            G.slots = (long long)dval.size();
+            for (size_t q = 0; q + 1 < dstart.size(); q++) G.ndmax = std::max(G.ndmax, dstart[q + 1] - dstart[q]);
+            if ((st = upload(h, &G.start, dstart.data(), dstart.size()))) return st;
+            if ((st = upload(h, &G.offs, doffs.data(), doffs.size()))) return st;
+            if ((st = upload(h, &G.val, dval.data(), dval.size()))) return st;
+            if (f32) {
+                auto v32 = to32(dval);
+                if ((st = upload(h, &G.val32, v32.data(), v32.size()))) return st;
+            }
+            if (l < L - 1) {
+                // A M^-1 in place: a_ij minv_j on every stored diagonal slot
+                // (slots outside the matrix hold 0 and stay 0)
+                const int64_t ns = (int64_t)dstart.size() - 1;
+#pragma omp parallel for schedule(static)
+                for (int64_t sl = 0; sl < ns; sl++)
+                    for (int32_t k = dstart[sl]; k < dstart[sl + 1]; k++)
+                        for (int lane = 0; lane < SLICE; lane++) {
+                            const int64_t c = sl * SLICE + lane + doffs[k];
+                            double& x = dval[(size_t)k * SLICE + lane];
+                            if (c >= 0 && c < H.n) x = x * mv[c];
+                        }
+                if ((st = upload(h, &D.amd, dval.data(), dval.size()))) return st;
+                if (f32) {
+                    auto s32 = to32(dval);
+                    if ((st = upload(h, &D.amd32, s32.data(), s32.size()))) return st;
+                }
+            }
+        }
+        if (f32) {
+            auto m32 = to32(mv);
+            if ((st = upload(h, &D.minv32, m32.data(), m32.size()))) return st;
+        }
+        if (l == 0 && (h->fai || h->cheb) && L > 1) {
+            // the smoothed iterate of level 0 (the other levels keep it in x)
+            if ((st = dalloc(h, (void**)&D.x, H.n * sizeof(double)))) return st;
+            if (f32 && (st = dalloc(h, (void**)&D.x32, H.n * sizeof(float)))) return st;
+        }
+        if (l > 0) {
+            if ((st = dalloc(h, (void**)&D.b, H.n * sizeof(double)))) return st;
+            if ((st = dalloc(h, (void**)&D.x, H.n * sizeof(double)))) return st;
+            if (f32) {
+                if ((st = dalloc(h, (void**)&D.b32, H.n * sizeof(float)))) return st;
+                if ((st = dalloc(h, (void**)&D.x32, H.n * sizeof(float)))) return st;
+            }
+        }
+        if (l == L - 1 && l > 0 && h->host.coarse_sweeps > 0) {
+            if ((st = dalloc(h, (void**)&D.r, H.n * sizeof(double)))) return st;
+        }
+        if (l < L - 1 && D.nu > 1) {
+            for (double** q : {&D.rb, &D.s, &D.sb, &D.xt, &D.xt2})
+                if ((st = dalloc(h, (void**)q, H.n * sizeof(double)))) return st;
+            if (f32)
+                for (float** q : {&D.rb32, &D.s32, &D.sb32, &D.xt32, &D.xt232})
+                    if ((st = dalloc(h, (void**)q, H.n * sizeof(float)))) return st;
+        }
+        if (l < L - 1) {
+            if ((st = dalloc(h, (void**)&D.r, H.n * sizeof(double)))) return st;
+            if (f32 && (st = dalloc(h, (void**)&D.r32, H.n * sizeof(float)))) return st;
+            if ((st = upload(h, &D.agg, H.agg.data(), H.n))) return st;
+            if ((st = upload(h, &D.pval, H.p.data(), H.n))) return st;
+            if (f32) {
+                auto p32 = to32(H.p);
+                if ((st = upload(h, &D.pval32, p32.data(), p32.size()))) return st;
+            }
+            // R = P^T as CSR over coarse rows: fine rows ascending
+            const size_t pn = H.pci.size();
+            std::vector<int32_t> rrp(H.nc + 1, 0), rci(pn);
+            std::vector<double> rv(pn);
+            for (size_t m = 0; m < pn; m++) rrp[H.pci[m] + 1]++;
+            for (int64_t I = 0; I < H.nc; I++) rrp[I + 1] += rrp[I];
+            std::vector<int32_t> pos(rrp.begin(), rrp.end() - 1);
+            for (int64_t i = 0; i < H.n; i++) {
+                for (int32_t m = H.prp[i]; m < H.prp[i + 1]; m++) {
+                    int32_t o = pos[H.pci[m]]++;
+                    rci[o] = (int32_t)i;
+                    rv[o] = H.pv[m];
+                }
+            }
+            if ((st = upload_ell(h, D.R, H.nc, H.n, rrp.data(), rci.data(), rv.data(), f32))) return st;
+            // smoothed prolongator for the split post-smoothing sweep
+            std::vector<int32_t> sprp, spci;
+            std::vector<double> spv;
+            jacobi_smoothed_prolongator(H, mv.data(), sprp, spci, spv);
+            if ((st = upload_ell(h, D.SP, H.n, H.nc, sprp.data(), spci.data(), spv.data(), f32))) return st;
+            if (h->fai || h->cheb) {
+                if ((st = upload_fai(h, D, H, f32))) return st;
+            }
+        }
+    }
+    // coarsest inverse, stored transposed for coalesced reads
+    h->coarse_n = (int)h->host.lev[L - 1].n;
+    if (h->host.coarse_sweeps == 0) {
+        int nc = h->coarse_n;
+        std::vector<double> invT((size_t)nc * nc);
+        for (int i = 0; i < nc; i++)
+            for (int k = 0; k < nc; k++) invT[(size_t)k * nc + i] = h->host.coarse_inv[(size_t)i * nc + k];
+        if ((st = upload(h, &h->coarse_invT, invT.data(), invT.size()))) return st;
+    }
+    return PSC_OK;
+}
+
 }  // namespace psc
 
 using namespace psc;
@@ -2811,6 +2986,7 @@ void psc_hier_free(psc_hier* h) {
         if (e) (void)hipEventDestroy(e);
     if (h->stream) (void)hipStreamDestroy(h->stream);
     for (void* p : h->allocs) (void)hipFree(p);
+    for (void* p : h->lev_allocs) (void)hipFree(p);
     if (h->hctl) (void)hipHostFree(h->hctl);
     delete h;
 }
@@ -2833,19 +3009,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
         for (auto& e : h->ev_join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         HIPCHK(hipStreamSynchronize(h->user_stream));
     }
-    SetupOpts so;
-    so.sweeps = h->opts.sweeps;
-    so.coarse_max = h->opts.coarse_max;
-    so.max_levels = h->opts.max_levels;
-    so.coarse_sweeps = h->opts.coarse_sweeps;
-    so.prol = h->opts.smoothed_prol;
-    so.aggr = h->opts.aggregation;
-    so.theta = h->opts.vbm_theta;
-    so.device = h->opts.setup_device != 0 && !h->opts.host_only;
-    so.smoother = h->opts.smoother;
-    so.tau = h->opts.ainv_tau;
-    so.fill1 = h->opts.invk_fill;
-    so.fill2 = h->opts.invk_inv_fill;
+    SetupOpts so = setup_opts_of(h.get());
     if (so.smoother < 0 || so.smoother > 3 || !(so.tau >= 0.0) || so.fill1 < 0 || so.fill1 > 64 || so.fill2 < 0 ||
         so.fill2 > 64)
         return fail(PSC_ERR_ARG, "smoother must be 0..3, ainv_tau >= 0, INVK fill levels 0..64");
@@ -2878,137 +3042,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
         *out = h.release();
         return PSC_OK;
     }
-    for (int l = 0; l < L; l++) {
-        HostLevel& H = h->host.lev[l];
-        DevLevel& D = h->lev[l];
-        D.n = H.n;
-        D.nc = H.nc;
-        D.nnz = H.rp[H.n];
-        D.nu = h->opts.vcycle_double ? std::min(h->nu << std::min(l, 12), 4096) : h->nu;
-        // the smoother's inverse diagonal: M^-1, or (4/3) M^-1 for the degree-1
-        // polynomial smoother (never on the coarsest level, whose sweeps stay l1-Jacobi)
-        std::vector<double> wminv;
-        if (cheb1 && l < L - 1) {
-            wminv.resize(H.n);
-            const double c0 = 4.0 / 3.0;
-            for (int64_t i = 0; i < H.n; i++) wminv[i] = c0 * H.minv[i];
-        }
-        const std::vector<double>& mv = wminv.empty() ? H.minv : wminv;
-        if (l < L - 1) {
-            if ((st = upload_ell(h.get(), D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32, mv.data(),
-                                 &D.am, &D.am32)))
-                return st;
-        } else if ((st = upload_ell(h.get(), D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32))) {
-            return st;
-        }
-        if ((st = upload(h.get(), &D.minv, mv.data(), H.n))) return st;
-        // hacked-DIA copy when it stores at most 4/3 of the ELL slots (8 instead
-        // of 12 bytes per slot: at least 11 % fewer bytes); A M^-1 shares its layout
-        std::vector<int32_t> dstart, doffs;
-        std::vector<double> dval;
-        if (pack_dia(H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), D.A.slots * 4 / 3, dstart, doffs, dval)) {
-            DevDia& G = D.Ad;
-            G.nrows = H.n;
-            G.ncols = H.n;
-            G.nslices = (long long)dstart.size() - 1;
-            G.slots = (long long)dval.size();
-            for (size_t q = 0; q + 1 < dstart.size(); q++) G.ndmax = std::max(G.ndmax, dstart[q + 1] - dstart[q]);
-            if ((st = upload(h.get(), &G.start, dstart.data(), dstart.size()))) return st;
-            if ((st = upload(h.get(), &G.offs, doffs.data(), doffs.size()))) return st;
-            if ((st = upload(h.get(), &G.val, dval.data(), dval.size()))) return st;
-            if (f32) {
-                auto v32 = to32(dval);
-                if ((st = upload(h.get(), &G.val32, v32.data(), v32.size()))) return st;
-            }
-            if (l < L - 1) {
-                // A M^-1 in place: a_ij minv_j on every stored diagonal slot
-                // (slots outside the matrix hold 0 and stay 0)
-                const int64_t ns = (int64_t)dstart.size() - 1;
-#pragma omp parallel for schedule(static)
-                for (int64_t sl = 0; sl < ns; sl++)
-                    for (int32_t k = dstart[sl]; k < dstart[sl + 1]; k++)
-                        for (int lane = 0; lane < SLICE; lane++) {
-                            const int64_t c = sl * SLICE + lane + doffs[k];
-                            double& x = dval[(size_t)k * SLICE + lane];
-                            if (c >= 0 && c < H.n) x = x * mv[c];
-                        }
-                if ((st = upload(h.get(), &D.amd, dval.data(), dval.size()))) return st;
-                if (f32) {
-                    auto s32 = to32(dval);
-                    if ((st = upload(h.get(), &D.amd32, s32.data(), s32.size()))) return st;
-                }
-            }
-        }
-        if (f32) {
-            auto m32 = to32(mv);
-            if ((st = upload(h.get(), &D.minv32, m32.data(), m32.size()))) return st;
-        }
-        if (l == 0 && (h->fai || h->cheb) && L > 1) {
-            // the smoothed iterate of level 0 (the other levels keep it in x)
-            if ((st = dalloc(h.get(), (void**)&D.x, H.n * sizeof(double)))) return st;
-            if (f32 && (st = dalloc(h.get(), (void**)&D.x32, H.n * sizeof(float)))) return st;
-        }
-        if (l > 0) {
-            if ((st = dalloc(h.get(), (void**)&D.b, H.n * sizeof(double)))) return st;
-            if ((st = dalloc(h.get(), (void**)&D.x, H.n * sizeof(double)))) return st;
-            if (f32) {
-                if ((st = dalloc(h.get(), (void**)&D.b32, H.n * sizeof(float)))) return st;
-                if ((st = dalloc(h.get(), (void**)&D.x32, H.n * sizeof(float)))) return st;
-            }
-        }
-        if (l == L - 1 && l > 0 && h->host.coarse_sweeps > 0) {
-            if ((st = dalloc(h.get(), (void**)&D.r, H.n * sizeof(double)))) return st;
-        }
-        if (l < L - 1 && D.nu > 1) {
-            for (double** q : {&D.rb, &D.s, &D.sb, &D.xt, &D.xt2})
-                if ((st = dalloc(h.get(), (void**)q, H.n * sizeof(double)))) return st;
-            if (f32)
-                for (float** q : {&D.rb32, &D.s32, &D.sb32, &D.xt32, &D.xt232})
-                    if ((st = dalloc(h.get(), (void**)q, H.n * sizeof(float)))) return st;
-        }
-        if (l < L - 1) {
-            if ((st = dalloc(h.get(), (void**)&D.r, H.n * sizeof(double)))) return st;
-            if (f32 && (st = dalloc(h.get(), (void**)&D.r32, H.n * sizeof(float)))) return st;
-            if ((st = upload(h.get(), &D.agg, H.agg.data(), H.n))) return st;
-            if ((st = upload(h.get(), &D.pval, H.p.data(), H.n))) return st;
-            if (f32) {
-                auto p32 = to32(H.p);
-                if ((st = upload(h.get(), &D.pval32, p32.data(), p32.size()))) return st;
-            }
-            // R = P^T as CSR over coarse rows: fine rows ascending
-            const size_t pn = H.pci.size();
-            std::vector<int32_t> rrp(H.nc + 1, 0), rci(pn);
-            std::vector<double> rv(pn);
-            for (size_t m = 0; m < pn; m++) rrp[H.pci[m] + 1]++;
-            for (int64_t I = 0; I < H.nc; I++) rrp[I + 1] += rrp[I];
-            std::vector<int32_t> pos(rrp.begin(), rrp.end() - 1);
-            for (int64_t i = 0; i < H.n; i++) {
-                for (int32_t m = H.prp[i]; m < H.prp[i + 1]; m++) {
-                    int32_t o = pos[H.pci[m]]++;
-                    rci[o] = (int32_t)i;
-                    rv[o] = H.pv[m];
-                }
-            }
-            if ((st = upload_ell(h.get(), D.R, H.nc, H.n, rrp.data(), rci.data(), rv.data(), f32))) return st;
-            // smoothed prolongator for the split post-smoothing sweep
-            std::vector<int32_t> sprp, spci;
-            std::vector<double> spv;
-            jacobi_smoothed_prolongator(H, mv.data(), sprp, spci, spv);
-            if ((st = upload_ell(h.get(), D.SP, H.n, H.nc, sprp.data(), spci.data(), spv.data(), f32))) return st;
-            if (h->fai || h->cheb) {
-                if ((st = upload_fai(h.get(), D, H, f32))) return st;
-            }
-        }
-    }
-    // coarsest inverse, stored transposed for coalesced reads
-    h->coarse_n = (int)h->host.lev[L - 1].n;
-    if (h->host.coarse_sweeps == 0) {
-        int nc = h->coarse_n;
-        std::vector<double> invT((size_t)nc * nc);
-        for (int i = 0; i < nc; i++)
-            for (int k = 0; k < nc; k++) invT[(size_t)k * nc + i] = h->host.coarse_inv[(size_t)i * nc + k];
-        if ((st = upload(h.get(), &h->coarse_invT, invT.data(), invT.size()))) return st;
-    }
+    if ((st = upload_levels(h.get()))) return st;
     // solver workspace
     const int64_t N = n;
     if ((st = dalloc(h.get(), (void**)&h->ctl, sizeof(Ctl)))) return st;
@@ -3030,6 +3064,33 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     return PSC_OK;
 }
 
+int psc_amg_rebuild(psc_hier* h, const double* val) {
+    if (!h || !val) return fail(PSC_ERR_ARG, "NULL argument");
+    auto t0 = std::chrono::steady_clock::now();
+    std::string err;
+    if (!h->opts.host_only) {
+        HIPCHK(hipSetDevice(h->device));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    h->stale = true;
+    int st = rebuild_numeric(h->host, val, setup_opts_of(h), err);
+    if (st) return fail(st, err);
+    if (!h->opts.host_only) {
+        // captured iterations point at the old level buffers
+        drop_graphs(h);
+        for (void* p : h->lev_allocs) (void)hipFree(p);
+        h->lev_allocs.clear();
+        h->device_bytes -= h->lev_bytes;
+        h->lev_bytes = 0;
+        if ((st = upload_levels(h))) return st;
+        if ((st = build_tail(h))) return st;
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    h->stale = false;
+    h->rebuild_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return PSC_OK;
+}
+
 int psc_pcg_solve(psc_hier* h, const double* b, double* x, double rtol, int32_t maxit,
                   int32_t* iters, double* relres) {
     return solve(h, 0, nullptr, b, x, rtol, maxit, iters, relres, nullptr);
@@ -3047,6 +3108,7 @@ int psc_pairs_collect(psc_hier* h, const double* b, int32_t nx, int32_t ny, int3
                       float* r_out, float* z_out, int32_t capacity, int32_t* count) {
     if (!h || !b || !origins || !r_out || !z_out || !count) return fail(PSC_ERR_ARG, "NULL argument");
     if (!h->ctl) return fail(PSC_ERR_STATE, "hierarchy was built host-only");
+    if (h->stale) return fail(PSC_ERR_STATE, "the last numeric rebuild failed");
     if ((long long)nx * ny * nz != h->lev[0].n) return fail(PSC_ERR_ARG, "grid does not match the matrix size");
     if (crop < 1 || crop > nx || crop > ny || crop > nz || cpi < 1 || n_origins < 0 || capacity < 0 ||
         *count < 0 || *count > capacity || maxit < 0 || !(rtol > 0.0))
@@ -3157,6 +3219,7 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
     s->aggregation = h->opts.aggregation;
     s->smoothed_prol = h->opts.smoothed_prol;
     s->smoother = h->opts.smoother;
+    s->rebuild_seconds = h->rebuild_seconds;
     if (h->opts.host_only)
         for (int l = 0; l + 1 < L; l++) s->smoother_nnz[l] = (int64_t)h->host.lev[l].fai.zi.size();
     return PSC_OK;
@@ -3199,6 +3262,7 @@ int psc_hier_export_prolongator(const psc_hier* h, int32_t l, int32_t* rp, int32
 int psc_vcycle_apply(psc_hier* h, int32_t prec, const double* r, double* z) {
     if (!h || !r || !z) return fail(PSC_ERR_ARG, "NULL argument");
     if (!h->ctl) return fail(PSC_ERR_STATE, "hierarchy was built host-only");
+    if (h->stale) return fail(PSC_ERR_STATE, "the last numeric rebuild failed");
     if (prec != PSC_FP64 && prec != PSC_FP32) return fail(PSC_ERR_ARG, "prec must be PSC_FP64 or PSC_FP32");
     if (prec == PSC_FP32 && !h->has32) return fail(PSC_ERR_STATE, "FP32 V-cycle needs build_fp32");
     HIPCHK(hipSetDevice(h->device));
@@ -3215,6 +3279,7 @@ int psc_spmv(psc_hier* h, int32_t l, int32_t prec, const void* x, void* y) {
     if (!h || !x || !y || l < 0 || l >= (int)h->lev.size()) return fail(PSC_ERR_ARG, "bad argument");
     if (prec == PSC_FP32 && !h->has32) return fail(PSC_ERR_STATE, "FP32 copies not built");
     if (!h->ctl) return fail(PSC_ERR_STATE, "hierarchy was built host-only");
+    if (h->stale) return fail(PSC_ERR_STATE, "the last numeric rebuild failed");
     HIPCHK(hipSetDevice(h->device));
     int st = join_in(h);
     if (st) return st;

@@ -471,6 +471,89 @@ int coarse_inverse(const Csr& A, std::vector<double>& inv) {
     return PSC_OK;
 }
 
+// The numeric part of coarsening level l, given its aggregates F.agg and
+// F.nc: the next sample vector, the tentative prolongator values, the
+// prolongator the V-cycle uses (tentative or smoothed) and the Galerkin
+// operator of level l + 1 (Cl). Shared by the build and the numeric rebuild.
+void level_numeric(const Csr& A, const SetupOpts& o, HostLevel& F, HostLevel& Cl) {
+    const int64_t nc = F.nc;
+    Cl.n = nc;
+    std::vector<int64_t> start;
+    std::vector<int32_t> mem;
+    members_of(F.agg, nc, start, mem);
+    Cl.w.resize(nc);
+    F.p.resize(F.n);
+    if (o.aggr == 0) {
+        // matching: P^ columns are the normalised restrictions of w
+#pragma omp parallel for schedule(static)
+        for (int64_t I = 0; I < nc; I++) {
+            double s = 0.0;
+            for (int64_t m = start[I]; m < start[I + 1]; m++) s += F.w[mem[m]] * F.w[mem[m]];
+            Cl.w[I] = std::sqrt(s);
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < F.n; i++) F.p[i] = F.w[i] / Cl.w[F.agg[i]];
+    } else {
+        // VBM, eq. (prolongator_vbm): P^_{i,agg_i} = w_i; the coarse sample is 1
+        std::fill(Cl.w.begin(), Cl.w.end(), 1.0);
+        for (int64_t i = 0; i < F.n; i++) F.p[i] = F.w[i];
+    }
+    Csr Ac;
+    if (o.prol == 0) {
+        // tentative: one entry per row, canonical Galerkin sum
+        F.prp.resize(F.n + 1);
+        for (int64_t i = 0; i <= F.n; i++) F.prp[i] = (int32_t)i;
+        F.pci = F.agg;
+        F.pv = F.p;
+        galerkin(A, F.agg, nc, F.p.data(), Ac);
+    } else {
+        // smoothed: omega = 1 / max_i sum_j |a_ij| / a_ii, then
+        // P_iJ = [J = agg_i] p_i - (omega / a_ii) (A P^)_iJ and C = P^T (A P)
+        double norm = 0.0;
+        for (int64_t i = 0; i < A.n; i++) {
+            double sabs = 0.0, aii = 0.0;
+            for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++) {
+                sabs += std::fabs(A.v[k]);
+                if (A.ci[k] == i) aii = A.v[k];
+            }
+            if (sabs / aii > norm) norm = sabs / aii;
+        }
+        F.omega = 1.0 / norm;
+        Csr Ph, T;
+        Ph.n = F.n;
+        Ph.rp.resize(F.n + 1);
+        for (int64_t i = 0; i <= F.n; i++) Ph.rp[i] = (int32_t)i;
+        Ph.ci = F.agg;
+        Ph.v = F.p;
+        spgemm(A, Ph, nc, T);
+        Csr Pm;
+        Pm.n = F.n;
+        Pm.rp = T.rp;
+        Pm.ci = T.ci;
+        Pm.v.resize(T.v.size());
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < F.n; i++) {
+            double aii = 0.0;
+            for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++)
+                if (A.ci[k] == i) aii = A.v[k];
+            for (int32_t m = T.rp[i]; m < T.rp[i + 1]; m++) {
+                const double pk = T.ci[m] == F.agg[i] ? F.p[i] : 0.0;
+                Pm.v[m] = pk - (F.omega / aii) * T.v[m];
+            }
+        }
+        Csr AP, R;
+        spgemm(A, Pm, nc, AP);
+        transpose(Pm, nc, R);
+        spgemm(R, AP, nc, Ac);
+        F.prp.swap(Pm.rp);
+        F.pci.swap(Pm.ci);
+        F.pv.swap(Pm.v);
+    }
+    Cl.rp.swap(Ac.rp);
+    Cl.ci.swap(Ac.ci);
+    Cl.v.swap(Ac.v);
+}
+
 }  // namespace
 
 void pack_ell(int64_t nrows, const int32_t* rp, const int32_t* ci, const double* v,
@@ -647,85 +730,15 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
         HostLevel& Cl = H.lev[l + 1];
         F.nc = nc;
         F.agg.swap(agg);
-        Cl.n = nc;
-        std::vector<int64_t> start;
-        std::vector<int32_t> mem;
-        members_of(F.agg, nc, start, mem);
-        Cl.w.resize(nc);
-        F.p.resize(F.n);
-        if (o.aggr == 0) {
-            // matching: P^ columns are the normalised restrictions of w
-#pragma omp parallel for schedule(static)
-            for (int64_t I = 0; I < nc; I++) {
-                double s = 0.0;
-                for (int64_t m = start[I]; m < start[I + 1]; m++) s += F.w[mem[m]] * F.w[mem[m]];
-                Cl.w[I] = std::sqrt(s);
-            }
-#pragma omp parallel for schedule(static)
-            for (int64_t i = 0; i < F.n; i++) F.p[i] = F.w[i] / Cl.w[F.agg[i]];
-        } else {
-            // VBM, eq. (prolongator_vbm): P^_{i,agg_i} = w_i; the coarse sample is 1
-            std::fill(Cl.w.begin(), Cl.w.end(), 1.0);
-            for (int64_t i = 0; i < F.n; i++) F.p[i] = F.w[i];
-        }
-        Csr Ac;
-        if (o.prol == 0) {
-            // tentative: one entry per row, canonical Galerkin sum
-            F.prp.resize(F.n + 1);
-            for (int64_t i = 0; i <= F.n; i++) F.prp[i] = (int32_t)i;
-            F.pci = F.agg;
-            F.pv = F.p;
-            galerkin(A, F.agg, nc, F.p.data(), Ac);
-        } else {
-            // smoothed: omega = 1 / max_i sum_j |a_ij| / a_ii, then
-            // P_iJ = [J = agg_i] p_i - (omega / a_ii) (A P^)_iJ and C = P^T (A P)
-            double norm = 0.0;
-            for (int64_t i = 0; i < A.n; i++) {
-                double sabs = 0.0, aii = 0.0;
-                for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++) {
-                    sabs += std::fabs(A.v[k]);
-                    if (A.ci[k] == i) aii = A.v[k];
-                }
-                if (sabs / aii > norm) norm = sabs / aii;
-            }
-            F.omega = 1.0 / norm;
-            Csr Ph, T;
-            Ph.n = F.n;
-            Ph.rp.resize(F.n + 1);
-            for (int64_t i = 0; i <= F.n; i++) Ph.rp[i] = (int32_t)i;
-            Ph.ci = F.agg;
-            Ph.v = F.p;
-            spgemm(A, Ph, nc, T);
-            Csr Pm;
-            Pm.n = F.n;
-            Pm.rp = T.rp;
-            Pm.ci = T.ci;
-            Pm.v.resize(T.v.size());
-#pragma omp parallel for schedule(static)
-            for (int64_t i = 0; i < F.n; i++) {
-                double aii = 0.0;
-                for (int32_t k = A.rp[i]; k < A.rp[i + 1]; k++)
-                    if (A.ci[k] == i) aii = A.v[k];
-                for (int32_t m = T.rp[i]; m < T.rp[i + 1]; m++) {
-                    const double pk = T.ci[m] == F.agg[i] ? F.p[i] : 0.0;
-                    Pm.v[m] = pk - (F.omega / aii) * T.v[m];
-                }
-            }
-            Csr AP, R;
-            spgemm(A, Pm, nc, AP);
-            transpose(Pm, nc, R);
-            spgemm(R, AP, nc, Ac);
-            F.prp.swap(Pm.rp);
-            F.pci.swap(Pm.ci);
-            F.pv.swap(Pm.v);
-        }
-        Cl.rp.swap(Ac.rp);
-        Cl.ci.swap(Ac.ci);
-        Cl.v.swap(Ac.v);
+        level_numeric(A, o, F, Cl);
         F.rp.swap(A.rp);
         F.ci.swap(A.ci);
         F.v.swap(A.v);
     }
+    return build_smoothers(H, o, err);
+}
+
+int build_smoothers(HostHier& H, const SetupOpts& o, std::string& err) {
     // AINV / INVK smoothers of the levels above the coarsest
     if (o.smoother == 1 || o.smoother == 2) {
         for (size_t l = 0; l + 1 < H.lev.size(); l++) {
@@ -740,6 +753,47 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
         }
     }
     return PSC_OK;
+}
+
+int rebuild_numeric(HostHier& H, const double* v0, const SetupOpts& o, std::string& err) {
+    const size_t L = H.lev.size();
+    if (L == 0) {
+        err = "empty hierarchy";
+        return PSC_ERR_STATE;
+    }
+    {
+        HostLevel& L0 = H.lev[0];
+        const int64_t nnz = L0.rp[L0.n];
+        for (int64_t i = 0; i < L0.n; i++) {
+            bool diag = false;
+            for (int32_t k = L0.rp[i]; k < L0.rp[i + 1]; k++) diag = diag || (L0.ci[k] == i && v0[k] > 0.0);
+            if (!diag) {
+                err = "row " + std::to_string(i) + " has no positive diagonal";
+                return PSC_ERR_NOT_SPD;
+            }
+        }
+        L0.v.assign(v0, v0 + nnz);
+    }
+    for (size_t l = 0; l < L; l++) {
+        HostLevel& F = H.lev[l];
+        Csr A;
+        A.n = F.n;
+        A.rp.swap(F.rp);
+        A.ci.swap(F.ci);
+        A.v.swap(F.v);
+        int st = l1_inverse_diag(A, F.minv);
+        if (st == PSC_OK && l + 1 == L && H.coarse_sweeps == 0) st = coarse_inverse(A, H.coarse_inv);
+        if (st == PSC_OK && l + 1 < L) level_numeric(A, o, F, H.lev[l + 1]);
+        F.rp.swap(A.rp);
+        F.ci.swap(A.ci);
+        F.v.swap(A.v);
+        if (st != PSC_OK) {
+            err = l + 1 == L ? "Cholesky breakdown on the coarsest level" : "non-positive l1 diagonal";
+            return st;
+        }
+    }
+    for (auto& F : H.lev) F.fai = HostFai();
+    return build_smoothers(H, o, err);
 }
 
 // S P = (I - M^-1 A_l) P_l as CSR over the rows of A_l with aggregate

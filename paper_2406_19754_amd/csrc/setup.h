@@ -61,6 +61,18 @@ int validate_csr(int64_t n, const int32_t* rp, const int32_t* ci, const double* 
 int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
                     const SetupOpts& o, HostHier& H, std::string& err);
 
+// AINV / INVK factors of every level above the coarsest (nothing for the
+// other smoothers).
+int build_smoothers(HostHier& H, const SetupOpts& o, std::string& err);
+
+// Numeric-only rebuild: new values v0 of A_0 on the sparsity pattern the
+// hierarchy was built with. Aggregates, prolongator patterns and the
+// coarsest-level choice are kept; everything that depends on the values
+// (l1 diagonals, smoothed prolongators, Galerkin values, the coarsest
+// factor, AINV / INVK factors) is recomputed in the build's order, so the
+// result equals a build that reached the same aggregates.
+int rebuild_numeric(HostHier& H, const double* v0, const SetupOpts& o, std::string& err);
+
 // AINV / INVK factors of one SPD CSR matrix (Section "GPU enabled smoothers").
 int build_ainv(int64_t n, const int32_t* rp, const int32_t* ci, const double* v, double tau, HostFai& F,
                std::string& err);

@@ -58,7 +58,7 @@ class HierStats(C.Structure):
                 ("dia_slots", C.c_int64 * MAX_LEVELS), ("p_nnz", C.c_int64 * MAX_LEVELS),
                 ("omega", C.c_double * MAX_LEVELS), ("smoother_sweeps", C.c_int32), ("smoothed_prol", C.c_int32),
                 ("vcycle_double", C.c_int32), ("aggregation", C.c_int32), ("smoother", C.c_int32),
-                ("smoother_nnz", C.c_int64 * MAX_LEVELS)]
+                ("smoother_nnz", C.c_int64 * MAX_LEVELS), ("rebuild_seconds", C.c_double)]
 
 
 def _load():
@@ -73,6 +73,7 @@ def _load():
         "psc_last_error": ([], C.c_char_p),
         "psc_amg_opts_default": ([P(AmgOpts)], None),
         "psc_amg_build": ([i32, vp, vp, vp, P(AmgOpts), vp, P(vp)], C.c_int),
+        "psc_amg_rebuild": ([vp, vp], C.c_int),
         "psc_pcg_solve": ([vp, vp, vp, f64, i32, P(i32), P(f64)], C.c_int),
         "psc_fcg_solve": ([vp, vp, i32, vp, vp, f64, i32, P(i32), P(f64), P(i32)], C.c_int),
         "psc_hier_info": ([vp, P(HierStats)], C.c_int),
@@ -189,7 +190,13 @@ class Hierarchy:
                     coarse_sweeps=s.coarse_sweeps, sp_nnz=list(s.sp_nnz[:L]), dia_slots=list(s.dia_slots[:L]),
                     p_nnz=list(s.p_nnz[:L]), omega=list(s.omega[:L]), smoother_sweeps=s.smoother_sweeps,
                     smoothed_prol=s.smoothed_prol, vcycle_double=s.vcycle_double, aggregation=s.aggregation,
-                    smoother=s.smoother, smoother_nnz=list(s.smoother_nnz[:L]))
+                    smoother=s.smoother, smoother_nnz=list(s.smoother_nnz[:L]),
+                    rebuild_seconds=s.rebuild_seconds)
+
+    def rebuild(self, val):
+        """Numeric-only rebuild with new values of A (same pattern as at build)."""
+        v, pv = _hptr(val, np.float64)
+        _check(_lib.psc_amg_rebuild(self._h, pv))
 
     def export_level(self, l):
         inf = self.info()

@@ -1,0 +1,132 @@
+"""GPU side of the numeric-only rebuild (psc_amg_rebuild): the device copies
+are refreshed (V-cycle and solves against the oracle's build of 4A, which
+reaches the same aggregates), captured iterations are dropped, solves on new
+coefficients converge and agree with a V-cycle written from the exported
+levels, and a failed rebuild makes the handle refuse work until a rebuild
+succeeds. Tolerances as for the other parity tests."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as sla
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle
+from paper_2406_19754_amd import problems as P
+
+
+@pytest.fixture(scope="module")
+def psc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_19754_amd import psc as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+CONFIGS = {
+    "matching": (dict(), dict()),
+    "smoothed_nu2": (dict(smoothed_prol=True, sweeps=3, smoother_sweeps=2), dict(prol=1, sweeps=3, nu=2)),
+    "ainv": (dict(smoother=1), dict(smoother=1)),
+    "cheb2": (dict(smoother=3, smoother_sweeps=2), dict(smoother=3, nu=2)),
+}
+
+
+@pytest.mark.parametrize("cfg", list(CONFIGS))
+def test_rebuild_4a_matches_oracle_build_of_4a(psc, cfg):
+    rp, c, v = P.poisson7(20)
+    n = len(rp) - 1
+    lo, oo = CONFIGS[cfg]
+    h = psc.Hierarchy(rp, c, v, build_fp32=True, **lo)
+    b = P.rhs_uniform(n, 1)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    h.pcg(dev(b), x)                                 # capture iteration graphs on the old buffers
+    h.fcg(dev(b), x, prec=psc.FP32)
+    h.rebuild(4.0 * v)
+    o = oracle.Hierarchy(rp, c, 4.0 * v, **oo)
+    r = np.random.default_rng(4).standard_normal(n)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.vcycle(dev(r), z)
+    ref = o.vcycle(r)
+    assert np.linalg.norm(z.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+    h.vcycle(dev(r), z, prec=psc.FP32)
+    ref32 = o.vcycle32(r)
+    assert np.linalg.norm(z.cpu().numpy() - ref32) <= 1e-5 * np.linalg.norm(ref32)
+    b4 = P.rhs_from_solution(rp, c, 4.0 * v, P.x_true(n, 2))
+    ro = o.pcg(b4)
+    for fused in (1, 0):
+        h.tune(psc.TUNE_FUSED_PCG, fused)
+        x.zero_()
+        g = h.pcg(dev(b4), x)
+        assert g["status"] == psc.OK and abs(g["iters"] - ro["iters"]) <= 1 and g["relres"] <= 1e-6
+
+
+def _vcycle_from_exports(h, r):
+    """V(1,1) with l1-Jacobi written from the exported levels (scipy)."""
+    inf = h.info()
+    L = inf["levels"]
+    levs = [h.export_level(l) for l in range(L)]
+    mats = [sp.csr_matrix((lv["val"], lv["col"], lv["rowptr"]), shape=(lv["n"], lv["n"])) for lv in levs]
+    Ps = []
+    for l in range(L - 1):
+        prp, pci, pv = h.export_prolongator(l)
+        Ps.append(sp.csr_matrix((pv, pci, prp), shape=(levs[l]["n"], levs[l + 1]["n"])))
+
+    def vc(l, b):
+        A = mats[l]
+        if l == L - 1:
+            return np.linalg.solve(A.toarray(), b)
+        m = levs[l]["minv"]
+        x = m * b
+        xc = vc(l + 1, Ps[l].T @ (b - A @ x))
+        x = x + Ps[l] @ xc
+        return x + m * (b - A @ x)
+    return vc(0, r)
+
+
+def test_rebuild_with_new_coefficients(psc):
+    rp, c, v = P.diffusion7(20, seed=1)
+    _, _, v2 = P.diffusion7(20, seed=5, az=20.0)
+    n = len(rp) - 1
+    h = psc.Hierarchy(rp, c, v, build_fp32=True)
+    assert h.info()["coarse_sweeps"] == 0
+    h.rebuild(v2)
+    r = np.random.default_rng(6).standard_normal(n)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.vcycle(dev(r), z)
+    ref = _vcycle_from_exports(h, r)
+    assert np.linalg.norm(z.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+    b = P.rhs_from_solution(rp, c, v2, P.x_true(n, 3))
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    g = h.pcg(dev(b), x)
+    assert g["status"] == psc.OK and g["relres"] <= 1e-6
+    A2 = sp.csr_matrix((v2, c, rp))
+    assert np.linalg.norm(b - A2 @ x.cpu().numpy()) <= 1.01e-6 * np.linalg.norm(b)
+    x.zero_()
+    g = h.fcg(dev(b), x, prec=psc.FP32)
+    assert g["status"] == psc.OK and g["relres"] <= 1e-6
+
+
+def test_failed_rebuild_refuses_work_until_a_rebuild_succeeds(psc):
+    rp, c, v = P.poisson7(10)
+    n = len(rp) - 1
+    h = psc.Hierarchy(rp, c, v)
+    bad = v.copy()
+    bad[rp[7]:rp[8]][c[rp[7]:rp[8]] == 7] = 0.0
+    with pytest.raises(psc.PscError) as e:
+        h.rebuild(bad)
+    assert e.value.status == psc.ERR_NOT_SPD
+    b = P.rhs_uniform(n, 2)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    with pytest.raises(psc.PscError) as e:
+        h.pcg(dev(b), x)
+    assert e.value.status == psc.ERR_STATE
+    with pytest.raises(psc.PscError):
+        h.vcycle(dev(b), x)
+    h.rebuild(v)
+    g = h.pcg(dev(b), x)
+    assert g["status"] == psc.OK and g["relres"] <= 1e-6
