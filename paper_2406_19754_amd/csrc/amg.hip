@@ -39,6 +39,7 @@
 #include <memory>
 #include <string>
 #include <type_traits>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/psc.h"
@@ -1552,6 +1553,10 @@ struct psc_hier {
     std::vector<void*> lev_allocs;        // per-level device data (released by a numeric rebuild)
     int64_t lev_bytes = 0;
     bool lev_phase = false;               // dalloc records into lev_allocs
+    // refresh: a numeric rebuild writes new values into the existing level
+    // buffers (same sizes), skipping allocations and index arrays
+    bool refresh = false;
+    std::unordered_map<void*, size_t> asize;   // bytes of every level allocation
     int64_t device_bytes = 0;
     double setup_seconds = 0.0;
     double rebuild_seconds = 0.0;         // last numeric rebuild
@@ -1573,10 +1578,19 @@ namespace psc {
 
 static int dalloc(psc_hier* h, void** p, size_t bytes) {
     if (bytes == 0) bytes = 64;
+    if (h->refresh) {
+        // reuse the buffer of the same size; anything else needs a full re-upload
+        auto it = *p ? h->asize.find(*p) : h->asize.end();
+        if (it == h->asize.end() || it->second != bytes) return PSC_ERR_STATE;
+        return PSC_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) return fail(PSC_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
     (h->lev_phase ? h->lev_allocs : h->allocs).push_back(*p);
-    if (h->lev_phase) h->lev_bytes += (int64_t)bytes;
+    if (h->lev_phase) {
+        h->lev_bytes += (int64_t)bytes;
+        h->asize[*p] = bytes;
+    }
     h->device_bytes += (int64_t)bytes;
     return PSC_OK;
 }
@@ -1602,9 +1616,11 @@ static int upload(psc_hier* h, T** d, const T* src, size_t count) {
     return PSC_OK;
 }
 
+// value_pattern: the sparsity depends on the values (AINV factors), so a
+// refresh rewrites the index arrays too (same sizes) instead of keeping them.
 static int upload_ell(psc_hier* h, DevEll<double>& E, int64_t nrows, int64_t ncols, const int32_t* rp,
                       const int32_t* ci, const double* v, bool fp32, const double* minv = nullptr,
-                      double** am = nullptr, float** am32 = nullptr) {
+                      double** am = nullptr, float** am32 = nullptr, bool value_pattern = false) {
     std::vector<long long> off;
     std::vector<double> val;
     std::vector<int> col;
@@ -1616,9 +1632,14 @@ static int upload_ell(psc_hier* h, DevEll<double>& E, int64_t nrows, int64_t nco
     E.nnz = rp[nrows];
     for (size_t q = 0; q + 1 < off.size(); q++) E.wmax = std::max(E.wmax, (int)((off[q + 1] - off[q]) / SLICE));
     int st;
-    if ((st = upload(h, &E.off, off.data(), off.size()))) return st;
+    if (h->refresh && !value_pattern) {
+        // the pattern is the one uploaded at build: new values only
+        if (E.off == nullptr || E.col == nullptr) return PSC_ERR_STATE;
+    } else {
+        if ((st = upload(h, &E.off, off.data(), off.size()))) return st;
+        if ((st = upload(h, &E.col, col.data(), col.size()))) return st;
+    }
     if ((st = upload(h, &E.val, val.data(), val.size()))) return st;
-    if ((st = upload(h, &E.col, col.data(), col.size()))) return st;
     std::vector<float> v32;
     if (fp32) {
         v32.resize(val.size());
@@ -1679,8 +1700,10 @@ static int upload_fai(psc_hier* h, DevLevel& D, const HostLevel& H, bool f32) {
             zci[o] = (int32_t)k;
             zv[o] = F.zv[e];
         }
-    if ((st = upload_ell(h, D.W, n, n, wrp.data(), F.zi.data(), wv.data(), f32))) return st;
-    if ((st = upload_ell(h, D.Z, n, n, zrp.data(), zci.data(), zv.data(), f32))) return st;
+    if ((st = upload_ell(h, D.W, n, n, wrp.data(), F.zi.data(), wv.data(), f32, nullptr, nullptr, nullptr, true)))
+        return st;
+    if ((st = upload_ell(h, D.Z, n, n, zrp.data(), zci.data(), zv.data(), f32, nullptr, nullptr, nullptr, true)))
+        return st;
     if ((st = upload_ell(h, D.P, n, H.nc, H.prp.data(), H.pci.data(), H.pv.data(), f32))) return st;
     for (double** q : {&D.ft, &D.fu})
         if ((st = dalloc(h, (void**)q, n * sizeof(double)))) return st;
@@ -2800,8 +2823,12 @@ static int upload_levels(psc_hier* h) {
     const bool f32 = h->has32;
     const int L = (int)h->host.lev.size();
     const bool cheb1 = h->opts.smoother == PSC_SMOOTH_CHEB4 && !h->cheb;
-    h->lev.assign(L, DevLevel{});
-    h->coarse_invT = nullptr;
+    if (!h->refresh) {
+        h->lev.assign(L, DevLevel{});
+        h->coarse_invT = nullptr;
+    } else if ((int)h->lev.size() != L) {
+        return PSC_ERR_STATE;
+    }
     h->lev_phase = true;
     struct PhaseEnd {
         psc_hier* h;
@@ -3076,13 +3103,22 @@ int psc_amg_rebuild(psc_hier* h, const double* val) {
     int st = rebuild_numeric(h->host, val, setup_opts_of(h), err);
     if (st) return fail(st, err);
     if (!h->opts.host_only) {
-        // captured iterations point at the old level buffers
-        drop_graphs(h);
-        for (void* p : h->lev_allocs) (void)hipFree(p);
-        h->lev_allocs.clear();
-        h->device_bytes -= h->lev_bytes;
-        h->lev_bytes = 0;
-        if ((st = upload_levels(h))) return st;
+        // new values into the existing buffers when every size matches (the
+        // captured iterations stay valid); otherwise release and re-upload
+        h->refresh = true;
+        st = upload_levels(h);
+        h->refresh = false;
+        if (st == PSC_ERR_STATE) {
+            g_err.clear();
+            drop_graphs(h);   // they point at the buffers released below
+            for (void* p : h->lev_allocs) (void)hipFree(p);
+            h->lev_allocs.clear();
+            h->asize.clear();
+            h->device_bytes -= h->lev_bytes;
+            h->lev_bytes = 0;
+            st = upload_levels(h);
+        }
+        if (st) return st;
         if ((st = build_tail(h))) return st;
         HIPCHK(hipStreamSynchronize(h->stream));
     }

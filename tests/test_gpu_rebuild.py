@@ -65,8 +65,9 @@ def test_rebuild_4a_matches_oracle_build_of_4a(psc, cfg):
         assert g["status"] == psc.OK and abs(g["iters"] - ro["iters"]) <= 1 and g["relres"] <= 1e-6
 
 
-def _vcycle_from_exports(h, r):
-    """V(1,1) with l1-Jacobi written from the exported levels (scipy)."""
+def _vcycle_from_exports(h, r, fai=False):
+    """V(1,1) written from the exported levels (scipy): l1-Jacobi, or the
+    exported AINV / INVK factors G = Z D^-1 Z^T."""
     inf = h.info()
     L = inf["levels"]
     levs = [h.export_level(l) for l in range(L)]
@@ -76,15 +77,23 @@ def _vcycle_from_exports(h, r):
         prp, pci, pv = h.export_prolongator(l)
         Ps.append(sp.csr_matrix((pv, pci, prp), shape=(levs[l]["n"], levs[l + 1]["n"])))
 
+    Gs = []
+    for l in range(L - 1):
+        if fai:
+            zr, zi, zv, d = h.export_smoother(l)
+            Z = sp.csc_matrix((zv, zi, zr), shape=(levs[l]["n"], levs[l]["n"]))
+            Gs.append(lambda t, Z=Z, d=d: Z @ ((Z.T @ t) / d))
+        else:
+            Gs.append(lambda t, m=levs[l]["minv"]: m * t)
+
     def vc(l, b):
         A = mats[l]
         if l == L - 1:
             return np.linalg.solve(A.toarray(), b)
-        m = levs[l]["minv"]
-        x = m * b
+        x = Gs[l](b)
         xc = vc(l + 1, Ps[l].T @ (b - A @ x))
         x = x + Ps[l] @ xc
-        return x + m * (b - A @ x)
+        return x + Gs[l](b - A @ x)
     return vc(0, r)
 
 
@@ -129,4 +138,27 @@ def test_failed_rebuild_refuses_work_until_a_rebuild_succeeds(psc):
         h.vcycle(dev(b), x)
     h.rebuild(v)
     g = h.pcg(dev(b), x)
+    assert g["status"] == psc.OK and g["relres"] <= 1e-6
+
+
+@pytest.mark.parametrize("smoother", [1, 2])
+def test_rebuild_of_factored_smoothers_with_new_coefficients(psc, smoother):
+    # AINV's pattern depends on the values (the rebuild may re-upload the
+    # factors); INVK's does not (refreshed in place)
+    rp, c, v = P.diffusion7(16, seed=2)
+    _, _, v2 = P.diffusion7(16, seed=9, az=5.0)
+    n = len(rp) - 1
+    h = psc.Hierarchy(rp, c, v, build_fp32=True, smoother=smoother)
+    b = P.rhs_uniform(n, 5)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    h.pcg(dev(b), x)
+    h.rebuild(v2)
+    r = np.random.default_rng(7).standard_normal(n)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.vcycle(dev(r), z)
+    ref = _vcycle_from_exports(h, r, fai=True)
+    assert np.linalg.norm(z.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+    b2 = P.rhs_from_solution(rp, c, v2, P.x_true(n, 4))
+    x.zero_()
+    g = h.pcg(dev(b2), x)
     assert g["status"] == psc.OK and g["relres"] <= 1e-6
