@@ -411,7 +411,8 @@ int gs_galerkin(hipStream_t st, int nc, int stride, const int* mem, int n, const
 }  // namespace
 
 int gpu_coarsen_level(int64_t n64, const int32_t* hrp, const int32_t* hci, const double* hv, const double* hw,
-                      int sweeps, std::vector<int32_t>& agg_out, int64_t& nc_out, std::vector<double>& p_out,
+                      int sweeps, bool want_coarse, std::vector<int32_t>& agg_out, int64_t& nc_out,
+                      std::vector<double>& p_out,
                       std::vector<double>& wc_out, std::vector<int32_t>& crp_out, std::vector<int32_t>& cci_out,
                       std::vector<double>& cv_out, std::string& err) {
     const int64_t nnz64 = hrp[n64];
@@ -537,20 +538,24 @@ int gpu_coarsen_level(int64_t n64, const int32_t* hrp, const int32_t* hci, const
     DBuf<int> crp, cci;
     DBuf<double> cv;
     int cnnz = 0;
-    int r = gs_galerkin(st, nc, stride, mem.p, n, rp.p, ci.p, v.p, agg.p, p.p, crp, cci, cv, cnnz, err);
-    if (r) return r;
+    if (want_coarse) {
+        int r = gs_galerkin(st, nc, stride, mem.p, n, rp.p, ci.p, v.p, agg.p, p.p, crp, cci, cv, cnnz, err);
+        if (r) return r;
+    }
     agg_out.resize(n);
     p_out.resize(n);
     wc_out.resize(nc);
-    crp_out.resize(nc + 1);
-    cci_out.resize(cnnz);
-    cv_out.resize(cnnz);
     GS_CHK(hipMemcpyAsync(agg_out.data(), agg.p, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, st));
     GS_CHK(hipMemcpyAsync(p_out.data(), p.p, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st));
     GS_CHK(hipMemcpyAsync(wc_out.data(), wc.p, (size_t)nc * sizeof(double), hipMemcpyDeviceToHost, st));
-    GS_CHK(hipMemcpyAsync(crp_out.data(), crp.p, (size_t)(nc + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
-    GS_CHK(hipMemcpyAsync(cci_out.data(), cci.p, (size_t)cnnz * sizeof(int), hipMemcpyDeviceToHost, st));
-    GS_CHK(hipMemcpyAsync(cv_out.data(), cv.p, (size_t)cnnz * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (want_coarse) {
+        crp_out.resize(nc + 1);
+        cci_out.resize(cnnz);
+        cv_out.resize(cnnz);
+        GS_CHK(hipMemcpyAsync(crp_out.data(), crp.p, (size_t)(nc + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+        GS_CHK(hipMemcpyAsync(cci_out.data(), cci.p, (size_t)cnnz * sizeof(int), hipMemcpyDeviceToHost, st));
+        GS_CHK(hipMemcpyAsync(cv_out.data(), cv.p, (size_t)cnnz * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
     GS_CHK(hipStreamSynchronize(st));
     nc_out = nc;
     return PSC_OK;

@@ -63,29 +63,28 @@ void members_of(const std::vector<int32_t>& agg, int64_t nc, std::vector<int64_t
 // product a_ij b_jJ into C[i,J] in that arrival order; columns ascending,
 // every reached entry stored.
 void spgemm_raw(int64_t n, const int32_t* arp, const int32_t* aci, const double* av, const int32_t* brp,
-                const int32_t* bci, const double* bv, Csr& C) {
+                const int32_t* bci, const double* bv, int64_t ncols, Csr& C) {
+    // Row i of C: the products a_ik b_kj in the order k ascending (row i of
+    // A), then row k of B, summed per column j in that order (the first
+    // product of a column assigns, later ones add); columns stored ascending.
+    // A dense accumulator per thread keeps that order without sorting the
+    // products; only the distinct columns are sorted.
     C.n = n;
     C.rp.assign(n + 1, 0);
-    auto row = [&](int64_t i, std::vector<std::pair<int32_t, double>>& e) {
-        e.clear();
-        for (int32_t k = arp[i]; k < arp[i + 1]; k++) {
-            const int32_t j = aci[k];
-            for (int32_t m = brp[j]; m < brp[j + 1]; m++) e.emplace_back(bci[m], av[k] * bv[m]);
-        }
-        std::stable_sort(e.begin(), e.end(),
-                         [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
-                             return a.first < b.first;
-                         });
-    };
 #pragma omp parallel
     {
-        std::vector<std::pair<int32_t, double>> e;
+        std::vector<int64_t> tag(ncols, -1);
 #pragma omp for schedule(dynamic, 1024)
         for (int64_t i = 0; i < n; i++) {
-            row(i, e);
-            int32_t cnt = 0, last = -1;
-            for (const auto& x : e)
-                if (x.first != last) { cnt++; last = x.first; }
+            int32_t cnt = 0;
+            for (int32_t k = arp[i]; k < arp[i + 1]; k++) {
+                const int32_t j = aci[k];
+                for (int32_t m = brp[j]; m < brp[j + 1]; m++)
+                    if (tag[bci[m]] != i) {
+                        tag[bci[m]] = i;
+                        cnt++;
+                    }
+            }
             C.rp[i + 1] = cnt;
         }
     }
@@ -94,19 +93,32 @@ void spgemm_raw(int64_t n, const int32_t* arp, const int32_t* aci, const double*
     C.v.resize(C.rp[n]);
 #pragma omp parallel
     {
-        std::vector<std::pair<int32_t, double>> e;
+        std::vector<int64_t> tag(ncols, -1);
+        std::vector<double> acc(ncols);
+        std::vector<int32_t> cols;
 #pragma omp for schedule(dynamic, 1024)
         for (int64_t i = 0; i < n; i++) {
-            row(i, e);
-            int32_t o = C.rp[i] - 1, last = -1;
-            for (const auto& x : e) {
-                if (x.first != last) {
-                    C.ci[++o] = x.first;
-                    C.v[o] = x.second;
-                    last = x.first;
-                } else {
-                    C.v[o] += x.second;
+            cols.clear();
+            for (int32_t k = arp[i]; k < arp[i + 1]; k++) {
+                const int32_t j = aci[k];
+                for (int32_t m = brp[j]; m < brp[j + 1]; m++) {
+                    const int32_t c = bci[m];
+                    const double x = av[k] * bv[m];
+                    if (tag[c] != i) {
+                        tag[c] = i;
+                        acc[c] = x;
+                        cols.push_back(c);
+                    } else {
+                        acc[c] += x;
+                    }
                 }
+            }
+            std::sort(cols.begin(), cols.end());
+            int64_t o = C.rp[i];
+            for (int32_t c : cols) {
+                C.ci[o] = c;
+                C.v[o] = acc[c];
+                o++;
             }
         }
     }
@@ -114,7 +126,7 @@ void spgemm_raw(int64_t n, const int32_t* arp, const int32_t* aci, const double*
 
 void spgemm(const Csr& A, const Csr& B, int64_t ncols, Csr& C) {
     (void)ncols;
-    spgemm_raw(A.n, A.rp.data(), A.ci.data(), A.v.data(), B.rp.data(), B.ci.data(), B.v.data(), C);
+    spgemm_raw(A.n, A.rp.data(), A.ci.data(), A.v.data(), B.rp.data(), B.ci.data(), B.v.data(), ncols, C);
 }
 
 // Transpose of an n x ncols CSR: row J lists (i, v_iJ) for i ascending.
@@ -693,13 +705,18 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
         }
         int64_t nc = 0;
         std::vector<int32_t> agg;
-        if (o.device && o.aggr == 0 && o.prol == 0) {
-            // matching, tentative prolongator: the whole coarsening on the GPU
+        bool have_agg = false;
+        if (o.device && o.aggr == 0) {
+            // matching on the GPU; with the tentative prolongator the whole
+            // coarsening (the smoothed one takes the aggregates, its products
+            // are formed below on the host)
             std::vector<double> gp, gwc, gcv;
             std::vector<int32_t> gcrp, gcci;
-            st = gpu_coarsen_level(A.n, A.rp.data(), A.ci.data(), A.v.data(), H.lev[l].w.data(), o.sweeps, agg,
-                                   nc, gp, gwc, gcrp, gcci, gcv, err);
-            if (st == PSC_OK) {
+            st = gpu_coarsen_level(A.n, A.rp.data(), A.ci.data(), A.v.data(), H.lev[l].w.data(), o.sweeps,
+                                   o.prol == 0, agg, nc, gp, gwc, gcrp, gcci, gcv, err);
+            if (st == PSC_OK && o.prol != 0) {
+                have_agg = true;
+            } else if (st == PSC_OK) {
                 H.lev.emplace_back();
                 HostLevel& F = H.lev[l];
                 HostLevel& Cl = H.lev[l + 1];
@@ -720,11 +737,13 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
                 F.v.swap(A.v);
                 continue;
             }
-            if (st != PSC_ERR_STATE) return st;
-            err.clear();
+            if (st != PSC_OK && st != PSC_ERR_STATE) return st;
+            if (st != PSC_OK) err.clear();
         }
-        if (o.aggr == 0) coarsen(A, H.lev[l].w, o.sweeps, agg, nc);
-        else vbm_aggregate(A, o.theta, agg, nc);
+        if (!have_agg) {
+            if (o.aggr == 0) coarsen(A, H.lev[l].w, o.sweeps, agg, nc);
+            else vbm_aggregate(A, o.theta, agg, nc);
+        }
         H.lev.emplace_back();
         HostLevel& F = H.lev[l];
         HostLevel& Cl = H.lev[l + 1];
@@ -803,7 +822,7 @@ int rebuild_numeric(HostHier& H, const double* v0, const SetupOpts& o, std::stri
 void jacobi_smoothed_prolongator(const HostLevel& H, const double* minv, std::vector<int32_t>& rp,
                                  std::vector<int32_t>& ci, std::vector<double>& v) {
     Csr T;
-    spgemm_raw(H.n, H.rp.data(), H.ci.data(), H.v.data(), H.prp.data(), H.pci.data(), H.pv.data(), T);
+    spgemm_raw(H.n, H.rp.data(), H.ci.data(), H.v.data(), H.prp.data(), H.pci.data(), H.pv.data(), H.nc, T);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < H.n; i++) {
         int32_t m = H.prp[i];

@@ -86,11 +86,11 @@ void jacobi_smoothed_prolongator(const HostLevel& H, const double* minv, std::ve
                                  std::vector<int32_t>& ci, std::vector<double>& v);
 
 // One level's coarsening on the GPU (matching aggregation, tentative
-// prolongator): aggregates, p, the next sample vector and the Galerkin
-// product, bit-identical to the host path. Returns PSC_ERR_STATE when the
+// prolongator): aggregates, p, the next sample vector and (want_coarse) the
+// Galerkin product, bit-identical to the host path. Returns PSC_ERR_STATE when the
 // level does not fit the device kernels (the caller then uses the host).
 int gpu_coarsen_level(int64_t n, const int32_t* rp, const int32_t* ci, const double* v, const double* w,
-                      int sweeps, std::vector<int32_t>& agg, int64_t& nc, std::vector<double>& p,
+                      int sweeps, bool want_coarse, std::vector<int32_t>& agg, int64_t& nc, std::vector<double>& p,
                       std::vector<double>& wc, std::vector<int32_t>& crp, std::vector<int32_t>& cci,
                       std::vector<double>& cv, std::string& err);
 

@@ -373,13 +373,19 @@ def test_smoothing_configurations_match_oracle(psc, case, cfg):
             h.tune(psc.TUNE_SPLIT, 0)
 
 
-@pytest.mark.parametrize("case,sweeps,cm", [("poisson32", 2, 200), ("poisson13", 2, 200), ("poisson24", 3, 200),
-                                            ("diffusion20_az100", 2, 200), ("random_long_rows", 2, 40),
-                                            ("diffusion48_lognormal", 2, 200)])
-def test_device_setup_bit_identical_to_host(psc, case, sweeps, cm):
+@pytest.mark.parametrize("case,sweeps,cm,smoothed", [("poisson32", 2, 200, False), ("poisson13", 2, 200, False),
+                                                     ("poisson24", 3, 200, False), ("diffusion20_az100", 2, 200, False),
+                                                     ("random_long_rows", 2, 40, False),
+                                                     ("diffusion48_lognormal", 2, 200, False),
+                                                     # smoothed prolongator: device aggregates, host products
+                                                     ("poisson24", 3, 200, True), ("poisson13", 3, 200, True),
+                                                     ("diffusion20_az100", 3, 200, True),
+                                                     ("random_long_rows", 2, 40, True)])
+def test_device_setup_bit_identical_to_host(psc, case, sweeps, cm, smoothed):
     rp, c, v = P.poisson7(24) if case == "poisson24" else CASES[case]()
-    hd = psc.Hierarchy(rp, c, v, sweeps=sweeps, coarse_max=cm, setup_device=True)
-    hh = psc.Hierarchy(rp, c, v, sweeps=sweeps, coarse_max=cm, setup_device=False, host_only=True)
+    hd = psc.Hierarchy(rp, c, v, sweeps=sweeps, coarse_max=cm, setup_device=True, smoothed_prol=smoothed)
+    hh = psc.Hierarchy(rp, c, v, sweeps=sweeps, coarse_max=cm, setup_device=False, host_only=True,
+                       smoothed_prol=smoothed)
     a, b = hd.info(), hh.info()
     assert a["rows"] == b["rows"] and a["nnz"] == b["nnz"] and a["coarse_sweeps"] == b["coarse_sweeps"]
     for l in range(a["levels"]):
@@ -388,3 +394,6 @@ def test_device_setup_bit_identical_to_host(psc, case, sweeps, cm):
             assert np.array_equal(x[key], y[key]), (l, key)
         if l < a["levels"] - 1:
             assert np.array_equal(x["agg"], y["agg"]) and np.array_equal(x["p"], y["p"]), l
+            if smoothed:
+                px, py = hd.export_prolongator(l), hh.export_prolongator(l)
+                assert all(np.array_equal(u, w) for u, w in zip(px, py)), l
