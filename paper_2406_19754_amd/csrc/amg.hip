@@ -2951,6 +2951,10 @@ static int upload_levels(psc_hier* h) {
             std::vector<int32_t> sprp, spci;
             std::vector<double> spv;
             jacobi_smoothed_prolongator(H, mv.data(), sprp, spci, spv);
+            // the kept A P is not needed after this (a rebuild forms it again)
+            std::vector<int32_t>().swap(H.aprp);
+            std::vector<int32_t>().swap(H.apci);
+            std::vector<double>().swap(H.apv);
             if ((st = upload_ell(h, D.SP, H.n, H.nc, sprp.data(), spci.data(), spv.data(), f32))) return st;
             if (h->fai || h->cheb) {
                 if ((st = upload_fai(h, D, H, f32))) return st;

@@ -560,6 +560,10 @@ void level_numeric(const Csr& A, const SetupOpts& o, HostLevel& F, HostLevel& Cl
         F.prp.swap(Pm.rp);
         F.pci.swap(Pm.ci);
         F.pv.swap(Pm.v);
+        // kept for the split smoothing operator (I - M^-1 A) P
+        F.aprp.swap(AP.rp);
+        F.apci.swap(AP.ci);
+        F.apv.swap(AP.v);
     }
     Cl.rp.swap(Ac.rp);
     Cl.ci.swap(Ac.ci);
@@ -822,7 +826,15 @@ int rebuild_numeric(HostHier& H, const double* v0, const SetupOpts& o, std::stri
 void jacobi_smoothed_prolongator(const HostLevel& H, const double* minv, std::vector<int32_t>& rp,
                                  std::vector<int32_t>& ci, std::vector<double>& v) {
     Csr T;
-    spgemm_raw(H.n, H.rp.data(), H.ci.data(), H.v.data(), H.prp.data(), H.pci.data(), H.pv.data(), H.nc, T);
+    if (!H.aprp.empty()) {
+        // A P as formed by the level's Galerkin product (the same product)
+        T.n = H.n;
+        T.rp = H.aprp;
+        T.ci = H.apci;
+        T.v = H.apv;
+    } else {
+        spgemm_raw(H.n, H.rp.data(), H.ci.data(), H.v.data(), H.prp.data(), H.pci.data(), H.pv.data(), H.nc, T);
+    }
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < H.n; i++) {
         int32_t m = H.prp[i];

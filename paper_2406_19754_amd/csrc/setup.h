@@ -32,6 +32,10 @@ struct HostLevel {
     std::vector<int32_t> prp, pci;
     std::vector<double> pv;
     double omega = 0.0;
+    // A_l P_l when the smoothed prolongator's Galerkin product formed it
+    // (reused for (I - M^-1 A) P; empty otherwise)
+    std::vector<int32_t> aprp, apci;
+    std::vector<double> apv;
     HostFai fai;                // AINV / INVK smoother (empty with l1-Jacobi)
 };
 
