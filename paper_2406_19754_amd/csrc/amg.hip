@@ -3056,7 +3056,10 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     h->nu = h->opts.smoother_sweeps;
     if (h->opts.vcycle_double < 0 || h->opts.vcycle_double > 1)
         return fail(PSC_ERR_ARG, "vcycle_double must be 0 or 1");
-    st = build_hierarchy(n, rp, ci, v, so, h->host, err);
+    {
+        PhaseTimer pt("hierarchy (host and device coarsening)");
+        st = build_hierarchy(n, rp, ci, v, so, h->host, err);
+    }
     if (st) return fail(st, err);
     const bool f32 = h->opts.build_fp32 != 0;
     h->has32 = f32;
@@ -3073,7 +3076,10 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
         *out = h.release();
         return PSC_OK;
     }
-    if ((st = upload_levels(h.get()))) return st;
+    {
+        PhaseTimer pt("pack and upload levels");
+        if ((st = upload_levels(h.get()))) return st;
+    }
     // solver workspace
     const int64_t N = n;
     if ((st = dalloc(h.get(), (void**)&h->ctl, sizeof(Ctl)))) return st;
@@ -3104,13 +3110,20 @@ int psc_amg_rebuild(psc_hier* h, const double* val) {
         HIPCHK(hipStreamSynchronize(h->stream));
     }
     h->stale = true;
-    int st = rebuild_numeric(h->host, val, setup_opts_of(h), err);
+    int st;
+    {
+        PhaseTimer pt("rebuild numerics");
+        st = rebuild_numeric(h->host, val, setup_opts_of(h), err);
+    }
     if (st) return fail(st, err);
     if (!h->opts.host_only) {
         // new values into the existing buffers when every size matches (the
         // captured iterations stay valid); otherwise release and re-upload
         h->refresh = true;
-        st = upload_levels(h);
+        {
+            PhaseTimer pt("rebuild: refresh level values");
+            st = upload_levels(h);
+        }
         h->refresh = false;
         if (st == PSC_ERR_STATE) {
             g_err.clear();

@@ -24,6 +24,8 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <omp.h>
 
@@ -570,7 +572,17 @@ void level_numeric(const Csr& A, const SetupOpts& o, HostLevel& F, HostLevel& Cl
     Cl.v.swap(Ac.v);
 }
 
+bool trace_on() {
+    static const bool on = std::getenv("PSC_SETUP_TRACE") != nullptr;
+    return on;
+}
+
 }  // namespace
+
+PhaseTimer::PhaseTimer(const char* n) : name(n), t0(omp_get_wtime()) {}
+PhaseTimer::~PhaseTimer() {
+    if (trace_on()) std::fprintf(stderr, "[psc setup] %s %.3f\n", name, omp_get_wtime() - t0);
+}
 
 void pack_ell(int64_t nrows, const int32_t* rp, const int32_t* ci, const double* v,
               std::vector<long long>& off, std::vector<double>& val, std::vector<int>& col) {
@@ -710,6 +722,7 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
         int64_t nc = 0;
         std::vector<int32_t> agg;
         bool have_agg = false;
+        PhaseTimer pt_level("coarsen level (aggregation + numerics)");
         if (o.device && o.aggr == 0) {
             // matching on the GPU; with the tentative prolongator the whole
             // coarsening (the smoothed one takes the aggregates, its products
@@ -745,6 +758,7 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
             if (st != PSC_OK) err.clear();
         }
         if (!have_agg) {
+            PhaseTimer pt("host aggregation");
             if (o.aggr == 0) coarsen(A, H.lev[l].w, o.sweeps, agg, nc);
             else vbm_aggregate(A, o.theta, agg, nc);
         }
@@ -753,7 +767,10 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
         HostLevel& Cl = H.lev[l + 1];
         F.nc = nc;
         F.agg.swap(agg);
-        level_numeric(A, o, F, Cl);
+        {
+            PhaseTimer pt("level numerics (prolongator, Galerkin)");
+            level_numeric(A, o, F, Cl);
+        }
         F.rp.swap(A.rp);
         F.ci.swap(A.ci);
         F.v.swap(A.v);
@@ -762,6 +779,7 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
 }
 
 int build_smoothers(HostHier& H, const SetupOpts& o, std::string& err) {
+    PhaseTimer pt("smoother factors");
     // AINV / INVK smoothers of the levels above the coarsest
     if (o.smoother == 1 || o.smoother == 2) {
         for (size_t l = 0; l + 1 < H.lev.size(); l++) {

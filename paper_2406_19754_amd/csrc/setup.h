@@ -59,6 +59,15 @@ struct SetupOpts {
     int fill1 = 0, fill2 = 1;   // INVK fill levels of the factor and of its inverse
 };
 
+// Setup phase trace: with the environment variable PSC_SETUP_TRACE set, the
+// build prints "[psc setup] <phase> <seconds>" lines to stderr.
+struct PhaseTimer {
+    const char* name;
+    double t0;
+    explicit PhaseTimer(const char* n);
+    ~PhaseTimer();
+};
+
 // Status codes follow psc.h.
 int validate_csr(int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
                  std::string& err);
