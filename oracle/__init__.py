@@ -56,7 +56,8 @@ def lib():
     L.orc_match.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p]
     L.orc_match.restype = C.c_int
     L.orc_build.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
-                            C.c_int, C.c_int, C.c_double, C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(vp)]
+                            C.c_int, C.c_int, C.c_double, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int,
+                            C.c_double, C.POINTER(vp)]
     L.orc_cheb4_apply.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, _f64p, _f64p]
     L.orc_cheb4_apply.restype = None
     L.orc_fai_nnz.argtypes = [vp, C.c_int]
@@ -175,12 +176,12 @@ class Hierarchy:
 
     def __init__(self, rowptr, col, val, sweeps=2, coarse_max=200, max_levels=30, coarse_sweeps=30,
                  prol=0, nu=1, nu_double=False, aggr=0, theta=0.01, smoother=SMOOTH_L1JACOBI, ainv_tau=0.1,
-                 invk_fill=0, invk_inv_fill=1):
+                 invk_fill=0, invk_inv_fill=1, coarse_pcg=0, coarse_rtol=1e-4):
         self._rowptr, self._col, self._val = _i32(rowptr), _i32(col), _f64(val)
         h = C.c_void_p()
         st = lib().orc_build(len(rowptr) - 1, self._rowptr, self._col, self._val,
                              sweeps, coarse_max, max_levels, coarse_sweeps, prol, nu, int(nu_double), aggr, theta,
-                             smoother, ainv_tau, invk_fill, invk_inv_fill, C.byref(h))
+                             smoother, ainv_tau, invk_fill, invk_inv_fill, coarse_pcg, coarse_rtol, C.byref(h))
         self.status = st
         if st != OK:
             raise RuntimeError(f"oracle build failed with status {st}")
