@@ -124,7 +124,13 @@ def time_configs(args, psc, torch, rp, col, val, bd, x, ms64=None):
              "invk00": dict(smoother=psc.SMOOTH_INVK, invk_fill=0, invk_inv_fill=0),
              "cheb1": dict(smoother=psc.SMOOTH_CHEB4, smoother_sweeps=1),
              "cheb2": dict(smoother=psc.SMOOTH_CHEB4, smoother_sweeps=2),
-             "cheb3": dict(smoother=psc.SMOOTH_CHEB4, smoother_sweeps=3)}
+             "cheb3": dict(smoother=psc.SMOOTH_CHEB4, smoother_sweeps=3),
+             # the paper's settings with its inexact coarsest solver (at most 40
+             # l1-Jacobi PCG iterations), solved with FCG as in the paper
+             "smatch_paper": dict(sweeps=3, smoothed_prol=True, smoother_sweeps=4, coarse_pcg_iters=40),
+             "vmatch_paper": dict(sweeps=3, smoother_sweeps=2, vcycle_double=True, coarse_pcg_iters=40),
+             "vbm_paper": dict(aggregation=psc.AGGR_VBM, vbm_theta=0.01, smoothed_prol=True, smoother_sweeps=4,
+                               coarse_pcg_iters=40)}
     for cfg in [c for c in args.configs.split(",") if c]:
         t0 = time.time()
         hs = psc.Hierarchy(rp, col, val, build_fp32=not args.no_mixed, use_graph=not args.no_graph,
@@ -133,11 +139,13 @@ def time_configs(args, psc, torch, rp, col, val, bd, x, ms64=None):
         log(f"{cfg} hierarchy {infs['rows']} built in {time.time() - t0:.1f}s, "
             f"opcx {infs['operator_complexity']:.4f}")
         for form in ["fp64"] + ([] if args.no_mixed else ["mixed"]):
+            inexact = extra[cfg].get("coarse_pcg_iters", 0) > 0
+
             def run_s():
                 x.zero_()
-                if form == "fp64":
+                if form == "fp64" and not inexact:
                     return hs.pcg(bd, x, rtol=1e-6, maxit=500)
-                return hs.fcg(bd, x, rtol=1e-6, maxit=500, prec=psc.FP32)
+                return hs.fcg(bd, x, rtol=1e-6, maxit=500, prec=psc.FP64 if form == "fp64" else psc.FP32)
             for _ in range(args.warmup):
                 run_s()
             torch.cuda.synchronize()
@@ -195,7 +203,8 @@ def main():
                          "vbm (strength-based aggregation, smoothed prolongator, 4 sweeps), "
                          "ainv (AINV smoother, drop tolerance 0.1), invk (INVK smoother, fill 0, inverse fill 1), "
                          "invk00 (INVK, no inverse fill), cheb1/cheb2/cheb3 (fourth-kind Chebyshev "
-                         "polynomial smoother of degree 1/2/3)")
+                         "polynomial smoother of degree 1/2/3), smatch_paper/vmatch_paper/vbm_paper (the paper's "
+                         "settings with at most 40 l1-Jacobi PCG iterations on the coarsest level, FCG)")
     ap.add_argument("--only-configs", action="store_true",
                     help="time only the --configs settings (no headline solve; one JSON line of their results)")
     ap.add_argument("--rebuild-timing", action="store_true",

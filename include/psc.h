@@ -120,6 +120,17 @@ typedef struct psc_net  psc_net;    /* opaque: owns the learned preconditioner  
  *                    no eigenvalue estimate is needed; its error propagation is
  *                    W_nu(I - 2 M^-1 A) / (2 nu + 1), W the Chebyshev polynomial
  *                    of the fourth kind. Degree 1 is l1-Jacobi weighted 4/3.
+ *   coarse_pcg_iters = 0  > 0: the coarsest level, where it would be
+ *                    factored, is solved instead by at most this many
+ *                    iterations of CG preconditioned by l1-Jacobi from a zero
+ *                    guess, stopped at ||r|| <= coarse_rtol ||b|| (the paper's
+ *                    coarsest solver in its tests, Section "Algorithmic tests",
+ *                    with 40 iterations). The V-cycle then depends nonlinearly
+ *                    on its input: use psc_fcg_solve. Runs in one workgroup;
+ *                    the coarsest level must have at most 4096 rows
+ *                    (PSC_ERR_ARG otherwise). Coarsest levels left by a stall
+ *                    above 2000 rows keep their l1-Jacobi sweeps.
+ *   coarse_rtol = 1e-4  tolerance of that solve (>= 0; 0: always the cap).
  *   ainv_tau = 0.1   AINV drop tolerance (>= 0).
  *   invk_fill = 0, invk_inv_fill = 1   INVK levels of fill (0..64).
  *   host_only = 0    build the hierarchy on the host only and make no HIP
@@ -153,6 +164,9 @@ typedef struct {
     int32_t reserved;
     double  vbm_theta;
     double  ainv_tau;
+    int32_t coarse_pcg_iters;
+    int32_t reserved2;
+    double  coarse_rtol;
 } psc_amg_opts;
 
 void psc_amg_opts_default(psc_amg_opts* opts);
@@ -271,6 +285,7 @@ typedef struct {
     int32_t smoother;
     int64_t smoother_nnz[PSC_MAX_LEVELS];    /* AINV / INVK: nonzeros of Z_l (0 otherwise) */
     double  rebuild_seconds;                 /* wall time of the last psc_amg_rebuild (0: none) */
+    int32_t coarse_pcg_iters;                /* > 0: coarsest solved by at most this many PCG iterations */
 } psc_hier_stats;
 
 int psc_hier_info(const psc_hier* h, psc_hier_stats* s);

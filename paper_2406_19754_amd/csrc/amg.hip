@@ -1228,6 +1228,107 @@ __global__ __launch_bounds__(WG) void k_jacobi(M A, const double* __restrict__ m
 // handle
 // ---------------------------------------------------------------------------
 
+// Coarsest level by at most maxit iterations of l1-Jacobi preconditioned CG
+// from x = 0, stopped at ||r|| <= rtol ||b||, in FP64, in one workgroup of
+// CPCG_WG threads: thread t owns rows t, t + CPCG_WG, ... (at most
+// CPCG_ROWS), keeping x, r, z and q in registers; the direction p lives in
+// LDS, where the product A p gathers it (hacked-ELL rows, padding is 0).
+// Block sums are formed in a fixed order and broadcast, so every thread
+// takes the same branches and the loop ends after at most maxit iterations.
+constexpr int CPCG_WG = 1024;
+constexpr int CPCG_ROWS = 4;
+constexpr int CPCG_MAX = CPCG_WG * CPCG_ROWS;
+
+__device__ double cpcg_sum(double v, double* red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();   // earlier readers of red are done
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < CPCG_WG / 64; k++) t += red[k];
+    return t;
+}
+
+template <typename TB, typename TX>
+__global__ __launch_bounds__(CPCG_WG) void k_coarse_pcg(Ell<double> A, const double* __restrict__ minv,
+                                                        const TB* __restrict__ b, TX* __restrict__ x, int maxit,
+                                                        double rtol, Gate g) {
+    if (gate_skip(g)) return;
+    __shared__ double p[CPCG_MAX];
+    __shared__ double red[CPCG_WG / 64];
+    const int n = (int)A.nrows;
+    double xr[CPCG_ROWS], rr[CPCG_ROWS], zr[CPCG_ROWS], qr[CPCG_ROWS];
+    double bb = 0.0, rz0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < CPCG_ROWS; k++) {
+        const int i = threadIdx.x + k * CPCG_WG;
+        xr[k] = 0.0;
+        rr[k] = i < n ? (double)b[i] : 0.0;
+        zr[k] = i < n ? minv[i] * rr[k] : 0.0;
+        if (i < n) p[i] = zr[k];
+        bb += rr[k] * rr[k];
+        rz0 += rr[k] * zr[k];
+    }
+    const double bn = sqrt(cpcg_sum(bb, red));
+    double rz = cpcg_sum(rz0, red);
+    if (bn > 0.0) {
+        for (int it = 0; it < maxit && rz > 0.0; it++) {
+            __syncthreads();   // p complete
+            double pq = 0.0;
+#pragma unroll
+            for (int k = 0; k < CPCG_ROWS; k++) {
+                const int i = threadIdx.x + k * CPCG_WG;
+                qr[k] = 0.0;
+                if (i < n) {
+                    const long long s = i / SLICE, o = A.off[s];
+                    const int w = (int)((A.off[s + 1] - o) / SLICE), lane = i % SLICE;
+                    double acc = 0.0;
+                    for (int e = 0; e < w; e++) acc += A.val[o + (long long)e * SLICE + lane] * p[A.col[o + (long long)e * SLICE + lane]];
+                    qr[k] = acc;
+                    pq += p[i] * acc;
+                }
+            }
+            pq = cpcg_sum(pq, red);
+            if (!(pq > 0.0)) break;
+            const double alpha = rz / pq;
+            double rn = 0.0;
+#pragma unroll
+            for (int k = 0; k < CPCG_ROWS; k++) {
+                const int i = threadIdx.x + k * CPCG_WG;
+                if (i < n) {
+                    xr[k] += alpha * p[i];
+                    rr[k] -= alpha * qr[k];
+                    rn += rr[k] * rr[k];
+                }
+            }
+            rn = cpcg_sum(rn, red);
+            if (sqrt(rn) <= rtol * bn) break;
+            double rz2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < CPCG_ROWS; k++) {
+                const int i = threadIdx.x + k * CPCG_WG;
+                zr[k] = i < n ? minv[i] * rr[k] : 0.0;
+                rz2 += rr[k] * zr[k];
+            }
+            rz2 = cpcg_sum(rz2, red);
+            const double beta = rz2 / rz;
+            // every read of p in this iteration happened before the sums above
+#pragma unroll
+            for (int k = 0; k < CPCG_ROWS; k++) {
+                const int i = threadIdx.x + k * CPCG_WG;
+                if (i < n) p[i] = zr[k] + beta * p[i];
+            }
+            rz = rz2;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < CPCG_ROWS; k++) {
+        const int i = threadIdx.x + k * CPCG_WG;
+        if (i < n) x[i] = (TX)xr[k];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Factored approximate inverse smoothers (AINV / INVK): a sweep is
 // x <- x + Z (W (b - A x)) with W = D^-1 Z^T, both stored as hacked ELL
@@ -1894,6 +1995,11 @@ static void finish(psc_hier* h, const Red& R, int grid) {
 template <typename TB, typename TX>
 static void coarse_solve(psc_hier* h, const TB* b, TX* x, Gate g) {
     DevLevel& C = h->lev.back();
+    if (h->host.coarse_pcg > 0) {
+        k_coarse_pcg<TB, TX><<<1, CPCG_WG, 0, h->stream>>>(C.A.view(), C.minv, b, x, h->host.coarse_pcg,
+                                                          h->host.coarse_rtol, g);
+        return;
+    }
     const int K = h->host.coarse_sweeps;
     if (K == 0) {
         k_coarse<TB, TX><<<1, WG, 0, h->stream>>>(h->coarse_n, h->coarse_invT, b, x, g);
@@ -1948,7 +2054,8 @@ static TailLevel<T> tail_level(const psc_hier* h, const DevLevel& V) {
 static int build_tail(psc_hier* h) {
     const int L = (int)h->lev.size();
     h->tail_t = 0;
-    if (L < 3 || h->host.coarse_sweeps > 0 || !h->split || h->opts.vcycle_double || h->nu != 1 || h->fai || h->cheb)
+    if (L < 3 || h->host.coarse_sweeps > 0 || h->host.coarse_pcg > 0 || !h->split || h->opts.vcycle_double ||
+        h->nu != 1 || h->fai || h->cheb)
         return PSC_OK;
     int t = L - 1;
     while (t - 1 >= 1 && h->lev[t - 1].n <= h->tail_rows) t--;
@@ -2313,7 +2420,7 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
     R0.fin = FIN_NONE;
     TimeScope whole(h, 6);
     if (L == 1) {
-        k_coarse<double, double><<<1, WG, 0, st>>>(h->coarse_n, h->coarse_invT, r0, z0, g);
+        coarse_solve<double, double>(h, r0, z0, g);
         if (fin != FIN_NONE) {
             int gr = grid_vec(h, h->lev[0].n);
             k_dot<<<gr, WG, 0, st>>>(h->lev[0].n, z0, d, R);
@@ -2812,6 +2919,8 @@ static SetupOpts setup_opts_of(const psc_hier* h) {
     so.tau = h->opts.ainv_tau;
     so.fill1 = h->opts.invk_fill;
     so.fill2 = h->opts.invk_inv_fill;
+    so.coarse_pcg = h->opts.coarse_pcg_iters;
+    so.coarse_rtol = h->opts.coarse_rtol;
     return so;
 }
 
@@ -2963,7 +3072,7 @@ static int upload_levels(psc_hier* h) {
     }
     // coarsest inverse, stored transposed for coalesced reads
     h->coarse_n = (int)h->host.lev[L - 1].n;
-    if (h->host.coarse_sweeps == 0) {
+    if (h->host.coarse_sweeps == 0 && h->host.coarse_pcg == 0) {
         int nc = h->coarse_n;
         std::vector<double> invT((size_t)nc * nc);
         for (int i = 0; i < nc; i++)
@@ -3003,6 +3112,8 @@ void psc_amg_opts_default(psc_amg_opts* o) {
     o->invk_fill = 0;
     o->invk_inv_fill = 1;
     o->ainv_tau = 0.1;
+    o->coarse_pcg_iters = 0;
+    o->coarse_rtol = 1e-4;
 }
 
 void psc_hier_free(psc_hier* h) {
@@ -3078,6 +3189,8 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     }
     {
         PhaseTimer pt("pack and upload levels");
+            if (h->host.coarse_pcg > 0 && h->host.lev.back().n > CPCG_MAX)
+            return fail(PSC_ERR_ARG, "the PCG coarsest solver takes at most 4096 rows");
         if ((st = upload_levels(h.get()))) return st;
     }
     // solver workspace
@@ -3273,6 +3386,7 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
     s->smoothed_prol = h->opts.smoothed_prol;
     s->smoother = h->opts.smoother;
     s->rebuild_seconds = h->rebuild_seconds;
+    s->coarse_pcg_iters = h->host.coarse_pcg;
     if (h->opts.host_only)
         for (int l = 0; l + 1 < L; l++) s->smoother_nnz[l] = (int64_t)h->host.lev[l].fai.zi.size();
     return PSC_OK;

@@ -669,7 +669,8 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
     if (o.sweeps < 1 || o.sweeps > 8 || o.coarse_max < 1 || o.max_levels < 1 ||
         o.max_levels > PSC_MAX_LEVELS || o.coarse_sweeps < 0 || o.coarse_sweeps > 1000 || o.aggr < 0 ||
         o.aggr > 1 || !(o.theta >= 0.0 && o.theta < 1.0) || o.smoother < 0 || o.smoother > 3 ||
-        !(o.tau >= 0.0) || o.fill1 < 0 || o.fill1 > 64 || o.fill2 < 0 || o.fill2 > 64) {
+        !(o.tau >= 0.0) || o.fill1 < 0 || o.fill1 > 64 || o.fill2 < 0 || o.fill2 > 64 || o.coarse_pcg < 0 ||
+        o.coarse_pcg > 10000 || !(o.coarse_rtol >= 0.0)) {
         err = "invalid hierarchy options";
         return PSC_ERR_ARG;
     }
@@ -712,7 +713,10 @@ int build_hierarchy(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
             if (A.n > 4096) { err = "coarsest level too large for a dense solve"; return PSC_ERR_COARSEN; }
             H.lev[l].nc = 0;
             H.coarse_sweeps = 0;
-            st = coarse_inverse(A, H.coarse_inv);
+            H.coarse_pcg = o.coarse_pcg;
+            H.coarse_rtol = o.coarse_rtol;
+            if (o.coarse_pcg > 0) H.coarse_inv.clear();   // inexact PCG solve instead of the factor
+            else st = coarse_inverse(A, H.coarse_inv);
             H.lev[l].rp.swap(A.rp);
             H.lev[l].ci.swap(A.ci);
             H.lev[l].v.swap(A.v);
@@ -823,7 +827,8 @@ int rebuild_numeric(HostHier& H, const double* v0, const SetupOpts& o, std::stri
         A.ci.swap(F.ci);
         A.v.swap(F.v);
         int st = l1_inverse_diag(A, F.minv);
-        if (st == PSC_OK && l + 1 == L && H.coarse_sweeps == 0) st = coarse_inverse(A, H.coarse_inv);
+        if (st == PSC_OK && l + 1 == L && H.coarse_sweeps == 0 && H.coarse_pcg == 0)
+            st = coarse_inverse(A, H.coarse_inv);
         if (st == PSC_OK && l + 1 < L) level_numeric(A, o, F, H.lev[l + 1]);
         F.rp.swap(A.rp);
         F.ci.swap(A.ci);

@@ -43,6 +43,8 @@ struct HostHier {
     std::vector<HostLevel> lev;
     std::vector<double> coarse_inv;   // dense inverse of the coarsest A, row-major
     int coarse_sweeps = 0;            // > 0: coarsest solved by l1-Jacobi sweeps instead
+    int coarse_pcg = 0;               // > 0: coarsest solved by at most this many l1-Jacobi PCG iterations
+    double coarse_rtol = 1e-4;        // their relative residual tolerance
 };
 
 struct SetupOpts {
@@ -57,6 +59,8 @@ struct SetupOpts {
     int smoother = 0;           // 0 l1-Jacobi, 1 AINV, 2 INVK, 3 polynomial (levels above the coarsest)
     double tau = 0.1;           // AINV drop tolerance
     int fill1 = 0, fill2 = 1;   // INVK fill levels of the factor and of its inverse
+    int coarse_pcg = 0;         // > 0: factored coarsest replaced by at most this many PCG iterations
+    double coarse_rtol = 1e-4;
 };
 
 // Setup phase trace: with the environment variable PSC_SETUP_TRACE set, the

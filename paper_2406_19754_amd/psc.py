@@ -44,7 +44,8 @@ class AmgOpts(C.Structure):
                 ("coarse_sweeps", C.c_int32), ("smoothed_prol", C.c_int32), ("smoother_sweeps", C.c_int32),
                 ("vcycle_double", C.c_int32), ("aggregation", C.c_int32), ("setup_device", C.c_int32),
                 ("smoother", C.c_int32), ("invk_fill", C.c_int32), ("invk_inv_fill", C.c_int32),
-                ("reserved", C.c_int32), ("vbm_theta", C.c_double), ("ainv_tau", C.c_double)]
+                ("reserved", C.c_int32), ("vbm_theta", C.c_double), ("ainv_tau", C.c_double),
+                ("coarse_pcg_iters", C.c_int32), ("reserved2", C.c_int32), ("coarse_rtol", C.c_double)]
 
 
 class HierStats(C.Structure):
@@ -58,7 +59,8 @@ class HierStats(C.Structure):
                 ("dia_slots", C.c_int64 * MAX_LEVELS), ("p_nnz", C.c_int64 * MAX_LEVELS),
                 ("omega", C.c_double * MAX_LEVELS), ("smoother_sweeps", C.c_int32), ("smoothed_prol", C.c_int32),
                 ("vcycle_double", C.c_int32), ("aggregation", C.c_int32), ("smoother", C.c_int32),
-                ("smoother_nnz", C.c_int64 * MAX_LEVELS), ("rebuild_seconds", C.c_double)]
+                ("smoother_nnz", C.c_int64 * MAX_LEVELS), ("rebuild_seconds", C.c_double),
+                ("coarse_pcg_iters", C.c_int32)]
 
 
 def _load():
@@ -151,7 +153,8 @@ class Hierarchy:
     def __init__(self, rowptr, col, val, sweeps=2, coarse_max=200, max_levels=30,
                  build_fp32=False, use_graph=True, host_only=False, stream=None, coarse_sweeps=30,
                  smoothed_prol=False, smoother_sweeps=1, vcycle_double=False, aggregation=0, vbm_theta=0.01,
-                 setup_device=True, smoother=SMOOTH_L1JACOBI, ainv_tau=0.1, invk_fill=0, invk_inv_fill=1):
+                 setup_device=True, smoother=SMOOTH_L1JACOBI, ainv_tau=0.1, invk_fill=0, invk_inv_fill=1,
+                 coarse_pcg_iters=0, coarse_rtol=1e-4):
         import torch
         o = AmgOpts()
         _lib.psc_amg_opts_default(C.byref(o))
@@ -162,6 +165,7 @@ class Hierarchy:
         o.aggregation, o.vbm_theta = aggregation, vbm_theta
         o.setup_device = int(setup_device)
         o.smoother, o.ainv_tau, o.invk_fill, o.invk_inv_fill = smoother, ainv_tau, invk_fill, invk_inv_fill
+        o.coarse_pcg_iters, o.coarse_rtol = coarse_pcg_iters, coarse_rtol
         o.build_fp32, o.use_graph, o.host_only = int(build_fp32), int(use_graph), int(host_only)
         rp, prp = _hptr(rowptr, np.int32)
         ci, pci = _hptr(col, np.int32)
@@ -191,7 +195,7 @@ class Hierarchy:
                     p_nnz=list(s.p_nnz[:L]), omega=list(s.omega[:L]), smoother_sweeps=s.smoother_sweeps,
                     smoothed_prol=s.smoothed_prol, vcycle_double=s.vcycle_double, aggregation=s.aggregation,
                     smoother=s.smoother, smoother_nnz=list(s.smoother_nnz[:L]),
-                    rebuild_seconds=s.rebuild_seconds)
+                    rebuild_seconds=s.rebuild_seconds, coarse_pcg_iters=s.coarse_pcg_iters)
 
     def rebuild(self, val):
         """Numeric-only rebuild with new values of A (same pattern as at build)."""

@@ -1,0 +1,76 @@
+"""GPU parity of the inexact coarsest solver (at most k l1-Jacobi PCG
+iterations in one workgroup) against the oracle. CG iterates drift apart by
+rounding (different reduction order), so the V-cycle is compared at 1e-10
+relative with a fixed iteration count (rtol 0); with the tolerance on, the
+outer FCG solves are compared by iterations (+-2) and true residual."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle
+from paper_2406_19754_amd import problems as P
+
+
+@pytest.fixture(scope="module")
+def psc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_19754_amd import psc as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("case", ["random60", "poisson6", "random3000"])
+@pytest.mark.parametrize("k", [1, 3, 12])
+def test_single_level_pcg_matches_oracle(psc, case, k):
+    rp, c, v = {"random60": lambda: P.random_spd_csr(60, 7, density=0.1), "poisson6": lambda: P.poisson7(6),
+                "random3000": lambda: P.random_spd_csr(3000, 5, density=0.002, maxrow=20)}[case]()
+    n = len(rp) - 1
+    h = psc.Hierarchy(rp, c, v, coarse_max=n, coarse_pcg_iters=k, coarse_rtol=0.0)
+    o = oracle.Hierarchy(rp, c, v, coarse_max=n, coarse_pcg=k, coarse_rtol=0.0)
+    assert h.info()["levels"] == 1 == o.nlevels and h.info()["coarse_pcg_iters"] == k
+    b = np.random.default_rng(k).standard_normal(n)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.vcycle(dev(b), z)
+    ref = o.vcycle(b)
+    assert np.linalg.norm(z.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+CONFIGS = {
+    # the paper's three settings with its inexact coarsest solver
+    "vmatch": (dict(sweeps=3, smoother_sweeps=2, vcycle_double=True), dict(sweeps=3, nu=2, nu_double=True)),
+    "smatch": (dict(sweeps=3, smoothed_prol=True, smoother_sweeps=4), dict(sweeps=3, prol=1, nu=4)),
+    "vbm": (dict(aggregation=1, smoothed_prol=True, smoother_sweeps=4), dict(aggr=1, prol=1, nu=4)),
+}
+
+
+@pytest.mark.parametrize("cfg", list(CONFIGS))
+def test_paper_settings_with_inexact_coarsest(psc, cfg):
+    rp, c, v = P.poisson7(24)
+    n = len(rp) - 1
+    lo, oo = CONFIGS[cfg]
+    # fixed iteration count: V-cycle parity
+    h = psc.Hierarchy(rp, c, v, build_fp32=True, coarse_pcg_iters=40, coarse_rtol=0.0, **lo)
+    o = oracle.Hierarchy(rp, c, v, coarse_pcg=40, coarse_rtol=0.0, **oo)
+    assert h.info()["rows"] == o.sizes()
+    r = np.random.default_rng(4).standard_normal(n)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.vcycle(dev(r), z)
+    ref = o.vcycle(r)
+    assert np.linalg.norm(z.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
+    # with the tolerance: FCG as in the paper
+    h = psc.Hierarchy(rp, c, v, build_fp32=True, coarse_pcg_iters=40, coarse_rtol=1e-4, **lo)
+    o = oracle.Hierarchy(rp, c, v, coarse_pcg=40, coarse_rtol=1e-4, **oo)
+    b = P.rhs_from_solution(rp, c, v, P.x_true(n, 1))
+    ro = o.fcg(b)
+    assert ro["status"] == oracle.OK
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for prec in (psc.FP64, psc.FP32):
+        x.zero_()
+        g = h.fcg(dev(b), x, prec=prec)
+        assert g["status"] == psc.OK and g["relres"] <= 1e-6 and abs(g["iters"] - ro["iters"]) <= 2
