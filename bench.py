@@ -192,6 +192,10 @@ def main():
     ap.add_argument("--grid-max", type=int, default=0, help="workgroup cap of the streaming kernels")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-dia", action="store_true", help="read level operators from hacked ELL only")
+    ap.add_argument("--no-dia-uniform", action="store_true",
+                    help="hacked DIA with per-slice offset arrays instead of uniform offsets in the kernel argument")
+    ap.add_argument("--xcd-chunks", action="store_true",
+                    help="give each accelerator die a contiguous chunk of the work (default: launch order)")
     ap.add_argument("--tail-rows", type=int, default=-1,
                     help="levels up to this many rows run in one workgroup (0: launch their kernels one by one)")
     ap.add_argument("--coarse-sweeps", type=int, default=30,
@@ -296,6 +300,10 @@ def main():
         h.tune(psc.TUNE_SPLIT, 0)
     if args.no_dia:
         h.tune(psc.TUNE_DIA, 0)
+    if args.no_dia_uniform:
+        h.tune(psc.TUNE_DIA_UNIFORM, 0)
+    if args.xcd_chunks:
+        h.tune(psc.TUNE_XCD, 1)
     if args.tail_rows >= 0:
         h.tune(psc.TUNE_TAIL, args.tail_rows)
     info = h.info()

@@ -380,6 +380,17 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
  * workgroup per V-cycle (one sweep, split operators); 0 launches their
  * kernels one by one, which is as fast or faster under graph replay. */
 #define PSC_TUNE_TAIL 8
+/* PSC_TUNE_DIA_UNIFORM (default 1): a level whose hacked-DIA copy has at most 8
+ * distinct diagonals over the whole matrix stores every slice with all of them
+ * and passes the offsets in the kernel argument (no per-slice metadata load);
+ * 0 reads the per-slice offset arrays instead (same values and results). */
+#define PSC_TUNE_DIA_UNIFORM 9
+/* PSC_TUNE_XCD (default 0): 1 makes the streaming kernels give each
+ * accelerator die a contiguous chunk of the work (workgroups are dealt to the
+ * 8 dies round robin); 0 lets workgroups take the work in launch order, which
+ * measured faster (all dies share the neighbour gathers through the Infinity
+ * Cache). This setting is per device and applies to every handle on it. */
+#define PSC_TUNE_XCD 10
 int psc_tune(psc_hier* h, int32_t key, int32_t value);
 
 void psc_hier_free(psc_hier* h);

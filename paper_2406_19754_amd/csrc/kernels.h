@@ -62,6 +62,10 @@ struct Ell {
 // offsets offs[k] = column - row (ascending) and values at val[k*64 + lane],
 // zero where the row stores nothing on that diagonal. A 7-point stencil slice
 // keeps 7 diagonals: 8 bytes per entry instead of 12 for hacked ELL.
+//
+// Uniform variant (nd > 0): every slice holds the same nd <= 8 diagonals, at
+// the offsets uo[0..nd) carried in the kernel argument itself (start[s] =
+// s*nd still holds), so a slice needs no metadata load before its gathers.
 template <typename T>
 struct Dia {
     using value_type = T;
@@ -71,6 +75,8 @@ struct Dia {
     long long nrows;
     long long nslices;
     long long ncols;
+    int nd = 0;
+    int uo[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 }  // namespace psc

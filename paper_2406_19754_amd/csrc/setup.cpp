@@ -22,6 +22,7 @@
 #include "setup.h"
 
 #include <algorithm>
+#include <iterator>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -874,10 +875,11 @@ void jacobi_smoothed_prolongator(const HostLevel& H, const double* minv, std::ve
 
 bool pack_dia(int64_t nrows, int64_t ncols, const int32_t* rp, const int32_t* ci, const double* v,
               long long max_slots, std::vector<int32_t>& start, std::vector<int32_t>& offs,
-              std::vector<double>& val) {
+              std::vector<double>& val, std::vector<int32_t>* uniform) {
     start.clear();
     offs.clear();
     val.clear();
+    if (uniform) uniform->clear();
     if (nrows + 64 + ncols >= (int64_t)1 << 30) return false;
     const int64_t ns = (nrows + 63) / 64;
     std::vector<int64_t> cnt(ns + 1, 0);
@@ -889,14 +891,56 @@ bool pack_dia(int64_t nrows, int64_t ncols, const int32_t* rp, const int32_t* ci
         std::sort(o.begin(), o.end());
         o.erase(std::unique(o.begin(), o.end()), o.end());
     };
+    // union of the slices' offsets (kept while it has at most 8 members)
+    std::vector<int32_t> uni;
+    bool uni_ok = uniform != nullptr;
 #pragma omp parallel
     {
-        std::vector<int32_t> o;
+        std::vector<int32_t> o, mine;
+        bool mine_ok = true;
 #pragma omp for schedule(static)
         for (int64_t s = 0; s < ns; s++) {
             slice_offsets(s, o);
             cnt[s + 1] = (int64_t)o.size();
+            if (mine_ok) {
+                std::vector<int32_t> u;
+                std::set_union(mine.begin(), mine.end(), o.begin(), o.end(), std::back_inserter(u));
+                mine.swap(u);
+                mine_ok = mine.size() <= 8;
+            }
         }
+#pragma omp critical
+        {
+            if (!mine_ok) uni_ok = false;
+            if (uni_ok) {
+                std::vector<int32_t> u;
+                std::set_union(uni.begin(), uni.end(), mine.begin(), mine.end(), std::back_inserter(u));
+                uni.swap(u);
+                if (uni.size() > 8) uni_ok = false;
+            }
+        }
+    }
+    if (uni_ok && !uni.empty() && (int64_t)uni.size() * ns * 64 <= max_slots &&
+        (int64_t)uni.size() * ns < ((int64_t)1 << 31)) {
+        // uniform layout: every slice holds the union's diagonals
+        const int64_t nd = (int64_t)uni.size();
+        start.resize(ns + 1);
+        for (int64_t s = 0; s <= ns; s++) start[s] = (int32_t)(s * nd);
+        offs.resize(ns * nd);
+        for (int64_t s = 0; s < ns; s++) std::copy(uni.begin(), uni.end(), offs.begin() + s * nd);
+        val.assign((size_t)(ns * nd) * 64, 0.0);
+#pragma omp parallel for schedule(static)
+        for (int64_t s = 0; s < ns; s++) {
+            const int64_t r1 = std::min<int64_t>(nrows, (s + 1) * 64);
+            for (int64_t i = s * 64; i < r1; i++)
+                for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
+                    const int32_t d = (int32_t)(ci[k] - i);
+                    const int64_t kk = std::lower_bound(uni.begin(), uni.end(), d) - uni.begin();
+                    val[(size_t)(s * nd + kk) * 64 + (size_t)(i - s * 64)] = v[k];
+                }
+        }
+        *uniform = uni;
+        return true;
     }
     for (int64_t s = 0; s < ns; s++) cnt[s + 1] += cnt[s];
     if (cnt[ns] * 64 > max_slots || cnt[ns] >= ((int64_t)1 << 31)) return false;

@@ -115,9 +115,12 @@ int gpu_coarsen_level(int64_t n, const int32_t* rp, const int32_t* ci, const dou
 // slice, values diagonal-major in a slice, zeros where a row has no entry).
 // Returns false and packs nothing when the diagonal slots would exceed
 // max_ratio times max_slots, or when row + offset could leave int32.
+// With uniform != NULL and at most 8 distinct offsets over the whole matrix,
+// every slice gets all of them (zeros where a row has no entry) and *uniform
+// receives the offsets (ascending); otherwise it is left empty.
 bool pack_dia(int64_t nrows, int64_t ncols, const int32_t* rp, const int32_t* ci, const double* v,
               long long max_slots, std::vector<int32_t>& start, std::vector<int32_t>& offs,
-              std::vector<double>& val);
+              std::vector<double>& val, std::vector<int32_t>* uniform = nullptr);
 
 // Pack CSR rows into hacked ELL with 64-row slices (column-major in a
 // slice). Padding slots carry value 0 and repeat the row's last column (0 for

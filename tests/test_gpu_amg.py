@@ -246,7 +246,7 @@ def test_fused_and_unfused_iterations_agree(psc, case, form):
 
 
 @pytest.mark.parametrize("knob", ["tail_off", "tail_4096", "dia_off", "split_off", "bufload_all", "bufload_none", "unroll4", "grid256",
-                                  "spmv2"])
+                                  "spmv2", "dia_per_slice", "xcd_chunks"])
 @pytest.mark.parametrize("case", ["poisson13", "random_long_rows", "diffusion20_az100"])
 def test_kernel_variants_match_oracle(psc, case, knob):
     rp, c, v = CASES[case]()
@@ -263,6 +263,10 @@ def test_kernel_variants_match_oracle(psc, case, knob):
         h.tune(psc.TUNE_TAIL, 0)
     if knob == "tail_4096":
         h.tune(psc.TUNE_TAIL, 4096)
+    if knob == "dia_per_slice":
+        h.tune(psc.TUNE_DIA_UNIFORM, 0)
+    if knob == "xcd_chunks":
+        h.tune(psc.TUNE_XCD, 1)
     if knob in ("split_off", "bufload_all", "bufload_none", "unroll4"):
         h.tune(psc.TUNE_SPLIT, 0)                    # sweeps gather through A, M^-1, P
     if knob == "bufload_all":
@@ -274,7 +278,7 @@ def test_kernel_variants_match_oracle(psc, case, knob):
         h.tune(psc.TUNE_UNROLL4, 1)
     elif knob == "spmv2":
         h.tune(psc.TUNE_SPMV2, 1)
-    else:
+    elif knob == "grid256":
         h.tune(psc.TUNE_GRID_MAX, 256)               # several slices per wavefront
     o = oracle.Hierarchy(rp, c, v, coarse_max=cm)
     n = len(rp) - 1
@@ -298,6 +302,8 @@ def test_kernel_variants_match_oracle(psc, case, knob):
     g = h.fcg(dev(b), xg, prec=psc.FP32)
     r = o.fcg(b, form=1)
     assert abs(g["iters"] - r["iters"]) <= 1 and g["relres"] <= 1e-6
+    if knob == "xcd_chunks":
+        h.tune(psc.TUNE_XCD, 0)                      # per device: restore the default for later tests
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
