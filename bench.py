@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--no-dia", action="store_true", help="read level operators from hacked ELL only")
     ap.add_argument("--no-dia-uniform", action="store_true",
                     help="hacked DIA with per-slice offset arrays instead of uniform offsets in the kernel argument")
+    ap.add_argument("--mixed-fused", action="store_true",
+                    help="FP32 V-cycle: fuse the residual update with the level-0 pre-smoothing")
     ap.add_argument("--xcd-chunks", action="store_true",
                     help="give each accelerator die a contiguous chunk of the work (default: launch order)")
     ap.add_argument("--tail-rows", type=int, default=-1,
@@ -304,6 +306,8 @@ def main():
         h.tune(psc.TUNE_DIA_UNIFORM, 0)
     if args.xcd_chunks:
         h.tune(psc.TUNE_XCD, 1)
+    if args.mixed_fused:
+        h.tune(psc.TUNE_MIXED_SPLIT, 0)
     if args.tail_rows >= 0:
         h.tune(psc.TUNE_TAIL, args.tail_rows)
     info = h.info()

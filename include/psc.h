@@ -391,6 +391,12 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
  * measured faster (all dies share the neighbour gathers through the Infinity
  * Cache). This setting is per device and applies to every handle on it. */
 #define PSC_TUNE_XCD 10
+/* PSC_TUNE_MIXED_SPLIT (default 1): in the FP32-V-cycle FCG iteration, the
+ * residual update r -= alpha q (with an FP32 copy of r) and the level-0 FP32
+ * pre-smoothing residual run as two passes, the second gathering the FP32 copy;
+ * 0 fuses them, recomputing r at every gathered neighbour from FP64 r and q.
+ * Same values either way. */
+#define PSC_TUNE_MIXED_SPLIT 11
 int psc_tune(psc_hier* h, int32_t key, int32_t value);
 
 void psc_hier_free(psc_hier* h);

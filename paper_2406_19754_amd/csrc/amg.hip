@@ -1517,7 +1517,8 @@ __global__ __launch_bounds__(WG) void k_cheb_fin(long long nslices, long long n,
 // smoothers start the V-cycle from r): r_new = r_old - alpha q, partial
 // ||r_new||^2 (same reduction layout as k_update_pre_s).
 __global__ __launch_bounds__(WG) void k_rupdate(long long nslices, long long n, const double* __restrict__ rold,
-                                                const double* __restrict__ q, double* __restrict__ rnew, Red R) {
+                                                const double* __restrict__ q, double* __restrict__ rnew, Red R,
+                                                float* __restrict__ rnew32 = nullptr) {
     if (skip_red(R)) return;
     const double nalpha = -R.ctl->alpha;
     long long lo, hi;
@@ -1526,6 +1527,7 @@ __global__ __launch_bounds__(WG) void k_rupdate(long long nslices, long long n, 
     for (long long i = lo * SLICE + threadIdx.x; i < hi * SLICE && i < n; i += WG) {
         const double rn = fma(nalpha, q[i], rold[i]);
         rnew[i] = rn;
+        if (rnew32) rnew32[i] = (float)rn;
         s0 += rn * rn;
     }
     block_partial(s0, 0.0, R.part);
@@ -1682,6 +1684,8 @@ struct psc_hier {
     bool split = true;                    // smoothing sweeps through A M^-1 and A P
     bool dia = true;                      // use the hacked-DIA copies where a level has them
     bool dia_uniform = true;              // a level with <= 8 distinct offsets keeps them in the kernel argument
+    bool mixed_split = true;              // FP32 V-cycle: residual update and pre-smoothing as two passes
+    float* r32 = nullptr;                 // FP32 copy of the outer residual (mixed_split)
     // Small levels in one workgroup (k_tail): off by default. Under graph
     // replay each small kernel costs about as much as one latency-bound round
     // inside the tail, so the per-level launches are as fast or faster
@@ -2605,7 +2609,19 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
                 if (h->fai || h->cheb) {
                     k_rupdate<<<ge, WG, 0, st>>>(L0.A.nslices, n, rold, h->q, rnew, red_of(h, FIN_UPDATE_FCG));
                 } else if (h->split) {
-                    if (f32)
+                    if (f32 && h->mixed_split) {
+                        // r = r - alpha q (also rounded to FP32), then the FP32
+                        // pre-smoothing residual gathering the FP32 copy: the same
+                        // values as the fused pass, fewer FP64 gathers
+                        k_rupdate<<<ge, WG, 0, st>>>(L0.A.nslices, n, rold, h->q, rnew, red_of(h, FIN_UPDATE_FCG),
+                                                     h->r32);
+                        const bool wide = wide_A(h, L0);
+                        with_AM32(h, L0, [&](auto AM) {
+                            using M = decltype(AM);
+                            if (wide) k_pre_s<M, float, 8><<<ge, WG, 0, st>>>(AM, h->r32, pre_rbuf<float>(h, L0, 1), gd);
+                            else k_pre_s<M, float, 4><<<ge, WG, 0, st>>>(AM, h->r32, pre_rbuf<float>(h, L0, 1), gd);
+                        });
+                    } else if (f32)
                         with_AM32(h, L0, [&](auto AM) {
                             k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, pre_rbuf<float>(h, L0, 1),
                                                                             red_of(h, FIN_UPDATE_FCG));
@@ -3249,6 +3265,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     if ((st = dalloc(h.get(), (void**)&h->part2, 2 * 256 * sizeof(double)))) return st;
     for (double** p : {&h->xs, &h->bs, &h->r, &h->z, &h->p, &h->q, &h->r2, &h->p2})
         if ((st = dalloc(h.get(), (void**)p, N * sizeof(double)))) return st;
+    if (f32 && (st = dalloc(h.get(), (void**)&h->r32, N * sizeof(float)))) return st;
     HIPCHK(hipHostMalloc((void**)&h->hctl, sizeof(HostCtl), hipHostMallocMapped | hipHostMallocCoherent));
     std::memset(h->hctl, 0, sizeof(HostCtl));
     HIPCHK(hipHostGetDevicePointer((void**)&h->hctl_dev, h->hctl, 0));
@@ -3547,6 +3564,11 @@ int psc_tune(psc_hier* h, int32_t key, int32_t value) {
         h->dia = value != 0;
         drop_graphs(h);
         return build_tail(h);
+    }
+    if (key == PSC_TUNE_MIXED_SPLIT) {
+        h->mixed_split = value != 0;
+        drop_graphs(h);
+        return PSC_OK;
     }
     if (key == PSC_TUNE_DIA_UNIFORM) {
         h->dia_uniform = value != 0;

@@ -246,7 +246,7 @@ def test_fused_and_unfused_iterations_agree(psc, case, form):
 
 
 @pytest.mark.parametrize("knob", ["tail_off", "tail_4096", "dia_off", "split_off", "bufload_all", "bufload_none", "unroll4", "grid256",
-                                  "spmv2", "dia_per_slice", "xcd_chunks"])
+                                  "spmv2", "dia_per_slice", "xcd_chunks", "mixed_fused"])
 @pytest.mark.parametrize("case", ["poisson13", "random_long_rows", "diffusion20_az100"])
 def test_kernel_variants_match_oracle(psc, case, knob):
     rp, c, v = CASES[case]()
@@ -267,6 +267,8 @@ def test_kernel_variants_match_oracle(psc, case, knob):
         h.tune(psc.TUNE_DIA_UNIFORM, 0)
     if knob == "xcd_chunks":
         h.tune(psc.TUNE_XCD, 1)
+    if knob == "mixed_fused":
+        h.tune(psc.TUNE_MIXED_SPLIT, 0)
     if knob in ("split_off", "bufload_all", "bufload_none", "unroll4"):
         h.tune(psc.TUNE_SPLIT, 0)                    # sweeps gather through A, M^-1, P
     if knob == "bufload_all":
