@@ -286,6 +286,8 @@ typedef struct {
     int64_t smoother_nnz[PSC_MAX_LEVELS];    /* AINV / INVK: nonzeros of Z_l (0 otherwise) */
     double  rebuild_seconds;                 /* wall time of the last psc_amg_rebuild (0: none) */
     int32_t coarse_pcg_iters;                /* > 0: coarsest solved by at most this many PCG iterations */
+    int32_t tail_level;                      /* first level run by the one-workgroup tail (0: none) */
+    int32_t tail_lds_bytes;                  /* LDS of the FP64 tail kernel (0: none) */
 } psc_hier_stats;
 
 int psc_hier_info(const psc_hier* h, psc_hier_stats* s);
@@ -375,10 +377,12 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
  * when its diagonal slots are at most 4/3 of its ELL slots (7-point
  * stencils: 8 bytes per entry instead of 12); 0 reads hacked ELL. */
 #define PSC_TUNE_DIA 7
-/* PSC_TUNE_TAIL (default 0): the levels with at most `value` rows (value <=
+/* PSC_TUNE_TAIL (default 1024): the levels with at most `value` rows (value <=
  * 4096), down to the dense coarsest solve, run in one kernel of one
- * workgroup per V-cycle (one sweep, split operators); 0 launches their
- * kernels one by one, which is as fast or faster under graph replay. */
+ * workgroup per V-cycle (one sweep, split operators, no other coarsest
+ * solver), whose vectors are held in LDS (16 bytes per row, within the
+ * device's LDS per workgroup: the largest such levels are left out until
+ * they fit); 0 launches their kernels one by one. */
 #define PSC_TUNE_TAIL 8
 /* PSC_TUNE_DIA_UNIFORM (default 1): a level whose hacked-DIA copy has at most 8
  * distinct diagonals over the whole matrix stores every slice with all of them

@@ -1168,6 +1168,7 @@ __global__ __launch_bounds__(WG) void k_coarse(int n, const double* __restrict__
 // k_coarse and k_post_s with one sweep.
 constexpr int TAIL_WG = 1024;
 constexpr int TAIL_MAX_ROWS = 4096;
+constexpr int TAIL_LDS_BYTES = 160 * 1024;   // gfx950: 160 KB of LDS per workgroup
 
 template <typename T>
 struct TailLevel {
@@ -1183,53 +1184,79 @@ struct TailLevel {
 template <typename T>
 struct TailDesc {
     int t, L, nL;
+    int lds_elems;                 // 2 * (rows of levels t .. L-1): b and r of each in LDS
+    int base[PSC_MAX_LEVELS];      // element offset of level l's b (r follows, then x over r)
     const double* invT;
     TailLevel<T> lev[PSC_MAX_LEVELS];
 };
 
+// Levels t .. L-1 of the V-cycle in one workgroup: b and r of every such
+// level live in LDS, and x replaces r once the post-smoothing has read it
+// (level t's b is read from and its x written to device memory, where the
+// neighbouring launches exchange them), so a step waits on an LDS barrier
+// instead of a device-memory round trip; only the operators come from the
+// L2. One smoothing sweep, split operators, dense coarsest.
 template <typename T>
 __global__ __launch_bounds__(TAIL_WG) void k_tail(const TailDesc<T>* __restrict__ D, Gate g) {
     if (gate_skip(g)) return;
+    extern __shared__ __align__(16) unsigned char tail_lds[];
+    T* lds = reinterpret_cast<T*>(tail_lds);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = TAIL_WG / 64;
     const int t = D->t, L = D->L;
+    {
+        const T* bg = D->lev[t].b;
+        T* bt = lds + D->base[t];
+        const int n = (int)D->lev[t].am_ell.nrows;
+        for (int i = threadIdx.x; i < n; i += TAIL_WG) bt[i] = bg[i];
+        __syncthreads();
+    }
     for (int l = t; l < L - 1; l++) {
         const TailLevel<T>& V = D->lev[l];
-        const T* b = V.b;
         const long long ns = V.am_ell.nslices, n = V.am_ell.nrows;
+        const T* b = lds + D->base[l];
+        T* r = lds + D->base[l] + n;
         for (long long s = wv; s < ns; s += nw) {
             const T acc = V.dia ? dia_row(V.am_dia, s, lane, [&](int c) { return b[c]; })
                                 : ell_row(V.am_ell, s, lane, [&](int c) { return b[c]; });
             const long long row = s * SLICE + lane;
-            if (row < n) V.r[row] = b[row] - acc;
+            if (row < n) r[row] = b[row] - acc;
         }
         __syncthreads();
-        const T* r = V.r;
-        T* bc = D->lev[l + 1].b;
+        T* bc = lds + D->base[l + 1];
         for (long long s = wv; s < V.R.nslices; s += nw) {
-            const T acc = ell_row(V.R, s, lane, [&](int c) { return r[c]; });
+            const T acc = ell_row(V.R, s, lane, [&](int c) { return (T)r[c]; });
             const long long row = s * SLICE + lane;
             if (row < V.R.nrows) bc[row] = acc;
         }
         __syncthreads();
     }
     {
-        const TailLevel<T>& C = D->lev[L - 1];
         const int nL = D->nL;
+        const T* bL = lds + D->base[L - 1];
+        T* xL = lds + D->base[L - 1] + nL;
         for (int i = threadIdx.x; i < nL; i += TAIL_WG) {
             double s = 0.0;
-            for (int k = 0; k < nL; k++) s += D->invT[(size_t)k * nL + i] * (double)C.b[k];
-            C.x[i] = (T)s;
+            for (int k = 0; k < nL; k++) s += D->invT[(size_t)k * nL + i] * (double)bL[k];
+            xL[i] = (T)s;
         }
         __syncthreads();
     }
     for (int l = L - 2; l >= t; l--) {
         const TailLevel<T>& V = D->lev[l];
-        const T* xc = D->lev[l + 1].x;
         const long long ns = V.SP.nslices, n = V.SP.nrows;
+        const long long nc = D->lev[l + 1].am_ell.nrows;
+        const T* b = lds + D->base[l];
+        T* rx = lds + D->base[l] + n;              // r in, x out (same row, same lane)
+        const T* xc = lds + D->base[l + 1] + nc;
+        T* xg = V.x;
         for (long long s = wv; s < ns; s += nw) {
             const T acc = ell_row(V.SP, s, lane, [&](int c) { return xc[c]; });
             const long long row = s * SLICE + lane;
-            if (row < n) V.x[row] = V.minv[row] * (V.b[row] + V.r[row]) + acc;
+            if (row < n) {
+                const T xi = V.minv[row] * (b[row] + rx[row]) + acc;
+                rx[row] = xi;
+                if (l == t) xg[row] = xi;
+            }
         }
         __syncthreads();
     }
@@ -1690,9 +1717,10 @@ struct psc_hier {
     // replay each small kernel costs about as much as one latency-bound round
     // inside the tail, so the per-level launches are as fast or faster
     // (measured at 128^3 and 256^3); without graphs the tail saves launches.
-    bool tail = false;
-    int tail_rows = 0;                    // largest level (rows) the tail takes
+    bool tail = true;
+    int tail_rows = 1024;                 // largest level (rows) the tail takes
     int tail_t = 0;                       // first level of the tail (0: no tail)
+    int tail_lds = 0;                     // elements of the tail's LDS arrays
     psc::TailDesc<double>* tail64 = nullptr;   // device descriptors (built at setup)
     psc::TailDesc<float>* tail32 = nullptr;
     bool tail_dia = true;                 // the DIA setting the descriptors were built with
@@ -2109,8 +2137,41 @@ static int build_tail(psc_hier* h) {
     int t = L - 1;
     while (t - 1 >= 1 && h->lev[t - 1].n <= h->tail_rows) t--;
     if (t > L - 2 || h->lev[L - 1].n > TAIL_MAX_ROWS) return PSC_OK;
+    // LDS: b and r (then x) of levels t .. L-1 (FP64 sized, so the FP32 tail
+    // fits too); drop the largest tail levels until that fits in what a
+    // workgroup may take
+    int dev = 0, lds_max = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    lds_max = std::min(lds_max, TAIL_LDS_BYTES);
+    auto lds_of = [&](int t0) {
+        long long e = 0;
+        for (int l = t0; l < L; l++) e += 2 * h->lev[l].n;
+        return e;
+    };
+    while (t <= L - 2 && lds_of(t) * (long long)sizeof(double) > lds_max) t++;
+    if (t > L - 2) return PSC_OK;
+    const int lds_bytes = (int)(lds_of(t) * (long long)sizeof(double));
+    if (lds_bytes > 64 * 1024 &&
+        (hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes) !=
+             hipSuccess ||
+         hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes) !=
+             hipSuccess)) {
+        // the runtime refuses more than 64 KB: keep to that
+        (void)hipGetLastError();
+        while (t <= L - 2 && lds_of(t) * (long long)sizeof(double) > 64 * 1024) t++;
+        if (t > L - 2) return PSC_OK;
+    }
     TailDesc<double> d64{};
     TailDesc<float> d32{};
+    {
+        int e = 0;
+        for (int l = t; l < L; l++) {
+            d64.base[l] = d32.base[l] = e;
+            e += 2 * (int)h->lev[l].n;
+        }
+        d64.lds_elems = d32.lds_elems = e;
+    }
     d64.t = d32.t = t;
     d64.L = d32.L = L;
     d64.nL = d32.nL = h->coarse_n;
@@ -2125,6 +2186,7 @@ static int build_tail(psc_hier* h) {
     HIPCHK(hipMemcpy(h->tail64, &d64, sizeof(d64), hipMemcpyHostToDevice));
     if (h->has32) HIPCHK(hipMemcpy(h->tail32, &d32, sizeof(d32), hipMemcpyHostToDevice));
     h->tail_dia = h->dia;
+    h->tail_lds = d64.lds_elems;
     h->tail_t = t;
     return PSC_OK;
 }
@@ -2235,7 +2297,7 @@ static void vcycle_t(psc_hier* h, const double* r0, double* z0, const double* d,
     }
     if (tail) {
         TimeScope t(h, 7);
-        k_tail<T><<<1, TAIL_WG, 0, h->stream>>>(tail_desc<T>(h), g);
+        k_tail<T><<<1, TAIL_WG, (size_t)h->tail_lds * sizeof(T), h->stream>>>(tail_desc<T>(h), g);
     } else {
         DevLevel& C = h->lev[L - 1];
         TimeScope t(h, 7);
@@ -3453,6 +3515,9 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
     s->smoother = h->opts.smoother;
     s->rebuild_seconds = h->rebuild_seconds;
     s->coarse_pcg_iters = h->host.coarse_pcg;
+    const bool tail = h->tail && h->tail_t > 0 && h->split && h->tail_dia == h->dia;
+    s->tail_level = tail ? h->tail_t : 0;
+    s->tail_lds_bytes = tail ? h->tail_lds * (int)sizeof(double) : 0;
     if (h->opts.host_only)
         for (int l = 0; l + 1 < L; l++) s->smoother_nnz[l] = (int64_t)h->host.lev[l].fai.zi.size();
     return PSC_OK;

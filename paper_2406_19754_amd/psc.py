@@ -61,7 +61,7 @@ class HierStats(C.Structure):
                 ("omega", C.c_double * MAX_LEVELS), ("smoother_sweeps", C.c_int32), ("smoothed_prol", C.c_int32),
                 ("vcycle_double", C.c_int32), ("aggregation", C.c_int32), ("smoother", C.c_int32),
                 ("smoother_nnz", C.c_int64 * MAX_LEVELS), ("rebuild_seconds", C.c_double),
-                ("coarse_pcg_iters", C.c_int32)]
+                ("coarse_pcg_iters", C.c_int32), ("tail_level", C.c_int32), ("tail_lds_bytes", C.c_int32)]
 
 
 def _load():
@@ -196,7 +196,8 @@ class Hierarchy:
                     p_nnz=list(s.p_nnz[:L]), omega=list(s.omega[:L]), smoother_sweeps=s.smoother_sweeps,
                     smoothed_prol=s.smoothed_prol, vcycle_double=s.vcycle_double, aggregation=s.aggregation,
                     smoother=s.smoother, smoother_nnz=list(s.smoother_nnz[:L]),
-                    rebuild_seconds=s.rebuild_seconds, coarse_pcg_iters=s.coarse_pcg_iters)
+                    rebuild_seconds=s.rebuild_seconds, coarse_pcg_iters=s.coarse_pcg_iters,
+                    tail_level=s.tail_level, tail_lds_bytes=s.tail_lds_bytes)
 
     def rebuild(self, val):
         """Numeric-only rebuild with new values of A (same pattern as at build)."""

@@ -31,3 +31,28 @@ def test_binding_loads_without_gpu():
     from paper_2406_19754_amd import psc
     assert psc.net_param_count() == 7809
     assert psc.lib().psc_last_error() is not None
+
+
+def _c_layout(type_name, fields):
+    """sizeof and offsetof of a header struct, from a C program compiled here."""
+    import subprocess
+    import tempfile
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "psc.h"', 'int main(void) {',
+             f'  printf("%zu\\n", sizeof({type_name}));']
+    lines += [f'  printf("%zu\\n", offsetof({type_name}, {f}));' for f in fields]
+    lines += ['  return 0;', '}']
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        open(src, "w").write("\n".join(lines) + "\n")
+        subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+def test_binding_structs_match_the_header_layout():
+    from paper_2406_19754_amd import psc
+    for cls, name in [(psc.AmgOpts, "psc_amg_opts"), (psc.HierStats, "psc_hier_stats")]:
+        fields = [f[0] for f in cls._fields_]
+        size, offs = _c_layout(name, fields)
+        assert ctypes.sizeof(cls) == size, name
+        assert [getattr(cls, f).offset for f in fields] == offs, name

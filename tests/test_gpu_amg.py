@@ -308,6 +308,39 @@ def test_kernel_variants_match_oracle(psc, case, knob):
         h.tune(psc.TUNE_XCD, 0)                      # per device: restore the default for later tests
 
 
+@pytest.mark.parametrize("rows", [1024, 4096])
+def test_tail_in_lds_matches_oracle(psc, rows):
+    """Levels 4000, 1000, 250 and 63 (coarsest) of Poisson 40^3 in the
+    one-workgroup tail: 21 KB of LDS at 1024 rows, 85 KB at 4096."""
+    rp, c, v = P.poisson7(40)
+    h = psc.Hierarchy(rp, c, v, build_fp32=True)
+    h.tune(psc.TUNE_TAIL, rows)
+    info = h.info()
+    assert info["rows"][2:] == [4000, 1000, 250, 63]
+    assert info["tail_level"] == (2 if rows == 4096 else 3)
+    assert info["tail_lds_bytes"] == 16 * sum(info["rows"][info["tail_level"]:])
+    o = oracle.Hierarchy(rp, c, v)
+    n = len(rp) - 1
+    x = np.random.default_rng(5).standard_normal(n)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.vcycle(dev(x), y)
+    ref = o.vcycle(x)
+    assert np.linalg.norm(y.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+    h.vcycle(dev(x), y, prec=psc.FP32)
+    ref = o.vcycle32(x)
+    assert np.linalg.norm(y.cpu().numpy() - ref) <= 1e-5 * np.linalg.norm(ref)
+    b = P.rhs_uniform(n, 4)
+    for form in ("pcg", "fcg32"):
+        xg = torch.zeros(n, dtype=torch.float64, device="cuda")
+        if form == "pcg":
+            g, r = h.pcg(dev(b), xg), o.pcg(b)
+        else:
+            g, r = h.fcg(dev(b), xg, prec=psc.FP32), o.fcg(b, form=1)
+        assert g["status"] == psc.OK and abs(g["iters"] - r["iters"]) <= 1 and g["relres"] <= 1e-6
+    h.tune(psc.TUNE_TAIL, 0)
+    assert h.info()["tail_level"] == 0
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_fcg_tight_tolerance_residual_replacement(psc, prec):
     """At rtol 1e-11 the recursive residual can pass before the true one;
