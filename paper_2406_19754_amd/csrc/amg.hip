@@ -1735,6 +1735,8 @@ struct psc_hier {
     // buffers (same sizes), skipping allocations and index arrays
     bool refresh = false;
     std::unordered_map<void*, size_t> asize;   // bytes of every level allocation
+    void* stage = nullptr;                // rebuild staging of CSR rows and values (freed after it)
+    size_t stage_bytes = 0;
     int64_t device_bytes = 0;
     double setup_seconds = 0.0;
     double rebuild_seconds = 0.0;         // last numeric rebuild
@@ -1836,6 +1838,91 @@ static int upload_ell(psc_hier* h, DevEll<double>& E, int64_t nrows, int64_t nco
             if ((st = upload(h, am32, v32.data(), v32.size()))) return st;
         }
     }
+    return PSC_OK;
+}
+
+// Numeric rebuild on an unchanged pattern: row i's new CSR values go into
+// the slots the build gave them, hacked ELL (entry q of the row at
+// off[s] + 64 q + lane) and, when the level has one, hacked DIA (slot
+// (start[s] + k) 64 + lane, k the slice's diagonal of the entry's column),
+// with A M^-1 (a_ij minv_j) and the FP32 copies formed on the way. Padding
+// and empty diagonal slots keep the zeros the build wrote.
+__global__ void k_refresh_values(long long n, const int32_t* __restrict__ rp, const double* __restrict__ v,
+                                 const double* __restrict__ mv, const long long* __restrict__ off,
+                                 const int* __restrict__ col, double* __restrict__ val, float* __restrict__ val32,
+                                 double* __restrict__ am, float* __restrict__ am32, const int* __restrict__ dstart,
+                                 const int* __restrict__ doffs, double* __restrict__ dval,
+                                 float* __restrict__ dval32, double* __restrict__ damd,
+                                 float* __restrict__ damd32) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long s = i >> 6;
+    const int lane = (int)(i & 63);
+    const long long o = off[s] + lane;
+    const int32_t b = rp[i], e = rp[i + 1];
+    const int k0 = dstart ? dstart[s] : 0, k1 = dstart ? dstart[s + 1] : 0;
+    for (int32_t q = b; q < e; q++) {
+        const long long slot = o + (long long)(q - b) * SLICE;
+        const double x = v[q];
+        const int c = col[slot];
+        val[slot] = x;
+        if (val32) val32[slot] = (float)x;
+        double y = 0.0;
+        if (am) {
+            y = x * mv[c];
+            am[slot] = y;
+            if (am32) am32[slot] = (float)y;
+        }
+        if (dstart) {
+            const int d = c - (int)i;
+            int k = k0;
+            while (k < k1 && doffs[k] != d) k++;
+            if (k < k1) {
+                const long long ds = (long long)k * SLICE + lane;
+                dval[ds] = x;
+                if (dval32) dval32[ds] = (float)x;
+                if (damd) {
+                    damd[ds] = y;
+                    if (damd32) damd32[ds] = (float)y;
+                }
+            }
+        }
+    }
+}
+
+// Device side of a refresh: stage the rows and values of a CSR operator with
+// the pattern uploaded at build and scatter them (see k_refresh_values).
+// mv != nullptr also refreshes A M^-1 (am / amd and their FP32 copies).
+static int refresh_values(psc_hier* h, DevEll<double>& E, const DevDia* G, int64_t n, const int32_t* rp,
+                          const double* v, const double* mv, double* am, float* am32, double* amd, float* amd32) {
+    if (!E.off || !E.col || !E.val || E.nrows != n || E.nnz != (long long)rp[n]) return PSC_ERR_STATE;
+    const size_t brp = ((size_t)(n + 1) * sizeof(int32_t) + 255) & ~(size_t)255;
+    const size_t bv = ((size_t)rp[n] * sizeof(double) + 255) & ~(size_t)255;
+    const size_t bm = mv ? (size_t)n * sizeof(double) : 0;
+    const size_t need = brp + bv + bm;
+    if (h->stage_bytes < need) {
+        if (h->stage) HIPCHK(hipFree(h->stage));
+        h->stage = nullptr;
+        h->stage_bytes = 0;
+        if (hipMalloc(&h->stage, need) != hipSuccess) return fail(PSC_ERR_OOM, "rebuild staging allocation failed");
+        h->stage_bytes = need;
+    }
+    char* sb = (char*)h->stage;
+    int32_t* drp = (int32_t*)sb;
+    double* dv = (double*)(sb + brp);
+    double* dm = mv ? (double*)(sb + brp + bv) : nullptr;
+    HIPCHK(hipMemcpyAsync(drp, rp, (size_t)(n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    if (rp[n] > 0) HIPCHK(hipMemcpyAsync(dv, v, (size_t)rp[n] * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    if (mv) HIPCHK(hipMemcpyAsync(dm, mv, bm, hipMemcpyHostToDevice, h->stream));
+    const bool dia = G && G->on();
+    const long long blocks = (n + WG - 1) / WG;
+    k_refresh_values<<<(unsigned)blocks, WG, 0, h->stream>>>(
+        n, drp, dv, dm, E.off, E.col, E.val, E.val32, mv ? am : nullptr, mv ? am32 : nullptr,
+        dia ? G->start : nullptr, dia ? G->offs : nullptr, dia ? G->val : nullptr, dia ? G->val32 : nullptr,
+        (dia && mv) ? amd : nullptr, (dia && mv) ? amd32 : nullptr);
+    HIPCHK(hipGetLastError());
+    // the staging buffer and the host arrays are reused or released next
+    HIPCHK(hipStreamSynchronize(h->stream));
     return PSC_OK;
 }
 
@@ -3083,7 +3170,13 @@ static int upload_levels(psc_hier* h) {
             for (int64_t i = 0; i < H.n; i++) wminv[i] = c0 * H.minv[i];
         }
         const std::vector<double>& mv = wminv.empty() ? H.minv : wminv;
-        if (l < L - 1) {
+        if (h->refresh) {
+            // same pattern as at build: scatter the new values on the device
+            // into the ELL and DIA slots of A and A M^-1
+            if ((st = refresh_values(h, D.A, &D.Ad, H.n, H.rp.data(), H.v.data(), l < L - 1 ? mv.data() : nullptr,
+                                     D.am, D.am32, D.amd, D.amd32)))
+                return st;
+        } else if (l < L - 1) {
             if ((st = upload_ell(h, D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32, mv.data(),
                                  &D.am, &D.am32)))
                 return st;
@@ -3096,7 +3189,8 @@ static int upload_levels(psc_hier* h) {
         std::vector<int32_t> dstart, doffs;
         std::vector<double> dval;
         std::vector<int32_t> duo;
-        if (pack_dia(H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), D.A.slots * 4 / 3, dstart, doffs, dval, &duo)) {
+        if (!h->refresh &&
+            pack_dia(H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), D.A.slots * 4 / 3, dstart, doffs, dval, &duo)) {
             DevDia& G = D.Ad;
             G.nrows = H.n;
             G.ncols = H.n;
@@ -3182,7 +3276,10 @@ static int upload_levels(psc_hier* h) {
                     rv[o] = H.pv[m];
                 }
             }
-            if ((st = upload_ell(h, D.R, H.nc, H.n, rrp.data(), rci.data(), rv.data(), f32))) return st;
+            if (h->refresh) st = refresh_values(h, D.R, nullptr, H.nc, rrp.data(), rv.data(), nullptr, nullptr,
+                                                nullptr, nullptr, nullptr);
+            else st = upload_ell(h, D.R, H.nc, H.n, rrp.data(), rci.data(), rv.data(), f32);
+            if (st) return st;
             // smoothed prolongator for the split post-smoothing sweep
             std::vector<int32_t> sprp, spci;
             std::vector<double> spv;
@@ -3191,7 +3288,10 @@ static int upload_levels(psc_hier* h) {
             std::vector<int32_t>().swap(H.aprp);
             std::vector<int32_t>().swap(H.apci);
             std::vector<double>().swap(H.apv);
-            if ((st = upload_ell(h, D.SP, H.n, H.nc, sprp.data(), spci.data(), spv.data(), f32))) return st;
+            if (h->refresh) st = refresh_values(h, D.SP, nullptr, H.n, sprp.data(), spv.data(), nullptr, nullptr,
+                                                nullptr, nullptr, nullptr);
+            else st = upload_ell(h, D.SP, H.n, H.nc, sprp.data(), spci.data(), spv.data(), f32);
+            if (st) return st;
             if (h->fai || h->cheb) {
                 if ((st = upload_fai(h, D, H, f32))) return st;
             }
@@ -3375,6 +3475,11 @@ int psc_amg_rebuild(psc_hier* h, const double* val) {
             h->device_bytes -= h->lev_bytes;
             h->lev_bytes = 0;
             st = upload_levels(h);
+        }
+        if (h->stage) {
+            (void)hipFree(h->stage);
+            h->stage = nullptr;
+            h->stage_bytes = 0;
         }
         if (st) return st;
         if ((st = build_tail(h))) return st;
