@@ -1894,7 +1894,8 @@ __global__ void k_refresh_values(long long n, const int32_t* __restrict__ rp, co
 // the pattern uploaded at build and scatter them (see k_refresh_values).
 // mv != nullptr also refreshes A M^-1 (am / amd and their FP32 copies).
 static int refresh_values(psc_hier* h, DevEll<double>& E, const DevDia* G, int64_t n, const int32_t* rp,
-                          const double* v, const double* mv, double* am, float* am32, double* amd, float* amd32) {
+                          const double* v, const double* mv, double* am, float* am32, double* amd, float* amd32,
+                          const int32_t** staged_rp = nullptr) {
     if (!E.off || !E.col || !E.val || E.nrows != n || E.nnz != (long long)rp[n]) return PSC_ERR_STATE;
     const size_t brp = ((size_t)(n + 1) * sizeof(int32_t) + 255) & ~(size_t)255;
     const size_t bv = ((size_t)rp[n] * sizeof(double) + 255) & ~(size_t)255;
@@ -1923,6 +1924,7 @@ static int refresh_values(psc_hier* h, DevEll<double>& E, const DevDia* G, int64
     HIPCHK(hipGetLastError());
     // the staging buffer and the host arrays are reused or released next
     HIPCHK(hipStreamSynchronize(h->stream));
+    if (staged_rp) *staged_rp = drp;   // valid until the next refresh_values call
     return PSC_OK;
 }
 
@@ -3170,11 +3172,12 @@ static int upload_levels(psc_hier* h) {
             for (int64_t i = 0; i < H.n; i++) wminv[i] = c0 * H.minv[i];
         }
         const std::vector<double>& mv = wminv.empty() ? H.minv : wminv;
+        const int32_t* a_rp_dev = nullptr;   // A's rows staged by the refresh (kept until R is refreshed)
         if (h->refresh) {
             // same pattern as at build: scatter the new values on the device
             // into the ELL and DIA slots of A and A M^-1
             if ((st = refresh_values(h, D.A, &D.Ad, H.n, H.rp.data(), H.v.data(), l < L - 1 ? mv.data() : nullptr,
-                                     D.am, D.am32, D.amd, D.amd32)))
+                                     D.am, D.am32, D.amd, D.amd32, &a_rp_dev)))
                 return st;
         } else if (l < L - 1) {
             if ((st = upload_ell(h, D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32, mv.data(),
@@ -3262,6 +3265,18 @@ static int upload_levels(psc_hier* h) {
                 auto p32 = to32(H.p);
                 if ((st = upload(h, &D.pval32, p32.data(), p32.size()))) return st;
             }
+            // tentative prolongator (row i: p_i at agg_i) on a refresh: S P is
+            // recomputed on the device from A's refreshed slots
+            const bool tentative = (int64_t)H.pci.size() == H.n && (int64_t)H.prp.size() == H.n + 1 &&
+                                   H.prp[H.n] == H.n && !h->opts.smoothed_prol;
+            const bool sp_on_device = h->refresh && tentative && a_rp_dev != nullptr;
+            if (sp_on_device) {
+                if (!D.SP.off || !D.SP.col || !D.SP.val || D.SP.nrows != H.n) return PSC_ERR_STATE;
+                std::string err;
+                if ((st = gpu_tentative_sp((void*)h->stream, H.n, D.A.off, D.A.col, D.A.val, a_rp_dev, D.agg, D.pval,
+                                           D.minv, D.SP.off, D.SP.col, D.SP.val, D.SP.val32, err)))
+                    return fail(st, err);
+            }
             // R = P^T as CSR over coarse rows: fine rows ascending
             const size_t pn = H.pci.size();
             std::vector<int32_t> rrp(H.nc + 1, 0), rci(pn);
@@ -3281,17 +3296,19 @@ static int upload_levels(psc_hier* h) {
             else st = upload_ell(h, D.R, H.nc, H.n, rrp.data(), rci.data(), rv.data(), f32);
             if (st) return st;
             // smoothed prolongator for the split post-smoothing sweep
-            std::vector<int32_t> sprp, spci;
-            std::vector<double> spv;
-            jacobi_smoothed_prolongator(H, mv.data(), sprp, spci, spv);
+            if (!sp_on_device) {
+                std::vector<int32_t> sprp, spci;
+                std::vector<double> spv;
+                jacobi_smoothed_prolongator(H, mv.data(), sprp, spci, spv);
+                if (h->refresh) st = refresh_values(h, D.SP, nullptr, H.n, sprp.data(), spv.data(), nullptr, nullptr,
+                                                    nullptr, nullptr, nullptr);
+                else st = upload_ell(h, D.SP, H.n, H.nc, sprp.data(), spci.data(), spv.data(), f32);
+                if (st) return st;
+            }
             // the kept A P is not needed after this (a rebuild forms it again)
             std::vector<int32_t>().swap(H.aprp);
             std::vector<int32_t>().swap(H.apci);
             std::vector<double>().swap(H.apv);
-            if (h->refresh) st = refresh_values(h, D.SP, nullptr, H.n, sprp.data(), spv.data(), nullptr, nullptr,
-                                                nullptr, nullptr, nullptr);
-            else st = upload_ell(h, D.SP, H.n, H.nc, sprp.data(), spci.data(), spv.data(), f32);
-            if (st) return st;
             if (h->fai || h->cheb) {
                 if ((st = upload_fai(h, D, H, f32))) return st;
             }

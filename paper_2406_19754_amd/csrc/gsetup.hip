@@ -408,6 +408,54 @@ int gs_galerkin(hipStream_t st, int nc, int stride, const int* mem, int n, const
     return PSC_OK;
 }
 
+// S P = (I - M^-1 A) P for the tentative prolongator (one entry p_j at
+// column agg_j in row j of P), in place in the build's hacked-ELL slots of S P:
+// row i's columns are the distinct aggregates of its columns, ascending, so
+// its length is their count; (A P)_iJ sums a_ij p_j over the row's entries
+// ascending with agg_j = J (the first product assigns), as the host's sparse
+// product does, and s_iJ = [J = agg_i] p_i - minv_i (A P)_iJ.
+__global__ void k_gs_tentative_sp(long long n, const long long* __restrict__ a_off, const int* __restrict__ a_col,
+                                  const double* __restrict__ a_val, const int32_t* __restrict__ a_rp,
+                                  const int32_t* __restrict__ agg, const double* __restrict__ p,
+                                  const double* __restrict__ minv, const long long* __restrict__ sp_off,
+                                  const int* __restrict__ sp_col, double* __restrict__ sp_val,
+                                  float* __restrict__ sp_val32) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long s = i >> 6;
+    const int lane = (int)(i & 63);
+    const long long ao = a_off[s] + lane, so = sp_off[s] + lane;
+    const int la = a_rp[i + 1] - a_rp[i];
+    int ls = 0;
+    for (int q = 0; q < la; q++) {
+        const int J = agg[a_col[ao + (long long)q * 64]];
+        bool first = true;
+        for (int u = 0; u < q && first; u++) first = agg[a_col[ao + (long long)u * 64]] != J;
+        ls += first ? 1 : 0;
+    }
+    const int wsp = (int)((sp_off[s + 1] - sp_off[s]) >> 6);   // never past the slice (same pattern as at build)
+    if (ls > wsp) ls = wsp;
+    const int ai = agg[i];
+    const double mi = minv[i];
+    for (int q = 0; q < ls; q++) {
+        const long long slot = so + (long long)q * 64;
+        const int J = sp_col[slot];
+        double t = 0.0;
+        bool any = false;
+        for (int u = 0; u < la; u++) {
+            const int c = a_col[ao + (long long)u * 64];
+            if (agg[c] != J) continue;
+            const double x = a_val[ao + (long long)u * 64] * p[c];
+            t = any ? t + x : x;
+            any = true;
+        }
+        const double pk = J == ai ? p[i] : 0.0;
+        const double val = pk - mi * t;
+        sp_val[slot] = val;
+        if (sp_val32) sp_val32[slot] = (float)val;
+    }
+}
+
 }  // namespace
 
 int gpu_coarsen_level(int64_t n64, const int32_t* hrp, const int32_t* hci, const double* hv, const double* hw,
@@ -558,6 +606,18 @@ int gpu_coarsen_level(int64_t n64, const int32_t* hrp, const int32_t* hci, const
     }
     GS_CHK(hipStreamSynchronize(st));
     nc_out = nc;
+    return PSC_OK;
+}
+
+
+int gpu_tentative_sp(void* stream, int64_t n, const long long* a_off, const int* a_col, const double* a_val,
+                     const int32_t* a_rp, const int32_t* agg, const double* p, const double* minv,
+                     const long long* sp_off, const int* sp_col, double* sp_val, float* sp_val32, std::string& err) {
+    hipStream_t st = (hipStream_t)stream;
+    k_gs_tentative_sp<<<gs_grid(n), GS_WG, 0, st>>>(n, a_off, a_col, a_val, a_rp, agg, p, minv, sp_off, sp_col,
+                                                     sp_val, sp_val32);
+    GS_CHK(hipGetLastError());
+    GS_CHK(hipStreamSynchronize(st));
     return PSC_OK;
 }
 

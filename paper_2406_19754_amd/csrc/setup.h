@@ -111,6 +111,15 @@ int gpu_coarsen_level(int64_t n, const int32_t* rp, const int32_t* ci, const dou
                       std::vector<double>& wc, std::vector<int32_t>& crp, std::vector<int32_t>& cci,
                       std::vector<double>& cv, std::string& err);
 
+// Numeric rebuild, tentative prolongator: S P = (I - M^-1 A) P recomputed on
+// the device into the build's hacked-ELL slots of S P from A's refreshed
+// hacked-ELL values (a_rp: A's row pointers, device), agg, p and minv, with
+// the host's summation order (bit-identical to jacobi_smoothed_prolongator).
+// Every pointer is a device pointer; stream is a hipStream_t.
+int gpu_tentative_sp(void* stream, int64_t n, const long long* a_off, const int* a_col, const double* a_val,
+                     const int32_t* a_rp, const int32_t* agg, const double* p, const double* minv,
+                     const long long* sp_off, const int* sp_col, double* sp_val, float* sp_val32, std::string& err);
+
 // Pack CSR rows into hacked DIA with 64-row slices (offsets ascending per
 // slice, values diagonal-major in a slice, zeros where a row has no entry).
 // Returns false and packs nothing when the diagonal slots would exceed
