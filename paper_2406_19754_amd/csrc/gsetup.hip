@@ -420,39 +420,40 @@ __global__ void k_gs_tentative_sp(long long n, const long long* __restrict__ a_o
                                   const double* __restrict__ minv, const long long* __restrict__ sp_off,
                                   const int* __restrict__ sp_col, double* __restrict__ sp_val,
                                   float* __restrict__ sp_val32) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const long long s = i >> 6;
-    const int lane = (int)(i & 63);
-    const long long ao = a_off[s] + lane, so = sp_off[s] + lane;
-    const int la = a_rp[i + 1] - a_rp[i];
-    int ls = 0;
-    for (int q = 0; q < la; q++) {
-        const int J = agg[a_col[ao + (long long)q * 64]];
-        bool first = true;
-        for (int u = 0; u < q && first; u++) first = agg[a_col[ao + (long long)u * 64]] != J;
-        ls += first ? 1 : 0;
-    }
-    const int wsp = (int)((sp_off[s + 1] - sp_off[s]) >> 6);   // never past the slice (same pattern as at build)
-    if (ls > wsp) ls = wsp;
-    const int ai = agg[i];
-    const double mi = minv[i];
-    for (int q = 0; q < ls; q++) {
-        const long long slot = so + (long long)q * 64;
-        const int J = sp_col[slot];
-        double t = 0.0;
-        bool any = false;
-        for (int u = 0; u < la; u++) {
-            const int c = a_col[ao + (long long)u * 64];
-            if (agg[c] != J) continue;
-            const double x = a_val[ao + (long long)u * 64] * p[c];
-            t = any ? t + x : x;
-            any = true;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long s = i >> 6;
+        const int lane = (int)(i & 63);
+        const long long ao = a_off[s] + lane, so = sp_off[s] + lane;
+        const int la = a_rp[i + 1] - a_rp[i];
+        int ls = 0;
+        for (int q = 0; q < la; q++) {
+            const int J = agg[a_col[ao + (long long)q * 64]];
+            bool first = true;
+            for (int u = 0; u < q && first; u++) first = agg[a_col[ao + (long long)u * 64]] != J;
+            ls += first ? 1 : 0;
         }
-        const double pk = J == ai ? p[i] : 0.0;
-        const double val = pk - mi * t;
-        sp_val[slot] = val;
-        if (sp_val32) sp_val32[slot] = (float)val;
+        const int wsp = (int)((sp_off[s + 1] - sp_off[s]) >> 6);   // never past the slice (same pattern as at build)
+        if (ls > wsp) ls = wsp;
+        const int ai = agg[i];
+        const double mi = minv[i];
+        for (int q = 0; q < ls; q++) {
+            const long long slot = so + (long long)q * 64;
+            const int J = sp_col[slot];
+            double t = 0.0;
+            bool any = false;
+            for (int u = 0; u < la; u++) {
+                const int c = a_col[ao + (long long)u * 64];
+                if (agg[c] != J) continue;
+                const double x = a_val[ao + (long long)u * 64] * p[c];
+                t = any ? t + x : x;
+                any = true;
+            }
+            const double pk = J == ai ? p[i] : 0.0;
+            const double val = pk - mi * t;
+            sp_val[slot] = val;
+            if (sp_val32) sp_val32[slot] = (float)val;
+        }
     }
 }
 

@@ -206,3 +206,26 @@ def test_rebuild_of_factored_smoothers_with_new_coefficients(psc, smoother):
     x.zero_()
     g = h.pcg(dev(b2), x)
     assert g["status"] == psc.OK and g["relres"] <= 1e-6
+
+
+def test_rebuild_refreshes_rows_beyond_one_full_grid(psc):
+    """260^3 = 17.6 M rows: more rows than one launch of the capped grid
+    covers (65536 workgroups of 256), so every refresh kernel must stride;
+    the rebuilt handle's operators equal a fresh build on 4A bit for bit."""
+    rp, c, v = P.poisson7(260)
+    n = len(rp) - 1
+    assert n > 65536 * 256
+    r = dev(np.random.default_rng(9).standard_normal(n))
+    f = psc.Hierarchy(rp, c, 4.0 * v)
+    zf = torch.empty(n, dtype=torch.float64, device="cuda")
+    yf = torch.empty(n, dtype=torch.float64, device="cuda")
+    f.vcycle(r, zf)
+    f.spmv(r, yf)
+    f.close()
+    h = psc.Hierarchy(rp, c, v)
+    h.rebuild(4.0 * v)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.vcycle(r, z)
+    h.spmv(r, y)
+    assert torch.equal(y, yf) and torch.equal(z, zf)
