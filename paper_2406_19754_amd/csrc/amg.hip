@@ -1928,6 +1928,42 @@ static int refresh_values(psc_hier* h, DevEll<double>& E, const DevDia* G, int64
     return PSC_OK;
 }
 
+// Allocation cleared to zero (padding and empty diagonal slots of a layout).
+static int zalloc(psc_hier* h, void** p, size_t bytes) {
+    int st = dalloc(h, p, bytes);
+    if (st) return st;
+    HIPCHK(hipMemsetAsync(*p, 0, bytes, h->stream));
+    return PSC_OK;
+}
+
+// Hacked-ELL layout of a CSR operator on the device: slice offsets and
+// columns packed on the host, value arrays (FP64, FP32 when fp32, and A M^-1
+// when am != nullptr) allocated and cleared, for refresh_values to fill.
+static int upload_ell_layout(psc_hier* h, DevEll<double>& E, int64_t nrows, int64_t ncols, const int32_t* rp,
+                             const int32_t* ci, bool fp32, double** am = nullptr, float** am32 = nullptr) {
+    std::vector<long long> off;
+    std::vector<double> none;
+    std::vector<int> col;
+    pack_ell(nrows, rp, ci, nullptr, off, none, col);
+    E.nrows = nrows;
+    E.ncols = ncols;
+    E.nslices = (long long)off.size() - 1;
+    E.slots = off.back();
+    E.nnz = rp[nrows];
+    for (size_t q = 0; q + 1 < off.size(); q++) E.wmax = std::max(E.wmax, (int)((off[q + 1] - off[q]) / SLICE));
+    int st;
+    if ((st = upload(h, &E.off, off.data(), off.size()))) return st;
+    if ((st = upload(h, &E.col, col.data(), col.size()))) return st;
+    const size_t slots = (size_t)E.slots;
+    if ((st = zalloc(h, (void**)&E.val, slots * sizeof(double)))) return st;
+    if (fp32 && (st = zalloc(h, (void**)&E.val32, slots * sizeof(float)))) return st;
+    if (am) {
+        if ((st = zalloc(h, (void**)am, slots * sizeof(double)))) return st;
+        if (fp32 && (st = zalloc(h, (void**)am32, slots * sizeof(float)))) return st;
+    }
+    return PSC_OK;
+}
+
 static std::vector<float> to32(const std::vector<double>& a) {
     std::vector<float> r(a.size());
     for (size_t i = 0; i < a.size(); i++) r[i] = (float)a[i];
@@ -3172,63 +3208,45 @@ static int upload_levels(psc_hier* h) {
             for (int64_t i = 0; i < H.n; i++) wminv[i] = c0 * H.minv[i];
         }
         const std::vector<double>& mv = wminv.empty() ? H.minv : wminv;
-        const int32_t* a_rp_dev = nullptr;   // A's rows staged by the refresh (kept until R is refreshed)
-        if (h->refresh) {
-            // same pattern as at build: scatter the new values on the device
-            // into the ELL and DIA slots of A and A M^-1
-            if ((st = refresh_values(h, D.A, &D.Ad, H.n, H.rp.data(), H.v.data(), l < L - 1 ? mv.data() : nullptr,
-                                     D.am, D.am32, D.amd, D.amd32, &a_rp_dev)))
+        // A, its hacked-DIA copy and A M^-1 in both: the layouts are packed
+        // on the host at build (kept by a refresh: same pattern), the values
+        // scattered into them on the device
+        if (!h->refresh) {
+            if ((st = upload_ell_layout(h, D.A, H.n, H.n, H.rp.data(), H.ci.data(), f32,
+                                        l < L - 1 ? &D.am : nullptr, &D.am32)))
                 return st;
-        } else if (l < L - 1) {
-            if ((st = upload_ell(h, D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32, mv.data(),
-                                 &D.am, &D.am32)))
-                return st;
-        } else if ((st = upload_ell(h, D.A, H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), f32))) {
-            return st;
-        }
-        if ((st = upload(h, &D.minv, mv.data(), H.n))) return st;
-        // hacked-DIA copy when it stores at most 4/3 of the ELL slots (8 instead
-        // of 12 bytes per slot: at least 11 % fewer bytes); A M^-1 shares its layout
-        std::vector<int32_t> dstart, doffs;
-        std::vector<double> dval;
-        std::vector<int32_t> duo;
-        if (!h->refresh &&
-            pack_dia(H.n, H.n, H.rp.data(), H.ci.data(), H.v.data(), D.A.slots * 4 / 3, dstart, doffs, dval, &duo)) {
-            DevDia& G = D.Ad;
-            G.nrows = H.n;
-            G.ncols = H.n;
-            G.nslices = (long long)dstart.size() - 1;
-            G.slots = (long long)dval.size();
-            for (size_t q = 0; q + 1 < dstart.size(); q++) G.ndmax = std::max(G.ndmax, dstart[q + 1] - dstart[q]);
-            G.nd_u = (int)duo.size();
-            G.nd = h->dia_uniform ? G.nd_u : 0;
-            for (size_t k = 0; k < duo.size() && k < 8; k++) G.uo[k] = duo[k];
-            if ((st = upload(h, &G.start, dstart.data(), dstart.size()))) return st;
-            if ((st = upload(h, &G.offs, doffs.data(), doffs.size()))) return st;
-            if ((st = upload(h, &G.val, dval.data(), dval.size()))) return st;
-            if (f32) {
-                auto v32 = to32(dval);
-                if ((st = upload(h, &G.val32, v32.data(), v32.size()))) return st;
-            }
-            if (l < L - 1) {
-                // A M^-1 in place: a_ij minv_j on every stored diagonal slot
-                // (slots outside the matrix hold 0 and stay 0)
-                const int64_t ns = (int64_t)dstart.size() - 1;
-#pragma omp parallel for schedule(static)
-                for (int64_t sl = 0; sl < ns; sl++)
-                    for (int32_t k = dstart[sl]; k < dstart[sl + 1]; k++)
-                        for (int lane = 0; lane < SLICE; lane++) {
-                            const int64_t c = sl * SLICE + lane + doffs[k];
-                            double& x = dval[(size_t)k * SLICE + lane];
-                            if (c >= 0 && c < H.n) x = x * mv[c];
-                        }
-                if ((st = upload(h, &D.amd, dval.data(), dval.size()))) return st;
-                if (f32) {
-                    auto s32 = to32(dval);
-                    if ((st = upload(h, &D.amd32, s32.data(), s32.size()))) return st;
+            // hacked-DIA copy when it stores at most 4/3 of the ELL slots (8
+            // instead of 12 bytes per slot: at least 11 % fewer bytes)
+            std::vector<int32_t> dstart, doffs, duo;
+            std::vector<double> none;
+            if (pack_dia(H.n, H.n, H.rp.data(), H.ci.data(), nullptr, D.A.slots * 4 / 3, dstart, doffs, none,
+                         &duo)) {
+                DevDia& G = D.Ad;
+                G.nrows = H.n;
+                G.ncols = H.n;
+                G.nslices = (long long)dstart.size() - 1;
+                G.slots = (long long)dstart.back() * SLICE;
+                for (size_t q = 0; q + 1 < dstart.size(); q++)
+                    G.ndmax = std::max(G.ndmax, dstart[q + 1] - dstart[q]);
+                G.nd_u = (int)duo.size();
+                G.nd = h->dia_uniform ? G.nd_u : 0;
+                for (size_t k = 0; k < duo.size() && k < 8; k++) G.uo[k] = duo[k];
+                if ((st = upload(h, &G.start, dstart.data(), dstart.size()))) return st;
+                if ((st = upload(h, &G.offs, doffs.data(), doffs.size()))) return st;
+                const size_t slots = (size_t)G.slots;
+                if ((st = zalloc(h, (void**)&G.val, slots * sizeof(double)))) return st;
+                if (f32 && (st = zalloc(h, (void**)&G.val32, slots * sizeof(float)))) return st;
+                if (l < L - 1) {
+                    if ((st = zalloc(h, (void**)&D.amd, slots * sizeof(double)))) return st;
+                    if (f32 && (st = zalloc(h, (void**)&D.amd32, slots * sizeof(float)))) return st;
                 }
             }
         }
+        const int32_t* a_rp_dev = nullptr;   // A's rows staged on the device (kept until R is filled)
+        if ((st = refresh_values(h, D.A, &D.Ad, H.n, H.rp.data(), H.v.data(), l < L - 1 ? mv.data() : nullptr,
+                                 D.am, D.am32, D.amd, D.amd32, &a_rp_dev)))
+            return st;
+        if ((st = upload(h, &D.minv, mv.data(), H.n))) return st;
         if (f32) {
             auto m32 = to32(mv);
             if ((st = upload(h, &D.minv32, m32.data(), m32.size()))) return st;
@@ -3265,12 +3283,19 @@ static int upload_levels(psc_hier* h) {
                 auto p32 = to32(H.p);
                 if ((st = upload(h, &D.pval32, p32.data(), p32.size()))) return st;
             }
-            // tentative prolongator (row i: p_i at agg_i) on a refresh: S P is
-            // recomputed on the device from A's refreshed slots
+            // smoothed prolongator S P = (I - M^-1 A) P of the split post-smoothing
+            // sweep. Tentative prolongator (row i: p_i at agg_i): its layout is
+            // the distinct aggregates of each row's columns, its values are formed
+            // on the device from A's slots (before R reuses the staging)
             const bool tentative = (int64_t)H.pci.size() == H.n && (int64_t)H.prp.size() == H.n + 1 &&
                                    H.prp[H.n] == H.n && !h->opts.smoothed_prol;
-            const bool sp_on_device = h->refresh && tentative && a_rp_dev != nullptr;
+            const bool sp_on_device = tentative && a_rp_dev != nullptr;
             if (sp_on_device) {
+                if (!h->refresh) {
+                    std::vector<int32_t> sprp, spci;
+                    tentative_sp_pattern(H, sprp, spci);
+                    if ((st = upload_ell_layout(h, D.SP, H.n, H.nc, sprp.data(), spci.data(), f32))) return st;
+                }
                 if (!D.SP.off || !D.SP.col || !D.SP.val || D.SP.nrows != H.n) return PSC_ERR_STATE;
                 std::string err;
                 if ((st = gpu_tentative_sp((void*)h->stream, H.n, D.A.off, D.A.col, D.A.val, a_rp_dev, D.agg, D.pval,
@@ -3291,19 +3316,21 @@ static int upload_levels(psc_hier* h) {
                     rv[o] = H.pv[m];
                 }
             }
-            if (h->refresh) st = refresh_values(h, D.R, nullptr, H.nc, rrp.data(), rv.data(), nullptr, nullptr,
-                                                nullptr, nullptr, nullptr);
-            else st = upload_ell(h, D.R, H.nc, H.n, rrp.data(), rci.data(), rv.data(), f32);
-            if (st) return st;
-            // smoothed prolongator for the split post-smoothing sweep
+            if (!h->refresh && (st = upload_ell_layout(h, D.R, H.nc, H.n, rrp.data(), rci.data(), f32))) return st;
+            if ((st = refresh_values(h, D.R, nullptr, H.nc, rrp.data(), rv.data(), nullptr, nullptr, nullptr, nullptr,
+                                     nullptr)))
+                return st;
+            // general prolongator: S P from the host's sparse product
             if (!sp_on_device) {
                 std::vector<int32_t> sprp, spci;
                 std::vector<double> spv;
                 jacobi_smoothed_prolongator(H, mv.data(), sprp, spci, spv);
-                if (h->refresh) st = refresh_values(h, D.SP, nullptr, H.n, sprp.data(), spv.data(), nullptr, nullptr,
-                                                    nullptr, nullptr, nullptr);
-                else st = upload_ell(h, D.SP, H.n, H.nc, sprp.data(), spci.data(), spv.data(), f32);
-                if (st) return st;
+                if (!h->refresh &&
+                    (st = upload_ell_layout(h, D.SP, H.n, H.nc, sprp.data(), spci.data(), f32)))
+                    return st;
+                if ((st = refresh_values(h, D.SP, nullptr, H.n, sprp.data(), spv.data(), nullptr, nullptr, nullptr,
+                                         nullptr, nullptr)))
+                    return st;
             }
             // the kept A P is not needed after this (a rebuild forms it again)
             std::vector<int32_t>().swap(H.aprp);

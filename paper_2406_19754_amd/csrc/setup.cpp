@@ -599,7 +599,8 @@ void pack_ell(int64_t nrows, const int32_t* rp, const int32_t* ci, const double*
         width[s] = wmax;
     }
     for (int64_t s = 0; s < ns; s++) off[s + 1] = off[s] + width[s] * S;
-    val.resize(off[ns]);
+    if (v) val.resize(off[ns]);
+    else val.clear();
     col.resize(off[ns]);
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < ns; s++) {
@@ -610,8 +611,13 @@ void pack_ell(int64_t nrows, const int32_t* rp, const int32_t* ci, const double*
             int last = (r < nrows && len > 0) ? ci[rp[r + 1] - 1] : 0;
             for (int k = 0; k < w; k++) {
                 long long slot = off[s] + (long long)k * S + lane;
-                if (k < len) { val[slot] = v[rp[r] + k]; col[slot] = ci[rp[r] + k]; }
-                else { val[slot] = 0.0; col[slot] = last; }
+                if (k < len) {
+                    if (v) val[slot] = v[rp[r] + k];
+                    col[slot] = ci[rp[r] + k];
+                } else {
+                    if (v) val[slot] = 0.0;
+                    col[slot] = last;
+                }
             }
         }
     }
@@ -873,6 +879,44 @@ void jacobi_smoothed_prolongator(const HostLevel& H, const double* minv, std::ve
     v.swap(T.v);
 }
 
+void tentative_sp_pattern(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci) {
+    const int64_t n = H.n;
+    rp.assign(n + 1, 0);
+    auto row = [&](int64_t i, int32_t* out) {
+        // distinct aggregates of row i's columns, ascending (rows are short)
+        int32_t cnt = 0;
+        for (int32_t k = H.rp[i]; k < H.rp[i + 1]; k++) {
+            const int32_t J = H.agg[H.ci[k]];
+            int32_t q = 0;
+            while (q < cnt && out[q] < J) q++;
+            if (q < cnt && out[q] == J) continue;
+            for (int32_t u = cnt; u > q; u--) out[u] = out[u - 1];
+            out[q] = J;
+            cnt++;
+        }
+        return cnt;
+    };
+    int32_t wmax = 0;
+    for (int64_t i = 0; i < n; i++) wmax = std::max(wmax, H.rp[i + 1] - H.rp[i]);
+#pragma omp parallel
+    {
+        std::vector<int32_t> buf(wmax + 1);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; i++) rp[i + 1] = row(i, buf.data());
+    }
+    for (int64_t i = 0; i < n; i++) rp[i + 1] += rp[i];
+    ci.resize(rp[n]);
+#pragma omp parallel
+    {
+        std::vector<int32_t> buf(wmax + 1);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; i++) {
+            const int32_t c = row(i, buf.data());
+            std::copy(buf.begin(), buf.begin() + c, ci.begin() + rp[i]);
+        }
+    }
+}
+
 bool pack_dia(int64_t nrows, int64_t ncols, const int32_t* rp, const int32_t* ci, const double* v,
               long long max_slots, std::vector<int32_t>& start, std::vector<int32_t>& offs,
               std::vector<double>& val, std::vector<int32_t>* uniform) {
@@ -928,6 +972,8 @@ bool pack_dia(int64_t nrows, int64_t ncols, const int32_t* rp, const int32_t* ci
         for (int64_t s = 0; s <= ns; s++) start[s] = (int32_t)(s * nd);
         offs.resize(ns * nd);
         for (int64_t s = 0; s < ns; s++) std::copy(uni.begin(), uni.end(), offs.begin() + s * nd);
+        *uniform = uni;
+        if (!v) return true;
         val.assign((size_t)(ns * nd) * 64, 0.0);
 #pragma omp parallel for schedule(static)
         for (int64_t s = 0; s < ns; s++) {
@@ -939,7 +985,6 @@ bool pack_dia(int64_t nrows, int64_t ncols, const int32_t* rp, const int32_t* ci
                     val[(size_t)(s * nd + kk) * 64 + (size_t)(i - s * 64)] = v[k];
                 }
         }
-        *uniform = uni;
         return true;
     }
     for (int64_t s = 0; s < ns; s++) cnt[s + 1] += cnt[s];
@@ -947,7 +992,7 @@ bool pack_dia(int64_t nrows, int64_t ncols, const int32_t* rp, const int32_t* ci
     start.resize(ns + 1);
     for (int64_t s = 0; s <= ns; s++) start[s] = (int32_t)cnt[s];
     offs.resize(cnt[ns]);
-    val.assign((size_t)cnt[ns] * 64, 0.0);
+    if (v) val.assign((size_t)cnt[ns] * 64, 0.0);
 #pragma omp parallel
     {
         std::vector<int32_t> o;
@@ -955,6 +1000,7 @@ bool pack_dia(int64_t nrows, int64_t ncols, const int32_t* rp, const int32_t* ci
         for (int64_t s = 0; s < ns; s++) {
             slice_offsets(s, o);
             std::copy(o.begin(), o.end(), offs.begin() + cnt[s]);
+            if (!v) continue;
             const int64_t r1 = std::min<int64_t>(nrows, (s + 1) * 64);
             for (int64_t i = s * 64; i < r1; i++) {
                 for (int32_t k = rp[i]; k < rp[i + 1]; k++) {

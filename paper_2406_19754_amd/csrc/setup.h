@@ -111,6 +111,11 @@ int gpu_coarsen_level(int64_t n, const int32_t* rp, const int32_t* ci, const dou
                       std::vector<double>& wc, std::vector<int32_t>& crp, std::vector<int32_t>& cci,
                       std::vector<double>& cv, std::string& err);
 
+// Pattern of S P for the tentative prolongator (one entry per row of P, at
+// column agg_i): row i holds the distinct aggregates of its columns,
+// ascending, which is the pattern jacobi_smoothed_prolongator stores.
+void tentative_sp_pattern(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci);
+
 // Numeric rebuild, tentative prolongator: S P = (I - M^-1 A) P recomputed on
 // the device into the build's hacked-ELL slots of S P from A's refreshed
 // hacked-ELL values (a_rp: A's row pointers, device), agg, p and minv, with
@@ -124,6 +129,7 @@ int gpu_tentative_sp(void* stream, int64_t n, const long long* a_off, const int*
 // slice, values diagonal-major in a slice, zeros where a row has no entry).
 // Returns false and packs nothing when the diagonal slots would exceed
 // max_ratio times max_slots, or when row + offset could leave int32.
+// v == NULL packs the layout only (start, offs, uniform; val left empty).
 // With uniform != NULL and at most 8 distinct offsets over the whole matrix,
 // every slice gets all of them (zeros where a row has no entry) and *uniform
 // receives the offsets (ascending); otherwise it is left empty.
@@ -134,6 +140,7 @@ bool pack_dia(int64_t nrows, int64_t ncols, const int32_t* rp, const int32_t* ci
 // Pack CSR rows into hacked ELL with 64-row slices (column-major in a
 // slice). Padding slots carry value 0 and repeat the row's last column (0 for
 // rows past the end), so every slot reads a valid, usually cached, entry.
+// v == NULL packs the layout only (off and col; val left empty).
 void pack_ell(int64_t nrows, const int32_t* rp, const int32_t* ci, const double* v,
               std::vector<long long>& off, std::vector<double>& val, std::vector<int>& col);
 
