@@ -134,7 +134,8 @@ def time_configs(args, psc, torch, rp, col, val, bd, x, ms64=None):
     for cfg in [c for c in args.configs.split(",") if c]:
         t0 = time.time()
         hs = psc.Hierarchy(rp, col, val, build_fp32=not args.no_mixed, use_graph=not args.no_graph,
-                           setup_device=not args.config_host_setup, **extra[cfg])
+                           setup_device=not args.config_host_setup,
+                           setup_device_products=args.device_products, **extra[cfg])
         infs = hs.info()
         log(f"{cfg} hierarchy {infs['rows']} built in {time.time() - t0:.1f}s, "
             f"opcx {infs['operator_complexity']:.4f}")
@@ -216,6 +217,8 @@ def main():
     ap.add_argument("--rebuild-timing", action="store_true",
                     help="time a numeric-only rebuild (new coefficients on the same pattern) against the full "
                          "build, then solve with the rebuilt hierarchy (one JSON line)")
+    ap.add_argument("--device-products", action="store_true",
+                    help="smoothed-prolongator settings: form their sparse products on the GPU")
     ap.add_argument("--config-host-setup", action="store_true",
                     help="build the --configs hierarchies with the host setup only")
     ap.add_argument("--no-split", action="store_true",

@@ -95,6 +95,14 @@ typedef struct psc_net  psc_net;    /* opaque: owns the learned preconditioner  
  *                    bit; levels the kernels cannot take (a coarse row with
  *                    more than 64 distinct columns) fall back to the host.
  *                    Ignored (host setup) with host_only.
+ *   setup_device_products = 0  with setup_device and the smoothed
+ *                    prolongator, also form omega, P, A P and the Galerkin
+ *                    product P^T (A P) on the GPU (sparse products summed in
+ *                    the host's order: the same hierarchy bit for bit); levels
+ *                    whose operator rows exceed 64 entries, or whose product
+ *                    rows exceed 1024 columns, stay on the host. Off by
+ *                    default: the products travel back to the host, and those
+ *                    transfers cost about what the host's products do.
  *   build_fp32 = 0   also build the FP32 copies of the level operators that
  *                    the mixed-precision V-cycle needs.
  *   use_graph = 1    capture the per-iteration kernel sequence as a HIP
@@ -161,7 +169,7 @@ typedef struct {
     int32_t smoother;
     int32_t invk_fill;
     int32_t invk_inv_fill;
-    int32_t reserved;
+    int32_t setup_device_products;
     double  vbm_theta;
     double  ainv_tau;
     int32_t coarse_pcg_iters;

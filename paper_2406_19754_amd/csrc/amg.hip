@@ -3163,6 +3163,7 @@ static SetupOpts setup_opts_of(const psc_hier* h) {
     so.aggr = h->opts.aggregation;
     so.theta = h->opts.vbm_theta;
     so.device = h->opts.setup_device != 0 && !h->opts.host_only;
+    so.device_products = so.device && h->opts.setup_device_products != 0;
     so.smoother = h->opts.smoother;
     so.tau = h->opts.ainv_tau;
     so.fill1 = h->opts.invk_fill;
@@ -3379,6 +3380,7 @@ void psc_amg_opts_default(psc_amg_opts* o) {
     o->aggregation = PSC_AGGR_MATCHING;
     o->vbm_theta = 0.01;
     o->setup_device = 1;
+    o->setup_device_products = 0;
     o->smoother = PSC_SMOOTH_L1JACOBI;
     o->invk_fill = 0;
     o->invk_inv_fill = 1;

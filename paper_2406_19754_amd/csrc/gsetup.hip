@@ -23,9 +23,19 @@
 // aggregate has at most 2^sweeps members); the only other primitive is an
 // integer exclusive scan. Rows with more than GS_MAXC distinct coarse
 // columns are reported so the caller can build that level on the host.
+//
+// For the smoothed prolongator (Section "Aggregation strategies", the
+// prolongator smoothed by one damped Jacobi step) the level's products run
+// here as well: omega = 1 / max_i sum_j |a_ij| / a_ii, T = A P^ and
+// P = P^ - (omega / a_ii) T row by row, A P, R = P^T and the Galerkin
+// operator R (A P), each sparse product summed as the host's: for row i the
+// products a_ik b_kj for k ascending, then row k of B ascending, added into
+// column j in that order (the first assigns), columns stored ascending.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -408,6 +418,133 @@ int gs_galerkin(hipStream_t st, int nc, int stride, const int* mem, int n, const
     return PSC_OK;
 }
 
+constexpr int SG_CAP = 1024;            // distinct columns one product row may collect
+constexpr int SG_WAVES = GS_WG / 64;
+constexpr int SG_MAX_AROW = 64;        // longest operator row the device products take
+
+// C = A B, one row per wavefront: the row's distinct columns and their sums
+// in LDS, each product looked up by the whole wavefront (ballot) and added by
+// one lane, in the order the products arrive. pass 0 writes the row lengths,
+// pass 1 the row with its columns sorted (rank of each column). A row with
+// more than SG_CAP columns sets *overflow.
+__global__ __launch_bounds__(GS_WG) void k_sg_spgemm(int n, const int* __restrict__ arp, const int* __restrict__ aci,
+                                                     const double* __restrict__ av, const int* __restrict__ brp,
+                                                     const int* __restrict__ bci, const double* __restrict__ bv,
+                                                     int pass, int* __restrict__ len, const int* __restrict__ crp,
+                                                     int* __restrict__ cci, double* __restrict__ cv, int* overflow) {
+    __shared__ int scol[SG_WAVES][SG_CAP];
+    __shared__ double sval[SG_WAVES][SG_CAP];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int* cols = scol[wv];
+    double* vals = sval[wv];
+    for (int i = blockIdx.x * SG_WAVES + wv; i < n; i += gridDim.x * SG_WAVES) {
+        int nq = 0;
+        bool over = false;
+        for (int ka = arp[i]; ka < arp[i + 1] && !over; ka++) {
+            const int k = aci[ka];
+            const double a = av[ka];
+            for (int kb = brp[k]; kb < brp[k + 1]; kb++) {
+                const int J = bci[kb];
+                const double x = __dmul_rn(a, bv[kb]);
+                int pos = -1;
+                for (int base = 0; base < nq && pos < 0; base += 64) {
+                    const int q = base + lane;
+                    const unsigned long long m = __ballot(q < nq && cols[q] == J);
+                    if (m) pos = base + __ffsll((long long)m) - 1;
+                }
+                if (pos >= 0) {
+                    if (lane == 0) vals[pos] = __dadd_rn(vals[pos], x);
+                } else if (nq == SG_CAP) {
+                    over = true;
+                    break;
+                } else {
+                    if (lane == 0) {
+                        cols[nq] = J;
+                        vals[nq] = x;
+                    }
+                    nq++;
+                }
+                // the next lookup reads what lane 0 wrote (one wavefront: in order)
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (over) {
+            if (lane == 0) {
+                atomicOr(overflow, 1);
+                if (pass == 0) len[i] = 0;
+            }
+            continue;
+        }
+        if (pass == 0) {
+            if (lane == 0) len[i] = nq;
+            continue;
+        }
+        const int o = crp[i];
+        for (int q = lane; q < nq; q += 64) {
+            const int c = cols[q];
+            int rank = 0;
+            for (int u = 0; u < nq; u++) rank += cols[u] < c ? 1 : 0;
+            cci[o + rank] = c;
+            cv[o + rank] = vals[q];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// max over rows of sum_j |a_ij| / a_ii (positive values order like their bit
+// patterns as signed integers; the host's maximum starts at 0 as well)
+__global__ void k_sg_ratio(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const double* __restrict__ v, long long* maxbits) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double sabs = 0.0, aii = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; k++) {
+            sabs = __dadd_rn(sabs, fabs(v[k]));
+            if (ci[k] == i) aii = v[k];
+        }
+        const double r = sabs / aii;
+        if (r > 0.0) atomicMax(maxbits, __double_as_longlong(r));
+    }
+}
+
+// P = P^ - (omega / a_ii) T in place of T (T = A P^, same pattern)
+__global__ void k_sg_pm(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
+                        const int* __restrict__ agg, const double* __restrict__ p, double omega,
+                        const int* __restrict__ trp, const int* __restrict__ tci, double* __restrict__ tv) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double aii = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; k++)
+            if (ci[k] == i) aii = v[k];
+        const double f = omega / aii;
+        for (int m = trp[i]; m < trp[i + 1]; m++) {
+            const double pk = tci[m] == agg[i] ? p[i] : 0.0;
+            tv[m] = __dsub_rn(pk, __dmul_rn(f, tv[m]));
+        }
+    }
+}
+
+__global__ void k_sg_rows(int n, const int* __restrict__ rp, int* __restrict__ row) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        for (int m = rp[i]; m < rp[i + 1]; m++) row[m] = i;
+}
+
+__global__ void k_sg_count(int nnz, const int* __restrict__ col, int* __restrict__ cnt) {
+    for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < nnz; m += gridDim.x * blockDim.x)
+        atomicAdd(&cnt[col[m]], 1);
+}
+
+// R = P^T from the entries sorted stably by column: R row J lists the rows i
+// of column J ascending
+__global__ void k_sg_tfill(int nnz, const int* __restrict__ order, const int* __restrict__ row,
+                           const double* __restrict__ pv, int* __restrict__ rci, double* __restrict__ rv) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nnz; t += gridDim.x * blockDim.x) {
+        const int m = order[t];
+        rci[t] = row[m];
+        rv[t] = pv[m];
+    }
+}
+
 // S P = (I - M^-1 A) P for the tentative prolongator (one entry p_j at
 // column agg_j in row j of P), in place in the build's hacked-ELL slots of S P:
 // row i's columns are the distinct aggregates of its columns, ascending, so
@@ -455,6 +592,50 @@ __global__ void k_gs_tentative_sp(long long n, const long long* __restrict__ a_o
             if (sp_val32) sp_val32[slot] = (float)val;
         }
     }
+}
+
+inline int sg_grid(long long rows) {
+    long long g = (rows + SG_WAVES - 1) / SG_WAVES;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+// C = A B on the device (row lengths, scan, rows); PSC_ERR_STATE when a row
+// of C would collect more than SG_CAP columns
+int sg_spgemm(hipStream_t st, int n, const int* arp, const int* aci, const double* av, const int* brp, const int* bci,
+              const double* bv, DBuf<int>& crp, DBuf<int>& cci, DBuf<double>& cv, int& cnnz, std::string& err) {
+    DBuf<int> len, over;
+    GS_CHK(len.alloc(n));
+    GS_CHK(over.alloc(1));
+    GS_CHK(hipMemsetAsync(over.p, 0, sizeof(int), st));
+    k_sg_spgemm<<<sg_grid(n), GS_WG, 0, st>>>(n, arp, aci, av, brp, bci, bv, 0, len.p, nullptr, nullptr, nullptr,
+                                              over.p);
+    GS_CHK(hipGetLastError());
+    int ov = 0;
+    GS_CHK(hipMemcpyAsync(&ov, over.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    GS_CHK(hipStreamSynchronize(st));
+    if (ov) return PSC_ERR_STATE;
+    GS_CHK(crp.alloc((size_t)n + 1));
+    int total = 0;
+    int r = gs_scan(st, n, len.p, crp.p, total, err);
+    if (r) return r;
+    if (total < 0) return PSC_ERR_STATE;
+    GS_CHK(hipMemcpyAsync(crp.p + n, &total, sizeof(int), hipMemcpyHostToDevice, st));
+    GS_CHK(cci.alloc(total));
+    GS_CHK(cv.alloc(total));
+    k_sg_spgemm<<<sg_grid(n), GS_WG, 0, st>>>(n, arp, aci, av, brp, bci, bv, 1, nullptr, crp.p, cci.p, cv.p, over.p);
+    GS_CHK(hipGetLastError());
+    GS_CHK(hipStreamSynchronize(st));
+    cnnz = total;
+    return PSC_OK;
+}
+
+template <typename T>
+int sg_download(hipStream_t st, const DBuf<T>& d, size_t count, std::vector<T>& out, std::string& err) {
+    out.resize(count);
+    if (count) GS_CHK(hipMemcpyAsync(out.data(), d.p, count * sizeof(T), hipMemcpyDeviceToHost, st));
+    return PSC_OK;
 }
 
 }  // namespace
@@ -618,6 +799,126 @@ int gpu_tentative_sp(void* stream, int64_t n, const long long* a_off, const int*
     k_gs_tentative_sp<<<gs_grid(n), GS_WG, 0, st>>>(n, a_off, a_col, a_val, a_rp, agg, p, minv, sp_off, sp_col,
                                                      sp_val, sp_val32);
     GS_CHK(hipGetLastError());
+    GS_CHK(hipStreamSynchronize(st));
+    return PSC_OK;
+}
+
+int gpu_smoothed_products(int64_t n64, const int32_t* hrp, const int32_t* hci, const double* hv, const int32_t* hagg,
+                          const double* hp, int64_t nc64, double& omega, std::vector<int32_t>& prp_out,
+                          std::vector<int32_t>& pci_out, std::vector<double>& pv_out, std::vector<int32_t>& aprp_out,
+                          std::vector<int32_t>& apci_out, std::vector<double>& apv_out,
+                          std::vector<int32_t>& crp_out, std::vector<int32_t>& cci_out, std::vector<double>& cv_out,
+                          std::string& err) {
+    const int64_t nnz64 = hrp[n64];
+    if (n64 >= ((int64_t)1 << 30) || nnz64 >= ((int64_t)1 << 31) || nc64 < 1 || nc64 > n64) {
+        err = "level too large for device products";
+        return PSC_ERR_STATE;
+    }
+    const int n = (int)n64, nnz = (int)nnz64, nc = (int)nc64;
+    // wide operator rows make product rows too wide and slow for one
+    // wavefront's sequential sums: those levels stay on the host
+    for (int i = 0; i < n; i++)
+        if (hrp[i + 1] - hrp[i] > SG_MAX_AROW) {
+            err = "operator rows too wide for device products";
+            return PSC_ERR_STATE;
+        }
+    hipStream_t st;
+    GS_CHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+    } guard{st};
+    DBuf<int> rp, ci, agg, iota;
+    DBuf<double> v, p;
+    GS_CHK(rp.alloc((size_t)n + 1));
+    GS_CHK(ci.alloc(nnz));
+    GS_CHK(v.alloc(nnz));
+    GS_CHK(agg.alloc(n));
+    GS_CHK(p.alloc(n));
+    GS_CHK(iota.alloc((size_t)n + 1));
+    GS_CHK(hipMemcpyAsync(rp.p, hrp, ((size_t)n + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+    GS_CHK(hipMemcpyAsync(ci.p, hci, (size_t)nnz * sizeof(int), hipMemcpyHostToDevice, st));
+    GS_CHK(hipMemcpyAsync(v.p, hv, (size_t)nnz * sizeof(double), hipMemcpyHostToDevice, st));
+    GS_CHK(hipMemcpyAsync(agg.p, hagg, (size_t)n * sizeof(int), hipMemcpyHostToDevice, st));
+    GS_CHK(hipMemcpyAsync(p.p, hp, (size_t)n * sizeof(double), hipMemcpyHostToDevice, st));
+    k_gs_iota<<<gs_grid((long long)n + 1), GS_WG, 0, st>>>(n + 1, iota.p);
+    // omega = 1 / max_i sum_j |a_ij| / a_ii
+    DBuf<long long> mb;
+    GS_CHK(mb.alloc(1));
+    GS_CHK(hipMemsetAsync(mb.p, 0, sizeof(long long), st));
+    k_sg_ratio<<<gs_grid(n), GS_WG, 0, st>>>(n, rp.p, ci.p, v.p, mb.p);
+    GS_CHK(hipGetLastError());
+    long long bits = 0;
+    GS_CHK(hipMemcpyAsync(&bits, mb.p, sizeof(long long), hipMemcpyDeviceToHost, st));
+    GS_CHK(hipStreamSynchronize(st));
+    double norm = 0.0;
+    static_assert(sizeof(norm) == sizeof(bits), "64-bit double");
+    std::memcpy(&norm, &bits, sizeof(norm));
+    omega = 1.0 / norm;
+    // T = A P^ (P^: row i holds p_i at column agg_i), then P in place
+    DBuf<int> trp, tci;
+    DBuf<double> tv;
+    int tnnz = 0;
+    int r = sg_spgemm(st, n, rp.p, ci.p, v.p, iota.p, agg.p, p.p, trp, tci, tv, tnnz, err);
+    if (r) return r;
+    k_sg_pm<<<gs_grid(n), GS_WG, 0, st>>>(n, rp.p, ci.p, v.p, agg.p, p.p, omega, trp.p, tci.p, tv.p);
+    GS_CHK(hipGetLastError());
+    // A P
+    DBuf<int> aprp, apci;
+    DBuf<double> apv;
+    int apnnz = 0;
+    r = sg_spgemm(st, n, rp.p, ci.p, v.p, trp.p, tci.p, tv.p, aprp, apci, apv, apnnz, err);
+    if (r) return r;
+    // R = P^T: entries sorted stably by column keep their rows ascending
+    DBuf<int> row, keys_out, order, idx, cnt, rrp, rci;
+    DBuf<double> rv;
+    GS_CHK(row.alloc(tnnz));
+    GS_CHK(keys_out.alloc(tnnz));
+    GS_CHK(order.alloc(tnnz));
+    GS_CHK(idx.alloc(tnnz));
+    GS_CHK(cnt.alloc(nc));
+    GS_CHK(rrp.alloc((size_t)nc + 1));
+    GS_CHK(rci.alloc(tnnz));
+    GS_CHK(rv.alloc(tnnz));
+    k_sg_rows<<<gs_grid(n), GS_WG, 0, st>>>(n, trp.p, row.p);
+    k_gs_iota<<<gs_grid(tnnz), GS_WG, 0, st>>>(tnnz, idx.p);
+    GS_CHK(hipMemsetAsync(cnt.p, 0, (size_t)nc * sizeof(int), st));
+    k_sg_count<<<gs_grid(tnnz), GS_WG, 0, st>>>(tnnz, tci.p, cnt.p);
+    GS_CHK(hipGetLastError());
+    int end_bit = 1;
+    while (end_bit < 31 && ((int64_t)1 << end_bit) < nc64) end_bit++;
+    size_t tmp_bytes = 0;
+    GS_CHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, tci.p, keys_out.p, idx.p, order.p, tnnz, 0, end_bit,
+                                             st));
+    DBuf<char> tmp;
+    GS_CHK(tmp.alloc(tmp_bytes));
+    GS_CHK(hipcub::DeviceRadixSort::SortPairs(tmp.p, tmp_bytes, tci.p, keys_out.p, idx.p, order.p, tnnz, 0, end_bit,
+                                             st));
+    int rtotal = 0;
+    r = gs_scan(st, nc, cnt.p, rrp.p, rtotal, err);
+    if (r) return r;
+    if (rtotal != tnnz) {
+        err = "device transpose lost entries";
+        return PSC_ERR_HIP;
+    }
+    GS_CHK(hipMemcpyAsync(rrp.p + nc, &rtotal, sizeof(int), hipMemcpyHostToDevice, st));
+    k_sg_tfill<<<gs_grid(tnnz), GS_WG, 0, st>>>(tnnz, order.p, row.p, tv.p, rci.p, rv.p);
+    GS_CHK(hipGetLastError());
+    // A_{l+1} = R (A P)
+    DBuf<int> crp, cci;
+    DBuf<double> cv;
+    int cnnz = 0;
+    r = sg_spgemm(st, nc, rrp.p, rci.p, rv.p, aprp.p, apci.p, apv.p, crp, cci, cv, cnnz, err);
+    if (r) return r;
+    if ((r = sg_download(st, trp, (size_t)n + 1, prp_out, err))) return r;
+    if ((r = sg_download(st, tci, (size_t)tnnz, pci_out, err))) return r;
+    if ((r = sg_download(st, tv, (size_t)tnnz, pv_out, err))) return r;
+    if ((r = sg_download(st, aprp, (size_t)n + 1, aprp_out, err))) return r;
+    if ((r = sg_download(st, apci, (size_t)apnnz, apci_out, err))) return r;
+    if ((r = sg_download(st, apv, (size_t)apnnz, apv_out, err))) return r;
+    if ((r = sg_download(st, crp, (size_t)nc + 1, crp_out, err))) return r;
+    if ((r = sg_download(st, cci, (size_t)cnnz, cci_out, err))) return r;
+    if ((r = sg_download(st, cv, (size_t)cnnz, cv_out, err))) return r;
     GS_CHK(hipStreamSynchronize(st));
     return PSC_OK;
 }

@@ -521,6 +521,15 @@ void level_numeric(const Csr& A, const SetupOpts& o, HostLevel& F, HostLevel& Cl
         F.pci = F.agg;
         F.pv = F.p;
         galerkin(A, F.agg, nc, F.p.data(), Ac);
+    } else if (o.device_products && [&] {
+                   // the same products on the GPU (bit-identical); a row too wide
+                   // for its kernels, or any device error, leaves them to the host
+                   std::string derr;
+                   return gpu_smoothed_products(A.n, A.rp.data(), A.ci.data(), A.v.data(), F.agg.data(),
+                                                F.p.data(), nc, F.omega, F.prp, F.pci, F.pv, F.aprp, F.apci,
+                                                F.apv, Ac.rp, Ac.ci, Ac.v, derr) == PSC_OK;
+               }()) {
+        Ac.n = nc;
     } else {
         // smoothed: omega = 1 / max_i sum_j |a_ij| / a_ii, then
         // P_iJ = [J = agg_i] p_i - (omega / a_ii) (A P^)_iJ and C = P^T (A P)

@@ -56,6 +56,7 @@ struct SetupOpts {
     int aggr = 0;               // 0 coupled matching, 1 decoupled VBM
     double theta = 0.01;        // VBM strength threshold
     bool device = false;        // coarsen matching / tentative levels on the GPU
+    bool device_products = false;   // smoothed prolongator: its products on the GPU
     int smoother = 0;           // 0 l1-Jacobi, 1 AINV, 2 INVK, 3 polynomial (levels above the coarsest)
     double tau = 0.1;           // AINV drop tolerance
     int fill1 = 0, fill2 = 1;   // INVK fill levels of the factor and of its inverse
@@ -110,6 +111,17 @@ int gpu_coarsen_level(int64_t n, const int32_t* rp, const int32_t* ci, const dou
                       int sweeps, bool want_coarse, std::vector<int32_t>& agg, int64_t& nc, std::vector<double>& p,
                       std::vector<double>& wc, std::vector<int32_t>& crp, std::vector<int32_t>& cci,
                       std::vector<double>& cv, std::string& err);
+
+// The smoothed prolongator's products of one level on the GPU, bit-identical
+// to the host's: omega, P = (I - omega D^-1 A) P^ (CSR), A P (CSR) and the
+// Galerkin operator P^T (A P) (CSR), from the level's CSR, its aggregates and
+// p (P^_{i,agg_i} = p_i). Returns PSC_ERR_STATE when a product row exceeds
+// the device kernels' column capacity (the caller then uses the host).
+int gpu_smoothed_products(int64_t n, const int32_t* rp, const int32_t* ci, const double* v, const int32_t* agg,
+                          const double* p, int64_t nc, double& omega, std::vector<int32_t>& prp,
+                          std::vector<int32_t>& pci, std::vector<double>& pv, std::vector<int32_t>& aprp,
+                          std::vector<int32_t>& apci, std::vector<double>& apv, std::vector<int32_t>& crp,
+                          std::vector<int32_t>& cci, std::vector<double>& cv, std::string& err);
 
 // Pattern of S P for the tentative prolongator (one entry per row of P, at
 // column agg_i): row i holds the distinct aggregates of its columns,

@@ -45,7 +45,7 @@ class AmgOpts(C.Structure):
                 ("coarse_sweeps", C.c_int32), ("smoothed_prol", C.c_int32), ("smoother_sweeps", C.c_int32),
                 ("vcycle_double", C.c_int32), ("aggregation", C.c_int32), ("setup_device", C.c_int32),
                 ("smoother", C.c_int32), ("invk_fill", C.c_int32), ("invk_inv_fill", C.c_int32),
-                ("reserved", C.c_int32), ("vbm_theta", C.c_double), ("ainv_tau", C.c_double),
+                ("setup_device_products", C.c_int32), ("vbm_theta", C.c_double), ("ainv_tau", C.c_double),
                 ("coarse_pcg_iters", C.c_int32), ("reserved2", C.c_int32), ("coarse_rtol", C.c_double)]
 
 
@@ -155,7 +155,7 @@ class Hierarchy:
                  build_fp32=False, use_graph=True, host_only=False, stream=None, coarse_sweeps=30,
                  smoothed_prol=False, smoother_sweeps=1, vcycle_double=False, aggregation=0, vbm_theta=0.01,
                  setup_device=True, smoother=SMOOTH_L1JACOBI, ainv_tau=0.1, invk_fill=0, invk_inv_fill=1,
-                 coarse_pcg_iters=0, coarse_rtol=1e-4):
+                 coarse_pcg_iters=0, coarse_rtol=1e-4, setup_device_products=False):
         import torch
         o = AmgOpts()
         _lib.psc_amg_opts_default(C.byref(o))
@@ -164,7 +164,7 @@ class Hierarchy:
         o.smoothed_prol, o.smoother_sweeps = int(smoothed_prol), smoother_sweeps
         o.vcycle_double = int(vcycle_double)
         o.aggregation, o.vbm_theta = aggregation, vbm_theta
-        o.setup_device = int(setup_device)
+        o.setup_device, o.setup_device_products = int(setup_device), int(setup_device_products)
         o.smoother, o.ainv_tau, o.invk_fill, o.invk_inv_fill = smoother, ainv_tau, invk_fill, invk_inv_fill
         o.coarse_pcg_iters, o.coarse_rtol = coarse_pcg_iters, coarse_rtol
         o.build_fp32, o.use_graph, o.host_only = int(build_fp32), int(use_graph), int(host_only)

@@ -418,13 +418,14 @@ def test_smoothing_configurations_match_oracle(psc, case, cfg):
                                                      ("poisson24", 3, 200, False), ("diffusion20_az100", 2, 200, False),
                                                      ("random_long_rows", 2, 40, False),
                                                      ("diffusion48_lognormal", 2, 200, False),
-                                                     # smoothed prolongator: device aggregates, host products
+                                                     # smoothed prolongator: device aggregates and products
                                                      ("poisson24", 3, 200, True), ("poisson13", 3, 200, True),
                                                      ("diffusion20_az100", 3, 200, True),
                                                      ("random_long_rows", 2, 40, True)])
 def test_device_setup_bit_identical_to_host(psc, case, sweeps, cm, smoothed):
     rp, c, v = P.poisson7(24) if case == "poisson24" else CASES[case]()
-    hd = psc.Hierarchy(rp, c, v, sweeps=sweeps, coarse_max=cm, setup_device=True, smoothed_prol=smoothed)
+    hd = psc.Hierarchy(rp, c, v, sweeps=sweeps, coarse_max=cm, setup_device=True, smoothed_prol=smoothed,
+                       setup_device_products=smoothed)
     hh = psc.Hierarchy(rp, c, v, sweeps=sweeps, coarse_max=cm, setup_device=False, host_only=True,
                        smoothed_prol=smoothed)
     a, b = hd.info(), hh.info()
@@ -438,3 +439,24 @@ def test_device_setup_bit_identical_to_host(psc, case, sweeps, cm, smoothed):
             if smoothed:
                 px, py = hd.export_prolongator(l), hh.export_prolongator(l)
                 assert all(np.array_equal(u, w) for u, w in zip(px, py)), l
+
+
+@pytest.mark.parametrize("case", ["poisson24", "diffusion20_az100", "random_long_rows"])
+def test_device_products_of_vbm_smoothed_hierarchy_bit_identical_to_host(psc, case):
+    """VBM aggregation stays on the host; its smoothed prolongator's products
+    (omega, P, A P, P^T A P) run on the GPU and must equal the host's."""
+    rp, c, v = P.poisson7(24) if case == "poisson24" else CASES[case]()
+    cm = 40 if case == "random_long_rows" else 200
+    kw = dict(coarse_max=cm, aggregation=psc.AGGR_VBM, smoothed_prol=True, smoother_sweeps=4)
+    hd = psc.Hierarchy(rp, c, v, setup_device=True, setup_device_products=True, **kw)
+    hh = psc.Hierarchy(rp, c, v, setup_device=False, host_only=True, **kw)
+    a, b = hd.info(), hh.info()
+    assert a["rows"] == b["rows"] and a["nnz"] == b["nnz"] and a["omega"] == b["omega"]
+    assert a["levels"] >= 2
+    for l in range(a["levels"]):
+        x, y = hd.export_level(l), hh.export_level(l)
+        for key in ["rowptr", "col", "val", "minv"]:
+            assert np.array_equal(x[key], y[key]), (l, key)
+        if l < a["levels"] - 1:
+            px, py = hd.export_prolongator(l), hh.export_prolongator(l)
+            assert all(np.array_equal(u, w) for u, w in zip(px, py)), l

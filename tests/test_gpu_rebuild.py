@@ -31,6 +31,8 @@ def dev(a):
 CONFIGS = {
     "matching": (dict(), dict()),
     "smoothed_nu2": (dict(smoothed_prol=True, sweeps=3, smoother_sweeps=2), dict(prol=1, sweeps=3, nu=2)),
+    "smoothed_device_products": (dict(smoothed_prol=True, sweeps=3, smoother_sweeps=2, setup_device_products=True),
+                                 dict(prol=1, sweeps=3, nu=2)),
     "ainv": (dict(smoother=1), dict(smoother=1)),
     "cheb2": (dict(smoother=3, smoother_sweeps=2), dict(smoother=3, nu=2)),
 }
