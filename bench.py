@@ -407,6 +407,10 @@ def main():
                           "err_vs_fp64_x": float(np.linalg.norm(x32 - xg) / np.linalg.norm(xg))}
     forms.update(time_configs(args, psc, torch, rp, col, val, bd, x, ms64))
     if net is not None:
+        # the learned forms run inside FCG(1): its plain FP64 time is their reference
+        msf, rf, _ = timed("fcg64", args.steps, args.warmup, False)
+        log(f"fp64 fcg (no network): {msf:.2f} ms/solve, {rf['iters']} its, relres {rf['relres']:.2e}")
+        forms["fcg64"] = {"ms": msf, "iters": rf["iters"], "relres": rf["relres"], "speedup_vs_fp64": ms64 / msf}
         msl, rl, _ = timed("learned", args.steps, args.warmup, False)
         log(f"learned fcg: {msl:.2f} ms/solve, {rl['iters']} its, relres {rl['relres']:.2e}, "
             f"fallbacks {rl['fallbacks']}")

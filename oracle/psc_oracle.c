@@ -1863,9 +1863,10 @@ void orc_net_apply(const double *params, int nx, int ny, int nz, const double *r
  * B_k: form 0 = FP64 V-cycle, form 1 = FP32 V-cycle (orc_vcycle32).
  * With params != NULL (learned form), iterations k = 1, 3, 5, ... use the
  * network z = s net(r/s) instead; if z.r <= 0 that step takes the V-cycle
- * instead; if after a network step ||r_new|| > 0.9 ||r_old||, the network
- * is switched off for the rest of the solve. *fallbacks counts scheduled
- * network steps that ran the V-cycle instead.
+ * instead. The network is switched off for the rest of the solve when a
+ * network step leaves ||r_new|| > 0.9 ||r_old|| (stagnation), or when two
+ * network steps in a row fail z.r > 0. *fallbacks counts scheduled network
+ * steps that ran the V-cycle instead.
  */
 int orc_fcg(const orc_hier *h, int form, const double *params, int nx, int ny, int nz,
             const double *b, double *x, double rtol, int maxit, int *iters, double *relres,
@@ -1883,7 +1884,7 @@ int orc_fcg(const orc_hier *h, int form, const double *params, int nx, int ny, i
     double *pp = malloc(sizeof(double) * (size_t)n), *qp = malloc(sizeof(double) * (size_t)n);
     orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, q);
     for (int i = 0; i < n; i++) r[i] = b[i] - q[i];
-    int st = ORC_NOCONV, k = 0, have_prev = 0, net_on = params != NULL;
+    int st = ORC_NOCONV, k = 0, have_prev = 0, net_on = params != NULL, net_fails = 0;
     double pqp = 0.0;
     if (sqrt(dot(n, r, r)) <= rtol * nb) st = ORC_OK;
     while (st == ORC_NOCONV && k < maxit) {
@@ -1895,6 +1896,9 @@ int orc_fcg(const orc_hier *h, int form, const double *params, int nx, int ny, i
                 apply_prec(h, vform, r, z);
                 use_net = 0;
                 if (fallbacks) (*fallbacks)++;
+                if (++net_fails >= 2) net_on = 0;
+            } else {
+                net_fails = 0;
             }
         } else {
             if (params && !net_on && k % 2 == 1 && fallbacks) (*fallbacks)++;

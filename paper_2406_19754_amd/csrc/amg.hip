@@ -206,8 +206,23 @@ __device__ void finalize(int fin, double s0, double s1, Ctl* c, HostCtl* hc) {
         break;
     case FIN_NETCHECK:
         c->zr = s0;
-        if (!(s0 > 0.0)) { c->use_net = 0; c->fallbacks += 1; }   // the V-cycle runs instead
-        else { c->zq = s1; c->beta = c->have_prev ? s1 / c->pq_prev : 0.0; }
+        if (!(s0 > 0.0)) {
+            // not a descent direction: the V-cycle runs instead; a second
+            // such step in a row switches the network off for the solve
+            c->use_net = 0;
+            c->fallbacks += 1;
+            if (++c->net_fails >= 2) {
+                c->net_on = 0;
+                if (hc) {
+                    hc->net_off = 1;
+                    __threadfence_system();
+                }
+            }
+        } else {
+            c->net_fails = 0;
+            c->zq = s1;
+            c->beta = c->have_prev ? s1 / c->pq_prev : 0.0;
+        }
         break;
     default:
         break;
@@ -951,6 +966,7 @@ __global__ void k_ctl_init(Ctl* c, HostCtl* hc, double rtol, int maxit, int form
         c->fallbacks = 0;
         c->form = form;
         c->redo = 0;
+        c->net_fails = 0;
         if (hc) {
             hc->done = 0;
             hc->iter = 0;

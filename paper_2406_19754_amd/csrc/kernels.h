@@ -18,7 +18,7 @@ struct Ctl {
     int done, iter, status, maxit;
     int check, have_prev, net_on, use_net, fallbacks, form;
     int redo;      // fused FCG: the residual was replaced, redo the level-0 pre-smoothing
-    int pad_;
+    int net_fails; // consecutive network steps whose output failed z.r > 0
 };
 
 // Which kernels of an iteration run: GATE_NONE always; GATE_DONE until the
