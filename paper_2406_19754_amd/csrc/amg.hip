@@ -1194,7 +1194,7 @@ struct TailLevel {
     Ell<T> R;          // restriction to the next level
     Ell<T> SP;         // (I - M^-1 A) P
     const T* minv;
-    T *b, *x, *r;
+    T *b, *x;          // the first tail level's input and output (device memory)
 };
 
 template <typename T>
@@ -1812,11 +1812,12 @@ static int upload(psc_hier* h, T** d, const T* src, size_t count) {
     return PSC_OK;
 }
 
-// value_pattern: the sparsity depends on the values (AINV factors), so a
-// refresh rewrites the index arrays too (same sizes) instead of keeping them.
+// Hacked-ELL copy of a CSR operator packed on the host (the factored
+// smoothers' W and Z and their prolongator). value_pattern: the sparsity
+// depends on the values (AINV factors), so a refresh rewrites the index
+// arrays too (same sizes) instead of keeping them.
 static int upload_ell(psc_hier* h, DevEll<double>& E, int64_t nrows, int64_t ncols, const int32_t* rp,
-                      const int32_t* ci, const double* v, bool fp32, const double* minv = nullptr,
-                      double** am = nullptr, float** am32 = nullptr, bool value_pattern = false) {
+                      const int32_t* ci, const double* v, bool fp32, bool value_pattern = false) {
     std::vector<long long> off;
     std::vector<double> val;
     std::vector<int> col;
@@ -1836,23 +1837,10 @@ static int upload_ell(psc_hier* h, DevEll<double>& E, int64_t nrows, int64_t nco
         if ((st = upload(h, &E.col, col.data(), col.size()))) return st;
     }
     if ((st = upload(h, &E.val, val.data(), val.size()))) return st;
-    std::vector<float> v32;
     if (fp32) {
-        v32.resize(val.size());
-#pragma omp parallel for schedule(static)
+        std::vector<float> v32(val.size());
         for (size_t i = 0; i < val.size(); i++) v32[i] = (float)val[i];
         if ((st = upload(h, &E.val32, v32.data(), v32.size()))) return st;
-    }
-    if (minv) {
-        // A M^-1 in the same layout, in place: a_ij minv_j (padding stays 0)
-#pragma omp parallel for schedule(static)
-        for (size_t i = 0; i < val.size(); i++) val[i] = val[i] * minv[col[i]];
-        if ((st = upload(h, am, val.data(), val.size()))) return st;
-        if (fp32) {
-#pragma omp parallel for schedule(static)
-            for (size_t i = 0; i < val.size(); i++) v32[i] = (float)val[i];
-            if ((st = upload(h, am32, v32.data(), v32.size()))) return st;
-        }
     }
     return PSC_OK;
 }
@@ -2019,9 +2007,9 @@ static int upload_fai(psc_hier* h, DevLevel& D, const HostLevel& H, bool f32) {
             zci[o] = (int32_t)k;
             zv[o] = F.zv[e];
         }
-    if ((st = upload_ell(h, D.W, n, n, wrp.data(), F.zi.data(), wv.data(), f32, nullptr, nullptr, nullptr, true)))
+    if ((st = upload_ell(h, D.W, n, n, wrp.data(), F.zi.data(), wv.data(), f32, true)))
         return st;
-    if ((st = upload_ell(h, D.Z, n, n, zrp.data(), zci.data(), zv.data(), f32, nullptr, nullptr, nullptr, true)))
+    if ((st = upload_ell(h, D.Z, n, n, zrp.data(), zci.data(), zv.data(), f32, true)))
         return st;
     if ((st = upload_ell(h, D.P, n, H.nc, H.prp.data(), H.pci.data(), H.pv.data(), f32))) return st;
     for (double** q : {&D.ft, &D.fu})
@@ -2254,7 +2242,6 @@ static TailLevel<T> tail_level(const psc_hier* h, const DevLevel& V) {
         e.minv = V.minv32;
         e.b = V.b32;
         e.x = V.x32;
-        e.r = V.r32;
     } else {
         e.am_ell = V.am_view();
         if (V.Ad.on()) e.am_dia = V.Ad.view(V.amd);
@@ -2263,7 +2250,6 @@ static TailLevel<T> tail_level(const psc_hier* h, const DevLevel& V) {
         e.minv = V.minv;
         e.b = V.b;
         e.x = V.x;
-        e.r = V.r;
     }
     e.dia = (h->dia && V.Ad.on()) ? 1 : 0;
     return e;
