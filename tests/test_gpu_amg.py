@@ -460,3 +460,46 @@ def test_device_products_of_vbm_smoothed_hierarchy_bit_identical_to_host(psc, ca
         if l < a["levels"] - 1:
             px, py = hd.export_prolongator(l), hh.export_prolongator(l)
             assert all(np.array_equal(u, w) for u, w in zip(px, py)), l
+
+
+def _diag_csr(d):
+    n = len(d)
+    return np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.asarray(d, dtype=np.float64)
+
+
+def _block_diag(*mats):
+    rps, cs, vs, off, nnz = [np.zeros(1, np.int32)], [], [], 0, 0
+    for rp, c, v in mats:
+        rps.append((rp[1:] + nnz).astype(np.int32))
+        cs.append((c + off).astype(np.int32))
+        vs.append(v)
+        off += len(rp) - 1
+        nnz += rp[-1]
+    return np.concatenate(rps), np.concatenate(cs), np.concatenate(vs)
+
+
+@pytest.mark.parametrize("case", ["one_by_one", "diagonal_3000", "two_components"])
+def test_degenerate_systems_match_oracle(psc, case):
+    """A 1x1 system, a diagonal matrix (nothing to match: every aggregate a
+    singleton, so coarsening stalls at once) and two disconnected Poisson
+    blocks of different sizes: GPU PCG and mixed FCG against the oracle."""
+    if case == "one_by_one":
+        rp, c, v = _diag_csr([4.0])
+    elif case == "diagonal_3000":
+        rp, c, v = _diag_csr(1.0 + np.random.default_rng(4).random(3000))
+    else:
+        rp, c, v = _block_diag(P.poisson7(10), P.poisson7(9))
+    n = len(rp) - 1
+    h = psc.Hierarchy(rp, c, v, build_fp32=True)
+    o = oracle.Hierarchy(rp, c, v)
+    assert h.info()["levels"] == o.nlevels
+    b = P.rhs_uniform(n, 6)
+    ro = o.pcg(b)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    g = h.pcg(dev(b), x)
+    assert g["status"] == psc.OK and ro["status"] == oracle.OK
+    assert abs(g["iters"] - ro["iters"]) <= 1 and g["relres"] <= 1e-6
+    assert np.linalg.norm(x.cpu().numpy() - ro["x"]) <= 1e-8 * np.linalg.norm(ro["x"])
+    x.zero_()
+    g = h.fcg(dev(b), x, prec=psc.FP32)
+    assert g["status"] == psc.OK and g["relres"] <= 1e-6

@@ -8,6 +8,17 @@ import oracle
 from paper_2406_19754_amd import problems as P
 from paper_2406_19754_amd import psc
 
+def _block_diag(*mats):
+    rps, cs, vs, off, nnz = [np.zeros(1, np.int32)], [], [], 0, 0
+    for rp, c, v in mats:
+        rps.append((rp[1:] + nnz).astype(np.int32))
+        cs.append((c + off).astype(np.int32))
+        vs.append(v)
+        off += len(rp) - 1
+        nnz += rp[-1]
+    return np.concatenate(rps), np.concatenate(cs), np.concatenate(vs)
+
+
 CASES = {
     "poisson32": (lambda: P.poisson7(32), 200, 2),
     "poisson9": (lambda: P.poisson7(9), 200, 2),
@@ -16,6 +27,12 @@ CASES = {
     "diffusion14_lognormal_az0.01": (lambda: P.diffusion7(14, seed=2, az=0.01), 100, 2),
     "random_spd": (lambda: P.random_spd_csr(500, 3, density=0.02, maxrow=50), 40, 2),
     "diffusion48_lognormal_stalls": (lambda: P.diffusion7(48, seed=0), 200, 2),
+    # degenerate: one row; a diagonal matrix (nothing to match, stalls at once);
+    # two disconnected Poisson blocks of different sizes
+    "one_by_one": (lambda: (np.array([0, 1], np.int32), np.array([0], np.int32), np.array([4.0])), 200, 2),
+    "diagonal_3000": (lambda: (np.arange(3001, dtype=np.int32), np.arange(3000, dtype=np.int32),
+                               1.0 + np.random.default_rng(4).random(3000)), 200, 2),
+    "two_components": (lambda: _block_diag(P.poisson7(10), P.poisson7(9)), 200, 2),
 }
 
 # smoothed prolongator (general Galerkin product); aggregates <= 8 is the
