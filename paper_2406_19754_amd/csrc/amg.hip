@@ -1894,6 +1894,14 @@ __global__ void k_refresh_values(long long n, const int32_t* __restrict__ rp, co
     }
 }
 
+// The staging buffer lives only while the level data are filled (build or
+// rebuild).
+static void release_stage(psc_hier* h) {
+    if (h->stage) (void)hipFree(h->stage);
+    h->stage = nullptr;
+    h->stage_bytes = 0;
+}
+
 // Device side of a refresh: stage the rows and values of a CSR operator with
 // the pattern uploaded at build and scatter them (see k_refresh_values).
 // mv != nullptr also refreshes A M^-1 (am / amd and their FP32 copies).
@@ -1909,7 +1917,7 @@ static int refresh_values(psc_hier* h, DevEll<double>& E, const DevDia* G, int64
         if (h->stage) HIPCHK(hipFree(h->stage));
         h->stage = nullptr;
         h->stage_bytes = 0;
-        if (hipMalloc(&h->stage, need) != hipSuccess) return fail(PSC_ERR_OOM, "rebuild staging allocation failed");
+        if (hipMalloc(&h->stage, need) != hipSuccess) return fail(PSC_ERR_OOM, "staging allocation failed");
         h->stage_bytes = need;
     }
     char* sb = (char*)h->stage;
@@ -3404,6 +3412,7 @@ void psc_hier_free(psc_hier* h) {
     if (h->stream) (void)hipStreamDestroy(h->stream);
     for (void* p : h->allocs) (void)hipFree(p);
     for (void* p : h->lev_allocs) (void)hipFree(p);
+    if (h->stage) (void)hipFree(h->stage);
     if (h->hctl) (void)hipHostFree(h->hctl);
     delete h;
 }
@@ -3466,7 +3475,9 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
         PhaseTimer pt("pack and upload levels");
             if (h->host.coarse_pcg > 0 && h->host.lev.back().n > CPCG_MAX)
             return fail(PSC_ERR_ARG, "the PCG coarsest solver takes at most 4096 rows");
-        if ((st = upload_levels(h.get()))) return st;
+        st = upload_levels(h.get());
+        release_stage(h.get());
+        if (st) return st;
     }
     // solver workspace
     const int64_t N = n;
@@ -3524,11 +3535,7 @@ int psc_amg_rebuild(psc_hier* h, const double* val) {
             h->lev_bytes = 0;
             st = upload_levels(h);
         }
-        if (h->stage) {
-            (void)hipFree(h->stage);
-            h->stage = nullptr;
-            h->stage_bytes = 0;
-        }
+        release_stage(h);
         if (st) return st;
         if ((st = build_tail(h))) return st;
         HIPCHK(hipStreamSynchronize(h->stream));

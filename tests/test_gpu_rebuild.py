@@ -231,3 +231,22 @@ def test_rebuild_refreshes_rows_beyond_one_full_grid(psc):
     h.vcycle(r, z)
     h.spmv(r, y)
     assert torch.equal(y, yf) and torch.equal(z, zf)
+
+
+def test_staging_memory_is_released_after_build_rebuild_and_free(psc):
+    """The device staging of CSR rows and values (here about 140 MB) lives
+    only while a build or a rebuild fills the level data: the memory a handle
+    holds is the same after its build and after a rebuild, and freeing the
+    handle returns everything."""
+    rp, c, v = P.poisson7(128)
+    stage = 4 * len(rp) + 8 * len(v) + 8 * (len(rp) - 1)
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    h = psc.Hierarchy(rp, c, v, build_fp32=True)
+    free1, _ = torch.cuda.mem_get_info()
+    h.rebuild(2.0 * v)
+    free2, _ = torch.cuda.mem_get_info()
+    assert abs(free1 - free2) < stage / 4
+    h.close()
+    free3, _ = torch.cuda.mem_get_info()
+    assert abs(free0 - free3) < 16 << 20
