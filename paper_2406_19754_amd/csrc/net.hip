@@ -217,6 +217,66 @@ __global__ __launch_bounds__(WG) void k_conv2(Dims d, const bf16r* __restrict__ 
     }
 }
 
+// Forward 16 -> 16 layer with the input tile staged in LDS: a workgroup
+// computes 16 cells of 4 consecutive x-rows (one per wavefront) at one z; the
+// 18 x 6 x 3 cells they read (zero outside the sample) are loaded once with
+// 16-byte loads, and every MFMA step then takes its A operand from LDS
+// instead of gathering it from the cache. Same operands and order as
+// k_conv2<0>, so the same results.
+constexpr int CT_X = 18, CT_Y = 6, CT_Z = 3, CT_CELLS = CT_X * CT_Y * CT_Z;
+__global__ __launch_bounds__(WG) void k_conv2_lds(Dims d, const bf16r* __restrict__ in,
+                                                  const bf16x8* __restrict__ frag, const float* __restrict__ wr,
+                                                  float* __restrict__ aout, bf16r* __restrict__ hout, Gate g) {
+    if (gate_skip(g)) return;
+    __shared__ u32x4 tile[CT_CELLS * 2];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nxt = (d.W + 15) / 16, nyt = (d.H + 3) / 4;
+    long long t = blockIdx.x;
+    const int x0 = (int)(t % nxt) * 16;
+    t /= nxt;
+    const int y0 = (int)(t % nyt) * 4;
+    t /= nyt;
+    const int z = (int)(t % d.D);
+    const int b = (int)(t / d.D);
+    for (int i = threadIdx.x; i < CT_CELLS * 2; i += WG) {
+        const int cell = i >> 1, half = i & 1;
+        const int rx = cell % CT_X, ry = (cell / CT_X) % CT_Y, rz = cell / (CT_X * CT_Y);
+        const int xx = x0 + rx - 1, yy = y0 + ry - 1, zz = z + rz - 1;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (xx >= 0 && xx < d.W && yy >= 0 && yy < d.H && zz >= 0 && zz < d.D)
+            v = *(const u32x4*)(in + ((((long long)b * d.D + zz) * d.H + yy) * d.W + xx) * NC + half * 8);
+        tile[i] = v;
+    }
+    __syncthreads();
+    const int y = y0 + wv;
+    if (y >= d.H) return;   // uniform per wavefront; no barrier follows
+    const int half = (lane >> 4) & 1, tsel = lane >> 5, cx = lane & 15;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int s = 0; s < KSTEPS; s++) {
+        const int tap = 2 * s + tsel;
+        u32x4 av = {0u, 0u, 0u, 0u};
+        if (tap < 27) {
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // offsets + 1
+            av = tile[(((dz * CT_Y) + wv + dy) * CT_X + cx + dx) * 2 + half];
+        }
+        const bf16x8 A = __builtin_bit_cast(bf16x8, av);
+        const bf16x8 Bm = frag[s * 64 + lane];
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bm, acc, 0, 0, 0);
+    }
+    const int co = lane & 15;
+    const long long rowbase = (((long long)b * d.D + z) * d.H + y) * d.W;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const int xx = x0 + 4 * (lane >> 4) + i;
+        if (xx >= d.W) continue;
+        const long long c = rowbase + xx;
+        const float v = acc[i] + wr[OB2 + co];
+        if (aout) aout[c * NC + co] = v;
+        hout[c * NC + co] = f2bf(gelu(v));
+    }
+}
+
 // out = W3 * h2 + b3; TO64: z = s * out with s = sqrt(*rr / N), else out32.
 template <bool TO64>
 __global__ __launch_bounds__(WG) void k_conv3(Dims d, const bf16r* __restrict__ h2, const float* __restrict__ wr,
@@ -512,8 +572,8 @@ static void forward(psc_net* n, hipStream_t st, const Dims& d, const double* r64
     if (r64) k_prep_u<true><<<blocks_for(cells), WG, 0, st>>>(cells, r64, nullptr, rr, N, u, g);
     else k_prep_u<false><<<blocks_for(cells), WG, 0, st>>>(cells, nullptr, in32, nullptr, 1, u, g);
     k_conv1<<<blocks_for(cells), WG, 0, st>>>(d, u, n->wr, h1, a1, g);
-    const long long tiles = (long long)d.B * d.D * d.H * ((d.W + 15) / 16);
-    k_conv2<0><<<(unsigned)((tiles + 3) / 4), WG, 0, st>>>(d, h1, (const bf16x8*)n->ffwd, n->wr, nullptr, a2, h2, g);
+    const long long tiles = (long long)d.B * d.D * ((d.H + 3) / 4) * ((d.W + 15) / 16);
+    k_conv2_lds<<<(unsigned)tiles, WG, 0, st>>>(d, h1, (const bf16x8*)n->ffwd, n->wr, a2, h2, g);
     if (z64) k_conv3<true><<<blocks_for(cells), WG, 0, st>>>(d, h2, n->wr, rr, N, z64, nullptr, g);
     else k_conv3<false><<<blocks_for(cells), WG, 0, st>>>(d, h2, n->wr, nullptr, 1, nullptr, out32, g);
 }
