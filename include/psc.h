@@ -385,11 +385,13 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
  * when its diagonal slots are at most 4/3 of its ELL slots (7-point
  * stencils: 8 bytes per entry instead of 12); 0 reads hacked ELL. */
 #define PSC_TUNE_DIA 7
-/* PSC_TUNE_TAIL (default 1024): the levels with at most `value` rows (value <=
- * 4096), down to the dense coarsest solve, run in one kernel of one
- * workgroup per V-cycle (one sweep, split operators, no other coarsest
- * solver), whose vectors are held in LDS (16 bytes per row, within the
- * device's LDS per workgroup: the largest such levels are left out until
+/* PSC_TUNE_TAIL (default: automatic, up to 1024 rows with one smoothing sweep
+ * per level and 4096 with more, and only levels whose sweep reads at most
+ * 512 KB of operators): the levels with at most `value` rows (value <= 4096),
+ * down to the dense coarsest solve, run in one kernel of one workgroup per V-cycle
+ * (l1-Jacobi sweeps on the split operators, no other coarsest solver), whose
+ * vectors are held in LDS (16 bytes per row, 24 with several sweeps, within
+ * the device's LDS per workgroup: the largest such levels are left out until
  * they fit); 0 launches their kernels one by one. */
 #define PSC_TUNE_TAIL 8
 /* PSC_TUNE_DIA_UNIFORM (default 1): a level whose hacked-DIA copy has at most 8

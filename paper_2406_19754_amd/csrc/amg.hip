@@ -1185,12 +1185,16 @@ __global__ __launch_bounds__(WG) void k_coarse(int n, const double* __restrict__
 constexpr int TAIL_WG = 1024;
 constexpr int TAIL_MAX_ROWS = 4096;
 constexpr int TAIL_LDS_BYTES = 160 * 1024;   // gfx950: 160 KB of LDS per workgroup
+constexpr long long TAIL_MAX_LEVEL_BYTES = 512 * 1024;   // operator bytes of one tail level's sweep
 
 template <typename T>
 struct TailLevel {
     Ell<T> am_ell;     // A M^-1 in hacked ELL (used when dia == 0)
     Dia<T> am_dia;     // A M^-1 in hacked DIA
+    Ell<T> a_ell;      // A (post-smoothing sweeps after the first)
+    Dia<T> a_dia;
     int dia;
+    int nu;            // smoothing sweeps on this level
     Ell<T> R;          // restriction to the next level
     Ell<T> SP;         // (I - M^-1 A) P
     const T* minv;
@@ -1200,18 +1204,26 @@ struct TailLevel {
 template <typename T>
 struct TailDesc {
     int t, L, nL;
-    int lds_elems;                 // 2 * (rows of levels t .. L-1): b and r of each in LDS
-    int base[PSC_MAX_LEVELS];      // element offset of level l's b (r follows, then x over r)
+    int lds_elems;                 // LDS elements of levels t .. L-1 (b, r and, with nu > 1, s)
+    int base[PSC_MAX_LEVELS];      // element offset of level l's b (r follows, then s)
     const double* invT;
     TailLevel<T> lev[PSC_MAX_LEVELS];
 };
 
-// Levels t .. L-1 of the V-cycle in one workgroup: b and r of every such
-// level live in LDS, and x replaces r once the post-smoothing has read it
-// (level t's b is read from and its x written to device memory, where the
-// neighbouring launches exchange them), so a step waits on an LDS barrier
-// instead of a device-memory round trip; only the operators come from the
-// L2. One smoothing sweep, split operators, dense coarsest.
+// LDS array of a tail level that holds its final post-smoothed x: the first
+// post sweep writes over r (one sweep) or over s, later sweeps alternate.
+__host__ __device__ inline int tail_xslot(int nu) { return nu == 1 ? 1 : (nu % 2 == 0 ? 1 : 2); }
+
+// Levels t .. L-1 of the V-cycle in one workgroup: b, r (and s with several
+// sweeps) of every such level live in LDS, and x is written over r or s once
+// the post-smoothing has read them (level t's b is read from and its x
+// written to device memory, where the neighbouring launches exchange them),
+// so a step waits on an LDS barrier instead of a device-memory round trip;
+// only the operators come from the L2. nu sweeps of the split smoother per
+// level (sweep k of the pre-smoothing: s_k = s_{k-1} + r_{k-1} with s_1 = b,
+// r_k = b - A M^-1 s_k; post: x = M^-1 (s + r) + S P x_c, then
+// x += M^-1 (b - A x)), dense coarsest. Same arithmetic as k_pre_s,
+// k_presweep, k_spmv on R, k_coarse, k_post_s and k_sweep.
 template <typename T>
 __global__ __launch_bounds__(TAIL_WG) void k_tail(const TailDesc<T>* __restrict__ D, Gate g) {
     if (gate_skip(g)) return;
@@ -1231,6 +1243,7 @@ __global__ __launch_bounds__(TAIL_WG) void k_tail(const TailDesc<T>* __restrict_
         const long long ns = V.am_ell.nslices, n = V.am_ell.nrows;
         const T* b = lds + D->base[l];
         T* r = lds + D->base[l] + n;
+        T* sv = lds + D->base[l] + 2 * n;
         for (long long s = wv; s < ns; s += nw) {
             const T acc = V.dia ? dia_row(V.am_dia, s, lane, [&](int c) { return b[c]; })
                                 : ell_row(V.am_ell, s, lane, [&](int c) { return b[c]; });
@@ -1238,6 +1251,17 @@ __global__ __launch_bounds__(TAIL_WG) void k_tail(const TailDesc<T>* __restrict_
             if (row < n) r[row] = b[row] - acc;
         }
         __syncthreads();
+        for (int k = 2; k <= V.nu; k++) {
+            for (int i = threadIdx.x; i < n; i += TAIL_WG) sv[i] = (k == 2 ? b[i] : sv[i]) + r[i];
+            __syncthreads();
+            for (long long s = wv; s < ns; s += nw) {
+                const T acc = V.dia ? dia_row(V.am_dia, s, lane, [&](int c) { return (T)sv[c]; })
+                                    : ell_row(V.am_ell, s, lane, [&](int c) { return (T)sv[c]; });
+                const long long row = s * SLICE + lane;
+                if (row < n) r[row] = b[row] - acc;
+            }
+            __syncthreads();
+        }
         T* bc = lds + D->base[l + 1];
         for (long long s = wv; s < V.R.nslices; s += nw) {
             const T acc = ell_row(V.R, s, lane, [&](int c) { return (T)r[c]; });
@@ -1261,20 +1285,41 @@ __global__ __launch_bounds__(TAIL_WG) void k_tail(const TailDesc<T>* __restrict_
         const TailLevel<T>& V = D->lev[l];
         const long long ns = V.SP.nslices, n = V.SP.nrows;
         const long long nc = D->lev[l + 1].am_ell.nrows;
+        const int cslot = l + 1 == L - 1 ? 1 : tail_xslot(D->lev[l + 1].nu);
         const T* b = lds + D->base[l];
-        T* rx = lds + D->base[l] + n;              // r in, x out (same row, same lane)
-        const T* xc = lds + D->base[l + 1] + nc;
+        T* r = lds + D->base[l] + n;
+        T* sv = lds + D->base[l] + 2 * n;
+        const T* xc = lds + D->base[l + 1] + cslot * nc;
         T* xg = V.x;
+        // first sweep, fused with the prolongation; x over r (one sweep) or s
+        T* x = V.nu == 1 ? r : sv;
+        const T* s_nu = V.nu == 1 ? b : sv;
         for (long long s = wv; s < ns; s += nw) {
             const T acc = ell_row(V.SP, s, lane, [&](int c) { return xc[c]; });
             const long long row = s * SLICE + lane;
             if (row < n) {
-                const T xi = V.minv[row] * (b[row] + rx[row]) + acc;
-                rx[row] = xi;
-                if (l == t) xg[row] = xi;
+                const T xi = V.minv[row] * (s_nu[row] + r[row]) + acc;
+                x[row] = xi;
+                if (l == t && V.nu == 1) xg[row] = xi;
             }
         }
         __syncthreads();
+        for (int k = 2; k <= V.nu; k++) {
+            const T* xin = x;
+            T* xo = x == sv ? r : sv;
+            for (long long s = wv; s < ns; s += nw) {
+                const T acc = V.dia ? dia_row(V.a_dia, s, lane, [&](int c) { return xin[c]; })
+                                    : ell_row(V.a_ell, s, lane, [&](int c) { return xin[c]; });
+                const long long row = s * SLICE + lane;
+                if (row < n) {
+                    const T xi = xin[row] + V.minv[row] * (b[row] - acc);
+                    xo[row] = xi;
+                    if (l == t && k == V.nu) xg[row] = xi;
+                }
+            }
+            __syncthreads();
+            x = xo;
+        }
     }
 }
 
@@ -1734,7 +1779,7 @@ struct psc_hier {
     // inside the tail, so the per-level launches are as fast or faster
     // (measured at 128^3 and 256^3); without graphs the tail saves launches.
     bool tail = true;
-    int tail_rows = 1024;                 // largest level (rows) the tail takes
+    int tail_rows = -1;                   // largest level (rows) the tail takes; -1: automatic
     int tail_t = 0;                       // first level of the tail (0: no tail)
     int tail_lds = 0;                     // elements of the tail's LDS arrays
     psc::TailDesc<double>* tail64 = nullptr;   // device descriptors (built at setup)
@@ -2237,7 +2282,8 @@ static void coarse_solve(psc_hier* h, const TB* b, TX* x, Gate g) {
 
 // Descriptors of the small levels run by k_tail: levels t..L-1 with at most
 // TAIL_MAX_ROWS rows (t >= 1, at least one level above the coarsest), for a
-// V-cycle with one sweep, the split operators and a dense coarsest solve.
+// V-cycle with l1-Jacobi sweeps on the split operators and a dense coarsest
+// solve.
 template <typename T>
 static TailLevel<T> tail_level(const psc_hier* h, const DevLevel& V) {
     TailLevel<T> e{};
@@ -2245,6 +2291,8 @@ static TailLevel<T> tail_level(const psc_hier* h, const DevLevel& V) {
     if constexpr (f32) {
         e.am_ell = V.am_view32();
         if (V.Ad.on()) e.am_dia = V.Ad.view32(V.amd32);
+        e.a_ell = V.A.view32();
+        if (V.Ad.on()) e.a_dia = V.Ad.view32(V.Ad.val32);
         e.R = V.R.view32();
         e.SP = V.SP.view32();
         e.minv = V.minv32;
@@ -2253,6 +2301,8 @@ static TailLevel<T> tail_level(const psc_hier* h, const DevLevel& V) {
     } else {
         e.am_ell = V.am_view();
         if (V.Ad.on()) e.am_dia = V.Ad.view(V.amd);
+        e.a_ell = V.A.view();
+        if (V.Ad.on()) e.a_dia = V.Ad.view(V.Ad.val);
         e.R = V.R.view();
         e.SP = V.SP.view();
         e.minv = V.minv;
@@ -2260,28 +2310,46 @@ static TailLevel<T> tail_level(const psc_hier* h, const DevLevel& V) {
         e.x = V.x;
     }
     e.dia = (h->dia && V.Ad.on()) ? 1 : 0;
+    e.nu = V.nu;
     return e;
 }
 
 static int build_tail(psc_hier* h) {
     const int L = (int)h->lev.size();
     h->tail_t = 0;
-    if (L < 3 || h->host.coarse_sweeps > 0 || h->host.coarse_pcg > 0 || !h->split || h->opts.vcycle_double ||
-        h->nu != 1 || h->fai || h->cheb)
+    if (L < 3 || h->host.coarse_sweeps > 0 || h->host.coarse_pcg > 0 || !h->split || h->fai || h->cheb)
         return PSC_OK;
+    for (int l = 0; l < L - 1; l++)
+        if (h->lev[l].nu < 1) return PSC_OK;
+    // automatic: the levels up to 1024 rows with one sweep per level (taking
+    // the 4096-row level as well measured the same), up to 4096 rows with
+    // several, where each sweep would otherwise be a launch of its own
+    const int rows = h->tail_rows >= 0 ? h->tail_rows : ((h->nu > 1 || h->opts.vcycle_double) ? 4096 : 1024);
+    // one workgroup streams a level's operators through one compute unit: by
+    // default a level joins only while a sweep's operator bytes stay small
+    // enough to be latency-bound there (wide coarse operators, as the smoothed
+    // prolongator and VBM build, run faster spread over the chip); an explicit
+    // row limit is taken as given
+    auto op_bytes = [&](int l) {
+        const DevLevel& V = h->lev[l];
+        const long long a = (h->dia && V.Ad.on()) ? V.Ad.slots * 8LL : V.A.slots * 12LL;
+        return a + V.SP.slots * 12LL;
+    };
     int t = L - 1;
-    while (t - 1 >= 1 && h->lev[t - 1].n <= h->tail_rows) t--;
+    while (t - 1 >= 1 && h->lev[t - 1].n <= rows && (h->tail_rows >= 0 || op_bytes(t - 1) <= TAIL_MAX_LEVEL_BYTES))
+        t--;
     if (t > L - 2 || h->lev[L - 1].n > TAIL_MAX_ROWS) return PSC_OK;
-    // LDS: b and r (then x) of levels t .. L-1 (FP64 sized, so the FP32 tail
-    // fits too); drop the largest tail levels until that fits in what a
-    // workgroup may take
+    // LDS: b and r (and s) of levels t .. L-1, x over r or s (FP64 sized, so
+    // the FP32 tail fits too); drop the largest tail levels until that fits in
+    // what a workgroup may take
     int dev = 0, lds_max = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     lds_max = std::min(lds_max, TAIL_LDS_BYTES);
+    auto width = [&](int l) { return (l < L - 1 && h->lev[l].nu > 1) ? 3 : 2; };   // b, r (, s)
     auto lds_of = [&](int t0) {
         long long e = 0;
-        for (int l = t0; l < L; l++) e += 2 * h->lev[l].n;
+        for (int l = t0; l < L; l++) e += width(l) * h->lev[l].n;
         return e;
     };
     while (t <= L - 2 && lds_of(t) * (long long)sizeof(double) > lds_max) t++;
@@ -2303,7 +2371,7 @@ static int build_tail(psc_hier* h) {
         int e = 0;
         for (int l = t; l < L; l++) {
             d64.base[l] = d32.base[l] = e;
-            e += 2 * (int)h->lev[l].n;
+            e += width(l) * (int)h->lev[l].n;
         }
         d64.lds_elems = d32.lds_elems = e;
     }

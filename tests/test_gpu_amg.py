@@ -369,9 +369,12 @@ SMOOTHING = {
 }
 
 
+@pytest.mark.parametrize("tail", [True, False])
 @pytest.mark.parametrize("cfg", list(SMOOTHING))
 @pytest.mark.parametrize("case", ["poisson24", "diffusion20_az100", "random_long_rows"])
-def test_smoothing_configurations_match_oracle(psc, case, cfg):
+def test_smoothing_configurations_match_oracle(psc, case, cfg, tail):
+    """tail: the levels up to 4096 rows (several sweeps each) in the
+    one-workgroup LDS kernel, or launched level by level."""
     o_ = dict(sweeps=2, prol=0, nu=1, double=False, aggr=0)
     o_.update(SMOOTHING[cfg])
     sweeps, smoothed, nu, double, aggr = o_["sweeps"], o_["prol"], o_["nu"], o_["double"], o_["aggr"]
@@ -382,6 +385,9 @@ def test_smoothing_configurations_match_oracle(psc, case, cfg):
     o = oracle.Hierarchy(rp, c, v, coarse_max=cm, sweeps=sweeps, prol=smoothed, nu=nu, nu_double=double,
                          aggr=aggr, theta=0.05)
     assert h.info()["rows"] == o.sizes()
+    # an explicit row limit takes the small levels whatever their operator bytes
+    h.tune(psc.TUNE_TAIL, 4096 if tail else 0)
+    assert (h.info()["tail_level"] > 0) == (tail and h.info()["levels"] >= 3)
     n = len(rp) - 1
     x = np.random.default_rng(5).standard_normal(n)
     y = torch.empty(n, dtype=torch.float64, device="cuda")
