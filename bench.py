@@ -6,7 +6,7 @@ Default workload (one step = one full solve to rtol 1e-6 from x0 = 0): the
 b = A x_true with x_true ~ U[0,1) seed 0), FP64 preconditioned CG with the
 FP64 AMG V-cycle. On the same problem and GPU the FP32 V-cycle inside FP64
 flexible CG and, when trained weights are present, the learned form are
-timed and reported beside it, each judged by its true FP64 residual.
+timed and reported beside it, each checked by its true FP64 residual.
 
 Printed: one JSON line with the time to solution (ms per step), the HBM
 roofline of the dominant kernel (average duration from HIP events recorded
@@ -235,8 +235,7 @@ def main():
                          "(counter calibration), 10 SpMVs on A_0, one FP64 PCG and one mixed FCG solve")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the solve is not sharded across GPUs "
-                                   "(the sharding design is described in the design notes)",
+        print(json.dumps({"error": "one GPU only: the solve path is not sharded across GPUs",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "learned128":

@@ -138,7 +138,7 @@ def test_solve_matches_oracle(psc, case, form):
     assert g["relres"] <= 1e-6
     k = min(g["iters"], r["iters"])
     if form == "fcg32":
-        # FP32 V-cycle: judged by the true FP64 residual; the error to the
+        # FP32 V-cycle: checked by the true FP64 residual; the error to the
         # FP64 oracle solution is stated, not bounded tightly
         assert np.linalg.norm(xg - r["x"]) <= 1e-4 * np.linalg.norm(r["x"])
         return
