@@ -27,8 +27,7 @@
  *     Section "Numerical Example".
  * Readings where the paper is silent (edge weights, tie order, weight
  * quantisation, the graph of the second sweep, coarsest solve, FCG variant,
- * the learned preconditioner) are listed in the design notes; each is
- * restated at the function that takes it.
+ * the learned preconditioner) are stated at the function that takes each.
  *
  * Parity pins live in tests/test_oracle_*.py. Functions marked
  * "parity unpinned" have no independent pin.
