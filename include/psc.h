@@ -389,7 +389,7 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
  * per level and 4096 with more, and only levels whose sweep reads at most
  * 512 KB of operators): the levels with at most `value` rows (value <= 4096),
  * down to the dense coarsest solve, run in one kernel of one workgroup per V-cycle
- * (l1-Jacobi sweeps on the split operators, no other coarsest solver), whose
+ * (l1-Jacobi sweeps on the split operators; dense or PCG coarsest), whose
  * vectors are held in LDS (16 bytes per row, 24 with several sweeps, within
  * the device's LDS per workgroup: the largest such levels are left out until
  * they fit); 0 launches their kernels one by one. */

@@ -1174,14 +1174,121 @@ __global__ __launch_bounds__(WG) void k_coarse(int n, const double* __restrict__
     }
 }
 
-// ---- the small levels in one workgroup (optional) --------------------------
+// Coarsest level by at most maxit iterations of l1-Jacobi preconditioned CG
+// from x = 0, stopped at ||r|| <= rtol ||b||, in FP64, in one workgroup of
+// CPCG_WG threads: thread t owns rows t, t + CPCG_WG, ... (at most
+// CPCG_ROWS), keeping x, r, z and q in registers; the direction p lives in
+// LDS, where the product A p gathers it (hacked-ELL rows, padding is 0).
+// Block sums are formed in a fixed order and broadcast, so every thread
+// takes the same branches and the loop ends after at most maxit iterations.
+constexpr int CPCG_WG = 1024;
+constexpr int CPCG_ROWS = 4;
+constexpr int CPCG_MAX = CPCG_WG * CPCG_ROWS;
+
+__device__ double cpcg_sum(double v, double* red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();   // earlier readers of red are done
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < CPCG_WG / 64; k++) t += red[k];
+    return t;
+}
+
+// The solve itself, for a workgroup of CPCG_WG threads; p (at least n
+// doubles) and red (CPCG_WG / 64 doubles) are LDS scratch.
+template <typename TB, typename TX>
+__device__ void coarse_pcg_block(const Ell<double>& A, const double* __restrict__ minv, const TB* b, TX* x,
+                                 int maxit, double rtol, double* p, double* red) {
+    const int n = (int)A.nrows;
+    double xr[CPCG_ROWS], rr[CPCG_ROWS], zr[CPCG_ROWS], qr[CPCG_ROWS];
+    double bb = 0.0, rz0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < CPCG_ROWS; k++) {
+        const int i = threadIdx.x + k * CPCG_WG;
+        xr[k] = 0.0;
+        rr[k] = i < n ? (double)b[i] : 0.0;
+        zr[k] = i < n ? minv[i] * rr[k] : 0.0;
+        if (i < n) p[i] = zr[k];
+        bb += rr[k] * rr[k];
+        rz0 += rr[k] * zr[k];
+    }
+    const double bn = sqrt(cpcg_sum(bb, red));
+    double rz = cpcg_sum(rz0, red);
+    if (bn > 0.0) {
+        for (int it = 0; it < maxit && rz > 0.0; it++) {
+            __syncthreads();   // p complete
+            double pq = 0.0;
+#pragma unroll
+            for (int k = 0; k < CPCG_ROWS; k++) {
+                const int i = threadIdx.x + k * CPCG_WG;
+                qr[k] = 0.0;
+                if (i < n) {
+                    const long long s = i / SLICE, o = A.off[s];
+                    const int w = (int)((A.off[s + 1] - o) / SLICE), lane = i % SLICE;
+                    double acc = 0.0;
+                    for (int e = 0; e < w; e++) acc += A.val[o + (long long)e * SLICE + lane] * p[A.col[o + (long long)e * SLICE + lane]];
+                    qr[k] = acc;
+                    pq += p[i] * acc;
+                }
+            }
+            pq = cpcg_sum(pq, red);
+            if (!(pq > 0.0)) break;
+            const double alpha = rz / pq;
+            double rn = 0.0;
+#pragma unroll
+            for (int k = 0; k < CPCG_ROWS; k++) {
+                const int i = threadIdx.x + k * CPCG_WG;
+                if (i < n) {
+                    xr[k] += alpha * p[i];
+                    rr[k] -= alpha * qr[k];
+                    rn += rr[k] * rr[k];
+                }
+            }
+            rn = cpcg_sum(rn, red);
+            if (sqrt(rn) <= rtol * bn) break;
+            double rz2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < CPCG_ROWS; k++) {
+                const int i = threadIdx.x + k * CPCG_WG;
+                zr[k] = i < n ? minv[i] * rr[k] : 0.0;
+                rz2 += rr[k] * zr[k];
+            }
+            rz2 = cpcg_sum(rz2, red);
+            const double beta = rz2 / rz;
+            // every read of p in this iteration happened before the sums above
+#pragma unroll
+            for (int k = 0; k < CPCG_ROWS; k++) {
+                const int i = threadIdx.x + k * CPCG_WG;
+                if (i < n) p[i] = zr[k] + beta * p[i];
+            }
+            rz = rz2;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < CPCG_ROWS; k++) {
+        const int i = threadIdx.x + k * CPCG_WG;
+        if (i < n) x[i] = (TX)xr[k];
+    }
+}
+
+template <typename TB, typename TX>
+__global__ __launch_bounds__(CPCG_WG) void k_coarse_pcg(Ell<double> A, const double* __restrict__ minv,
+                                                        const TB* __restrict__ b, TX* __restrict__ x, int maxit,
+                                                        double rtol, Gate g) {
+    if (gate_skip(g)) return;
+    __shared__ double p[CPCG_MAX];
+    __shared__ double red[CPCG_WG / 64];
+    coarse_pcg_block<TB, TX>(A, minv, b, x, maxit, rtol, p, red);
+}
+
+// ---- the small levels in one workgroup --------------------------------------
 // Below a few thousand rows a level's pre-smoothing, restriction and
 // post-smoothing are dominated by launch and drain time; levels t..L-1
-// (ending in the dense coarsest solve) can run in one workgroup of 16 waves:
-// each wave takes whole 64-row slices, and a workgroup barrier separates the
-// steps (the waves share the CU's L1, and every vector is written before it
-// is first read in this kernel). Same arithmetic as k_pre_s, k_spmv on R,
-// k_coarse and k_post_s with one sweep.
+// (ending in the coarsest solve) can run in one workgroup of 16 waves: each
+// wave takes whole 64-row slices, and a workgroup barrier separates the
+// steps.
 constexpr int TAIL_WG = 1024;
 constexpr int TAIL_MAX_ROWS = 4096;
 constexpr int TAIL_LDS_BYTES = 160 * 1024;   // gfx950: 160 KB of LDS per workgroup
@@ -1206,7 +1313,12 @@ struct TailDesc {
     int t, L, nL;
     int lds_elems;                 // LDS elements of levels t .. L-1 (b, r and, with nu > 1, s)
     int base[PSC_MAX_LEVELS];      // element offset of level l's b (r follows, then s)
-    const double* invT;
+    const double* invT;            // dense coarsest solve (cmaxit == 0)
+    int cmaxit;                    // > 0: coarsest by at most cmaxit PCG iterations (FP64)
+    int cpcg_off;                  // byte offset of the PCG direction and sums in LDS
+    double crtol;
+    Ell<double> cA;                // coarsest operator and l1 inverse diagonal for the PCG
+    const double* cminv;
     TailLevel<T> lev[PSC_MAX_LEVELS];
 };
 
@@ -1222,8 +1334,8 @@ __host__ __device__ inline int tail_xslot(int nu) { return nu == 1 ? 1 : (nu % 2
 // only the operators come from the L2. nu sweeps of the split smoother per
 // level (sweep k of the pre-smoothing: s_k = s_{k-1} + r_{k-1} with s_1 = b,
 // r_k = b - A M^-1 s_k; post: x = M^-1 (s + r) + S P x_c, then
-// x += M^-1 (b - A x)), dense coarsest. Same arithmetic as k_pre_s,
-// k_presweep, k_spmv on R, k_coarse, k_post_s and k_sweep.
+// x += M^-1 (b - A x)), dense or PCG coarsest. Same arithmetic as k_pre_s,
+// k_presweep, k_spmv on R, k_coarse or k_coarse_pcg, k_post_s and k_sweep.
 template <typename T>
 __global__ __launch_bounds__(TAIL_WG) void k_tail(const TailDesc<T>* __restrict__ D, Gate g) {
     if (gate_skip(g)) return;
@@ -1274,10 +1386,15 @@ __global__ __launch_bounds__(TAIL_WG) void k_tail(const TailDesc<T>* __restrict_
         const int nL = D->nL;
         const T* bL = lds + D->base[L - 1];
         T* xL = lds + D->base[L - 1] + nL;
-        for (int i = threadIdx.x; i < nL; i += TAIL_WG) {
-            double s = 0.0;
-            for (int k = 0; k < nL; k++) s += D->invT[(size_t)k * nL + i] * (double)bL[k];
-            xL[i] = (T)s;
+        if (D->cmaxit > 0) {
+            double* pd = reinterpret_cast<double*>(tail_lds + D->cpcg_off);
+            coarse_pcg_block<T, T>(D->cA, D->cminv, bL, xL, D->cmaxit, D->crtol, pd, pd + CPCG_MAX);
+        } else {
+            for (int i = threadIdx.x; i < nL; i += TAIL_WG) {
+                double s = 0.0;
+                for (int k = 0; k < nL; k++) s += D->invT[(size_t)k * nL + i] * (double)bL[k];
+                xL[i] = (T)s;
+            }
         }
         __syncthreads();
     }
@@ -1350,106 +1467,6 @@ __global__ __launch_bounds__(WG) void k_jacobi(M A, const double* __restrict__ m
 // handle
 // ---------------------------------------------------------------------------
 
-// Coarsest level by at most maxit iterations of l1-Jacobi preconditioned CG
-// from x = 0, stopped at ||r|| <= rtol ||b||, in FP64, in one workgroup of
-// CPCG_WG threads: thread t owns rows t, t + CPCG_WG, ... (at most
-// CPCG_ROWS), keeping x, r, z and q in registers; the direction p lives in
-// LDS, where the product A p gathers it (hacked-ELL rows, padding is 0).
-// Block sums are formed in a fixed order and broadcast, so every thread
-// takes the same branches and the loop ends after at most maxit iterations.
-constexpr int CPCG_WG = 1024;
-constexpr int CPCG_ROWS = 4;
-constexpr int CPCG_MAX = CPCG_WG * CPCG_ROWS;
-
-__device__ double cpcg_sum(double v, double* red) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    v = wave_sum(v);
-    __syncthreads();   // earlier readers of red are done
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    double t = 0.0;
-    for (int k = 0; k < CPCG_WG / 64; k++) t += red[k];
-    return t;
-}
-
-template <typename TB, typename TX>
-__global__ __launch_bounds__(CPCG_WG) void k_coarse_pcg(Ell<double> A, const double* __restrict__ minv,
-                                                        const TB* __restrict__ b, TX* __restrict__ x, int maxit,
-                                                        double rtol, Gate g) {
-    if (gate_skip(g)) return;
-    __shared__ double p[CPCG_MAX];
-    __shared__ double red[CPCG_WG / 64];
-    const int n = (int)A.nrows;
-    double xr[CPCG_ROWS], rr[CPCG_ROWS], zr[CPCG_ROWS], qr[CPCG_ROWS];
-    double bb = 0.0, rz0 = 0.0;
-#pragma unroll
-    for (int k = 0; k < CPCG_ROWS; k++) {
-        const int i = threadIdx.x + k * CPCG_WG;
-        xr[k] = 0.0;
-        rr[k] = i < n ? (double)b[i] : 0.0;
-        zr[k] = i < n ? minv[i] * rr[k] : 0.0;
-        if (i < n) p[i] = zr[k];
-        bb += rr[k] * rr[k];
-        rz0 += rr[k] * zr[k];
-    }
-    const double bn = sqrt(cpcg_sum(bb, red));
-    double rz = cpcg_sum(rz0, red);
-    if (bn > 0.0) {
-        for (int it = 0; it < maxit && rz > 0.0; it++) {
-            __syncthreads();   // p complete
-            double pq = 0.0;
-#pragma unroll
-            for (int k = 0; k < CPCG_ROWS; k++) {
-                const int i = threadIdx.x + k * CPCG_WG;
-                qr[k] = 0.0;
-                if (i < n) {
-                    const long long s = i / SLICE, o = A.off[s];
-                    const int w = (int)((A.off[s + 1] - o) / SLICE), lane = i % SLICE;
-                    double acc = 0.0;
-                    for (int e = 0; e < w; e++) acc += A.val[o + (long long)e * SLICE + lane] * p[A.col[o + (long long)e * SLICE + lane]];
-                    qr[k] = acc;
-                    pq += p[i] * acc;
-                }
-            }
-            pq = cpcg_sum(pq, red);
-            if (!(pq > 0.0)) break;
-            const double alpha = rz / pq;
-            double rn = 0.0;
-#pragma unroll
-            for (int k = 0; k < CPCG_ROWS; k++) {
-                const int i = threadIdx.x + k * CPCG_WG;
-                if (i < n) {
-                    xr[k] += alpha * p[i];
-                    rr[k] -= alpha * qr[k];
-                    rn += rr[k] * rr[k];
-                }
-            }
-            rn = cpcg_sum(rn, red);
-            if (sqrt(rn) <= rtol * bn) break;
-            double rz2 = 0.0;
-#pragma unroll
-            for (int k = 0; k < CPCG_ROWS; k++) {
-                const int i = threadIdx.x + k * CPCG_WG;
-                zr[k] = i < n ? minv[i] * rr[k] : 0.0;
-                rz2 += rr[k] * zr[k];
-            }
-            rz2 = cpcg_sum(rz2, red);
-            const double beta = rz2 / rz;
-            // every read of p in this iteration happened before the sums above
-#pragma unroll
-            for (int k = 0; k < CPCG_ROWS; k++) {
-                const int i = threadIdx.x + k * CPCG_WG;
-                if (i < n) p[i] = zr[k] + beta * p[i];
-            }
-            rz = rz2;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < CPCG_ROWS; k++) {
-        const int i = threadIdx.x + k * CPCG_WG;
-        if (i < n) x[i] = (TX)xr[k];
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Factored approximate inverse smoothers (AINV / INVK): a sweep is
@@ -1782,6 +1799,7 @@ struct psc_hier {
     int tail_rows = -1;                   // largest level (rows) the tail takes; -1: automatic
     int tail_t = 0;                       // first level of the tail (0: no tail)
     int tail_lds = 0;                     // elements of the tail's LDS arrays
+    int tail_pcg_bytes = 0;               // LDS after them for a PCG coarsest solve
     psc::TailDesc<double>* tail64 = nullptr;   // device descriptors (built at setup)
     psc::TailDesc<float>* tail32 = nullptr;
     bool tail_dia = true;                 // the DIA setting the descriptors were built with
@@ -2317,8 +2335,11 @@ static TailLevel<T> tail_level(const psc_hier* h, const DevLevel& V) {
 static int build_tail(psc_hier* h) {
     const int L = (int)h->lev.size();
     h->tail_t = 0;
-    if (L < 3 || h->host.coarse_sweeps > 0 || h->host.coarse_pcg > 0 || !h->split || h->fai || h->cheb)
-        return PSC_OK;
+    if (L < 3 || h->host.coarse_sweeps > 0 || !h->split || h->fai || h->cheb) return PSC_OK;
+    const bool cpcg = h->host.coarse_pcg > 0;
+    if (cpcg && h->lev[L - 1].n > CPCG_MAX) return PSC_OK;
+    // the PCG coarsest solve's direction and block sums (FP64, after the level arrays)
+    const long long pcg_bytes = cpcg ? (long long)(CPCG_MAX + CPCG_WG / 64) * sizeof(double) : 0;
     for (int l = 0; l < L - 1; l++)
         if (h->lev[l].nu < 1) return PSC_OK;
     // automatic: the levels up to 1024 rows with one sweep per level (taking
@@ -2352,9 +2373,9 @@ static int build_tail(psc_hier* h) {
         for (int l = t0; l < L; l++) e += width(l) * h->lev[l].n;
         return e;
     };
-    while (t <= L - 2 && lds_of(t) * (long long)sizeof(double) > lds_max) t++;
+    while (t <= L - 2 && lds_of(t) * (long long)sizeof(double) + pcg_bytes > lds_max) t++;
     if (t > L - 2) return PSC_OK;
-    const int lds_bytes = (int)(lds_of(t) * (long long)sizeof(double));
+    const int lds_bytes = (int)(lds_of(t) * (long long)sizeof(double) + pcg_bytes);
     if (lds_bytes > 64 * 1024 &&
         (hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes) !=
              hipSuccess ||
@@ -2362,7 +2383,7 @@ static int build_tail(psc_hier* h) {
              hipSuccess)) {
         // the runtime refuses more than 64 KB: keep to that
         (void)hipGetLastError();
-        while (t <= L - 2 && lds_of(t) * (long long)sizeof(double) > 64 * 1024) t++;
+        while (t <= L - 2 && lds_of(t) * (long long)sizeof(double) + pcg_bytes > 64 * 1024) t++;
         if (t > L - 2) return PSC_OK;
     }
     TailDesc<double> d64{};
@@ -2379,6 +2400,12 @@ static int build_tail(psc_hier* h) {
     d64.L = d32.L = L;
     d64.nL = d32.nL = h->coarse_n;
     d64.invT = d32.invT = h->coarse_invT;
+    d64.cmaxit = d32.cmaxit = cpcg ? h->host.coarse_pcg : 0;
+    d64.crtol = d32.crtol = h->host.coarse_rtol;
+    d64.cA = d32.cA = h->lev[L - 1].A.view();
+    d64.cminv = d32.cminv = h->lev[L - 1].minv;
+    d64.cpcg_off = (int)(((long long)d64.lds_elems * (long long)sizeof(double) + 7) & ~7LL);
+    d32.cpcg_off = (int)(((long long)d32.lds_elems * (long long)sizeof(float) + 7) & ~7LL);
     for (int l = t; l < L; l++) {
         d64.lev[l] = tail_level<double>(h, h->lev[l]);
         if (h->has32) d32.lev[l] = tail_level<float>(h, h->lev[l]);
@@ -2390,6 +2417,7 @@ static int build_tail(psc_hier* h) {
     if (h->has32) HIPCHK(hipMemcpy(h->tail32, &d32, sizeof(d32), hipMemcpyHostToDevice));
     h->tail_dia = h->dia;
     h->tail_lds = d64.lds_elems;
+    h->tail_pcg_bytes = (int)pcg_bytes;
     h->tail_t = t;
     return PSC_OK;
 }
@@ -2500,7 +2528,8 @@ static void vcycle_t(psc_hier* h, const double* r0, double* z0, const double* d,
     }
     if (tail) {
         TimeScope t(h, 7);
-        k_tail<T><<<1, TAIL_WG, (size_t)h->tail_lds * sizeof(T), h->stream>>>(tail_desc<T>(h), g);
+        const size_t lds = (((size_t)h->tail_lds * sizeof(T) + 7) & ~(size_t)7) + (size_t)h->tail_pcg_bytes;
+        k_tail<T><<<1, TAIL_WG, lds, h->stream>>>(tail_desc<T>(h), g);
     } else {
         DevLevel& C = h->lev[L - 1];
         TimeScope t(h, 7);
@@ -3745,7 +3774,7 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
     s->coarse_pcg_iters = h->host.coarse_pcg;
     const bool tail = h->tail && h->tail_t > 0 && h->split && h->tail_dia == h->dia;
     s->tail_level = tail ? h->tail_t : 0;
-    s->tail_lds_bytes = tail ? h->tail_lds * (int)sizeof(double) : 0;
+    s->tail_lds_bytes = tail ? h->tail_lds * (int)sizeof(double) + h->tail_pcg_bytes : 0;
     if (h->opts.host_only)
         for (int l = 0; l + 1 < L; l++) s->smoother_nnz[l] = (int64_t)h->host.lev[l].fai.zi.size();
     return PSC_OK;

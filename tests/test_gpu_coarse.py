@@ -49,8 +49,11 @@ CONFIGS = {
 }
 
 
+@pytest.mark.parametrize("tail", [True, False])
 @pytest.mark.parametrize("cfg", list(CONFIGS))
-def test_paper_settings_with_inexact_coarsest(psc, cfg):
+def test_paper_settings_with_inexact_coarsest(psc, cfg, tail):
+    """tail: the small levels and the PCG coarsest solve in the one-workgroup
+    LDS kernel (explicit row limit), or launched level by level."""
     rp, c, v = P.poisson7(24)
     n = len(rp) - 1
     lo, oo = CONFIGS[cfg]
@@ -58,6 +61,8 @@ def test_paper_settings_with_inexact_coarsest(psc, cfg):
     h = psc.Hierarchy(rp, c, v, build_fp32=True, coarse_pcg_iters=40, coarse_rtol=0.0, **lo)
     o = oracle.Hierarchy(rp, c, v, coarse_pcg=40, coarse_rtol=0.0, **oo)
     assert h.info()["rows"] == o.sizes()
+    h.tune(psc.TUNE_TAIL, 4096 if tail else 0)
+    assert (h.info()["tail_level"] > 0) == (tail and h.info()["levels"] >= 3)
     r = np.random.default_rng(4).standard_normal(n)
     z = torch.empty(n, dtype=torch.float64, device="cuda")
     h.vcycle(dev(r), z)
@@ -65,6 +70,7 @@ def test_paper_settings_with_inexact_coarsest(psc, cfg):
     assert np.linalg.norm(z.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
     # with the tolerance: FCG as in the paper
     h = psc.Hierarchy(rp, c, v, build_fp32=True, coarse_pcg_iters=40, coarse_rtol=1e-4, **lo)
+    h.tune(psc.TUNE_TAIL, 4096 if tail else 0)
     o = oracle.Hierarchy(rp, c, v, coarse_pcg=40, coarse_rtol=1e-4, **oo)
     b = P.rhs_from_solution(rp, c, v, P.x_true(n, 1))
     ro = o.fcg(b)
