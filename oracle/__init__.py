@@ -99,7 +99,7 @@ def lib():
     L.orc_pcg.restype = C.c_int
     L.orc_fcg.argtypes = [vp, C.c_int, _of64, C.c_int, C.c_int, C.c_int, _f64p, _f64p,
                           C.c_double, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double),
-                          C.POINTER(C.c_int)]
+                          C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.orc_fcg.restype = C.c_int
     L.orc_net_param_count.argtypes = []
     L.orc_net_param_count.restype = C.c_int
@@ -284,14 +284,14 @@ class Hierarchy:
     def fcg(self, b, x0=None, rtol=1e-6, maxit=1000, form=0, params=None, dims=None):
         b = _f64(b)
         x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
-        it, rr, fb = C.c_int(), C.c_double(), C.c_int()
+        it, rr, fb, ne = C.c_int(), C.c_double(), C.c_int(), C.c_int()
         nx = ny = nz = 0
         if params is not None:
             nz, ny, nx = dims
             params = _f64(params)
         st = lib().orc_fcg(self._h, form, params, nx, ny, nz, b, x, rtol, maxit,
-                           C.byref(it), C.byref(rr), C.byref(fb))
-        return dict(status=st, x=x, iters=it.value, relres=rr.value, fallbacks=fb.value)
+                           C.byref(it), C.byref(rr), C.byref(fb), C.byref(ne))
+        return dict(status=st, x=x, iters=it.value, relres=rr.value, fallbacks=fb.value, net_evals=ne.value)
 
 
 def net_param_count():

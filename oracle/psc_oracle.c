@@ -1865,16 +1865,17 @@ void orc_net_apply(const double *params, int nx, int ny, int nz, const double *r
  * instead. The network is switched off for the rest of the solve when a
  * network step leaves ||r_new|| > 0.9 ||r_old|| (stagnation), or when two
  * network steps in a row fail z.r > 0. *fallbacks counts scheduled network
- * steps that ran the V-cycle instead.
+ * steps that ran the V-cycle instead, *net_evals the network applications.
  */
 int orc_fcg(const orc_hier *h, int form, const double *params, int nx, int ny, int nz,
             const double *b, double *x, double rtol, int maxit, int *iters, double *relres,
-            int *fallbacks) {
+            int *fallbacks, int *net_evals) {
     const orc_level *L = &h->lev[0];
     int n = L->A.n;
     double nb = sqrt(dot(n, b, b));
     *iters = 0;
     if (fallbacks) *fallbacks = 0;
+    if (net_evals) *net_evals = 0;
     if (isnan(nb) || isinf(nb)) return ORC_ERR_NAN;
     if (nb == 0.0) { for (int i = 0; i < n; i++) x[i] = 0.0; *relres = 0.0; return ORC_OK; }
     if (params && (size_t)nx * ny * nz != (size_t)n) return ORC_ERR_ARG;
@@ -1891,6 +1892,7 @@ int orc_fcg(const orc_hier *h, int form, const double *params, int nx, int ny, i
         int vform = form == 1 ? ORC_PREC_VCYCLE32 : ORC_PREC_VCYCLE;
         if (use_net) {
             orc_net_apply(params, nx, ny, nz, r, z);
+            if (net_evals) (*net_evals)++;
             if (!(dot(n, z, r) > 0.0)) {
                 apply_prec(h, vform, r, z);
                 use_net = 0;

@@ -104,6 +104,9 @@ def test_zero_network_falls_back_to_vcycle(psc):
     x2 = torch.zeros_like(x)
     g0 = h.fcg(b, x2)
     assert g["status"] == psc.OK and g["relres"] <= 1e-6 and g["fallbacks"] >= 1
+    # every scheduled network step counts: the two that failed z.r > 0 and,
+    # once that switched the network off, the rest
+    assert g["fallbacks"] == g["iters"] // 2
     assert g["iters"] == g0["iters"]
     assert torch.equal(x, x2)
 

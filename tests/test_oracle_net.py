@@ -138,6 +138,9 @@ def test_net_apply_is_scale_equivariant_and_zero_net_falls_back():
     f = h.fcg(b, rtol=1e-6, params=zero, dims=(n, n, n))
     base = h.fcg(b, rtol=1e-6)
     assert f["status"] == oracle.OK and f["fallbacks"] >= 1
+    # z = 0 fails z.r > 0 every time: two such steps in a row switch the
+    # network off, later scheduled steps count as fallbacks without it
+    assert f["net_evals"] == 2 and f["fallbacks"] == f["iters"] // 2
     # every network step fell back, so the iterates are the plain V-cycle ones
     assert f["iters"] == base["iters"]
     np.testing.assert_allclose(f["x"], base["x"], rtol=0, atol=1e-12 * np.abs(base["x"]).max())
