@@ -2376,10 +2376,12 @@ static int build_tail(psc_hier* h) {
     while (t <= L - 2 && lds_of(t) * (long long)sizeof(double) + pcg_bytes > lds_max) t++;
     if (t > L - 2) return PSC_OK;
     const int lds_bytes = (int)(lds_of(t) * (long long)sizeof(double) + pcg_bytes);
+    // the limit is per kernel and process-wide: raise it to what the device
+    // allows, never to this handle's size (another handle may need more)
     if (lds_bytes > 64 * 1024 &&
-        (hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes) !=
+        (hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max) !=
              hipSuccess ||
-         hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes) !=
+         hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max) !=
              hipSuccess)) {
         // the runtime refuses more than 64 KB: keep to that
         (void)hipGetLastError();

@@ -509,3 +509,24 @@ def test_degenerate_systems_match_oracle(psc, case):
     x.zero_()
     g = h.fcg(dev(b), x, prec=psc.FP32)
     assert g["status"] == psc.OK and g["relres"] <= 1e-6
+
+
+def test_tail_lds_limit_holds_across_handles(psc):
+    """The dynamic-LDS limit of the tail kernel is per kernel and process-wide:
+    a handle built later with a smaller tail above 64 KB must not shrink it
+    below what an earlier handle launches (85 KB after 73 KB here)."""
+    hs, outs = [], []
+    for n in (40, 38):
+        rp, c, v = P.poisson7(n)
+        h = psc.Hierarchy(rp, c, v)
+        h.tune(psc.TUNE_TAIL, 4096)
+        assert h.info()["tail_lds_bytes"] > 64 * 1024
+        hs.append((h, rp, c, v))
+    assert hs[0][0].info()["tail_lds_bytes"] > hs[1][0].info()["tail_lds_bytes"]
+    for h, rp, c, v in hs:                    # the larger tail runs after the smaller one was set up
+        n = len(rp) - 1
+        x = np.random.default_rng(7).standard_normal(n)
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        h.vcycle(dev(x), y)
+        ref = oracle.Hierarchy(rp, c, v).vcycle(x)
+        assert np.linalg.norm(y.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
