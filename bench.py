@@ -189,7 +189,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3, help="oracle PCG iterations in the CPU sample")
-    ap.add_argument("--spmv-reps", type=int, default=50)
+    ap.add_argument("--spmv-reps", type=int, default=100)
     ap.add_argument("--grid-max", type=int, default=0, help="workgroup cap of the streaming kernels")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-dia", action="store_true", help="read level operators from hacked ELL only")
