@@ -1941,10 +1941,16 @@ __global__ void k_refresh_values(long long n, const int32_t* __restrict__ rp, co
             if (am32) am32[slot] = (float)y;
         }
         if (dstart) {
+            // the slice's offsets ascend: binary search for this column's diagonal
             const int d = c - (int)i;
-            int k = k0;
-            while (k < k1 && doffs[k] != d) k++;
-            if (k < k1) {
+            int lo = k0, hi = k1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (doffs[mid] < d) lo = mid + 1;
+                else hi = mid;
+            }
+            const int k = lo;
+            if (k < k1 && doffs[k] == d) {
                 const long long ds = (long long)k * SLICE + lane;
                 dval[ds] = x;
                 if (dval32) dval32[ds] = (float)x;
