@@ -2,20 +2,24 @@
 """Benchmark of the AMG-PCG solve phase on one MI355X.
 
 Default workload (one step = one full solve to rtol 1e-6 from x0 = 0): the
-7-point 3D Poisson problem on a 256^3 grid (16.8M unknowns, 117M nonzeros,
+7-point 3D Poisson problem on a 384^3 grid (56.6M unknowns, 395M nonzeros,
 b = A x_true with x_true ~ U[0,1) seed 0), FP64 preconditioned CG with the
-FP64 AMG V-cycle. On the same problem and GPU the FP32 V-cycle inside FP64
-flexible CG and, when trained weights are present, the learned form are
-timed and reported beside it, each checked by its true FP64 residual.
+FP64 AMG V-cycle -- the largest single-GPU configuration, on which plain
+FP64, the FP32 V-cycle inside FP64 flexible CG and the learned form are all
+run. Each form is timed on the same problem and GPU and checked by its true
+FP64 residual.
 
 Printed: one JSON line with the time to solution (ms per step), the HBM
-roofline of the dominant kernel (average duration from HIP events recorded
-on the library's stream around every launch during the timed steps), and
-the CPU oracle timed on a bounded sample of the same workload.
+roofline of the dominant kernel, k_spmv_pfuse (the fused CG pass: direction
+update, q = A p, deferred x update and p.q), from HIP events recorded on the
+library's stream around each of its launches during timed solves (the rest
+of the iteration runs back to back; launches issued past convergence, which
+exit at entry, are not counted), and the CPU oracle's full solve of the same
+problem on the host's cores.
 
-Other workloads (not the headline line): --workload diffusion256 (lognormal
-coefficients, --az anisotropy), poisson384, learned128 (collect pairs, train
-the network, evaluate on held-out right-hand sides).
+Other workloads (not the headline line): --workload poisson256,
+diffusion256 (lognormal coefficients, --az anisotropy), learned128 (collect
+pairs, train the network, evaluate on held-out right-hand sides).
 """
 from __future__ import annotations
 
@@ -30,7 +34,7 @@ METRIC = "time-to-rtol 1e-6 + SpMV/V-cycle HBM GB/s: FP64 vs mixed vs learned"
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(ROOT, "paper_2406_19754_amd", "weights", "net_poisson128.f32")
-TRAFFIC = os.path.join(ROOT, "profiles", "traffic_poisson256.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_poisson384.json")
 
 
 def log(*a):
@@ -63,10 +67,10 @@ def kernel_bytes(info, form="fp64", fused=False, split=True, dia=True):
     if fused:
         return {
             # A; z and p_old gathered; p_new, q written; x read and written
-            "spmv_dot": Z * a64 + 2 * 8 * N + 2 * 8 * N + 2 * 8 * N,
-            "pre_smooth_l0": pre,
-            "restrict_l0": N * (v + 4) + v * N + v * Nc,
-            "post_smooth_l0": post,
+            "k_spmv_pfuse": Z * a64 + 2 * 8 * N + 2 * 8 * N + 2 * 8 * N,
+            "k_update_pre_s": pre,
+            "k_spmv_R": N * (v + 4) + v * N + v * Nc,
+            "k_post_s": post,
         }
     return {
         "spmv_dot": Z * a64 + 2 * 8 * N,                       # A, p gathered, q written
@@ -85,14 +89,14 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel):
+def traffic_for(kernel, n):
     """Per-launch HBM bytes of `kernel` from committed PMC counters, or None
-    when the counters were taken on other kernel sources."""
+    when the counters were taken on other kernel sources or another size."""
     try:
         t = json.load(open(TRAFFIC))
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != source_hash():
+    if t.get("source_hash") != source_hash() or t.get("n") != n:
         return None
     k = t.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
@@ -181,14 +185,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="poisson256",
+    ap.add_argument("--workload", default="poisson384",
                     choices=["poisson256", "poisson384", "diffusion256", "learned128"])
     ap.add_argument("--n", type=int, default=0, help="grid size per axis (default from the workload)")
     ap.add_argument("--az", type=float, default=1.0, help="z anisotropy of the diffusion workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=3, help="oracle PCG iterations in the CPU sample")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="oracle threads (default: OMP_NUM_THREADS, else every core of the affinity mask)")
     ap.add_argument("--spmv-reps", type=int, default=100)
     ap.add_argument("--grid-max", type=int, default=0, help="workgroup cap of the streaming kernels")
     ap.add_argument("--no-graph", action="store_true")
@@ -335,9 +340,11 @@ def main():
         return h.fcg(bd, x, rtol=1e-6, maxit=500, net=net)
 
     def timed(form, steps, warmup, events):
+        """events: 0 graph replay (the headline), 1 HIP events around every
+        level-0 kernel, 2 HIP events around the outer SpMV pass only."""
         for _ in range(warmup):
             run(form)
-        h.timing(events)
+        h.timing(int(events))
         h.timing_get()
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -351,30 +358,41 @@ def main():
         return ms, res, kt
 
     # Timed region: K solves replayed from the captured iteration graph (the
-    # headline time to solution), then K solves launched kernel by kernel with
-    # HIP events recorded on the library's stream around every level-0 kernel
-    # (per-kernel durations for the roofline; the events themselves cost
-    # launch gaps, so these solves are not the headline).
+    # headline time to solution); then K solves launched kernel by kernel with
+    # HIP events on the library's stream around every level-0 kernel (the
+    # per-kernel table; the events add launch gaps, so these solves are not the
+    # headline); then K solves with events around the outer SpMV pass only, the
+    # rest of each iteration back to back as in a replay (the roofline).
+    fused = not args.unfused and info["levels"] > 1
     ms64, r64, _ = timed("fp64", args.steps, args.warmup, False)
     log(f"fp64 pcg: {ms64:.2f} ms/solve, {r64['iters']} its, relres {r64['relres']:.2e}")
-    ms64e, r64e, kt64 = timed("fp64", args.steps, 0, True)
-    log(f"fp64 pcg, event-instrumented launches: {ms64e:.2f} ms/solve")
-    assert r64e["iters"] == r64["iters"]
     xg = x.cpu().numpy()
+    ms64e, r64e, kt64 = timed("fp64", args.steps, 0, 1)
+    log(f"fp64 pcg, events around every level-0 kernel: {ms64e:.2f} ms/solve")
+    assert r64e["iters"] == r64["iters"]
+    ms64r, r64r, kt64r = timed("fp64", args.steps, 0, 2)
+    log(f"fp64 pcg, events around the outer SpMV pass only: {ms64r:.2f} ms/solve")
+    assert r64r["iters"] == r64["iters"]
     err_true = float(np.linalg.norm(xg - xt) / np.linalg.norm(xt))
 
-    kb = kernel_bytes(info, "fp64", fused=not args.unfused and info["levels"] > 1, split=not args.no_split,
-                      dia=not args.no_dia)
+    kb = kernel_bytes(info, "fp64", fused=fused, split=not args.no_split, dia=not args.no_dia)
+    tname = ({"spmv_dot": "k_spmv_pfuse", "pre_smooth_l0": "k_update_pre_s", "restrict_l0": "k_spmv_R",
+              "post_smooth_l0": "k_post_s"} if fused else {})
     kernels = {}
     for name, (cnt, tot) in kt64.items():
-        if cnt and name in kb:
+        kname = tname.get(name, name)
+        if cnt and kname in kb:
             avg = tot / cnt
-            kernels[name] = {"launches": cnt, "avg_ms": avg, "alg_bytes": kb[name],
-                             "gbs": kb[name] / (avg * 1e-3) / 1e9}
-    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
-    d = kernels[dom]
+            kernels[kname] = {"launches": cnt, "avg_ms": avg, "alg_bytes": kb[kname],
+                              "gbs": kb[kname] / (avg * 1e-3) / 1e9}
     vc_cnt, vc_ms = kt64["vcycle"]
     vcycle_gbs = info["vcycle_bytes_fp64"] / (vc_ms / vc_cnt * 1e-3) / 1e9 if vc_cnt else None
+    # the roofline kernel: the outer SpMV pass, timed alone
+    dom = tname.get("spmv_dot", "spmv_dot")
+    rc, rt = kt64r["spmv_dot"]
+    d = {"launches": rc, "avg_ms": rt / rc, "alg_bytes": kb[dom], "gbs": kb[dom] / (rt / rc * 1e-3) / 1e9}
+    log(f"{dom}: {rc} launches, {d['avg_ms'] * 1e3:.1f} us avg, {d['gbs']:.0f} GB/s "
+        f"({d['gbs'] / HBM_PEAK_GBS:.3f} of peak)")
 
     # isolated SpMV loop on A_0 (the same kernel family)
     xs = torch.rand(N, dtype=torch.float64, device=dev)
@@ -385,7 +403,7 @@ def main():
     for _ in range(args.spmv_reps):
         h.spmv(xs, ys)
     ks = h.timing_get()["spmv_dot"]
-    h.timing(False)
+    h.timing(0)
     spmv_ms = ks[1] / ks[0]
     spmv_gbs = info["spmv_bytes_fp64"] / (spmv_ms * 1e-3) / 1e9
 
@@ -423,21 +441,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        import oracle
-        t0 = time.time()
-        o = oracle.Hierarchy(rp, col, val)
-        t_setup = time.time() - t0
-        k = args.cpu_iters
-        t0 = time.perf_counter()
-        o.pcg(b, rtol=1e-30, maxit=k)
-        t_k = time.perf_counter() - t0
-        est = t_k / k * r64["iters"] * 1e3
-        cpu = {"value": est, "unit": "ms", "cores": 1, "kind": "oracle",
-               "sample": f"oracle PCG, {k} of {r64['iters']} iterations on the same {n}^3 problem "
-                         f"({t_k:.1f}s, single thread), scaled to {r64['iters']}; oracle setup {t_setup:.1f}s "
-                         "excluded like the GPU setup",
-               "gpu_speedup": est / ms64}
-        log(f"cpu oracle: {t_k / k:.2f} s/iter -> {est / 1e3:.1f} s/solve (setup {t_setup:.1f}s)")
+        cpu = cpu_baseline(args, rp, col, val, b, n, r64, xg, ms64)
 
     out = {
         "metric": METRIC,
@@ -466,11 +470,53 @@ def main():
         "forms": forms,
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": traffic_for(dom),
-                     "alg_bytes_per_launch": d["alg_bytes"], "avg_ms": d["avg_ms"]},
+                     "unit": "GB/s", "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": traffic_for(dom, n),
+                     "alg_bytes_per_launch": d["alg_bytes"], "avg_ms": d["avg_ms"], "launches": d["launches"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(args, rp, col, val, b, n, r64, xg, ms64):
+    """The CPU oracle (plain C, FP64 CSR) on the same problem: its own
+    hierarchy build, then one full PCG solve to rtol 1e-6 from x0 = 0, timed
+    with the host clock. Its row loops run on the host threads; dots,
+    restrictions and the build are serial. Also states how far the GPU's FP64
+    solution is from the oracle's."""
+    import numpy as np
+    import oracle
+    threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS", "0") or 0) \
+        or len(os.sched_getaffinity(0))
+    oracle.set_threads(threads)
+    threads = oracle.get_threads()
+    t0 = time.perf_counter()
+    o = oracle.Hierarchy(rp, col, val)
+    t_setup = time.perf_counter() - t0
+    log(f"cpu oracle: hierarchy {o.sizes()} built in {t_setup:.1f}s (serial)")
+    t0 = time.perf_counter()
+    res = o.pcg(b, rtol=1e-6, maxit=500)
+    t_solve = time.perf_counter() - t0
+    xo = res["x"]
+    diff = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+    log(f"cpu oracle: PCG {res['iters']} its in {t_solve:.1f}s on {threads} threads, relres {res['relres']:.2e}; "
+        f"|x_gpu - x_oracle|/|x_oracle| = {diff:.2e}")
+    return {"value": t_solve * 1e3, "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": f"one full oracle PCG solve of the same {n}^3 problem to rtol 1e-6 from x0 = 0 "
+                      f"({res['iters']} iterations; row loops on {threads} threads, dots and restrictions "
+                      f"serial); its serial hierarchy build ({t_setup:.1f} s) is excluded like the GPU setup",
+            "cpu_model": cpu_model(), "oracle_iters": res["iters"], "oracle_relres": res["relres"],
+            "oracle_setup_s": t_setup, "gpu_iters": r64["iters"],
+            "x_gpu_vs_oracle": diff, "gpu_speedup": t_solve * 1e3 / ms64}
 
 
 def profile_mix(args):

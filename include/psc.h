@@ -193,8 +193,12 @@ void psc_amg_opts_default(psc_amg_opts* opts);
  *   opts        NULL for defaults
  *   hip_stream  hipStream_t used for all device work of the handle
  *   out         receives the handle; release with psc_hier_free
- * The setup runs on the host (as in the paper, where the hierarchy build is
- * mostly host-side) and ends with one host-to-device copy of every level.
+ * With setup_device = 1 (the default) the coarsening of the matching
+ * setting runs on the GPU (matching, aggregates, prolongator, Galerkin
+ * product) and the values of every storage format are filled on the GPU;
+ * the layouts, the smoother setup of other settings and the coarsest factor
+ * are computed on the host (the paper's build is mostly host-side). The CSR
+ * arrays are copied; the caller keeps them.
  * Errors: PSC_ERR_ARG (malformed CSR or options), PSC_ERR_NOT_SPD
  * (diagonal <= 0 or coarsest Cholesky breakdown), PSC_ERR_COARSEN (a stall
  * above 2000 rows with coarse_sweeps = 0, or a coarsest level forced by
@@ -237,7 +241,8 @@ int psc_amg_rebuild(psc_hier* h, const double* val_host);
  *   relres   out: true relative residual ||b - A x||_2 / ||b||_2 in FP64
  * b = 0 gives x = 0, iters = 0. Returns PSC_NOCONV when maxit is reached,
  * PSC_ERR_NAN when b or an iterate holds NaN/Inf, PSC_ERR_NOT_SPD on a
- * breakdown (p.q <= 0 or r.z <= 0).
+ * breakdown (p.q <= 0 or r.z <= 0); x_dev then holds the last iterate
+ * before the breakdown.
  */
 int psc_pcg_solve(psc_hier* h, const double* b_dev, double* x_dev, double rtol,
                   int32_t maxit, int32_t* iters, double* relres);
@@ -252,14 +257,16 @@ int psc_pcg_solve(psc_hier* h, const double* b_dev, double* x_dev, double rtol,
  *   vcycle_prec  PSC_FP64, or PSC_FP32 (the V-cycle in FP32: level
  *                operators, smoothing and transfers in FP32, the coarsest
  *                solve in FP64; needs build_fp32)
- *   net          NULL for the V-cycle only; else odd iterations apply the
- *                learned network z = s net(r/s), s = ||r||/sqrt(n), with
- *                the V-cycle taken instead when z.r <= 0, and the network
- *                switched off for the rest of the solve when a network step
- *                leaves ||r_new|| > 0.9 ||r_old||. The grid given at
- *                psc_net_apply time must have nx*ny*nz = n.
+ *   net          NULL for the V-cycle only; else the iterations k = 1, 3,
+ *                5, ... (counting from 0) apply the learned network
+ *                z = s net(r/s), s = ||r||/sqrt(n), with the V-cycle taken
+ *                instead when z.r <= 0. The network is switched off for the
+ *                rest of the solve when a network step leaves
+ *                ||r_new|| > 0.9 ||r_old|| (stagnation), or when two
+ *                scheduled network steps in a row fail z.r > 0. The grid
+ *                declared with psc_net_set_grid must have nx*ny*nz = n.
  *   fallbacks    out (may be NULL): scheduled network steps that ran the
- *                V-cycle instead
+ *                V-cycle instead (also those after the switch-off)
  * Other arguments and errors as for psc_pcg_solve.
  */
 int psc_fcg_solve(psc_hier* h, psc_net* net, int32_t vcycle_prec, const double* b_dev,
@@ -339,10 +346,14 @@ int psc_vcycle_apply(psc_hier* h, int32_t prec, const double* r_dev, double* z_d
 int psc_spmv(psc_hier* h, int32_t level, int32_t prec, const void* x_dev, void* y_dev);
 
 /*
- * Kernel timing. When enabled, the library records HIP events on its stream
- * around every launch of the level-0 kernels during solves (which disables
- * graph replay) and accumulates their durations; psc_timing_get returns,
- * per kernel id, the launch count and the total milliseconds, and resets.
+ * Kernel timing. When enabled (on = 1), the library records HIP events on its
+ * stream around every launch of the level-0 kernels during solves (which
+ * disables graph replay) and accumulates their durations; on = 2 records
+ * only the outer SpMV pass (kernel id 0), so the rest of each iteration runs
+ * back to back as in a replay. Launches issued past convergence (they exit at
+ * entry) are not counted. psc_timing_get returns, per kernel id, the launch
+ * count and the total milliseconds, and resets. The V-cycle ids count the
+ * V-cycle-only forms exactly (on a learned step the V-cycle is skipped).
  * Kernel ids: 0 outer SpMV (+p.q), 1 CG update (+||r||^2), 2 level-0
  * pre-smoothing + residual, 3 level-0 restriction, 4 level-0 prolongation +
  * post-smoothing (+r.z), 5 direction update, 6 whole V-cycle.

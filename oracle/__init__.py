@@ -115,6 +115,10 @@ def lib():
     L.orc_adam_step.restype = None
     L.orc_net_apply.argtypes = [_f64p, C.c_int, C.c_int, C.c_int, _f64p, _f64p]
     L.orc_net_apply.restype = None
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_set_threads.restype = None
+    L.orc_get_threads.argtypes = []
+    L.orc_get_threads.restype = C.c_int
     _lib = L
     return L
 
@@ -125,6 +129,15 @@ def _f64(a):
 
 def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def set_threads(t):
+    """Host threads of the oracle's row loops (results do not depend on it)."""
+    lib().orc_set_threads(int(t))
+
+
+def get_threads():
+    return lib().orc_get_threads()
 
 
 def spmv(rowptr, col, val, x):

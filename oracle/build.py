@@ -10,7 +10,7 @@ LIB = os.path.join(HERE, "libpsc_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
            "-fPIC", "-shared", "-Wall", "-Wno-maybe-uninitialized", "-o", LIB, SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))

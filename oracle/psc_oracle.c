@@ -32,7 +32,8 @@
  * Parity pins live in tests/test_oracle_*.py. Functions marked
  * "parity unpinned" have no independent pin.
  *
- * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared (no fast-math).
+ * Build: gcc -O2 -std=gnu11 -fopenmp -ffp-contract=off -fPIC -shared (no
+ * fast-math).
  */
 #include <math.h>
 #include <stdint.h>
@@ -48,6 +49,36 @@
 #define ORC_ERR_COARSEN -6
 
 #define ORC_MAXLEV 64
+
+/*
+ * Row-independent loops (y_i = sum_k a_ik x_k, elementwise vector updates)
+ * may run on several host threads: every row is still computed by one thread
+ * in the same order, so the results are identical for any thread count.
+ * Dot products, restrictions (scatter sums) and the whole setup stay serial.
+ */
+#ifdef _OPENMP
+#include <omp.h>
+#define ORC_ROWS _Pragma("omp parallel for schedule(static) if (n >= 65536)")
+#else
+#define ORC_ROWS
+#endif
+
+/* Threads used by the row loops (<= 0: leave the OpenMP default). */
+void orc_set_threads(int t) {
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
+int orc_get_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* CSR helpers                                                              */
@@ -68,6 +99,7 @@ static void csr_free(csr *a) {
 /* y = A x, each row summed in ascending column order */
 void orc_spmv(int n, const int *rp, const int *ci, const double *v,
               const double *x, double *y) {
+    ORC_ROWS
     for (int i = 0; i < n; i++) {
         double s = 0.0;
         for (int k = rp[i]; k < rp[i + 1]; k++) s += v[k] * x[ci[k]];
@@ -1389,20 +1421,25 @@ static void vcycle_level(const orc_hier *h, int l, const double *b, double *x) {
         y = malloc(sizeof(double) * (size_t)n);
         fai_apply(&L->S, b, x, y);
     } else {
+        ORC_ROWS
         for (int i = 0; i < n; i++) x[i] = L->minv[i] * b[i];
     }
     for (int k = 1; k < nu && h->smoother != 3; k++) {
         orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
         if (L->S.n) {
+            ORC_ROWS
             for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
             fai_apply(&L->S, r, t, y);
+            ORC_ROWS
             for (int i = 0; i < n; i++) x[i] += t[i];
         } else {
+            ORC_ROWS
             for (int i = 0; i < n; i++) x[i] += L->minv[i] * (b[i] - r[i]);
         }
     }
     /* residual r = b - A x */
     orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
+    ORC_ROWS
     for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
     /* restriction b_c = P^T r (fine rows ascending, then row entries) */
     for (int I = 0; I < nc; I++) bc[I] = 0.0;
@@ -1410,6 +1447,7 @@ static void vcycle_level(const orc_hier *h, int l, const double *b, double *x) {
         for (int m = P->rp[i]; m < P->rp[i + 1]; m++) bc[P->ci[m]] += P->v[m] * r[i];
     vcycle_level(h, l + 1, bc, xc);
     /* prolongation and correction x += P x_c */
+    ORC_ROWS
     for (int i = 0; i < n; i++) {
         double s = 0.0;
         for (int m = P->rp[i]; m < P->rp[i + 1]; m++) s += P->v[m] * xc[P->ci[m]];
@@ -1421,10 +1459,13 @@ static void vcycle_level(const orc_hier *h, int l, const double *b, double *x) {
     for (int k = 0; k < nu && h->smoother != 3; k++) {
         orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, r);
         if (L->S.n) {
+            ORC_ROWS
             for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
             fai_apply(&L->S, r, t, y);
+            ORC_ROWS
             for (int i = 0; i < n; i++) x[i] += t[i];
         } else {
+            ORC_ROWS
             for (int i = 0; i < n; i++) x[i] += L->minv[i] * (b[i] - r[i]);
         }
     }
@@ -1471,22 +1512,28 @@ static void vcycle32_level(const orc_hier *h, int l, const float *b, float *x) {
         y = malloc(sizeof(float) * (size_t)n);
         fai_apply32(&L->S, b, x, y);
     } else {
+        ORC_ROWS
         for (int i = 0; i < n; i++) x[i] = (float)L->minv[i] * b[i];
     }
     for (int k = 1; k < nu && h->smoother != 3; k++) {
+        ORC_ROWS
         for (int i = 0; i < n; i++) {
             float s = 0.0f;
             for (int q = L->A.rp[i]; q < L->A.rp[i + 1]; q++) s += (float)L->A.v[q] * x[L->A.ci[q]];
             r[i] = s;
         }
         if (L->S.n) {
+            ORC_ROWS
             for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
             fai_apply32(&L->S, r, t, y);
+            ORC_ROWS
             for (int i = 0; i < n; i++) x[i] += t[i];
         } else {
+            ORC_ROWS
             for (int i = 0; i < n; i++) x[i] += (float)L->minv[i] * (b[i] - r[i]);
         }
     }
+    ORC_ROWS
     for (int i = 0; i < n; i++) {
         float s = 0.0f;
         for (int q = L->A.rp[i]; q < L->A.rp[i + 1]; q++) s += (float)L->A.v[q] * x[L->A.ci[q]];
@@ -1496,6 +1543,7 @@ static void vcycle32_level(const orc_hier *h, int l, const float *b, float *x) {
     for (int i = 0; i < n; i++)
         for (int m = P->rp[i]; m < P->rp[i + 1]; m++) bc[P->ci[m]] += (float)P->v[m] * r[i];
     vcycle32_level(h, l + 1, bc, xc);
+    ORC_ROWS
     for (int i = 0; i < n; i++) {
         float s = 0.0f;
         for (int m = P->rp[i]; m < P->rp[i + 1]; m++) s += (float)P->v[m] * xc[P->ci[m]];
@@ -1503,16 +1551,20 @@ static void vcycle32_level(const orc_hier *h, int l, const float *b, float *x) {
     }
     if (h->smoother == 3) cheb4_smooth32(L, nu, b, x, 0, r, t, y);
     for (int k = 0; k < nu && h->smoother != 3; k++) {
+        ORC_ROWS
         for (int i = 0; i < n; i++) {
             float s = 0.0f;
             for (int q = L->A.rp[i]; q < L->A.rp[i + 1]; q++) s += (float)L->A.v[q] * x[L->A.ci[q]];
             r[i] = s;
         }
         if (L->S.n) {
+            ORC_ROWS
             for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
             fai_apply32(&L->S, r, t, y);
+            ORC_ROWS
             for (int i = 0; i < n; i++) x[i] += t[i];
         } else {
+            ORC_ROWS
             for (int i = 0; i < n; i++) x[i] += (float)L->minv[i] * (b[i] - r[i]);
         }
     }
@@ -1523,8 +1575,10 @@ void orc_vcycle32(const orc_hier *h, const double *b, double *x) {
     int n = h->lev[0].A.n;
     float *bf = malloc(sizeof(float) * (size_t)n);
     float *xf = malloc(sizeof(float) * (size_t)n);
+    ORC_ROWS
     for (int i = 0; i < n; i++) bf[i] = (float)b[i];
     vcycle32_level(h, 0, bf, xf);
+    ORC_ROWS
     for (int i = 0; i < n; i++) x[i] = (double)xf[i];
     free(bf); free(xf);
 }
@@ -1573,6 +1627,7 @@ int orc_pcg(const orc_hier *h, int prec, const double *b, double *x, double rtol
     double *r = malloc(sizeof(double) * (size_t)n), *z = malloc(sizeof(double) * (size_t)n);
     double *p = malloc(sizeof(double) * (size_t)n), *q = malloc(sizeof(double) * (size_t)n);
     orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, q);
+    ORC_ROWS
     for (int i = 0; i < n; i++) r[i] = b[i] - q[i];
     int st = ORC_NOCONV, k = 0;
     if (sqrt(dot(n, r, r)) <= rtol * nb) st = ORC_OK;
@@ -1586,6 +1641,7 @@ int orc_pcg(const orc_hier *h, int prec, const double *b, double *x, double rtol
             double pq = dot(n, p, q);
             if (!(pq > 0.0)) { st = isnan(pq) ? ORC_ERR_NAN : ORC_ERR_NOT_SPD; break; }
             double alpha = rho / pq;
+            ORC_ROWS
             for (int i = 0; i < n; i++) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
             k++;
             double rr = dot(n, r, r);
@@ -1597,12 +1653,14 @@ int orc_pcg(const orc_hier *h, int prec, const double *b, double *x, double rtol
             if (!(rho2 > 0.0)) { st = isnan(rho2) ? ORC_ERR_NAN : ORC_ERR_NOT_SPD; break; }
             double beta = rho2 / rho;
             if (hist) hist[2 * (k - 1) + 1] = beta;
+            ORC_ROWS
             for (int i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
             rho = rho2;
         }
     }
     *iters = k;
     orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, q);
+    ORC_ROWS
     for (int i = 0; i < n; i++) r[i] = b[i] - q[i];
     *relres = sqrt(dot(n, r, r)) / nb;
     free(r); free(z); free(p); free(q);
@@ -1883,6 +1941,7 @@ int orc_fcg(const orc_hier *h, int form, const double *params, int nx, int ny, i
     double *p = malloc(sizeof(double) * (size_t)n), *q = malloc(sizeof(double) * (size_t)n);
     double *pp = malloc(sizeof(double) * (size_t)n), *qp = malloc(sizeof(double) * (size_t)n);
     orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, q);
+    ORC_ROWS
     for (int i = 0; i < n; i++) r[i] = b[i] - q[i];
     int st = ORC_NOCONV, k = 0, have_prev = 0, net_on = params != NULL, net_fails = 0;
     double pqp = 0.0;
@@ -1907,6 +1966,7 @@ int orc_fcg(const orc_hier *h, int form, const double *params, int nx, int ny, i
         }
         if (have_prev) {
             double beta = dot(n, z, qp) / pqp;
+            ORC_ROWS
             for (int i = 0; i < n; i++) p[i] = z[i] - beta * pp[i];
         } else {
             memcpy(p, z, sizeof(double) * (size_t)n);
@@ -1917,6 +1977,7 @@ int orc_fcg(const orc_hier *h, int form, const double *params, int nx, int ny, i
         if (!(pq > 0.0)) { st = ORC_ERR_NOT_SPD; break; }
         double rr_old = dot(n, r, r);
         double alpha = dot(n, p, r) / pq;
+        ORC_ROWS
         for (int i = 0; i < n; i++) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
         k++;
         double rr = dot(n, r, r);
@@ -1928,6 +1989,7 @@ int orc_fcg(const orc_hier *h, int form, const double *params, int nx, int ny, i
         have_prev = 1;
         if (sqrt(rr) <= rtol * nb) {
             orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, q);
+            ORC_ROWS
             for (int i = 0; i < n; i++) q[i] = b[i] - q[i];
             if (sqrt(dot(n, q, q)) <= rtol * nb) { st = ORC_OK; break; }
             memcpy(r, q, sizeof(double) * (size_t)n);
@@ -1936,6 +1998,7 @@ int orc_fcg(const orc_hier *h, int form, const double *params, int nx, int ny, i
     }
     *iters = k;
     orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, q);
+    ORC_ROWS
     for (int i = 0; i < n; i++) r[i] = b[i] - q[i];
     *relres = sqrt(dot(n, r, r)) / nb;
     free(r); free(z); free(p); free(q); free(pp); free(qp);

@@ -13,10 +13,11 @@
 //     bytes of values and 256 of indices, streamed with non-temporal loads
 //     so the gathered vectors keep the L2 and Infinity Cache;
 //   * streaming kernels run a fixed grid (a few workgroups per CU) in which
-//     workgroup b walks a contiguous range of slices; workgroup ids are
-//     remapped so each of the 8 XCDs (which receive workgroups round-robin)
-//     owns one contiguous eighth of the rows and its L2 holds the x-planes
-//     its rows gather from;
+//     workgroup b walks a contiguous range of slices in launch order, so the
+//     8 XCDs (which receive workgroups round-robin) sweep the same region at
+//     once and share the neighbour gathers through the Infinity Cache; an
+//     optional remap (PSC_TUNE_XCD) gives each XCD one contiguous eighth of
+//     the rows instead, which measured slower;
 //   * every dot product is fused into the kernel that produces one of its
 //     operands: wavefront shuffles, then LDS, then one partial per
 //     workgroup; a one-workgroup finishing kernel adds the partials in a
@@ -73,16 +74,14 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// XCD-aware logical workgroup id: physical ids are dealt round-robin to the
-// 8 XCDs, so XCD x receives ids x, x+8, ...; mapping them to the contiguous
-// range [x*G/8, (x+1)*G/8) gives each XCD one contiguous block of rows.
-// G (gridDim.x) is always a multiple of 8.
 // Block order. Workgroups are dealt round-robin to the 8 accelerator dies
 // (block b runs on die b % 8). By default a block takes the work in launch
 // order, so all dies sweep the same region at once and share the neighbour
 // gathers through the Infinity Cache; measured faster (5 % on the 256^3 PCG
 // iteration) than giving each die its own contiguous chunk, which keeps the
-// gathers in the die's L2. PSC_TUNE_XCD = 1 selects the chunked order.
+// gathers in the die's L2. PSC_TUNE_XCD = 1 selects the chunked order:
+// XCD x receives ids x, x+8, ... and maps them to the contiguous range
+// [x*G/8, (x+1)*G/8) (G = gridDim.x, always a multiple of 8).
 __constant__ int g_xcd_chunked = 0;
 
 __device__ __forceinline__ int logical_block() {
@@ -151,8 +150,10 @@ __device__ void finalize(int fin, double s0, double s1, Ctl* c, HostCtl* hc) {
     case FIN_ALPHA_FCG:
         c->pq = s0;
         c->pr = s1;
-        if (isnan(s0) || isnan(s1)) { c->status = PSC_ERR_NAN; c->done = 1; }
-        else if (!(s0 > 0.0)) { c->status = PSC_ERR_NOT_SPD; c->done = 1; }
+        // on a breakdown alpha = 0: the deferred x update of the fused forms
+        // (already applied for the previous direction) is not repeated
+        if (isnan(s0) || isnan(s1)) { c->status = PSC_ERR_NAN; c->done = 1; c->alpha = 0.0; }
+        else if (!(s0 > 0.0)) { c->status = PSC_ERR_NOT_SPD; c->done = 1; c->alpha = 0.0; }
         else { c->alpha = s1 / s0; c->pq_prev = s0; c->have_prev = 1; }
         break;
     case FIN_UPDATE_PCG:
@@ -1823,10 +1824,13 @@ struct psc_hier {
     int gmax = psc::GMAX;                 // workgroup cap of the streaming kernels
     // captured iterations, one per (form, network, network generation)
     std::vector<psc::GraphEntry> graphs;
-    // timing
-    bool timing = false;
+    // timing: 0 off, 1 every level-0 kernel and the whole V-cycle, 2 only
+    // the outer SpMV pass (kernel id 0)
+    int timing = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
     std::vector<int> ev_kind;
+    std::vector<int> ev_iter;             // iteration a timed launch belongs to (-1: outside the loop)
+    int t_iter = -1;                      // iteration being issued
     size_t ev_used = 0;
     int64_t t_count[PSC_TIMING_KERNELS] = {0};
     double t_ms[PSC_TIMING_KERNELS] = {0};
@@ -2158,16 +2162,18 @@ struct TimeScope {
     int kind;
     size_t idx = (size_t)-1;
     TimeScope(psc_hier* hh, int k) : h(hh), kind(k) {
-        if (!h->timing) return;
+        if (!h->timing || (h->timing == 2 && kind != 0)) return;
         if (h->ev_used >= h->ev_pool.size()) {
             hipEvent_t a, b;
             if (hipEventCreate(&a) != hipSuccess) return;
             if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
             h->ev_pool.push_back({a, b});
             h->ev_kind.push_back(0);
+            h->ev_iter.push_back(-1);
         }
         idx = h->ev_used++;
         h->ev_kind[idx] = kind;
+        h->ev_iter[idx] = h->t_iter;
         (void)hipEventRecord(h->ev_pool[idx].first, h->stream);
     }
     ~TimeScope() {
@@ -2175,10 +2181,18 @@ struct TimeScope {
     }
 };
 
-static void timing_collect(psc_hier* h) {
+// Accumulate the recorded launch durations. After a solve of `iters`
+// iterations, launches issued past convergence (they exit at entry) are left
+// out: the outer-pass kernels (ids 0-2) of iteration i ran when i < iters, the
+// V-cycle kernels (ids 3-7) when i < iters - vc_lag (vc_lag = 1 where the
+// V-cycle closes an iteration, after its convergence test; 0 where it opens
+// one). iters < 0: keep every launch.
+static void timing_collect(psc_hier* h, int iters = -1, int vc_lag = 0) {
     if (!h->timing || h->ev_used == 0) return;
     (void)hipStreamSynchronize(h->stream);
     for (size_t i = 0; i < h->ev_used; i++) {
+        const int it = h->ev_iter[i];
+        if (iters >= 0 && it >= 0 && it >= (h->ev_kind[i] <= 2 ? iters : iters - vc_lag)) continue;
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, h->ev_pool[i].first, h->ev_pool[i].second) == hipSuccess) {
             h->t_count[h->ev_kind[i]] += 1;
@@ -2847,7 +2861,9 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
     const Gate gd{h->ctl, GATE_DONE};
     if (form == FORM_FUSED) {
         // two iterations (even, odd) with the p and r buffers swapped between them
+        const int it0 = h->t_iter;
         for (int parity = 0; parity < 2; parity++) {
+            if (it0 >= 0) h->t_iter = it0 + parity;
             double* pold = parity ? h->p2 : h->p;
             double* pnew = parity ? h->p : h->p2;
             double* rold = parity ? h->r2 : h->r;
@@ -2891,7 +2907,9 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
         // in every one: on a grid of at most 1024 workgroups their early exit
         // costs a few microseconds instead of tens.
         const int gq = std::min(ge, 1024);
+        const int it0 = h->t_iter;
         for (int parity = 0; parity < 2; parity++) {
+            if (it0 >= 0) h->t_iter = it0 + parity;
             double* pold = parity ? h->p2 : h->p;
             double* pnew = parity ? h->p : h->p2;
             double* rold = parity ? h->r2 : h->r;
@@ -3141,7 +3159,12 @@ static int solve_impl(psc_hier* h, int form, psc_net* net, const double* b_dev, 
         psc_net* inet = net;
         for (int k = 0; k * per_launch < maxit; k++) {
             if (use_graph) HIPCHK(hipGraphLaunch(gexec, st));
-            else if ((rs = issue_iteration(h, form, inet))) return rs;
+            else {
+                h->t_iter = k * per_launch;
+                rs = issue_iteration(h, form, inet);
+                h->t_iter = -1;
+                if (rs) return rs;
+            }
             HIPCHK(hipEventRecord(h->ring[k % RING], st));
             if (k >= LAG) {
                 HIPCHK(hipEventSynchronize(h->ring[(k - LAG) % RING]));
@@ -3156,9 +3179,10 @@ static int solve_impl(psc_hier* h, int form, psc_net* net, const double* b_dev, 
         }
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
-        timing_collect(h);
         rs = read_ctl(h, &c);
         if (rs) return rs;
+        // the V-cycle closes the iteration in the fused forms and in PCG
+        timing_collect(h, c.iter, (fused || form == 0) ? 1 : 0);
         if (fused) {
             // the last iteration's x update is deferred: x += alpha p_last
             k_final_axpy<<<gv, WG, 0, st>>>(n, h->xs, (c.iter & 1) ? h->p2 : h->p, h->ctl);
@@ -3866,7 +3890,9 @@ int psc_spmv(psc_hier* h, int32_t l, int32_t prec, const void* x, void* y) {
 
 int psc_timing_enable(psc_hier* h, int32_t on) {
     if (!h) return fail(PSC_ERR_ARG, "NULL handle");
-    h->timing = on != 0;
+    if (on < 0 || on > 2) return fail(PSC_ERR_ARG, "timing mode must be 0, 1 or 2");
+    timing_collect(h);
+    h->timing = on;
     return PSC_OK;
 }
 

@@ -729,3 +729,34 @@ def test_vbm_operator_complexity_near_paper():
     rp, c, v = P.poisson7(200)
     h = oracle.Hierarchy(rp, c, v, aggr=1, theta=0.01, prol=1, nu=4)
     assert abs(h.operator_complexity() - ref) <= 0.02
+
+
+def _indefinite_shifted_poisson(n, sigma):
+    # Poisson - sigma I with lambda_min(A) < sigma < lambda_min(A_coarse):
+    # the build succeeds (positive diagonals, SPD coarsest level) but A has a
+    # negative eigenvalue, so CG meets p.Ap <= 0 after a few iterations
+    rp, c, v = P.poisson7(n)
+    v = v.copy()
+    rows = np.repeat(np.arange(n ** 3), np.diff(rp))
+    v[rows == c] -= sigma
+    return rp, c, v
+
+
+@pytest.mark.parametrize("kind", ["pcg", "fcg64", "fcg32"])
+def test_breakdown_returns_last_valid_iterate(kind):
+    n, sigma = 8, 0.40
+    lam_min = 6.0 - 6.0 * np.cos(np.pi / (n + 1))          # closed form, 0.3618
+    assert lam_min < sigma
+    rp, c, v = _indefinite_shifted_poisson(n, sigma)
+    h = oracle.Hierarchy(rp, c, v, coarse_max=20)
+    b = P.rhs_uniform(n ** 3, 1)
+
+    def solve(maxit):
+        if kind == "pcg":
+            return h.pcg(b, rtol=1e-10, maxit=maxit)
+        return h.fcg(b, rtol=1e-10, maxit=maxit, form=0 if kind == "fcg64" else 1)
+    bad = solve(300)
+    assert bad["status"] == oracle.ERR_NOT_SPD and bad["iters"] >= 2
+    last = solve(bad["iters"])
+    assert last["status"] == oracle.NOCONV and last["iters"] == bad["iters"]
+    np.testing.assert_array_equal(bad["x"], last["x"])
