@@ -33,7 +33,7 @@ import time
 METRIC = "time-to-rtol 1e-6 + SpMV/V-cycle HBM GB/s: FP64 vs mixed vs learned"
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
-WEIGHTS = os.path.join(ROOT, "paper_2406_19754_amd", "weights", "net_poisson128.f32")
+WEIGHTS = os.path.join(ROOT, "paper_2406_19754_amd", "weights", "net_poisson128.ckpt")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_poisson384.json")
 
 
@@ -324,7 +324,7 @@ def main():
     x = torch.zeros(N, dtype=torch.float64, device=dev)
     net = None
     if not args.no_learned and os.path.exists(WEIGHTS) and not args.workload.startswith("diffusion"):
-        net = psc.Net(np.fromfile(WEIGHTS, dtype=np.float32))
+        net = psc.Net.load(WEIGHTS)
         net.set_grid((n, n, n))
 
     def run(form):
@@ -556,7 +556,7 @@ def learned(args):
     h = psc.Hierarchy(rp, col, val, build_fp32=True)
     if args.eval_only:
         # the shipped weights, no data collection or training
-        net = psc.Net(np.fromfile(WEIGHTS, dtype=np.float32))
+        net = psc.Net.load(WEIGHTS)
         losses, v0, v1, t_collect, t_train = np.zeros(0), None, None, 0.0, 0.0
     else:
         t0 = time.time()
@@ -571,7 +571,7 @@ def learned(args):
         log(f"trained {len(losses)} steps in {t_train:.1f}s; validation MSE {v0:.4e} -> {v1:.4e}")
         if args.save_weights:
             os.makedirs(os.path.dirname(os.path.abspath(args.save_weights)), exist_ok=True)
-            net.params().tofile(args.save_weights)
+            net.save(args.save_weights)
         del r, z
         torch.cuda.empty_cache()
     net.set_grid((n, n, n))

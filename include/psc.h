@@ -44,6 +44,7 @@ extern "C" {
 #define PSC_ERR_OOM      -5   /* host or device allocation failed */
 #define PSC_ERR_COARSEN  -6   /* coarsening stalled above the coarsest-size limit */
 #define PSC_ERR_STATE    -7   /* handle not in a state that allows the call */
+#define PSC_ERR_IO       -8   /* checkpoint file cannot be opened, read or written, or is not one */
 
 /* ---- precisions ---------------------------------------------------------- */
 #define PSC_FP64 0
@@ -486,6 +487,26 @@ int psc_net_train(psc_net* net, const float* r_dev, const float* z_dev, int32_t 
                   int32_t crop, int32_t margin, const int32_t* order_host, int32_t steps,
                   int32_t batch, float lr, float beta1, float beta2, float eps,
                   float* losses_host);
+
+/*
+ * Checkpoint / resume of a network (the caller owns `path`; the files are the
+ * caller's). The file is little-endian: a 40-byte header
+ *   char magic[8] = "PSCNET01"; uint32 header_bytes = 40, nparams = 7809,
+ *   channels = 16, ksize = 3, flags (bit 0: Adam moments follow), reserved;
+ *   int64 adam_t (optimiser steps taken)
+ * then nparams FP32 master weights in the layout above, then (flag bit 0)
+ * the first and second Adam moment vectors, nparams floats each.
+ * psc_net_save writes the current master weights and Adam state (waits for
+ * the network's pending work first). psc_net_load creates a new handle
+ * bound to `hip_stream` with those weights (the bfloat16 working copy is
+ * derived from them) and restores the Adam state, so psc_net_train resumes
+ * where the saved run stopped. Errors: PSC_ERR_ARG (NULL), PSC_ERR_IO
+ * (open/read/write failure, bad magic, a header that does not match this
+ * network, a truncated file or trailing bytes), PSC_ERR_HIP / PSC_ERR_OOM
+ * from the device; on error *out is NULL and no handle is leaked.
+ */
+int psc_net_save(const psc_net* net, const char* path);
+int psc_net_load(const char* path, void* hip_stream, psc_net** out);
 
 void psc_net_free(psc_net* net);
 

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -813,6 +814,87 @@ int psc_net_train(psc_net* n, const float* r_crops, const float* z_crops, int32_
     (void)hipFree(ids);
     (void)hipFree(ldev);
     return join_out(n);
+}
+
+
+// Checkpoint file: a 40-byte little-endian header, then the FP32 master
+// weights, then (flag bit 0) the two Adam moment vectors, each param-count
+// floats in the order of psc_net_get_params.
+static const char kMagic[8] = {'P', 'S', 'C', 'N', 'E', 'T', '0', '1'};
+struct NetFileHeader {
+    char magic[8];
+    uint32_t header_bytes, nparams, channels, ksize, flags, reserved;
+    int64_t adam_t;
+};
+static_assert(sizeof(NetFileHeader) == 40, "checkpoint header layout");
+
+static bool host_little_endian() {
+    const uint32_t one = 1;
+    unsigned char c;
+    std::memcpy(&c, &one, 1);
+    return c == 1;
+}
+
+int psc_net_save(const psc_net* n, const char* path) {
+    if (!n || !path) return nfail(PSC_ERR_ARG, "NULL argument");
+    if (!host_little_endian()) return nfail(PSC_ERR_IO, "checkpoints are little-endian; host is not");
+    std::vector<float> buf((size_t)3 * NP);
+    NHIPCHK(hipSetDevice(n->device));
+    NHIPCHK(hipStreamSynchronize(n->stream));
+    NHIPCHK(hipMemcpy(buf.data(), n->master, NP * sizeof(float), hipMemcpyDeviceToHost));
+    NHIPCHK(hipMemcpy(buf.data() + NP, n->m, NP * sizeof(float), hipMemcpyDeviceToHost));
+    NHIPCHK(hipMemcpy(buf.data() + 2 * NP, n->v, NP * sizeof(float), hipMemcpyDeviceToHost));
+    NetFileHeader hd{};
+    std::memcpy(hd.magic, kMagic, 8);
+    hd.header_bytes = sizeof(NetFileHeader);
+    hd.nparams = NP;
+    hd.channels = NC;
+    hd.ksize = 3;
+    hd.flags = 1;
+    hd.adam_t = n->adam_t;
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return nfail(PSC_ERR_IO, std::string("cannot open for writing: ") + path);
+    bool ok = std::fwrite(&hd, sizeof hd, 1, f) == 1 && std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return nfail(PSC_ERR_IO, std::string("write failed: ") + path);
+    return PSC_OK;
+}
+
+int psc_net_load(const char* path, void* hip_stream, psc_net** out) {
+    if (!path || !out) return nfail(PSC_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    if (!host_little_endian()) return nfail(PSC_ERR_IO, "checkpoints are little-endian; host is not");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return nfail(PSC_ERR_IO, std::string("cannot open for reading: ") + path);
+    NetFileHeader hd{};
+    std::vector<float> buf((size_t)3 * NP, 0.f);
+    bool ok = std::fread(&hd, sizeof hd, 1, f) == 1;
+    std::string why;
+    if (!ok) why = "short header";
+    else if (std::memcmp(hd.magic, kMagic, 8) != 0) why = "not a network checkpoint (bad magic)";
+    else if (hd.header_bytes != sizeof(NetFileHeader) || hd.nparams != (uint32_t)NP || hd.channels != (uint32_t)NC ||
+             hd.ksize != 3 || (hd.flags & ~1u) != 0 || hd.adam_t < 0)
+        why = "checkpoint header does not match this network (size, channels, kernel or flags)";
+    else {
+        const size_t want = (hd.flags & 1u) ? buf.size() : (size_t)NP;
+        if (std::fread(buf.data(), sizeof(float), want, f) != want) why = "truncated checkpoint";
+        else if (std::fgetc(f) != EOF) why = "trailing bytes after the checkpoint";
+    }
+    std::fclose(f);
+    if (!why.empty()) return nfail(PSC_ERR_IO, why + ": " + path);
+    psc_net* n = nullptr;
+    int st = psc_net_create(buf.data(), hip_stream, &n);
+    if (st) return st;
+    if (hd.flags & 1u) {
+        if (hipMemcpy(n->m, buf.data() + NP, NP * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(n->v, buf.data() + 2 * NP, NP * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+            psc_net_free(n);
+            return nfail(PSC_ERR_HIP, "optimiser state upload failed");
+        }
+        n->adam_t = hd.adam_t;
+    }
+    *out = n;
+    return PSC_OK;
 }
 
 }  // extern "C"

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpsc.so")
 
 OK, NOCONV = 0, 1
-ERR_ARG, ERR_NOT_SPD, ERR_NAN, ERR_HIP, ERR_OOM, ERR_COARSEN, ERR_STATE = -1, -2, -3, -4, -5, -6, -7
+ERR_ARG, ERR_NOT_SPD, ERR_NAN, ERR_HIP, ERR_OOM, ERR_COARSEN, ERR_STATE, ERR_IO = -1, -2, -3, -4, -5, -6, -7, -8
 FP64, FP32 = 0, 1
 TUNE_GRID_MAX, TUNE_FUSED_PCG, TUNE_UNROLL4, TUNE_BUFLOAD, TUNE_SPMV2, TUNE_SPLIT, TUNE_DIA, TUNE_TAIL = 1, 2, 3, 4, 5, 6, 7, 8
 TUNE_DIA_UNIFORM, TUNE_XCD, TUNE_MIXED_SPLIT = 9, 10, 11
@@ -30,7 +30,7 @@ TIMING_NAMES = ["spmv_dot", "cg_update", "pre_smooth_l0", "restrict_l0", "post_s
 
 _STATUS = {OK: "PSC_OK", NOCONV: "PSC_NOCONV", ERR_ARG: "PSC_ERR_ARG", ERR_NOT_SPD: "PSC_ERR_NOT_SPD",
            ERR_NAN: "PSC_ERR_NAN", ERR_HIP: "PSC_ERR_HIP", ERR_OOM: "PSC_ERR_OOM",
-           ERR_COARSEN: "PSC_ERR_COARSEN", ERR_STATE: "PSC_ERR_STATE"}
+           ERR_COARSEN: "PSC_ERR_COARSEN", ERR_STATE: "PSC_ERR_STATE", ERR_IO: "PSC_ERR_IO"}
 
 
 class PscError(RuntimeError):
@@ -99,6 +99,8 @@ def _load():
         "psc_net_loss_grad": ([vp, vp, vp, i32, i32, i32, P(f32), vp], C.c_int),
         "psc_pairs_collect": ([vp, vp, i32, i32, i32, f64, i32, i32, i32, vp, i32, vp, vp, i32, P(i32)], C.c_int),
         "psc_net_train": ([vp, vp, vp, i32, i32, i32, vp, i32, i32, f32, f32, f32, f32, vp], C.c_int),
+        "psc_net_save": ([vp, C.c_char_p], C.c_int),
+        "psc_net_load": ([C.c_char_p, vp, P(vp)], C.c_int),
         "psc_net_free": ([vp], None),
     }
     for name, (args, res) in sig.items():
@@ -283,11 +285,24 @@ class Net:
     def __init__(self, params, stream=None):
         import torch
         self._torch = torch
+        self._h = C.c_void_p()
+        if params is None:      # filled by load()
+            return
         p, pp = _hptr(params, np.float32)
         if p.size != net_param_count():
             raise ValueError(f"expected {net_param_count()} parameters")
-        self._h = C.c_void_p()
         _check(_lib.psc_net_create(pp, C.c_void_p(_stream(stream)), C.byref(self._h)))
+
+    @classmethod
+    def load(cls, path, stream=None):
+        """psc_net_load: a new network from a checkpoint written by save()."""
+        net = cls(None)
+        _check(_lib.psc_net_load(os.fsencode(path), C.c_void_p(_stream(stream)), C.byref(net._h)))
+        return net
+
+    def save(self, path):
+        """psc_net_save: master weights and Adam state to `path`."""
+        _check(_lib.psc_net_save(self._h, os.fsencode(path)))
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:

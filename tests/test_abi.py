@@ -56,3 +56,51 @@ def test_binding_structs_match_the_header_layout():
         size, offs = _c_layout(name, fields)
         assert ctypes.sizeof(cls) == size, name
         assert [getattr(cls, f).offset for f in fields] == offs, name
+
+
+def test_net_load_rejects_bad_files_before_any_device_call(tmp_path):
+    """psc_net_load checks the file on the host first: a missing file, bad
+    magic, a header for another network and a truncated file all return
+    PSC_ERR_IO and a NULL handle (no GPU is touched on these paths)."""
+    import struct
+    from paper_2406_19754_amd import psc
+    L = psc.lib()
+    npar = psc.net_param_count()
+
+    def load(path):
+        h = ctypes.c_void_p(123)
+        st = L.psc_net_load(os.fsencode(str(path)), None, ctypes.byref(h))
+        return st, h.value
+
+    def header(magic=b"PSCNET01", hb=40, np_=npar, ch=16, k=3, flags=1, t=5):
+        return magic + struct.pack("<6Iq", hb, np_, ch, k, flags, 0, t)
+
+    cases = {
+        "missing": None,
+        "magic": header(magic=b"NOTANET!") + bytes(12 * npar),
+        "params": header(np_=npar + 1) + bytes(12 * npar),
+        "channels": header(ch=8) + bytes(12 * npar),
+        "flags": header(flags=2) + bytes(12 * npar),
+        "truncated": header() + bytes(12 * npar - 4),
+        "trailing": header() + bytes(12 * npar + 4),
+        "short": b"PSCNET",
+    }
+    for name, blob in cases.items():
+        path = tmp_path / name
+        if blob is not None:
+            path.write_bytes(blob)
+        st, h = load(path)
+        assert st == psc.ERR_IO, (name, st)
+        assert h is None, name
+        assert L.psc_last_error()
+
+
+def test_shipped_network_checkpoint_header():
+    """The trained 128^3 network ships in the checkpoint format psc_net_load reads."""
+    import struct
+    from paper_2406_19754_amd import psc
+    path = os.path.join(ROOT, "paper_2406_19754_amd", "weights", "net_poisson128.ckpt")
+    blob = open(path, "rb").read()
+    hb, npar, ch, k, flags, _, t = struct.unpack("<6Iq", blob[8:40])
+    assert blob[:8] == b"PSCNET01" and hb == 40 and npar == psc.net_param_count() and ch == 16 and k == 3
+    assert len(blob) == 40 + 4 * npar * (3 if flags & 1 else 1)

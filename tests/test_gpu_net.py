@@ -5,6 +5,8 @@ Both sides round the same operands to bfloat16; the GPU accumulates in FP32
 land on the other side of a bfloat16 rounding boundary. Tolerances: forward
 outputs 1e-2 relative (norm), gradients 3e-2 relative per parameter group.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -183,3 +185,36 @@ def test_learned_fused_unfused_and_switch_off(psc, prec):
     assert abs(res[(1, True)][0]["iters"] - res[(0, True)][0]["iters"]) <= 1
     # scheduled network steps that ran the V-cycle are counted (also after the switch)
     assert res[(1, True)][0]["fallbacks"] >= 1
+
+
+def test_save_load_round_trip_resumes_training(psc, tmp_path):
+    """psc_net_save / psc_net_load: weights and Adam state survive the file;
+    the loaded handle applies identically and its next training steps equal
+    those of the handle that kept running."""
+    p = params(8)
+    rng = np.random.default_rng(9)
+    ncrops, D, margin = 6, 12, 2
+    r = torch.from_numpy(rng.standard_normal((ncrops, D, D, D)).astype(np.float32)).cuda()
+    z = torch.from_numpy(rng.standard_normal((ncrops, D, D, D)).astype(np.float32)).cuda()
+    net = psc.Net(p)
+    net.train(r, z, np.arange(6, dtype=np.int32), steps=3, batch=2, margin=margin, lr=1e-3)
+    path = str(tmp_path / "net.ckpt")
+    net.save(path)
+    assert os.path.getsize(path) == 40 + 3 * 4 * psc.net_param_count()
+    net2 = psc.Net.load(path)
+    np.testing.assert_array_equal(net2.params(), net.params())
+    n = 20
+    rv = torch.from_numpy(rng.standard_normal(n ** 3)).cuda()
+    z1, z2 = torch.empty_like(rv), torch.empty_like(rv)
+    net.apply(rv, z1, (n, n, n))
+    net2.apply(rv, z2, (n, n, n))
+    assert torch.equal(z1, z2)
+    order = np.array([5, 1, 4, 0], np.int32)
+    l1 = net.train(r, z, order, steps=2, batch=2, margin=margin, lr=1e-3)
+    l2 = net2.train(r, z, order, steps=2, batch=2, margin=margin, lr=1e-3)
+    np.testing.assert_array_equal(l1, l2)
+    np.testing.assert_array_equal(net2.params(), net.params())
+    # a fresh handle with the same weights but no Adam state takes a different step
+    net3 = psc.Net(np.fromfile(path, dtype=np.float32, count=psc.net_param_count(), offset=40))
+    net3.train(r, z, order, steps=2, batch=2, margin=margin, lr=1e-3)
+    assert not np.array_equal(net3.params(), net.params())
