@@ -447,6 +447,22 @@ int psc_net_set_params(psc_net* net, const float* params_host);
 int psc_net_apply(psc_net* net, const double* r_dev, double* z_dev, int32_t nx,
                   int32_t ny, int32_t nz);
 
+/*
+ * psc_net_apply without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Same result as psc_net_apply (the same
+ * kernels); its scratch (activations and the norm reduction, 66 bytes per
+ * cell plus 8.5 KB) lives in a fixed array of about 17.3 MB that every device
+ * the library runs on holds until the process ends. Grids above
+ * PSC_NET_NOALLOC_MAX_CELLS cells (64^3) return PSC_ERR_ARG. The handle's own
+ * grid buffers are neither used nor changed. All calls on one device share
+ * that array: calls that overlap on one device (several host threads, or
+ * several streams) race and give wrong results; serialise them.
+ */
+#define PSC_NET_NOALLOC_MAX_CELLS 262144
+int psc_net_apply_noalloc(psc_net* net, const double* r_dev, double* z_dev, int32_t nx,
+                          int32_t ny, int32_t nz);
+
 /* Declare the grid used by psc_fcg_solve (n = nx*ny*nz). */
 int psc_net_set_grid(psc_net* net, int32_t nx, int32_t ny, int32_t nz);
 

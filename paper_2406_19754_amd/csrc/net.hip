@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -816,6 +817,70 @@ int psc_net_train(psc_net* n, const float* r_crops, const float* z_crops, int32_
     return join_out(n);
 }
 
+
+// ---- allocation-free apply ------------------------------------------------
+// psc_net_apply_noalloc keeps its scratch (the ||r||^2 partials and sum, and
+// the three bfloat16 activation fields) in one file-scope device array of
+// fixed size instead of buffers sized per grid. Each device holds its own copy
+// until the process ends; its address is looked up once per device and the
+// kernels receive that address, never the host-side symbol. Layout (bytes):
+//   [0, 16) ||r||^2 | [256, 256 + 8*NA_PARTS) partials | h1 | h2 | u
+// with h1, h2 sized 32 bytes and u 2 bytes per cell of the largest grid.
+constexpr int NA_PARTS = 1024;
+constexpr long long NA_H1 = 256 + 8 * NA_PARTS;
+constexpr long long NA_H2 = NA_H1 + 32ll * PSC_NET_NOALLOC_MAX_CELLS;
+constexpr long long NA_U = NA_H2 + 32ll * PSC_NET_NOALLOC_MAX_CELLS;
+constexpr long long NA_BYTES = NA_U + 2ll * PSC_NET_NOALLOC_MAX_CELLS;
+static_assert(NA_H1 % 256 == 0 && NA_H2 % 256 == 0 && NA_U % 256 == 0, "scratch regions stay 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+constexpr int NA_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch_dev[NA_MAX_DEVICES] = {};
+
+// Device address of `scratch` on `dev` (which must be current), looked up on
+// the first call for that device.
+static int scratch_on(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= NA_MAX_DEVICES) return nfail(PSC_ERR_ARG, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return nfail(PSC_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = (unsigned char*)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return PSC_OK;
+}
+
+int psc_net_apply_noalloc(psc_net* n, const double* r, double* z, int32_t nx, int32_t ny, int32_t nz) {
+    if (!n || !r || !z) return nfail(PSC_ERR_ARG, "NULL argument");
+    if (nx < 1 || ny < 1 || nz < 1) return nfail(PSC_ERR_ARG, "bad grid");
+    const long long N = (long long)nx * ny * nz;
+    if (N > PSC_NET_NOALLOC_MAX_CELLS)
+        return nfail(PSC_ERR_ARG, "grid of " + std::to_string(N) + " cells exceeds the allocation-free maximum of " +
+                                      std::to_string(PSC_NET_NOALLOC_MAX_CELLS) + " cells");
+    NHIPCHK(hipSetDevice(n->device));
+    unsigned char* base = nullptr;
+    int st = scratch_on(n->device, &base);
+    if (st) return st;
+    st = join_in(n);
+    if (st) return st;
+    double* rr = (double*)base;
+    double* part = (double*)(base + 256);
+    bf16r* h1 = (bf16r*)(base + NA_H1);
+    bf16r* h2 = (bf16r*)(base + NA_H2);
+    bf16r* u = (bf16r*)(base + NA_U);
+    k_sumsq<<<NA_PARTS, WG, 0, n->stream>>>(N, r, part);
+    k_sum_partials<<<1, WG, 0, n->stream>>>(part, NA_PARTS, 1.0, rr, nullptr);
+    const Dims d{1, nz, ny, nx};
+    forward(n, n->stream, d, r, nullptr, rr, N, u, h1, h2, nullptr, nullptr, z, nullptr, Gate{nullptr, GATE_NONE});
+    NHIPCHK(hipGetLastError());
+    NHIPCHK(hipStreamSynchronize(n->stream));
+    return join_out(n);
+}
 
 // Checkpoint file: a 40-byte little-endian header, then the FP32 master
 // weights, then (flag bit 0) the two Adam moment vectors, each param-count

@@ -24,6 +24,7 @@ TUNE_DIA_UNIFORM, TUNE_XCD, TUNE_MIXED_SPLIT = 9, 10, 11
 AGGR_MATCHING, AGGR_VBM = 0, 1
 SMOOTH_L1JACOBI, SMOOTH_AINV, SMOOTH_INVK, SMOOTH_CHEB4 = 0, 1, 2, 3
 MAX_LEVELS = 32
+NET_NOALLOC_MAX_CELLS = 262144
 TIMING_KERNELS = 8
 TIMING_NAMES = ["spmv_dot", "cg_update", "pre_smooth_l0", "restrict_l0", "post_smooth_l0",
                 "dir_update", "vcycle", "other_levels"]
@@ -95,6 +96,7 @@ def _load():
         "psc_net_set_params": ([vp, vp], C.c_int),
         "psc_net_apply": ([vp, vp, vp, i32, i32, i32], C.c_int),
         "psc_net_set_grid": ([vp, i32, i32, i32], C.c_int),
+        "psc_net_apply_noalloc": ([vp, vp, vp, i32, i32, i32], C.c_int),
         "psc_net_forward_batch": ([vp, vp, vp, i32, i32], C.c_int),
         "psc_net_loss_grad": ([vp, vp, vp, i32, i32, i32, P(f32), vp], C.c_int),
         "psc_pairs_collect": ([vp, vp, i32, i32, i32, f64, i32, i32, i32, vp, i32, vp, vp, i32, P(i32)], C.c_int),
@@ -328,6 +330,13 @@ class Net:
         nz, ny, nx = dims
         f64 = self._torch.float64
         _check(_lib.psc_net_apply(self._h, _dptr(r, f64), _dptr(z, f64), nx, ny, nz))
+
+    def apply_noalloc(self, r, z, dims):
+        """psc_net_apply_noalloc: the same result without device allocation
+        (grids up to NET_NOALLOC_MAX_CELLS cells)."""
+        nz, ny, nx = dims
+        f64 = self._torch.float64
+        _check(_lib.psc_net_apply_noalloc(self._h, _dptr(r, f64), _dptr(z, f64), nx, ny, nz))
 
     def forward_batch(self, inp, out):
         B, D = inp.shape[0], inp.shape[1]

@@ -1,0 +1,57 @@
+"""psc_net_apply_noalloc (scratch in a fixed device array, no allocation)
+against psc_net_apply through the C ABI: the same kernels on the same
+operands, so the outputs must be bit-identical. Two calls in a row, the
+second on a smaller grid, then the largest grid allowed, then a grid that
+must be refused."""
+import ctypes
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2406_19754_amd import problems as P
+
+
+@pytest.fixture(scope="module")
+def psc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_19754_amd import psc as m
+    return m
+
+
+def _apply(psc, fn, net, r, dims):
+    nz, ny, nx = dims
+    z = torch.full_like(r, float("nan"))
+    st = fn(net._h, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(z.data_ptr()), nx, ny, nz)
+    assert st == psc.OK, psc.lib().psc_last_error()
+    torch.cuda.synchronize()
+    return z
+
+
+def test_noalloc_apply_matches_apply(psc):
+    L = psc.lib()
+    p = (P.net_init(11).astype(np.float64) * 0.7 + 0.03 * np.random.default_rng(12).standard_normal(7809))
+    net = psc.Net(p.astype(np.float32))
+    rng = np.random.default_rng(13)
+    # x sizes 40 and 20 leave ragged 16-wide tiles; the last grid is the maximum
+    for dims in [(33, 36, 40), (9, 17, 20), (64, 64, 64)]:
+        n = int(np.prod(dims))
+        r = torch.from_numpy(rng.standard_normal(n)).cuda()
+        print(f"noalloc apply on grid {dims}", flush=True)
+        z_ref = _apply(psc, L.psc_net_apply, net, r, dims)
+        z_na = _apply(psc, L.psc_net_apply_noalloc, net, r, dims)
+        assert torch.isfinite(z_na).all()
+        assert torch.equal(z_na, z_ref), float((z_na - z_ref).abs().max())
+
+
+def test_noalloc_apply_refuses_grids_above_the_maximum(psc):
+    L = psc.lib()
+    net = psc.Net(P.net_init(3).astype(np.float32))
+    r = torch.zeros(65 * 64 * 64, dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(r)
+    st = L.psc_net_apply_noalloc(net._h, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(z.data_ptr()), 64, 64, 65)
+    assert st == psc.ERR_ARG
+    assert b"exceeds" in L.psc_last_error()
