@@ -533,13 +533,15 @@ __device__ __forceinline__ T dia_row(const Dia<T>& A, long long s, int lane, G g
         const int nd = A.nd;
         const int row = (int)(s * SLICE) + lane;
         const int cmax = (int)A.ncols - 1;
-        const T* vp = A.val + s * (long long)nd * SLICE + lane;
+        const int ks = A.pair ? 2 * SLICE : SLICE;   // diagonal stride
+        const T* vp = A.val + (A.pair ? (s >> 1) * (long long)nd * 2 * SLICE + (s & 1) * SLICE
+                                      : s * (long long)nd * SLICE) + lane;
         T v[8];
         int c[8];
 #pragma unroll
         for (int k = 0; k < 8; k++) {
             if (k < nd) {
-                v[k] = ntload(vp + k * SLICE);
+                v[k] = ntload(vp + k * ks);
                 c[k] = min(max(row + A.uo[k], 0), cmax);
             }
         }
@@ -557,7 +559,10 @@ __device__ __forceinline__ T dia_row(const Dia<T>& A, long long s, int lane, G g
     const int nd = A.start[s + 1] - k0;
     const int row = (int)(s * SLICE) + lane;
     const int cmax = (int)A.ncols - 1;
-    const T* vp = A.val + (long long)k0 * SLICE + lane;
+    // a paired layout is uniform: k0 = s * nd
+    const int ks = A.pair ? 2 * SLICE : SLICE;
+    const T* vp = A.val + (A.pair ? (s >> 1) * (long long)nd * 2 * SLICE + (s & 1) * SLICE
+                                  : (long long)k0 * SLICE) + lane;
     const int* op = A.offs + k0;
     T acc = T(0);
     if (nd <= 8) {
@@ -566,7 +571,7 @@ __device__ __forceinline__ T dia_row(const Dia<T>& A, long long s, int lane, G g
 #pragma unroll
         for (int k = 0; k < 8; k++) {
             if (k < nd) {
-                v[k] = ntload(vp + k * SLICE);
+                v[k] = ntload(vp + k * ks);
                 c[k] = min(max(row + op[k], 0), cmax);
             }
         }
@@ -585,7 +590,7 @@ __device__ __forceinline__ T dia_row(const Dia<T>& A, long long s, int lane, G g
         int c[GB];
 #pragma unroll
         for (int j = 0; j < GB; j++) {
-            v[j] = ntload(vp + (k + j) * SLICE);
+            v[j] = ntload(vp + (k + j) * ks);
             c[j] = min(max(row + op[k + j], 0), cmax);
         }
         T gv[GB];
@@ -595,10 +600,84 @@ __device__ __forceinline__ T dia_row(const Dia<T>& A, long long s, int lane, G g
         for (int j = 0; j < GB; j++) acc += v[j] * gv[j];
     }
     for (; k < nd; k++) {
-        const T v0 = ntload(vp + k * SLICE);
+        const T v0 = ntload(vp + k * ks);
         acc += v0 * g(min(max(row + op[k], 0), cmax));
     }
     return acc;
+}
+
+// ---- two rows per lane on the paired uniform hacked-DIA layout -----------
+// A wavefront takes one 128-row block S and lane l its rows 2l and 2l+1:
+// every value load and, inside the matrix, every gather reads two
+// consecutive elements with one 8- or 16-byte access. gp(c) returns
+// {g(c), g(c+1)}; g1(c) one element (blocks whose gathers leave [0, ncols),
+// where the index is clamped and the value is zero).
+template <typename T>
+struct V2;
+template <>
+struct V2<double> {
+    typedef double u __attribute__((ext_vector_type(2), aligned(8)));    // any 8-byte address
+    typedef double a __attribute__((ext_vector_type(2), aligned(16)));   // values of the layout
+};
+template <>
+struct V2<float> {
+    typedef float u __attribute__((ext_vector_type(2), aligned(4)));
+    typedef float a __attribute__((ext_vector_type(2), aligned(8)));
+};
+template <typename T>
+using v2u = typename V2<T>::u;
+template <typename T>
+using v2a = typename V2<T>::a;
+
+template <typename T>
+__device__ __forceinline__ v2u<T> ld2(const T* p) { return *(const v2u<T>*)p; }
+template <typename T>
+__device__ __forceinline__ void st2(T* p, T a, T b) { *(v2u<T>*)p = v2u<T>{a, b}; }
+
+template <typename T>
+__device__ __forceinline__ bool dia_pair_on(const Dia<T>& A) { return A.pair && A.nd > 0; }
+
+// number of 128-row blocks of a paired layout
+template <typename T>
+__device__ __forceinline__ long long dia_blocks(const Dia<T>& A) { return (A.nslices + 1) >> 1; }
+
+template <typename T, typename GP, typename G1>
+__device__ __forceinline__ void dia_pair_rows(const Dia<T>& A, long long S, int lane, GP gp, G1 g1, T& a0, T& a1) {
+    const int nd = A.nd;
+    const long long r0 = S * (2 * SLICE) + 2 * lane;
+    const v2a<T>* vp = (const v2a<T>*)(A.val + S * (long long)nd * 2 * SLICE) + lane;
+    v2a<T> v[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+        if (k < nd) v[k] = ntload(vp + k * SLICE);
+    const long long b0 = S * (2 * SLICE);
+    // wave-uniform: every row of the block exists and every gather is in range
+    const bool inner = b0 + A.uo[0] >= 0 && b0 + 2 * SLICE - 1 + A.uo[nd - 1] < A.ncols &&
+                       b0 + 2 * SLICE <= A.nrows;
+    T s0 = T(0), s1 = T(0);
+    if (inner) {
+        v2u<T> g[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (k < nd) g[k] = gp(r0 + A.uo[k]);
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (k < nd) {
+                s0 += v[k].x * g[k].x;
+                s1 += v[k].y * g[k].y;
+            }
+    } else {
+        const long long cmax = A.ncols - 1;
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (k < nd) {
+                const long long c0 = min(max(r0 + A.uo[k], 0ll), cmax), c1 = min(max(r0 + 1 + A.uo[k], 0ll), cmax);
+                s0 += v[k].x * g1((int)c0);
+                s1 += v[k].y * g1((int)c1);
+            }
+    }
+    a0 = s0;
+    a1 = s1;
 }
 
 // Row sum of either storage format; GB is the batch of the wide-row path.
@@ -622,8 +701,21 @@ __global__ __launch_bounds__(WG) void k_spmv(M A, const typename M::value_type* 
     using T = typename M::value_type;
     if (gate_skip(g)) return;
     long long lo, hi;
-    chunk_range(A.nslices, lo, hi);
     const int lane = threadIdx.x & 63, w = wave_id();
+    if constexpr (std::is_same<M, Dia<T>>::value) {
+        if (dia_pair_on(A)) {
+            chunk_range(dia_blocks(A), lo, hi);
+            for (long long S = lo + w; S < hi; S += WG / 64) {
+                T a0, a1;
+                dia_pair_rows(A, S, lane, [&](long long c) { return ld2(x + c); }, [&](int c) { return x[c]; }, a0, a1);
+                const long long row = S * (2 * SLICE) + 2 * lane;
+                if (row + 1 < A.nrows) st2(y + row, a0, a1);
+                else if (row < A.nrows) y[row] = a0;
+            }
+            return;
+        }
+    }
+    chunk_range(A.nslices, lo, hi);
     const BVec<T> bx = bvec(x, A.ncols);
     for (long long s = lo + w; s < hi; s += WG / 64) {
         T acc;
@@ -774,10 +866,44 @@ __global__ __launch_bounds__(WG) void k_spmv_pfuse(M A, const double* __restrict
     if (skip_red(R)) return;
     const double beta = R.ctl->beta, alpha_prev = R.ctl->alpha;
     long long lo, hi;
-    chunk_range(A.nslices, lo, hi);
     const int lane = threadIdx.x & 63, w = wave_id();
-    const BVec<double> bz = bvec(z, A.ncols), bp = bvec(pold, A.ncols);
     double s0 = 0.0;
+    if constexpr (std::is_same<M, Dia<double>>::value) {
+        if (dia_pair_on(A)) {
+            chunk_range(dia_blocks(A), lo, hi);
+            for (long long S = lo + w; S < hi; S += WG / 64) {
+                double a0, a1;
+                dia_pair_rows(
+                    A, S, lane,
+                    [&](long long c) {
+                        const v2u<double> pp = ld2(pold + c), zz = ld2(z + c);
+                        return v2u<double>{fma(beta, pp.x, zz.x), fma(beta, pp.y, zz.y)};
+                    },
+                    [&](int c) { return fma(beta, pold[c], z[c]); }, a0, a1);
+                const long long row = S * (2 * SLICE) + 2 * lane;
+                if (row + 1 < A.nrows) {
+                    const v2u<double> po = ld2(pold + row), zz = ld2(z + row), xx = ld2((const double*)x + row);
+                    const double p0 = fma(beta, po.x, zz.x), p1 = fma(beta, po.y, zz.y);
+                    st2(pnew + row, p0, p1);
+                    st2(q + row, a0, a1);
+                    st2(x + row, fma(alpha_prev, po.x, xx.x), fma(alpha_prev, po.y, xx.y));
+                    s0 += p0 * a0;
+                    s0 += p1 * a1;
+                } else if (row < A.nrows) {
+                    const double po = pold[row];
+                    const double pn = fma(beta, po, z[row]);
+                    pnew[row] = pn;
+                    q[row] = a0;
+                    x[row] = fma(alpha_prev, po, x[row]);
+                    s0 += pn * a0;
+                }
+            }
+            block_partial(s0, 0.0, R.part);
+            return;
+        }
+    }
+    chunk_range(A.nslices, lo, hi);
+    const BVec<double> bz = bvec(z, A.ncols), bp = bvec(pold, A.ncols);
     for (long long s = lo + w; s < hi; s += WG / 64) {
         double acc;
         if constexpr (BUF) acc = ell_row_buf(A, s, lane, [&](int c) { return fma(beta, bp[c], bz[c]); });
@@ -839,10 +965,48 @@ __global__ __launch_bounds__(WG) void k_spmv_pfuse_fcg(M A, const double* __rest
     if (skip_red(R)) return;
     const double nb = R.ctl->have_prev ? -R.ctl->beta : 0.0, alpha_prev = R.ctl->alpha;
     long long lo, hi;
-    chunk_range(A.nslices, lo, hi);
     const int lane = threadIdx.x & 63, w = wave_id();
-    const BVec<double> bz = bvec(z, A.ncols), bp = bvec(pold, A.ncols);
     double s0 = 0.0, s1 = 0.0;
+    if constexpr (std::is_same<M, Dia<double>>::value) {
+        if (dia_pair_on(A)) {
+            chunk_range(dia_blocks(A), lo, hi);
+            for (long long S = lo + w; S < hi; S += WG / 64) {
+                double a0, a1;
+                dia_pair_rows(
+                    A, S, lane,
+                    [&](long long c) {
+                        const v2u<double> pp = ld2(pold + c), zz = ld2(z + c);
+                        return v2u<double>{fma(nb, pp.x, zz.x), fma(nb, pp.y, zz.y)};
+                    },
+                    [&](int c) { return fma(nb, pold[c], z[c]); }, a0, a1);
+                const long long row = S * (2 * SLICE) + 2 * lane;
+                if (row + 1 < A.nrows) {
+                    const v2u<double> po = ld2(pold + row), zz = ld2(z + row), xx = ld2((const double*)x + row),
+                                      rr = ld2(rold + row);
+                    const double p0 = fma(nb, po.x, zz.x), p1 = fma(nb, po.y, zz.y);
+                    st2(pnew + row, p0, p1);
+                    st2(q + row, a0, a1);
+                    st2(x + row, fma(alpha_prev, po.x, xx.x), fma(alpha_prev, po.y, xx.y));
+                    s0 += p0 * a0;
+                    s0 += p1 * a1;
+                    s1 += p0 * rr.x;
+                    s1 += p1 * rr.y;
+                } else if (row < A.nrows) {
+                    const double po = pold[row];
+                    const double pn = fma(nb, po, z[row]);
+                    pnew[row] = pn;
+                    q[row] = a0;
+                    x[row] = fma(alpha_prev, po, x[row]);
+                    s0 += pn * a0;
+                    s1 += pn * rold[row];
+                }
+            }
+            block_partial(s0, s1, R.part);
+            return;
+        }
+    }
+    chunk_range(A.nslices, lo, hi);
+    const BVec<double> bz = bvec(z, A.ncols), bp = bvec(pold, A.ncols);
     for (long long s = lo + w; s < hi; s += WG / 64) {
         double acc;
         if constexpr (BUF) acc = ell_row_buf(A, s, lane, [&](int c) { return fma(nb, bp[c], bz[c]); });
@@ -1052,8 +1216,31 @@ __global__ __launch_bounds__(WG) void k_pre_s(M AM, const TB* __restrict__ b, ty
     using T = typename M::value_type;
     if (gate_skip(g)) return;
     long long lo, hi;
-    chunk_range(AM.nslices, lo, hi);
     const int lane = threadIdx.x & 63, w = wave_id();
+    if constexpr (std::is_same<M, Dia<T>>::value) {
+        if (dia_pair_on(AM)) {
+            chunk_range(dia_blocks(AM), lo, hi);
+            for (long long S = lo + w; S < hi; S += WG / 64) {
+                T a0, a1;
+                dia_pair_rows(
+                    AM, S, lane,
+                    [&](long long c) {
+                        const v2u<TB> bb = ld2(b + c);
+                        return v2u<T>{(T)bb.x, (T)bb.y};
+                    },
+                    [&](int c) { return (T)b[c]; }, a0, a1);
+                const long long row = S * (2 * SLICE) + 2 * lane;
+                if (row + 1 < AM.nrows) {
+                    const v2u<TB> bb = ld2(b + row);
+                    st2(r + row, (T)bb.x - a0, (T)bb.y - a1);
+                } else if (row < AM.nrows) {
+                    r[row] = (T)b[row] - a0;
+                }
+            }
+            return;
+        }
+    }
+    chunk_range(AM.nslices, lo, hi);
     for (long long s = lo + w; s < hi; s += WG / 64) {
         const T acc = mat_row<GB>(AM, s, lane, [&](int c) { return (T)b[c]; });
         const long long row = s * SLICE + lane;
@@ -1071,9 +1258,40 @@ __global__ __launch_bounds__(WG) void k_update_pre_s(M AM, const double* __restr
     if (skip_red(R)) return;
     const double nalpha = -R.ctl->alpha;
     long long lo, hi;
-    chunk_range(AM.nslices, lo, hi);
     const int lane = threadIdx.x & 63, w = wave_id();
     double s0 = 0.0;
+    if constexpr (std::is_same<M, Dia<T>>::value) {
+        if (dia_pair_on(AM)) {
+            chunk_range(dia_blocks(AM), lo, hi);
+            for (long long S = lo + w; S < hi; S += WG / 64) {
+                T a0, a1;
+                dia_pair_rows(
+                    AM, S, lane,
+                    [&](long long c) {
+                        const v2u<double> qq = ld2(q + c), rr = ld2(rold + c);
+                        return v2u<T>{(T)fma(nalpha, qq.x, rr.x), (T)fma(nalpha, qq.y, rr.y)};
+                    },
+                    [&](int c) { return (T)fma(nalpha, q[c], rold[c]); }, a0, a1);
+                const long long row = S * (2 * SLICE) + 2 * lane;
+                if (row + 1 < AM.nrows) {
+                    const v2u<double> qq = ld2(q + row), rr = ld2(rold + row);
+                    const double n0 = fma(nalpha, qq.x, rr.x), n1 = fma(nalpha, qq.y, rr.y);
+                    st2(rnew + row, n0, n1);
+                    st2(r0 + row, (T)n0 - a0, (T)n1 - a1);
+                    s0 += n0 * n0;
+                    s0 += n1 * n1;
+                } else if (row < AM.nrows) {
+                    const double rn = fma(nalpha, q[row], rold[row]);
+                    rnew[row] = rn;
+                    r0[row] = (T)rn - a0;
+                    s0 += rn * rn;
+                }
+            }
+            block_partial(s0, 0.0, R.part);
+            return;
+        }
+    }
+    chunk_range(AM.nslices, lo, hi);
     for (long long s = lo + w; s < hi; s += WG / 64) {
         const T acc = mat_row(AM, s, lane, [&](int c) { return (T)fma(nalpha, q[c], rold[c]); });
         const long long row = s * SLICE + lane;
@@ -1671,11 +1889,13 @@ struct DevDia {
     int nd = 0;                            // uniform offsets in use (0: per-slice offsets)
     int nd_u = 0;                          // uniform offset count of the layout (0: not uniform)
     int uo[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int pair = 0;                          // paired 128-row layout (every uniform layout)
     template <typename T>
     Dia<T> make(const T* v) const {
         Dia<T> d{start, offs, v, nrows, nslices, ncols};
         d.nd = nd;
         for (int k = 0; k < 8; k++) d.uo[k] = uo[k];
+        d.pair = pair;
         return d;
     }
     Dia<double> view(const double* v) const { return make<double>(v); }
@@ -1916,15 +2136,16 @@ static int upload_ell(psc_hier* h, DevEll<double>& E, int64_t nrows, int64_t nco
 // the slots the build gave them, hacked ELL (entry q of the row at
 // off[s] + 64 q + lane) and, when the level has one, hacked DIA (slot
 // (start[s] + k) 64 + lane, k the slice's diagonal of the entry's column),
-// with A M^-1 (a_ij minv_j) and the FP32 copies formed on the way. Padding
-// and empty diagonal slots keep the zeros the build wrote.
+// with A M^-1 (a_ij minv_j) and the FP32 copies formed on the way (a paired
+// layout places slice s at (s >> 1) nd 128 + (s & 1) 64 with diagonal
+// stride 128). Padding and empty diagonal slots keep the zeros the build wrote.
 __global__ void k_refresh_values(long long n, const int32_t* __restrict__ rp, const double* __restrict__ v,
                                  const double* __restrict__ mv, const long long* __restrict__ off,
                                  const int* __restrict__ col, double* __restrict__ val, float* __restrict__ val32,
                                  double* __restrict__ am, float* __restrict__ am32, const int* __restrict__ dstart,
                                  const int* __restrict__ doffs, double* __restrict__ dval,
                                  float* __restrict__ dval32, double* __restrict__ damd,
-                                 float* __restrict__ damd32) {
+                                 float* __restrict__ damd32, int dpair) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const long long s = i >> 6;
@@ -1955,7 +2176,10 @@ __global__ void k_refresh_values(long long n, const int32_t* __restrict__ rp, co
             }
             const int k = lo;
             if (k < k1 && doffs[k] == d) {
-                const long long ds = (long long)k * SLICE + lane;
+                // paired layout: slice s is half (s & 1) of block s >> 1
+                const long long ds = dpair ? (s >> 1) * (long long)(k1 - k0) * 2 * SLICE + (k - k0) * 2 * SLICE +
+                                                 (s & 1) * SLICE + lane
+                                           : (long long)k * SLICE + lane;
                 dval[ds] = x;
                 if (dval32) dval32[ds] = (float)x;
                 if (damd) {
@@ -2005,7 +2229,7 @@ static int refresh_values(psc_hier* h, DevEll<double>& E, const DevDia* G, int64
     k_refresh_values<<<(unsigned)blocks, WG, 0, h->stream>>>(
         n, drp, dv, dm, E.off, E.col, E.val, E.val32, mv ? am : nullptr, mv ? am32 : nullptr,
         dia ? G->start : nullptr, dia ? G->offs : nullptr, dia ? G->val : nullptr, dia ? G->val32 : nullptr,
-        (dia && mv) ? amd : nullptr, (dia && mv) ? amd32 : nullptr);
+        (dia && mv) ? amd : nullptr, (dia && mv) ? amd32 : nullptr, dia ? G->pair : 0);
     HIPCHK(hipGetLastError());
     // the staging buffer and the host arrays are reused or released next
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -3371,6 +3595,10 @@ static int upload_levels(psc_hier* h) {
                 G.nd_u = (int)duo.size();
                 G.nd = h->dia_uniform ? G.nd_u : 0;
                 for (size_t k = 0; k < duo.size() && k < 8; k++) G.uo[k] = duo[k];
+                // uniform layouts are stored in 128-row blocks (an odd last
+                // slice gets an empty partner)
+                G.pair = G.nd_u > 0 ? 1 : 0;
+                if (G.pair && (G.nslices & 1)) G.slots += (long long)G.nd_u * SLICE;
                 if ((st = upload(h, &G.start, dstart.data(), dstart.size()))) return st;
                 if ((st = upload(h, &G.offs, doffs.data(), doffs.size()))) return st;
                 const size_t slots = (size_t)G.slots;

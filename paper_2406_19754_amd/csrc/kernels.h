@@ -66,6 +66,12 @@ struct Ell {
 // Uniform variant (nd > 0): every slice holds the same nd <= 8 diagonals, at
 // the offsets uo[0..nd) carried in the kernel argument itself (start[s] =
 // s*nd still holds), so a slice needs no metadata load before its gathers.
+//
+// Paired layout (pair = 1, every uniform layout): the slices are stored two
+// by two as blocks of 128 rows, block S holding diagonal k of its rows r at
+// val[S*nd*128 + k*128 + r], so that one lane can read two consecutive rows
+// with one 16-byte load; slice s of 64 rows starts at (s>>1)*nd*128 +
+// (s&1)*64 with a diagonal stride of 128.
 template <typename T>
 struct Dia {
     using value_type = T;
@@ -77,6 +83,7 @@ struct Dia {
     long long ncols;
     int nd = 0;
     int uo[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int pair = 0;
 };
 
 }  // namespace psc

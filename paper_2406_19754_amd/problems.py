@@ -153,6 +153,15 @@ def rhs_from_solution(rowptr, col, val, x) -> np.ndarray:
     return A @ np.asarray(x, dtype=np.float64)
 
 
+def projection_signs(N: int, j: int) -> np.ndarray:
+    """The j-th random +-1 test vector of length N (``default_rng(50000 + j)``).
+
+    Comparison harness only: for a difference d, (w.d)^2 has mean |d|^2 over
+    such w, so a few projections of a long vector stand in for its norm
+    without storing it."""
+    return np.random.default_rng(50000 + j).integers(0, 2, N, dtype=np.int8).astype(np.float64) * 2.0 - 1.0
+
+
 def rhs_uniform(N: int, seed: int) -> np.ndarray:
     """Right-hand side with entries U[-1,1) from ``default_rng(seed)``."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, N)

@@ -1,8 +1,23 @@
-"""Full-size parity (256^3 Poisson, the benchmark's workload and launch
-configuration) against reference values the CPU oracle wrote
-(tests/golden/make_poisson256.py): bit-identical hierarchy (hashes of every
-level's aggregate map and values), sampled SpMV rows, a sampled V-cycle,
-the PCG iteration count and sampled solution entries."""
+"""Full-size parity against reference values the CPU oracle wrote
+(tests/golden/make_golden.py), in the launch configuration the benchmark
+times (device setup, captured iterations):
+
+  poisson256    3D Poisson 256^3, FP64 PCG
+  diffusion256  lognormal diffusion 256^3 (a_z = 1), FP64 PCG and FCG(1)
+                with the FP32 V-cycle
+  poisson384    3D Poisson 384^3 (the benchmark's workload), FP64 PCG
+
+Checked: bit-identical hierarchy (hash of every level's aggregate map and
+values), a sampled V-cycle, iteration counts within one, and the solution
+at equal iteration count -- when the GPU stops one iteration earlier or
+later than the oracle, the GPU solve is re-run with maxit set to the smaller
+count and compared with the oracle's iterate after that many steps -- on
+2048 sampled entries and through 8 random +-1 projections of the whole
+vector (their mean square is an unbiased estimate of |x_gpu - x_orc|^2).
+Tolerance 1e-8 relative for both forms (FP64 iterates agree to about 1e-14;
+the FP32 V-cycles of the two sides differ by float rounding, about 1e-7 per
+application, which moved the FCG solution by about 1e-10 in measurements).
+"""
 import hashlib
 import json
 import os
@@ -15,23 +30,36 @@ pytestmark = pytest.mark.gpu
 
 from paper_2406_19754_amd import problems as P
 
-GOLD = os.path.join(os.path.dirname(__file__), "golden", "poisson256_oracle.json")
+HERE = os.path.join(os.path.dirname(__file__), "golden")
+WORKLOADS = ["poisson256", "diffusion256", "poisson384"]
 
 
-@pytest.fixture(scope="module")
-def setup():
+def _problem(name, n):
+    if name.startswith("poisson"):
+        return P.poisson7(n)
+    return P.diffusion7(n, seed=0, sigma=1.5, az=1.0)
+
+
+@pytest.fixture(scope="module", params=WORKLOADS)
+def setup(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2406_19754_amd import psc
-    g = json.load(open(GOLD))
-    n = 256
-    rp, col, val = P.poisson7(n)
+    name = request.param
+    g = json.load(open(os.path.join(HERE, f"{name}_oracle.json")))
+    n = g["n"]
+    rp, col, val = _problem(name, n)
+    print(f"\n[full-size parity] {name}: building the hierarchy", flush=True)
     h = psc.Hierarchy(rp, col, val, build_fp32=True)
-    return psc, g, n, (rp, col, val), h
+    N = n ** 3
+    b = torch.from_numpy(P.rhs_from_solution(rp, col, val, P.x_true(N, 0))).cuda()
+    yield psc, name, g, n, (rp, col, val), h, b
+    h.close()
+    torch.cuda.empty_cache()
 
 
 def test_hierarchy_bit_identical(setup):
-    psc, g, n, _, h = setup
+    psc, name, g, n, _, h, _ = setup
     inf = h.info()
     assert inf["rows"] == [L["rows"] for L in g["levels"]]
     assert inf["nnz"] == [L["nnz"] for L in g["levels"]]
@@ -43,24 +71,23 @@ def test_hierarchy_bit_identical(setup):
 
 
 def test_spmv_sampled_rows(setup):
-    psc, g, n, (rp, col, val), h = setup
+    psc, name, g, n, (rp, col, val), h, _ = setup
     N = n ** 3
     x = np.random.default_rng(5).standard_normal(N)
     y = torch.empty(N, dtype=torch.float64, device="cuda")
     h.spmv(torch.from_numpy(x).cuda(), y)
     yg = y.cpu().numpy()
     rows = np.random.default_rng(6).choice(N, 4096, replace=False)
-    rows = np.concatenate([rows, [0, N - 1, n - 1, n * n - 1]])
+    rows = np.concatenate([rows, [0, N - 1, n - 1, n * n - 1, N - n * n]])
     ref = np.array([sum(val[k] * x[col[k]] for k in range(rp[i], rp[i + 1])) for i in rows])
     assert np.abs(yg[rows] - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
 def test_vcycle_sampled(setup):
-    psc, g, n, _, h = setup
+    psc, name, g, n, _, h, _ = setup
     N = n ** 3
-    r = P.rhs_uniform(N, 7)
     z = torch.empty(N, dtype=torch.float64, device="cuda")
-    h.vcycle(torch.from_numpy(r).cuda(), z)
+    h.vcycle(torch.from_numpy(P.rhs_uniform(N, 7)).cuda(), z)
     zg = z.cpu().numpy()
     idx = np.array(g["sample_idx"])
     ref = np.array(g["vcycle_sample"])
@@ -68,22 +95,57 @@ def test_vcycle_sampled(setup):
     assert abs(np.linalg.norm(zg) - g["vcycle_norm"]) <= 1e-12 * g["vcycle_norm"]
 
 
-def test_pcg_and_mixed_full_size(setup):
-    psc, g, n, (rp, col, val), h = setup
-    N = n ** 3
-    b = torch.from_numpy(P.rhs_from_solution(rp, col, val, P.x_true(N, 0))).cuda()
+def _compare_at(x, ref, idx, N, tol, what):
+    xs = x[idx]
+    rs = np.array(ref["sample"])
+    assert np.linalg.norm(xs - rs) <= tol * np.linalg.norm(rs), what
+    assert abs(np.linalg.norm(x) - ref["norm"]) <= tol * ref["norm"], what
+    d2 = [(P.projection_signs(N, j) @ x - p) ** 2 for j, p in enumerate(ref["proj"])]
+    est = float(np.sqrt(np.mean(d2)))
+    assert est <= tol * ref["norm"], (what, est / ref["norm"])
+    return est / ref["norm"]
+
+
+def _solve_and_compare(psc, h, b, fam, run, idx, N, what):
     x = torch.zeros(N, dtype=torch.float64, device="cuda")
-    res = h.pcg(b, x)
-    assert res["status"] == psc.OK and res["relres"] <= 1e-6
-    assert abs(res["iters"] - g["pcg_iters"]) <= 1
+    res = run(x, 1e-6, 500)
+    assert res["status"] == psc.OK and res["relres"] <= 1e-6, (what, res)
+    o = fam["iters"]
+    assert abs(res["iters"] - o) <= 1, (what, res["iters"], o)
+    k = min(res["iters"], o)
+    if k != res["iters"]:
+        x.zero_()
+        r2 = run(x, 1e-30, k)
+        assert r2["iters"] == k, (what, r2)
+    return _compare_at(x.cpu().numpy(), fam["at"][str(k)], idx, N, 1e-8, what)
+
+
+def test_pcg_full_size(setup):
+    psc, name, g, n, _, h, b = setup
+    N = n ** 3
     idx = np.array(g["sample_idx"])
-    ref = np.array(g["x_sample"])
-    if res["iters"] == g["pcg_iters"]:
-        xs = x.cpu().numpy()[idx]
-        assert np.linalg.norm(xs - ref) <= 1e-8 * np.linalg.norm(ref)
-    x64 = x.clone()
-    x.zero_()
+    err = _solve_and_compare(psc, h, b, g["pcg"], lambda x, rtol, maxit: h.pcg(b, x, rtol=rtol, maxit=maxit),
+                             idx, N, f"{name} FP64 PCG")
+    print(f"[full-size parity] {name} FP64 PCG: |x_gpu - x_orc|/|x_orc| ~ {err:.1e}", flush=True)
+
+
+def test_mixed_full_size(setup):
+    psc, name, g, n, _, h, b = setup
+    N = n ** 3
+    if "fcg32" in g:
+        idx = np.array(g["sample_idx"])
+        err = _solve_and_compare(
+            psc, h, b, g["fcg32"],
+            lambda x, rtol, maxit: h.fcg(b, x, rtol=rtol, maxit=maxit, prec=psc.FP32), idx, N,
+            f"{name} FCG with the FP32 V-cycle")
+        print(f"[full-size parity] {name} mixed FCG: |x_gpu - x_orc|/|x_orc| ~ {err:.1e}", flush=True)
+        return
+    # no oracle mixed run stored: the FP32-V-cycle solve reaches rtol and stays
+    # close to the GPU's own FP64 solution
+    x64 = torch.zeros(N, dtype=torch.float64, device="cuda")
+    r64 = h.pcg(b, x64)
+    x = torch.zeros_like(x64)
     m = h.fcg(b, x, prec=psc.FP32)
     assert m["status"] == psc.OK and m["relres"] <= 1e-6
-    assert m["iters"] <= res["iters"] + 3
+    assert m["iters"] <= r64["iters"] + 3
     assert torch.linalg.norm(x - x64) <= 1e-4 * torch.linalg.norm(x64)
