@@ -463,6 +463,20 @@ int psc_net_apply(psc_net* net, const double* r_dev, double* z_dev, int32_t nx,
 int psc_net_apply_noalloc(psc_net* net, const double* r_dev, double* z_dev, int32_t nx,
                           int32_t ny, int32_t nz);
 
+/*
+ * The comparison arm of the learned form: a network handle whose "network"
+ * is one l1-Jacobi sweep from zero on the finest level, z = M_0^-1 r with
+ * M_0 = diag(a_ii + sum_{j != i} |a_ij|) (Section "GPU enabled smoothers"),
+ * taken in psc_fcg_solve's schedule exactly where the network would be (same
+ * z.r > 0 test, fallback and switch-off rules). The handle copies M_0^-1 from
+ * h (h may be freed afterwards) and acts on vectors of h's size only;
+ * psc_net_apply and psc_net_apply_noalloc give z = M_0^-1 r; calls that need
+ * weights (get/set params, training, save) return PSC_ERR_STATE. Release with
+ * psc_net_free. Errors: PSC_ERR_ARG (NULL), PSC_ERR_STATE (h holds no
+ * finest-level diagonal), PSC_ERR_OOM, PSC_ERR_HIP.
+ */
+int psc_net_create_l1jacobi(const psc_hier* h, void* hip_stream, psc_net** out);
+
 /* Declare the grid used by psc_fcg_solve (n = nx*ny*nz). */
 int psc_net_set_grid(psc_net* net, int32_t nx, int32_t ny, int32_t nz);
 

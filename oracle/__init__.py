@@ -294,8 +294,13 @@ class Hierarchy:
             out["beta"] = hist[1:2 * it.value:2]
         return out
 
-    def fcg(self, b, x0=None, rtol=1e-6, maxit=1000, form=0, params=None, dims=None):
+    def fcg(self, b, x0=None, rtol=1e-6, maxit=1000, form=0, params=None, dims=None, alt_jacobi=False):
+        """FCG(1); form 0/1: FP64/FP32 V-cycle. params: the learned form's
+        network; alt_jacobi: the same schedule with z = M_0^-1 r in place of
+        the network (params unused)."""
         b = _f64(b)
+        if alt_jacobi:
+            form, params = form | 4, None
         x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
         it, rr, fb, ne = C.c_int(), C.c_double(), C.c_int(), C.c_int()
         nx = ny = nz = 0

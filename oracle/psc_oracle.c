@@ -1924,7 +1924,11 @@ void orc_net_apply(const double *params, int nx, int ny, int nz, const double *r
  * network step leaves ||r_new|| > 0.9 ||r_old|| (stagnation), or when two
  * network steps in a row fail z.r > 0. *fallbacks counts scheduled network
  * steps that ran the V-cycle instead, *net_evals the network applications.
+ * form | ORC_ALT_JACOBI (comparison arm of the learned form, params unused):
+ * the same schedule and rules with one l1-Jacobi sweep from zero on level 0,
+ * z = M_0^-1 r, in place of the network.
  */
+#define ORC_ALT_JACOBI 4
 int orc_fcg(const orc_hier *h, int form, const double *params, int nx, int ny, int nz,
             const double *b, double *x, double rtol, int maxit, int *iters, double *relres,
             int *fallbacks, int *net_evals) {
@@ -1936,6 +1940,9 @@ int orc_fcg(const orc_hier *h, int form, const double *params, int nx, int ny, i
     if (net_evals) *net_evals = 0;
     if (isnan(nb) || isinf(nb)) return ORC_ERR_NAN;
     if (nb == 0.0) { for (int i = 0; i < n; i++) x[i] = 0.0; *relres = 0.0; return ORC_OK; }
+    const int alt_jacobi = (form & ORC_ALT_JACOBI) != 0;
+    form &= 3;
+    if (alt_jacobi) params = NULL;
     if (params && (size_t)nx * ny * nz != (size_t)n) return ORC_ERR_ARG;
     double *r = malloc(sizeof(double) * (size_t)n), *z = malloc(sizeof(double) * (size_t)n);
     double *p = malloc(sizeof(double) * (size_t)n), *q = malloc(sizeof(double) * (size_t)n);
@@ -1943,14 +1950,19 @@ int orc_fcg(const orc_hier *h, int form, const double *params, int nx, int ny, i
     orc_spmv(n, L->A.rp, L->A.ci, L->A.v, x, q);
     ORC_ROWS
     for (int i = 0; i < n; i++) r[i] = b[i] - q[i];
-    int st = ORC_NOCONV, k = 0, have_prev = 0, net_on = params != NULL, net_fails = 0;
+    const int learned = params != NULL || alt_jacobi;
+    int st = ORC_NOCONV, k = 0, have_prev = 0, net_on = learned, net_fails = 0;
     double pqp = 0.0;
     if (sqrt(dot(n, r, r)) <= rtol * nb) st = ORC_OK;
     while (st == ORC_NOCONV && k < maxit) {
         int use_net = net_on && (k % 2 == 1);
         int vform = form == 1 ? ORC_PREC_VCYCLE32 : ORC_PREC_VCYCLE;
         if (use_net) {
-            orc_net_apply(params, nx, ny, nz, r, z);
+            if (alt_jacobi) {
+                for (int i = 0; i < n; i++) z[i] = L->minv[i] * r[i];
+            } else {
+                orc_net_apply(params, nx, ny, nz, r, z);
+            }
             if (net_evals) (*net_evals)++;
             if (!(dot(n, z, r) > 0.0)) {
                 apply_prec(h, vform, r, z);
@@ -1961,7 +1973,7 @@ int orc_fcg(const orc_hier *h, int form, const double *params, int nx, int ny, i
                 net_fails = 0;
             }
         } else {
-            if (params && !net_on && k % 2 == 1 && fallbacks) (*fallbacks)++;
+            if (learned && !net_on && k % 2 == 1 && fallbacks) (*fallbacks)++;
             apply_prec(h, vform, r, z);
         }
         if (have_prev) {

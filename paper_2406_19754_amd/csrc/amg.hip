@@ -4074,6 +4074,15 @@ int psc_hier_export_prolongator(const psc_hier* h, int32_t l, int32_t* rp, int32
     return PSC_OK;
 }
 
+int psc_net_create_l1jacobi(const psc_hier* h, void* hip_stream, psc_net** out) {
+    if (!h || !out) return fail(PSC_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    if (h->host.lev.empty() || (int64_t)h->host.lev[0].minv.size() != h->host.lev[0].n)
+        return fail(PSC_ERR_STATE, "hierarchy holds no level-0 l1 diagonal");
+    HIPCHK(hipSetDevice(h->device));
+    return net_create_jacobi(h->host.lev[0].minv.data(), h->host.lev[0].n, hip_stream, out);
+}
+
 int psc_vcycle_apply(psc_hier* h, int32_t prec, const double* r, double* z) {
     if (!h || !r || !z) return fail(PSC_ERR_ARG, "NULL argument");
     if (!h->ctl) return fail(PSC_ERR_STATE, "hierarchy was built host-only");

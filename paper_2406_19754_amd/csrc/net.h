@@ -17,5 +17,7 @@ int net_launch_apply(psc_net* net, hipStream_t st, const double* r, double* z, c
 int net_check_grid(const psc_net* net, long long n);
 // Changes whenever buffers captured in a graph are reallocated.
 uint64_t net_generation(const psc_net* net);
+// The l1-Jacobi alternate of the learned schedule (copies M_0^-1).
+int net_create_jacobi(const double* minv_host, long long n, void* hip_stream, psc_net** out);
 
 }  // namespace psc

@@ -441,6 +441,127 @@ __global__ __launch_bounds__(WG) void k_wgrad(Dims d, const bf16r* __restrict__ 
     }
 }
 
+// Weight gradient of the 16 -> 16 layer on MFMA:
+//   dW2[co][ci][t] = sum_c g[c][co] h1[c + off_t][ci],  db2[co] = sum_c g[c][co],
+// an implicit GEMM per tap with the cells as the K dimension. A workgroup
+// takes tiles of 4 x-rows x 32 cells at one z (wavefront w: row w); the tile's
+// g (FP32, split into bfloat16 hi + lo so that the products keep about 16 bits)
+// and the 6 x 3 rows x 34 cells of h1 it reaches (zero outside the sample)
+// are staged in LDS channel-major, h1 in three copies shifted by dx so that
+// every operand is one aligned 16-byte LDS read: lane l holds g of channel
+// l & 15 at cells 8 (l >> 4) .. + 7 (A) and h1 of channel l & 15 at the same
+// cells shifted by the tap (B). Each wavefront keeps the 27 tap accumulators
+// (D[co = 4 (l >> 4) + i][ci = l & 15]) over the workgroup's tile range; the
+// four wavefronts, then the blocks (k_wreduce), are added in a fixed order.
+constexpr int WG2_X = 32, WG2_R = 4, WG2_HX = WG2_X + 2, WG2_HR = (WG2_R + 2) * 3;
+__global__ __launch_bounds__(WG) void k_wgrad2_mfma(Dims d, const bf16r* __restrict__ h1, const float* __restrict__ g,
+                                                    float* __restrict__ part) {
+    __shared__ __align__(16) bf16r gl[2][WG2_R][NC][WG2_X];          // hi, lo
+    __shared__ __align__(16) bf16r hl[3][WG2_HR][NC][WG2_X];         // shifted copies dx = 0, 1, 2
+    __shared__ float red[WG / 64][NC * NC];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nxt = (d.W + WG2_X - 1) / WG2_X, nyt = (d.H + WG2_R - 1) / WG2_R;
+    const long long ntiles = (long long)d.B * d.D * nyt * nxt;
+    const long long per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const long long t0 = (long long)blockIdx.x * per, t1 = t0 + per < ntiles ? t0 + per : ntiles;
+    f32x4 acc[27];
+#pragma unroll
+    for (int t = 0; t < 27; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bacc[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) bacc[j] = 0.f;
+    const int kg = lane >> 4, ch = lane & 15;
+    for (long long T = t0; T < t1; T++) {
+        long long q = T;
+        const int x0 = (int)(q % nxt) * WG2_X;
+        q /= nxt;
+        const int y0 = (int)(q % nyt) * WG2_R;
+        q /= nyt;
+        const int z = (int)(q % d.D);
+        const int b = (int)(q / d.D);
+        __syncthreads();   // the previous tile's operands have been read
+        {
+            // g: 4 rows x 32 cells x 2 halves of 8 channels = 256 tasks
+            const int cell = tid >> 1, half = tid & 1;
+            const int r = cell / WG2_X, xi = cell % WG2_X;
+            const int x = x0 + xi, y = y0 + r;
+            float v[8];
+            if (x < d.W && y < d.H) {
+                const float* gp = g + ((((long long)b * d.D + z) * d.H + y) * d.W + x) * NC + half * 8;
+                const f32x4 a = *(const f32x4*)gp, c = *(const f32x4*)(gp + 4);
+                v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
+                v[4] = c[0]; v[5] = c[1]; v[6] = c[2]; v[7] = c[3];
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; j++) v[j] = 0.f;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                bacc[j] += v[j];
+                const bf16r hi = f2bf(v[j]);
+                const bf16r lo = f2bf(v[j] - __uint_as_float((unsigned)hi << 16));
+                gl[0][r][half * 8 + j][xi] = hi;
+                gl[1][r][half * 8 + j][xi] = lo;
+            }
+        }
+        // h1: 18 rows x 34 cells x 2 halves
+        for (int task = tid; task < WG2_HR * WG2_HX * 2; task += WG) {
+            const int half = task & 1, cell = task >> 1;
+            const int xi = cell % WG2_HX, row = cell / WG2_HX;
+            const int dz = row / (WG2_R + 2), ry = row % (WG2_R + 2);
+            const int x = x0 + xi - 1, y = y0 + ry - 1, zz = z + dz - 1;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (x >= 0 && x < d.W && y >= 0 && y < d.H && zz >= 0 && zz < d.D)
+                v = *(const u32x4*)(h1 + ((((long long)b * d.D + zz) * d.H + y) * d.W + x) * NC + half * 8);
+            const unsigned w[4] = {v[0], v[1], v[2], v[3]};
+#pragma unroll
+            for (int dx = 0; dx < 3; dx++) {
+                const int pos = xi - dx;   // copy dx, position pos holds x0 + pos + dx - 1
+                if (pos < 0 || pos >= WG2_X) continue;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    hl[dx][row][half * 8 + 2 * j][pos] = (bf16r)(w[j] & 0xffffu);
+                    hl[dx][row][half * 8 + 2 * j + 1][pos] = (bf16r)(w[j] >> 16);
+                }
+            }
+        }
+        __syncthreads();
+        const bf16x8 ahi = *(const bf16x8*)&gl[0][wv][ch][8 * kg];
+        const bf16x8 alo = *(const bf16x8*)&gl[1][wv][ch][8 * kg];
+#pragma unroll
+        for (int t = 0; t < 27; t++) {
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+            const bf16x8 bm = *(const bf16x8*)&hl[dx][dz * (WG2_R + 2) + wv + dy][ch][8 * kg];
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bm, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bm, acc[t], 0, 0, 0);
+        }
+    }
+    // block partial: the four wavefronts' accumulators, tap by tap
+    float* dst = part + (size_t)blockIdx.x * (NC * NC * 27 + NC);
+    for (int t = 0; t < 27; t++) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; i++) red[wv][(4 * kg + i) * NC + ch] = acc[t][i];
+        __syncthreads();
+        // thread tid sums entry tid = co * 16 + ci over the wavefronts
+        const float sum = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+        dst[tid * 27 + t] = sum;
+    }
+    // bias: threads with the same half hold the same 8 channels
+    __syncthreads();
+    float* bred = &red[0][0];   // 256 threads x 8 values would not fit: reduce in two rounds
+    for (int j = 0; j < 8; j++) {
+        __syncthreads();
+        bred[tid] = bacc[j];
+        __syncthreads();
+        if (tid < 2) {
+            float sum = 0.f;
+            for (int k = tid; k < WG; k += 2) sum += bred[k];
+            dst[NC * NC * 27 + tid * 8 + j] = sum;
+        }
+    }
+}
+
 // grad[ow + w] / grad[ob + co] = sum over blocks (fixed order) of the partials
 __global__ __launch_bounds__(WG) void k_wreduce(const float* __restrict__ part, int nblk, int nw, int cout,
                                                 int ow, int ob, float* __restrict__ grad) {
@@ -499,6 +620,15 @@ __global__ __launch_bounds__(WG) void k_gather(long long per, const float* __res
 
 static inline unsigned blocks_for(long long n) { return (unsigned)((n + WG - 1) / WG); }
 
+// Comparison arm of the learned form: one l1-Jacobi sweep from zero on the
+// finest level, z = M_0^-1 r.
+__global__ __launch_bounds__(WG) void k_jacobi_alt(long long n, const double* __restrict__ minv,
+                                                   const double* __restrict__ r, double* __restrict__ z, Gate g) {
+    if (gate_skip(g)) return;
+    const long long i = (long long)blockIdx.x * WG + threadIdx.x;
+    if (i < n) z[i] = minv[i] * r[i];
+}
+
 }  // namespace psc
 
 using namespace psc;
@@ -507,6 +637,8 @@ struct psc_net {
     hipStream_t user_stream = nullptr, stream = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     int device = 0;
+    int kind = 0;                   // 0: the network; 1: l1-Jacobi alternate z = M_0^-1 r
+    double* jminv = nullptr;        // kind 1: its own copy of M_0^-1
     float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *wr = nullptr;
     bf16r *ffwd = nullptr, *fbwd = nullptr;
     long long adam_t = 0;
@@ -598,7 +730,7 @@ static void loss_grad(psc_net* n, hipStream_t st, const Dims& d, int margin, dou
     const long long tiles = (long long)d.B * d.D * d.H * ((d.W + 15) / 16);
     k_conv2<1><<<(unsigned)((tiles + 3) / 4), WG, 0, st>>>(d, n->ga2b, (const bf16x8*)n->fbwd, n->wr, n->a1, n->ga1,
                                                            nullptr, g0);
-    k_wgrad<NC, NC><<<WGRAD_BLOCKS, WG, 0, st>>>(d, n->th1, n->ga2f, n->wpart);
+    k_wgrad2_mfma<<<WGRAD_BLOCKS, WG, 0, st>>>(d, n->th1, n->ga2f, n->wpart);
     k_wreduce<<<blocks_for(NC * NC * 27 + NC), WG, 0, st>>>(n->wpart, WGRAD_BLOCKS, NC * NC * 27, NC, OW2, OB2, n->grad);
     // layer 1: weight gradient
     k_wgrad<1, NC><<<WGRAD_BLOCKS, WG, 0, st>>>(d, n->tu, n->ga1, n->wpart);
@@ -620,6 +752,10 @@ static int join_out(psc_net* n) {
 int net_launch_apply(psc_net* n, hipStream_t st, const double* r, double* z, const double* rr_dev, long long N,
                      Gate g) {
     if (!n || n->gcells != N) return nfail(PSC_ERR_ARG, "network grid does not match the vector size");
+    if (n->kind == 1) {
+        k_jacobi_alt<<<blocks_for(N), WG, 0, st>>>(N, n->jminv, r, z, g);
+        return PSC_OK;
+    }
     Dims d{1, n->gz, n->gy, n->gx};
     forward(n, st, d, r, nullptr, rr_dev, N, n->u, n->h1, n->h2, nullptr, nullptr, z, nullptr, g);
     return PSC_OK;
@@ -646,7 +782,7 @@ void psc_net_free(psc_net* n) {
     net_free_train(n);
     for (void* p : {(void*)n->master, (void*)n->m, (void*)n->v, (void*)n->grad, (void*)n->wr, (void*)n->ffwd,
                     (void*)n->fbwd, (void*)n->u, (void*)n->h1, (void*)n->h2, (void*)n->rr, (void*)n->dpart,
-                    (void*)n->wpart, (void*)n->loss_dev})
+                    (void*)n->wpart, (void*)n->loss_dev, (void*)n->jminv})
         if (p) (void)hipFree(p);
     for (auto& e : n->ev)
         if (e) (void)hipEventDestroy(e);
@@ -686,8 +822,39 @@ int psc_net_create(const float* params, void* hip_stream, psc_net** out) {
     return PSC_OK;
 }
 
+}  // extern "C"
+
+namespace psc {
+// An l1-Jacobi alternate for the learned schedule: its own device copy of
+// the n entries of M_0^-1 (given in host memory), bound to hip_stream.
+int net_create_jacobi(const double* minv_host, long long n, void* hip_stream, psc_net** out) {
+    *out = nullptr;
+    psc_net* net = new psc_net();
+    auto bail = [&](int st) { psc_net_free(net); return st; };
+    net->kind = 1;
+    net->user_stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&net->device) != hipSuccess) return bail(nfail(PSC_ERR_HIP, "hipGetDevice failed"));
+    if (hipStreamCreateWithFlags(&net->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&net->ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&net->ev[1], hipEventDisableTiming) != hipSuccess)
+        return bail(nfail(PSC_ERR_HIP, "stream or event creation failed"));
+    if (hipMalloc((void**)&net->jminv, (size_t)n * sizeof(double)) != hipSuccess)
+        return bail(nfail(PSC_ERR_OOM, "hipMalloc failed"));
+    if (hipMemcpy(net->jminv, minv_host, (size_t)n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(nfail(PSC_ERR_HIP, "copy of M_0^-1 failed"));
+    net->gx = (int)n;
+    net->gy = net->gz = 1;
+    net->gcells = n;
+    *out = net;
+    return PSC_OK;
+}
+}  // namespace psc
+
+extern "C" {
+
 int psc_net_get_params(const psc_net* n, float* params) {
     if (!n || !params) return nfail(PSC_ERR_ARG, "NULL argument");
+    if (n->kind != 0) return nfail(PSC_ERR_STATE, "an l1-Jacobi alternate has no weights");
     NHIPCHK(hipSetDevice(n->device));
     NHIPCHK(hipStreamSynchronize(n->stream));
     NHIPCHK(hipMemcpy(params, n->master, NP * sizeof(float), hipMemcpyDeviceToHost));
@@ -696,6 +863,7 @@ int psc_net_get_params(const psc_net* n, float* params) {
 
 int psc_net_set_params(psc_net* n, const float* params) {
     if (!n || !params) return nfail(PSC_ERR_ARG, "NULL argument");
+    if (n->kind != 0) return nfail(PSC_ERR_STATE, "an l1-Jacobi alternate has no weights");
     int st = join_in(n);
     if (st) return st;
     NHIPCHK(hipMemcpyAsync(n->master, params, NP * sizeof(float), hipMemcpyHostToDevice, n->stream));
@@ -710,6 +878,10 @@ int psc_net_set_params(psc_net* n, const float* params) {
 int psc_net_set_grid(psc_net* n, int32_t nx, int32_t ny, int32_t nz) {
     if (!n || nx < 1 || ny < 1 || nz < 1) return nfail(PSC_ERR_ARG, "bad grid");
     const long long cells = (long long)nx * ny * nz;
+    if (n->kind == 1) {
+        if (cells != n->gcells) return nfail(PSC_ERR_ARG, "an l1-Jacobi alternate acts on its matrix's rows only");
+        return PSC_OK;
+    }
     if (n->gx == nx && n->gy == ny && n->gz == nz) return PSC_OK;
     NHIPCHK(hipSetDevice(n->device));
     NHIPCHK(hipStreamSynchronize(n->stream));
@@ -735,6 +907,12 @@ int psc_net_apply(psc_net* n, const double* r, double* z, int32_t nx, int32_t ny
     st = join_in(n);
     if (st) return st;
     const long long N = n->gcells;
+    if (n->kind == 1) {
+        net_launch_apply(n, n->stream, r, z, nullptr, N, Gate{nullptr, GATE_NONE});
+        NHIPCHK(hipGetLastError());
+        NHIPCHK(hipStreamSynchronize(n->stream));
+        return join_out(n);
+    }
     const unsigned nb = 1024;
     k_sumsq<<<nb, WG, 0, n->stream>>>(N, r, n->dpart);
     k_sum_partials<<<1, WG, 0, n->stream>>>(n->dpart, (int)nb, 1.0, n->rr, nullptr);
@@ -746,6 +924,7 @@ int psc_net_apply(psc_net* n, const double* r, double* z, int32_t nx, int32_t ny
 
 int psc_net_forward_batch(psc_net* n, const float* in, float* out, int32_t B, int32_t D) {
     if (!n || !in || !out || B < 1 || D < 1) return nfail(PSC_ERR_ARG, "bad argument");
+    if (n->kind != 0) return nfail(PSC_ERR_STATE, "an l1-Jacobi alternate has no weights");
     Dims d{B, D, D, D};
     int st = join_in(n);
     if (st) return st;
@@ -762,6 +941,7 @@ int psc_net_loss_grad(psc_net* n, const float* in, const float* tgt, int32_t B, 
                       float* loss, float* grad_host) {
     if (!n || !in || !tgt || !loss || !grad_host || B < 1 || D < 1 || margin < 0 || 2 * margin >= D)
         return nfail(PSC_ERR_ARG, "bad argument");
+    if (n->kind != 0) return nfail(PSC_ERR_STATE, "an l1-Jacobi alternate has no weights");
     Dims d{B, D, D, D};
     int st = join_in(n);
     if (st) return st;
@@ -786,6 +966,7 @@ int psc_net_train(psc_net* n, const float* r_crops, const float* z_crops, int32_
     if (!n || !r_crops || !z_crops || !order || ncrops < 1 || crop < 1 || steps < 0 || batch < 1 ||
         margin < 0 || 2 * margin >= crop || !(lr > 0.f))
         return nfail(PSC_ERR_ARG, "bad argument");
+    if (n->kind != 0) return nfail(PSC_ERR_STATE, "an l1-Jacobi alternate has no weights");
     for (long long i = 0; i < (long long)steps * batch; i++)
         if (order[i] < 0 || order[i] >= ncrops) return nfail(PSC_ERR_ARG, "crop index out of range");
     Dims d{batch, crop, crop, crop};
@@ -863,6 +1044,15 @@ int psc_net_apply_noalloc(psc_net* n, const double* r, double* z, int32_t nx, in
         return nfail(PSC_ERR_ARG, "grid of " + std::to_string(N) + " cells exceeds the allocation-free maximum of " +
                                       std::to_string(PSC_NET_NOALLOC_MAX_CELLS) + " cells");
     NHIPCHK(hipSetDevice(n->device));
+    if (n->kind == 1) {
+        if (N != n->gcells) return nfail(PSC_ERR_ARG, "an l1-Jacobi alternate acts on its matrix's rows only");
+        int sj = join_in(n);
+        if (sj) return sj;
+        k_jacobi_alt<<<blocks_for(N), WG, 0, n->stream>>>(N, n->jminv, r, z, Gate{nullptr, GATE_NONE});
+        NHIPCHK(hipGetLastError());
+        NHIPCHK(hipStreamSynchronize(n->stream));
+        return join_out(n);
+    }
     unsigned char* base = nullptr;
     int st = scratch_on(n->device, &base);
     if (st) return st;
@@ -902,6 +1092,7 @@ static bool host_little_endian() {
 
 int psc_net_save(const psc_net* n, const char* path) {
     if (!n || !path) return nfail(PSC_ERR_ARG, "NULL argument");
+    if (n->kind != 0) return nfail(PSC_ERR_STATE, "an l1-Jacobi alternate has no weights");
     if (!host_little_endian()) return nfail(PSC_ERR_IO, "checkpoints are little-endian; host is not");
     std::vector<float> buf((size_t)3 * NP);
     NHIPCHK(hipSetDevice(n->device));

@@ -102,6 +102,7 @@ def _load():
         "psc_pairs_collect": ([vp, vp, i32, i32, i32, f64, i32, i32, i32, vp, i32, vp, vp, i32, P(i32)], C.c_int),
         "psc_net_train": ([vp, vp, vp, i32, i32, i32, vp, i32, i32, f32, f32, f32, f32, vp], C.c_int),
         "psc_net_save": ([vp, C.c_char_p], C.c_int),
+        "psc_net_create_l1jacobi": ([vp, vp, P(vp)], C.c_int),
         "psc_net_load": ([C.c_char_p, vp, P(vp)], C.c_int),
         "psc_net_free": ([vp], None),
     }
@@ -294,6 +295,14 @@ class Net:
         if p.size != net_param_count():
             raise ValueError(f"expected {net_param_count()} parameters")
         _check(_lib.psc_net_create(pp, C.c_void_p(_stream(stream)), C.byref(self._h)))
+
+    @classmethod
+    def l1jacobi(cls, hier, stream=None):
+        """psc_net_create_l1jacobi: the learned schedule's comparison arm,
+        z = M_0^-1 r in place of the network."""
+        net = cls(None)
+        _check(_lib.psc_net_create_l1jacobi(hier._h, C.c_void_p(_stream(stream)), C.byref(net._h)))
+        return net
 
     @classmethod
     def load(cls, path, stream=None):

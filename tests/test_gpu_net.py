@@ -1,9 +1,16 @@
 """GPU parity of the learned preconditioner's kernels against the CPU oracle.
 
 Both sides round the same operands to bfloat16; the GPU accumulates in FP32
-(MFMA for the 16 -> 16 layer) and the oracle in FP64, so an activation can
-land on the other side of a bfloat16 rounding boundary. Tolerances: forward
-outputs 1e-2 relative (norm), gradients 3e-2 relative per parameter group.
+(MFMA for the 16 -> 16 layers) and the oracle in FP64, so an activation can
+land on the other side of a bfloat16 rounding boundary, which moves that
+cell's output by about one bfloat16 step of the activation times its weight.
+Tolerances, element by element against max|ref| (see elementwise()): the
+99th percentile of |gpu - ref| within 1e-4 max|ref| (flips touched 0.09 -
+0.45 % of the cells in measurements, the others agree to FP32 summation
+error) and the largest within 2e-3 max|ref| (one flip moved an output by at
+most 4.1e-4 max|ref| in measurements); gradients per parameter group 1e-2
+relative in norm (measured: at most 8.8e-4, W1, whose gradient sums the
+flips of both layers) and 99th percentile 1e-2 element-wise.
 """
 import os
 
@@ -37,6 +44,18 @@ def relerr(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
+def elementwise(gpu, ref, what, q_tol=1e-4, max_tol=2e-3):
+    """|gpu - ref| against max|ref|: the 99th percentile and the largest."""
+    gpu, ref = np.asarray(gpu, np.float64).ravel(), np.asarray(ref, np.float64).ravel()
+    scale = np.abs(ref).max()
+    d = np.abs(gpu - ref) / scale
+    q, m = float(np.quantile(d, 0.99)), float(d.max())
+    frac = float(np.mean(d > 1e-4))
+    print(f"[net parity] {what}: q99 {q:.1e} max {m:.1e} (x max|ref|), cells beyond 1e-4: {frac:.2%}", flush=True)
+    assert q <= q_tol, (what, q)
+    assert m <= max_tol, (what, m)
+
+
 @pytest.mark.parametrize("B,D", [(2, 10), (3, 20), (1, 33)])
 def test_forward_batch_matches_oracle(psc, B, D):
     p = params(1)
@@ -45,7 +64,7 @@ def test_forward_batch_matches_oracle(psc, B, D):
     out = torch.empty(B, D, D, D, dtype=torch.float32, device="cuda")
     net.forward_batch(torch.from_numpy(u).cuda(), out)
     ref = oracle.net_forward(p.astype(np.float64), u.astype(np.float64), round_bf16=True)
-    assert relerr(out.cpu().numpy(), ref) <= 1e-2
+    elementwise(out.cpu().numpy(), ref, f"forward B={B} D={D}")
 
 
 def test_loss_and_gradients_match_oracle(psc):
@@ -60,7 +79,11 @@ def test_loss_and_gradients_match_oracle(psc):
                                       round_bf16=True)
     assert abs(loss - lref) <= 1e-3 * lref
     for name, (a, b) in GROUPS.items():
-        assert relerr(g[a:b], gref[a:b]) <= 3e-2, name
+        e = relerr(g[a:b], gref[a:b])
+        print(f"[net parity] gradient {name}: relative error {e:.1e}", flush=True)
+        assert e <= 1e-2, name
+        if b - a > 1:
+            elementwise(g[a:b], gref[a:b], f"gradient {name}", q_tol=1e-2, max_tol=2e-2)
 
 
 def test_adam_step_and_training_lowers_loss(psc):
@@ -91,7 +114,7 @@ def test_net_apply_matches_oracle(psc):
     z = torch.empty(N, dtype=torch.float64, device="cuda")
     net.apply(torch.from_numpy(r).cuda(), z, dims)
     ref = oracle.net_apply(p.astype(np.float64), r, dims)
-    assert relerr(z.cpu().numpy(), ref) <= 1e-2
+    elementwise(z.cpu().numpy(), ref, "apply 9x10x12")
 
 
 def test_zero_network_falls_back_to_vcycle(psc):
@@ -111,6 +134,73 @@ def test_zero_network_falls_back_to_vcycle(psc):
     assert g["fallbacks"] == g["iters"] // 2
     assert g["iters"] == g0["iters"]
     assert torch.equal(x, x2)
+
+
+def identity_like_net(a, c):
+    """Each cell alone (centre taps): out = c (G(G(a u)) - G(G(-a u))), G = GELU,
+    an odd increasing map of u, so z.r > 0 for every r != 0: every scheduled
+    network step is taken, and on Poisson each cuts ||r|| by more than 10 %."""
+    C = 16
+    W1, W2, W3 = np.zeros((C, 1, 27)), np.zeros((C, C, 27)), np.zeros((1, C, 27))
+    W1[0, 0, 13], W1[1, 0, 13] = a, -a
+    W2[0, 0, 13] = W2[1, 1, 13] = 1.0
+    W3[0, 0, 13], W3[0, 1, 13] = c, -c
+    return np.concatenate([W1.ravel(), np.zeros(C), W2.ravel(), np.zeros(C), W3.ravel(), [0.0]]).astype(np.float32)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_learned_fcg_accepted_steps_match_oracle(psc, prec):
+    """Every network step accepted (no fallback): iterations within one of the
+    oracle's, and the solutions after the same number of iterations agree."""
+    n = 16
+    rp, c, v = P.poisson7(n)
+    p = identity_like_net(4.0, 1.0)
+    pr, form = (psc.FP32, 1) if prec == "fp32" else (psc.FP64, 0)
+    h = psc.Hierarchy(rp, c, v, build_fp32=True)
+    o = oracle.Hierarchy(rp, c, v)
+    net = psc.Net(p)
+    net.set_grid((n, n, n))
+    b = P.rhs_uniform(n ** 3, 12)
+    bd = torch.from_numpy(b).cuda()
+    x = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+    g = h.fcg(bd, x, net=net, prec=pr)
+    r = o.fcg(b, params=p.astype(np.float64), dims=(n, n, n), form=form)
+    assert g["status"] == psc.OK and r["status"] == oracle.OK and g["relres"] <= 1e-6
+    assert g["fallbacks"] == 0 and r["fallbacks"] == 0 and r["net_evals"] == r["iters"] // 2 > 0
+    assert abs(g["iters"] - r["iters"]) <= 1
+    k = min(g["iters"], r["iters"]) - 1
+    x.zero_()
+    h.fcg(bd, x, rtol=1e-30, maxit=k, net=net, prec=pr)
+    ref = o.fcg(b, rtol=1e-30, maxit=k, params=p.astype(np.float64), dims=(n, n, n), form=form)["x"]
+    err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+    print(f"[net parity] learned FCG ({prec}) after {k} iterations: |x_gpu - x_orc|/|x_orc| = {err:.1e}", flush=True)
+    assert err <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_l1_jacobi_alternate_matches_oracle(psc, prec):
+    """The learned schedule's comparison arm (z = M_0^-1 r in place of the
+    network): same iterations and accounting as the oracle, iterates equal."""
+    n = 20
+    rp, c, v = P.poisson7(n)
+    pr, form = (psc.FP32, 1) if prec == "fp32" else (psc.FP64, 0)
+    h = psc.Hierarchy(rp, c, v, build_fp32=True)
+    o = oracle.Hierarchy(rp, c, v)
+    jac = psc.Net.l1jacobi(h)
+    b = P.rhs_uniform(n ** 3, 14)
+    bd = torch.from_numpy(b).cuda()
+    x = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+    g = h.fcg(bd, x, net=jac, prec=pr)
+    r = o.fcg(b, form=form, alt_jacobi=True)
+    assert g["status"] == psc.OK and r["status"] == oracle.OK and g["relres"] <= 1e-6
+    assert r["net_evals"] >= 1
+    assert g["iters"] == r["iters"] and g["fallbacks"] == r["fallbacks"]
+    ref = r["x"]
+    tol = 1e-8 if prec == "fp64" else 1e-6
+    assert np.linalg.norm(x.cpu().numpy() - ref) <= tol * np.linalg.norm(ref)
+    # the arm has no weights
+    with pytest.raises(psc.PscError):
+        jac.params()
 
 
 def test_learned_fcg_matches_oracle(psc):

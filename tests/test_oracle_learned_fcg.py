@@ -198,3 +198,26 @@ def test_net_apply_scale_is_rms_of_residual():
     assert frac > 0.95 and worst <= 2e-2
     frac_wrong, worst_wrong = close_fraction(np.linalg.norm(r))
     assert frac_wrong < 0.05 and worst_wrong > 0.1
+
+
+@pytest.mark.parametrize("n,shift", [(8, 0.0), (10, 0.5)])
+def test_l1_jacobi_alternate_matches_independent_reference(n, shift):
+    """The comparison arm of the learned form: the same schedule with one
+    l1-Jacobi sweep from zero, z = r / (a_ii + sum_j |a_ij|), in place of the
+    network. The l1 diagonal is formed here from the CSR arrays."""
+    rp, c, v = shifted_poisson(n, shift)
+    N = n ** 3
+    A = sp.csr_matrix((v, c, rp), shape=(N, N))
+    rows = np.repeat(np.arange(N), np.diff(rp))
+    l1 = np.zeros(N)
+    np.add.at(l1, rows, np.abs(v))          # a_ii > 0, so |a_ii| + sum |a_ij|
+    h = oracle.Hierarchy(rp, c, v, coarse_max=20)
+    b = P.rhs_uniform(N, 2)
+    xs, K, fb, ne, events = fcg_learned_reference(A, b, h.vcycle, lambda r: r / l1, 1e-6, 200)
+    assert ne >= 1 and "net" in [e for _, e in events]
+    full = h.fcg(b, rtol=1e-6, alt_jacobi=True)
+    assert full["status"] == oracle.OK
+    assert (full["iters"], full["fallbacks"], full["net_evals"]) == (K, fb, ne)
+    for k in range(1, K + 1):
+        o = h.fcg(b, rtol=1e-6, maxit=k, alt_jacobi=True)
+        np.testing.assert_allclose(o["x"], xs[k - 1], rtol=0, atol=1e-12 * np.abs(xs[k - 1]).max())
