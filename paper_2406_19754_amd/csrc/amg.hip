@@ -2751,9 +2751,12 @@ static void post_sweeps(psc_hier* h, DevLevel& V, const TB* b, TX* out, const T*
 }
 
 // The V-cycle below level 0's right-hand side r0 in precision T (split sweeps).
+// r0_32: when not NULL, an FP32 copy of r0 ((float) r0 element by element),
+// read by the FP32 level-0 post-smoothing instead of r0 (same values, half
+// the bytes).
 template <typename T>
 static void vcycle_t(psc_hier* h, const double* r0, double* z0, const double* d, const Red& R, Gate g,
-                     bool skip_pre0) {
+                     bool skip_pre0, const float* r0_32 = nullptr) {
     const int L = (int)h->lev.size();
     Red R0 = R;
     R0.fin = FIN_NONE;
@@ -2787,7 +2790,9 @@ static void vcycle_t(psc_hier* h, const double* r0, double* z0, const double* d,
         if (l == 0) {
             {
                 TimeScope t(h, 4);
-                if (h->split) post_sweeps<T, double, double>(h, V, r0, z0, xc, d, R);
+                if (h->split && std::is_same<T, float>::value && r0_32)
+                    post_sweeps<T, float, double>(h, V, r0_32, z0, xc, d, R);
+                else if (h->split) post_sweeps<T, double, double>(h, V, r0, z0, xc, d, R);
                 else launch_post(h, LV<T>::A(V), LV<T>::SP(V), LV<T>::minv(V), r0, (const T*)LV<T>::r(V), V.agg,
                                  LV<T>::pv(V), xc, V.nc, z0, d, R);
             }
@@ -3001,7 +3006,7 @@ static void vcycle_cheb(psc_hier* h, const double* r0, double* z0, const double*
 // z.d at level 0 with finaliser fin. g gates every kernel (g.ctl == NULL:
 // standalone V-cycle, always runs, no fused dot).
 static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin, const double* d,
-                   Gate g, bool skip_pre0 = false) {
+                   Gate g, bool skip_pre0 = false, const float* r0_32 = nullptr) {
     hipStream_t st = h->stream;
     const int L = (int)h->lev.size();
     Red R = red_of(h, fin, g.ctl ? g.mode : GATE_NONE);
@@ -3029,7 +3034,7 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
         return;
     }
     if (prec == PSC_FP64) vcycle_t<double>(h, r0, z0, d, R, g, skip_pre0);
-    else vcycle_t<float>(h, r0, z0, d, R, g, skip_pre0);
+    else vcycle_t<float>(h, r0, z0, d, R, g, skip_pre0, r0_32);
 }
 
 // ---------------------------------------------------------------------------
@@ -3194,15 +3199,18 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
             finish(h, red_of(h, FIN_TRUE), gq);
             // after a residual replacement, redo the level-0 pre-smoothing from the true residual
             const Gate gr{h->ctl, GATE_REDO};
+            // the FP32 copy of r (mixed form, split passes) read by the level-0 post-smoothing
+            const float* r32v = (f32 && h->split && h->mixed_split && !(h->fai || h->cheb)) ? h->r32 : nullptr;
             if (h->fai || h->cheb) {
                 // these smoothers have no fused pre-smoothing to redo
             } else if (f32) {
+                if (r32v) k_copy<float, double><<<gq, WG, 0, st>>>(n, h->r32, rnew, gr);
                 launch_pre(h, L0, (const double*)rnew, pre_rbuf<float>(h, L0, 1), gr, gq);
             } else {
                 launch_pre(h, L0, (const double*)rnew, pre_rbuf<double>(h, L0, 1), gr, gq);
             }
             if (!netf) {
-                vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, gd, true);
+                vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, gd, true, r32v);
                 continue;
             }
             // learned form: odd iterations try z = net(r); the V-cycle (its
@@ -3217,7 +3225,7 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
                 k_dot2<<<gv, WG, 0, st>>>(n, h->z, rnew, h->q, Rn);
                 finish(h, Rn, gv);
             }
-            vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, Gate{h->ctl, GATE_VC}, true);
+            vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, Gate{h->ctl, GATE_VC}, true, r32v);
         }
         return PSC_OK;
     }

@@ -530,3 +530,23 @@ def test_tail_lds_limit_holds_across_handles(psc):
         h.vcycle(dev(x), y)
         ref = oracle.Hierarchy(rp, c, v).vcycle(x)
         assert np.linalg.norm(y.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_mixed_split_passes_equal_fused_bit_for_bit(psc):
+    """The mixed form's split second pass (r -= alpha q with an FP32 copy of r,
+    the FP32 pre-smoothing and the level-0 post-smoothing reading that copy)
+    equals the fused pass that rounds FP64 r at every use: the same FP32
+    values in the same order, so the same iterates bit for bit, also across
+    residual replacements (rtol 1e-11)."""
+    rp, c, v = P.diffusion7(24, seed=3, az=0.01)
+    b = dev(P.rhs_from_solution(rp, c, v, P.x_true(24 ** 3, 2)))
+    out = []
+    for split in (1, 0):
+        h = psc.Hierarchy(rp, c, v, build_fp32=True)
+        h.tune(psc.TUNE_MIXED_SPLIT, split)
+        x = torch.zeros(len(b), dtype=torch.float64, device="cuda")
+        g = h.fcg(b, x, rtol=1e-11, maxit=400, prec=psc.FP32)
+        assert g["status"] == psc.OK and g["relres"] <= 1e-11
+        out.append((g["iters"], x))
+    assert out[0][0] == out[1][0]
+    assert torch.equal(out[0][1], out[1][1])
