@@ -310,6 +310,31 @@ __global__ __launch_bounds__(WG) void k_finish(Red R, int nblk) {
 // gathers in flight; wider slices take the general loop.
 template <typename T, typename G, int U = 8, int GB = 4>
 __device__ __forceinline__ T ell_row(const Ell<T>& A, long long s, int lane, G g) {
+    if (A.pair) {
+        // paired layout: one width per 128-row block, slot stride 128
+        const long long o = A.off[s], b0 = A.off[s & ~1ll];
+        const int w = (int)((A.off[(s & ~1ll) + 2] - b0) >> 7);
+        const T* vp = A.val + o + lane;
+        const int* cp = A.col + o + lane;
+        T acc = T(0);
+        int k = 0;
+        for (; k + GB <= w; k += GB) {
+            T v[GB];
+            int c[GB];
+#pragma unroll
+            for (int j = 0; j < GB; j++) {
+                v[j] = ntload(vp + (k + j) * 2 * SLICE);
+                c[j] = ntload(cp + (k + j) * 2 * SLICE);
+            }
+            T gv[GB];
+#pragma unroll
+            for (int j = 0; j < GB; j++) gv[j] = g(c[j]);
+#pragma unroll
+            for (int j = 0; j < GB; j++) acc += v[j] * gv[j];
+        }
+        for (; k < w; k++) acc += ntload(vp + k * 2 * SLICE) * g(ntload(cp + k * 2 * SLICE));
+        return acc;
+    }
     const long long o = A.off[s];
     const int w = (int)((A.off[s + 1] - o) >> 6);
     const T* vp = A.val + o + lane;
@@ -392,6 +417,11 @@ __device__ __forceinline__ T ell_row(const Ell<T>& A, long long s, int lane, G g
 // first gather, doubling the loads a wavefront keeps in flight.
 template <typename T, typename G>
 __device__ __forceinline__ void ell_row2(const Ell<T>& A, long long s1, long long s2, int lane, G g, T& a1, T& a2) {
+    if (A.pair) {
+        a1 = ell_row(A, s1, lane, g);
+        a2 = ell_row(A, s2, lane, g);
+        return;
+    }
     const long long o1 = A.off[s1], o2 = A.off[s2];
     const int w1 = (int)((A.off[s1 + 1] - o1) >> 6), w2 = (int)((A.off[s2 + 1] - o2) >> 6);
     if (w1 > 8 || w2 > 8) {
@@ -476,6 +506,7 @@ __device__ __forceinline__ BVec<T> bvec(const T* p, long long n) { return BVec<T
 // descriptors (s must be wave-uniform).
 template <typename T, typename G>
 __device__ __forceinline__ T ell_row_buf(const Ell<T>& A, long long s, int lane, G g) {
+    if (A.pair) return ell_row(A, s, lane, g);
     const long long o = A.off[s];
     const int w = (int)((A.off[s + 1] - o) >> 6);
     const rsrc_t rv = brsrc(A.val + o, (long long)w * SLICE * sizeof(T));
@@ -1313,9 +1344,67 @@ __global__ __launch_bounds__(WG) void k_post_s(Ell<T> SP, const T* __restrict__ 
                                                TX* __restrict__ x, const double* __restrict__ d, Red R) {
     if (skip_red(R)) return;
     long long lo, hi;
-    chunk_range(SP.nslices, lo, hi);
     const int lane = threadIdx.x & 63, w = wave_id();
     double s0 = 0.0;
+    if (SP.pair) {
+        // two rows per lane: their values (8/16 bytes) and columns (8 bytes)
+        // with one load per slot
+        typedef int i2 __attribute__((ext_vector_type(2), aligned(8)));
+        chunk_range((SP.nslices + 1) >> 1, lo, hi);
+        for (long long S = lo + w; S < hi; S += WG / 64) {
+            const long long b0 = SP.off[2 * S];
+            const int ws = (int)((SP.off[2 * S + 2] - b0) >> 7);
+            const v2a<T>* vp = (const v2a<T>*)(SP.val + b0) + lane;
+            const i2* cp = (const i2*)(SP.col + b0) + lane;
+            T a0 = T(0), a1 = T(0);
+            int k = 0;
+            for (; k + GB <= ws; k += GB) {
+                v2a<T> v[GB];
+                i2 c[GB];
+#pragma unroll
+                for (int j = 0; j < GB; j++) {
+                    v[j] = ntload(vp + (k + j) * SLICE);
+                    c[j] = ntload(cp + (k + j) * SLICE);
+                }
+                T g0[GB], g1[GB];
+#pragma unroll
+                for (int j = 0; j < GB; j++) {
+                    g0[j] = xc[c[j].x];
+                    g1[j] = xc[c[j].y];
+                }
+#pragma unroll
+                for (int j = 0; j < GB; j++) {
+                    a0 += v[j].x * g0[j];
+                    a1 += v[j].y * g1[j];
+                }
+            }
+            for (; k < ws; k++) {
+                const v2a<T> v = ntload(vp + k * SLICE);
+                const i2 c = ntload(cp + k * SLICE);
+                a0 += v.x * xc[c.x];
+                a1 += v.y * xc[c.y];
+            }
+            const long long row = S * (2 * SLICE) + 2 * lane;
+            if (row + 1 < SP.nrows) {
+                const v2u<T> m = ld2(minv + row), rr = ld2(r + row);
+                const v2u<TB> bb = ld2(b + row);
+                const T x0 = m.x * ((T)bb.x + rr.x) + a0, x1 = m.y * ((T)bb.y + rr.y) + a1;
+                st2(x + row, (TX)x0, (TX)x1);
+                if (d) {
+                    const v2u<double> dd = ld2(d + row);
+                    s0 += (double)(TX)x0 * dd.x;
+                    s0 += (double)(TX)x1 * dd.y;
+                }
+            } else if (row < SP.nrows) {
+                const T xi = minv[row] * ((T)b[row] + r[row]) + a0;
+                x[row] = (TX)xi;
+                if (d) s0 += (double)(TX)xi * d[row];
+            }
+        }
+        if (R.fin != FIN_NONE) block_partial(s0, 0.0, R.part);
+        return;
+    }
+    chunk_range(SP.nslices, lo, hi);
     for (long long s = lo + w; s < hi; s += WG / 64) {
         const T acc = mat_row<GB>(SP, s, lane, [&](int c) { return xc[c]; });
         const long long row = s * SLICE + lane;
@@ -1872,8 +1961,17 @@ struct DevEll {
     float* val32 = nullptr;
     long long nrows = 0, nslices = 0, slots = 0, ncols = 0, nnz = 0;
     int wmax = 0;                          // widest slice (entries per row)
-    Ell<T> view() const { return Ell<T>{off, val, col, nrows, nslices, ncols}; }
-    Ell<float> view32() const { return Ell<float>{off, val32, col, nrows, nslices, ncols}; }
+    int pair = 0;                          // paired 128-row layout (see Ell)
+    Ell<T> view() const {
+        Ell<T> e{off, val, col, nrows, nslices, ncols};
+        e.pair = pair;
+        return e;
+    }
+    Ell<float> view32() const {
+        Ell<float> e{off, val32, col, nrows, nslices, ncols};
+        e.pair = pair;
+        return e;
+    }
 };
 
 // Hacked-DIA copy of a level operator; the scaled operator A M^-1 shares
@@ -2134,7 +2232,8 @@ static int upload_ell(psc_hier* h, DevEll<double>& E, int64_t nrows, int64_t nco
 
 // Numeric rebuild on an unchanged pattern: row i's new CSR values go into
 // the slots the build gave them, hacked ELL (entry q of the row at
-// off[s] + 64 q + lane) and, when the level has one, hacked DIA (slot
+// off[s] + 64 q + lane, or off[s] + 128 q + lane in the paired layout) and,
+// when the level has one, hacked DIA (slot
 // (start[s] + k) 64 + lane, k the slice's diagonal of the entry's column),
 // with A M^-1 (a_ij minv_j) and the FP32 copies formed on the way (a paired
 // layout places slice s at (s >> 1) nd 128 + (s & 1) 64 with diagonal
@@ -2145,16 +2244,17 @@ __global__ void k_refresh_values(long long n, const int32_t* __restrict__ rp, co
                                  double* __restrict__ am, float* __restrict__ am32, const int* __restrict__ dstart,
                                  const int* __restrict__ doffs, double* __restrict__ dval,
                                  float* __restrict__ dval32, double* __restrict__ damd,
-                                 float* __restrict__ damd32, int dpair) {
+                                 float* __restrict__ damd32, int dpair, int epair) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const long long s = i >> 6;
     const int lane = (int)(i & 63);
     const long long o = off[s] + lane;
+    const long long estride = epair ? 2 * SLICE : SLICE;   // paired hacked ELL: slot stride 128
     const int32_t b = rp[i], e = rp[i + 1];
     const int k0 = dstart ? dstart[s] : 0, k1 = dstart ? dstart[s + 1] : 0;
     for (int32_t q = b; q < e; q++) {
-        const long long slot = o + (long long)(q - b) * SLICE;
+        const long long slot = o + (long long)(q - b) * estride;
         const double x = v[q];
         const int c = col[slot];
         val[slot] = x;
@@ -2229,7 +2329,7 @@ static int refresh_values(psc_hier* h, DevEll<double>& E, const DevDia* G, int64
     k_refresh_values<<<(unsigned)blocks, WG, 0, h->stream>>>(
         n, drp, dv, dm, E.off, E.col, E.val, E.val32, mv ? am : nullptr, mv ? am32 : nullptr,
         dia ? G->start : nullptr, dia ? G->offs : nullptr, dia ? G->val : nullptr, dia ? G->val32 : nullptr,
-        (dia && mv) ? amd : nullptr, (dia && mv) ? amd32 : nullptr, dia ? G->pair : 0);
+        (dia && mv) ? amd : nullptr, (dia && mv) ? amd32 : nullptr, dia ? G->pair : 0, E.pair);
     HIPCHK(hipGetLastError());
     // the staging buffer and the host arrays are reused or released next
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -2249,17 +2349,26 @@ static int zalloc(psc_hier* h, void** p, size_t bytes) {
 // columns packed on the host, value arrays (FP64, FP32 when fp32, and A M^-1
 // when am != nullptr) allocated and cleared, for refresh_values to fill.
 static int upload_ell_layout(psc_hier* h, DevEll<double>& E, int64_t nrows, int64_t ncols, const int32_t* rp,
-                             const int32_t* ci, bool fp32, double** am = nullptr, float** am32 = nullptr) {
+                             const int32_t* ci, bool fp32, double** am = nullptr, float** am32 = nullptr,
+                             bool paired = false) {
     std::vector<long long> off;
     std::vector<double> none;
     std::vector<int> col;
-    pack_ell(nrows, rp, ci, nullptr, off, none, col);
     E.nrows = nrows;
     E.ncols = ncols;
-    E.nslices = (long long)off.size() - 1;
-    E.slots = off.back();
     E.nnz = rp[nrows];
-    for (size_t q = 0; q + 1 < off.size(); q++) E.wmax = std::max(E.wmax, (int)((off[q + 1] - off[q]) / SLICE));
+    E.nslices = (nrows + SLICE - 1) / SLICE;
+    E.pair = paired ? 1 : 0;
+    if (paired) {
+        pack_ell_paired(nrows, rp, ci, nullptr, off, none, col);
+        E.slots = off.back();
+        for (long long q = 0; q < E.nslices; q += 2)
+            E.wmax = std::max(E.wmax, (int)((off[q + 2] - off[q]) / (2 * SLICE)));
+    } else {
+        pack_ell(nrows, rp, ci, nullptr, off, none, col);
+        E.slots = off.back();
+        for (size_t q = 0; q + 1 < off.size(); q++) E.wmax = std::max(E.wmax, (int)((off[q + 1] - off[q]) / SLICE));
+    }
     int st;
     if ((st = upload(h, &E.off, off.data(), off.size()))) return st;
     if ((st = upload(h, &E.col, col.data(), col.size()))) return st;
@@ -3670,12 +3779,14 @@ static int upload_levels(psc_hier* h) {
                 if (!h->refresh) {
                     std::vector<int32_t> sprp, spci;
                     tentative_sp_pattern(H, sprp, spci);
-                    if ((st = upload_ell_layout(h, D.SP, H.n, H.nc, sprp.data(), spci.data(), f32))) return st;
+                    if ((st = upload_ell_layout(h, D.SP, H.n, H.nc, sprp.data(), spci.data(), f32, nullptr, nullptr,
+                                                true)))
+                        return st;
                 }
                 if (!D.SP.off || !D.SP.col || !D.SP.val || D.SP.nrows != H.n) return PSC_ERR_STATE;
                 std::string err;
                 if ((st = gpu_tentative_sp((void*)h->stream, H.n, D.A.off, D.A.col, D.A.val, a_rp_dev, D.agg, D.pval,
-                                           D.minv, D.SP.off, D.SP.col, D.SP.val, D.SP.val32, err)))
+                                           D.minv, D.SP.off, D.SP.col, D.SP.val, D.SP.val32, D.SP.pair, err)))
                     return fail(st, err);
             }
             // R = P^T as CSR over coarse rows: fine rows ascending
@@ -3702,7 +3813,8 @@ static int upload_levels(psc_hier* h) {
                 std::vector<double> spv;
                 jacobi_smoothed_prolongator(H, mv.data(), sprp, spci, spv);
                 if (!h->refresh &&
-                    (st = upload_ell_layout(h, D.SP, H.n, H.nc, sprp.data(), spci.data(), f32)))
+                    (st = upload_ell_layout(h, D.SP, H.n, H.nc, sprp.data(), spci.data(), f32, nullptr, nullptr,
+                                            true)))
                     return st;
                 if ((st = refresh_values(h, D.SP, nullptr, H.n, sprp.data(), spv.data(), nullptr, nullptr, nullptr,
                                          nullptr, nullptr)))

@@ -556,7 +556,7 @@ __global__ void k_gs_tentative_sp(long long n, const long long* __restrict__ a_o
                                   const int32_t* __restrict__ agg, const double* __restrict__ p,
                                   const double* __restrict__ minv, const long long* __restrict__ sp_off,
                                   const int* __restrict__ sp_col, double* __restrict__ sp_val,
-                                  float* __restrict__ sp_val32) {
+                                  float* __restrict__ sp_val32, int sp_pair) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         const long long s = i >> 6;
@@ -570,12 +570,16 @@ __global__ void k_gs_tentative_sp(long long n, const long long* __restrict__ a_o
             for (int u = 0; u < q && first; u++) first = agg[a_col[ao + (long long)u * 64]] != J;
             ls += first ? 1 : 0;
         }
-        const int wsp = (int)((sp_off[s + 1] - sp_off[s]) >> 6);   // never past the slice (same pattern as at build)
+        // never past the slice (same pattern as at build); the paired layout
+        // keeps one width per 128-row block and a slot stride of 128
+        const int wsp = sp_pair ? (int)((sp_off[(s & ~1ll) + 2] - sp_off[s & ~1ll]) >> 7)
+                                : (int)((sp_off[s + 1] - sp_off[s]) >> 6);
+        const long long sstride = sp_pair ? 128 : 64;
         if (ls > wsp) ls = wsp;
         const int ai = agg[i];
         const double mi = minv[i];
         for (int q = 0; q < ls; q++) {
-            const long long slot = so + (long long)q * 64;
+            const long long slot = so + (long long)q * sstride;
             const int J = sp_col[slot];
             double t = 0.0;
             bool any = false;
@@ -794,10 +798,11 @@ int gpu_coarsen_level(int64_t n64, const int32_t* hrp, const int32_t* hci, const
 
 int gpu_tentative_sp(void* stream, int64_t n, const long long* a_off, const int* a_col, const double* a_val,
                      const int32_t* a_rp, const int32_t* agg, const double* p, const double* minv,
-                     const long long* sp_off, const int* sp_col, double* sp_val, float* sp_val32, std::string& err) {
+                     const long long* sp_off, const int* sp_col, double* sp_val, float* sp_val32, int sp_pair,
+                     std::string& err) {
     hipStream_t st = (hipStream_t)stream;
     k_gs_tentative_sp<<<gs_grid(n), GS_WG, 0, st>>>(n, a_off, a_col, a_val, a_rp, agg, p, minv, sp_off, sp_col,
-                                                     sp_val, sp_val32);
+                                                     sp_val, sp_val32, sp_pair);
     GS_CHK(hipGetLastError());
     GS_CHK(hipStreamSynchronize(st));
     return PSC_OK;

@@ -80,6 +80,11 @@ static long long pack_levels(const HostHier& H) {
         }
         jacobi_smoothed_prolongator(L, L.minv.data(), sprp, spci, spv);
         sum += (long long)spv.size();
+        std::vector<long long> poff;
+        std::vector<double> pval;
+        std::vector<int> pcol;
+        pack_ell_paired(L.n, sprp.data(), spci.data(), spv.data(), poff, pval, pcol);
+        sum += poff.back();
     }
     return sum;
 }

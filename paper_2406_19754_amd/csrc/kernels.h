@@ -46,6 +46,14 @@ struct HostCtl {
 
 // Hacked-ELL operator: slices of 64 rows; slice s holds its w_s columns
 // column-major at [off[s], off[s+1]) (w_s = (off[s+1]-off[s])/64).
+//
+// Paired layout (pair = 1): slices 2S and 2S+1 form a block of 128 rows with
+// one width w_S (the larger of the two), block-major: entry k of row r of the
+// block at off[2S] + k*128 + r, so one lane reads two consecutive rows'
+// entries with one 16-byte (FP64 values) or 8-byte (indices, FP32 values)
+// load. off[s] = off[2S] + (s & 1)*64 is slice s's first entry, the slot
+// stride is 128, w_S = (off[2S+2] - off[2S]) / 128, and off holds nslices + 2
+// entries (the last two equal: the total).
 template <typename T>
 struct Ell {
     using value_type = T;
@@ -55,6 +63,7 @@ struct Ell {
     long long nrows;
     long long nslices;
     long long ncols;
+    int pair = 0;
 };
 
 // Hacked-DIA operator (the hacked diagonal format of the PSBLAS extensions):

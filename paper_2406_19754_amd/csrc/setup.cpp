@@ -632,6 +632,44 @@ void pack_ell(int64_t nrows, const int32_t* rp, const int32_t* ci, const double*
     }
 }
 
+void pack_ell_paired(int64_t nrows, const int32_t* rp, const int32_t* ci, const double* v,
+                     std::vector<long long>& off, std::vector<double>& val, std::vector<int>& col) {
+    const int64_t ns = (nrows + 63) / 64, nb = (ns + 1) / 2;
+    std::vector<long long> width(nb, 0), base(nb + 1, 0);
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < nb; b++) {
+        int wmax = 0;
+        for (int64_t r = b * 128; r < std::min<int64_t>(nrows, (b + 1) * 128); r++)
+            wmax = std::max(wmax, rp[r + 1] - rp[r]);
+        width[b] = wmax;
+    }
+    for (int64_t b = 0; b < nb; b++) base[b + 1] = base[b] + width[b] * 128;
+    off.assign(ns + 2, base[nb]);
+    for (int64_t s = 0; s < ns; s++) off[s] = base[s >> 1] + (s & 1) * 64;
+    if (v) val.resize(base[nb]);
+    else val.clear();
+    col.resize(base[nb]);
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < nb; b++) {
+        const int w = (int)width[b];
+        for (int r = 0; r < 128; r++) {
+            const int64_t row = b * 128 + r;
+            const int len = row < nrows ? rp[row + 1] - rp[row] : 0;
+            const int last = (row < nrows && len > 0) ? ci[rp[row + 1] - 1] : 0;
+            for (int k = 0; k < w; k++) {
+                const long long slot = base[b] + (long long)k * 128 + r;
+                if (k < len) {
+                    if (v) val[slot] = v[rp[row] + k];
+                    col[slot] = ci[rp[row] + k];
+                } else {
+                    if (v) val[slot] = 0.0;
+                    col[slot] = last;
+                }
+            }
+        }
+    }
+}
+
 int validate_csr(int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
                  std::string& err) {
     if (n <= 0 || !rp || !ci || !v) { err = "n must be positive and arrays non-NULL"; return PSC_ERR_ARG; }

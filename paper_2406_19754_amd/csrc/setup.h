@@ -129,13 +129,15 @@ int gpu_smoothed_products(int64_t n, const int32_t* rp, const int32_t* ci, const
 void tentative_sp_pattern(const HostLevel& H, std::vector<int32_t>& rp, std::vector<int32_t>& ci);
 
 // Numeric rebuild, tentative prolongator: S P = (I - M^-1 A) P recomputed on
-// the device into the build's hacked-ELL slots of S P from A's refreshed
+// the device into the build's hacked-ELL slots of S P (sp_pair: the paired
+// layout) from A's refreshed
 // hacked-ELL values (a_rp: A's row pointers, device), agg, p and minv, with
 // the host's summation order (bit-identical to jacobi_smoothed_prolongator).
 // Every pointer is a device pointer; stream is a hipStream_t.
 int gpu_tentative_sp(void* stream, int64_t n, const long long* a_off, const int* a_col, const double* a_val,
                      const int32_t* a_rp, const int32_t* agg, const double* p, const double* minv,
-                     const long long* sp_off, const int* sp_col, double* sp_val, float* sp_val32, std::string& err);
+                     const long long* sp_off, const int* sp_col, double* sp_val, float* sp_val32, int sp_pair,
+                     std::string& err);
 
 // Pack CSR rows into hacked DIA with 64-row slices (offsets ascending per
 // slice, values diagonal-major in a slice, zeros where a row has no entry).
@@ -155,5 +157,11 @@ bool pack_dia(int64_t nrows, int64_t ncols, const int32_t* rp, const int32_t* ci
 // v == NULL packs the layout only (off and col; val left empty).
 void pack_ell(int64_t nrows, const int32_t* rp, const int32_t* ci, const double* v,
               std::vector<long long>& off, std::vector<double>& val, std::vector<int>& col);
+
+// The same in the paired layout of two 64-row slices per 128-row block (one
+// width per block; entry k of block row r at off[2S] + 128 k + r; off[s] =
+// off[2S] + 64 (s & 1); off has nslices + 2 entries, the last two the total).
+void pack_ell_paired(int64_t nrows, const int32_t* rp, const int32_t* ci, const double* v,
+                     std::vector<long long>& off, std::vector<double>& val, std::vector<int>& col);
 
 }  // namespace psc
