@@ -41,7 +41,7 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(info, form="fp64", fused=False, split=True, dia=True):
+def kernel_bytes(info, form="fp64", fused=False, split=True, dia=True, split_update=True):
     """Algorithmic bytes per launch of the level-0 kernels (each array once, no padding).
 
     split: smoothing through A M^-1 (pre) and A P (post), the library default.
@@ -64,6 +64,16 @@ def kernel_bytes(info, form="fp64", fused=False, split=True, dia=True):
     else:
         pre = Z * (v + 4) + 8 * N + v * N + v * N if not fused else Z * (v + 4) + 2 * 8 * N + v * N + 8 * N + v * N
         post = Z * (v + 4) + 8 * N + v * N + v * N + 4 * N + v * Nc + 8 * N
+    if fused and split and split_update:
+        # pass 2 as two kernels: r = r - alpha q (r_old, q read, r_new written),
+        # then r_0 = r_new - (A M^-1) r_new (A M^-1, r_new gathered, r_0 written)
+        pre2 = 3 * 8 * N + Z * av + 8 * N + v * N
+        return {
+            "k_spmv_pfuse": Z * a64 + 2 * 8 * N + 2 * 8 * N + 2 * 8 * N,
+            "k_rupdate + k_pre_s": pre2,
+            "k_spmv_R": N * (v + 4) + v * N + v * Nc,
+            "k_post_s": post,
+        }
     if fused:
         return {
             # A; z and p_old gathered; p_new, q written; x read and written
@@ -207,6 +217,8 @@ def main():
                     help="hacked DIA with per-slice offset arrays instead of uniform offsets in the kernel argument")
     ap.add_argument("--mixed-fused", action="store_true",
                     help="FP32 V-cycle: fuse the residual update with the level-0 pre-smoothing")
+    ap.add_argument("--fused-update", action="store_true",
+                    help="FP64 forms: residual update and level-0 pre-smoothing in one pass (PSC_TUNE_FP64_SPLIT = 0)")
     ap.add_argument("--xcd-chunks", action="store_true",
                     help="give each accelerator die a contiguous chunk of the work (default: launch order)")
     ap.add_argument("--tail-rows", type=int, default=-1,
@@ -318,6 +330,8 @@ def main():
         h.tune(psc.TUNE_XCD, 1)
     if args.mixed_fused:
         h.tune(psc.TUNE_MIXED_SPLIT, 0)
+    if args.fused_update:
+        h.tune(psc.TUNE_FP64_SPLIT, 0)
     if args.tail_rows >= 0:
         h.tune(psc.TUNE_TAIL, args.tail_rows)
     info = h.info()
@@ -378,9 +392,11 @@ def main():
     assert r64r["iters"] == r64["iters"]
     err_true = float(np.linalg.norm(xg - xt) / np.linalg.norm(xt))
 
-    kb = kernel_bytes(info, "fp64", fused=fused, split=not args.no_split, dia=not args.no_dia)
-    tname = ({"spmv_dot": "k_spmv_pfuse", "pre_smooth_l0": "k_update_pre_s", "restrict_l0": "k_spmv_R",
-              "post_smooth_l0": "k_post_s"} if fused else {})
+    split_update = not args.fused_update and not args.no_split
+    kb = kernel_bytes(info, "fp64", fused=fused, split=not args.no_split, dia=not args.no_dia,
+                      split_update=split_update)
+    tname = ({"spmv_dot": "k_spmv_pfuse", "pre_smooth_l0": "k_rupdate + k_pre_s" if split_update else "k_update_pre_s",
+              "restrict_l0": "k_spmv_R", "post_smooth_l0": "k_post_s"} if fused else {})
     kernels = {}
     for name, (cnt, tot) in kt64.items():
         kname = tname.get(name, name)

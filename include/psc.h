@@ -423,6 +423,11 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
  * 0 fuses them, recomputing r at every gathered neighbour from FP64 r and q.
  * Same values either way. */
 #define PSC_TUNE_MIXED_SPLIT 11
+/* PSC_TUNE_FP64_SPLIT (default 1): the same two passes with the FP64 V-cycle
+ * (r -= alpha q, then the level-0 pre-smoothing residual gathering r); 0 fuses
+ * them into one pass that recomputes r at every gathered neighbour. Same
+ * values either way. */
+#define PSC_TUNE_FP64_SPLIT 12
 int psc_tune(psc_hier* h, int32_t key, int32_t value);
 
 void psc_hier_free(psc_hier* h);

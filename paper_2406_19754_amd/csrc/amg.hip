@@ -2109,6 +2109,7 @@ struct psc_hier {
     bool dia = true;                      // use the hacked-DIA copies where a level has them
     bool dia_uniform = true;              // a level with <= 8 distinct offsets keeps them in the kernel argument
     bool mixed_split = true;              // FP32 V-cycle: residual update and pre-smoothing as two passes
+    bool fp64_split = true;               // FP64 V-cycle: the same two passes
     float* r32 = nullptr;                 // FP32 copy of the outer residual (mixed_split)
     // Small levels in one workgroup (k_tail): off by default. Under graph
     // replay each small kernel costs about as much as one latency-bound round
@@ -3220,7 +3221,14 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
                 TimeScope t(h, 2);
                 if (h->fai || h->cheb)
                     k_rupdate<<<ge, WG, 0, st>>>(L0.A.nslices, n, rold, h->q, rnew, red_of(h, FIN_UPDATE_PCG));
-                else if (h->split)
+                else if (h->split && h->fp64_split) {
+                    // r = r - alpha q, then the level-0 pre-smoothing residual
+                    // gathering r: the same values as the fused pass, half its gathers
+                    k_rupdate<<<ge, WG, 0, st>>>(L0.A.nslices, n, rold, h->q, rnew, red_of(h, FIN_UPDATE_PCG));
+                    with_AM(h, L0, [&](auto AM) {
+                        k_pre_s<decltype(AM), double, 4><<<ge, WG, 0, st>>>(AM, rnew, pre_rbuf<double>(h, L0, 1), gd);
+                    });
+                } else if (h->split)
                     with_AM(h, L0, [&](auto AM) {
                         k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, pre_rbuf<double>(h, L0, 1),
                                                                         red_of(h, FIN_UPDATE_PCG));
@@ -3284,7 +3292,13 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
                             k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, pre_rbuf<float>(h, L0, 1),
                                                                             red_of(h, FIN_UPDATE_FCG));
                         });
-                    else
+                    else if (h->fp64_split) {
+                        k_rupdate<<<ge, WG, 0, st>>>(L0.A.nslices, n, rold, h->q, rnew, red_of(h, FIN_UPDATE_FCG));
+                        with_AM(h, L0, [&](auto AM) {
+                            k_pre_s<decltype(AM), double, 4><<<ge, WG, 0, st>>>(AM, rnew, pre_rbuf<double>(h, L0, 1),
+                                                                                gd);
+                        });
+                    } else
                         with_AM(h, L0, [&](auto AM) {
                             k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, pre_rbuf<double>(h, L0, 1),
                                                                             red_of(h, FIN_UPDATE_FCG));
@@ -4277,6 +4291,11 @@ int psc_tune(psc_hier* h, int32_t key, int32_t value) {
         h->dia = value != 0;
         drop_graphs(h);
         return build_tail(h);
+    }
+    if (key == PSC_TUNE_FP64_SPLIT) {
+        h->fp64_split = value != 0;
+        drop_graphs(h);
+        return PSC_OK;
     }
     if (key == PSC_TUNE_MIXED_SPLIT) {
         h->mixed_split = value != 0;

@@ -550,3 +550,23 @@ def test_mixed_split_passes_equal_fused_bit_for_bit(psc):
         out.append((g["iters"], x))
     assert out[0][0] == out[1][0]
     assert torch.equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("form", ["pcg", "fcg"])
+def test_fp64_split_update_equals_fused_bit_for_bit(psc, form):
+    """FP64 second pass as two kernels (r -= alpha q, then the level-0
+    pre-smoothing residual gathering r) equals the fused pass that recomputes
+    r at every gathered neighbour: bit-identical iterates, also across FCG's
+    residual replacements (rtol 1e-11)."""
+    rp, c, v = P.diffusion7(24, seed=3, az=0.01)
+    b = dev(P.rhs_from_solution(rp, c, v, P.x_true(24 ** 3, 2)))
+    out = []
+    for split in (1, 0):
+        h = psc.Hierarchy(rp, c, v)
+        h.tune(psc.TUNE_FP64_SPLIT, split)
+        x = torch.zeros(len(b), dtype=torch.float64, device="cuda")
+        g = h.pcg(b, x, rtol=1e-9) if form == "pcg" else h.fcg(b, x, rtol=1e-11, maxit=400)
+        assert g["status"] == psc.OK
+        out.append((g["iters"], x))
+    assert out[0][0] == out[1][0]
+    assert torch.equal(out[0][1], out[1][1])
