@@ -1936,8 +1936,19 @@ __global__ __launch_bounds__(WG) void k_rupdate(long long nslices, long long n, 
     const double nalpha = -R.ctl->alpha;
     long long lo, hi;
     chunk_range(nslices, lo, hi);
+    const long long end = hi * SLICE < n ? hi * SLICE : n;
     double s0 = 0.0;
-    for (long long i = lo * SLICE + threadIdx.x; i < hi * SLICE && i < n; i += WG) {
+    // two elements per thread (16-byte loads); the range starts on an even index
+    long long i = lo * SLICE + 2 * threadIdx.x;
+    for (; i + 1 < end; i += 2 * WG) {
+        const v2u<double> qq = ld2(q + i), rr = ld2(rold + i);
+        const double r0 = fma(nalpha, qq.x, rr.x), r1 = fma(nalpha, qq.y, rr.y);
+        st2(rnew + i, r0, r1);
+        if (rnew32) st2(rnew32 + i, (float)r0, (float)r1);
+        s0 += r0 * r0;
+        s0 += r1 * r1;
+    }
+    if (i < end) {   // odd tail (last element)
         const double rn = fma(nalpha, q[i], rold[i]);
         rnew[i] = rn;
         if (rnew32) rnew32[i] = (float)rn;
