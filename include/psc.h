@@ -456,9 +456,10 @@ int psc_net_apply(psc_net* net, const double* r_dev, double* z_dev, int32_t nx,
  * psc_net_apply without any device allocation, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc). Same result as psc_net_apply (the same
- * kernels); its scratch (activations and the norm reduction, 66 bytes per
- * cell plus 8.5 KB) lives in a fixed array of about 17.3 MB that every device
- * the library runs on holds until the process ends. Grids above
+ * kernels); its scratch (the norm reduction, 8.5 KB, and with the unfused
+ * kernels of psc_net_tune the activations, 66 bytes per cell) lives in a
+ * fixed array of about 17.3 MB that every device the library runs on holds
+ * until the process ends. Grids above
  * PSC_NET_NOALLOC_MAX_CELLS cells (64^3) return PSC_ERR_ARG. The handle's own
  * grid buffers are neither used nor changed. All calls on one device share
  * that array: calls that overlap on one device (several host threads, or
@@ -484,6 +485,22 @@ int psc_net_create_l1jacobi(const psc_hier* h, void* hip_stream, psc_net** out);
 
 /* Declare the grid used by psc_fcg_solve (n = nx*ny*nz). */
 int psc_net_set_grid(psc_net* net, int32_t nx, int32_t ny, int32_t nz);
+
+/*
+ * Inference kernels of psc_net_apply, psc_net_apply_noalloc and the network
+ * steps of psc_fcg_solve. PSC_NET_TUNE_FUSED (default 1): one kernel computes
+ * the three layers, walking 16 x 16 columns of the grid plane by plane with
+ * the activations in LDS (16 bytes of HBM traffic per cell: r in, z out;
+ * every layer on MFMA, the third as 27 tap projections of each cell summed
+ * over its neighbours); 0: one kernel per layer with bfloat16 activation
+ * fields in device memory (66 bytes per cell, allocated by psc_net_set_grid).
+ * The two agree up to FP32 summation order, which can move a bfloat16
+ * rounding of an activation. Without layers (the l1-Jacobi alternate) the
+ * call does nothing. Errors: PSC_ERR_ARG (NULL handle, unknown key),
+ * PSC_ERR_OOM, PSC_ERR_HIP.
+ */
+#define PSC_NET_TUNE_FUSED 1
+int psc_net_tune(psc_net* net, int32_t key, int32_t value);
 
 /*
  * Batched forward / loss-gradient on B cubic crops of side D (float, device):

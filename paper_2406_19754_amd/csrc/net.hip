@@ -73,7 +73,36 @@ __host__ __device__ inline bf16r f2bf(float f) {
     return (bf16r)(u >> 16);
 }
 __device__ inline float bf2f(bf16r b) { return __uint_as_float((unsigned)b << 16); }
-__device__ inline float gelu(float t) { return 0.5f * t * (1.0f + erff(t * 0.70710678118654752f)); }
+// GELU(t) = t Phi(t) with Phi(t) = erfc(-t / sqrt 2) / 2, erfc(z) (z >= 0)
+// from the Chebyshev fit erfc(z) = u exp(-z^2 + P(u)), u = 1 / (1 + z/2), of
+// Press et al., Numerical Recipes (their erfcc; fractional error below
+// 1.2e-7 for every z >= 0), evaluated branch-free in FP32 with the hardware
+// reciprocal and exp2. In FP32 the result is within 5e-7 relative of the
+// exact GELU for |t| <= 1, 2e-6 for -4 <= t <= -1 and 1.4e-7 for t >= 1;
+// unlike 1 + erf(t / sqrt 2), it does not cancel for negative t.
+__device__ inline float gelu(float t) {
+    const float z = fabsf(t) * 0.70710678118654752f;
+    const float u = __builtin_amdgcn_rcpf(fmaf(0.5f, z, 1.0f));
+    float p = 0.17087277f;
+    p = fmaf(p, u, -0.82215223f);
+    p = fmaf(p, u, 1.48851587f);
+    p = fmaf(p, u, -1.13520398f);
+    p = fmaf(p, u, 0.27886807f);
+    p = fmaf(p, u, -0.18628806f);
+    p = fmaf(p, u, 0.09678418f);
+    p = fmaf(p, u, 0.37409196f);
+    p = fmaf(p, u, 1.00002368f);
+    p = fmaf(p, u, -1.26551223f);
+    const float e = u * __builtin_amdgcn_exp2f(fmaf(-z, z, p) * 1.44269504088896341f);   // erfc(z)
+    const float phi = t >= 0.0f ? fmaf(-0.5f, e, 1.0f) : 0.5f * e;
+    return t * phi;
+}
+// two floats to bfloat16 (round to nearest even), packed low then high
+__device__ inline unsigned pack_bf16(float lo, float hi) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(unsigned, v);
+}
 __device__ inline float gelu_d(float t) {
     return 0.5f * (1.0f + erff(t * 0.70710678118654752f)) + t * expf(-0.5f * t * t) * 0.39894228040143268f;
 }
@@ -309,6 +338,253 @@ __global__ __launch_bounds__(WG) void k_conv3(Dims d, const bf16r* __restrict__ 
         z64[c] = s * (double)acc;
     } else {
         out32[c] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fused inference: the three layers in one kernel
+// ---------------------------------------------------------------------------
+//
+// One workgroup owns a 16 x 16 column of output cells in (x, y) and a range
+// of z-planes, and walks it plane by plane, so that only r is read and z
+// written in HBM (16 bytes per cell, plus the re-read halo of r). Output
+// plane k-1 needs h2 on planes k-2..k over the 18 x 18 cells around the
+// tile; h2 needs h1 on 20 x 20 cells and h1 needs u on 22 x 22. Step k
+//   (1) stores u = bf16(r/s) of plane k+2 (22 x 22) in an LDS ring of three
+//       planes (r was loaded into registers during step k-1);
+//   (2) computes h1 on plane k+1 (20 x 20 cells) into an LDS ring of three
+//       planes, channel-last in two 8-channel halves: per 16 cells one
+//       16x16x32 MFMA, W1 (16 channels x 27 taps, padded to 32) as the A
+//       operand and the cells' 27 input taps as the B operand;
+//   (3) computes h2 on plane k (18 x 18 cells): the implicit GEMM of the
+//       16 -> 16 layer (14 MFMA steps, K = (tap, channel)) with the weight
+//       fragments as the A operand and the cells' neighbourhoods, read from
+//       the h1 ring, as the B operand, so that a lane ends with four channels
+//       of one cell; those registers are at once the B operand of two
+//       16x16x16 MFMAs with W3 transposed (taps x channels), which give the 27
+//       tap projections g_t(c) = sum_ch W3[ch][t] h2[ch](c) of every cell,
+//       stored in LDS;
+//   (4) adds for every output cell the projections g_t(c + offset_t) of the
+//       9 taps with each dz to the plane they feed (k+1, k, k-1), kept in
+//       three registers; plane k-1 is then complete: z = s (b3 + sum).
+// Every convolution sums in FP32 (MFMA), activations are bfloat16 and zero
+// outside the sample (the zero padding). Results equal the unfused kernels'
+// up to FP32 summation order (which can move a bfloat16 rounding).
+constexpr int FT = 16;                                       // output tile edge in x and y
+constexpr int FE0 = FT + 6, FE1 = FT + 4, FE2 = FT + 2;      // u, h1, h2 region edges
+constexpr int FN0 = FE0 * FE0, FN1 = FE1 * FE1, FN2 = FE2 * FE2;
+constexpr int FT1 = (FN1 + 15) / 16, FT2 = (FN2 + 15) / 16;  // MFMA tiles of h1, h2
+constexpr int FU_STRIDE = (FN0 + 7) & ~7;                    // bf16 elements per u plane
+constexpr int FR_PER = (FN0 + WG - 1) / WG;                  // r values per thread and plane
+// dynamic LDS, bytes: h1 ring u32x4[3][2][FN1] | projections float[27][FN2] | u ring bf16[3][FU_STRIDE]
+constexpr int FL_H1 = 0;
+constexpr int FL_G = FL_H1 + 3 * 2 * FN1 * 16;
+constexpr int FL_U = FL_G + 27 * FN2 * 4;
+constexpr int FL_BYTES = FL_U + 3 * FU_STRIDE * 2;
+static_assert(FN1 % 16 == 0, "h1 region is whole MFMA tiles");
+static_assert(FL_G % 16 == 0 && FL_U % 16 == 0, "LDS regions aligned");
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int ring3(int p) { return ((p % 3) + 3) % 3; }
+__device__ __forceinline__ int slot3(int s0, int dz) { return s0 + dz >= 3 ? s0 + dz - 3 : s0 + dz; }
+__device__ __forceinline__ unsigned wbits(float w) { return __float_as_uint(w) >> 16; }   // bf16-valued float
+
+__global__ __launch_bounds__(WG) void k_net_fused(Dims d, int zc, const double* __restrict__ r, const double* rr,
+                                                  long long N, const float* __restrict__ wr,
+                                                  const bf16x8* __restrict__ frag, double* __restrict__ z, Gate g) {
+    if (gate_skip(g)) return;
+    extern __shared__ __align__(16) unsigned char fl[];
+    u32x4* h1s = (u32x4*)(fl + FL_H1);
+    float* gs = (float*)(fl + FL_G);
+    bf16r* us = (bf16r*)(fl + FL_U);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n16 = lane & 15, grp = lane >> 4;
+    const int ntx = (d.W + FT - 1) / FT, nty = (d.H + FT - 1) / FT;
+    long long bid = blockIdx.x;
+    const int x0 = (int)(bid % ntx) * FT;
+    bid /= ntx;
+    const int y0 = (int)(bid % nty) * FT;
+    bid /= nty;
+    const int z0 = (int)bid * zc;
+    const int z1 = min(z0 + zc, d.D);
+    const double s = sqrt(*rr / (double)N);
+    const double s_inv = s > 0.0 ? 1.0 / s : 0.0;
+
+    // weights of the working copy (bfloat16 values) as MFMA A operands
+    bf16x8 w1f;   // W1[co = n16][tap 8 grp + j]
+    {
+        unsigned pk[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int t0 = 8 * grp + 2 * j, t1 = t0 + 1;
+            const unsigned lo = t0 < 27 ? wbits(wr[OW1 + n16 * 27 + t0]) : 0u;
+            const unsigned hi = t1 < 27 ? wbits(wr[OW1 + n16 * 27 + t1]) : 0u;
+            pk[j] = lo | (hi << 16);
+        }
+        w1f = __builtin_bit_cast(bf16x8, u32x4{pk[0], pk[1], pk[2], pk[3]});
+    }
+    s16x4 w3f[2];   // W3[ch = 4 grp + i][tap = 16 m + n16]
+#pragma unroll
+    for (int m = 0; m < 2; m++) {
+        const int t = 16 * m + n16;
+        unsigned pk[2];
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const int c0 = 4 * grp + 2 * j;
+            const unsigned lo = t < 27 ? wbits(wr[OW3 + c0 * 27 + t]) : 0u;
+            const unsigned hi = t < 27 ? wbits(wr[OW3 + (c0 + 1) * 27 + t]) : 0u;
+            pk[j] = lo | (hi << 16);
+        }
+        w3f[m] = __builtin_bit_cast(s16x4, make_uint2(pk[0], pk[1]));
+    }
+    bf16x8 w2f[KSTEPS];
+#pragma unroll
+    for (int st = 0; st < KSTEPS; st++) w2f[st] = frag[st * 64 + lane];
+    float b1v[4], b2v[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        b1v[i] = wr[OB1 + 4 * grp + i];
+        b2v[i] = wr[OB2 + 4 * grp + i];
+    }
+    const float b3 = wr[OB3];
+    // this lane's 8 layer-1 taps: offset in the u plane and dz (taps past 26
+    // have zero weights; they read tap 26's input, which is finite)
+    int t1off[8], t1dz[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        const int t = min(8 * grp + j, 26);
+        t1dz[j] = t / 9;
+        t1off[j] = ((t / 3) % 3) * FE0 + t % 3;
+    }
+
+    // r of plane p, cells tid + WG i of the 22 x 22 region, into registers
+    double rv[FR_PER];
+    auto load_r = [&](int p) {
+#pragma unroll
+        for (int i = 0; i < FR_PER; i++) {
+            const int q = tid + WG * i;
+            const int gx = x0 - 3 + q % FE0, gy = y0 - 3 + q / FE0;
+            rv[i] = 0.0;
+            if (q < FN0 && p >= 0 && p < d.D && gx >= 0 && gx < d.W && gy >= 0 && gy < d.H)
+                rv[i] = r[((long long)p * d.H + gy) * d.W + gx];
+        }
+    };
+    auto store_u = [&](int p) {
+        bf16r* up = us + ring3(p) * FU_STRIDE;
+#pragma unroll
+        for (int i = 0; i < FR_PER; i++) {
+            const int q = tid + WG * i;
+            if (q < FN0) up[q] = f2bf((float)(rv[i] * s_inv));
+        }
+    };
+    // (out-of-sample cells hold r = 0, so u = 0 there: the zero padding)
+    load_r(z0 - 3);
+    store_u(z0 - 3);
+    load_r(z0 - 2);
+    store_u(z0 - 2);
+    load_r(z0 - 1);
+
+    float oacc[3] = {0.f, 0.f, 0.f};   // output planes k-1, k, k+1
+    const int ox = tid & 15, oy = tid >> 4;
+    for (int k = z0 - 3; k <= z1; k++) {
+        // (1) u of plane k+2; start loading r of plane k+3
+        store_u(k + 2);
+        load_r(k + 3);
+        __syncthreads();
+        // (2) h1 of plane k+1
+        {
+            const int p1 = k + 1;
+            u32x4* h1p = h1s + ring3(p1) * 2 * FN1;
+            const bool in1 = p1 >= 0 && p1 < d.D;
+            const int s0 = ring3(p1 - 1);   // u slots of planes p1-1, p1, p1+1: s0, s0+1, s0+2 (mod 3)
+            for (int T = wv; T < FT1; T += WG / 64) {
+                const int q = T * 16 + n16;
+                const int hx = q % FE1, hy = q / FE1;
+                const int gx = x0 - 2 + hx, gy = y0 - 2 + hy;
+                unsigned o0 = 0u, o1 = 0u;
+                if (in1) {
+                    unsigned pk[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const int ja = 2 * j, jb = 2 * j + 1;
+                        const unsigned lo = us[slot3(s0, t1dz[ja]) * FU_STRIDE + hy * FE0 + hx + t1off[ja]];
+                        const unsigned hi = us[slot3(s0, t1dz[jb]) * FU_STRIDE + hy * FE0 + hx + t1off[jb]];
+                        pk[j] = lo | (hi << 16);
+                    }
+                    const bf16x8 B = __builtin_bit_cast(bf16x8, u32x4{pk[0], pk[1], pk[2], pk[3]});
+                    const f32x4 a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f, B, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                    if (gx >= 0 && gx < d.W && gy >= 0 && gy < d.H) {
+                        o0 = pack_bf16(gelu(a[0] + b1v[0]), gelu(a[1] + b1v[1]));
+                        o1 = pack_bf16(gelu(a[2] + b1v[2]), gelu(a[3] + b1v[3]));
+                    }
+                }
+                // channels 4 grp .. 4 grp + 3 of cell q
+                uint2* dst = (uint2*)(h1p + (grp >> 1) * FN1 + q) + (grp & 1);
+                *dst = make_uint2(o0, o1);
+            }
+        }
+        __syncthreads();
+        // (3) h2 of plane k and its tap projections
+        const bool in2 = k >= z0 - 1 && k >= 0 && k < d.D;
+        if (in2) {
+            const int s0 = ring3(k - 1);   // h1 slots of planes k-1, k, k+1
+            for (int T = wv; T < FT2; T += WG / 64) {
+                const int q = T * 16 + n16;
+                const bool valid = q < FN2;
+                // cells past the region read cell 0 (their column of the product
+                // is dropped); tap 27 (zero weights) reads tap 26's input
+                const int ax = valid ? q % FE2 : 0, ay = valid ? q / FE2 : 0;
+                const int gx = x0 - 1 + ax, gy = y0 - 1 + ay;
+                const int base = ay * FE1 + ax + (grp & 1) * FN1;
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int st = 0; st < KSTEPS; st++) {
+                    const int tap = min(2 * st + (grp >> 1), 26);
+                    const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+                    const u32x4 av = h1s[slot3(s0, dz) * 2 * FN1 + base + dy * FE1 + dx];
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2f[st], __builtin_bit_cast(bf16x8, av), acc, 0, 0, 0);
+                }
+                unsigned o0 = 0u, o1 = 0u;
+                if (valid && gx >= 0 && gx < d.W && gy >= 0 && gy < d.H) {
+                    o0 = pack_bf16(gelu(acc[0] + b2v[0]), gelu(acc[1] + b2v[1]));
+                    o1 = pack_bf16(gelu(acc[2] + b2v[2]), gelu(acc[3] + b2v[3]));
+                }
+                const s16x4 hv = __builtin_bit_cast(s16x4, make_uint2(o0, o1));
+                const f32x4 g0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w3f[0], hv, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                const f32x4 g1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w3f[1], hv, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                if (valid) {
+#pragma unroll
+                    for (int i = 0; i < 4; i++) {
+                        gs[(4 * grp + i) * FN2 + q] = g0[i];
+                        const int t = 16 + 4 * grp + i;
+                        if (t < 27) gs[t * FN2 + q] = g1[i];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // (4) projections of plane k into output planes k+1 (dz = 0), k, k-1
+        if (in2) {
+#pragma unroll
+            for (int dz = 0; dz < 3; dz++) {
+                float sum = oacc[2 - dz];
+#pragma unroll
+                for (int dy = 0; dy < 3; dy++)
+#pragma unroll
+                    for (int dx = 0; dx < 3; dx++)
+                        sum += gs[(dz * 9 + dy * 3 + dx) * FN2 + (oy + dy) * FE2 + ox + dx];
+                oacc[2 - dz] = sum;
+            }
+        }
+        const int pk1 = k - 1;
+        if (pk1 >= z0 && pk1 < z1) {
+            const int gx = x0 + ox, gy = y0 + oy;
+            if (gx < d.W && gy < d.H) z[((long long)pk1 * d.H + gy) * d.W + gx] = s * (double)(b3 + oacc[0]);
+        }
+        oacc[0] = oacc[1];
+        oacc[1] = oacc[2];
+        oacc[2] = 0.f;
     }
 }
 
@@ -643,6 +919,7 @@ struct psc_net {
     bf16r *ffwd = nullptr, *fbwd = nullptr;
     long long adam_t = 0;
     // inference grid
+    int fused = 1;                  // 1: the fused 3-layer kernel; 0: one kernel per layer
     int gx = 0, gy = 0, gz = 0;
     long long gcells = 0;
     bf16r *u = nullptr, *h1 = nullptr, *h2 = nullptr;
@@ -712,6 +989,35 @@ static void forward(psc_net* n, hipStream_t st, const Dims& d, const double* r64
     else k_conv3<false><<<blocks_for(cells), WG, 0, st>>>(d, h2, n->wr, nullptr, 1, nullptr, out32, g);
 }
 
+// z = s net(r/s) on one sample (d.B = 1) by the fused kernel: workgroups of
+// 16 x 16 output columns, the z-range cut into chunks so that the grid has
+// about 2048 workgroups (chunks of at least 8 planes).
+static int fused_lds_ready(int dev) {
+    static std::mutex mu;
+    static bool done[64] = {};
+    if (dev < 0 || dev >= 64) return nfail(PSC_ERR_ARG, "device ordinal beyond the fused-kernel table");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!done[dev]) {
+        if (FL_BYTES > 64 * 1024)
+            NHIPCHK(hipFuncSetAttribute((const void*)k_net_fused, hipFuncAttributeMaxDynamicSharedMemorySize, FL_BYTES));
+        done[dev] = true;
+    }
+    return PSC_OK;
+}
+
+static int forward_fused(psc_net* n, hipStream_t st, const Dims& d, const double* r64, const double* rr, long long N,
+                         double* z64, Gate g) {
+    int rc = fused_lds_ready(n->device);
+    if (rc) return rc;
+    const long long tiles = (long long)((d.W + FT - 1) / FT) * ((d.H + FT - 1) / FT);
+    long long nch = (2048 + tiles - 1) / tiles;
+    nch = std::max<long long>(1, std::min<long long>(nch, d.D / 8));
+    const int zc = (int)((d.D + nch - 1) / nch);
+    const long long blocks = tiles * ((d.D + zc - 1) / zc);
+    k_net_fused<<<(unsigned)blocks, WG, FL_BYTES, st>>>(d, zc, r64, rr, N, n->wr, (const bf16x8*)n->ffwd, z64, g);
+    return PSC_OK;
+}
+
 // Loss and gradient of the current batch (in_b, tgt_b) into n->grad; loss
 // (mean) into *loss_dst (device double) and, if given, loss32 (device float).
 static void loss_grad(psc_net* n, hipStream_t st, const Dims& d, int margin, double* loss_dst, float* loss32) {
@@ -757,6 +1063,7 @@ int net_launch_apply(psc_net* n, hipStream_t st, const double* r, double* z, con
         return PSC_OK;
     }
     Dims d{1, n->gz, n->gy, n->gx};
+    if (n->fused) return forward_fused(n, st, d, r, rr_dev, N, z, g);
     forward(n, st, d, r, nullptr, rr_dev, N, n->u, n->h1, n->h2, nullptr, nullptr, z, nullptr, g);
     return PSC_OK;
 }
@@ -875,6 +1182,26 @@ int psc_net_set_params(psc_net* n, const float* params) {
     return join_out(n);
 }
 
+}  // extern "C"
+
+namespace psc {
+// The per-layer activations of the unfused inference kernels (u, h1, h2) for
+// `cells` cells; none with the fused kernel. Bumps the generation, so that
+// captured solver iterations are captured again.
+static int grid_buffers(psc_net* n, long long cells) {
+    for (bf16r** p : {&n->u, &n->h1, &n->h2})
+        if (*p) { (void)hipFree(*p); *p = nullptr; }
+    n->gen += 1;
+    if (n->fused || cells == 0) return PSC_OK;
+    NHIPCHK(hipMalloc((void**)&n->u, (size_t)cells * 2));
+    NHIPCHK(hipMalloc((void**)&n->h1, (size_t)cells * NC * 2));
+    NHIPCHK(hipMalloc((void**)&n->h2, (size_t)cells * NC * 2));
+    return PSC_OK;
+}
+}  // namespace psc
+
+extern "C" {
+
 int psc_net_set_grid(psc_net* n, int32_t nx, int32_t ny, int32_t nz) {
     if (!n || nx < 1 || ny < 1 || nz < 1) return nfail(PSC_ERR_ARG, "bad grid");
     const long long cells = (long long)nx * ny * nz;
@@ -885,19 +1212,27 @@ int psc_net_set_grid(psc_net* n, int32_t nx, int32_t ny, int32_t nz) {
     if (n->gx == nx && n->gy == ny && n->gz == nz) return PSC_OK;
     NHIPCHK(hipSetDevice(n->device));
     NHIPCHK(hipStreamSynchronize(n->stream));
-    for (bf16r** p : {&n->u, &n->h1, &n->h2})
-        if (*p) { (void)hipFree(*p); *p = nullptr; }
     n->gx = n->gy = n->gz = 0;
     n->gcells = 0;
-    NHIPCHK(hipMalloc((void**)&n->u, (size_t)cells * 2));
-    NHIPCHK(hipMalloc((void**)&n->h1, (size_t)cells * NC * 2));
-    NHIPCHK(hipMalloc((void**)&n->h2, (size_t)cells * NC * 2));
+    const int st = grid_buffers(n, cells);
+    if (st) return st;
     n->gx = nx;
     n->gy = ny;
     n->gz = nz;
     n->gcells = cells;
-    n->gen += 1;
     return PSC_OK;
+}
+
+int psc_net_tune(psc_net* n, int32_t key, int32_t value) {
+    if (!n) return nfail(PSC_ERR_ARG, "NULL network");
+    if (key != PSC_NET_TUNE_FUSED) return nfail(PSC_ERR_ARG, "unknown network tuning key");
+    if (n->kind != 0) return PSC_OK;   // the l1-Jacobi alternate has no layers
+    const int f = value != 0;
+    if (f == n->fused) return PSC_OK;
+    NHIPCHK(hipSetDevice(n->device));
+    NHIPCHK(hipStreamSynchronize(n->stream));
+    n->fused = f;
+    return grid_buffers(n, n->gcells);
 }
 
 int psc_net_apply(psc_net* n, const double* r, double* z, int32_t nx, int32_t ny, int32_t nz) {
@@ -916,7 +1251,8 @@ int psc_net_apply(psc_net* n, const double* r, double* z, int32_t nx, int32_t ny
     const unsigned nb = 1024;
     k_sumsq<<<nb, WG, 0, n->stream>>>(N, r, n->dpart);
     k_sum_partials<<<1, WG, 0, n->stream>>>(n->dpart, (int)nb, 1.0, n->rr, nullptr);
-    net_launch_apply(n, n->stream, r, z, n->rr, N, Gate{nullptr, GATE_NONE});
+    st = net_launch_apply(n, n->stream, r, z, n->rr, N, Gate{nullptr, GATE_NONE});
+    if (st) return st;
     NHIPCHK(hipGetLastError());
     NHIPCHK(hipStreamSynchronize(n->stream));
     return join_out(n);
@@ -1066,7 +1402,12 @@ int psc_net_apply_noalloc(psc_net* n, const double* r, double* z, int32_t nx, in
     k_sumsq<<<NA_PARTS, WG, 0, n->stream>>>(N, r, part);
     k_sum_partials<<<1, WG, 0, n->stream>>>(part, NA_PARTS, 1.0, rr, nullptr);
     const Dims d{1, nz, ny, nx};
-    forward(n, n->stream, d, r, nullptr, rr, N, u, h1, h2, nullptr, nullptr, z, nullptr, Gate{nullptr, GATE_NONE});
+    if (n->fused) {
+        st = forward_fused(n, n->stream, d, r, rr, N, z, Gate{nullptr, GATE_NONE});
+        if (st) return st;
+    } else {
+        forward(n, n->stream, d, r, nullptr, rr, N, u, h1, h2, nullptr, nullptr, z, nullptr, Gate{nullptr, GATE_NONE});
+    }
     NHIPCHK(hipGetLastError());
     NHIPCHK(hipStreamSynchronize(n->stream));
     return join_out(n);

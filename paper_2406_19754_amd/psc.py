@@ -25,6 +25,7 @@ AGGR_MATCHING, AGGR_VBM = 0, 1
 SMOOTH_L1JACOBI, SMOOTH_AINV, SMOOTH_INVK, SMOOTH_CHEB4 = 0, 1, 2, 3
 MAX_LEVELS = 32
 NET_NOALLOC_MAX_CELLS = 262144
+NET_TUNE_FUSED = 1
 TIMING_KERNELS = 8
 TIMING_NAMES = ["spmv_dot", "cg_update", "pre_smooth_l0", "restrict_l0", "post_smooth_l0",
                 "dir_update", "vcycle", "other_levels"]
@@ -96,6 +97,7 @@ def _load():
         "psc_net_set_params": ([vp, vp], C.c_int),
         "psc_net_apply": ([vp, vp, vp, i32, i32, i32], C.c_int),
         "psc_net_set_grid": ([vp, i32, i32, i32], C.c_int),
+        "psc_net_tune": ([vp, i32, i32], C.c_int),
         "psc_net_apply_noalloc": ([vp, vp, vp, i32, i32, i32], C.c_int),
         "psc_net_forward_batch": ([vp, vp, vp, i32, i32], C.c_int),
         "psc_net_loss_grad": ([vp, vp, vp, i32, i32, i32, P(f32), vp], C.c_int),
@@ -334,6 +336,11 @@ class Net:
     def set_grid(self, dims):
         nz, ny, nx = dims
         _check(_lib.psc_net_set_grid(self._h, nx, ny, nz))
+
+    def tune(self, key, value):
+        """psc_net_tune (NET_TUNE_FUSED: fused 3-layer inference kernel or one
+        kernel per layer)."""
+        _check(_lib.psc_net_tune(self._h, key, value))
 
     def apply(self, r, z, dims):
         nz, ny, nx = dims

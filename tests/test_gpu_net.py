@@ -117,6 +117,59 @@ def test_net_apply_matches_oracle(psc):
     elementwise(z.cpu().numpy(), ref, "apply 9x10x12")
 
 
+@pytest.mark.parametrize("dims", [(9, 10, 12), (40, 33, 35), (17, 48, 16)])
+def test_fused_and_unfused_apply_match_oracle(psc, dims):
+    """Both inference paths (psc_net_tune) against the oracle and each other.
+    (40, 33, 35) cuts z into 5 chunks of 8 planes with ragged 16-wide x and y
+    tiles; (17, 48, 16) has whole tiles in x and three in y."""
+    p = params(21)
+    N = int(np.prod(dims))
+    r = np.random.default_rng(22).standard_normal(N)
+    ref = oracle.net_apply(p.astype(np.float64), r, dims)
+    net = psc.Net(p)
+    rd = torch.from_numpy(r).cuda()
+    out = {}
+    for fused in (1, 0, 1):
+        net.tune(psc.NET_TUNE_FUSED, fused)
+        z = torch.full_like(rd, float("nan"))
+        net.apply(rd, z, dims)
+        out[fused] = z.cpu().numpy()
+        elementwise(out[fused], ref, f"apply {dims} fused={fused}")
+    elementwise(out[1], out[0], f"fused vs unfused {dims}")
+
+
+def test_fused_apply_sampled_at_128(psc):
+    """The fused kernel on the learned form's 128^3 grid, checked at 256 cells
+    (corners, faces and interior) against the oracle on the part of the 7^3
+    neighbourhood each output depends on that lies in the grid (the oracle's
+    zero padding then falls where the grid's does), with s = ||r|| / sqrt(N)."""
+    n = 128
+    dims, N = (n, n, n), n ** 3
+    p = params(23)
+    rng = np.random.default_rng(24)
+    r = rng.standard_normal(N)
+    net = psc.Net(p)
+    rd = torch.from_numpy(r).cuda()
+    z = torch.full_like(rd, float("nan"))
+    net.apply(rd, z, dims)
+    zg = z.cpu().numpy().reshape(dims)
+    assert np.isfinite(zg).all()
+    s = np.linalg.norm(r) / np.sqrt(N)
+    u = (r / s).reshape(dims)
+    cells = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 5), (n - 1, 0, 64), (3, 2, 1)]
+    cells += [tuple(c) for c in rng.integers(0, n, (251, 3))]
+    ref = []
+    for c in cells:
+        lo = [max(0, a - 3) for a in c]
+        hi = [min(n, a + 4) for a in c]
+        crop = u[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]]
+        out = oracle.net_forward(p.astype(np.float64), crop[None], round_bf16=True)[0]
+        ref.append(out[c[0] - lo[0], c[1] - lo[1], c[2] - lo[2]] * s)
+    ref = np.array(ref)
+    gpu = np.array([zg[c] for c in cells])
+    elementwise(gpu, ref, "fused apply 128^3, 256 sampled cells", q_tol=2e-3)
+
+
 def test_zero_network_falls_back_to_vcycle(psc):
     n = 16
     rp, c, v = P.poisson7(n)

@@ -31,16 +31,20 @@ def _apply(psc, fn, net, r, dims):
     return z
 
 
-def test_noalloc_apply_matches_apply(psc):
+@pytest.mark.parametrize("fused", [1, 0])
+def test_noalloc_apply_matches_apply(psc, fused):
+    """With the fused inference kernel (scratch: the norm reduction only) and
+    with one kernel per layer (scratch: the activations as well)."""
     L = psc.lib()
     p = (P.net_init(11).astype(np.float64) * 0.7 + 0.03 * np.random.default_rng(12).standard_normal(7809))
     net = psc.Net(p.astype(np.float32))
+    net.tune(psc.NET_TUNE_FUSED, fused)
     rng = np.random.default_rng(13)
     # x sizes 40 and 20 leave ragged 16-wide tiles; the last grid is the maximum
     for dims in [(33, 36, 40), (9, 17, 20), (64, 64, 64)]:
         n = int(np.prod(dims))
         r = torch.from_numpy(rng.standard_normal(n)).cuda()
-        print(f"noalloc apply on grid {dims}", flush=True)
+        print(f"noalloc apply on grid {dims} (fused {fused})", flush=True)
         z_ref = _apply(psc, L.psc_net_apply, net, r, dims)
         z_na = _apply(psc, L.psc_net_apply_noalloc, net, r, dims)
         assert torch.isfinite(z_na).all()
