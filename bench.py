@@ -31,6 +31,7 @@ import sys
 import time
 
 METRIC = "time-to-rtol 1e-6 + SpMV/V-cycle HBM GB/s: FP64 vs mixed vs learned"
+NET_FLOP_PER_CELL = 2 * 27 * (16 + 16 * 16 + 16)   # three 3x3x3 layers, 1 -> 16 -> 16 -> 1
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(ROOT, "paper_2406_19754_amd", "weights", "net_poisson128.ckpt")
@@ -457,6 +458,7 @@ def main():
             log(f"learned fcg with FP32 V-cycle: {msm:.2f} ms/solve, {rm['iters']} its, fallbacks {rm['fallbacks']}")
             forms["learned_mixed"] = {"ms": msm, "iters": rm["iters"], "relres": rm["relres"],
                                       "fallbacks": rm["fallbacks"], "speedup_vs_fp64": ms64 / msm}
+        forms["learned"]["net_apply"] = net_apply_timing(psc, torch, net, n, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -561,6 +563,28 @@ def profile_mix(args):
     torch.cuda.synchronize()
     print(json.dumps({"profile_mix": desc, "copy_bytes_read": 2 ** 30, "copy_bytes_written": 2 ** 30,
                       "pcg": r1, "mixed": r2}), flush=True)
+
+
+def net_apply_timing(psc, torch, net, n, dev, reps=10):
+    """One network application z = s net(r/s) on the n^3 grid (psc_net_apply,
+    host clock around `reps` calls, each ending in a stream synchronisation;
+    the ||r|| reduction included), with the fused kernel and with one kernel
+    per layer."""
+    N = n ** 3
+    r = torch.rand(N, dtype=torch.float64, device=dev) - 0.5
+    z = torch.empty_like(r)
+    out = {}
+    for key, fused in (("per_layer_ms", 0), ("fused_ms", 1)):
+        net.tune(psc.NET_TUNE_FUSED, fused)
+        net.apply(r, z, (n, n, n))
+        t = time.perf_counter()
+        for _ in range(reps):
+            net.apply(r, z, (n, n, n))
+        out[key] = (time.perf_counter() - t) * 1e3 / reps
+    out["fused_tflops"] = NET_FLOP_PER_CELL * N / (out["fused_ms"] * 1e-3) / 1e12
+    log(f"network application at {n}^3: fused {out['fused_ms']:.2f} ms ({out['fused_tflops']:.0f} TFLOP/s), "
+        f"one kernel per layer {out['per_layer_ms']:.2f} ms")
+    return out
 
 
 def learned(args):

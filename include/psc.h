@@ -365,7 +365,7 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
 
 /*
  * Tuning. PSC_TUNE_GRID_MAX caps the number of workgroups of the streaming
- * kernels (multiple of 8, at most 65536; default 65536; invalidates captured
+ * kernels (multiple of 8, at most 131072; default 131072; invalidates captured
  * graphs). PSC_TUNE_FUSED_PCG (default 1) selects the fused CG / FCG(1)
  * iteration (V-cycle-only forms): the direction update and the (deferred)
  * x update ride in the SpMV pass, the residual update rides in the level-0
@@ -428,6 +428,15 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
  * them into one pass that recomputes r at every gathered neighbour. Same
  * values either way. */
 #define PSC_TUNE_FP64_SPLIT 12
+/* PSC_TUNE_DIA_ALIGN (default 1): a level read from a paired uniform hacked-DIA
+ * copy whose largest diagonal offset is a multiple of 8 x 128 rows (the plane
+ * of a 3D stencil) gets a grid whose 128-row blocks per workgroup divide that
+ * offset over 8, so the rows a plane away are swept by a workgroup on the same
+ * accelerator die (workgroups are dealt to the 8 dies round robin) and its
+ * gathers hit that die's L2; 0 keeps the default grid. Same values either way
+ * (the partial sums of the reductions are added in a fixed order either way;
+ * their grouping follows the grid, so results agree up to rounding). */
+#define PSC_TUNE_DIA_ALIGN 13
 int psc_tune(psc_hier* h, int32_t key, int32_t value);
 
 void psc_hier_free(psc_hier* h);

@@ -2119,6 +2119,7 @@ struct psc_hier {
     bool split = true;                    // smoothing sweeps through A M^-1 and A P
     bool dia = true;                      // use the hacked-DIA copies where a level has them
     bool dia_uniform = true;              // a level with <= 8 distinct offsets keeps them in the kernel argument
+    int dia_align = 1;                    // grids aligned to the largest DIA offset (grid_lvl); >1: least blocks per workgroup
     bool mixed_split = true;              // FP32 V-cycle: residual update and pre-smoothing as two passes
     bool fp64_split = true;               // FP64 V-cycle: the same two passes
     float* r32 = nullptr;                 // FP32 copy of the outer residual (mixed_split)
@@ -2151,7 +2152,7 @@ struct psc_hier {
     double setup_seconds = 0.0;
     double rebuild_seconds = 0.0;         // last numeric rebuild
     bool stale = false;                   // a numeric rebuild failed: solves refused until one succeeds
-    int gmax = psc::GMAX;                 // workgroup cap of the streaming kernels
+    int gmax = psc::GDEF;                 // workgroup cap of the streaming kernels
     // captured iterations, one per (form, network, network generation)
     std::vector<psc::GraphEntry> graphs;
     // timing: 0 off, 1 every level-0 kernel and the whole V-cycle, 2 only
@@ -2458,6 +2459,34 @@ static int grid_of(const psc_hier* h, long long units_per_block_4, long long tot
 
 static inline int grid_ell(const psc_hier* h, long long nslices) { return grid_of(h, 4, nslices); }
 
+// Grid of the kernels that sweep level V's rows. Workgroup b runs on die
+// b % 8 and takes `per` consecutive 128-row blocks. When V is read from a
+// paired uniform hacked-DIA copy whose largest offset D is a whole number of
+// blocks per die (D = 8 k 128 rows: the plane of a 3D stencil), `per` is
+// chosen to divide k, so that the rows D away from a workgroup's rows belong
+// to a workgroup D / (128 per) = a multiple of 8 launches away, on the same
+// die: those gathers then find the lines the die fetched for its own rows a
+// plane earlier in its L2 instead of fetching them again through the fabric.
+// Otherwise (or with PSC_TUNE_DIA_ALIGN = 0) the default grid.
+static int grid_lvl(const psc_hier* h, const DevLevel& V) {
+    const int g = grid_ell(h, V.A.nslices);
+    const DevDia& G = V.Ad;
+    if (!h->dia_align || !h->dia || !G.on() || !G.pair || G.nd <= 0) return g;
+    long long D = 0;
+    for (int k = 0; k < G.nd; k++) D = std::max(D, (long long)std::abs(G.uo[k]));
+    if (D <= 0 || D % (2 * SLICE * NXCD) != 0) return g;
+    const long long k8 = D / (2 * SLICE * NXCD);
+    const long long nb = (G.nslices + 1) / 2;
+    const long long per0 = std::max<long long>((nb + g - 1) / g, h->dia_align);
+    for (long long per = per0; per <= 2 * per0 && per <= k8; per++) {
+        if (k8 % per) continue;
+        long long gg = (nb + per - 1) / per;
+        gg = (gg + NXCD - 1) / NXCD * NXCD;
+        if (gg <= h->gmax && (nb + gg - 1) / gg == per) return (int)gg;
+    }
+    return g;
+}
+
 // Call f with the level operator (FP64 / FP32) or its scaled form A M^-1 in
 // the storage the level uses: hacked DIA when present and enabled, else
 // hacked ELL. Both have the same slices, so grids do not change.
@@ -2555,7 +2584,7 @@ static void timing_collect(psc_hier* h, int iters = -1, int vc_lag = 0) {
 // precision T (r = b - A M^-1 b).
 template <typename T, typename TB>
 static void launch_pre(psc_hier* h, const DevLevel& V, const TB* b, T* r, Gate g, int grid = 0) {
-    const int gr = grid ? grid : grid_ell(h, V.A.nslices);
+    const int gr = grid ? grid : grid_lvl(h, V);
     constexpr bool f32 = std::is_same<T, float>::value;
     if (h->split) {
         const bool wide = wide_A(h, V);
@@ -2597,9 +2626,9 @@ static void launch_spmv(psc_hier* h, const M& A, const typename M::value_type* x
 }
 
 template <typename T, typename TB, typename TX>
-static void launch_post(psc_hier* h, const Ell<T>& A, const Ell<T>& SP, const T* minv, const TB* b, const T* r,
-                        const int* agg, const T* pv, const T* xc, long long nc, TX* x, const double* d, const Red& R) {
-    const int gr = grid_ell(h, A.nslices);
+static void launch_post(psc_hier* h, int gr, const Ell<T>& A, const Ell<T>& SP, const T* minv, const TB* b,
+                        const T* r, const int* agg, const T* pv, const T* xc, long long nc, TX* x, const double* d,
+                        const Red& R) {
     if (h->split) k_post_s<T, TB, TX><<<gr, WG, 0, h->stream>>>(SP, minv, b, r, xc, x, d, R);
     else if (h->bufload >= 1) k_post<T, TB, TX, 8, true><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
     else if (h->unroll4) k_post<T, TB, TX, 4, false><<<gr, WG, 0, h->stream>>>(A, minv, b, agg, pv, xc, nc, x, d, R);
@@ -2647,7 +2676,7 @@ static void coarse_solve(psc_hier* h, const TB* b, TX* x, Gate g) {
         k_coarse<TB, TX><<<1, WG, 0, h->stream>>>(h->coarse_n, h->coarse_invT, b, x, g);
         return;
     }
-    const int gr = grid_ell(h, C.A.nslices);
+    const int gr = grid_lvl(h, C);
     const bool wide = wide_A(h, C);
     with_A(h, C, [&](auto A) {
         using M = decltype(A);
@@ -2807,7 +2836,7 @@ static T* pre_rbuf(const psc_hier*, DevLevel& V, int k) {
 // side, FP64 at level 0). Sweep 1 is skipped when a fused kernel has done it.
 template <typename T, typename TB>
 static void pre_sweeps(psc_hier* h, DevLevel& V, const TB* b, bool skip1, Gate g) {
-    const int gr = grid_ell(h, V.A.nslices);
+    const int gr = grid_lvl(h, V);
     if (!skip1) launch_pre(h, V, b, pre_rbuf<T>(h, V, 1), g);
     const T* rp = pre_rbuf<T>(h, V, 1);
     const T* sp = nullptr;
@@ -2837,7 +2866,7 @@ static void pre_sweeps(psc_hier* h, DevLevel& V, const TB* b, bool skip1, Gate g
 template <typename T, typename TB, typename TX>
 static void post_sweeps(psc_hier* h, DevLevel& V, const TB* b, TX* out, const T* xc, const double* d,
                         const Red& Rf) {
-    const int gr = grid_ell(h, V.A.nslices);
+    const int gr = grid_lvl(h, V);
     Red Rn = Rf;
     Rn.fin = FIN_NONE;
     const Ell<T> SP = LV<T>::SP(V);
@@ -2914,14 +2943,14 @@ static void vcycle_t(psc_hier* h, const double* r0, double* z0, const double* d,
                 if (h->split && std::is_same<T, float>::value && r0_32)
                     post_sweeps<T, float, double>(h, V, r0_32, z0, xc, d, R);
                 else if (h->split) post_sweeps<T, double, double>(h, V, r0, z0, xc, d, R);
-                else launch_post(h, LV<T>::A(V), LV<T>::SP(V), LV<T>::minv(V), r0, (const T*)LV<T>::r(V), V.agg,
+                else launch_post(h, grid_lvl(h, V), LV<T>::A(V), LV<T>::SP(V), LV<T>::minv(V), r0, (const T*)LV<T>::r(V), V.agg,
                                  LV<T>::pv(V), xc, V.nc, z0, d, R);
             }
-            finish(h, R, grid_ell(h, V.A.nslices));
+            finish(h, R, grid_lvl(h, V));
         } else {
             TimeScope t(h, 7);
             if (h->split) post_sweeps<T, T, T>(h, V, (const T*)LV<T>::b(V), LV<T>::x(V), xc, nullptr, R0);
-            else launch_post(h, LV<T>::A(V), LV<T>::SP(V), LV<T>::minv(V), (const T*)LV<T>::b(V),
+            else launch_post(h, grid_lvl(h, V), LV<T>::A(V), LV<T>::SP(V), LV<T>::minv(V), (const T*)LV<T>::b(V),
                              (const T*)LV<T>::r(V), V.agg, LV<T>::pv(V), xc, V.nc, LV<T>::x(V), (const double*)nullptr,
                              R0);
         }
@@ -2943,7 +2972,7 @@ static void vcycle_fai(psc_hier* h, const double* r0, double* z0, const double* 
     // t = b - A x
     auto resid = [&](DevLevel& V, auto b, const T* x, T* t) {
         using TB = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
-        const int gr = grid_ell(h, V.A.nslices);
+        const int gr = grid_lvl(h, V);
         const bool wa = wide_A(h, V);
         with_A_t<T>(h, V, [&](auto A) {
             using M = decltype(A);
@@ -3030,7 +3059,7 @@ static void vcycle_cheb(psc_hier* h, const double* r0, double* z0, const double*
         using TX = std::remove_pointer_t<decltype(xout)>;
         T ak = T(0), bk = T(0);
         if (fold || dout) coef(k, ak, bk);
-        const int gr = grid_ell(h, V.A.nslices);
+        const int gr = grid_lvl(h, V);
         const bool wa = wide_A(h, V);
         T* r = LV<T>::r(V);
         T* x = LV<T>::x(V);
@@ -3080,7 +3109,7 @@ static void vcycle_cheb(psc_hier* h, const double* r0, double* z0, const double*
         T* t = LV<T>::ft(V);
         T* da = LV<T>::fu(V);
         T* db = LV<T>::fd(V);
-        const int gr = grid_ell(h, V.A.nslices);
+        const int gr = grid_lvl(h, V);
         const int gp = grid_ell(h, V.P.nslices);
         if (V.P.wmax > 8) k_fprol<T, 8><<<gp, WG, 0, st>>>(LV<T>::P(V), LV<T>::x(h->lev[l + 1]), x, g);
         else k_fprol<T, 4><<<gp, WG, 0, st>>>(LV<T>::P(V), LV<T>::x(h->lev[l + 1]), x, g);
@@ -3207,7 +3236,7 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
     hipStream_t st = h->stream;
     DevLevel& L0 = h->lev[0];
     const long long n = L0.n;
-    const int ge = grid_ell(h, L0.A.nslices), gv = grid_vec(h, n);
+    const int ge = grid_lvl(h, L0), gv = grid_vec(h, n);
     const Gate gd{h->ctl, GATE_DONE};
     if (form == FORM_FUSED) {
         // two iterations (even, odd) with the p and r buffers swapped between them
@@ -3457,7 +3486,7 @@ static int solve_begin(psc_hier* h, int form, const double* b_dev, const double*
     hipStream_t st = h->stream;
     DevLevel& L0 = h->lev[0];
     const long long n = L0.n;
-    const int ge = grid_ell(h, L0.A.nslices);
+    const int ge = grid_lvl(h, L0);
     HIPCHK(hipMemcpyAsync(h->bs, b_dev, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(h->xs, x_dev, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     k_ctl_init<<<1, 64, 0, st>>>(h->ctl, h->hctl_dev, rtol, maxit, form);
@@ -3478,7 +3507,7 @@ static int solve_impl(psc_hier* h, int form, psc_net* net, const double* b_dev, 
     hipStream_t st = h->stream;
     DevLevel& L0 = h->lev[0];
     const long long n = L0.n;
-    const int gv = grid_vec(h, n), ge = grid_ell(h, L0.A.nslices);
+    const int gv = grid_vec(h, n), ge = grid_lvl(h, L0);
     if (form_net(form)) {
         int rs = net_check_grid(net, n);
         if (rs) return rs;
@@ -4319,6 +4348,12 @@ int psc_tune(psc_hier* h, int32_t key, int32_t value) {
         drop_graphs(h);
         return build_tail(h);
     }
+    if (key == PSC_TUNE_DIA_ALIGN) {
+        if (value < 0 || value > 4096) return fail(PSC_ERR_ARG, "alignment setting must be 0..4096");
+        h->dia_align = value;
+        drop_graphs(h);
+        return PSC_OK;
+    }
     if (key == PSC_TUNE_XCD) {
         const int v = value != 0;
         HIPCHK(hipSetDevice(h->device));
@@ -4358,7 +4393,7 @@ int psc_tune(psc_hier* h, int32_t key, int32_t value) {
         return PSC_OK;
     }
     if (key == PSC_TUNE_GRID_MAX) {
-        if (value < NXCD || value > GMAX || value % NXCD) return fail(PSC_ERR_ARG, "grid cap must be a multiple of 8 in [8, 65536]");
+        if (value < NXCD || value > GMAX || value % NXCD) return fail(PSC_ERR_ARG, "grid cap must be a multiple of 8 in [8, 131072]");
         h->gmax = value;
         drop_graphs(h);
         return PSC_OK;

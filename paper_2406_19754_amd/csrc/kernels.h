@@ -9,7 +9,8 @@ namespace psc {
 constexpr int WG = 256;        // threads per workgroup: 4 wavefronts of 64
 constexpr int SLICE = 64;      // rows per hacked-ELL slice: one wavefront
 constexpr int NXCD = 8;        // accelerator complex dies; workgroups are dealt round-robin
-constexpr int GMAX = 65536;    // largest grid of the streaming kernels
+constexpr int GMAX = 131072;   // largest grid of the streaming kernels (PSC_TUNE_GRID_MAX)
+constexpr int GDEF = 131072;   // their default cap
 
 // Solver control block, device resident. Scalars of the Krylov recurrence
 // live here so no host round trip is needed between kernels.
