@@ -672,8 +672,16 @@ __device__ __forceinline__ bool dia_pair_on(const Dia<T>& A) { return A.pair && 
 template <typename T>
 __device__ __forceinline__ long long dia_blocks(const Dia<T>& A) { return (A.nslices + 1) >> 1; }
 
-template <typename T, typename GP, typename G1>
-__device__ __forceinline__ void dia_pair_rows(const Dia<T>& A, long long S, int lane, GP gp, G1 g1, T& a0, T& a1) {
+// Row sums a0, a1 of the two rows 2 lane, 2 lane + 1 of block S of a paired
+// uniform hacked-DIA operator: a = sum_k v_k cb(gl(column_k)). gl loads what
+// one entry needs (any type), cb turns it into the two rows' operands; every
+// gl of the block is issued before any cb, so that the loads of all diagonals
+// are in flight together (a cb that used its loads at once would make each
+// diagonal wait for the previous one's). g1 gives one row's operand at a
+// clamped column (blocks at the ends of the matrix).
+template <typename T, typename GL, typename CB, typename G1>
+__device__ __forceinline__ void dia_pair_rows_lc(const Dia<T>& A, long long S, int lane, GL gl, CB cb, G1 g1, T& a0,
+                                                 T& a1) {
     const int nd = A.nd;
     const long long r0 = S * (2 * SLICE) + 2 * lane;
     const v2a<T>* vp = (const v2a<T>*)(A.val + S * (long long)nd * 2 * SLICE) + lane;
@@ -687,15 +695,16 @@ __device__ __forceinline__ void dia_pair_rows(const Dia<T>& A, long long S, int 
                        b0 + 2 * SLICE <= A.nrows;
     T s0 = T(0), s1 = T(0);
     if (inner) {
-        v2u<T> g[8];
+        decltype(gl(0ll)) g[8];
 #pragma unroll
         for (int k = 0; k < 8; k++)
-            if (k < nd) g[k] = gp(r0 + A.uo[k]);
+            if (k < nd) g[k] = gl(r0 + A.uo[k]);
 #pragma unroll
         for (int k = 0; k < 8; k++)
             if (k < nd) {
-                s0 += v[k].x * g[k].x;
-                s1 += v[k].y * g[k].y;
+                const v2u<T> c = cb(g[k]);
+                s0 += v[k].x * c.x;
+                s1 += v[k].y * c.y;
             }
     } else {
         const long long cmax = A.ncols - 1;
@@ -710,6 +719,17 @@ __device__ __forceinline__ void dia_pair_rows(const Dia<T>& A, long long S, int 
     a0 = s0;
     a1 = s1;
 }
+
+// The same with gp giving the two rows' operands directly.
+template <typename T, typename GP, typename G1>
+__device__ __forceinline__ void dia_pair_rows(const Dia<T>& A, long long S, int lane, GP gp, G1 g1, T& a0, T& a1) {
+    dia_pair_rows_lc(A, S, lane, gp, [](const v2u<T>& g) { return g; }, g1, a0, a1);
+}
+
+// Two gathered FP64 vectors of one entry.
+struct Gather2 {
+    v2u<double> a, b;
+};
 
 // Row sum of either storage format; GB is the batch of the wide-row path.
 template <int GB = 4, typename T, typename G>
@@ -904,11 +924,10 @@ __global__ __launch_bounds__(WG) void k_spmv_pfuse(M A, const double* __restrict
             chunk_range(dia_blocks(A), lo, hi);
             for (long long S = lo + w; S < hi; S += WG / 64) {
                 double a0, a1;
-                dia_pair_rows(
-                    A, S, lane,
-                    [&](long long c) {
-                        const v2u<double> pp = ld2(pold + c), zz = ld2(z + c);
-                        return v2u<double>{fma(beta, pp.x, zz.x), fma(beta, pp.y, zz.y)};
+                dia_pair_rows_lc(
+                    A, S, lane, [&](long long c) { return Gather2{ld2(pold + c), ld2(z + c)}; },
+                    [&](const Gather2& t) {
+                        return v2u<double>{fma(beta, t.a.x, t.b.x), fma(beta, t.a.y, t.b.y)};
                     },
                     [&](int c) { return fma(beta, pold[c], z[c]); }, a0, a1);
                 const long long row = S * (2 * SLICE) + 2 * lane;
@@ -987,9 +1006,11 @@ __global__ __launch_bounds__(WG) void k_update_pre(Ell<double> A, const double* 
 
 // Fused FCG(1), first pass: p_new = z - beta p_old (p_new = z without a
 // previous direction), q = A p_new, the deferred x += alpha_prev p_old, and
-// the partials (p_new.q, p_new.r_old).
+// the partials (p_new.q, p_new.r_old). Held to 168 registers, three waves
+// per SIMD: the compiler's 170 would allow only two, measured 2 % slower at
+// 384^3 (two registers spill).
 template <typename M, bool BUF = false>
-__global__ __launch_bounds__(WG) void k_spmv_pfuse_fcg(M A, const double* __restrict__ z,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void k_spmv_pfuse_fcg(M A, const double* __restrict__ z,
                                                        const double* __restrict__ pold, double* __restrict__ pnew,
                                                        double* __restrict__ q, double* __restrict__ x,
                                                        const double* __restrict__ rold, Red R) {
@@ -1003,11 +1024,10 @@ __global__ __launch_bounds__(WG) void k_spmv_pfuse_fcg(M A, const double* __rest
             chunk_range(dia_blocks(A), lo, hi);
             for (long long S = lo + w; S < hi; S += WG / 64) {
                 double a0, a1;
-                dia_pair_rows(
-                    A, S, lane,
-                    [&](long long c) {
-                        const v2u<double> pp = ld2(pold + c), zz = ld2(z + c);
-                        return v2u<double>{fma(nb, pp.x, zz.x), fma(nb, pp.y, zz.y)};
+                dia_pair_rows_lc(
+                    A, S, lane, [&](long long c) { return Gather2{ld2(pold + c), ld2(z + c)}; },
+                    [&](const Gather2& t) {
+                        return v2u<double>{fma(nb, t.a.x, t.b.x), fma(nb, t.a.y, t.b.y)};
                     },
                     [&](int c) { return fma(nb, pold[c], z[c]); }, a0, a1);
                 const long long row = S * (2 * SLICE) + 2 * lane;
@@ -1253,13 +1273,10 @@ __global__ __launch_bounds__(WG) void k_pre_s(M AM, const TB* __restrict__ b, ty
             chunk_range(dia_blocks(AM), lo, hi);
             for (long long S = lo + w; S < hi; S += WG / 64) {
                 T a0, a1;
-                dia_pair_rows(
-                    AM, S, lane,
-                    [&](long long c) {
-                        const v2u<TB> bb = ld2(b + c);
-                        return v2u<T>{(T)bb.x, (T)bb.y};
-                    },
-                    [&](int c) { return (T)b[c]; }, a0, a1);
+                dia_pair_rows_lc(
+                    AM, S, lane, [&](long long c) { return ld2(b + c); },
+                    [&](const v2u<TB>& bb) { return v2u<T>{(T)bb.x, (T)bb.y}; }, [&](int c) { return (T)b[c]; },
+                    a0, a1);
                 const long long row = S * (2 * SLICE) + 2 * lane;
                 if (row + 1 < AM.nrows) {
                     const v2u<TB> bb = ld2(b + row);
@@ -1296,11 +1313,10 @@ __global__ __launch_bounds__(WG) void k_update_pre_s(M AM, const double* __restr
             chunk_range(dia_blocks(AM), lo, hi);
             for (long long S = lo + w; S < hi; S += WG / 64) {
                 T a0, a1;
-                dia_pair_rows(
-                    AM, S, lane,
-                    [&](long long c) {
-                        const v2u<double> qq = ld2(q + c), rr = ld2(rold + c);
-                        return v2u<T>{(T)fma(nalpha, qq.x, rr.x), (T)fma(nalpha, qq.y, rr.y)};
+                dia_pair_rows_lc(
+                    AM, S, lane, [&](long long c) { return Gather2{ld2(q + c), ld2(rold + c)}; },
+                    [&](const Gather2& t) {
+                        return v2u<T>{(T)fma(nalpha, t.a.x, t.b.x), (T)fma(nalpha, t.a.y, t.b.y)};
                     },
                     [&](int c) { return (T)fma(nalpha, q[c], rold[c]); }, a0, a1);
                 const long long row = S * (2 * SLICE) + 2 * lane;
