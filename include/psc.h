@@ -429,13 +429,14 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
  * values either way. */
 #define PSC_TUNE_FP64_SPLIT 12
 /* PSC_TUNE_DIA_ALIGN (default 1): a level read from a paired uniform hacked-DIA
- * copy whose largest diagonal offset is a multiple of 8 x 128 rows (the plane
- * of a 3D stencil) gets a grid whose 128-row blocks per workgroup divide that
- * offset over 8, so the rows a plane away are swept by a workgroup on the same
- * accelerator die (workgroups are dealt to the 8 dies round robin) and its
- * gathers hit that die's L2; 0 keeps the default grid. Same values either way
- * (the partial sums of the reductions are added in a fixed order either way;
- * their grouping follows the grid, so results agree up to rounding). */
+ * copy (which gets at least one 128-row block per wavefront in any case) whose
+ * largest diagonal offset is a multiple of 8 x 128 rows (the plane of a 3D
+ * stencil) gets a grid whose blocks per workgroup divide that offset over 8,
+ * so the rows a plane away are swept by a workgroup on the same accelerator
+ * die (workgroups are dealt to the 8 dies round robin) and its gathers hit
+ * that die's L2; 0 skips that choice. The reductions' partial sums are added
+ * in a fixed order either way; their grouping follows the grid, so results
+ * agree up to rounding. */
 #define PSC_TUNE_DIA_ALIGN 13
 int psc_tune(psc_hier* h, int32_t key, int32_t value);
 

@@ -2135,7 +2135,7 @@ struct psc_hier {
     bool split = true;                    // smoothing sweeps through A M^-1 and A P
     bool dia = true;                      // use the hacked-DIA copies where a level has them
     bool dia_uniform = true;              // a level with <= 8 distinct offsets keeps them in the kernel argument
-    int dia_align = 1;                    // grids aligned to the largest DIA offset (grid_lvl); >1: least blocks per workgroup
+    bool dia_align = true;                // grids aligned to the largest DIA offset (grid_lvl)
     bool mixed_split = true;              // FP32 V-cycle: residual update and pre-smoothing as two passes
     bool fp64_split = true;               // FP64 V-cycle: the same two passes
     float* r32 = nullptr;                 // FP32 copy of the outer residual (mixed_split)
@@ -2476,31 +2476,39 @@ static int grid_of(const psc_hier* h, long long units_per_block_4, long long tot
 static inline int grid_ell(const psc_hier* h, long long nslices) { return grid_of(h, 4, nslices); }
 
 // Grid of the kernels that sweep level V's rows. Workgroup b runs on die
-// b % 8 and takes `per` consecutive 128-row blocks. When V is read from a
-// paired uniform hacked-DIA copy whose largest offset D is a whole number of
-// blocks per die (D = 8 k 128 rows: the plane of a 3D stencil), `per` is
-// chosen to divide k, so that the rows D away from a workgroup's rows belong
-// to a workgroup D / (128 per) = a multiple of 8 launches away, on the same
-// die: those gathers then find the lines the die fetched for its own rows a
-// plane earlier in its L2 instead of fetching them again through the fabric.
-// Otherwise (or with PSC_TUNE_DIA_ALIGN = 0) the default grid.
+// b % 8 and its four wavefronts take `per` consecutive 128-row blocks of a
+// paired layout one at a time, so per >= 4 keeps every wavefront busy (the
+// default grid of four 64-row slices per workgroup leaves two of them idle).
+// When V is read from a paired uniform hacked-DIA copy whose largest offset
+// D is a whole number of blocks per die (D = 8 k 128 rows: the plane of a 3D
+// stencil), `per` is also chosen to divide k, so that the rows D away from a
+// workgroup's rows belong to a workgroup D / (128 per) = a multiple of 8
+// launches away, on the same die: those gathers then find the lines the die
+// fetched a plane earlier in its L2 instead of fetching them again through
+// the fabric (PSC_TUNE_DIA_ALIGN = 0 skips this choice).
 static int grid_lvl(const psc_hier* h, const DevLevel& V) {
     const int g = grid_ell(h, V.A.nslices);
     const DevDia& G = V.Ad;
-    if (!h->dia_align || !h->dia || !G.on() || !G.pair || G.nd <= 0) return g;
-    long long D = 0;
-    for (int k = 0; k < G.nd; k++) D = std::max(D, (long long)std::abs(G.uo[k]));
-    if (D <= 0 || D % (2 * SLICE * NXCD) != 0) return g;
-    const long long k8 = D / (2 * SLICE * NXCD);
+    if (!h->dia || !G.on() || !G.pair || G.nd <= 0) return g;
     const long long nb = (G.nslices + 1) / 2;
-    const long long per0 = std::max<long long>((nb + g - 1) / g, h->dia_align);
-    for (long long per = per0; per <= 2 * per0 && per <= k8; per++) {
-        if (k8 % per) continue;
-        long long gg = (nb + per - 1) / per;
-        gg = (gg + NXCD - 1) / NXCD * NXCD;
-        if (gg <= h->gmax && (nb + gg - 1) / gg == per) return (int)gg;
+    const long long per0 = std::max<long long>((nb + g - 1) / g, WG / 64);
+    auto grid_for = [&](long long per) {
+        const long long gg = (nb + per - 1) / per;
+        return (gg + NXCD - 1) / NXCD * NXCD;
+    };
+    if (h->dia_align) {
+        long long D = 0;
+        for (int k = 0; k < G.nd; k++) D = std::max(D, (long long)std::abs(G.uo[k]));
+        if (D > 0 && D % (2 * SLICE * NXCD) == 0) {
+            const long long k8 = D / (2 * SLICE * NXCD);
+            for (long long per = per0; per <= 2 * per0 && per <= k8; per++) {
+                if (k8 % per) continue;
+                const long long gg = grid_for(per);
+                if (gg <= h->gmax && (nb + gg - 1) / gg == per) return (int)gg;
+            }
+        }
     }
-    return g;
+    return (int)std::min<long long>(grid_for(per0), h->gmax);
 }
 
 // Call f with the level operator (FP64 / FP32) or its scaled form A M^-1 in
@@ -4365,8 +4373,7 @@ int psc_tune(psc_hier* h, int32_t key, int32_t value) {
         return build_tail(h);
     }
     if (key == PSC_TUNE_DIA_ALIGN) {
-        if (value < 0 || value > 4096) return fail(PSC_ERR_ARG, "alignment setting must be 0..4096");
-        h->dia_align = value;
+        h->dia_align = value != 0;
         drop_graphs(h);
         return PSC_OK;
     }
