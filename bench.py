@@ -246,7 +246,7 @@ def main():
                     help="smoothing sweeps gather through A, M^-1 and P instead of A M^-1 and A P")
     ap.add_argument("--unfused", action="store_true", help="one kernel per CG operation instead of the fused PCG iteration")
     ap.add_argument("--train-epochs", type=int, default=6)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--crops", type=int, default=20000)
     ap.add_argument("--save-weights", default="")
     ap.add_argument("--eval-only", action="store_true",
