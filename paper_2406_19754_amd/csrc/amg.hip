@@ -12,12 +12,14 @@
 //     layout so each load instruction of a wavefront reads 512 contiguous
 //     bytes of values and 256 of indices, streamed with non-temporal loads
 //     so the gathered vectors keep the L2 and Infinity Cache;
-//   * streaming kernels run a fixed grid (a few workgroups per CU) in which
+//   * streaming kernels run a grid of up to 131072 workgroups in which
 //     workgroup b walks a contiguous range of slices in launch order, so the
 //     8 XCDs (which receive workgroups round-robin) sweep the same region at
-//     once and share the neighbour gathers through the Infinity Cache; an
-//     optional remap (PSC_TUNE_XCD) gives each XCD one contiguous eighth of
-//     the rows instead, which measured slower;
+//     once and share the neighbour gathers through the Infinity Cache; on a
+//     stencil level the range is sized so that a z-plane is a multiple of 8
+//     ranges (the rows a plane away are then swept on the same die,
+//     grid_lvl); an optional remap (PSC_TUNE_XCD) gives each XCD one
+//     contiguous eighth of the rows instead, which measured slower;
 //   * every dot product is fused into the kernel that produces one of its
 //     operands: wavefront shuffles, then LDS, then one partial per
 //     workgroup; a one-workgroup finishing kernel adds the partials in a
