@@ -245,6 +245,38 @@ def test_fused_and_unfused_iterations_agree(psc, case, form):
     assert np.linalg.norm(x1 - x0) <= 1e-10 * np.linalg.norm(x0)
 
 
+@pytest.mark.parametrize("n", [64, 48])
+def test_plane_aligned_grid_gives_the_same_iterates(psc, n):
+    """The level grids (at least one 128-row block per wavefront; at 64^3 the
+    blocks per workgroup also divide a z-plane's blocks over the 8 dies, at
+    48^3 a plane of 2304 rows cannot be aligned) change only how the
+    reductions' partial sums are grouped: the same iterations as with the
+    alignment off and with the old workgroup cap, x to 1e-12, and the
+    oracle's iteration count within one."""
+    rp, c, v = P.poisson7(n)
+    b = P.rhs_from_solution(rp, c, v, P.x_true(n ** 3, 0))
+    h = psc.Hierarchy(rp, c, v, build_fp32=True)
+    out = {}
+    for key, align, gmax in (("aligned", 1, 131072), ("unaligned", 0, 131072), ("cap65536", 1, 65536)):
+        h.tune(psc.TUNE_DIA_ALIGN, align)
+        h.tune(psc.TUNE_GRID_MAX, gmax)
+        for form in ("pcg", "fcg32"):
+            x = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+            g = h.pcg(dev(b), x) if form == "pcg" else h.fcg(dev(b), x, prec=psc.FP32)
+            assert g["status"] == psc.OK and g["relres"] <= 1e-6
+            out[key, form] = (g["iters"], x.cpu().numpy())
+    h.tune(psc.TUNE_DIA_ALIGN, 1)
+    h.tune(psc.TUNE_GRID_MAX, 131072)
+    for form in ("pcg", "fcg32"):
+        it0, x0 = out["aligned", form]
+        for key in ("unaligned", "cap65536"):
+            it, xk = out[key, form]
+            assert it == it0, (key, form)
+            assert np.linalg.norm(xk - x0) <= 1e-12 * np.linalg.norm(x0), (key, form)
+    ref = oracle.Hierarchy(rp, c, v).pcg(b)
+    assert abs(out["aligned", "pcg"][0] - ref["iters"]) <= 1
+
+
 @pytest.mark.parametrize("knob", ["tail_off", "tail_4096", "dia_off", "split_off", "bufload_all", "bufload_none", "unroll4", "grid256",
                                   "spmv2", "dia_per_slice", "xcd_chunks", "mixed_fused"])
 @pytest.mark.parametrize("case", ["poisson13", "random_long_rows", "diffusion20_az100"])
