@@ -414,6 +414,76 @@ __device__ __forceinline__ T ell_row(const Ell<T>& A, long long s, int lane, G g
     return acc;
 }
 
+// Operators with wide rows (the coarse operators, transfers and smoothed
+// prolongators of smoothed hierarchies: hundreds to thousands of slots per
+// row) are latency-bound with one lane per row walking its slots, and their
+// few slices leave most of the GPU idle. GB = GB_SPLIT selects the split
+// form: the WG / 64 wavefronts of a workgroup share each slice, wavefront q
+// taking the slots q, q + 4, q + 8, ... of all its 64 rows (batches of 8,
+// every load of a batch issued before its gathers); the partial sums meet in
+// LDS and wavefront 0 adds them in a fixed order and finishes the rows.
+constexpr int GB_SPLIT = 0;
+constexpr int SPLIT_W = 48;
+static_assert(WG == 256, "the split form adds four wavefronts' partial sums");   // hacked-ELL slots per row above which a level takes the split form
+
+template <typename T, typename G>
+__device__ __forceinline__ T ell_row_part(const Ell<T>& A, long long s, int lane, int q, G g) {
+    constexpr int NQ = WG / 64, B = 8;
+    long long o, stride;
+    int w;
+    if (A.pair) {
+        const long long b0 = A.off[s & ~1ll];
+        o = A.off[s];
+        w = (int)((A.off[(s & ~1ll) + 2] - b0) >> 7);
+        stride = 2 * SLICE;
+    } else {
+        o = A.off[s];
+        w = (int)((A.off[s + 1] - o) >> 6);
+        stride = SLICE;
+    }
+    const T* vp = A.val + o + lane;
+    const int* cp = A.col + o + lane;
+    T acc = T(0);
+    int k = q;
+    for (; k + (B - 1) * NQ < w; k += B * NQ) {
+        T v[B];
+        int c[B];
+#pragma unroll
+        for (int j = 0; j < B; j++) {
+            v[j] = ntload(vp + (long long)(k + j * NQ) * stride);
+            c[j] = ntload(cp + (long long)(k + j * NQ) * stride);
+        }
+        T gv[B];
+#pragma unroll
+        for (int j = 0; j < B; j++) gv[j] = g(c[j]);
+#pragma unroll
+        for (int j = 0; j < B; j++) acc += v[j] * gv[j];
+    }
+    for (; k < w; k += NQ) acc += ntload(vp + (long long)k * stride) * g(ntload(cp + (long long)k * stride));
+    return acc;
+}
+
+// The split form's loop over the slices of this workgroup's chunk: row sums
+// a = sum_k v_k g(col_k), then epi(row, a) on wavefront 0. Every thread of the
+// workgroup runs the loop (two barriers per slice).
+template <typename T, typename G, typename E>
+__device__ __forceinline__ void ell_split_slices(const Ell<T>& A, G g, E epi) {
+    __shared__ T part[WG / 64][SLICE];
+    long long lo, hi;
+    chunk_range(A.nslices, lo, hi);
+    const int lane = threadIdx.x & 63, q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (long long s = lo; s < hi; s++) {
+        part[q][lane] = ell_row_part(A, s, lane, q, g);
+        __syncthreads();
+        if (q == 0) {
+            const T a = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+            const long long row = s * SLICE + lane;
+            if (row < A.nrows) epi(row, a);
+        }
+        __syncthreads();
+    }
+}
+
 // Two rows of two different slices (s1, s2, both of width <= 8) computed
 // together: all value and index loads of both slices are issued before the
 // first gather, doubling the loads a wavefront keeps in flight.
@@ -753,6 +823,12 @@ __global__ __launch_bounds__(WG) void k_spmv(M A, const typename M::value_type* 
                                              typename M::value_type* __restrict__ y, Gate g) {
     using T = typename M::value_type;
     if (gate_skip(g)) return;
+    if constexpr (GB == GB_SPLIT) {
+        if constexpr (std::is_same<M, Ell<T>>::value)
+            ell_split_slices(A, [&](int c) { return x[c]; }, [&](long long row, T a) { y[row] = a; });
+        return;
+    }
+    constexpr int GBN = GB == GB_SPLIT ? 4 : GB;   // (the split form returned above)
     long long lo, hi;
     const int lane = threadIdx.x & 63, w = wave_id();
     if constexpr (std::is_same<M, Dia<T>>::value) {
@@ -773,7 +849,7 @@ __global__ __launch_bounds__(WG) void k_spmv(M A, const typename M::value_type* 
     for (long long s = lo + w; s < hi; s += WG / 64) {
         T acc;
         if constexpr (BUF) acc = ell_row_buf(A, s, lane, [&](int c) { return bx[c]; });
-        else acc = mat_row<GB>(A, s, lane, [&](int c) { return x[c]; });
+        else acc = mat_row<GBN>(A, s, lane, [&](int c) { return x[c]; });
         long long row = s * SLICE + lane;
         if (row < A.nrows) y[row] = acc;
     }
@@ -1268,6 +1344,12 @@ __global__ __launch_bounds__(WG) void k_pre_s(M AM, const TB* __restrict__ b, ty
                                               Gate g) {
     using T = typename M::value_type;
     if (gate_skip(g)) return;
+    if constexpr (GB == GB_SPLIT) {
+        if constexpr (std::is_same<M, Ell<T>>::value)
+            ell_split_slices(AM, [&](int c) { return (T)b[c]; }, [&](long long row, T a) { r[row] = (T)b[row] - a; });
+        return;
+    }
+    constexpr int GBN = GB == GB_SPLIT ? 4 : GB;   // (the split form returned above)
     long long lo, hi;
     const int lane = threadIdx.x & 63, w = wave_id();
     if constexpr (std::is_same<M, Dia<T>>::value) {
@@ -1292,7 +1374,7 @@ __global__ __launch_bounds__(WG) void k_pre_s(M AM, const TB* __restrict__ b, ty
     }
     chunk_range(AM.nslices, lo, hi);
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        const T acc = mat_row<GB>(AM, s, lane, [&](int c) { return (T)b[c]; });
+        const T acc = mat_row<GBN>(AM, s, lane, [&](int c) { return (T)b[c]; });
         const long long row = s * SLICE + lane;
         if (row < AM.nrows) r[row] = (T)b[row] - acc;
     }
@@ -1364,6 +1446,16 @@ __global__ __launch_bounds__(WG) void k_post_s(Ell<T> SP, const T* __restrict__ 
     long long lo, hi;
     const int lane = threadIdx.x & 63, w = wave_id();
     double s0 = 0.0;
+    if constexpr (GB == GB_SPLIT) {
+        ell_split_slices(SP, [&](int c) { return xc[c]; }, [&](long long row, T a) {
+            const T xi = minv[row] * ((T)b[row] + r[row]) + a;
+            x[row] = (TX)xi;
+            if (d) s0 += (double)(TX)xi * d[row];
+        });
+        if (R.fin != FIN_NONE) block_partial(s0, 0.0, R.part);
+        return;
+    }
+    constexpr int GBN = GB == GB_SPLIT ? 4 : GB;   // (the split form returned above)
     if (SP.pair) {
         // two rows per lane: their values (8/16 bytes) and columns (8 bytes)
         // with one load per slot
@@ -1376,22 +1468,22 @@ __global__ __launch_bounds__(WG) void k_post_s(Ell<T> SP, const T* __restrict__ 
             const i2* cp = (const i2*)(SP.col + b0) + lane;
             T a0 = T(0), a1 = T(0);
             int k = 0;
-            for (; k + GB <= ws; k += GB) {
-                v2a<T> v[GB];
-                i2 c[GB];
+            for (; k + GBN <= ws; k += GBN) {
+                v2a<T> v[GBN];
+                i2 c[GBN];
 #pragma unroll
-                for (int j = 0; j < GB; j++) {
+                for (int j = 0; j < GBN; j++) {
                     v[j] = ntload(vp + (k + j) * SLICE);
                     c[j] = ntload(cp + (k + j) * SLICE);
                 }
-                T g0[GB], g1[GB];
+                T g0[GBN], g1[GBN];
 #pragma unroll
-                for (int j = 0; j < GB; j++) {
+                for (int j = 0; j < GBN; j++) {
                     g0[j] = xc[c[j].x];
                     g1[j] = xc[c[j].y];
                 }
 #pragma unroll
-                for (int j = 0; j < GB; j++) {
+                for (int j = 0; j < GBN; j++) {
                     a0 += v[j].x * g0[j];
                     a1 += v[j].y * g1[j];
                 }
@@ -1424,7 +1516,7 @@ __global__ __launch_bounds__(WG) void k_post_s(Ell<T> SP, const T* __restrict__ 
     }
     chunk_range(SP.nslices, lo, hi);
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        const T acc = mat_row<GB>(SP, s, lane, [&](int c) { return xc[c]; });
+        const T acc = mat_row<GBN>(SP, s, lane, [&](int c) { return xc[c]; });
         const long long row = s * SLICE + lane;
         if (row < SP.nrows) {
             const T xi = minv[row] * ((T)b[row] + r[row]) + acc;
@@ -1446,11 +1538,20 @@ __global__ __launch_bounds__(WG) void k_presweep(M AM, const TB* __restrict__ b,
                                                  typename M::value_type* __restrict__ rout, Gate g) {
     using T = typename M::value_type;
     if (gate_skip(g)) return;
+    if constexpr (GB == GB_SPLIT) {
+        if constexpr (std::is_same<M, Ell<T>>::value)
+            ell_split_slices(AM, [&](int c) { return (T)sprev[c] + rprev[c]; }, [&](long long row, T a) {
+                sout[row] = (T)sprev[row] + rprev[row];
+                rout[row] = (T)b[row] - a;
+            });
+        return;
+    }
+    constexpr int GBN = GB == GB_SPLIT ? 4 : GB;   // (the split form returned above)
     long long lo, hi;
     chunk_range(AM.nslices, lo, hi);
     const int lane = threadIdx.x & 63, w = wave_id();
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        const T acc = mat_row<GB>(AM, s, lane, [&](int c) { return (T)sprev[c] + rprev[c]; });
+        const T acc = mat_row<GBN>(AM, s, lane, [&](int c) { return (T)sprev[c] + rprev[c]; });
         const long long row = s * SLICE + lane;
         if (row < AM.nrows) {
             sout[row] = (T)sprev[row] + rprev[row];
@@ -1468,12 +1569,23 @@ __global__ __launch_bounds__(WG) void k_sweep(M A, const typename M::value_type*
                                               const double* __restrict__ d, Red R) {
     using T = typename M::value_type;
     if (skip_red(R)) return;
+    double s0 = 0.0;
+    if constexpr (GB == GB_SPLIT) {
+        if constexpr (std::is_same<M, Ell<T>>::value)
+            ell_split_slices(A, [&](int c) { return xin[c]; }, [&](long long row, T a) {
+                const T xi = xin[row] + minv[row] * ((T)b[row] - a);
+                xout[row] = (TX)xi;
+                if (d) s0 += (double)(TX)xi * d[row];
+            });
+        if (R.fin != FIN_NONE) block_partial(s0, 0.0, R.part);
+        return;
+    }
+    constexpr int GBN = GB == GB_SPLIT ? 4 : GB;   // (the split form returned above)
     long long lo, hi;
     chunk_range(A.nslices, lo, hi);
     const int lane = threadIdx.x & 63, w = wave_id();
-    double s0 = 0.0;
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        const T acc = mat_row<GB>(A, s, lane, [&](int c) { return xin[c]; });
+        const T acc = mat_row<GBN>(A, s, lane, [&](int c) { return xin[c]; });
         const long long row = s * SLICE + lane;
         if (row < A.nrows) {
             const T xi = xin[row] + minv[row] * ((T)b[row] - acc);
@@ -2488,7 +2600,10 @@ static inline int grid_ell(const psc_hier* h, long long nslices) { return grid_o
 // launches away, on the same die: those gathers then find the lines the die
 // fetched a plane earlier in its L2 instead of fetching them again through
 // the fabric (PSC_TUNE_DIA_ALIGN = 0 skips this choice).
+static bool split_A(const psc_hier* h, const DevLevel& V);
+
 static int grid_lvl(const psc_hier* h, const DevLevel& V) {
+    if (split_A(h, V)) return grid_of(h, 1, V.A.nslices);   // one slice per workgroup
     const int g = grid_ell(h, V.A.nslices);
     const DevDia& G = V.Ad;
     if (!h->dia || !G.on() || !G.pair || G.nd <= 0) return g;
@@ -2550,6 +2665,11 @@ static void with_AM_t(const psc_hier* h, const DevLevel& V, F f) {
 // more loads in flight); stencil operators keep the 4-slot ones.
 static bool wide_A(const psc_hier* h, const DevLevel& V) {
     return (h->dia && V.Ad.on()) ? V.Ad.ndmax > 8 : V.A.wmax > 8;
+}
+// Level V's operator read from hacked ELL with rows wider than SPLIT_W slots:
+// its kernels take the split form (GB_SPLIT) on one slice per workgroup.
+static bool split_A(const psc_hier* h, const DevLevel& V) {
+    return !(h->dia && V.Ad.on()) && V.A.wmax > SPLIT_W;
 }
 static inline int grid_vec(const psc_hier* h, long long n) { return grid_of(h, 1024, n); }
 
@@ -2613,9 +2733,10 @@ static void launch_pre(psc_hier* h, const DevLevel& V, const TB* b, T* r, Gate g
     const int gr = grid ? grid : grid_lvl(h, V);
     constexpr bool f32 = std::is_same<T, float>::value;
     if (h->split) {
-        const bool wide = wide_A(h, V);
+        const bool wide = wide_A(h, V), spl = split_A(h, V);
         auto go = [&](auto AM) {
-            if (wide) k_pre_s<decltype(AM), TB, 8><<<gr, WG, 0, h->stream>>>(AM, b, r, g);
+            if (spl) k_pre_s<decltype(AM), TB, GB_SPLIT><<<gr, WG, 0, h->stream>>>(AM, b, r, g);
+            else if (wide) k_pre_s<decltype(AM), TB, 8><<<gr, WG, 0, h->stream>>>(AM, b, r, g);
             else k_pre_s<decltype(AM), TB, 4><<<gr, WG, 0, h->stream>>>(AM, b, r, g);
         };
         if constexpr (f32) with_AM32(h, V, go);
@@ -2633,10 +2754,14 @@ static void launch_pre(psc_hier* h, const DevLevel& V, const TB* b, T* r, Gate g
 // y = A x for an operator in either storage; the variant knobs apply to ELL.
 template <typename M>
 static void launch_spmv(psc_hier* h, const M& A, const typename M::value_type* x, typename M::value_type* y,
-                        Gate g, bool wide = false) {
+                        Gate g, bool wide = false, bool split = false) {
     using T = typename M::value_type;
     const int gr = grid_ell(h, A.nslices);
     if constexpr (std::is_same<M, Ell<T>>::value) {
+        if (split) {
+            k_spmv<M, false, GB_SPLIT><<<grid_of(h, 1, A.nslices), WG, 0, h->stream>>>(A, x, y, g);
+            return;
+        }
         if (h->spmv2) {
             // two slices per wavefront: half the workgroups of the one-slice grid
             k_spmv2<T><<<grid_of(h, 8, A.nslices), WG, 0, h->stream>>>(A, x, y, g);
@@ -2869,14 +2994,16 @@ static void pre_sweeps(psc_hier* h, DevLevel& V, const TB* b, bool skip1, Gate g
     for (int k = 2; k <= V.nu; k++) {
         T* so = ((V.nu - k) % 2 == 0) ? LV<T>::s(V) : LV<T>::sb(V);
         T* ro = pre_rbuf<T>(h, V, k);
-        const bool wide = wide_A(h, V);
+        const bool wide = wide_A(h, V), spl = split_A(h, V);
         with_AM_t<T>(h, V, [&](auto AM) {
             using M = decltype(AM);
             if (k == 2) {
-                if (wide) k_presweep<M, TB, TB, 8><<<gr, WG, 0, h->stream>>>(AM, b, b, rp, so, ro, g);
+                if (spl) k_presweep<M, TB, TB, GB_SPLIT><<<gr, WG, 0, h->stream>>>(AM, b, b, rp, so, ro, g);
+                else if (wide) k_presweep<M, TB, TB, 8><<<gr, WG, 0, h->stream>>>(AM, b, b, rp, so, ro, g);
                 else k_presweep<M, TB, TB, 4><<<gr, WG, 0, h->stream>>>(AM, b, b, rp, so, ro, g);
             } else {
-                if (wide) k_presweep<M, TB, T, 8><<<gr, WG, 0, h->stream>>>(AM, b, sp, rp, so, ro, g);
+                if (spl) k_presweep<M, TB, T, GB_SPLIT><<<gr, WG, 0, h->stream>>>(AM, b, sp, rp, so, ro, g);
+                else if (wide) k_presweep<M, TB, T, 8><<<gr, WG, 0, h->stream>>>(AM, b, sp, rp, so, ro, g);
                 else k_presweep<M, TB, T, 4><<<gr, WG, 0, h->stream>>>(AM, b, sp, rp, so, ro, g);
             }
         });
@@ -2898,27 +3025,31 @@ static void post_sweeps(psc_hier* h, DevLevel& V, const TB* b, TX* out, const T*
     const Ell<T> SP = LV<T>::SP(V);
     const T* r = LV<T>::r(V);
     const T* minv = LV<T>::minv(V);
-    const bool wsp = V.SP.wmax > 8, wa = wide_A(h, V);
+    const bool wsp = V.SP.wmax > 8, ssp = V.SP.wmax > SPLIT_W, wa = wide_A(h, V), sa = split_A(h, V);
     if (V.nu == 1) {
-        if (wsp) k_post_s<T, TB, TX, 8><<<gr, WG, 0, h->stream>>>(SP, minv, b, r, xc, out, d, Rf);
+        if (ssp) k_post_s<T, TB, TX, GB_SPLIT><<<gr, WG, 0, h->stream>>>(SP, minv, b, r, xc, out, d, Rf);
+        else if (wsp) k_post_s<T, TB, TX, 8><<<gr, WG, 0, h->stream>>>(SP, minv, b, r, xc, out, d, Rf);
         else k_post_s<T, TB, TX, 4><<<gr, WG, 0, h->stream>>>(SP, minv, b, r, xc, out, d, Rf);
         return;
     }
     T* ta = LV<T>::xt(V);
     T* tb = LV<T>::xt2(V);
     const T* sn = LV<T>::s(V);
-    if (wsp) k_post_s<T, T, T, 8><<<gr, WG, 0, h->stream>>>(SP, minv, sn, r, xc, ta, nullptr, Rn);
+    if (ssp) k_post_s<T, T, T, GB_SPLIT><<<gr, WG, 0, h->stream>>>(SP, minv, sn, r, xc, ta, nullptr, Rn);
+    else if (wsp) k_post_s<T, T, T, 8><<<gr, WG, 0, h->stream>>>(SP, minv, sn, r, xc, ta, nullptr, Rn);
     else k_post_s<T, T, T, 4><<<gr, WG, 0, h->stream>>>(SP, minv, sn, r, xc, ta, nullptr, Rn);
     const T* xin = ta;
     for (int k = 2; k <= V.nu; k++) {
         with_A_t<T>(h, V, [&](auto A) {
             using M = decltype(A);
             if (k == V.nu) {
-                if (wa) k_sweep<M, TB, TX, 8><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, out, d, Rf);
+                if (sa) k_sweep<M, TB, TX, GB_SPLIT><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, out, d, Rf);
+                else if (wa) k_sweep<M, TB, TX, 8><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, out, d, Rf);
                 else k_sweep<M, TB, TX, 4><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, out, d, Rf);
             } else {
                 T* xo = xin == ta ? tb : ta;
-                if (wa) k_sweep<M, TB, T, 8><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, xo, nullptr, Rn);
+                if (sa) k_sweep<M, TB, T, GB_SPLIT><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, xo, nullptr, Rn);
+                else if (wa) k_sweep<M, TB, T, 8><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, xo, nullptr, Rn);
                 else k_sweep<M, TB, T, 4><<<gr, WG, 0, h->stream>>>(A, minv, b, xin, xo, nullptr, Rn);
                 xin = xo;
             }
@@ -2948,7 +3079,7 @@ static void vcycle_t(psc_hier* h, const double* r0, double* z0, const double* d,
         }
         {
             TimeScope t(h, l == 0 ? 3 : 7);
-            launch_spmv(h, LV<T>::R(V), (const T*)LV<T>::r(V), LV<T>::b(h->lev[l + 1]), g, V.R.wmax > 8);
+            launch_spmv(h, LV<T>::R(V), (const T*)LV<T>::r(V), LV<T>::b(h->lev[l + 1]), g, V.R.wmax > 8, V.R.wmax > SPLIT_W);
         }
     }
     if (tail) {
@@ -3036,7 +3167,7 @@ static void vcycle_fai(psc_hier* h, const double* r0, double* z0, const double* 
         };
         if (l == 0) pre(r0);
         else pre((const T*)LV<T>::b(V));
-        launch_spmv(h, LV<T>::R(V), (const T*)LV<T>::r(V), LV<T>::b(h->lev[l + 1]), g, V.R.wmax > 8);
+        launch_spmv(h, LV<T>::R(V), (const T*)LV<T>::r(V), LV<T>::b(h->lev[l + 1]), g, V.R.wmax > 8, V.R.wmax > SPLIT_W);
     }
     {
         DevLevel& C = h->lev[L - 1];
@@ -3120,7 +3251,7 @@ static void vcycle_cheb(psc_hier* h, const double* r0, double* z0, const double*
         };
         if (l == 0) pre(r0);
         else pre((const T*)LV<T>::b(V));
-        launch_spmv(h, LV<T>::R(V), (const T*)LV<T>::r(V), LV<T>::b(h->lev[l + 1]), g, V.R.wmax > 8);
+        launch_spmv(h, LV<T>::R(V), (const T*)LV<T>::r(V), LV<T>::b(h->lev[l + 1]), g, V.R.wmax > 8, V.R.wmax > SPLIT_W);
     }
     {
         DevLevel& C = h->lev[L - 1];
