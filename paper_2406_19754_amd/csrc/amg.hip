@@ -802,6 +802,12 @@ __device__ __forceinline__ void dia_pair_rows(const Dia<T>& A, long long S, int 
 struct Gather2 {
     v2u<double> a, b;
 };
+// Two gathered vectors of any element types.
+template <typename A, typename B>
+struct GatherAB {
+    v2u<A> a;
+    v2u<B> b;
+};
 
 // Row sum of either storage format; GB is the batch of the wide-row path.
 template <int GB = 4, typename T, typename G>
@@ -1548,8 +1554,33 @@ __global__ __launch_bounds__(WG) void k_presweep(M AM, const TB* __restrict__ b,
     }
     constexpr int GBN = GB == GB_SPLIT ? 4 : GB;   // (the split form returned above)
     long long lo, hi;
-    chunk_range(AM.nslices, lo, hi);
     const int lane = threadIdx.x & 63, w = wave_id();
+    if constexpr (std::is_same<M, Dia<T>>::value) {
+        if (dia_pair_on(AM)) {
+            // two rows per lane, every diagonal's loads in flight together
+            chunk_range(dia_blocks(AM), lo, hi);
+            for (long long S = lo + w; S < hi; S += WG / 64) {
+                T a0, a1;
+                dia_pair_rows_lc(
+                    AM, S, lane, [&](long long c) { return GatherAB<TS, T>{ld2(sprev + c), ld2(rprev + c)}; },
+                    [&](const GatherAB<TS, T>& t) { return v2u<T>{(T)t.a.x + t.b.x, (T)t.a.y + t.b.y}; },
+                    [&](int c) { return (T)sprev[c] + rprev[c]; }, a0, a1);
+                const long long row = S * (2 * SLICE) + 2 * lane;
+                if (row + 1 < AM.nrows) {
+                    const v2u<TS> sp = ld2(sprev + row);
+                    const v2u<T> rp = ld2(rprev + row);
+                    const v2u<TB> bb = ld2(b + row);
+                    st2(sout + row, (T)sp.x + rp.x, (T)sp.y + rp.y);
+                    st2(rout + row, (T)bb.x - a0, (T)bb.y - a1);
+                } else if (row < AM.nrows) {
+                    sout[row] = (T)sprev[row] + rprev[row];
+                    rout[row] = (T)b[row] - a0;
+                }
+            }
+            return;
+        }
+    }
+    chunk_range(AM.nslices, lo, hi);
     for (long long s = lo + w; s < hi; s += WG / 64) {
         const T acc = mat_row<GBN>(AM, s, lane, [&](int c) { return (T)sprev[c] + rprev[c]; });
         const long long row = s * SLICE + lane;
@@ -1582,8 +1613,37 @@ __global__ __launch_bounds__(WG) void k_sweep(M A, const typename M::value_type*
     }
     constexpr int GBN = GB == GB_SPLIT ? 4 : GB;   // (the split form returned above)
     long long lo, hi;
-    chunk_range(A.nslices, lo, hi);
     const int lane = threadIdx.x & 63, w = wave_id();
+    if constexpr (std::is_same<M, Dia<T>>::value) {
+        if (dia_pair_on(A)) {
+            // two rows per lane
+            chunk_range(dia_blocks(A), lo, hi);
+            for (long long S = lo + w; S < hi; S += WG / 64) {
+                T a0, a1;
+                dia_pair_rows(A, S, lane, [&](long long c) { return ld2(xin + c); }, [&](int c) { return xin[c]; },
+                              a0, a1);
+                const long long row = S * (2 * SLICE) + 2 * lane;
+                if (row + 1 < A.nrows) {
+                    const v2u<T> xx = ld2(xin + row), mm = ld2(minv + row);
+                    const v2u<TB> bb = ld2(b + row);
+                    const T x0 = xx.x + mm.x * ((T)bb.x - a0), x1 = xx.y + mm.y * ((T)bb.y - a1);
+                    st2(xout + row, (TX)x0, (TX)x1);
+                    if (d) {
+                        const v2u<double> dd = ld2(d + row);
+                        s0 += (double)(TX)x0 * dd.x;
+                        s0 += (double)(TX)x1 * dd.y;
+                    }
+                } else if (row < A.nrows) {
+                    const T xi = xin[row] + minv[row] * ((T)b[row] - a0);
+                    xout[row] = (TX)xi;
+                    if (d) s0 += (double)(TX)xi * d[row];
+                }
+            }
+            if (R.fin != FIN_NONE) block_partial(s0, 0.0, R.part);
+            return;
+        }
+    }
+    chunk_range(A.nslices, lo, hi);
     for (long long s = lo + w; s < hi; s += WG / 64) {
         const T acc = mat_row<GBN>(A, s, lane, [&](int c) { return xin[c]; });
         const long long row = s * SLICE + lane;
