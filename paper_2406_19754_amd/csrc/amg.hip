@@ -639,6 +639,25 @@ __device__ __forceinline__ T dia_row(const Dia<T>& A, long long s, int lane, G g
         const int ks = A.pair ? 2 * SLICE : SLICE;   // diagonal stride
         const T* vp = A.val + (A.pair ? (s >> 1) * (long long)nd * 2 * SLICE + (s & 1) * SLICE
                                       : s * (long long)nd * SLICE) + lane;
+        if (nd == 7) {
+            // 7-point stencils: the diagonal count known at compile time, so
+            // no branch per diagonal (a gather that combines several loads
+            // would otherwise wait for each diagonal's before the next)
+            T v[7];
+            int c[7];
+#pragma unroll
+            for (int k = 0; k < 7; k++) {
+                v[k] = ntload(vp + k * ks);
+                c[k] = min(max(row + A.uo[k], 0), cmax);
+            }
+            T gv[7];
+#pragma unroll
+            for (int k = 0; k < 7; k++) gv[k] = g(c[k]);
+            T acc = T(0);
+#pragma unroll
+            for (int k = 0; k < 7; k++) acc += v[k] * gv[k];
+            return acc;
+        }
         T v[8];
         int c[8];
 #pragma unroll
