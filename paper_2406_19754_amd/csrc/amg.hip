@@ -785,7 +785,18 @@ __device__ __forceinline__ void dia_pair_rows_lc(const Dia<T>& A, long long S, i
     const bool inner = b0 + A.uo[0] >= 0 && b0 + 2 * SLICE - 1 + A.uo[nd - 1] < A.ncols &&
                        b0 + 2 * SLICE <= A.nrows;
     T s0 = T(0), s1 = T(0);
-    if (inner) {
+    if (inner && nd == 7) {
+        // 7-point stencils: no branch per diagonal
+        decltype(gl(0ll)) g[7];
+#pragma unroll
+        for (int k = 0; k < 7; k++) g[k] = gl(r0 + A.uo[k]);
+#pragma unroll
+        for (int k = 0; k < 7; k++) {
+            const v2u<T> c = cb(g[k]);
+            s0 += v[k].x * c.x;
+            s1 += v[k].y * c.y;
+        }
+    } else if (inner) {
         decltype(gl(0ll)) g[8];
 #pragma unroll
         for (int k = 0; k < 8; k++)
