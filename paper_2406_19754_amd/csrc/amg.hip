@@ -1504,6 +1504,37 @@ __global__ __launch_bounds__(WG) void k_post_s(Ell<T> SP, const T* __restrict__ 
             const i2* cp = (const i2*)(SP.col + b0) + lane;
             T a0 = T(0), a1 = T(0);
             int k = 0;
+            // FP64: the usual widths (5 and 6 slots: a tentative prolongator's
+            // own aggregate and its stencil neighbours' ones) in one batch,
+            // every slot's loads and gathers in flight together (same sums,
+            // same order); FP32 levels keep the batches of GBN, which measure
+            // faster there
+            auto whole = [&](auto wc) {
+                constexpr int W = decltype(wc)::value;
+                v2a<T> v[W];
+                i2 c[W];
+#pragma unroll
+                for (int j = 0; j < W; j++) {
+                    v[j] = ntload(vp + j * SLICE);
+                    c[j] = ntload(cp + j * SLICE);
+                }
+                T g0[W], g1[W];
+#pragma unroll
+                for (int j = 0; j < W; j++) {
+                    g0[j] = xc[c[j].x];
+                    g1[j] = xc[c[j].y];
+                }
+#pragma unroll
+                for (int j = 0; j < W; j++) {
+                    a0 += v[j].x * g0[j];
+                    a1 += v[j].y * g1[j];
+                }
+                k = W;
+            };
+            if constexpr (sizeof(T) == 8) {
+                if (ws == 5) whole(std::integral_constant<int, 5>{});
+                else if (ws == 6) whole(std::integral_constant<int, 6>{});
+            }
             for (; k + GBN <= ws; k += GBN) {
                 v2a<T> v[GBN];
                 i2 c[GBN];
