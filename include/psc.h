@@ -142,6 +142,11 @@ typedef struct psc_net  psc_net;    /* opaque: owns the learned preconditioner  
  *   coarse_rtol = 1e-4  tolerance of that solve (>= 0; 0: always the cap).
  *   ainv_tau = 0.1   AINV drop tolerance (>= 0).
  *   invk_fill = 0, invk_inv_fill = 1   INVK levels of fill (0..64).
+ *   capped_min_rows = 65536  levels with at least this many rows whose row
+ *                    lengths vary widely get a capped hacked-ELL copy
+ *                    (PSC_TUNE_CAPPED); smaller levels are bound by their
+ *                    longest slice, not by the bytes read, and keep the plain
+ *                    layout. 1: every level where a cap pays; 0: none.
  *   host_only = 0    build the hierarchy on the host only and make no HIP
  *                    call (for inspection with psc_hier_info and
  *                    psc_hier_export_level on machines without a GPU);
@@ -174,7 +179,7 @@ typedef struct {
     double  vbm_theta;
     double  ainv_tau;
     int32_t coarse_pcg_iters;
-    int32_t reserved2;
+    int32_t capped_min_rows;
     double  coarse_rtol;
 } psc_amg_opts;
 
@@ -304,6 +309,9 @@ typedef struct {
     int32_t coarse_pcg_iters;                /* > 0: coarsest solved by at most this many PCG iterations */
     int32_t tail_level;                      /* first level run by the one-workgroup tail (0: none) */
     int32_t tail_lds_bytes;                  /* LDS of the FP64 tail kernel (0: none) */
+    int32_t capped_cap[PSC_MAX_LEVELS];      /* slots per row of A_l's capped hacked-ELL copy
+                                                (PSC_TUNE_CAPPED; 0: no such copy) */
+    int64_t capped_slots[PSC_MAX_LEVELS];    /* its slice slots, plus its overflow entries */
 } psc_hier_stats;
 
 int psc_hier_info(const psc_hier* h, psc_hier_stats* s);
@@ -438,6 +446,18 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
  * in a fixed order either way; their grouping follows the grid, so results
  * agree up to rounding. */
 #define PSC_TUNE_DIA_ALIGN 13
+/* PSC_TUNE_CAPPED (default 1): a level without a hacked-DIA copy, with at
+ * least capped_min_rows rows, whose row lengths vary so widely that its
+ * hacked-ELL slices are mostly padding (a few long rows in most 64-row
+ * slices, as on the stalled coarse levels of strongly varying coefficients)
+ * is read, by the kernels that take it (smoothing sweeps, residuals, the
+ * l1-Jacobi coarsest solve, psc_spmv), from a copy whose slices keep at most
+ * a cap of slots per row, the rest of each longer row in an overflow that one
+ * wavefront sums with a segmented scan; the build keeps that copy when it
+ * costs at most 0.75 of the plain layout's wavefront loads. 0 reads the plain
+ * hacked ELL. Same values up to rounding (overflow entries are summed in scan
+ * order). */
+#define PSC_TUNE_CAPPED 14
 int psc_tune(psc_hier* h, int32_t key, int32_t value);
 
 void psc_hier_free(psc_hier* h);

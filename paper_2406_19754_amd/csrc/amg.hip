@@ -414,6 +414,77 @@ __device__ __forceinline__ T ell_row(const Ell<T>& A, long long s, int lane, G g
     return acc;
 }
 
+// Lanes of one wavefront exchanging values through LDS: order the writes of
+// every lane before the reads that follow.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Overflow of slice s in a capped layout (see Ell), as the row sum of each
+// lane's row (0 for rows without overflow). The wavefront takes the entries
+// 64 at a time, lane j one entry, four such rounds with all their loads and
+// gathers in flight together; within a round a row's entries are adjacent
+// lanes, summed by a segmented inclusive scan (distances 1, 2, 4, ..., 32,
+// each adding the partial sum d lanes down when it belongs to the same row),
+// and the last lane of each run adds its sum to the row's slot in LDS (one
+// writer per row and round, rounds in order). The wavefront's LDS accesses
+// run in program order, and the compiler keeps the order of these (their
+// addresses may alias). Every lane of the wavefront must call this with the
+// same s; workgroups of up to 1024 threads.
+template <typename T, typename G>
+__device__ __forceinline__ T ell_ovf(const EllC<T>& A, long long s, int lane, G g) {
+    constexpr int RB = 4;
+    __shared__ T ov_acc[16][SLICE];
+    T* acc = ov_acc[threadIdx.x >> 6];
+    acc[lane] = T(0);
+    const long long e0 = A.xs[s], e1 = A.xs[s + 1];
+    wave_lds_sync();
+    for (long long base = e0; base < e1; base += RB * SLICE) {
+        T v[RB], p[RB];
+        int c[RB], key[RB];
+#pragma unroll
+        for (int t = 0; t < RB; t++) {
+            const long long e = base + t * SLICE + lane;
+            key[t] = SLICE + lane;   // lanes past the end: a key of their own
+            v[t] = T(0);
+            c[t] = 0;
+            if (e < e1) {
+                key[t] = A.xl[e];
+                v[t] = A.xv[e];
+                c[t] = A.xc[e];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RB; t++) p[t] = base + t * SLICE + lane < e1 ? v[t] * g(c[t]) : T(0);
+#pragma unroll
+        for (int t = 0; t < RB; t++) {
+#pragma unroll
+            for (int d = 1; d < SLICE; d <<= 1) {
+                const T q = __shfl_up(p[t], d);
+                const int kq = __shfl_up(key[t], d);
+                if (lane >= d && kq == key[t]) p[t] += q;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RB; t++) {
+            const int kn = __shfl_down(key[t], 1);
+            if (key[t] < SLICE && (lane == SLICE - 1 || kn != key[t])) acc[key[t]] += p[t];
+        }
+    }
+    wave_lds_sync();
+    return acc[lane];
+}
+
+// Row sum over one row of a capped layout: its slots, then its overflow.
+// Wave-uniform s.
+template <typename T, typename G, int U = 8, int GB = 4>
+__device__ __forceinline__ T ell_row(const EllC<T>& A, long long s, int lane, G g) {
+    T acc = ell_row<T, G, U, GB>(static_cast<const Ell<T>&>(A), s, lane, g);
+    return acc + ell_ovf(A, s, lane, g);
+}
+
 // Operators with wide rows (the coarse operators, transfers and smoothed
 // prolongators of smoothed hierarchies: hundreds to thousands of slots per
 // row) are latency-bound with one lane per row walking its slots, and their
@@ -466,14 +537,19 @@ __device__ __forceinline__ T ell_row_part(const Ell<T>& A, long long s, int lane
 // The split form's loop over the slices of this workgroup's chunk: row sums
 // a = sum_k v_k g(col_k), then epi(row, a) on wavefront 0. Every thread of the
 // workgroup runs the loop (two barriers per slice).
-template <typename T, typename G, typename E>
-__device__ __forceinline__ void ell_split_slices(const Ell<T>& A, G g, E epi) {
+template <typename MT, typename G, typename E>
+__device__ __forceinline__ void ell_split_slices(const MT& A, G g, E epi) {
+    using T = typename MT::value_type;
     __shared__ T part[WG / 64][SLICE];
     long long lo, hi;
     chunk_range(A.nslices, lo, hi);
     const int lane = threadIdx.x & 63, q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (long long s = lo; s < hi; s++) {
-        part[q][lane] = ell_row_part(A, s, lane, q, g);
+        T a = ell_row_part(static_cast<const Ell<T>&>(A), s, lane, q, g);
+        if constexpr (std::is_same<MT, EllC<T>>::value) {
+            if (q == 0) a += ell_ovf(A, s, lane, g);
+        }
+        part[q][lane] = a;
         __syncthreads();
         if (q == 0) {
             const T a = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
@@ -607,6 +683,17 @@ __device__ __forceinline__ T ell_row_buf(const Ell<T>& A, long long s, int lane,
     for (int k = 0; k < w; k++)
         acc += bload<T, 2>(rv, lv + (unsigned)k * SLICE * sizeof(T)) * g(bload<int, 2>(rc, lc + (unsigned)k * SLICE * 4));
     return acc;
+}
+
+// The capped layout reads its slots with plain loads, then its overflow.
+template <typename T, typename G>
+__device__ __forceinline__ T ell_row_buf(const EllC<T>& A, long long s, int lane, G g) {
+    return ell_row(A, s, lane, g);
+}
+template <typename T, typename G>
+__device__ __forceinline__ void ell_row2(const EllC<T>& A, long long s1, long long s2, int lane, G g, T& a1, T& a2) {
+    a1 = ell_row(A, s1, lane, g);
+    a2 = ell_row(A, s2, lane, g);
 }
 
 // wave-uniform wave index of this thread within its workgroup
@@ -845,6 +932,10 @@ __device__ __forceinline__ T mat_row(const Ell<T>& A, long long s, int lane, G g
     return ell_row<T, G, 8, GB>(A, s, lane, g);
 }
 template <int GB = 4, typename T, typename G>
+__device__ __forceinline__ T mat_row(const EllC<T>& A, long long s, int lane, G g) {
+    return ell_row<T, G, 8, GB>(A, s, lane, g);
+}
+template <int GB = 4, typename T, typename G>
 __device__ __forceinline__ T mat_row(const Dia<T>& A, long long s, int lane, G g) {
     return dia_row<T, G, GB>(A, s, lane, g);
 }
@@ -860,7 +951,7 @@ __global__ __launch_bounds__(WG) void k_spmv(M A, const typename M::value_type* 
     using T = typename M::value_type;
     if (gate_skip(g)) return;
     if constexpr (GB == GB_SPLIT) {
-        if constexpr (std::is_same<M, Ell<T>>::value)
+        if constexpr (is_ell<M>::value)
             ell_split_slices(A, [&](int c) { return x[c]; }, [&](long long row, T a) { y[row] = a; });
         return;
     }
@@ -1381,7 +1472,7 @@ __global__ __launch_bounds__(WG) void k_pre_s(M AM, const TB* __restrict__ b, ty
     using T = typename M::value_type;
     if (gate_skip(g)) return;
     if constexpr (GB == GB_SPLIT) {
-        if constexpr (std::is_same<M, Ell<T>>::value)
+        if constexpr (is_ell<M>::value)
             ell_split_slices(AM, [&](int c) { return (T)b[c]; }, [&](long long row, T a) { r[row] = (T)b[row] - a; });
         return;
     }
@@ -1606,7 +1697,7 @@ __global__ __launch_bounds__(WG) void k_presweep(M AM, const TB* __restrict__ b,
     using T = typename M::value_type;
     if (gate_skip(g)) return;
     if constexpr (GB == GB_SPLIT) {
-        if constexpr (std::is_same<M, Ell<T>>::value)
+        if constexpr (is_ell<M>::value)
             ell_split_slices(AM, [&](int c) { return (T)sprev[c] + rprev[c]; }, [&](long long row, T a) {
                 sout[row] = (T)sprev[row] + rprev[row];
                 rout[row] = (T)b[row] - a;
@@ -1663,7 +1754,7 @@ __global__ __launch_bounds__(WG) void k_sweep(M A, const typename M::value_type*
     if (skip_red(R)) return;
     double s0 = 0.0;
     if constexpr (GB == GB_SPLIT) {
-        if constexpr (std::is_same<M, Ell<T>>::value)
+        if constexpr (is_ell<M>::value)
             ell_split_slices(A, [&](int c) { return xin[c]; }, [&](long long row, T a) {
                 const T xi = xin[row] + minv[row] * ((T)b[row] - a);
                 xout[row] = (TX)xi;
@@ -1895,6 +1986,8 @@ __host__ __device__ inline int tail_xslot(int nu) { return nu == 1 ? 1 : (nu % 2
 // r_k = b - A M^-1 s_k; post: x = M^-1 (s + r) + S P x_c, then
 // x += M^-1 (b - A x)), dense or PCG coarsest. Same arithmetic as k_pre_s,
 // k_presweep, k_spmv on R, k_coarse or k_coarse_pcg, k_post_s and k_sweep.
+// The operators are the levels' plain hacked ELL (or DIA), never the capped
+// copies.
 template <typename T>
 __global__ __launch_bounds__(TAIL_WG) void k_tail(const TailDesc<T>* __restrict__ D, Gate g) {
     if (gate_skip(g)) return;
@@ -2009,6 +2102,24 @@ __global__ __launch_bounds__(WG) void k_jacobi(M A, const double* __restrict__ m
                                                TX* __restrict__ xout, Gate g) {
     if (gate_skip(g)) return;
     long long lo, hi;
+    if constexpr (GB == GB_SPLIT) {
+        // rows wider than SPLIT_W slots: the four wavefronts share each slice
+        if constexpr (is_ell<M>::value) {
+            if (xin) {
+                ell_split_slices(A, [&](int c) { return xin[c]; }, [&](long long row, double a) {
+                    xout[row] = (TX)(xin[row] + minv[row] * ((double)b[row] - a));
+                });
+            } else {
+                chunk_range(A.nslices, lo, hi);
+                for (long long s = lo; s < hi; s++) {
+                    const long long row = s * SLICE + threadIdx.x;
+                    if (threadIdx.x < SLICE && row < A.nrows) xout[row] = (TX)(minv[row] * (double)b[row]);
+                }
+            }
+        }
+        return;
+    }
+    constexpr int GBN = GB == GB_SPLIT ? 4 : GB;   // (the split form returned above)
     chunk_range(A.nslices, lo, hi);
     const int lane = threadIdx.x & 63, w = wave_id();
     for (long long s = lo + w; s < hi; s += WG / 64) {
@@ -2017,7 +2128,7 @@ __global__ __launch_bounds__(WG) void k_jacobi(M A, const double* __restrict__ m
             if (row < A.nrows) xout[row] = (TX)(minv[row] * (double)b[row]);
             continue;
         }
-        double acc = mat_row<GB>(A, s, lane, [&](int c) { return xin[c]; });
+        double acc = mat_row<GBN>(A, s, lane, [&](int c) { return xin[c]; });
         if (row < A.nrows) xout[row] = (TX)(xin[row] + minv[row] * ((double)b[row] - acc));
     }
 }
@@ -2042,10 +2153,26 @@ __global__ __launch_bounds__(WG) void k_fres(M A, const TB* __restrict__ b, cons
     using T = typename M::value_type;
     if (gate_skip(g)) return;
     long long lo, hi;
+    if constexpr (GB == GB_SPLIT) {
+        // rows wider than SPLIT_W slots: the four wavefronts share each slice
+        if constexpr (is_ell<M>::value) {
+            if (x) {
+                ell_split_slices(A, [&](int c) { return x[c]; }, [&](long long row, T a) { t[row] = (T)b[row] - a; });
+            } else {
+                chunk_range(A.nslices, lo, hi);
+                for (long long s = lo; s < hi; s++) {
+                    const long long row = s * SLICE + threadIdx.x;
+                    if (threadIdx.x < SLICE && row < A.nrows) t[row] = (T)b[row];
+                }
+            }
+        }
+        return;
+    }
+    constexpr int GBN = GB == GB_SPLIT ? 4 : GB;   // (the split form returned above)
     chunk_range(A.nslices, lo, hi);
     const int lane = threadIdx.x & 63, w = wave_id();
     for (long long s = lo + w; s < hi; s += WG / 64) {
-        const T acc = x ? mat_row<GB>(A, s, lane, [&](int c) { return x[c]; }) : T(0);
+        const T acc = x ? mat_row<GBN>(A, s, lane, [&](int c) { return x[c]; }) : T(0);
         const long long row = s * SLICE + lane;
         if (row < A.nrows) t[row] = (T)b[row] - acc;
     }
@@ -2224,6 +2351,14 @@ struct DevEll {
     long long nrows = 0, nslices = 0, slots = 0, ncols = 0, nnz = 0;
     int wmax = 0;                          // widest slice (entries per row)
     int pair = 0;                          // paired 128-row layout (see Ell)
+    // capped layout (see Ell): per-slice overflow ranges and their entries
+    long long* xs = nullptr;
+    int* xc = nullptr;
+    unsigned char* xl = nullptr;
+    T* xv = nullptr;
+    float* xv32 = nullptr;
+    int cap = 0;                           // slots per row kept in the slices (0: plain layout)
+    long long xents = 0;                   // overflow entries
     Ell<T> view() const {
         Ell<T> e{off, val, col, nrows, nslices, ncols};
         e.pair = pair;
@@ -2232,6 +2367,19 @@ struct DevEll {
     Ell<float> view32() const {
         Ell<float> e{off, val32, col, nrows, nslices, ncols};
         e.pair = pair;
+        return e;
+    }
+    // the capped layout (xs != nullptr)
+    EllC<T> cview() const {
+        EllC<T> e;
+        static_cast<Ell<T>&>(e) = view();
+        e.xs = xs, e.xv = xv, e.xc = xc, e.xl = xl;
+        return e;
+    }
+    EllC<float> cview32() const {
+        EllC<float> e;
+        static_cast<Ell<float>&>(e) = view32();
+        e.xs = xs, e.xv = xv32, e.xc = xc, e.xl = xl;
         return e;
     }
 };
@@ -2274,6 +2422,13 @@ struct DevLevel {
     float* am32 = nullptr;
     Ell<double> am_view() const { Ell<double> e = A.view(); e.val = am; return e; }
     Ell<float> am_view32() const { Ell<float> e = A.view32(); e.val = am32; return e; }
+    // capped hacked-ELL copy of A (and A M^-1 in its slots and records) for
+    // levels whose row lengths vary widely; Ac.off == nullptr: none
+    DevEll<double> Ac;
+    double *acm = nullptr, *acm_x = nullptr;
+    float *acm32 = nullptr, *acm32_x = nullptr;
+    EllC<double> acm_view() const { EllC<double> e = Ac.cview(); e.val = acm; e.xv = acm_x; return e; }
+    EllC<float> acm_view32() const { EllC<float> e = Ac.cview32(); e.val = acm32; e.xv = acm32_x; return e; }
     double* minv = nullptr;
     float* minv32 = nullptr;
     int* agg = nullptr;
@@ -2369,6 +2524,7 @@ struct psc_hier {
     bool spmv2 = false;                   // plain SpMV / restriction: two slices per wavefront
     bool split = true;                    // smoothing sweeps through A M^-1 and A P
     bool dia = true;                      // use the hacked-DIA copies where a level has them
+    bool capped = true;                   // use the capped hacked-ELL copies where a level has them
     bool dia_uniform = true;              // a level with <= 8 distinct offsets keeps them in the kernel argument
     bool dia_align = true;                // grids aligned to the largest DIA offset (grid_lvl)
     bool mixed_split = true;              // FP32 V-cycle: residual update and pre-smoothing as two passes
@@ -2646,6 +2802,64 @@ static int upload_ell_layout(psc_hier* h, DevEll<double>& E, int64_t nrows, int6
     return PSC_OK;
 }
 
+// Capped hacked-ELL copy of level operator A (see Ell) with, when mv is
+// given, A M^-1 (a_ij mv_j) in the same slots and overflow, and FP32 copies
+// when f32; built for levels of at least capped_min_rows rows when
+// choose_ell_cap finds a cap that pays, refilled with the same cap by a
+// numeric rebuild.
+static std::vector<float> to32(const std::vector<double>& a);
+static int upload_capped(psc_hier* h, DevLevel& D, const HostLevel& H, const double* mv, bool f32) {
+    const int min_rows = h->opts.capped_min_rows;
+    if (!h->refresh && (min_rows <= 0 || H.n < min_rows)) return PSC_OK;
+    const int cap = h->refresh ? D.Ac.cap : choose_ell_cap(H.n, H.rp.data());
+    if (cap <= 0) return PSC_OK;
+    std::vector<long long> off, xs, xsrc;
+    std::vector<double> val;
+    std::vector<int> col, xc;
+    std::vector<unsigned char> xl;
+    pack_ell_capped(H.n, H.rp.data(), H.ci.data(), H.v.data(), cap, off, val, col, xs, xc, xl, xsrc);
+    DevEll<double>& E = D.Ac;
+    E.cap = cap;
+    E.nrows = H.n;
+    E.ncols = H.n;
+    E.nnz = H.rp[H.n];
+    E.nslices = (long long)off.size() - 1;
+    E.slots = off.back();
+    E.xents = (long long)xsrc.size();
+    E.wmax = 0;
+    for (size_t q = 0; q + 1 < off.size(); q++) E.wmax = std::max(E.wmax, (int)((off[q + 1] - off[q]) / SLICE));
+    std::vector<double> xv(xsrc.size());
+    for (size_t e = 0; e < xsrc.size(); e++) xv[e] = H.v[xsrc[e]];
+    int st;
+    if ((st = upload(h, &E.off, off.data(), off.size()))) return st;
+    if ((st = upload(h, &E.col, col.data(), col.size()))) return st;
+    if ((st = upload(h, &E.xs, xs.data(), xs.size()))) return st;
+    if ((st = upload(h, &E.xc, xc.data(), xc.size()))) return st;
+    if ((st = upload(h, &E.xl, xl.data(), xl.size()))) return st;
+    if ((st = upload(h, &E.val, val.data(), val.size()))) return st;
+    if ((st = upload(h, &E.xv, xv.data(), xv.size()))) return st;
+    if (f32) {
+        auto v32 = to32(val), x32 = to32(xv);
+        if ((st = upload(h, &E.val32, v32.data(), v32.size()))) return st;
+        if ((st = upload(h, &E.xv32, x32.data(), x32.size()))) return st;
+    }
+    if (mv) {
+        // A M^-1: the same product as the plain layout's refresh (a_ij mv_j);
+        // padding slots hold 0
+        std::vector<double> am(val.size()), amx(xv.size());
+        for (size_t k = 0; k < val.size(); k++) am[k] = val[k] * mv[col[k]];
+        for (size_t e = 0; e < xv.size(); e++) amx[e] = xv[e] * mv[xc[e]];
+        if ((st = upload(h, &D.acm, am.data(), am.size()))) return st;
+        if ((st = upload(h, &D.acm_x, amx.data(), amx.size()))) return st;
+        if (f32) {
+            auto a32 = to32(am), ax32 = to32(amx);
+            if ((st = upload(h, &D.acm32, a32.data(), a32.size()))) return st;
+            if ((st = upload(h, &D.acm32_x, ax32.data(), ax32.size()))) return st;
+        }
+    }
+    return PSC_OK;
+}
+
 static std::vector<float> to32(const std::vector<double>& a) {
     std::vector<float> r(a.size());
     for (size_t i = 0; i < a.size(); i++) r[i] = (float)a[i];
@@ -2750,26 +2964,32 @@ static int grid_lvl(const psc_hier* h, const DevLevel& V) {
 }
 
 // Call f with the level operator (FP64 / FP32) or its scaled form A M^-1 in
-// the storage the level uses: hacked DIA when present and enabled, else
-// hacked ELL. Both have the same slices, so grids do not change.
+// the storage the level uses: hacked DIA when present and enabled, else the
+// capped hacked ELL when present and enabled, else hacked ELL. All have the
+// same slices, so grids do not change.
+static inline bool capped_on(const psc_hier* h, const DevLevel& V) { return h->capped && V.Ac.off != nullptr; }
 template <typename F>
 static void with_A(const psc_hier* h, const DevLevel& V, F f) {
     if (h->dia && V.Ad.on()) f(V.Ad.view(V.Ad.val));
+    else if (capped_on(h, V)) f(V.Ac.cview());
     else f(V.A.view());
 }
 template <typename F>
 static void with_A32(const psc_hier* h, const DevLevel& V, F f) {
     if (h->dia && V.Ad.on()) f(V.Ad.view32(V.Ad.val32));
+    else if (capped_on(h, V)) f(V.Ac.cview32());
     else f(V.A.view32());
 }
 template <typename F>
 static void with_AM(const psc_hier* h, const DevLevel& V, F f) {
     if (h->dia && V.Ad.on()) f(V.Ad.view(V.amd));
+    else if (capped_on(h, V) && V.acm) f(V.acm_view());
     else f(V.am_view());
 }
 template <typename F>
 static void with_AM32(const psc_hier* h, const DevLevel& V, F f) {
     if (h->dia && V.Ad.on()) f(V.Ad.view32(V.amd32));
+    else if (capped_on(h, V) && V.acm32) f(V.acm_view32());
     else f(V.am_view32());
 }
 template <typename T, typename F>
@@ -2785,12 +3005,12 @@ static void with_AM_t(const psc_hier* h, const DevLevel& V, F f) {
 // Rows wider than 8 entries take the 8-slot batch kernels (more registers,
 // more loads in flight); stencil operators keep the 4-slot ones.
 static bool wide_A(const psc_hier* h, const DevLevel& V) {
-    return (h->dia && V.Ad.on()) ? V.Ad.ndmax > 8 : V.A.wmax > 8;
+    return (h->dia && V.Ad.on()) ? V.Ad.ndmax > 8 : (capped_on(h, V) ? V.Ac.wmax : V.A.wmax) > 8;
 }
 // Level V's operator read from hacked ELL with rows wider than SPLIT_W slots:
 // its kernels take the split form (GB_SPLIT) on one slice per workgroup.
 static bool split_A(const psc_hier* h, const DevLevel& V) {
-    return !(h->dia && V.Ad.on()) && V.A.wmax > SPLIT_W;
+    return !(h->dia && V.Ad.on()) && (capped_on(h, V) ? V.Ac.wmax : V.A.wmax) > SPLIT_W;
 }
 static inline int grid_vec(const psc_hier* h, long long n) { return grid_of(h, 1024, n); }
 
@@ -2878,15 +3098,17 @@ static void launch_spmv(psc_hier* h, const M& A, const typename M::value_type* x
                         Gate g, bool wide = false, bool split = false) {
     using T = typename M::value_type;
     const int gr = grid_ell(h, A.nslices);
-    if constexpr (std::is_same<M, Ell<T>>::value) {
+    if constexpr (is_ell<M>::value) {
         if (split) {
             k_spmv<M, false, GB_SPLIT><<<grid_of(h, 1, A.nslices), WG, 0, h->stream>>>(A, x, y, g);
             return;
         }
-        if (h->spmv2) {
-            // two slices per wavefront: half the workgroups of the one-slice grid
-            k_spmv2<T><<<grid_of(h, 8, A.nslices), WG, 0, h->stream>>>(A, x, y, g);
-            return;
+        if constexpr (std::is_same<M, Ell<T>>::value) {
+            if (h->spmv2) {
+                // two slices per wavefront: half the workgroups of the one-slice grid
+                k_spmv2<T><<<grid_of(h, 8, A.nslices), WG, 0, h->stream>>>(A, x, y, g);
+                return;
+            }
         }
         if (h->bufload == 1) {
             k_spmv<M, true><<<gr, WG, 0, h->stream>>>(A, x, y, g);
@@ -2949,17 +3171,19 @@ static void coarse_solve(psc_hier* h, const TB* b, TX* x, Gate g) {
         return;
     }
     const int gr = grid_lvl(h, C);
-    const bool wide = wide_A(h, C);
+    const bool wide = wide_A(h, C), spl = split_A(h, C);
     with_A(h, C, [&](auto A) {
         using M = decltype(A);
         const double* xin = nullptr;
         for (int k = 1; k < K; k++) {
             double* xo = ((K - k) % 2 == 0) ? C.x : C.r;
-            if (wide) k_jacobi<M, TB, double, 8><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, xo, g);
+            if (spl) k_jacobi<M, TB, double, GB_SPLIT><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, xo, g);
+            else if (wide) k_jacobi<M, TB, double, 8><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, xo, g);
             else k_jacobi<M, TB, double, 4><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, xo, g);
             xin = xo;
         }
-        if (wide) k_jacobi<M, TB, TX, 8><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, x, g);
+        if (spl) k_jacobi<M, TB, TX, GB_SPLIT><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, x, g);
+        else if (wide) k_jacobi<M, TB, TX, 8><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, x, g);
         else k_jacobi<M, TB, TX, 4><<<gr, WG, 0, h->stream>>>(A, C.minv, b, xin, x, g);
     });
 }
@@ -3251,10 +3475,11 @@ static void vcycle_fai(psc_hier* h, const double* r0, double* z0, const double* 
     auto resid = [&](DevLevel& V, auto b, const T* x, T* t) {
         using TB = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
         const int gr = grid_lvl(h, V);
-        const bool wa = wide_A(h, V);
+        const bool wa = wide_A(h, V), sa = split_A(h, V);
         with_A_t<T>(h, V, [&](auto A) {
             using M = decltype(A);
-            if (wa) k_fres<M, TB, 8><<<gr, WG, 0, st>>>(A, b, x, t, g);
+            if (sa) k_fres<M, TB, GB_SPLIT><<<gr, WG, 0, st>>>(A, b, x, t, g);
+            else if (wa) k_fres<M, TB, 8><<<gr, WG, 0, st>>>(A, b, x, t, g);
             else k_fres<M, TB, 4><<<gr, WG, 0, st>>>(A, b, x, t, g);
         });
     };
@@ -3391,12 +3616,13 @@ static void vcycle_cheb(psc_hier* h, const double* r0, double* z0, const double*
         const int gp = grid_ell(h, V.P.nslices);
         if (V.P.wmax > 8) k_fprol<T, 8><<<gp, WG, 0, st>>>(LV<T>::P(V), LV<T>::x(h->lev[l + 1]), x, g);
         else k_fprol<T, 4><<<gp, WG, 0, st>>>(LV<T>::P(V), LV<T>::x(h->lev[l + 1]), x, g);
-        const bool wa = wide_A(h, V);
+        const bool wa = wide_A(h, V), sa = split_A(h, V);
         auto res = [&](auto b) {
             using TB = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
             with_A_t<T>(h, V, [&](auto A) {
                 using M = decltype(A);
-                if (wa) k_fres<M, TB, 8><<<gr, WG, 0, st>>>(A, b, x, t, g);
+                if (sa) k_fres<M, TB, GB_SPLIT><<<gr, WG, 0, st>>>(A, b, x, t, g);
+                else if (wa) k_fres<M, TB, 8><<<gr, WG, 0, st>>>(A, b, x, t, g);
                 else k_fres<M, TB, 4><<<gr, WG, 0, st>>>(A, b, x, t, g);
             });
         };
@@ -4063,6 +4289,7 @@ static int upload_levels(psc_hier* h) {
         if ((st = refresh_values(h, D.A, &D.Ad, H.n, H.rp.data(), H.v.data(), l < L - 1 ? mv.data() : nullptr,
                                  D.am, D.am32, D.amd, D.amd32, &a_rp_dev)))
             return st;
+        if (!D.Ad.on() && (st = upload_capped(h, D, H, l < L - 1 ? mv.data() : nullptr, f32))) return st;
         if ((st = upload(h, &D.minv, mv.data(), H.n))) return st;
         if (f32) {
             auto m32 = to32(mv);
@@ -4206,6 +4433,7 @@ void psc_amg_opts_default(psc_amg_opts* o) {
     o->ainv_tau = 0.1;
     o->coarse_pcg_iters = 0;
     o->coarse_rtol = 1e-4;
+    o->capped_min_rows = 65536;
 }
 
 void psc_hier_free(psc_hier* h) {
@@ -4260,6 +4488,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     h->nu = h->opts.smoother_sweeps;
     if (h->opts.vcycle_double < 0 || h->opts.vcycle_double > 1)
         return fail(PSC_ERR_ARG, "vcycle_double must be 0 or 1");
+    if (h->opts.capped_min_rows < 0) return fail(PSC_ERR_ARG, "capped_min_rows must be >= 0");
     {
         PhaseTimer pt("hierarchy (host and device coarsening)");
         st = build_hierarchy(n, rp, ci, v, so, h->host, err);
@@ -4402,6 +4631,8 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
         s->nnz[l] = D.nnz;
         s->ell_slots[l] = D.A.slots;
         s->dia_slots[l] = D.Ad.slots;
+        s->capped_cap[l] = D.Ac.off ? D.Ac.cap : 0;
+        s->capped_slots[l] = D.Ac.off ? D.Ac.slots + D.Ac.xents : 0;
         if (l + 1 < L) {
             s->p_nnz[l] = (int64_t)h->host.lev[l].pci.size();
             s->omega[l] = h->host.lev[l].omega;
@@ -4628,6 +4859,11 @@ int psc_tune(psc_hier* h, int32_t key, int32_t value) {
     }
     if (key == PSC_TUNE_DIA_ALIGN) {
         h->dia_align = value != 0;
+        drop_graphs(h);
+        return PSC_OK;
+    }
+    if (key == PSC_TUNE_CAPPED) {
+        h->capped = value != 0;
         drop_graphs(h);
         return PSC_OK;
     }

@@ -71,6 +71,15 @@ static long long pack_levels(const HostHier& H) {
         std::vector<double> dv;
         pack_dia(L.n, L.n, L.rp.data(), L.ci.data(), L.v.data(), off.back() * 4 / 3, start, offs, dv, &uni);
         sum += off.back() + (long long)dv.size();
+        const int cap = choose_ell_cap(L.n, L.rp.data());
+        if (cap > 0) {
+            std::vector<long long> coff, xs, xsrc;
+            std::vector<double> cval;
+            std::vector<int> ccol, xc;
+            std::vector<unsigned char> xl;
+            pack_ell_capped(L.n, L.rp.data(), L.ci.data(), L.v.data(), cap, coff, cval, ccol, xs, xc, xl, xsrc);
+            sum += coff.back() + (long long)xsrc.size();
+        }
         if (l + 1 == H.lev.size()) break;
         std::vector<int32_t> sprp, spci;
         std::vector<double> spv;
@@ -89,7 +98,74 @@ static long long pack_levels(const HostHier& H) {
     return sum;
 }
 
+// The capped hacked-ELL packing of rows whose lengths vary widely (a long row
+// every 37 rows): every row's entries must come back, in CSR order, from its
+// slots followed by its overflow record.
+static int check_capped() {
+    const int64_t n = 1000;
+    std::vector<int32_t> rp(1, 0), ci;
+    std::vector<double> v;
+    for (int64_t i = 0; i < n; i++) {
+        const int len = i % 37 == 5 ? 150 + (int)(i % 7) : 1 + (int)(i % 5);
+        for (int k = 0; k < len; k++) {
+            ci.push_back((int32_t)((i + 3 * k) % n));
+            v.push_back(1.0 + (double)(i * 1000 + k));
+        }
+        rp.push_back((int32_t)ci.size());
+    }
+    const int cap = choose_ell_cap(n, rp.data());
+    if (cap <= 0) {
+        std::fprintf(stderr, "capped: no cap chosen for irregular rows\n");
+        return 1;
+    }
+    std::vector<long long> off, xs, xsrc;
+    std::vector<double> val;
+    std::vector<int> col, xc;
+    std::vector<unsigned char> xl;
+    pack_ell_capped(n, rp.data(), ci.data(), v.data(), cap, off, val, col, xs, xc, xl, xsrc);
+    for (int64_t i = 0; i < n; i++) {
+        const int64_t s = i / 64;
+        const int lane = (int)(i % 64);
+        const int w = (int)((off[s + 1] - off[s]) / 64);
+        std::vector<int> gc;
+        std::vector<double> gv;
+        for (int k = 0; k < w; k++) {
+            const long long slot = off[s] + (long long)k * 64 + lane;
+            if (k < rp[i + 1] - rp[i]) {
+                gc.push_back(col[slot]);
+                gv.push_back(val[slot]);
+            } else if (val[slot] != 0.0) {
+                std::fprintf(stderr, "capped: row %lld padding slot holds %g\n", (long long)i, val[slot]);
+                return 1;
+            }
+        }
+        int prev = -1;
+        for (long long e = xs[s]; e < xs[s + 1]; e++) {
+            if ((int)xl[e] < prev) {
+                std::fprintf(stderr, "capped: slice %lld overflow not in lane order\n", (long long)s);
+                return 1;
+            }
+            prev = xl[e];
+            if (xl[e] != lane) continue;
+            gc.push_back(xc[e]);
+            gv.push_back(v[xsrc[e]]);
+        }
+        if ((int32_t)gc.size() != rp[i + 1] - rp[i]) {
+            std::fprintf(stderr, "capped: row %lld has %zu entries, CSR %d\n", (long long)i, gc.size(), rp[i + 1] - rp[i]);
+            return 1;
+        }
+        for (size_t k = 0; k < gc.size(); k++)
+            if (gc[k] != ci[rp[i] + k] || gv[k] != v[rp[i] + k]) {
+                std::fprintf(stderr, "capped: row %lld entry %zu differs\n", (long long)i, k);
+                return 1;
+            }
+    }
+    std::printf("capped layout: cap %d, %zu overflow entries, rows reproduced\n", cap, xc.size());
+    return 0;
+}
+
 int main(int argc, char** argv) {
+    if (check_capped()) return 1;
     const int n = argc > 1 ? std::atoi(argv[1]) : 32;
     const int reps = argc > 2 ? std::atoi(argv[2]) : 1;
     const std::string only = argc > 3 ? std::string(",") + argv[3] + "," : std::string();

@@ -1,5 +1,6 @@
 // kernels.h -- device-side building blocks shared by the HIP sources of libpsc.
 #pragma once
+#include <type_traits>
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -55,6 +56,7 @@ struct HostCtl {
 // load. off[s] = off[2S] + (s & 1)*64 is slice s's first entry, the slot
 // stride is 128, w_S = (off[2S+2] - off[2S]) / 128, and off holds nslices + 2
 // entries (the last two equal: the total).
+//
 template <typename T>
 struct Ell {
     using value_type = T;
@@ -66,6 +68,28 @@ struct Ell {
     long long ncols;
     int pair = 0;
 };
+
+// Capped hacked ELL (never paired): the slices hold at most a cap of slots
+// per row; a longer row's remaining entries go to the overflow of its slice,
+// entries xs[s] .. xs[s+1]-1 (values xv, columns xc, and xl = the lane of
+// their row), grouped by row in lane order, each row's in CSR order. A
+// wavefront takes them 64 at a time, one per lane, and sums each row's run
+// with a segmented scan across the lanes (fixed order). A type of its own, so
+// that only the kernels instantiated for it carry the overflow code.
+template <typename T>
+struct EllC : Ell<T> {
+    const long long* xs = nullptr;
+    const T* xv = nullptr;
+    const int* xc = nullptr;
+    const unsigned char* xl = nullptr;
+};
+
+template <typename M>
+struct is_ell : std::false_type {};
+template <typename T>
+struct is_ell<Ell<T>> : std::true_type {};
+template <typename T>
+struct is_ell<EllC<T>> : std::true_type {};
 
 // Hacked-DIA operator (the hacked diagonal format of the PSBLAS extensions):
 // slice s of 64 rows holds the diagonals start[s] .. start[s+1]-1, with

@@ -632,6 +632,86 @@ void pack_ell(int64_t nrows, const int32_t* rp, const int32_t* ci, const double*
     }
 }
 
+void pack_ell_capped(int64_t nrows, const int32_t* rp, const int32_t* ci, const double* v, int cap,
+                     std::vector<long long>& off, std::vector<double>& val, std::vector<int>& col,
+                     std::vector<long long>& xs, std::vector<int>& xc, std::vector<unsigned char>& xl,
+                     std::vector<long long>& xsrc) {
+    const int S = 64;
+    const int64_t ns = (nrows + S - 1) / S;
+    off.assign(ns + 1, 0);
+    xs.assign(ns + 1, 0);
+    xc.clear();
+    xl.clear();
+    xsrc.clear();
+    for (int64_t s = 0; s < ns; s++) {
+        int w = 0;
+        for (int64_t r = s * S; r < std::min<int64_t>(nrows, (s + 1) * S); r++) {
+            const int len = rp[r + 1] - rp[r];
+            w = std::max(w, std::min(len, cap));
+            for (int32_t q = rp[r] + cap; q < rp[r + 1]; q++) {
+                xc.push_back(ci[q]);
+                xl.push_back((unsigned char)(r - s * S));
+                xsrc.push_back(q);
+            }
+        }
+        off[s + 1] = off[s] + (long long)w * S;
+        xs[s + 1] = (long long)xc.size();
+    }
+    if (v) val.assign(off[ns], 0.0);
+    else val.clear();
+    col.resize(off[ns]);
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < ns; s++) {
+        const int w = (int)((off[s + 1] - off[s]) / S);
+        for (int lane = 0; lane < S; lane++) {
+            const int64_t r = s * S + lane;
+            const int len = r < nrows ? std::min(rp[r + 1] - rp[r], cap) : 0;
+            const int last = (r < nrows && len > 0) ? ci[rp[r] + len - 1] : 0;
+            for (int k = 0; k < w; k++) {
+                const long long slot = off[s] + (long long)k * S + lane;
+                if (k < len) {
+                    if (v) val[slot] = v[rp[r] + k];
+                    col[slot] = ci[rp[r] + k];
+                } else {
+                    col[slot] = last;
+                }
+            }
+        }
+    }
+}
+
+int choose_ell_cap(int64_t nrows, const int32_t* rp) {
+    const int S = 64;
+    const int64_t ns = (nrows + S - 1) / S;
+    int wmax = 0;
+    for (int64_t r = 0; r < nrows; r++) wmax = std::max(wmax, rp[r + 1] - rp[r]);
+    if (wmax <= 8 || ns == 0) return 0;
+    std::vector<int> len((size_t)ns * S, 0), sw(ns, 0);
+    for (int64_t r = 0; r < nrows; r++) len[r] = rp[r + 1] - rp[r];
+    long long plain = 0;
+    for (int64_t s = 0; s < ns; s++) {
+        for (int l = 0; l < S; l++) sw[s] = std::max(sw[s], len[s * S + l]);
+        plain += sw[s];
+    }
+    long long best = plain;
+    int best_cap = 0;
+    for (int cap = 1; cap < wmax && cap <= 48; cap++) {
+        long long c = 0;
+        for (int64_t s = 0; s < ns && c < best; s++) {
+            c += std::min(sw[s], cap);
+            if (sw[s] <= cap) continue;
+            long long e = 0;
+            for (int l = 0; l < S; l++) e += std::max(0, len[s * S + l] - cap);
+            c += 3 * ((e + S - 1) / S);
+        }
+        if (c < best) {
+            best = c;
+            best_cap = cap;
+        }
+    }
+    return (best_cap > 0 && best * 4 <= plain * 3) ? best_cap : 0;
+}
+
 void pack_ell_paired(int64_t nrows, const int32_t* rp, const int32_t* ci, const double* v,
                      std::vector<long long>& off, std::vector<double>& val, std::vector<int>& col) {
     const int64_t ns = (nrows + 63) / 64, nb = (ns + 1) / 2;

@@ -164,4 +164,23 @@ void pack_ell(int64_t nrows, const int32_t* rp, const int32_t* ci, const double*
 void pack_ell_paired(int64_t nrows, const int32_t* rp, const int32_t* ci, const double* v,
                      std::vector<long long>& off, std::vector<double>& val, std::vector<int>& col);
 
+// Capped hacked ELL for operators whose row lengths vary widely (a few long
+// rows in most slices, as on the stalled coarse levels of strongly varying
+// coefficients): every slice stores at most `cap` slots per row, and the
+// entries of a longer row past its first `cap` go to the overflow of its
+// slice: entries xs[s] .. xs[s+1]-1, grouped by row in lane order (CSR order
+// within a row), with columns xc, the row's lane xl and the CSR position xsrc
+// (for filling values). v == NULL packs the layout only.
+void pack_ell_capped(int64_t nrows, const int32_t* rp, const int32_t* ci, const double* v, int cap,
+                     std::vector<long long>& off, std::vector<double>& val, std::vector<int>& col,
+                     std::vector<long long>& xs, std::vector<int>& xc, std::vector<unsigned char>& xl,
+                     std::vector<long long>& xsrc);
+
+// Cap for pack_ell_capped, or 0 when the plain layout is as good. A slice's
+// cost is counted in wavefront loads: min(w_s, cap) for its capped slots plus
+// three per 64 overflow entries (a load, a gather and the cross-lane scan);
+// the cheapest cap up to 48 (the widest one-row-per-lane slices) is taken
+// when it costs at most 0.75 of the plain layout's sum of slice widths.
+int choose_ell_cap(int64_t nrows, const int32_t* rp);
+
 }  // namespace psc

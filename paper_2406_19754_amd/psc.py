@@ -21,6 +21,7 @@ ERR_ARG, ERR_NOT_SPD, ERR_NAN, ERR_HIP, ERR_OOM, ERR_COARSEN, ERR_STATE, ERR_IO 
 FP64, FP32 = 0, 1
 TUNE_GRID_MAX, TUNE_FUSED_PCG, TUNE_UNROLL4, TUNE_BUFLOAD, TUNE_SPMV2, TUNE_SPLIT, TUNE_DIA, TUNE_TAIL = 1, 2, 3, 4, 5, 6, 7, 8
 TUNE_DIA_UNIFORM, TUNE_XCD, TUNE_MIXED_SPLIT, TUNE_FP64_SPLIT, TUNE_DIA_ALIGN = 9, 10, 11, 12, 13
+TUNE_CAPPED = 14
 AGGR_MATCHING, AGGR_VBM = 0, 1
 SMOOTH_L1JACOBI, SMOOTH_AINV, SMOOTH_INVK, SMOOTH_CHEB4 = 0, 1, 2, 3
 MAX_LEVELS = 32
@@ -48,7 +49,7 @@ class AmgOpts(C.Structure):
                 ("vcycle_double", C.c_int32), ("aggregation", C.c_int32), ("setup_device", C.c_int32),
                 ("smoother", C.c_int32), ("invk_fill", C.c_int32), ("invk_inv_fill", C.c_int32),
                 ("setup_device_products", C.c_int32), ("vbm_theta", C.c_double), ("ainv_tau", C.c_double),
-                ("coarse_pcg_iters", C.c_int32), ("reserved2", C.c_int32), ("coarse_rtol", C.c_double)]
+                ("coarse_pcg_iters", C.c_int32), ("capped_min_rows", C.c_int32), ("coarse_rtol", C.c_double)]
 
 
 class HierStats(C.Structure):
@@ -63,7 +64,8 @@ class HierStats(C.Structure):
                 ("omega", C.c_double * MAX_LEVELS), ("smoother_sweeps", C.c_int32), ("smoothed_prol", C.c_int32),
                 ("vcycle_double", C.c_int32), ("aggregation", C.c_int32), ("smoother", C.c_int32),
                 ("smoother_nnz", C.c_int64 * MAX_LEVELS), ("rebuild_seconds", C.c_double),
-                ("coarse_pcg_iters", C.c_int32), ("tail_level", C.c_int32), ("tail_lds_bytes", C.c_int32)]
+                ("coarse_pcg_iters", C.c_int32), ("tail_level", C.c_int32), ("tail_lds_bytes", C.c_int32),
+                ("capped_cap", C.c_int32 * MAX_LEVELS), ("capped_slots", C.c_int64 * MAX_LEVELS)]
 
 
 def _load():
@@ -162,7 +164,7 @@ class Hierarchy:
                  build_fp32=False, use_graph=True, host_only=False, stream=None, coarse_sweeps=30,
                  smoothed_prol=False, smoother_sweeps=1, vcycle_double=False, aggregation=0, vbm_theta=0.01,
                  setup_device=True, smoother=SMOOTH_L1JACOBI, ainv_tau=0.1, invk_fill=0, invk_inv_fill=1,
-                 coarse_pcg_iters=0, coarse_rtol=1e-4, setup_device_products=False):
+                 coarse_pcg_iters=0, coarse_rtol=1e-4, setup_device_products=False, capped_min_rows=None):
         import torch
         o = AmgOpts()
         _lib.psc_amg_opts_default(C.byref(o))
@@ -174,6 +176,8 @@ class Hierarchy:
         o.setup_device, o.setup_device_products = int(setup_device), int(setup_device_products)
         o.smoother, o.ainv_tau, o.invk_fill, o.invk_inv_fill = smoother, ainv_tau, invk_fill, invk_inv_fill
         o.coarse_pcg_iters, o.coarse_rtol = coarse_pcg_iters, coarse_rtol
+        if capped_min_rows is not None:
+            o.capped_min_rows = capped_min_rows
         o.build_fp32, o.use_graph, o.host_only = int(build_fp32), int(use_graph), int(host_only)
         rp, prp = _hptr(rowptr, np.int32)
         ci, pci = _hptr(col, np.int32)
@@ -204,7 +208,8 @@ class Hierarchy:
                     smoothed_prol=s.smoothed_prol, vcycle_double=s.vcycle_double, aggregation=s.aggregation,
                     smoother=s.smoother, smoother_nnz=list(s.smoother_nnz[:L]),
                     rebuild_seconds=s.rebuild_seconds, coarse_pcg_iters=s.coarse_pcg_iters,
-                    tail_level=s.tail_level, tail_lds_bytes=s.tail_lds_bytes)
+                    tail_level=s.tail_level, tail_lds_bytes=s.tail_lds_bytes,
+                    capped_cap=list(s.capped_cap[:L]), capped_slots=list(s.capped_slots[:L]))
 
     def rebuild(self, val):
         """Numeric-only rebuild with new values of A (same pattern as at build)."""

@@ -81,6 +81,63 @@ def test_spmv_matches_oracle(psc, case):
         assert np.abs(yl.cpu().numpy() - refl).max() <= 1e-13 * np.abs(refl).max()
 
 
+@pytest.mark.parametrize("case", ["diffusion48_lognormal", "random_long_rows"])
+def test_capped_layout_matches_plain_and_oracle(psc, case):
+    """Levels whose row lengths vary widely (a few long rows in most slices)
+    are read from a capped hacked-ELL copy, the long rows' remaining entries in
+    overflow records that one wavefront sums: SpMV on those levels, the V-cycle
+    and PCG agree with the plain layout up to rounding and with the oracle."""
+    rp, c, v = CASES[case]()
+    cm = 40 if case == "random_long_rows" else 200
+    # small operators: every level where a cap pays gets the copy
+    h = psc.Hierarchy(rp, c, v, build_fp32=True, coarse_max=cm, capped_min_rows=1)
+    o = oracle.Hierarchy(rp, c, v, coarse_max=cm)
+    inf = h.info()
+    capped = [l for l in range(inf["levels"]) if inf["capped_cap"][l] > 0]
+    assert capped, "the case has no level with a capped copy"
+    assert psc.Hierarchy(rp, c, v, coarse_max=cm).info()["capped_cap"] == [0] * inf["levels"]
+    for l in capped:
+        # the copy stores fewer slots than the plain slices (overflow included)
+        assert inf["capped_slots"][l] < inf["ell_slots"][l]
+        L = o.level(l)
+        xl = np.random.default_rng(10 + l).standard_normal(L["n"])
+        yl = torch.empty(L["n"], dtype=torch.float64, device="cuda")
+        h.spmv(dev(xl), yl, level=l)
+        refl = oracle.spmv(L["rowptr"], L["col"], L["val"], xl)
+        scale = oracle.spmv(L["rowptr"], L["col"], np.abs(L["val"]), np.abs(xl))
+        assert np.all(np.abs(yl.cpu().numpy() - refl) <= 1e-14 * scale + 1e-300)
+        y32 = torch.empty(L["n"], dtype=torch.float32, device="cuda")
+        h.spmv(dev(xl.astype(np.float32)), y32, level=l, prec=psc.FP32)
+        assert np.all(np.abs(y32.cpu().numpy() - refl) <= 1e-5 * scale + 1e-30)
+    n = len(rp) - 1
+    r = np.random.default_rng(3).standard_normal(n)
+    zc = torch.empty(n, dtype=torch.float64, device="cuda")
+    zp = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.vcycle(dev(r), zc)
+    h.tune(psc.TUNE_CAPPED, 0)
+    h.vcycle(dev(r), zp)
+    h.tune(psc.TUNE_CAPPED, 1)
+    zc, zp = zc.cpu().numpy(), zp.cpu().numpy()
+    assert np.linalg.norm(zc - zp) <= 1e-13 * np.linalg.norm(zp)
+    ref = o.vcycle(r)
+    assert np.linalg.norm(zc - ref) <= 1e-12 * np.linalg.norm(ref)
+    z32 = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.vcycle(dev(r), z32, prec=psc.FP32)
+    ref32 = o.vcycle32(r)
+    assert np.linalg.norm(z32.cpu().numpy() - ref32) <= 1e-5 * np.linalg.norm(ref32)
+    b = np.random.default_rng(4).standard_normal(n)
+    xs = []
+    for on in (1, 0):
+        h.tune(psc.TUNE_CAPPED, on)
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        g = h.pcg(dev(b), x, rtol=1e-6, maxit=500)
+        xs.append((g["iters"], x.cpu().numpy()))
+    h.tune(psc.TUNE_CAPPED, 1)
+    r_o = o.pcg(b, rtol=1e-6, maxit=500)
+    assert xs[0][0] == xs[1][0] and abs(xs[0][0] - r_o["iters"]) <= 1
+    assert np.linalg.norm(xs[0][1] - xs[1][1]) <= 1e-10 * np.linalg.norm(xs[1][1])
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_vcycle_matches_oracle(psc, case):
     rp, c, v = CASES[case]()
