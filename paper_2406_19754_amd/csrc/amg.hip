@@ -422,31 +422,34 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Overflow of slice s in a capped layout (see Ell), as the row sum of each
+// Overflow of slice s in a capped layout (see EllC), as the row sum of each
 // lane's row (0 for rows without overflow). The wavefront takes the entries
-// 64 at a time, lane j one entry, four such rounds with all their loads and
-// gathers in flight together; within a round a row's entries are adjacent
+// 64 at a time (a round), lane j one entry, four rounds with all their loads
+// and gathers in flight together; within a round a row's entries are adjacent
 // lanes, summed by a segmented inclusive scan (distances 1, 2, 4, ..., 32,
 // each adding the partial sum d lanes down when it belongs to the same row),
 // and the last lane of each run adds its sum to the row's slot in LDS (one
 // writer per row and round, rounds in order). The wavefront's LDS accesses
 // run in program order, and the compiler keeps the order of these (their
-// addresses may alias). Every lane of the wavefront must call this with the
-// same s; workgroups of up to 1024 threads.
+// addresses may alias). With nq > 1 (the split form) wavefront q of nq takes
+// the rounds q, q + nq, q + 2 nq, ... and returns its part of each row's sum.
+// Every lane of the wavefront must call this with the same s; workgroups of
+// up to 1024 threads.
 template <typename T, typename G>
-__device__ __forceinline__ T ell_ovf(const EllC<T>& A, long long s, int lane, G g) {
+__device__ __forceinline__ T ell_ovf(const EllC<T>& A, long long s, int lane, G g, int q = 0, int nq = 1) {
     constexpr int RB = 4;
     __shared__ T ov_acc[16][SLICE];
     T* acc = ov_acc[threadIdx.x >> 6];
     acc[lane] = T(0);
     const long long e0 = A.xs[s], e1 = A.xs[s + 1];
+    const long long step = (long long)nq * SLICE;
     wave_lds_sync();
-    for (long long base = e0; base < e1; base += RB * SLICE) {
+    for (long long base = e0 + (long long)q * SLICE; base < e1; base += RB * step) {
         T v[RB], p[RB];
         int c[RB], key[RB];
 #pragma unroll
         for (int t = 0; t < RB; t++) {
-            const long long e = base + t * SLICE + lane;
+            const long long e = base + t * step + lane;
             key[t] = SLICE + lane;   // lanes past the end: a key of their own
             v[t] = T(0);
             c[t] = 0;
@@ -457,7 +460,7 @@ __device__ __forceinline__ T ell_ovf(const EllC<T>& A, long long s, int lane, G 
             }
         }
 #pragma unroll
-        for (int t = 0; t < RB; t++) p[t] = base + t * SLICE + lane < e1 ? v[t] * g(c[t]) : T(0);
+        for (int t = 0; t < RB; t++) p[t] = base + t * step + lane < e1 ? v[t] * g(c[t]) : T(0);
 #pragma unroll
         for (int t = 0; t < RB; t++) {
 #pragma unroll
@@ -494,6 +497,7 @@ __device__ __forceinline__ T ell_row(const EllC<T>& A, long long s, int lane, G 
 // every load of a batch issued before its gathers); the partial sums meet in
 // LDS and wavefront 0 adds them in a fixed order and finishes the rows.
 constexpr int GB_SPLIT = 0;
+constexpr int OVF_SPLIT_ROUNDS = 8;   // capped layouts: overflow rounds per slice above which it takes the split form
 constexpr int SPLIT_W = 48;
 static_assert(WG == 256, "the split form adds four wavefronts' partial sums");   // hacked-ELL slots per row above which a level takes the split form
 
@@ -546,9 +550,7 @@ __device__ __forceinline__ void ell_split_slices(const MT& A, G g, E epi) {
     const int lane = threadIdx.x & 63, q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (long long s = lo; s < hi; s++) {
         T a = ell_row_part(static_cast<const Ell<T>&>(A), s, lane, q, g);
-        if constexpr (std::is_same<MT, EllC<T>>::value) {
-            if (q == 0) a += ell_ovf(A, s, lane, g);
-        }
+        if constexpr (std::is_same<MT, EllC<T>>::value) a += ell_ovf(A, s, lane, g, q, WG / 64);
         part[q][lane] = a;
         __syncthreads();
         if (q == 0) {
@@ -2359,6 +2361,7 @@ struct DevEll {
     float* xv32 = nullptr;
     int cap = 0;                           // slots per row kept in the slices (0: plain layout)
     long long xents = 0;                   // overflow entries
+    bool ovf_split = false;                // a slice's overflow is long: the split form shares it
     Ell<T> view() const {
         Ell<T> e{off, val, col, nrows, nslices, ncols};
         e.pair = pair;
@@ -2826,6 +2829,11 @@ static int upload_capped(psc_hier* h, DevLevel& D, const HostLevel& H, const dou
     E.nslices = (long long)off.size() - 1;
     E.slots = off.back();
     E.xents = (long long)xsrc.size();
+    // slices with more than OVF_SPLIT_ROUNDS rounds of 64 overflow entries
+    // bound the launch by their wavefront: the split form gives them four
+    long long most = 0;
+    for (size_t q = 0; q + 1 < xs.size(); q++) most = std::max(most, xs[q + 1] - xs[q]);
+    E.ovf_split = most > (long long)OVF_SPLIT_ROUNDS * SLICE;
     E.wmax = 0;
     for (size_t q = 0; q + 1 < off.size(); q++) E.wmax = std::max(E.wmax, (int)((off[q + 1] - off[q]) / SLICE));
     std::vector<double> xv(xsrc.size());
@@ -3010,7 +3018,9 @@ static bool wide_A(const psc_hier* h, const DevLevel& V) {
 // Level V's operator read from hacked ELL with rows wider than SPLIT_W slots:
 // its kernels take the split form (GB_SPLIT) on one slice per workgroup.
 static bool split_A(const psc_hier* h, const DevLevel& V) {
-    return !(h->dia && V.Ad.on()) && (capped_on(h, V) ? V.Ac.wmax : V.A.wmax) > SPLIT_W;
+    if (h->dia && V.Ad.on()) return false;
+    if (capped_on(h, V)) return V.Ac.wmax > SPLIT_W || V.Ac.ovf_split;
+    return V.A.wmax > SPLIT_W;
 }
 static inline int grid_vec(const psc_hier* h, long long n) { return grid_of(h, 1024, n); }
 
