@@ -54,12 +54,17 @@ def kernel_bytes(info, form="fp64", fused=False, split=True, dia=True, split_upd
     Zp = info["sp_nnz"][0] if info["levels"] > 1 else 0
     Nc = info["rows"][1] if info["levels"] > 1 else 0
     v = 8 if form == "fp64" else 4
+    # pair restriction: the pre-smoothing pass also writes N/2 pair sums; the
+    # restriction reads them with N/2 entries (value + index) instead of r with N
+    pr = bool(info.get("pair_restrict", [0])[0]) and split
+    hb = v * N // 2 if pr else 0
+    rb = (N // 2) * (v + 4) + v * (N // 2) + v * Nc if pr else N * (v + 4) + v * N + v * Nc
     dia = dia and info["dia_slots"][0] > 0
     a64 = 8 if dia else 12          # the outer operator is always FP64
     av = v if dia else v + 4        # A M^-1 in the V-cycle's precision
     if split:
         # pre: A M^-1, r gathered (fused: r_old and q gathered, r_new written), r_0 written
-        pre = Z * av + 8 * N + v * N if not fused else Z * av + 2 * 8 * N + 8 * N + v * N
+        pre = (Z * av + 8 * N + v * N if not fused else Z * av + 2 * 8 * N + 8 * N + v * N) + hb
         # post: S P; b (FP64), minv, r_0 read; x_c gathered; z (FP64) written
         post = Zp * (v + 4) + 8 * N + 2 * v * N + v * Nc + 8 * N
     else:
@@ -68,11 +73,11 @@ def kernel_bytes(info, form="fp64", fused=False, split=True, dia=True, split_upd
     if fused and split and split_update:
         # pass 2 as two kernels: r = r - alpha q (r_old, q read, r_new written),
         # then r_0 = r_new - (A M^-1) r_new (A M^-1, r_new gathered, r_0 written)
-        pre2 = 3 * 8 * N + Z * av + 8 * N + v * N
+        pre2 = 3 * 8 * N + Z * av + 8 * N + v * N + hb
         return {
             "k_spmv_pfuse": Z * a64 + 2 * 8 * N + 2 * 8 * N + 2 * 8 * N,
             "k_rupdate + k_pre_s": pre2,
-            "k_spmv_R": N * (v + 4) + v * N + v * Nc,
+            "k_spmv_R": rb,
             "k_post_s": post,
         }
     if fused:
@@ -80,14 +85,14 @@ def kernel_bytes(info, form="fp64", fused=False, split=True, dia=True, split_upd
             # A; z and p_old gathered; p_new, q written; x read and written
             "k_spmv_pfuse": Z * a64 + 2 * 8 * N + 2 * 8 * N + 2 * 8 * N,
             "k_update_pre_s": pre,
-            "k_spmv_R": N * (v + 4) + v * N + v * Nc,
+            "k_spmv_R": rb,
             "k_post_s": post,
         }
     return {
         "spmv_dot": Z * a64 + 2 * 8 * N,                       # A, p gathered, q written
         "cg_update": 6 * 8 * N,                                # x, r, p, q read; x, r written
         "pre_smooth_l0": pre,
-        "restrict_l0": N * (v + 4) + v * N + v * Nc,           # R, r_0 gathered, b_1 written
+        "restrict_l0": rb,                                     # R (or R2), r_0 (or pair sums) gathered, b_1 written
         "post_smooth_l0": post,
         "dir_update": 3 * 8 * N,                               # z, p read; p written
     }

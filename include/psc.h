@@ -312,6 +312,7 @@ typedef struct {
     int32_t capped_cap[PSC_MAX_LEVELS];      /* slots per row of A_l's capped hacked-ELL copy
                                                 (PSC_TUNE_CAPPED; 0: no such copy) */
     int64_t capped_slots[PSC_MAX_LEVELS];    /* its slice slots, plus its overflow entries */
+    int32_t pair_restrict[PSC_MAX_LEVELS];   /* 1: level l restricts pair sums (PSC_TUNE_PAIR_R) */
 } psc_hier_stats;
 
 int psc_hier_info(const psc_hier* h, psc_hier_stats* s);
@@ -458,6 +459,15 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
  * hacked ELL. Same values up to rounding (overflow entries are summed in scan
  * order). */
 #define PSC_TUNE_CAPPED 14
+/* PSC_TUNE_PAIR_R (default 1): on a level whose rows 2k and 2k+1 always share
+ * an aggregate and a prolongator value (Poisson's 2x2x1 aggregates of the
+ * first levels) and whose one pre-smoothing sweep reads the paired uniform
+ * hacked-DIA layout, that sweep also writes the pair sums r_2k + r_2k+1 and
+ * the restriction reads them with one entry per pair (Section "Multigrid
+ * preconditioners": b_c = P^T r, summed over pairs first): half the vector
+ * and half the index and value bytes of R. 0 restricts r itself. Same values
+ * up to rounding. */
+#define PSC_TUNE_PAIR_R 15
 int psc_tune(psc_hier* h, int32_t key, int32_t value);
 
 void psc_hier_free(psc_hier* h);

@@ -1468,9 +1468,13 @@ __global__ __launch_bounds__(WG) void k_post(Ell<T> A, const T* __restrict__ min
 // These give the sweeps of k_pre / k_post up to rounding.
 
 // r_i = b_i - sum_j am_ij b_j
+//
+// hp != nullptr (paired uniform DIA levels whose row pairs 2k, 2k+1 share an
+// aggregate and a prolongator value, see DevLevel::R2): also the pair sums
+// hp[k] = r_2k + r_2k+1, which the restriction then reads instead of r.
 template <typename M, typename TB, int GB = 4>
 __global__ __launch_bounds__(WG) void k_pre_s(M AM, const TB* __restrict__ b, typename M::value_type* __restrict__ r,
-                                              Gate g) {
+                                              Gate g, typename M::value_type* __restrict__ hp) {
     using T = typename M::value_type;
     if (gate_skip(g)) return;
     if constexpr (GB == GB_SPLIT) {
@@ -1493,7 +1497,9 @@ __global__ __launch_bounds__(WG) void k_pre_s(M AM, const TB* __restrict__ b, ty
                 const long long row = S * (2 * SLICE) + 2 * lane;
                 if (row + 1 < AM.nrows) {
                     const v2u<TB> bb = ld2(b + row);
-                    st2(r + row, (T)bb.x - a0, (T)bb.y - a1);
+                    const T r0 = (T)bb.x - a0, r1 = (T)bb.y - a1;
+                    st2(r + row, r0, r1);
+                    if (hp) hp[row >> 1] = r0 + r1;
                 } else if (row < AM.nrows) {
                     r[row] = (T)b[row] - a0;
                 }
@@ -1511,10 +1517,12 @@ __global__ __launch_bounds__(WG) void k_pre_s(M AM, const TB* __restrict__ b, ty
 
 // Fused update + level-0 pre-smoothing with AM in precision T:
 // r_new = r_old - alpha q (FP64), r0 = (T)r_new - AM_T (T)r_new, partial ||r_new||^2.
+// hp: the pair sums of r0 as in k_pre_s.
 template <typename M>
 __global__ __launch_bounds__(WG) void k_update_pre_s(M AM, const double* __restrict__ rold,
                                                      const double* __restrict__ q, double* __restrict__ rnew,
-                                                     typename M::value_type* __restrict__ r0, Red R) {
+                                                     typename M::value_type* __restrict__ r0, Red R,
+                                                     typename M::value_type* __restrict__ hp) {
     using T = typename M::value_type;
     if (skip_red(R)) return;
     const double nalpha = -R.ctl->alpha;
@@ -1537,7 +1545,9 @@ __global__ __launch_bounds__(WG) void k_update_pre_s(M AM, const double* __restr
                     const v2u<double> qq = ld2(q + row), rr = ld2(rold + row);
                     const double n0 = fma(nalpha, qq.x, rr.x), n1 = fma(nalpha, qq.y, rr.y);
                     st2(rnew + row, n0, n1);
-                    st2(r0 + row, (T)n0 - a0, (T)n1 - a1);
+                    const T z0 = (T)n0 - a0, z1 = (T)n1 - a1;
+                    st2(r0 + row, z0, z1);
+                    if (hp) hp[row >> 1] = z0 + z1;
                     s0 += n0 * n0;
                     s0 += n1 * n1;
                 } else if (row < AM.nrows) {
@@ -2421,6 +2431,14 @@ struct DevLevel {
     float* amd32 = nullptr;
     DevEll<double> A, R;                  // R = P^T (coarse rows, members as columns)
     DevEll<double> SP;                    // smoothed prolongator P - M^-1 A P
+    // Pair restriction: when rows 2k and 2k+1 always share an aggregate and a
+    // prolongator value (Poisson's 2x2x1 aggregates on the paired DIA
+    // layout), R r = R2 h with h_k = r_2k + r_2k+1 (written by the
+    // pre-smoothing pass) and R2 the coarse rows over pairs (value p_2k):
+    // half the vector and half the entries. R2.off == nullptr: not eligible.
+    DevEll<double> R2;
+    double* h2 = nullptr;
+    float* h2_32 = nullptr;
     double* am = nullptr;                 // A M^-1 values in A's hacked-ELL layout
     float* am32 = nullptr;
     Ell<double> am_view() const { Ell<double> e = A.view(); e.val = am; return e; }
@@ -2467,6 +2485,8 @@ struct LV<double> {
     static double* xt2(DevLevel& V) { return V.xt2; }
     static const double* minv(const DevLevel& V) { return V.minv; }
     static Ell<double> R(const DevLevel& V) { return V.R.view(); }
+    static Ell<double> R2(const DevLevel& V) { return V.R2.view(); }
+    static double* h2(DevLevel& V) { return V.h2; }
     static Ell<double> SP(const DevLevel& V) { return V.SP.view(); }
     static Ell<double> A(const DevLevel& V) { return V.A.view(); }
     static const double* pv(const DevLevel& V) { return V.pval; }
@@ -2489,6 +2509,8 @@ struct LV<float> {
     static float* xt2(DevLevel& V) { return V.xt232; }
     static const float* minv(const DevLevel& V) { return V.minv32; }
     static Ell<float> R(const DevLevel& V) { return V.R.view32(); }
+    static Ell<float> R2(const DevLevel& V) { return V.R2.view32(); }
+    static float* h2(DevLevel& V) { return V.h2_32; }
     static Ell<float> SP(const DevLevel& V) { return V.SP.view32(); }
     static Ell<float> A(const DevLevel& V) { return V.A.view32(); }
     static const float* pv(const DevLevel& V) { return V.pval32; }
@@ -2528,6 +2550,7 @@ struct psc_hier {
     bool split = true;                    // smoothing sweeps through A M^-1 and A P
     bool dia = true;                      // use the hacked-DIA copies where a level has them
     bool capped = true;                   // use the capped hacked-ELL copies where a level has them
+    bool pair_r = true;                   // pair restriction where a level is eligible
     bool dia_uniform = true;              // a level with <= 8 distinct offsets keeps them in the kernel argument
     bool dia_align = true;                // grids aligned to the largest DIA offset (grid_lvl)
     bool mixed_split = true;              // FP32 V-cycle: residual update and pre-smoothing as two passes
@@ -2868,6 +2891,42 @@ static int upload_capped(psc_hier* h, DevLevel& D, const HostLevel& H, const dou
     return PSC_OK;
 }
 
+// Pair restriction of level D (see DevLevel::R2): eligible when P is
+// tentative, the row count even, and rows 2k and 2k+1 share their aggregate
+// and their prolongator value for every k; R2 holds the coarse rows over the
+// pairs (ascending), value p_2k, and h2 (h2_32) the pair sums. A numeric
+// rebuild refills R2's values, or turns it off when the pairs no longer agree.
+static int upload_pair_r(psc_hier* h, DevLevel& D, const HostLevel& H, bool f32) {
+    const int64_t n = H.n;
+    bool ok = n > 0 && n % 2 == 0 && (int64_t)H.pci.size() == n && (int64_t)H.prp.size() == n + 1 &&
+              H.prp[n] == n && (int64_t)H.pv.size() == n;
+    for (int64_t k = 0; ok && k < n / 2; k++)
+        ok = H.pci[2 * k] == H.pci[2 * k + 1] && H.pv[2 * k] == H.pv[2 * k + 1];
+    if (!ok || (h->refresh && D.R2.off == nullptr)) {
+        D.R2.off = nullptr;   // (a rebuild keeps the buffers until the handle is freed)
+        return PSC_OK;
+    }
+    const int64_t np = n / 2;
+    std::vector<int32_t> rrp(H.nc + 1, 0), rci(np);
+    std::vector<double> rv(np);
+    for (int64_t k = 0; k < np; k++) rrp[H.pci[2 * k] + 1]++;
+    for (int64_t I = 0; I < H.nc; I++) rrp[I + 1] += rrp[I];
+    std::vector<int32_t> pos(rrp.begin(), rrp.end() - 1);
+    for (int64_t k = 0; k < np; k++) {
+        const int32_t o = pos[H.pci[2 * k]]++;
+        rci[o] = (int32_t)k;
+        rv[o] = H.pv[2 * k];
+    }
+    int st;
+    if (!h->refresh && (st = upload_ell_layout(h, D.R2, H.nc, np, rrp.data(), rci.data(), f32))) return st;
+    if ((st = refresh_values(h, D.R2, nullptr, H.nc, rrp.data(), rv.data(), nullptr, nullptr, nullptr, nullptr,
+                             nullptr)))
+        return st;
+    if ((st = dalloc(h, (void**)&D.h2, np * sizeof(double)))) return st;
+    if (f32 && (st = dalloc(h, (void**)&D.h2_32, np * sizeof(float)))) return st;
+    return PSC_OK;
+}
+
 static std::vector<float> to32(const std::vector<double>& a) {
     std::vector<float> r(a.size());
     for (size_t i = 0; i < a.size(); i++) r[i] = (float)a[i];
@@ -3022,6 +3081,17 @@ static bool split_A(const psc_hier* h, const DevLevel& V) {
     if (capped_on(h, V)) return V.Ac.wmax > SPLIT_W || V.Ac.ovf_split;
     return V.A.wmax > SPLIT_W;
 }
+// Level V restricts pair sums (see DevLevel::R2): eligible, enabled, and
+// its one pre-smoothing sweep runs the paired uniform DIA path that writes
+// them.
+static bool use_pr(const psc_hier* h, const DevLevel& V) {
+    return h->pair_r && V.R2.off != nullptr && h->split && h->dia && V.Ad.on() && V.Ad.pair && V.Ad.nd > 0 &&
+           V.nu == 1;
+}
+template <typename T>
+static T* pr_out(const psc_hier* h, DevLevel& V) {
+    return use_pr(h, V) ? LV<T>::h2(V) : nullptr;
+}
 static inline int grid_vec(const psc_hier* h, long long n) { return grid_of(h, 1024, n); }
 
 // ---------------------------------------------------------------------------
@@ -3080,15 +3150,16 @@ static void timing_collect(psc_hier* h, int iters = -1, int vc_lag = 0) {
 // Pre-smoothing from zero and its residual on level V, in the V-cycle's
 // precision T (r = b - A M^-1 b).
 template <typename T, typename TB>
-static void launch_pre(psc_hier* h, const DevLevel& V, const TB* b, T* r, Gate g, int grid = 0) {
+static void launch_pre(psc_hier* h, DevLevel& V, const TB* b, T* r, Gate g, int grid = 0) {
     const int gr = grid ? grid : grid_lvl(h, V);
     constexpr bool f32 = std::is_same<T, float>::value;
     if (h->split) {
         const bool wide = wide_A(h, V), spl = split_A(h, V);
+        T* hp = pr_out<T>(h, V);
         auto go = [&](auto AM) {
-            if (spl) k_pre_s<decltype(AM), TB, GB_SPLIT><<<gr, WG, 0, h->stream>>>(AM, b, r, g);
-            else if (wide) k_pre_s<decltype(AM), TB, 8><<<gr, WG, 0, h->stream>>>(AM, b, r, g);
-            else k_pre_s<decltype(AM), TB, 4><<<gr, WG, 0, h->stream>>>(AM, b, r, g);
+            if (spl) k_pre_s<decltype(AM), TB, GB_SPLIT><<<gr, WG, 0, h->stream>>>(AM, b, r, g, hp);
+            else if (wide) k_pre_s<decltype(AM), TB, 8><<<gr, WG, 0, h->stream>>>(AM, b, r, g, hp);
+            else k_pre_s<decltype(AM), TB, 4><<<gr, WG, 0, h->stream>>>(AM, b, r, g, hp);
         };
         if constexpr (f32) with_AM32(h, V, go);
         else with_AM(h, V, go);
@@ -3434,7 +3505,11 @@ static void vcycle_t(psc_hier* h, const double* r0, double* z0, const double* d,
         }
         {
             TimeScope t(h, l == 0 ? 3 : 7);
-            launch_spmv(h, LV<T>::R(V), (const T*)LV<T>::r(V), LV<T>::b(h->lev[l + 1]), g, V.R.wmax > 8, V.R.wmax > SPLIT_W);
+            if (use_pr(h, V))
+                launch_spmv(h, LV<T>::R2(V), (const T*)LV<T>::h2(V), LV<T>::b(h->lev[l + 1]), g, V.R2.wmax > 8);
+            else
+                launch_spmv(h, LV<T>::R(V), (const T*)LV<T>::r(V), LV<T>::b(h->lev[l + 1]), g, V.R.wmax > 8,
+                            V.R.wmax > SPLIT_W);
         }
     }
     if (tail) {
@@ -3780,12 +3855,13 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
                     // gathering r: the same values as the fused pass, half its gathers
                     k_rupdate<<<ge, WG, 0, st>>>(L0.A.nslices, n, rold, h->q, rnew, red_of(h, FIN_UPDATE_PCG));
                     with_AM(h, L0, [&](auto AM) {
-                        k_pre_s<decltype(AM), double, 4><<<ge, WG, 0, st>>>(AM, rnew, pre_rbuf<double>(h, L0, 1), gd);
+                        k_pre_s<decltype(AM), double, 4><<<ge, WG, 0, st>>>(AM, rnew, pre_rbuf<double>(h, L0, 1), gd,
+                                                                            pr_out<double>(h, L0));
                     });
                 } else if (h->split)
                     with_AM(h, L0, [&](auto AM) {
                         k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, pre_rbuf<double>(h, L0, 1),
-                                                                        red_of(h, FIN_UPDATE_PCG));
+                                                                        red_of(h, FIN_UPDATE_PCG), pr_out<double>(h, L0));
                     });
                 else if (h->bufload == 1)
                     k_update_pre<8, true><<<ge, WG, 0, st>>>(L0.A.view(), L0.minv, rold, h->q, rnew, L0.r, red_of(h, FIN_UPDATE_PCG));
@@ -3838,24 +3914,26 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
                         const bool wide = wide_A(h, L0);
                         with_AM32(h, L0, [&](auto AM) {
                             using M = decltype(AM);
-                            if (wide) k_pre_s<M, float, 8><<<ge, WG, 0, st>>>(AM, h->r32, pre_rbuf<float>(h, L0, 1), gd);
-                            else k_pre_s<M, float, 4><<<ge, WG, 0, st>>>(AM, h->r32, pre_rbuf<float>(h, L0, 1), gd);
+                            if (wide) k_pre_s<M, float, 8><<<ge, WG, 0, st>>>(AM, h->r32, pre_rbuf<float>(h, L0, 1), gd,
+                                                                              pr_out<float>(h, L0));
+                            else k_pre_s<M, float, 4><<<ge, WG, 0, st>>>(AM, h->r32, pre_rbuf<float>(h, L0, 1), gd,
+                                                                         pr_out<float>(h, L0));
                         });
                     } else if (f32)
                         with_AM32(h, L0, [&](auto AM) {
                             k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, pre_rbuf<float>(h, L0, 1),
-                                                                            red_of(h, FIN_UPDATE_FCG));
+                                                                            red_of(h, FIN_UPDATE_FCG), pr_out<float>(h, L0));
                         });
                     else if (h->fp64_split) {
                         k_rupdate<<<ge, WG, 0, st>>>(L0.A.nslices, n, rold, h->q, rnew, red_of(h, FIN_UPDATE_FCG));
                         with_AM(h, L0, [&](auto AM) {
                             k_pre_s<decltype(AM), double, 4><<<ge, WG, 0, st>>>(AM, rnew, pre_rbuf<double>(h, L0, 1),
-                                                                                gd);
+                                                                                gd, pr_out<double>(h, L0));
                         });
                     } else
                         with_AM(h, L0, [&](auto AM) {
                             k_update_pre_s<decltype(AM)><<<ge, WG, 0, st>>>(AM, rold, h->q, rnew, pre_rbuf<double>(h, L0, 1),
-                                                                            red_of(h, FIN_UPDATE_FCG));
+                                                                            red_of(h, FIN_UPDATE_FCG), pr_out<double>(h, L0));
                         });
                 } else if (f32) {
                     if (h->bufload == 1)
@@ -4376,6 +4454,7 @@ static int upload_levels(psc_hier* h) {
             if ((st = refresh_values(h, D.R, nullptr, H.nc, rrp.data(), rv.data(), nullptr, nullptr, nullptr, nullptr,
                                      nullptr)))
                 return st;
+            if ((st = upload_pair_r(h, D, H, f32))) return st;
             // general prolongator: S P from the host's sparse product
             if (!sp_on_device) {
                 std::vector<int32_t> sprp, spci;
@@ -4643,6 +4722,7 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
         s->dia_slots[l] = D.Ad.slots;
         s->capped_cap[l] = D.Ac.off ? D.Ac.cap : 0;
         s->capped_slots[l] = D.Ac.off ? D.Ac.slots + D.Ac.xents : 0;
+        s->pair_restrict[l] = use_pr(h, D) ? 1 : 0;
         if (l + 1 < L) {
             s->p_nnz[l] = (int64_t)h->host.lev[l].pci.size();
             s->omega[l] = h->host.lev[l].omega;
@@ -4689,11 +4769,15 @@ int psc_hier_info(const psc_hier* h, psc_hier_stats* s) {
                 // (nnz(P) entries), r, b_c; post sweep 1: S P, s (or b), minv, r
                 // read, x_c gathered, x written; sweeps 2..nu: A, x gathered, b and
                 // minv read, x written
-                const double Zr = (double)h->host.lev[l].pci.size(), nu = D.nu;
-                vb64 += Z * m64 + 16 * N + (nu - 1) * (Z * m64 + 40 * N) + Zr * 12 + 8 * N + 8 * Nc +
-                        Zp * 12 + 32 * N + 8 * Nc + (nu - 1) * (Z * m64 + 32 * N);
-                vb32 += Z * m32 + 8 * N + (nu - 1) * (Z * m32 + 20 * N) + Zr * 8 + 4 * N + 4 * Nc + Zp * 8 +
-                        16 * N + 4 * Nc + (nu - 1) * (Z * m32 + 16 * N) + e0 * 12 * N;
+                // (pair restriction: the pre sweep also writes N/2 pair sums, the
+                // restriction reads them with N/2 entries instead of r with nnz(P))
+                const double nu = D.nu;
+                const bool pr = use_pr(h, D);
+                const double Zr = pr ? 0.5 * N : (double)h->host.lev[l].pci.size(), Nr = pr ? 0.5 * N : N;
+                vb64 += Z * m64 + 16 * N + (pr ? 4 * N : 0) + (nu - 1) * (Z * m64 + 40 * N) + Zr * 12 + 8 * Nr +
+                        8 * Nc + Zp * 12 + 32 * N + 8 * Nc + (nu - 1) * (Z * m64 + 32 * N);
+                vb32 += Z * m32 + 8 * N + (pr ? 2 * N : 0) + (nu - 1) * (Z * m32 + 20 * N) + Zr * 8 + 4 * Nr +
+                        4 * Nc + Zp * 8 + 16 * N + 4 * Nc + (nu - 1) * (Z * m32 + 16 * N) + e0 * 12 * N;
             } else {
                 // pre: A, b and minv gathered, r written; restriction: R, r, b_c;
                 // post: A, b, minv, p, agg, x_c gathered, x written
@@ -4874,6 +4958,11 @@ int psc_tune(psc_hier* h, int32_t key, int32_t value) {
     }
     if (key == PSC_TUNE_CAPPED) {
         h->capped = value != 0;
+        drop_graphs(h);
+        return PSC_OK;
+    }
+    if (key == PSC_TUNE_PAIR_R) {
+        h->pair_r = value != 0;
         drop_graphs(h);
         return PSC_OK;
     }

@@ -21,7 +21,7 @@ ERR_ARG, ERR_NOT_SPD, ERR_NAN, ERR_HIP, ERR_OOM, ERR_COARSEN, ERR_STATE, ERR_IO 
 FP64, FP32 = 0, 1
 TUNE_GRID_MAX, TUNE_FUSED_PCG, TUNE_UNROLL4, TUNE_BUFLOAD, TUNE_SPMV2, TUNE_SPLIT, TUNE_DIA, TUNE_TAIL = 1, 2, 3, 4, 5, 6, 7, 8
 TUNE_DIA_UNIFORM, TUNE_XCD, TUNE_MIXED_SPLIT, TUNE_FP64_SPLIT, TUNE_DIA_ALIGN = 9, 10, 11, 12, 13
-TUNE_CAPPED = 14
+TUNE_CAPPED, TUNE_PAIR_R = 14, 15
 AGGR_MATCHING, AGGR_VBM = 0, 1
 SMOOTH_L1JACOBI, SMOOTH_AINV, SMOOTH_INVK, SMOOTH_CHEB4 = 0, 1, 2, 3
 MAX_LEVELS = 32
@@ -65,7 +65,8 @@ class HierStats(C.Structure):
                 ("vcycle_double", C.c_int32), ("aggregation", C.c_int32), ("smoother", C.c_int32),
                 ("smoother_nnz", C.c_int64 * MAX_LEVELS), ("rebuild_seconds", C.c_double),
                 ("coarse_pcg_iters", C.c_int32), ("tail_level", C.c_int32), ("tail_lds_bytes", C.c_int32),
-                ("capped_cap", C.c_int32 * MAX_LEVELS), ("capped_slots", C.c_int64 * MAX_LEVELS)]
+                ("capped_cap", C.c_int32 * MAX_LEVELS), ("capped_slots", C.c_int64 * MAX_LEVELS),
+                ("pair_restrict", C.c_int32 * MAX_LEVELS)]
 
 
 def _load():
@@ -209,7 +210,8 @@ class Hierarchy:
                     smoother=s.smoother, smoother_nnz=list(s.smoother_nnz[:L]),
                     rebuild_seconds=s.rebuild_seconds, coarse_pcg_iters=s.coarse_pcg_iters,
                     tail_level=s.tail_level, tail_lds_bytes=s.tail_lds_bytes,
-                    capped_cap=list(s.capped_cap[:L]), capped_slots=list(s.capped_slots[:L]))
+                    capped_cap=list(s.capped_cap[:L]), capped_slots=list(s.capped_slots[:L]),
+                    pair_restrict=list(s.pair_restrict[:L]))
 
     def rebuild(self, val):
         """Numeric-only rebuild with new values of A (same pattern as at build)."""

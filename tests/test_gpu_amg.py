@@ -138,6 +138,48 @@ def test_capped_layout_matches_plain_and_oracle(psc, case):
     assert np.linalg.norm(xs[0][1] - xs[1][1]) <= 1e-10 * np.linalg.norm(xs[1][1])
 
 
+def test_pair_restriction_matches_plain_and_oracle(psc):
+    """On levels whose rows 2k and 2k+1 share an aggregate and a prolongator
+    value (Poisson's 2x2x1 aggregates), the pre-smoothing pass also writes the
+    pair sums and the restriction reads them: the V-cycle in both precisions
+    and the fused PCG / FCG(1) solves agree with the plain restriction up to
+    rounding, and the V-cycle with the oracle."""
+    rp, c, v = P.poisson7(32)
+    h = psc.Hierarchy(rp, c, v, build_fp32=True)
+    inf = h.info()
+    assert inf["pair_restrict"][:2] == [1, 1]
+    # odd row counts are never eligible
+    assert psc.Hierarchy(*P.poisson7(13)).info()["pair_restrict"][0] == 0
+    n = len(rp) - 1
+    r = np.random.default_rng(5).standard_normal(n)
+    out = {}
+    for on in (1, 0):
+        h.tune(psc.TUNE_PAIR_R, on)
+        assert h.info()["pair_restrict"][0] == on
+        for prec in (psc.FP64, psc.FP32):
+            z = torch.empty(n, dtype=torch.float64, device="cuda")
+            h.vcycle(dev(r), z, prec=prec)
+            out[(on, prec)] = z.cpu().numpy()
+        b = np.random.default_rng(6).standard_normal(n)
+        for form in ("pcg", "fcg64", "fcg32"):
+            x = torch.zeros(n, dtype=torch.float64, device="cuda")
+            if form == "pcg":
+                g = h.pcg(dev(b), x, rtol=1e-6, maxit=200)
+            else:
+                g = h.fcg(dev(b), x, rtol=1e-6, maxit=200, prec=psc.FP32 if form == "fcg32" else psc.FP64)
+            out[(on, form)] = (g["iters"], x.cpu().numpy())
+    h.tune(psc.TUNE_PAIR_R, 1)
+    ref = oracle.Hierarchy(rp, c, v).vcycle(r)
+    for on in (1, 0):
+        assert np.linalg.norm(out[(on, psc.FP64)] - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.linalg.norm(out[(1, psc.FP64)] - out[(0, psc.FP64)]) <= 1e-14 * np.linalg.norm(ref)
+    assert np.linalg.norm(out[(1, psc.FP32)] - out[(0, psc.FP32)]) <= 1e-6 * np.linalg.norm(ref)
+    for form in ("pcg", "fcg64", "fcg32"):
+        (i1, x1), (i0, x0) = out[(1, form)], out[(0, form)]
+        assert i1 == i0
+        assert np.linalg.norm(x1 - x0) <= 1e-9 * np.linalg.norm(x0)
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_vcycle_matches_oracle(psc, case):
     rp, c, v = CASES[case]()
