@@ -1215,9 +1215,10 @@ __global__ __launch_bounds__(WG) void k_update_pre(Ell<double> A, const double* 
 // previous direction), q = A p_new, the deferred x += alpha_prev p_old, and
 // the partials (p_new.q, p_new.r_old). Held to 168 registers, three waves
 // per SIMD: the compiler's 170 would allow only two, measured 2 % slower at
-// 384^3 (two registers spill).
-template <typename M, bool BUF = false>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void k_spmv_pfuse_fcg(M A, const double* __restrict__ z,
+// 384^3 (two registers spill). TZ = float: z read from its FP32 copy (the
+// mixed form's V-cycle output) and widened.
+template <typename M, bool BUF = false, typename TZ = double>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void k_spmv_pfuse_fcg(M A, const TZ* __restrict__ z,
                                                        const double* __restrict__ pold, double* __restrict__ pnew,
                                                        double* __restrict__ q, double* __restrict__ x,
                                                        const double* __restrict__ rold, Red R) {
@@ -1232,16 +1233,16 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void k_
             for (long long S = lo + w; S < hi; S += WG / 64) {
                 double a0, a1;
                 dia_pair_rows_lc(
-                    A, S, lane, [&](long long c) { return Gather2{ld2(pold + c), ld2(z + c)}; },
-                    [&](const Gather2& t) {
-                        return v2u<double>{fma(nb, t.a.x, t.b.x), fma(nb, t.a.y, t.b.y)};
+                    A, S, lane, [&](long long c) { return GatherAB<double, TZ>{ld2(pold + c), ld2(z + c)}; },
+                    [&](const GatherAB<double, TZ>& t) {
+                        return v2u<double>{fma(nb, t.a.x, (double)t.b.x), fma(nb, t.a.y, (double)t.b.y)};
                     },
-                    [&](int c) { return fma(nb, pold[c], z[c]); }, a0, a1);
+                    [&](int c) { return fma(nb, pold[c], (double)z[c]); }, a0, a1);
                 const long long row = S * (2 * SLICE) + 2 * lane;
                 if (row + 1 < A.nrows) {
-                    const v2u<double> po = ld2(pold + row), zz = ld2(z + row), xx = ld2((const double*)x + row),
-                                      rr = ld2(rold + row);
-                    const double p0 = fma(nb, po.x, zz.x), p1 = fma(nb, po.y, zz.y);
+                    const v2u<double> po = ld2(pold + row), xx = ld2((const double*)x + row), rr = ld2(rold + row);
+                    const v2u<TZ> zz = ld2(z + row);
+                    const double p0 = fma(nb, po.x, (double)zz.x), p1 = fma(nb, po.y, (double)zz.y);
                     st2(pnew + row, p0, p1);
                     st2(q + row, a0, a1);
                     st2(x + row, fma(alpha_prev, po.x, xx.x), fma(alpha_prev, po.y, xx.y));
@@ -1251,7 +1252,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void k_
                     s1 += p1 * rr.y;
                 } else if (row < A.nrows) {
                     const double po = pold[row];
-                    const double pn = fma(nb, po, z[row]);
+                    const double pn = fma(nb, po, (double)z[row]);
                     pnew[row] = pn;
                     q[row] = a0;
                     x[row] = fma(alpha_prev, po, x[row]);
@@ -1264,15 +1265,16 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void k_
         }
     }
     chunk_range(A.nslices, lo, hi);
-    const BVec<double> bz = bvec(z, A.ncols), bp = bvec(pold, A.ncols);
+    const BVec<TZ> bz = bvec(z, A.ncols);
+    const BVec<double> bp = bvec(pold, A.ncols);
     for (long long s = lo + w; s < hi; s += WG / 64) {
         double acc;
-        if constexpr (BUF) acc = ell_row_buf(A, s, lane, [&](int c) { return fma(nb, bp[c], bz[c]); });
-        else acc = mat_row(A, s, lane, [&](int c) { return fma(nb, pold[c], z[c]); });
+        if constexpr (BUF) acc = ell_row_buf(A, s, lane, [&](int c) { return fma(nb, bp[c], (double)bz[c]); });
+        else acc = mat_row(A, s, lane, [&](int c) { return fma(nb, pold[c], (double)z[c]); });
         long long row = s * SLICE + lane;
         if (row < A.nrows) {
             const double po = pold[row];
-            const double pn = fma(nb, po, z[row]);
+            const double pn = fma(nb, po, (double)z[row]);
             pnew[row] = pn;
             q[row] = acc;
             x[row] = fma(alpha_prev, po, x[row]);
@@ -2556,6 +2558,8 @@ struct psc_hier {
     bool mixed_split = true;              // FP32 V-cycle: residual update and pre-smoothing as two passes
     bool fp64_split = true;               // FP64 V-cycle: the same two passes
     float* r32 = nullptr;                 // FP32 copy of the outer residual (mixed_split)
+    float* z32 = nullptr;                 // the FP32 V-cycle's output of the mixed form, kept in FP32
+    bool mixed_z32 = true;
     // Small levels in one workgroup (k_tail): off by default. Under graph
     // replay each small kernel costs about as much as one latency-bound round
     // inside the tail, so the per-level launches are as fast or faster
@@ -3092,6 +3096,15 @@ template <typename T>
 static T* pr_out(const psc_hier* h, DevLevel& V) {
     return use_pr(h, V) ? LV<T>::h2(V) : nullptr;
 }
+// The mixed form's z in FP32: the FP32 V-cycle computes it in FP32, so the
+// FP32 copy holds exactly the values the FP64 one would (the level-0
+// post-smoothing writes it, the next outer pass widens it on reading), in
+// half the bytes. l1-Jacobi split V-cycle only.
+static float* mixed_z(const psc_hier* h) {
+    return (h->mixed_z32 && h->z32 && h->split && !h->fai && !h->cheb && h->lev.size() > 1 && h->bufload != 1)
+               ? h->z32
+               : nullptr;
+}
 static inline int grid_vec(const psc_hier* h, long long n) { return grid_of(h, 1024, n); }
 
 // ---------------------------------------------------------------------------
@@ -3489,7 +3502,7 @@ static void post_sweeps(psc_hier* h, DevLevel& V, const TB* b, TX* out, const T*
 // the bytes).
 template <typename T>
 static void vcycle_t(psc_hier* h, const double* r0, double* z0, const double* d, const Red& R, Gate g,
-                     bool skip_pre0, const float* r0_32 = nullptr) {
+                     bool skip_pre0, const float* r0_32 = nullptr, float* z32 = nullptr) {
     const int L = (int)h->lev.size();
     Red R0 = R;
     R0.fin = FIN_NONE;
@@ -3527,11 +3540,19 @@ static void vcycle_t(psc_hier* h, const double* r0, double* z0, const double* d,
         if (l == 0) {
             {
                 TimeScope t(h, 4);
-                if (h->split && std::is_same<T, float>::value && r0_32)
-                    post_sweeps<T, float, double>(h, V, r0_32, z0, xc, d, R);
-                else if (h->split) post_sweeps<T, double, double>(h, V, r0, z0, xc, d, R);
-                else launch_post(h, grid_lvl(h, V), LV<T>::A(V), LV<T>::SP(V), LV<T>::minv(V), r0, (const T*)LV<T>::r(V), V.agg,
-                                 LV<T>::pv(V), xc, V.nc, z0, d, R);
+                if constexpr (std::is_same<T, float>::value) {
+                    // z32: the output kept in FP32 (its values are FP32 anyway)
+                    if (h->split && r0_32 && z32) post_sweeps<T, float, float>(h, V, r0_32, z32, xc, d, R);
+                    else if (h->split && r0_32) post_sweeps<T, float, double>(h, V, r0_32, z0, xc, d, R);
+                    else if (h->split && z32) post_sweeps<T, double, float>(h, V, r0, z32, xc, d, R);
+                    else if (h->split) post_sweeps<T, double, double>(h, V, r0, z0, xc, d, R);
+                }
+                if constexpr (std::is_same<T, double>::value) {
+                    if (h->split) post_sweeps<T, double, double>(h, V, r0, z0, xc, d, R);
+                }
+                if (!h->split)
+                    launch_post(h, grid_lvl(h, V), LV<T>::A(V), LV<T>::SP(V), LV<T>::minv(V), r0, (const T*)LV<T>::r(V),
+                                V.agg, LV<T>::pv(V), xc, V.nc, z0, d, R);
             }
             finish(h, R, grid_lvl(h, V));
         } else {
@@ -3744,8 +3765,9 @@ static void vcycle_cheb(psc_hier* h, const double* r0, double* z0, const double*
 // z = B r on level 0. prec: PSC_FP64 / PSC_FP32. fin/d: optional fused dot
 // z.d at level 0 with finaliser fin. g gates every kernel (g.ctl == NULL:
 // standalone V-cycle, always runs, no fused dot).
+// z32 (FP32 V-cycle only, see mixed_z): the output goes there instead of z0.
 static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin, const double* d,
-                   Gate g, bool skip_pre0 = false, const float* r0_32 = nullptr) {
+                   Gate g, bool skip_pre0 = false, const float* r0_32 = nullptr, float* z32 = nullptr) {
     hipStream_t st = h->stream;
     const int L = (int)h->lev.size();
     Red R = red_of(h, fin, g.ctl ? g.mode : GATE_NONE);
@@ -3773,7 +3795,7 @@ static void vcycle(psc_hier* h, int prec, const double* r0, double* z0, int fin,
         return;
     }
     if (prec == PSC_FP64) vcycle_t<double>(h, r0, z0, d, R, g, skip_pre0);
-    else vcycle_t<float>(h, r0, z0, d, R, g, skip_pre0, r0_32);
+    else vcycle_t<float>(h, r0, z0, d, R, g, skip_pre0, r0_32, z32);
 }
 
 // ---------------------------------------------------------------------------
@@ -3878,6 +3900,8 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
     if (form == FORM_FFUSED64 || form == FORM_FFUSED32 || form == FORM_FNET64 || form == FORM_FNET32) {
         const bool f32 = form == FORM_FFUSED32 || form == FORM_FNET32;
         const bool netf = form == FORM_FNET64 || form == FORM_FNET32;
+        // the mixed form without the network keeps z in FP32 (see mixed_z)
+        float* z32 = form == FORM_FFUSED32 ? mixed_z(h) : nullptr;
         // The true residual and the redo of the pre-smoothing run only in the
         // iterations whose recursive residual passed the test, but are launched
         // in every one: on a grid of at most 1024 workgroups their early exit
@@ -3894,6 +3918,11 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
                 TimeScope t(h, 0);
                 if (h->bufload == 1)
                     k_spmv_pfuse_fcg<Ell<double>, true><<<ge, WG, 0, st>>>(L0.A.view(), h->z, pold, pnew, h->q, h->xs, rold, red_of(h, FIN_ALPHA_FCG));
+                else if (z32)
+                    with_A(h, L0, [&](auto A) {
+                        k_spmv_pfuse_fcg<decltype(A), false, float><<<ge, WG, 0, st>>>(
+                            A, z32, pold, pnew, h->q, h->xs, rold, red_of(h, FIN_ALPHA_FCG));
+                    });
                 else
                     with_A(h, L0, [&](auto A) {
                         k_spmv_pfuse_fcg<decltype(A)><<<ge, WG, 0, st>>>(A, h->z, pold, pnew, h->q, h->xs, rold, red_of(h, FIN_ALPHA_FCG));
@@ -3965,7 +3994,7 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
                 launch_pre(h, L0, (const double*)rnew, pre_rbuf<double>(h, L0, 1), gr, gq);
             }
             if (!netf) {
-                vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, gd, true, r32v);
+                vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, gd, true, r32v, z32);
                 continue;
             }
             // learned form: odd iterations try z = net(r); the V-cycle (its
@@ -4128,7 +4157,8 @@ static int solve_impl(psc_hier* h, int form, psc_net* net, const double* b_dev, 
         } else if (fused) {
             k_fill<double><<<gv, WG, 0, st>>>(n, h->q, 0.0);
             k_fill<double><<<gv, WG, 0, st>>>(n, h->p, 0.0);
-            vcycle(h, form_prec(form), h->r, h->z, FIN_BETA_FCG, h->q, gd);   // z = B r0, beta = 0
+            vcycle(h, form_prec(form), h->r, h->z, FIN_BETA_FCG, h->q, gd, false, nullptr,
+                   form == FORM_FFUSED32 ? mixed_z(h) : nullptr);   // z = B r0, beta = 0
             if (form_net(form)) k_set_net_on<<<1, 64, 0, st>>>(h->ctl);
         } else if (form == 0) {
             vcycle(h, PSC_FP64, h->r, h->z, FIN_RHO_INIT, h->r, gd);
@@ -4614,6 +4644,7 @@ int psc_amg_build(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     for (double** p : {&h->xs, &h->bs, &h->r, &h->z, &h->p, &h->q, &h->r2, &h->p2})
         if ((st = dalloc(h.get(), (void**)p, N * sizeof(double)))) return st;
     if (f32 && (st = dalloc(h.get(), (void**)&h->r32, N * sizeof(float)))) return st;
+    if (f32 && (st = dalloc(h.get(), (void**)&h->z32, N * sizeof(float)))) return st;
     HIPCHK(hipHostMalloc((void**)&h->hctl, sizeof(HostCtl), hipHostMallocMapped | hipHostMallocCoherent));
     std::memset(h->hctl, 0, sizeof(HostCtl));
     HIPCHK(hipHostGetDevicePointer((void**)&h->hctl_dev, h->hctl, 0));
@@ -4963,6 +4994,11 @@ int psc_tune(psc_hier* h, int32_t key, int32_t value) {
     }
     if (key == PSC_TUNE_PAIR_R) {
         h->pair_r = value != 0;
+        drop_graphs(h);
+        return PSC_OK;
+    }
+    if (key == PSC_TUNE_MIXED_Z32) {
+        h->mixed_z32 = value != 0;
         drop_graphs(h);
         return PSC_OK;
     }

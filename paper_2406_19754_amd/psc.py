@@ -21,7 +21,7 @@ ERR_ARG, ERR_NOT_SPD, ERR_NAN, ERR_HIP, ERR_OOM, ERR_COARSEN, ERR_STATE, ERR_IO 
 FP64, FP32 = 0, 1
 TUNE_GRID_MAX, TUNE_FUSED_PCG, TUNE_UNROLL4, TUNE_BUFLOAD, TUNE_SPMV2, TUNE_SPLIT, TUNE_DIA, TUNE_TAIL = 1, 2, 3, 4, 5, 6, 7, 8
 TUNE_DIA_UNIFORM, TUNE_XCD, TUNE_MIXED_SPLIT, TUNE_FP64_SPLIT, TUNE_DIA_ALIGN = 9, 10, 11, 12, 13
-TUNE_CAPPED, TUNE_PAIR_R = 14, 15
+TUNE_CAPPED, TUNE_PAIR_R, TUNE_MIXED_Z32 = 14, 15, 16
 AGGR_MATCHING, AGGR_VBM = 0, 1
 SMOOTH_L1JACOBI, SMOOTH_AINV, SMOOTH_INVK, SMOOTH_CHEB4 = 0, 1, 2, 3
 MAX_LEVELS = 32

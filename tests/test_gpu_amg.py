@@ -180,6 +180,25 @@ def test_pair_restriction_matches_plain_and_oracle(psc):
         assert np.linalg.norm(x1 - x0) <= 1e-9 * np.linalg.norm(x0)
 
 
+@pytest.mark.parametrize("n", [32, 33])
+def test_mixed_form_fp32_z_is_bit_identical(psc, n):
+    """The mixed form keeps the FP32 V-cycle's output z in FP32 (the
+    precision it is computed in) and the outer pass widens it: iterates,
+    iteration count and residual are bit for bit those of the FP64 copy."""
+    rp, c, v = P.poisson7(n)
+    h = psc.Hierarchy(rp, c, v, build_fp32=True)
+    b = np.random.default_rng(7).standard_normal(len(rp) - 1)
+    out = []
+    for on in (1, 0):
+        h.tune(psc.TUNE_MIXED_Z32, on)
+        x = torch.zeros(len(b), dtype=torch.float64, device="cuda")
+        g = h.fcg(dev(b), x, rtol=1e-8, maxit=200, prec=psc.FP32)
+        out.append((g["iters"], g["relres"], x.cpu().numpy()))
+    h.tune(psc.TUNE_MIXED_Z32, 1)
+    assert out[0][0] == out[1][0] and out[0][1] == out[1][1]
+    assert np.array_equal(out[0][2], out[1][2])
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_vcycle_matches_oracle(psc, case):
     rp, c, v = CASES[case]()
