@@ -3900,8 +3900,9 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
     if (form == FORM_FFUSED64 || form == FORM_FFUSED32 || form == FORM_FNET64 || form == FORM_FNET32) {
         const bool f32 = form == FORM_FFUSED32 || form == FORM_FNET32;
         const bool netf = form == FORM_FNET64 || form == FORM_FNET32;
-        // the mixed form without the network keeps z in FP32 (see mixed_z)
-        float* z32 = form == FORM_FFUSED32 ? mixed_z(h) : nullptr;
+        // the mixed forms keep z in FP32 (see mixed_z); a network step's FP64 z
+        // is rounded into it for the outer pass
+        float* z32 = (form == FORM_FFUSED32 || form == FORM_FNET32) ? mixed_z(h) : nullptr;
         // The true residual and the redo of the pre-smoothing run only in the
         // iterations whose recursive residual passed the test, but are launched
         // in every one: on a grid of at most 1024 workgroups their early exit
@@ -4008,8 +4009,10 @@ static int issue_iteration(psc_hier* h, int form, psc_net* net) {
                 Red Rn = red_of(h, FIN_NETCHECK, GATE_NET);
                 k_dot2<<<gv, WG, 0, st>>>(n, h->z, rnew, h->q, Rn);
                 finish(h, Rn, gv);
+                if (z32) k_copy<float, double><<<gv, WG, 0, st>>>(n, z32, h->z, Gate{h->ctl, GATE_NET});
             }
-            vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, Gate{h->ctl, GATE_VC}, true, r32v);
+            vcycle(h, f32 ? PSC_FP32 : PSC_FP64, rnew, h->z, FIN_BETA_FCG, h->q, Gate{h->ctl, GATE_VC}, true, r32v,
+                   z32);
         }
         return PSC_OK;
     }
@@ -4158,7 +4161,7 @@ static int solve_impl(psc_hier* h, int form, psc_net* net, const double* b_dev, 
             k_fill<double><<<gv, WG, 0, st>>>(n, h->q, 0.0);
             k_fill<double><<<gv, WG, 0, st>>>(n, h->p, 0.0);
             vcycle(h, form_prec(form), h->r, h->z, FIN_BETA_FCG, h->q, gd, false, nullptr,
-                   form == FORM_FFUSED32 ? mixed_z(h) : nullptr);   // z = B r0, beta = 0
+                   (form == FORM_FFUSED32 || form == FORM_FNET32) ? mixed_z(h) : nullptr);   // z = B r0, beta = 0
             if (form_net(form)) k_set_net_on<<<1, 64, 0, st>>>(h->ctl);
         } else if (form == 0) {
             vcycle(h, PSC_FP64, h->r, h->z, FIN_RHO_INIT, h->r, gd);
