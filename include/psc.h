@@ -468,11 +468,13 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
  * and half the index and value bytes of R. 0 restricts r itself. Same values
  * up to rounding. */
 #define PSC_TUNE_PAIR_R 15
-/* PSC_TUNE_MIXED_Z32 (default 1): the mixed form (FCG(1) with the FP32
- * V-cycle, l1-Jacobi split smoother, no network) keeps the V-cycle's output
- * z in FP32, the precision it is computed in: the level-0 post-smoothing
- * writes 4 bytes per row instead of 8 and the next outer pass gathers them
- * and widens them exactly. 0 keeps z in FP64. The same values bit for bit. */
+/* PSC_TUNE_MIXED_Z32 (default 1): the mixed forms (FCG(1) with the FP32
+ * V-cycle, l1-Jacobi split smoother) keep the V-cycle's output z in FP32, the
+ * precision it is computed in: the level-0 post-smoothing writes 4 bytes per
+ * row instead of 8 and the next outer pass gathers them and widens them
+ * exactly (the same values bit for bit). In the learned form with the FP32
+ * V-cycle, a network step's z (from BF16 activations) is rounded to FP32 for
+ * the outer pass; its acceptance test reads the FP64 z. 0 keeps z in FP64. */
 #define PSC_TUNE_MIXED_Z32 16
 int psc_tune(psc_hier* h, int32_t key, int32_t value);
 
