@@ -72,6 +72,12 @@ REFRESH_CASES = {
     "diffusion20_az100": (lambda: P.diffusion7(20, seed=0, az=100.0), dict()),
     "random_long_rows": (lambda: P.random_spd_csr(700, 5, density=0.01, maxrow=90), dict(coarse_max=40)),
     "smoothed_nu2": (lambda: P.poisson7(17), dict(smoothed_prol=True, sweeps=3, smoother_sweeps=2)),
+    "poisson20_pairs": (lambda: P.poisson7(20), dict()),                 # pair restriction on levels 0 and 1
+    # capped hacked-ELL copies (every level where a cap pays): the stalled
+    # lognormal coarse levels, and a random matrix's uneven rows
+    "lognormal48_capped": (lambda: P.diffusion7(48, seed=0), dict(capped_min_rows=1)),
+    "random_long_rows_capped": (lambda: P.random_spd_csr(700, 5, density=0.01, maxrow=90),
+                                dict(coarse_max=40, capped_min_rows=1)),
 }
 
 
@@ -97,6 +103,12 @@ def test_rebuilt_device_data_equal_a_fresh_build_bitwise(psc, case, knob):
         elif knob == "split_off":
             q.tune(psc.TUNE_SPLIT, 0)
     assert h.info()["dia_slots"] == f.info()["dia_slots"]
+    assert h.info()["capped_cap"] == f.info()["capped_cap"]
+    assert h.info()["pair_restrict"] == f.info()["pair_restrict"]
+    if case.endswith("_capped"):
+        assert any(h.info()["capped_cap"])
+    if case == "poisson20_pairs" and knob == "default":
+        assert h.info()["pair_restrict"][:2] == [1, 1]
     r = dev(np.random.default_rng(8).standard_normal(n))
     outs = []
     for q in (h, f):
