@@ -455,7 +455,7 @@ int psc_timing_get(psc_hier* h, int64_t* counts, double* total_ms);
  * l1-Jacobi coarsest solve, psc_spmv), from a copy whose slices keep at most
  * a cap of slots per row, the rest of each longer row in an overflow that one
  * wavefront sums with a segmented scan; the build keeps that copy when it
- * costs at most 0.75 of the plain layout's wavefront loads. 0 reads the plain
+ * costs at most 0.9 of the plain layout's wavefront loads. 0 reads the plain
  * hacked ELL. Same values up to rounding (overflow entries are summed in scan
  * order). */
 #define PSC_TUNE_CAPPED 14

@@ -709,7 +709,7 @@ int choose_ell_cap(int64_t nrows, const int32_t* rp) {
             best_cap = cap;
         }
     }
-    return (best_cap > 0 && best * 4 <= plain * 3) ? best_cap : 0;
+    return (best_cap > 0 && best * 10 <= plain * 9) ? best_cap : 0;
 }
 
 void pack_ell_paired(int64_t nrows, const int32_t* rp, const int32_t* ci, const double* v,

@@ -180,7 +180,7 @@ void pack_ell_capped(int64_t nrows, const int32_t* rp, const int32_t* ci, const 
 // cost is counted in wavefront loads: min(w_s, cap) for its capped slots plus
 // three per 64 overflow entries (a load, a gather and the cross-lane scan);
 // the cheapest cap up to 48 (the widest one-row-per-lane slices) is taken
-// when it costs at most 0.75 of the plain layout's sum of slice widths.
+// when it costs at most 0.9 of the plain layout's sum of slice widths.
 int choose_ell_cap(int64_t nrows, const int32_t* rp);
 
 }  // namespace psc
