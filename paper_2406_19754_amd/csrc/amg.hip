@@ -1500,7 +1500,7 @@ __global__ __launch_bounds__(WG) void k_pre_s(M AM, const TB* __restrict__ b, ty
                 if (row + 1 < AM.nrows) {
                     const v2u<TB> bb = ld2(b + row);
                     const T r0 = (T)bb.x - a0, r1 = (T)bb.y - a1;
-                    st2(r + row, r0, r1);
+                    __builtin_nontemporal_store(v2a<T>{r0, r1}, (v2a<T>*)(r + row));
                     if (hp) hp[row >> 1] = r0 + r1;
                 } else if (row < AM.nrows) {
                     r[row] = (T)b[row] - a0;
