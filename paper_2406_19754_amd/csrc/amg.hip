@@ -1142,10 +1142,11 @@ __global__ __launch_bounds__(WG) void k_spmv_pfuse(M A, const double* __restrict
                     const v2u<double> po = ld2(pold + row), zz = ld2(z + row), xx = ld2((const double*)x + row);
                     const double p0 = fma(beta, po.x, zz.x), p1 = fma(beta, po.y, zz.y);
                     // p_new and x are read again only in the next iteration, after the whole
-                    // V-cycle: non-temporal stores leave the caches to q, which the residual
-                    // update reads next (pass 1 1031 -> 1018 us at 384^3)
+                    // V-cycle, and q mostly from HBM anyway (the residual update streams
+                    // it after the reduction; at 384^3 it is larger than the Infinity
+                    // Cache): non-temporal stores (pass 1 1031 -> 1013 us at 384^3)
                     __builtin_nontemporal_store(v2a<double>{p0, p1}, (v2a<double>*)(pnew + row));
-                    st2(q + row, a0, a1);
+                    __builtin_nontemporal_store(v2a<double>{a0, a1}, (v2a<double>*)(q + row));
                     __builtin_nontemporal_store(v2a<double>{fma(alpha_prev, po.x, xx.x), fma(alpha_prev, po.y, xx.y)},
                                                  (v2a<double>*)(x + row));
                     s0 += p0 * a0;
@@ -1248,7 +1249,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void k_
                     const v2u<TZ> zz = ld2(z + row);
                     const double p0 = fma(nb, po.x, (double)zz.x), p1 = fma(nb, po.y, (double)zz.y);
                     __builtin_nontemporal_store(v2a<double>{p0, p1}, (v2a<double>*)(pnew + row));
-                    st2(q + row, a0, a1);
+                    __builtin_nontemporal_store(v2a<double>{a0, a1}, (v2a<double>*)(q + row));
                     __builtin_nontemporal_store(v2a<double>{fma(alpha_prev, po.x, xx.x), fma(alpha_prev, po.y, xx.y)},
                                                  (v2a<double>*)(x + row));
                     s0 += p0 * a0;
