@@ -98,6 +98,28 @@ def kernel_bytes(info, form="fp64", fused=False, split=True, dia=True, split_upd
     }
 
 
+def mixed_kernel_bytes(info):
+    """Algorithmic bytes per launch of the level-0 kernels of the mixed form:
+    FP64 FCG(1) with the FP32 V-cycle, its output z kept in FP32, the update
+    pass split in two, smoothing through A M^-1 (hacked DIA) and S P."""
+    N, Z = info["rows"][0], info["nnz"][0]
+    Zp = info["sp_nnz"][0] if info["levels"] > 1 else 0
+    Nc = info["rows"][1] if info["levels"] > 1 else 0
+    pr = bool(info.get("pair_restrict", [0])[0])
+    return {
+        # A (FP64); z (FP32), p_old, x, r_old read; p_new, q, x written
+        "k_spmv_pfuse_fcg": Z * 8 + 4 * N + 3 * 8 * N + 3 * 8 * N,
+        # r_old, q read; r_new (FP64) and its FP32 copy written
+        "k_rupdate_r32": 3 * 8 * N + 4 * N,
+        # A M^-1 (FP32), r gathered, r_0 written (+ N/2 pair sums)
+        "k_pre_s_f32": Z * 4 + 4 * N + 4 * N + (2 * N if pr else 0),
+        # R2 over pair sums (N/2 entries of value + index) or R over r_0; b_1 written
+        "k_spmv_R_f32": ((N // 2) * 8 + 4 * (N // 2) if pr else N * 8 + 4 * N) + 4 * Nc,
+        # S P; minv, b, r_0 (FP32) and q (FP64, for z.q) read; x_c gathered; z (FP32) written
+        "k_post_s_f32": Zp * 8 + 3 * 4 * N + 8 * N + 4 * Nc + 4 * N,
+    }
+
+
 def source_hash():
     h = hashlib.sha256()
     for f in ["amg.hip", "kernels.h"]:
