@@ -281,6 +281,7 @@ def main():
     ap.add_argument("--profile-mix", action="store_true",
                     help="run the kernel mix used for rocprofv3 counter passes: a plain 1 GiB device copy "
                          "(counter calibration), 10 SpMVs on A_0, one FP64 PCG and one mixed FCG solve")
+    ap.add_argument("--oracle-child", default="", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: the solve path is not sharded across GPUs",
@@ -290,6 +291,8 @@ def main():
         return learned(args)
     if args.profile_mix:
         return profile_mix(args)
+    if args.oracle_child:
+        return oracle_child(args)
 
     import numpy as np
     import torch
@@ -469,6 +472,21 @@ def main():
                           "vcycle_gbs": info["vcycle_bytes_fp32"] / (vc_ms32 / vc_cnt32 * 1e-3) / 1e9
                           if vc_cnt32 else None,
                           "err_vs_fp64_x": float(np.linalg.norm(x32 - xg) / np.linalg.norm(xg))}
+        if fused and split_update and not args.no_dia and info["dia_slots"][0] > 0:
+            # per-kernel rates of the mixed form's level-0 kernels (its default path)
+            kbm = mixed_kernel_bytes(info)
+            tm = {"spmv_dot": ("k_spmv_pfuse_fcg",), "pre_smooth_l0": ("k_rupdate_r32", "k_pre_s_f32"),
+                  "restrict_l0": ("k_spmv_R_f32",), "post_smooth_l0": ("k_post_s_f32",)}
+            km = {}
+            for name, parts in tm.items():
+                cnt, tot = kt32.get(name, (0, 0.0))
+                if cnt:
+                    b = sum(kbm[p] for p in parts)
+                    km[" + ".join(parts)] = {"launches": cnt, "avg_ms": tot / cnt, "alg_bytes": b,
+                                             "gbs": b / (tot / cnt * 1e-3) / 1e9}
+                    log(f"mixed {' + '.join(parts)}: {tot / cnt * 1e3:.1f} us avg, "
+                        f"{km[' + '.join(parts)]['gbs'] / HBM_PEAK_GBS:.3f} of peak")
+            forms["mixed"]["kernels"] = km
     forms.update(time_configs(args, psc, torch, rp, col, val, bd, x, ms64))
     if net is not None:
         # the learned forms run inside FCG(1): its plain FP64 time is their reference
@@ -489,7 +507,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(args, rp, col, val, b, n, r64, xg, ms64)
+        cpu = cpu_baseline(args, n, r64, xg, ms64)
 
     out = {
         "metric": METRIC,
@@ -535,17 +553,54 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(args, rp, col, val, b, n, r64, xg, ms64):
+def cpu_baseline(args, n, r64, xg, ms64):
     """The CPU oracle (plain C, FP64 CSR) on the same problem: its own
     hierarchy build, then one full PCG solve to rtol 1e-6 from x0 = 0, timed
     with the host clock. Its row loops run on the host threads; dots,
-    restrictions and the build are serial. Also states how far the GPU's FP64
-    solution is from the oracle's."""
+    restrictions and the build are serial. It runs in a child process of its
+    own (a fresh interpreter that never touches the GPU and regenerates the
+    same seeded problem), so that the GPU process's runtime threads and heap
+    play no part in it; a failure there leaves the GPU results standing.
+    Also states how far the GPU's FP64 solution is from the oracle's."""
+    import subprocess
+    import tempfile
     import numpy as np
-    import oracle
     threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS", "0") or 0) \
         or len(os.sched_getaffinity(0))
-    oracle.set_threads(threads)
+    base = {"value": None, "unit": "ms", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+            "gpu_iters": r64["iters"]}
+    with tempfile.TemporaryDirectory() as td:
+        np.save(os.path.join(td, "x_gpu.npy"), xg)
+        cmd = [sys.executable, os.path.abspath(__file__), "--oracle-child", td, "--workload", args.workload,
+               "--n", str(n), "--az", repr(args.az), "--cpu-threads", str(threads)]
+        try:
+            p = subprocess.run(cmd, stdout=subprocess.PIPE, timeout=1500)
+        except subprocess.TimeoutExpired:
+            log("cpu oracle: its process did not finish within 1500 s; no CPU baseline")
+            return dict(base, error="oracle process timed out")
+    if p.returncode != 0:
+        log(f"cpu oracle: its process ended with status {p.returncode}; no CPU baseline")
+        return dict(base, error=f"oracle process ended with status {p.returncode}")
+    res = json.loads(p.stdout.decode().strip().splitlines()[-1])
+    t_solve, t_setup = res["solve_s"], res["setup_s"]
+    return dict(base, value=t_solve * 1e3, cores=res["threads"],
+                sample=f"one full oracle PCG solve of the same {n}^3 problem to rtol 1e-6 from x0 = 0 "
+                       f"({res['iters']} iterations; row loops on {res['threads']} threads, dots and restrictions "
+                       f"serial), in a process of its own; its serial hierarchy build ({t_setup:.1f} s) is "
+                       f"excluded like the GPU setup",
+                oracle_iters=res["iters"], oracle_relres=res["relres"], oracle_setup_s=t_setup,
+                x_gpu_vs_oracle=res["x_gpu_vs_oracle"], gpu_speedup=t_solve * 1e3 / ms64)
+
+
+def oracle_child(args):
+    """The oracle side of cpu_baseline, run as its own process: prints one
+    JSON line with the oracle's times, iterations and the distance of the GPU
+    solution (saved by the parent) from the oracle's."""
+    import numpy as np
+    import oracle
+    n = args.n
+    rp, col, val, xt, b, desc = problem(args.workload, n, args.az)
+    oracle.set_threads(args.cpu_threads)
     threads = oracle.get_threads()
     t0 = time.perf_counter()
     o = oracle.Hierarchy(rp, col, val)
@@ -555,16 +610,12 @@ def cpu_baseline(args, rp, col, val, b, n, r64, xg, ms64):
     res = o.pcg(b, rtol=1e-6, maxit=500)
     t_solve = time.perf_counter() - t0
     xo = res["x"]
+    xg = np.load(os.path.join(args.oracle_child, "x_gpu.npy"))
     diff = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
     log(f"cpu oracle: PCG {res['iters']} its in {t_solve:.1f}s on {threads} threads, relres {res['relres']:.2e}; "
         f"|x_gpu - x_oracle|/|x_oracle| = {diff:.2e}")
-    return {"value": t_solve * 1e3, "unit": "ms", "cores": threads, "kind": "oracle",
-            "sample": f"one full oracle PCG solve of the same {n}^3 problem to rtol 1e-6 from x0 = 0 "
-                      f"({res['iters']} iterations; row loops on {threads} threads, dots and restrictions "
-                      f"serial); its serial hierarchy build ({t_setup:.1f} s) is excluded like the GPU setup",
-            "cpu_model": cpu_model(), "oracle_iters": res["iters"], "oracle_relres": res["relres"],
-            "oracle_setup_s": t_setup, "gpu_iters": r64["iters"],
-            "x_gpu_vs_oracle": diff, "gpu_speedup": t_solve * 1e3 / ms64}
+    print(json.dumps({"solve_s": t_solve, "setup_s": t_setup, "iters": res["iters"], "relres": res["relres"],
+                      "threads": threads, "x_gpu_vs_oracle": diff}), flush=True)
 
 
 def profile_mix(args):
